@@ -1,0 +1,134 @@
+/*
+ * fd3d.h -- C ABI of the MI355X (gfx950) time-stepped 3D elastic velocity-stress
+ * staggered-grid finite-difference library (arXiv 2112.15071).
+ *
+ * The operation (all entry points share it):
+ *   Sec. 2.1, Eq.(1)-(3)  rho dv/dt = div(sigma) + f ;  dsigma/dt = C(lambda, mu) : strain rate
+ *   Sec. 2.1.1            Graves staggering: sxx,syy,szz at (x,y,z); sxy at (x+1/2,y+1/2,z);
+ *                         sxz at (x+1/2,y,z+1/2); syz at (x,y+1/2,z+1/2); vx at (x+1/2,y,z);
+ *                         vy at (x,y+1/2,z); vz at (x,y,z+1/2)
+ *   Sec. 2.1.2, Eq.(4)    fourth-order staggered derivative, weights 9/8 and -1/24, divided by dx
+ *   Sec. 2.2              one copy of each field, updated in place: velocity pass, then stress pass
+ *   Sec. 2.2.1            rho, lambda, mu at staggered points = means of the neighbouring nodes
+ *   Sec. 2.4              receivers: trilinear sampling of v every step, kept on the device
+ *   Sec. 2.5              edge damping (Cerjan profile) and a free top surface (stress imaging,
+ *                         second-order z difference next to the surface)
+ *
+ * Conventions.
+ *   - Arrays are x-fastest: idx = i + nx*(j + ny*k), k = 0 is the top (z down).
+ *   - A component staggered along an axis has n-1 active samples there; the last slot
+ *     stays zero.  Samples outside the grid read as zero.
+ *   - T is float (FD3D_F32) or double (FD3D_F64), chosen once per context.
+ *   - Positions are in grid units (node spacing 1), order (x, y, z).
+ *   - Step n (0-based): velocity pass v^{n-1/2} -> v^{n+1/2} (force source uses wavelet[n]);
+ *     receivers record v^{n+1/2} into traces[r][c][n]; stress pass sigma^n -> sigma^{n+1}
+ *     (moment source uses wavelet[n]).  Inside a pass the source is added before the
+ *     damping factor multiplies the field.
+ *
+ * Ownership.  The caller owns every device buffer (model, wavelet, traces, residual,
+ * gradients, workspaces) and keeps it alive until the work enqueued on the stream has
+ * finished.  The library never allocates device memory; it lays its state out inside
+ * the caller's workspace.  A context is host memory freed by fd3d_destroy.
+ *
+ * Streams.  Every call enqueues on the caller's hipStream_t (NULL = default stream) and
+ * returns without waiting, except fd3d_create (reads back model statistics) and calls
+ * with check_finite set (read back one flag).
+ *
+ * Errors.  Functions return FD3D_OK (0) or a negative code; fd3d_last_error() gives a
+ * message for the calling thread.  No C++ exception crosses the ABI.
+ */
+#ifndef FD3D_H
+#define FD3D_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FD3D_OK 0
+#define FD3D_EINVAL (-1)     /* bad shape, pointer, dtype, alignment or option */
+#define FD3D_ECFL (-2)       /* dt above the O(2,4) bound 6/(7 sqrt 3) dx / vp_max (Eq.(5)) */
+#define FD3D_EMODEL (-3)     /* rho <= 0, mu < 0, lambda + 2 mu <= 0 or a non-finite value */
+#define FD3D_ERANGE (-4)     /* a source or receiver tap falls outside a component's active samples */
+#define FD3D_EWS (-5)        /* workspace too small */
+#define FD3D_EHIP (-6)       /* a HIP call or kernel launch failed */
+#define FD3D_ENONFINITE (-7) /* check_finite found a non-finite field value */
+#define FD3D_ESTATE (-8)     /* call out of order (e.g. adjoint without checkpoints) */
+
+#define FD3D_F32 0
+#define FD3D_F64 1
+
+/* fd3d_forward flags */
+#define FD3D_KEEP_STATE 1 /* start from the current state instead of zeros */
+
+typedef struct fd3d_opts {
+    int dtype;           /* FD3D_F32 or FD3D_F64 */
+    int sponge[6];       /* damping width in cells per face: x-, x+, y-, y+, z- (top), z+ */
+    double sponge_alpha; /* Cerjan coefficient; <= 0 selects 0.3 / width per face */
+    int free_surface;    /* 1: stress-imaging free surface at k = 0 (top width ignored) */
+    int check_finite;    /* 1: forward returns FD3D_ENONFINITE if the final state blew up */
+    int max_receivers;   /* receiver capacity of the workspace; <= 0 selects 4096 */
+} fd3d_opts;
+
+typedef struct fd3d_source {
+    double pos[3];       /* grid units */
+    double moment[6];    /* Mxx Myy Mzz Mxy Mxz Myz (N m): sigma_ij -= dt w M_ij s[n] / dx^3 */
+    double force[3];     /* Fx Fy Fz (N): v_i += dt b w F_i s[n] / dx^3 */
+    const void *wavelet; /* device T[nt]: s[n] (moment rate, 1/s, for moment sources) */
+} fd3d_source;
+
+typedef struct fd3d_ctx fd3d_ctx;
+
+/* Library version string (static storage). */
+const char *fd3d_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *fd3d_last_error(void);
+
+/* Bytes of forward workspace for a grid (nine fields, damping profiles, receiver
+ * descriptors, reduction scratch).  opts may be NULL (FP32, no damping, 4096 receivers). */
+int fd3d_workspace_bytes(int nx, int ny, int nz, const fd3d_opts *opts, size_t *bytes);
+
+/* Create a context over caller-owned device node arrays lam, mu, rho (T[nz][ny][nx],
+ * Sec. 2.2 / 2.2.1) with spacing dx (m), step dt (s) and nt steps.  Validates the model
+ * on the device (FD3D_EMODEL), checks dt against 6/(7 sqrt 3) dx / vp_max (FD3D_ECFL;
+ * Eq.(5) prints the rounded 0.495), builds the damping profiles on the host in double
+ * and uploads them.  workspace: device, >= fd3d_workspace_bytes, 256-byte aligned.
+ * Synchronises the stream once (model statistics). */
+int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const void *mu,
+                const void *rho, double dx, double dt, int nt, const fd3d_opts *opts,
+                void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Run nt steps (Sec. 2.2 update order) from zero state (or the current state with
+ * FD3D_KEEP_STATE).  src may be NULL (no source); its wavelet is device T[nt].
+ * rec_pos: host double[nrec][3]; traces: device T[nrec][3][nt] (written).
+ * FD3D_ERANGE if a tap of the source or a receiver is not an active sample. */
+int fd3d_forward(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *rec_pos,
+                 void *traces, int flags, void *hip_stream);
+
+/* Copy the state out of / into the context: fields[9] are device T[nz][ny][nx] in the
+ * order vx vy vz sxx syy szz sxy sxz syz (v^{n-1/2}, sigma^n).  set_state zeroes the
+ * pinned slots of the staggered components. */
+int fd3d_get_state(fd3d_ctx *ctx, void *const fields[9], void *hip_stream);
+int fd3d_set_state(fd3d_ctx *ctx, const void *const fields[9], void *hip_stream);
+
+/* Model statistics read back at create: out[0] = vp_max, out[1] = vs_min over mu > 0
+ * (0 if none), out[2] = rho_min, out[3] = largest stable dt (m/s, m/s, kg/m^3, s). */
+int fd3d_model_info(const fd3d_ctx *ctx, double out[4]);
+
+/* Per-kernel timing of the step loop.  With enable = 1, later forward calls record a
+ * HIP event pair on the caller's stream around every kernel launch of the loop (the
+ * kernels themselves are unchanged).  fd3d_profile_read waits for the last recorded
+ * event and returns, per pass (0 = velocity, 1 = receiver sampling, 2 = stress), the
+ * summed kernel time in ms and the number of launches of the last profiled call. */
+int fd3d_profile(fd3d_ctx *ctx, int enable);
+int fd3d_profile_read(fd3d_ctx *ctx, double ms[3], int launches[3]);
+
+void fd3d_destroy(fd3d_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FD3D_H */

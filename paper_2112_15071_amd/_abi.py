@@ -1,0 +1,160 @@
+"""ctypes binding of the fd3d C ABI (include/fd3d.h): argument marshalling only.
+
+Every function keeps its C name.  Pointers are passed as integers (device
+addresses from torch tensors, host addresses from numpy arrays).  A non-zero
+return code raises FD3DError with the library's message.  There is no fallback:
+if libfd3d.so is missing, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfd3d.so")
+
+FD3D_OK = 0
+FD3D_EINVAL = -1
+FD3D_ECFL = -2
+FD3D_EMODEL = -3
+FD3D_ERANGE = -4
+FD3D_EWS = -5
+FD3D_EHIP = -6
+FD3D_ENONFINITE = -7
+FD3D_ESTATE = -8
+FD3D_F32 = 0
+FD3D_F64 = 1
+FD3D_KEEP_STATE = 1
+
+ERRNAMES = {
+    FD3D_EINVAL: "FD3D_EINVAL", FD3D_ECFL: "FD3D_ECFL", FD3D_EMODEL: "FD3D_EMODEL", FD3D_ERANGE: "FD3D_ERANGE",
+    FD3D_EWS: "FD3D_EWS", FD3D_EHIP: "FD3D_EHIP", FD3D_ENONFINITE: "FD3D_ENONFINITE", FD3D_ESTATE: "FD3D_ESTATE",
+}
+
+
+class FD3DError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class fd3d_opts(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int),
+        ("sponge", ctypes.c_int * 6),
+        ("sponge_alpha", ctypes.c_double),
+        ("free_surface", ctypes.c_int),
+        ("check_finite", ctypes.c_int),
+        ("max_receivers", ctypes.c_int),
+    ]
+
+
+class fd3d_source(ctypes.Structure):
+    _fields_ = [
+        ("pos", ctypes.c_double * 3),
+        ("moment", ctypes.c_double * 6),
+        ("force", ctypes.c_double * 3),
+        ("wavelet", ctypes.c_void_p),
+    ]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_sz = ctypes.c_size_t
+_dp = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "fd3d_version": ([], ctypes.c_char_p),
+    "fd3d_last_error": ([], ctypes.c_char_p),
+    "fd3d_workspace_bytes": ([_i, _i, _i, ctypes.POINTER(fd3d_opts), ctypes.POINTER(_sz)], _i),
+    "fd3d_create": ([ctypes.POINTER(_vp), _i, _i, _i, _vp, _vp, _vp, _d, _d, _i, ctypes.POINTER(fd3d_opts), _vp, _sz, _vp], _i),
+    "fd3d_forward": ([_vp, ctypes.POINTER(fd3d_source), _i, _dp, _vp, _i, _vp], _i),
+    "fd3d_get_state": ([_vp, ctypes.POINTER(_vp), _vp], _i),
+    "fd3d_set_state": ([_vp, ctypes.POINTER(_vp), _vp], _i),
+    "fd3d_model_info": ([_vp, _dp], _i),
+    "fd3d_profile": ([_vp, _i], _i),
+    "fd3d_profile_read": ([_vp, _dp, ctypes.POINTER(_i)], _i),
+    "fd3d_destroy": ([_vp], None),
+}
+
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def exported_symbols():
+    """Names this binding resolves in the library."""
+    return list(_SIGS)
+
+
+def _check(rc: int):
+    if rc != FD3D_OK:
+        raise FD3DError(rc, _lib.fd3d_last_error().decode())
+
+
+def fd3d_version() -> str:
+    return _lib.fd3d_version().decode()
+
+
+def fd3d_last_error() -> str:
+    return _lib.fd3d_last_error().decode()
+
+
+def fd3d_workspace_bytes(nx: int, ny: int, nz: int, opts: fd3d_opts | None) -> int:
+    out = _sz(0)
+    _check(_lib.fd3d_workspace_bytes(nx, ny, nz, ctypes.byref(opts) if opts is not None else None, ctypes.byref(out)))
+    return int(out.value)
+
+
+def fd3d_create(nx, ny, nz, lam, mu, rho, dx, dt, nt, opts, workspace, ws_bytes, stream) -> int:
+    ctx = _vp(0)
+    _check(_lib.fd3d_create(ctypes.byref(ctx), nx, ny, nz, lam, mu, rho, float(dx), float(dt), int(nt),
+                            ctypes.byref(opts) if opts is not None else None, workspace, ws_bytes, stream))
+    return int(ctx.value)
+
+
+def fd3d_forward(ctx, src: fd3d_source | None, nrec: int, rec_pos_ptr, traces, flags: int, stream) -> None:
+    _check(_lib.fd3d_forward(ctx, ctypes.byref(src) if src is not None else None, nrec,
+                             ctypes.cast(rec_pos_ptr, _dp) if rec_pos_ptr else None, traces, flags, stream))
+
+
+def _ptr9(fields):
+    arr = (_vp * 9)(*[int(p) for p in fields])
+    return arr
+
+
+def fd3d_get_state(ctx, fields, stream) -> None:
+    _check(_lib.fd3d_get_state(ctx, _ptr9(fields), stream))
+
+
+def fd3d_set_state(ctx, fields, stream) -> None:
+    _check(_lib.fd3d_set_state(ctx, _ptr9(fields), stream))
+
+
+def fd3d_model_info(ctx):
+    out = (ctypes.c_double * 4)()
+    _check(_lib.fd3d_model_info(ctx, out))
+    return list(out)
+
+
+def fd3d_profile(ctx, enable: bool) -> None:
+    _check(_lib.fd3d_profile(ctx, int(bool(enable))))
+
+
+def fd3d_profile_read(ctx):
+    """Summed ms and launch counts per pass (velocity, record, stress) of the last call."""
+    ms = (ctypes.c_double * 3)()
+    n = (ctypes.c_int * 3)()
+    _check(_lib.fd3d_profile_read(ctx, ms, n))
+    return list(ms), list(n)
+
+
+def fd3d_destroy(ctx) -> None:
+    _lib.fd3d_destroy(ctx)

@@ -1,0 +1,72 @@
+// Shared device-side definitions of the fd3d HIP library (gfx950).
+//
+// Field order, staggering (Sec. 2.1.1), the Eq.(4) weights and the kernel
+// parameter blocks used by every pass.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fd3d {
+
+enum Field { VX = 0, VY, VZ, SXX, SYY, SZZ, SXY, SXZ, SYZ, NFIELD };
+
+// Half-offset flags (x, y, z) of each component, Sec. 2.1.1.
+__host__ __device__ constexpr int stag(int c, int axis)
+{
+    return (c == VX) ? (axis == 0)
+         : (c == VY) ? (axis == 1)
+         : (c == VZ) ? (axis == 2)
+         : (c == SXY) ? (axis != 2)
+         : (c == SXZ) ? (axis != 1)
+         : (c == SYZ) ? (axis != 0)
+         : 0;
+}
+
+// Eq.(4): weights of f(x+1/2)-f(x-1/2) and f(x+3/2)-f(x-3/2).
+template <typename T> __host__ __device__ constexpr T c1() { return T(9.0 / 8.0); }
+template <typename T> __host__ __device__ constexpr T c2() { return T(-1.0 / 24.0); }
+
+// Staggered derivative from the two differences of Eq.(4), times 1/dx.
+template <typename T>
+__device__ __forceinline__ T dstag(T near_hi, T near_lo, T far_hi, T far_lo, T rdx)
+{
+    return (c1<T>() * (near_hi - near_lo) + c2<T>() * (far_hi - far_lo)) * rdx;
+}
+
+// Everything a pass needs about one grid.  Arrays are x-fastest, unpadded.
+template <typename T> struct Grid {
+    int nx, ny, nz;
+    long sy, sz;           // strides of y and z (nx, nx*ny)
+    T dt, rdx;             // time step and 1/dx
+    const T *lam, *mu, *rho;
+    T *f[NFIELD];
+    const T *g[3][2];      // damping profile per axis at integer [0] / half [1] positions
+};
+
+// A point source as kernel argument: per component, the base of its 2x2x2 tap box
+// on that component's subgrid and the eight coefficients (x fastest, then y, z).
+// Velocity components: dt w F / dx^3 (times b and s[n] in the kernel).
+// Stress components:  -dt w M / dx^3 (times s[n] in the kernel).
+template <typename T> struct Inject {
+    int on;
+    int i0[NFIELD], j0[NFIELD], k0[NFIELD];
+    T c[NFIELD][8];
+    const T *wavelet;
+};
+
+// One receiver component: eight storage indices (-1: none) and trilinear weights.
+template <typename T> struct RecTap {
+    int idx[8];
+    T w[8];
+};
+
+// Tap number of (i,j,k) in a source box, or -1.
+template <typename T>
+__device__ __forceinline__ int tap_of(const Inject<T> &s, int c, int i, int j, int k)
+{
+    unsigned a = (unsigned)(i - s.i0[c]), b = (unsigned)(j - s.j0[c]), d = (unsigned)(k - s.k0[c]);
+    return (a < 2u && b < 2u && d < 2u) ? (int)(a + 2u * b + 4u * d) : -1;
+}
+
+} // namespace fd3d

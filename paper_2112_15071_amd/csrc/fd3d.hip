@@ -1,0 +1,553 @@
+// fd3d.hip -- host side of the C ABI declared in include/fd3d.h.
+//
+// Validation, workspace layout, damping profiles, point-operator weights and the
+// step loop that enqueues the velocity pass, the receiver sampling and the
+// stress pass of every step on the caller's stream (Sec. 2.2 update order).
+#include "fd3d.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "fwd_cell.h"
+#include "util_kernels.h"
+
+using namespace fd3d;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(FD3D_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kDefaultMaxRec = 4096;
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t rectap_bytes(int tsize) { return 8 * sizeof(int) + 8 * (size_t)tsize; }
+
+// Workspace layout (byte offsets).  Fields are padded to 4 KiB plus a 1 KiB skew so
+// that the nine streams of a pass do not start on the same HBM channel.
+struct Layout {
+    size_t field[NFIELD];
+    size_t prof[3][2];
+    size_t rec;
+    size_t part;
+    size_t stats;
+    size_t flag;
+    size_t total;
+    size_t field_bytes;
+};
+
+Layout make_layout(int nx, int ny, int nz, int tsize, int max_rec)
+{
+    Layout L{};
+    size_t off = 0;
+    L.field_bytes = (size_t)nx * ny * nz * tsize;
+    const size_t stride = round_up(L.field_bytes, 4096) + 1024;
+    for (int f = 0; f < NFIELD; ++f) {
+        L.field[f] = off;
+        off += stride;
+    }
+    const int n[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a)
+        for (int h = 0; h < 2; ++h) {
+            L.prof[a][h] = off;
+            off += round_up((size_t)n[a] * tsize, kAlign);
+        }
+    L.rec = off;
+    off += round_up((size_t)max_rec * 3 * rectap_bytes(tsize), kAlign);
+    L.part = off;
+    off += round_up((size_t)kReduceBlocks * kStats * sizeof(double), kAlign);
+    L.stats = off;
+    off += round_up(kStats * sizeof(double), kAlign);
+    L.flag = off;
+    off += kAlign;
+    L.total = off;
+    return L;
+}
+
+int check_opts(const fd3d_opts *o)
+{
+    if (o->dtype != FD3D_F32 && o->dtype != FD3D_F64) return fail(FD3D_EINVAL, "opts.dtype must be FD3D_F32 or FD3D_F64");
+    for (int f = 0; f < 6; ++f)
+        if (o->sponge[f] < 0) return fail(FD3D_EINVAL, "opts.sponge widths must be >= 0");
+    if (!std::isfinite(o->sponge_alpha)) return fail(FD3D_EINVAL, "opts.sponge_alpha must be finite");
+    return FD3D_OK;
+}
+
+fd3d_opts default_opts()
+{
+    fd3d_opts o;
+    std::memset(&o, 0, sizeof o);
+    o.dtype = FD3D_F32;
+    o.max_receivers = kDefaultMaxRec;
+    return o;
+}
+
+int max_rec_of(const fd3d_opts &o) { return o.max_receivers > 0 ? o.max_receivers : kDefaultMaxRec; }
+
+// Cerjan factor of one face at distance d (cells) from it.
+double face_factor(double d, int width, double alpha)
+{
+    if (width <= 0 || d >= width) return 1.0;
+    const double a = alpha > 0.0 ? alpha : 0.3 / width;
+    const double t = a * (width - d);
+    return std::exp(-t * t);
+}
+
+// Eight trilinear taps of point p on component c's subgrid; false when a tap is not
+// an active sample.
+bool point_taps(int c, const double p[3], const int n[3], int base[3], double w[8])
+{
+    double fr[3];
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(p[a])) return false;
+        const double q = p[a] - 0.5 * stag(c, a);
+        const double b = std::floor(q);
+        const int last = n[a] - 1 - stag(c, a);
+        if (b < 0.0 || b + 1.0 > (double)last) return false;
+        base[a] = (int)b;
+        fr[a] = q - b;
+    }
+    int m = 0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx)
+                w[m++] = (dx ? fr[0] : 1.0 - fr[0]) * (dy ? fr[1] : 1.0 - fr[1]) * (dz ? fr[2] : 1.0 - fr[2]);
+    return true;
+}
+
+} // namespace
+
+struct fd3d_ctx {
+    int n[3];
+    int nt;
+    int tsize;
+    double dx, dt;
+    fd3d_opts opts;
+    const void *lam, *mu, *rho;
+    char *ws;
+    size_t ws_bytes;
+    Layout L;
+    double info[4];
+    std::vector<unsigned char> prof_host;  // typed profiles, kept for the async upload
+    std::vector<unsigned char> rec_host;   // receiver descriptors, kept for the async upload
+    hipEvent_t staged;
+    bool staged_pending;
+    // optional per-kernel timing of the step loop
+    int prof_on;
+    std::vector<hipEvent_t> prof_ev;  // pairs: [2*q] before, [2*q+1] after launch q
+    std::vector<int> prof_pass;       // pass of launch q
+    int prof_used;
+};
+
+namespace {
+
+template <typename T> Grid<T> make_grid(const fd3d_ctx *c)
+{
+    Grid<T> G;
+    G.nx = c->n[0];
+    G.ny = c->n[1];
+    G.nz = c->n[2];
+    G.sy = G.nx;
+    G.sz = (long)G.nx * G.ny;
+    G.dt = (T)c->dt;
+    G.rdx = (T)(1.0 / c->dx);
+    G.lam = (const T *)c->lam;
+    G.mu = (const T *)c->mu;
+    G.rho = (const T *)c->rho;
+    for (int f = 0; f < NFIELD; ++f) G.f[f] = (T *)(c->ws + c->L.field[f]);
+    for (int a = 0; a < 3; ++a)
+        for (int h = 0; h < 2; ++h) G.g[a][h] = (const T *)(c->ws + c->L.prof[a][h]);
+    return G;
+}
+
+template <typename T> int upload_profiles(fd3d_ctx *c, hipStream_t st)
+{
+    const int top = c->opts.free_surface ? 0 : c->opts.sponge[4];
+    const int width[3][2] = {{c->opts.sponge[0], c->opts.sponge[1]},
+                             {c->opts.sponge[2], c->opts.sponge[3]},
+                             {top, c->opts.sponge[5]}};
+    size_t total = 0;
+    for (int a = 0; a < 3; ++a) total += 2 * (size_t)c->n[a];
+    c->prof_host.assign(total * sizeof(T), 0);
+    T *h = (T *)c->prof_host.data();
+    size_t off = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int half = 0; half < 2; ++half) {
+            const int n = c->n[a];
+            for (int i = 0; i < n; ++i) {
+                const double pos = i + 0.5 * half;
+                h[off + i] = (T)(face_factor(pos, width[a][0], c->opts.sponge_alpha) *
+                                 face_factor((n - 1) - pos, width[a][1], c->opts.sponge_alpha));
+            }
+            HIP_TRY(hipMemcpyAsync(c->ws + c->L.prof[a][half], h + off, n * sizeof(T), hipMemcpyHostToDevice, st));
+            off += n;
+        }
+    return FD3D_OK;
+}
+
+template <typename T> int model_check(fd3d_ctx *c, hipStream_t st)
+{
+    const long N = (long)c->n[0] * c->n[1] * c->n[2];
+    double *part = (double *)(c->ws + c->L.part);
+    double *out = (double *)(c->ws + c->L.stats);
+    model_stats<T><<<kReduceBlocks, kReduceThreads, 0, st>>>((const T *)c->lam, (const T *)c->mu,
+                                                            (const T *)c->rho, N, part);
+    stats_final<<<1, kReduceThreads, 0, st>>>(part, kReduceBlocks, out);
+    HIP_TRY(hipGetLastError());
+    double s[kStats];
+    HIP_TRY(hipMemcpyAsync(s, out, sizeof s, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (s[5] != 0.0) return fail(FD3D_EMODEL, "model holds a non-finite value");
+    if (!(s[2] > 0.0)) return fail(FD3D_EMODEL, "rho must be > 0 everywhere");
+    if (s[3] < 0.0) return fail(FD3D_EMODEL, "mu must be >= 0 everywhere");
+    if (!(s[4] > 0.0)) return fail(FD3D_EMODEL, "lambda + 2 mu must be > 0 everywhere");
+    const double bound = 6.0 / (7.0 * std::sqrt(3.0));  // 1 / (sqrt(3) (9/8 + 1/24))
+    c->info[0] = s[0];
+    c->info[1] = s[1] < 1e299 ? s[1] : 0.0;
+    c->info[2] = s[2];
+    c->info[3] = bound * c->dx / s[0];
+    if (c->dt > c->info[3] * (1.0 + 1e-12))
+        return fail(FD3D_ECFL, "dt = " + std::to_string(c->dt) + " exceeds the stability bound " +
+                                   std::to_string(c->info[3]) + " (6/(7 sqrt 3) dx / vp_max)");
+    return FD3D_OK;
+}
+
+template <typename T> void zero_fields(fd3d_ctx *c, hipStream_t st)
+{
+    const long n = (long)((c->L.field[NFIELD - 1] + c->L.field_bytes) / sizeof(T));
+    fill_zero<T><<<2048, 256, 0, st>>>((T *)c->ws, n);
+}
+
+template <typename T> int build_source(const fd3d_ctx *c, const fd3d_source *src, Inject<T> &inj)
+{
+    std::memset(&inj, 0, sizeof inj);
+    for (int f = 0; f < NFIELD; ++f) inj.i0[f] = inj.j0[f] = inj.k0[f] = -(1 << 28);
+    if (!src) return FD3D_OK;
+    const double h3 = c->dx * c->dx * c->dx;
+    int base[3];
+    double w[8];
+    bool any = false;
+    for (int q = 0; q < 3; ++q) {
+        if (src->force[q] == 0.0) continue;
+        if (!std::isfinite(src->force[q])) return fail(FD3D_EINVAL, "source force must be finite");
+        if (!point_taps(VX + q, src->pos, c->n, base, w))
+            return fail(FD3D_ERANGE, "force source taps leave the active samples of v" + std::string(1, "xyz"[q]));
+        inj.i0[VX + q] = base[0]; inj.j0[VX + q] = base[1]; inj.k0[VX + q] = base[2];
+        for (int m = 0; m < 8; ++m) inj.c[VX + q][m] = (T)(c->dt * w[m] * src->force[q] / h3);
+        any = true;
+    }
+    for (int q = 0; q < 6; ++q)
+        if (!std::isfinite(src->moment[q])) return fail(FD3D_EINVAL, "source moment must be finite");
+    if (src->moment[0] != 0.0 || src->moment[1] != 0.0 || src->moment[2] != 0.0) {
+        if (!point_taps(SXX, src->pos, c->n, base, w))
+            return fail(FD3D_ERANGE, "moment source taps leave the normal-stress grid");
+        for (int q = 0; q < 3; ++q) {
+            inj.i0[SXX + q] = base[0]; inj.j0[SXX + q] = base[1]; inj.k0[SXX + q] = base[2];
+            for (int m = 0; m < 8; ++m) inj.c[SXX + q][m] = (T)(-c->dt * w[m] * src->moment[q] / h3);
+        }
+        any = true;
+    }
+    for (int q = 3; q < 6; ++q) {
+        if (src->moment[q] == 0.0) continue;
+        const int comp = SXY + (q - 3);
+        if (!point_taps(comp, src->pos, c->n, base, w))
+            return fail(FD3D_ERANGE, "moment source taps leave the shear-stress grid");
+        inj.i0[comp] = base[0]; inj.j0[comp] = base[1]; inj.k0[comp] = base[2];
+        for (int m = 0; m < 8; ++m) inj.c[comp][m] = (T)(-c->dt * w[m] * src->moment[q] / h3);
+        any = true;
+    }
+    if (any && !src->wavelet) return fail(FD3D_EINVAL, "source wavelet pointer is NULL");
+    inj.on = any ? 1 : 0;
+    inj.wavelet = (const T *)src->wavelet;
+    return FD3D_OK;
+}
+
+template <typename T> int stage_receivers(fd3d_ctx *c, int nrec, const double *rec_pos, hipStream_t st)
+{
+    if (nrec == 0) return FD3D_OK;
+    if (c->staged_pending) {
+        HIP_TRY(hipEventSynchronize(c->staged));
+        c->staged_pending = false;
+    }
+    c->rec_host.assign((size_t)nrec * 3 * sizeof(RecTap<T>), 0);
+    RecTap<T> *t = (RecTap<T> *)c->rec_host.data();
+    int base[3];
+    double w[8];
+    for (int r = 0; r < nrec; ++r)
+        for (int q = 0; q < 3; ++q) {
+            if (!point_taps(VX + q, rec_pos + 3 * r, c->n, base, w))
+                return fail(FD3D_ERANGE, "receiver " + std::to_string(r) + " taps leave the active samples of v" +
+                                             std::string(1, "xyz"[q]));
+            RecTap<T> &d = t[r * 3 + q];
+            int m = 0;
+            for (int dz = 0; dz < 2; ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        d.idx[m] = (base[0] + dx) + c->n[0] * ((base[1] + dy) + c->n[1] * (base[2] + dz));
+                        d.w[m] = (T)w[m];
+                        ++m;
+                    }
+        }
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.rec, c->rec_host.data(), c->rec_host.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(c->staged, st));
+    c->staged_pending = true;
+    return FD3D_OK;
+}
+
+// Event pair around one launch when timing is on.
+struct Timer {
+    fd3d_ctx *c;
+    hipStream_t st;
+    void begin(int pass)
+    {
+        if (!c->prof_on) return;
+        const int q = c->prof_used;
+        if ((size_t)(2 * q + 2) > c->prof_ev.size()) {
+            hipEvent_t a, b;
+            hipEventCreate(&a);
+            hipEventCreate(&b);
+            c->prof_ev.push_back(a);
+            c->prof_ev.push_back(b);
+            c->prof_pass.push_back(pass);
+        }
+        c->prof_pass[q] = pass;
+        hipEventRecord(c->prof_ev[2 * q], st);
+    }
+    void end()
+    {
+        if (!c->prof_on) return;
+        hipEventRecord(c->prof_ev[2 * c->prof_used + 1], st);
+        ++c->prof_used;
+    }
+};
+
+template <typename T, bool FS>
+void step(const Grid<T> &G, const Inject<T> &inj, int n, int nrec, int nt, const RecTap<T> *taps, T *traces,
+          hipStream_t st, Timer &tm)
+{
+    const dim3 blk(64, 4, 1);
+    const dim3 grd((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
+    tm.begin(0);
+    vel_cell<T, FS><<<grd, blk, 0, st>>>(G, inj, n);
+    tm.end();
+    if (nrec > 0) {
+        tm.begin(1);
+        record<T><<<(3 * nrec + 255) / 256, 256, 0, st>>>(G.f[VX], G.f[VY], G.f[VZ], taps, nrec, nt, n, traces);
+        tm.end();
+    }
+    tm.begin(2);
+    stress_cell<T, FS><<<grd, blk, 0, st>>>(G, inj, n);
+    tm.end();
+}
+
+template <typename T>
+int forward_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *rec_pos, void *traces, int flags,
+                 hipStream_t st)
+{
+    Inject<T> inj;
+    int rc = build_source<T>(c, src, inj);
+    if (rc) return rc;
+    rc = stage_receivers<T>(c, nrec, rec_pos, st);
+    if (rc) return rc;
+    if (!(flags & FD3D_KEEP_STATE)) zero_fields<T>(c, st);
+    const Grid<T> G = make_grid<T>(c);
+    const RecTap<T> *taps = (const RecTap<T> *)(c->ws + c->L.rec);
+    Timer tm{c, st};
+    c->prof_used = 0;
+    for (int n = 0; n < c->nt; ++n) {
+        if (c->opts.free_surface) step<T, true>(G, inj, n, nrec, c->nt, taps, (T *)traces, st, tm);
+        else step<T, false>(G, inj, n, nrec, c->nt, taps, (T *)traces, st, tm);
+    }
+    HIP_TRY(hipGetLastError());
+    if (c->opts.check_finite) {
+        int *flag = (int *)(c->ws + c->L.flag);
+        fill_zero<int><<<1, 64, 0, st>>>(flag, 1);
+        finite_check<T><<<1024, 256, 0, st>>>(G, flag);
+        HIP_TRY(hipGetLastError());
+        int h = 0;
+        HIP_TRY(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (h) return fail(FD3D_ENONFINITE, "non-finite value in the final state");
+    }
+    return FD3D_OK;
+}
+
+template <typename T> int set_state_impl(fd3d_ctx *c, const void *const fields[9], hipStream_t st)
+{
+    const Grid<T> G = make_grid<T>(c);
+    for (int f = 0; f < NFIELD; ++f)
+        copy_masked<T><<<1024, 256, 0, st>>>(G.f[f], (const T *)fields[f], G.nx, G.ny, G.nz, stag(f, 0), stag(f, 1),
+                                             stag(f, 2));
+    HIP_TRY(hipGetLastError());
+    return FD3D_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *fd3d_version(void) { return "fd3d 0.1.0 (gfx950)"; }
+
+const char *fd3d_last_error(void) { return g_err.c_str(); }
+
+int fd3d_workspace_bytes(int nx, int ny, int nz, const fd3d_opts *opts, size_t *bytes)
+{
+    if (!bytes) return fail(FD3D_EINVAL, "bytes is NULL");
+    if (nx < 4 || ny < 4 || nz < 4) return fail(FD3D_EINVAL, "grid must have at least 4 nodes per axis");
+    if ((double)nx * ny * nz >= 2147483647.0) return fail(FD3D_EINVAL, "grid must hold fewer than 2^31 nodes");
+    fd3d_opts o = opts ? *opts : default_opts();
+    int rc = check_opts(&o);
+    if (rc) return rc;
+    const int tsize = o.dtype == FD3D_F64 ? 8 : 4;
+    *bytes = make_layout(nx, ny, nz, tsize, max_rec_of(o)).total;
+    return FD3D_OK;
+}
+
+int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const void *mu, const void *rho, double dx,
+                double dt, int nt, const fd3d_opts *opts, void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    if (!out) return fail(FD3D_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    int rc = fd3d_workspace_bytes(nx, ny, nz, opts, &need);
+    if (rc) return rc;
+    if (!lam || !mu || !rho) return fail(FD3D_EINVAL, "model pointer is NULL");
+    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(FD3D_EINVAL, "dx must be > 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FD3D_EINVAL, "dt must be > 0");
+    if (nt < 0) return fail(FD3D_EINVAL, "nt must be >= 0");
+    if (!workspace || ((uintptr_t)workspace % kAlign)) return fail(FD3D_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return fail(FD3D_EWS, "workspace too small: need " + std::to_string(need) + " bytes");
+    fd3d_ctx *c = new (std::nothrow) fd3d_ctx();
+    if (!c) return fail(FD3D_EINVAL, "out of host memory");
+    c->n[0] = nx; c->n[1] = ny; c->n[2] = nz;
+    c->nt = nt;
+    c->opts = opts ? *opts : default_opts();
+    c->opts.max_receivers = max_rec_of(c->opts);
+    c->tsize = c->opts.dtype == FD3D_F64 ? 8 : 4;
+    c->dx = dx;
+    c->dt = dt;
+    c->lam = lam; c->mu = mu; c->rho = rho;
+    c->ws = (char *)workspace;
+    c->ws_bytes = ws_bytes;
+    c->L = make_layout(nx, ny, nz, c->tsize, c->opts.max_receivers);
+    c->staged_pending = false;
+    c->prof_on = 0;
+    c->prof_used = 0;
+    if (hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return fail(FD3D_EHIP, "hipEventCreateWithFlags failed");
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (c->tsize == 8) {
+        rc = model_check<double>(c, st);
+        if (!rc) rc = upload_profiles<double>(c, st);
+        if (!rc) zero_fields<double>(c, st);
+    } else {
+        rc = model_check<float>(c, st);
+        if (!rc) rc = upload_profiles<float>(c, st);
+        if (!rc) zero_fields<float>(c, st);
+    }
+    if (!rc && hipGetLastError() != hipSuccess) rc = fail(FD3D_EHIP, "launch failed in fd3d_create");
+    if (!rc) rc = hipStreamSynchronize(st) == hipSuccess ? FD3D_OK : fail(FD3D_EHIP, "hipStreamSynchronize failed");
+    if (rc) {
+        hipEventDestroy(c->staged);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return FD3D_OK;
+}
+
+int fd3d_forward(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *rec_pos, void *traces, int flags,
+                 void *hip_stream)
+{
+    if (!ctx) return fail(FD3D_EINVAL, "ctx is NULL");
+    if (nrec < 0 || nrec > ctx->opts.max_receivers)
+        return fail(FD3D_EINVAL, "nrec must be in [0, max_receivers = " + std::to_string(ctx->opts.max_receivers) + "]");
+    if (nrec > 0 && (!rec_pos || !traces)) return fail(FD3D_EINVAL, "rec_pos/traces is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    return ctx->tsize == 8 ? forward_impl<double>(ctx, src, nrec, rec_pos, traces, flags, st)
+                           : forward_impl<float>(ctx, src, nrec, rec_pos, traces, flags, st);
+}
+
+int fd3d_get_state(fd3d_ctx *ctx, void *const fields[9], void *hip_stream)
+{
+    if (!ctx || !fields) return fail(FD3D_EINVAL, "ctx/fields is NULL");
+    for (int f = 0; f < NFIELD; ++f)
+        if (!fields[f]) return fail(FD3D_EINVAL, "field pointer is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    for (int f = 0; f < NFIELD; ++f)
+        HIP_TRY(hipMemcpyAsync(fields[f], ctx->ws + ctx->L.field[f], ctx->L.field_bytes, hipMemcpyDeviceToDevice, st));
+    return FD3D_OK;
+}
+
+int fd3d_set_state(fd3d_ctx *ctx, const void *const fields[9], void *hip_stream)
+{
+    if (!ctx || !fields) return fail(FD3D_EINVAL, "ctx/fields is NULL");
+    for (int f = 0; f < NFIELD; ++f)
+        if (!fields[f]) return fail(FD3D_EINVAL, "field pointer is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    return ctx->tsize == 8 ? set_state_impl<double>(ctx, fields, st) : set_state_impl<float>(ctx, fields, st);
+}
+
+int fd3d_model_info(const fd3d_ctx *ctx, double out[4])
+{
+    if (!ctx || !out) return fail(FD3D_EINVAL, "ctx/out is NULL");
+    for (int q = 0; q < 4; ++q) out[q] = ctx->info[q];
+    return FD3D_OK;
+}
+
+int fd3d_profile(fd3d_ctx *ctx, int enable)
+{
+    if (!ctx) return fail(FD3D_EINVAL, "ctx is NULL");
+    ctx->prof_on = enable ? 1 : 0;
+    return FD3D_OK;
+}
+
+int fd3d_profile_read(fd3d_ctx *ctx, double ms[3], int launches[3])
+{
+    if (!ctx || !ms || !launches) return fail(FD3D_EINVAL, "ctx/ms/launches is NULL");
+    for (int p = 0; p < 3; ++p) { ms[p] = 0.0; launches[p] = 0; }
+    if (ctx->prof_used == 0) return FD3D_OK;
+    HIP_TRY(hipEventSynchronize(ctx->prof_ev[2 * ctx->prof_used - 1]));
+    for (int q = 0; q < ctx->prof_used; ++q) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, ctx->prof_ev[2 * q], ctx->prof_ev[2 * q + 1]));
+        const int p = ctx->prof_pass[q];
+        if (p >= 0 && p < 3) { ms[p] += t; launches[p] += 1; }
+    }
+    return FD3D_OK;
+}
+
+void fd3d_destroy(fd3d_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->staged_pending) hipEventSynchronize(ctx->staged);
+    hipEventDestroy(ctx->staged);
+    for (hipEvent_t e : ctx->prof_ev) {
+        hipEventSynchronize(e);
+        hipEventDestroy(e);
+    }
+    delete ctx;
+}
+
+} // extern "C"

@@ -1,0 +1,144 @@
+"""Torch-facing wrapper of the fd3d C ABI: device memory and streams come from torch,
+every step of the method runs in the HIP library.
+
+    sim = Simulator(lam, mu, rho, dx=10.0, dt=1e-3, nt=500, sponge=20)
+    traces = sim.forward(src_pos=(32, 32, 32), moment=(1e15, 1e15, 1e15, 0, 0, 0),
+                         wavelet=w, rec_pos=rec)            # [nrec, 3, nt] on the GPU
+    state = sim.state()                                     # [9, nz, ny, nx]
+"""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi
+
+FIELDS = ("vx", "vy", "vz", "sxx", "syy", "szz", "sxy", "sxz", "syz")
+
+
+def _dtype_code(dtype: torch.dtype) -> int:
+    if dtype == torch.float32:
+        return _abi.FD3D_F32
+    if dtype == torch.float64:
+        return _abi.FD3D_F64
+    raise ValueError("dtype must be torch.float32 or torch.float64")
+
+
+def _stream() -> int:
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def make_opts(dtype: torch.dtype, sponge=0, sponge_alpha: float = 0.0, free_surface: bool = False,
+              check_finite: bool = False, max_receivers: int = 4096) -> _abi.fd3d_opts:
+    o = _abi.fd3d_opts()
+    o.dtype = _dtype_code(dtype)
+    sp = [int(sponge)] * 6 if np.isscalar(sponge) else [int(v) for v in sponge]
+    if len(sp) != 6:
+        raise ValueError("sponge is one width or six (x-, x+, y-, y+, z-, z+)")
+    for f in range(6):
+        o.sponge[f] = sp[f]
+    o.sponge_alpha = float(sponge_alpha)
+    o.free_surface = int(bool(free_surface))
+    o.check_finite = int(bool(check_finite))
+    o.max_receivers = int(max_receivers)
+    return o
+
+
+def make_source(pos, moment=(0.0,) * 6, force=(0.0,) * 3, wavelet: Optional[torch.Tensor] = None) -> _abi.fd3d_source:
+    s = _abi.fd3d_source()
+    for a in range(3):
+        s.pos[a] = float(pos[a])
+        s.force[a] = float(force[a])
+    for q in range(6):
+        s.moment[q] = float(moment[q])
+    s.wavelet = int(wavelet.data_ptr()) if wavelet is not None else None
+    return s
+
+
+class Simulator:
+    """One grid and model on one GPU; forward runs of ``nt`` steps."""
+
+    def __init__(self, lam, mu, rho, dx: float, dt: float, nt: int, dtype: torch.dtype = torch.float32,
+                 sponge=20, sponge_alpha: float = 0.0, free_surface: bool = False, check_finite: bool = False,
+                 max_receivers: int = 4096, device="cuda"):
+        self.device = torch.device(device)
+        self.dtype = dtype
+        self.lam, self.mu, self.rho = (torch.as_tensor(a).to(device=self.device, dtype=dtype).contiguous()
+                                       for a in (lam, mu, rho))
+        if self.lam.dim() != 3 or self.mu.shape != self.lam.shape or self.rho.shape != self.lam.shape:
+            raise ValueError("lam, mu, rho must share one [nz, ny, nx] shape")
+        nz, ny, nx = self.lam.shape
+        self.shape = (nx, ny, nz)
+        self.dx, self.dt, self.nt = float(dx), float(dt), int(nt)
+        self.opts = make_opts(dtype, sponge, sponge_alpha, free_surface, check_finite, max_receivers)
+        nbytes = _abi.fd3d_workspace_bytes(nx, ny, nz, self.opts)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._ctx = _abi.fd3d_create(nx, ny, nz, self.lam.data_ptr(), self.mu.data_ptr(), self.rho.data_ptr(),
+                                     self.dx, self.dt, self.nt, self.opts, self.workspace.data_ptr(), nbytes, _stream())
+        self._rec_keep = None
+
+    # -- helpers -------------------------------------------------------------
+    def _wavelet(self, wavelet) -> Optional[torch.Tensor]:
+        if wavelet is None:
+            return None
+        w = torch.as_tensor(wavelet).to(device=self.device, dtype=self.dtype).contiguous()
+        if w.numel() != self.nt:
+            raise ValueError(f"wavelet needs nt = {self.nt} samples")
+        return w
+
+    @staticmethod
+    def _rec(rec_pos):
+        if rec_pos is None:
+            return np.zeros((0, 3)), 0
+        r = np.ascontiguousarray(np.asarray(rec_pos, dtype=np.float64).reshape(-1, 3))
+        return r, r.shape[0]
+
+    @property
+    def ctx(self) -> int:
+        return self._ctx
+
+    def info(self):
+        """(vp_max, vs_min, rho_min, dt_max) read back at creation."""
+        return _abi.fd3d_model_info(self._ctx)
+
+    # -- public API ----------------------------------------------------------
+    def forward(self, src_pos=None, moment=(0.0,) * 6, force=(0.0,) * 3, wavelet=None, rec_pos=None,
+                keep_state: bool = False, traces: Optional[torch.Tensor] = None) -> torch.Tensor:
+        w = self._wavelet(wavelet)
+        src = make_source(src_pos, moment, force, w) if src_pos is not None else None
+        rp, nrec = self._rec(rec_pos)
+        if traces is None:
+            traces = torch.empty((nrec, 3, self.nt), dtype=self.dtype, device=self.device)
+        flags = _abi.FD3D_KEEP_STATE if keep_state else 0
+        _abi.fd3d_forward(self._ctx, src, nrec, rp.ctypes.data if nrec else None,
+                          traces.data_ptr() if nrec else None, flags, _stream())
+        self._rec_keep = (rp, w)  # host/device inputs stay referenced until the next call
+        return traces
+
+    def state(self) -> torch.Tensor:
+        nx, ny, nz = self.shape
+        out = torch.empty((9, nz, ny, nx), dtype=self.dtype, device=self.device)
+        _abi.fd3d_get_state(self._ctx, [out[f].data_ptr() for f in range(9)], _stream())
+        return out
+
+    def set_state(self, st) -> None:
+        nx, ny, nz = self.shape
+        st = torch.as_tensor(st).to(device=self.device, dtype=self.dtype).contiguous()
+        if tuple(st.shape) != (9, nz, ny, nx):
+            raise ValueError("state must be [9, nz, ny, nx]")
+        self._state_keep = st
+        _abi.fd3d_set_state(self._ctx, [st[f].data_ptr() for f in range(9)], _stream())
+
+    def close(self) -> None:
+        if getattr(self, "_ctx", 0):
+            torch.cuda.current_stream().synchronize()
+            _abi.fd3d_destroy(self._ctx)
+            self._ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,45 @@
+"""Runs one workload through the HIP library and through the oracle (test-side glue)."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+from helpers import rel_l2
+
+
+def oracle_run(shot, nt=None, state=None):
+    nt = shot.nt if nt is None else nt
+    cfg = oracle.Config(shot.shape, shot.h, shot.dt, nt, sponge=shot.sponge, alpha=shot.alpha,
+                        free_surface=shot.free_surface)
+    src = oracle.Source(shot.src_pos, moment=shot.moment, force=shot.force)
+    return oracle.forward(cfg, shot.lam, shot.mu, shot.rho, src, shot.wavelet[:nt], shot.rec_pos, state=state)
+
+
+def gpu_run(shot, dtype, nt=None, **kw):
+    from paper_2112_15071_amd import Simulator
+
+    nt = shot.nt if nt is None else nt
+    sim = Simulator(shot.lam, shot.mu, shot.rho, shot.h, shot.dt, nt, dtype=dtype, sponge=shot.sponge,
+                    sponge_alpha=shot.alpha, free_surface=shot.free_surface, **kw)
+    tr = sim.forward(shot.src_pos, shot.moment, shot.force, shot.wavelet[:nt], shot.rec_pos)
+    st = sim.state()
+    torch.cuda.synchronize()
+    out = tr.double().cpu().numpy(), st.double().cpu().numpy()
+    sim.close()
+    return out
+
+
+def compare(gpu, ref, tol, what=""):
+    """rel-L2 per trace component (over receivers and samples) and per field."""
+    tr, st = gpu
+    rtr, rst = ref
+    worst = {}
+    for c in range(3):
+        worst[f"trace_{'xyz'[c]}"] = rel_l2(tr[:, c], rtr[:, c])
+    for f in range(9):
+        if np.linalg.norm(rst[f]) > 0:
+            worst[f"field_{f}"] = rel_l2(st[f], rst[f])
+    bad = {k: v for k, v in worst.items() if not v <= tol}
+    assert not bad, f"{what}: rel-L2 above {tol}: {bad}"
+    return worst

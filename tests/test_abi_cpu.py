@@ -1,0 +1,54 @@
+"""CPU checks of the C ABI: the library loads without a GPU and exports every function
+include/fd3d.h declares; host-only calls validate their arguments."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:const\s+)?(?:int|void|char|size_t)\s*\*?\s*(fd3d_\w+)\s*\(", text, re.M))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    import ctypes
+
+    from paper_2112_15071_amd import _abi
+
+    names = declared()
+    assert len(names) >= 9
+    lib = ctypes.CDLL(_abi.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert names <= set(_abi.exported_symbols()) | set(), names - set(_abi.exported_symbols())
+
+
+def test_host_only_calls():
+    from paper_2112_15071_amd import _abi
+
+    assert _abi.fd3d_version().startswith("fd3d")
+    o = _abi.fd3d_opts()
+    o.dtype = _abi.FD3D_F32
+    a = _abi.fd3d_workspace_bytes(64, 64, 64, o)
+    o.dtype = _abi.FD3D_F64
+    b = _abi.fd3d_workspace_bytes(64, 64, 64, o)
+    assert a >= 9 * 64 ** 3 * 4 and b >= 9 * 64 ** 3 * 8
+    for bad in [(3, 64, 64), (64, 0, 64)]:
+        with pytest.raises(_abi.FD3DError) as e:
+            _abi.fd3d_workspace_bytes(*bad, o)
+        assert e.value.code == _abi.FD3D_EINVAL
+    o.dtype = 7
+    with pytest.raises(_abi.FD3DError):
+        _abi.fd3d_workspace_bytes(64, 64, 64, o)
+    o.dtype = 0
+    o.sponge[2] = -1
+    with pytest.raises(_abi.FD3DError):
+        _abi.fd3d_workspace_bytes(64, 64, 64, o)
+    assert "sponge" in _abi.fd3d_last_error()

@@ -1,0 +1,137 @@
+"""GPU parity of the forward pass against the FP64 oracle: per trace component and per
+final field, rel-L2 <= 1e-4 in FP32 and <= 1e-12 in FP64, on the small workload at
+full length, on ragged grids with every source kind and the free surface, and at the
+full sizes of the 256^3 and 512x512x256 workloads on truncated step counts."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_cases import compare, gpu_run, oracle_run
+from helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float32: 1e-4, torch.float64: 1e-12}
+
+
+MID = 150
+
+
+@pytest.fixture(scope="module")
+def c0_ref():
+    """Oracle run of the 64^3 workload in two legs: 150 steps (wavefield filling the
+    box) and the remaining 350 (continued from the stored state)."""
+    import oracle
+
+    shot = W.c0()
+    print(f"[c0] oracle 64^3 x {shot.nt}", flush=True)
+    tr1, st1 = oracle_run(shot, nt=MID)
+    cfg = oracle.Config(shot.shape, shot.h, shot.dt, shot.nt - MID, sponge=shot.sponge)
+    src = oracle.Source(shot.src_pos, moment=shot.moment, force=shot.force)
+    tr2, st2 = oracle.forward(cfg, shot.lam, shot.mu, shot.rho, src, shot.wavelet[MID:], shot.rec_pos, state=st1)
+    return shot, (tr1, st1), (np.concatenate([tr1, tr2], axis=2), st2)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_c0_full_length(c0_ref, dtype):
+    """Traces over all 500 steps (rel-L2 per component).  By step 500 the sponge has
+    absorbed ~99.9 % of the field norm, so each final field's error is measured against
+    that field's norm at step 150, when the wavefield fills the box."""
+    shot, mid, ref = c0_ref
+    print(f"[c0] gpu {dtype}", flush=True)
+    got = gpu_run(shot, dtype)
+    assert np.all(np.abs(ref[0]).max(axis=(0, 2)) > 0)  # every component recorded something
+    compare((got[0], ref[1]), ref, TOL[dtype], f"c0 traces {dtype}")
+    for f in range(9):
+        err = np.linalg.norm(got[1][f] - ref[1][f]) / np.linalg.norm(mid[1][f])
+        assert err <= TOL[dtype], (f, err)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_c0_snapshot_midway(c0_ref, dtype):
+    """All nine fields after 150 steps, rel-L2 against their own norm."""
+    shot, mid, _ = c0_ref
+    got = gpu_run(shot, dtype, nt=MID)
+    compare(got, mid, TOL[dtype], f"c0 {MID} steps {dtype}")
+
+
+def ragged_shot(free_surface, seed, force=False):
+    shape = (37, 29, 23)
+    lam, mu, rho = W.layered_perturbed(shape, 10.0, seed)
+    nt = 160
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mt = W.random_mt(rng)
+    f = (2e10, -1e10, 3e10) if force else (0.0, 0.0, 0.0)
+    rec = np.array([[5.25, 6.5, 1.0], [30.6, 20.1, 1.0], [17.0, 14.0, 11.5], [9.9, 21.3, 18.2]])
+    wav = W.ricker(40.0, nt, 5e-4)
+    sponge = (6, 5, 4, 7, 0 if free_surface else 5, 6)
+    return W.Shot("ragged", shape, 10.0, 5e-4, nt, lam, mu, rho, (18.4, 13.7, 6.6), mt, f, wav, rec,
+                  sponge=sponge, free_surface=free_surface)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("free_surface", [False, True])
+@pytest.mark.parametrize("force", [False, True])
+def test_ragged_grids(dtype, free_surface, force):
+    shot = ragged_shot(free_surface, 2024 + int(free_surface) + 2 * int(force), force)
+    print(f"[ragged] fs={free_surface} force={force} {dtype}", flush=True)
+    ref = oracle_run(shot)
+    got = gpu_run(shot, dtype)
+    compare(got, ref, TOL[dtype], f"ragged fs={free_surface} force={force}")
+
+
+C1_NT = 16
+
+
+@pytest.fixture(scope="module")
+def c1_ref():
+    shot = W.c1()
+    print(f"[c1] oracle 256^3 x {C1_NT}", flush=True)
+    return shot, oracle_run(shot, nt=C1_NT)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_c1_full_size_truncated(c1_ref, dtype):
+    """256^3 layered model, the launch configuration of the benchmark, 16 steps."""
+    shot, ref = c1_ref
+    print(f"[c1] gpu 256^3 x {C1_NT} {dtype}", flush=True)
+    got = gpu_run(shot, dtype, nt=C1_NT)
+    compare(got, ref, TOL[dtype], "c1 truncated")
+
+
+def test_c2_full_size_truncated():
+    """512x512x256 with the free surface and the 30-cell sponge, 6 steps, FP32."""
+    shot = W.c2()
+    nt = 6
+    print(f"[c2] 512x512x256 x {nt}", flush=True)
+    ref = oracle_run(shot, nt=nt)
+    got = gpu_run(shot, torch.float32, nt=nt)
+    compare(got, ref, TOL[torch.float32], "c2 truncated")
+
+
+def test_c1_full_length_mirror_symmetry():
+    """Property at the full 256^3 x 2000 size: a centred explosion in a homogeneous model
+    gives fields that are even/odd under each axis mirror."""
+    from paper_2112_15071_amd import Simulator
+
+    n = 256
+    lam, mu, rho = W.homogeneous((n, n, n))
+    nt = 2000
+    sim = Simulator(lam, mu, rho, 10.0, 5e-4, nt, dtype=torch.float32, sponge=20)
+    c = (n - 1) / 2.0
+    sim.forward((c, c, c), W.explosion(), (0, 0, 0), W.ricker(12.0, nt, 5e-4), None)
+    st = sim.state().double()
+    odd = {0: {0, 6, 7}, 1: {1, 6, 8}, 2: {2, 7, 8}}
+    stagf = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (0, 0, 0), (0, 0, 0), (0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+    for a in range(3):
+        for f in range(9):
+            x = st[f]
+            d = 2 - a
+            core = x.narrow(d, 0, n - 1) if stagf[f][a] else x
+            mir = torch.flip(core, dims=[d])
+            sign = -1.0 if f in odd[a] else 1.0
+            scale = core.abs().max().item()
+            err = (core - sign * mir).abs().max().item()
+            assert err <= 1e-6 * scale, (a, f, err, scale)
+    sim.close()
