@@ -59,6 +59,10 @@ extern "C" {
 #define FD3D_F32 0
 #define FD3D_F64 1
 
+/* kernel variants of the step loop (fd3d_set_kernel) */
+#define FD3D_KERNEL_CELL 0 /* one thread per cell, neighbours from global memory */
+#define FD3D_KERNEL_TILE 1 /* LDS-staged x/y halo planes + register z sweep (default) */
+
 /* fd3d_forward flags */
 #define FD3D_KEEP_STATE 1 /* start from the current state instead of zeros */
 
@@ -116,6 +120,21 @@ int fd3d_set_state(fd3d_ctx *ctx, const void *const fields[9], void *hip_stream)
 /* Model statistics read back at create: out[0] = vp_max, out[1] = vs_min over mu > 0
  * (0 if none), out[2] = rho_min, out[3] = largest stable dt (m/s, m/s, kg/m^3, s). */
 int fd3d_model_info(const fd3d_ctx *ctx, double out[4]);
+
+/* Kernel selection for the step loop of later calls on this context.  All variants
+ * compute the same update with the same operation order per sample. */
+typedef struct fd3d_kernel {
+    int variant;  /* FD3D_KERNEL_CELL or FD3D_KERNEL_TILE */
+    int tile_x;   /* tile columns: 64, 128 or 256 */
+    int tile_y;   /* tile rows: FP32 64x{4,8,16}, 128x{4,8}, 256x4; FP64 64x{4,8}, 128x4 */
+    int zchunk;   /* z planes swept by one workgroup, >= 4 */
+} fd3d_kernel;
+
+/* Default at create: FD3D_KERNEL_TILE with 256x4 tiles (FP32, nx >= 256), 128x4
+ * (nx >= 128) or 64x8, and 64-plane sweeps (nz >= 128) or 32.  FD3D_EINVAL for an
+ * unsupported shape. */
+int fd3d_set_kernel(fd3d_ctx *ctx, const fd3d_kernel *k);
+int fd3d_get_kernel(const fd3d_ctx *ctx, fd3d_kernel *k);
 
 /* Per-kernel timing of the step loop.  With enable = 1, later forward calls record a
  * HIP event pair on the caller's stream around every kernel launch of the loop (the

@@ -25,6 +25,8 @@ FD3D_ESTATE = -8
 FD3D_F32 = 0
 FD3D_F64 = 1
 FD3D_KEEP_STATE = 1
+FD3D_KERNEL_CELL = 0
+FD3D_KERNEL_TILE = 1
 
 ERRNAMES = {
     FD3D_EINVAL: "FD3D_EINVAL", FD3D_ECFL: "FD3D_ECFL", FD3D_EMODEL: "FD3D_EMODEL", FD3D_ERANGE: "FD3D_ERANGE",
@@ -46,6 +48,15 @@ class fd3d_opts(ctypes.Structure):
         ("free_surface", ctypes.c_int),
         ("check_finite", ctypes.c_int),
         ("max_receivers", ctypes.c_int),
+    ]
+
+
+class fd3d_kernel(ctypes.Structure):
+    _fields_ = [
+        ("variant", ctypes.c_int),
+        ("tile_x", ctypes.c_int),
+        ("tile_y", ctypes.c_int),
+        ("zchunk", ctypes.c_int),
     ]
 
 
@@ -78,6 +89,8 @@ _SIGS = {
     "fd3d_get_state": ([_vp, ctypes.POINTER(_vp), _vp], _i),
     "fd3d_set_state": ([_vp, ctypes.POINTER(_vp), _vp], _i),
     "fd3d_model_info": ([_vp, _dp], _i),
+    "fd3d_set_kernel": ([_vp, ctypes.POINTER(fd3d_kernel)], _i),
+    "fd3d_get_kernel": ([_vp, ctypes.POINTER(fd3d_kernel)], _i),
     "fd3d_profile": ([_vp, _i], _i),
     "fd3d_profile_read": ([_vp, _dp, ctypes.POINTER(_i)], _i),
     "fd3d_destroy": ([_vp], None),
@@ -142,6 +155,16 @@ def fd3d_model_info(ctx):
     out = (ctypes.c_double * 4)()
     _check(_lib.fd3d_model_info(ctx, out))
     return list(out)
+
+
+def fd3d_set_kernel(ctx, k: fd3d_kernel) -> None:
+    _check(_lib.fd3d_set_kernel(ctx, ctypes.byref(k)))
+
+
+def fd3d_get_kernel(ctx) -> fd3d_kernel:
+    k = fd3d_kernel()
+    _check(_lib.fd3d_get_kernel(ctx, ctypes.byref(k)))
+    return k
 
 
 def fd3d_profile(ctx, enable: bool) -> None:

@@ -15,6 +15,7 @@
 
 #include "common.h"
 #include "fwd_cell.h"
+#include "fwd_tile.h"
 #include "util_kernels.h"
 
 using namespace fd3d;
@@ -156,6 +157,11 @@ struct fd3d_ctx {
     std::vector<hipEvent_t> prof_ev;  // pairs: [2*q] before, [2*q+1] after launch q
     std::vector<int> prof_pass;       // pass of launch q
     int prof_used;
+    // kernel selection for the step loop
+    int variant;  // FD3D_KERNEL_CELL or FD3D_KERNEL_TILE
+    int tile_x;   // columns of a tile (64, 128, 256)
+    int tile_y;   // rows of a tile (4, 8, 16)
+    int zchunk;   // z planes per workgroup sweep
 };
 
 namespace {
@@ -322,40 +328,94 @@ struct Timer {
         if (!c->prof_on) return;
         const int q = c->prof_used;
         if ((size_t)(2 * q + 2) > c->prof_ev.size()) {
-            hipEvent_t a, b;
-            hipEventCreate(&a);
-            hipEventCreate(&b);
+            hipEvent_t a = nullptr, b = nullptr;
+            (void)hipEventCreate(&a);
+            (void)hipEventCreate(&b);
             c->prof_ev.push_back(a);
             c->prof_ev.push_back(b);
             c->prof_pass.push_back(pass);
         }
         c->prof_pass[q] = pass;
-        hipEventRecord(c->prof_ev[2 * q], st);
+        (void)hipEventRecord(c->prof_ev[2 * q], st);
     }
     void end()
     {
         if (!c->prof_on) return;
-        hipEventRecord(c->prof_ev[2 * c->prof_used + 1], st);
+        (void)hipEventRecord(c->prof_ev[2 * c->prof_used + 1], st);
         ++c->prof_used;
     }
 };
 
+TileMap tile_map(const fd3d_ctx *c)
+{
+    TileMap tm;
+    tm.ntx = (c->n[0] + c->tile_x - 1) / c->tile_x;
+    tm.nty = (c->n[1] + c->tile_y - 1) / c->tile_y;
+    tm.zc = c->zchunk;
+    tm.nzc = (c->n[2] + c->zchunk - 1) / c->zchunk;
+    return tm;
+}
+
+template <typename T, int TX, int TY, bool FS>
+void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &tm, int pass, hipStream_t st)
+{
+    const int nwg = tm.ntx * tm.nty * tm.nzc;
+    if (pass == 0) vel_tile<T, TX, TY, FS><<<nwg, TX * TY, 0, st>>>(G, inj, n, tm);
+    else stress_tile<T, TX, TY, FS><<<nwg, TX * TY, 0, st>>>(G, inj, n, tm);
+}
+
+// Supported tile shapes: 64x{4,8,16}, 128x{4,8}, 256x4 (FP64: 64x{4,8}, 128x4).
+bool tile_supported(int tsize, int tx, int ty)
+{
+    if (tsize == 8) return (tx == 64 && (ty == 4 || ty == 8)) || (tx == 128 && ty == 4);
+    return (tx == 64 && (ty == 4 || ty == 8 || ty == 16)) || (tx == 128 && (ty == 4 || ty == 8)) ||
+           (tx == 256 && ty == 4);
+}
+
 template <typename T, bool FS>
-void step(const Grid<T> &G, const Inject<T> &inj, int n, int nrec, int nt, const RecTap<T> *taps, T *traces,
+void launch_pass(const fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int pass, hipStream_t st)
+{
+    if (c->variant == FD3D_KERNEL_CELL) {
+        const dim3 blk(64, 4, 1);
+        const dim3 grd((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
+        if (pass == 0) vel_cell<T, FS><<<grd, blk, 0, st>>>(G, inj, n);
+        else stress_cell<T, FS><<<grd, blk, 0, st>>>(G, inj, n);
+        return;
+    }
+    const TileMap tm = tile_map(c);
+    const int key = c->tile_x * 100 + c->tile_y;
+    if (sizeof(T) == 8) {
+        switch (key) {
+        case 6404: launch_tiles<T, 64, 4, FS>(G, inj, n, tm, pass, st); break;
+        case 12804: launch_tiles<T, 128, 4, FS>(G, inj, n, tm, pass, st); break;
+        default: launch_tiles<T, 64, 8, FS>(G, inj, n, tm, pass, st); break;
+        }
+        return;
+    }
+    switch (key) {
+    case 6404: launch_tiles<T, 64, 4, FS>(G, inj, n, tm, pass, st); break;
+    case 6416: launch_tiles<T, 64, 16, FS>(G, inj, n, tm, pass, st); break;
+    case 12804: launch_tiles<T, 128, 4, FS>(G, inj, n, tm, pass, st); break;
+    case 12808: launch_tiles<T, 128, 8, FS>(G, inj, n, tm, pass, st); break;
+    case 25604: launch_tiles<T, 256, 4, FS>(G, inj, n, tm, pass, st); break;
+    default: launch_tiles<T, 64, 8, FS>(G, inj, n, tm, pass, st); break;
+    }
+}
+
+template <typename T, bool FS>
+void step(fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int nrec, const RecTap<T> *taps, T *traces,
           hipStream_t st, Timer &tm)
 {
-    const dim3 blk(64, 4, 1);
-    const dim3 grd((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
     tm.begin(0);
-    vel_cell<T, FS><<<grd, blk, 0, st>>>(G, inj, n);
+    launch_pass<T, FS>(c, G, inj, n, 0, st);
     tm.end();
     if (nrec > 0) {
         tm.begin(1);
-        record<T><<<(3 * nrec + 255) / 256, 256, 0, st>>>(G.f[VX], G.f[VY], G.f[VZ], taps, nrec, nt, n, traces);
+        record<T><<<(3 * nrec + 255) / 256, 256, 0, st>>>(G.f[VX], G.f[VY], G.f[VZ], taps, nrec, c->nt, n, traces);
         tm.end();
     }
     tm.begin(2);
-    stress_cell<T, FS><<<grd, blk, 0, st>>>(G, inj, n);
+    launch_pass<T, FS>(c, G, inj, n, 1, st);
     tm.end();
 }
 
@@ -374,8 +434,8 @@ int forward_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
     Timer tm{c, st};
     c->prof_used = 0;
     for (int n = 0; n < c->nt; ++n) {
-        if (c->opts.free_surface) step<T, true>(G, inj, n, nrec, c->nt, taps, (T *)traces, st, tm);
-        else step<T, false>(G, inj, n, nrec, c->nt, taps, (T *)traces, st, tm);
+        if (c->opts.free_surface) step<T, true>(c, G, inj, n, nrec, taps, (T *)traces, st, tm);
+        else step<T, false>(c, G, inj, n, nrec, taps, (T *)traces, st, tm);
     }
     HIP_TRY(hipGetLastError());
     if (c->opts.check_finite) {
@@ -452,6 +512,13 @@ int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const v
     c->staged_pending = false;
     c->prof_on = 0;
     c->prof_used = 0;
+    // default tile shape by row length (measured on MI355X at 256^3: 256x4 tiles with
+    // 64-plane sweeps keep one 1024-thread workgroup per CU and 1 KiB row segments)
+    c->variant = FD3D_KERNEL_TILE;
+    if (c->tsize == 4 && nx >= 256) { c->tile_x = 256; c->tile_y = 4; }
+    else if (nx >= 128) { c->tile_x = 128; c->tile_y = 4; }
+    else { c->tile_x = 64; c->tile_y = 8; }
+    c->zchunk = nz >= 128 ? 64 : 32;
     if (hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess) {
         delete c;
         return fail(FD3D_EHIP, "hipEventCreateWithFlags failed");
@@ -469,7 +536,7 @@ int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const v
     if (!rc && hipGetLastError() != hipSuccess) rc = fail(FD3D_EHIP, "launch failed in fd3d_create");
     if (!rc) rc = hipStreamSynchronize(st) == hipSuccess ? FD3D_OK : fail(FD3D_EHIP, "hipStreamSynchronize failed");
     if (rc) {
-        hipEventDestroy(c->staged);
+        (void)hipEventDestroy(c->staged);
         delete c;
         return rc;
     }
@@ -516,6 +583,32 @@ int fd3d_model_info(const fd3d_ctx *ctx, double out[4])
     return FD3D_OK;
 }
 
+int fd3d_set_kernel(fd3d_ctx *ctx, const fd3d_kernel *k)
+{
+    if (!ctx || !k) return fail(FD3D_EINVAL, "ctx/k is NULL");
+    if (k->variant != FD3D_KERNEL_CELL && k->variant != FD3D_KERNEL_TILE) return fail(FD3D_EINVAL, "unknown kernel variant");
+    if (k->variant == FD3D_KERNEL_TILE && !tile_supported(ctx->tsize, k->tile_x, k->tile_y))
+        return fail(FD3D_EINVAL, "unsupported tile shape " + std::to_string(k->tile_x) + "x" + std::to_string(k->tile_y));
+    if (k->zchunk < 4) return fail(FD3D_EINVAL, "zchunk must be >= 4");
+    ctx->variant = k->variant;
+    if (k->variant == FD3D_KERNEL_TILE) {
+        ctx->tile_x = k->tile_x;
+        ctx->tile_y = k->tile_y;
+    }
+    ctx->zchunk = k->zchunk;
+    return FD3D_OK;
+}
+
+int fd3d_get_kernel(const fd3d_ctx *ctx, fd3d_kernel *k)
+{
+    if (!ctx || !k) return fail(FD3D_EINVAL, "ctx/k is NULL");
+    k->variant = ctx->variant;
+    k->tile_x = ctx->tile_x;
+    k->tile_y = ctx->tile_y;
+    k->zchunk = ctx->zchunk;
+    return FD3D_OK;
+}
+
 int fd3d_profile(fd3d_ctx *ctx, int enable)
 {
     if (!ctx) return fail(FD3D_EINVAL, "ctx is NULL");
@@ -541,11 +634,11 @@ int fd3d_profile_read(fd3d_ctx *ctx, double ms[3], int launches[3])
 void fd3d_destroy(fd3d_ctx *ctx)
 {
     if (!ctx) return;
-    if (ctx->staged_pending) hipEventSynchronize(ctx->staged);
-    hipEventDestroy(ctx->staged);
+    if (ctx->staged_pending) (void)hipEventSynchronize(ctx->staged);
+    (void)hipEventDestroy(ctx->staged);
     for (hipEvent_t e : ctx->prof_ev) {
-        hipEventSynchronize(e);
-        hipEventDestroy(e);
+        (void)hipEventSynchronize(e);
+        (void)hipEventDestroy(e);
     }
     delete ctx;
 }

@@ -1,0 +1,501 @@
+// Tiled forward passes: LDS-staged (x, y) halo planes, register-streamed z sweep.
+//
+// A workgroup owns a TX x TY column tile and sweeps a chunk of z planes.  Per plane,
+// every field is read from HBM once: the owner thread loads its own sample, a few
+// threads load the x/y halo of the LDS plane, and the z neighbours come from a
+// per-thread register queue.  All loads of plane k+1 are issued before the compute of
+// plane k (software pipelining), so one barrier per plane is the only stall.  LDS
+// planes are double-buffered (a ring of three for the two-plane mu window).
+//
+// Memory access is branch-free: fields are read and written through raw buffer
+// descriptors, one per z plane.  A sample outside the grid gets an out-of-range byte
+// offset (the load returns 0, the store is dropped) and a plane outside the chunk gets
+// an empty descriptor, so the loop body has no divergent memory operations and the
+// compiler can wait on exactly the loads each step needs.  Uniform per-plane values
+// (damping profile along z, wavelet sample) come through the scalar cache.
+//
+// Workgroup ids are remapped so that each XCD receives a contiguous block of tiles
+// (hardware dispatches consecutive ids round-robin over the 8 XCDs), which keeps the
+// halo rows shared by neighbouring tiles inside one XCD's L2.
+#pragma once
+
+#include "common.h"
+
+namespace fd3d {
+
+// Tile decomposition of a grid: ntx x nty column tiles, nzc z-chunks of zc planes.
+struct TileMap {
+    int ntx, nty, nzc, zc;
+};
+
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+constexpr unsigned kOOB = 0x80000000u;  // byte offset past every plane (< 2 GiB per plane)
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer descriptor, gfx9-family word 3
+
+// Descriptor over plane kk of field f; empty (every access out of range) unless ok.
+template <typename T>
+__device__ __forceinline__ rsrc_t plane(const T *f, int kk, long sz, bool ok)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(f + (ok ? kk * sz : 0)), (short)0,
+                                             ok ? (int)(sz * (long)sizeof(T)) : 0, kRsrcWord3);
+}
+
+__device__ __forceinline__ float bload(rsrc_t r, unsigned off, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double bload(rsrc_t r, unsigned off, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <typename T> __device__ __forceinline__ T ld(rsrc_t r, unsigned off) { return bload(r, off, T(0)); }
+
+__device__ __forceinline__ void st(rsrc_t r, unsigned off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st(rsrc_t r, unsigned off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
+// Uniform value through the scalar cache.
+template <typename T> __device__ __forceinline__ T sload(const T *p, int idx)
+{
+    typedef const __attribute__((address_space(4))) T cT;
+    return ((cT *)p)[idx];
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int nwg)
+{
+    const int q = nwg >> 3, r = nwg & 7;
+    const int x = b & 7, local = b >> 3;
+    return x * q + (x < r ? x : r) + local;
+}
+
+// One halo element of an LDS plane owned by this thread: LDS index (the array's dummy
+// slot when the thread has none) and in-plane byte offset (kOOB outside the grid).
+struct Slot {
+    int lds;
+    unsigned off;
+};
+
+// x-halo element e of a plane of width TX+LEFT+RIGHT whose TY core rows start at row OY.
+template <typename T, int TX, int TY, int LEFT, int RIGHT, int OY>
+__device__ __forceinline__ Slot xslot(int e, int i0, int j0, int nx, int ny, int sy, int dummy)
+{
+    constexpr int W = TX + LEFT + RIGHT;
+    constexpr int NH = (LEFT + RIGHT) * TY;
+    Slot s{dummy, kOOB};
+    if (e < NH) {
+        const int row = e / (LEFT + RIGHT), c = e % (LEFT + RIGHT);
+        const int col = c < LEFT ? c : TX + c;
+        const int gi = i0 - LEFT + col, gj = j0 + row;
+        s.lds = (row + OY) * W + col;
+        if (gi >= 0 && gi < nx && gj < ny) s.off = (unsigned)(gi + sy * gj) * (unsigned)sizeof(T);
+    }
+    return s;
+}
+
+// y-halo element e of a plane with TOP/BOT halo rows over the TX core columns at column OX.
+template <typename T, int TX, int TY, int TOP, int BOT, int OX, int W>
+__device__ __forceinline__ Slot yslot(int e, int i0, int j0, int nx, int ny, int sy, int dummy)
+{
+    constexpr int NH = (TOP + BOT) * TX;
+    Slot s{dummy, kOOB};
+    if (e < NH) {
+        const int r = e / TX, col = e % TX;
+        const int row = r < TOP ? r : TY + r;
+        const int gi = i0 + col, gj = j0 - TOP + row;
+        s.lds = row * W + col + OX;
+        if (gi < nx && gj >= 0 && gj < ny) s.off = (unsigned)(gi + sy * gj) * (unsigned)sizeof(T);
+    }
+    return s;
+}
+
+// Bottom-right corner element of a (+1, +1) plane, owned by one thread.
+template <typename T, int TX, int TY>
+__device__ __forceinline__ Slot cslot(bool mine, int i0, int j0, int nx, int ny, int sy, int dummy)
+{
+    Slot s{dummy, kOOB};
+    if (mine) {
+        s.lds = TY * (TX + 1) + TX;
+        const int gi = i0 + TX, gj = j0 + TY;
+        if (gi < nx && gj < ny) s.off = (unsigned)(gi + sy * gj) * (unsigned)sizeof(T);
+    }
+    return s;
+}
+
+__device__ __forceinline__ void tile_coords(const TileMap &tm, int &i0, int &j0, int &k0, int &k1, int TX, int TY,
+                                            int nz)
+{
+    int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tz = t % tm.nzc;
+    t /= tm.nzc;
+    const int bx = t % tm.ntx, by = t / tm.ntx;
+    i0 = bx * TX;
+    j0 = by * TY;
+    k0 = tz * tm.zc;
+    k1 = min(k0 + tm.zc, nz);
+}
+
+// Coefficient of tap t (or 0) without a data-dependent memory access.
+template <typename T> __device__ __forceinline__ T pick(const T (&c)[8], int t)
+{
+    T v = T(0);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v = (t == m) ? c[m] : v;
+    return v;
+}
+
+// ---------------------------------------------------------------------------------
+// (V) velocity pass, tiled.  Same arithmetic per sample as vel_cell.
+template <typename T, int TX, int TY, bool FS>
+__global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
+{
+    constexpr int NT = TX * TY;
+    // LDS plane shapes: sxx x(-1,+2); sxy x(-2,+1) y(-2,+1); sxz x(-2,+1); syy y(-1,+2);
+    // syz y(-2,+1); rho x(+1) y(+1) with the corner.  The last element is a dummy slot.
+    constexpr int W3 = TX + 3, H3 = TY + 3, WR = TX + 1, HR = TY + 1;
+    constexpr int NXX = TY * W3, NXY = H3 * W3, NXZ = TY * W3, NYY = H3 * TX, NYZ = H3 * TX, NR = HR * WR;
+    __shared__ T s_xx[2][NXX + 1];
+    __shared__ T s_xy[2][NXY + 1];
+    __shared__ T s_xz[2][NXZ + 1];
+    __shared__ T s_yy[2][NYY + 1];
+    __shared__ T s_yz[2][NYZ + 1];
+    __shared__ T s_r[2][NR + 1];
+
+    int i0, j0, k0, k1;
+    tile_coords(tm, i0, j0, k0, k1, TX, TY, G.nz);
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const int sy = (int)G.sy;
+    const long sz = G.sz;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool in = i < nx && j < ny;
+    const unsigned oc = in ? (unsigned)(i + sy * j) * (unsigned)sizeof(T) : kOOB;  // own column
+
+    // halo slots (fixed over the sweep); x-halo work on the last threads, y-halo on the first
+    const int ex = NT - 1 - tid;
+    const Slot hxx = xslot<T, TX, TY, 1, 2, 0>(ex, i0, j0, nx, ny, sy, NXX);
+    const Slot hxyx = xslot<T, TX, TY, 2, 1, 2>(ex, i0, j0, nx, ny, sy, NXY);
+    const Slot hxz = xslot<T, TX, TY, 2, 1, 0>(ex, i0, j0, nx, ny, sy, NXZ);
+    const Slot hyy = yslot<T, TX, TY, 1, 2, 0, TX>(tid, i0, j0, nx, ny, sy, NYY);
+    const Slot hxyy = yslot<T, TX, TY, 2, 1, 2, W3>(tid, i0, j0, nx, ny, sy, NXY);
+    const Slot hyz = yslot<T, TX, TY, 2, 1, 0, TX>(tid, i0, j0, nx, ny, sy, NYZ);
+    const Slot hrx = xslot<T, TX, TY, 0, 1, 0>(ex, i0, j0, nx, ny, sy, NR);
+    const Slot hry = yslot<T, TX, TY, 0, 1, 0, WR>(tid, i0, j0, nx, ny, sy, NR);
+    const Slot hrc = cslot<T, TX, TY>(tid == NT / 2, i0, j0, nx, ny, sy, NR);
+    const int own_c3 = ty * W3;  // row base in the x-halo planes without y halo
+
+    const T *fxx = G.f[SXX], *fyy = G.f[SYY], *fzz = G.f[SZZ];
+    const T *fxy = G.f[SXY], *fxz = G.f[SXZ], *fyz = G.f[SYZ];
+    const T *rho = G.rho;
+    const T rdx = G.rdx, dt = G.dt;
+    const T s = src.on ? sload(src.wavelet, n) : T(0);
+    const T gxh = in ? G.g[0][1][i] : T(0), gxi = in ? G.g[0][0][i] : T(0);
+    const T gyh = in ? G.g[1][1][j] : T(0), gyi = in ? G.g[1][0][j] : T(0);
+    const unsigned st_vx = (in && i <= nx - 2) ? oc : kOOB;
+    const unsigned st_vy = (in && j <= ny - 2) ? oc : kOOB;
+
+    auto zld = [&](const T *f, int kk, bool ok) -> T { return ld<T>(plane(f, kk, sz, ok && kk >= 0 && kk < nz), oc); };
+
+    // z queues at the first plane (with the free-surface odd images above k = 0)
+    T qxz[4], qyz[4], qzz[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int kk = k0 - 2 + m;
+        if (FS && kk < 0) {
+            qxz[m] = -zld(fxz, -1 - kk, true);
+            qyz[m] = -zld(fyz, -1 - kk, true);
+        } else {
+            qxz[m] = zld(fxz, kk, true);
+            qyz[m] = zld(fyz, kk, true);
+        }
+        const int kz = k0 - 1 + m;
+        qzz[m] = (FS && kz < 0) ? -zld(fzz, -kz, true) : zld(fzz, kz, true);
+    }
+    T r0 = zld(rho, k0, true), r1 = zld(rho, k0 + 1, true);
+
+    // plane registers, loaded one plane ahead
+    struct Plane {
+        T cxx, cyy, cxy, vx, vy, vz, xx, xyx, xz, yy, xyy, yz, rx, ry, rc;
+    };
+    auto loadplane = [&](int kk, bool ok, Plane &P) {
+        const rsrc_t bxx = plane(fxx, kk, sz, ok), byy = plane(fyy, kk, sz, ok), bxy = plane(fxy, kk, sz, ok);
+        const rsrc_t bxz = plane(fxz, kk, sz, ok), byz = plane(fyz, kk, sz, ok), br = plane(rho, kk, sz, ok);
+        P.cxx = ld<T>(bxx, oc);
+        P.cyy = ld<T>(byy, oc);
+        P.cxy = ld<T>(bxy, oc);
+        P.vx = ld<T>(plane(G.f[VX], kk, sz, ok), oc);
+        P.vy = ld<T>(plane(G.f[VY], kk, sz, ok), oc);
+        P.vz = ld<T>(plane(G.f[VZ], kk, sz, ok), oc);
+        P.xx = ld<T>(bxx, hxx.off);
+        P.xyx = ld<T>(bxy, hxyx.off);
+        P.xz = ld<T>(bxz, hxz.off);
+        P.yy = ld<T>(byy, hyy.off);
+        P.xyy = ld<T>(bxy, hxyy.off);
+        P.yz = ld<T>(byz, hyz.off);
+        P.rx = ld<T>(br, hrx.off);
+        P.ry = ld<T>(br, hry.off);
+        P.rc = ld<T>(br, hrc.off);
+    };
+    Plane P;
+    loadplane(k0, true, P);
+
+    for (int k = k0; k < k1; ++k) {
+        const int b = (k - k0) & 1;
+        T *Lxx = s_xx[b], *Lxy = s_xy[b], *Lxz = s_xz[b], *Lyy = s_yy[b], *Lyz = s_yz[b], *Lr = s_r[b];
+        // own samples and halos of plane k
+        Lxx[own_c3 + tx + 1] = P.cxx;
+        Lxy[(ty + 2) * W3 + tx + 2] = P.cxy;
+        Lxz[own_c3 + tx + 2] = qxz[2];
+        Lyy[(ty + 1) * TX + tx] = P.cyy;
+        Lyz[(ty + 2) * TX + tx] = qyz[2];
+        Lr[ty * WR + tx] = r0;
+        Lxx[hxx.lds] = P.xx;
+        Lxy[hxyx.lds] = P.xyx;
+        Lxz[hxz.lds] = P.xz;
+        Lyy[hyy.lds] = P.yy;
+        Lxy[hxyy.lds] = P.xyy;
+        Lyz[hyz.lds] = P.yz;
+        Lr[hrx.lds] = P.rx;
+        Lr[hry.lds] = P.ry;
+        Lr[hrc.lds] = P.rc;
+        const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
+        // loads of plane k+1 and the queue heads (empty descriptors past the chunk)
+        const bool more = k + 1 < k1;
+        loadplane(k + 1, more, P);
+        const T nxz = zld(fxz, k + 2, more), nyz = zld(fyz, k + 2, more);
+        const T nzz = zld(fzz, k + 3, more), nr = zld(rho, k + 2, more);
+        const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
+        __syncthreads();
+
+        const rsrc_t ovx = plane(G.f[VX], k, sz, true), ovy = plane(G.f[VY], k, sz, true);
+        const rsrc_t ovz = plane(G.f[VZ], k, sz, true);
+        {
+            const int o = own_c3 + tx + 1;
+            const int ox = (ty + 2) * W3 + tx + 2;
+            const T d = dstag(Lxx[o + 1], Lxx[o], Lxx[o + 2], Lxx[o - 1], rdx)
+                      + dstag(Lxy[ox], Lxy[ox - W3], Lxy[ox + W3], Lxy[ox - 2 * W3], rdx)
+                      + dstag(qxz[2], qxz[1], qxz[3], qxz[0], rdx);
+            const T bb = T(1) / ((r0 + Lr[ty * WR + tx + 1]) / T(2));
+            T v = vx0 + dt * bb * d;
+            v += bb * pick(src.c[VX], tap_of(src, VX, i, j, k)) * s;
+            st(ovx, st_vx, v * (gxh * gyi * gz_i));
+        }
+        {
+            const int ox = (ty + 2) * W3 + tx + 2;
+            const int oy = (ty + 1) * TX + tx;
+            const T d = dstag(Lxy[ox], Lxy[ox - 1], Lxy[ox + 1], Lxy[ox - 2], rdx)
+                      + dstag(Lyy[oy + TX], Lyy[oy], Lyy[oy + 2 * TX], Lyy[oy - TX], rdx)
+                      + dstag(qyz[2], qyz[1], qyz[3], qyz[0], rdx);
+            const T bb = T(1) / ((r0 + Lr[(ty + 1) * WR + tx]) / T(2));
+            T v = vy0 + dt * bb * d;
+            v += bb * pick(src.c[VY], tap_of(src, VY, i, j, k)) * s;
+            st(ovy, st_vy, v * (gxi * gyh * gz_i));
+        }
+        {
+            const int o = own_c3 + tx + 2;
+            const int oy = (ty + 2) * TX + tx;
+            const T d = dstag(Lxz[o], Lxz[o - 1], Lxz[o + 1], Lxz[o - 2], rdx)
+                      + dstag(Lyz[oy], Lyz[oy - TX], Lyz[oy + TX], Lyz[oy - 2 * TX], rdx)
+                      + dstag(qzz[2], qzz[1], qzz[3], qzz[0], rdx);
+            const T bb = T(1) / ((r0 + r1) / T(2));
+            T v = vz0 + dt * bb * d;
+            v += bb * pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s;
+            st(ovz, k <= nz - 2 ? oc : kOOB, v * (gxi * gyi * gz_h));
+        }
+        qxz[0] = qxz[1]; qxz[1] = qxz[2]; qxz[2] = qxz[3]; qxz[3] = nxz;
+        qyz[0] = qyz[1]; qyz[1] = qyz[2]; qyz[2] = qyz[3]; qyz[3] = nyz;
+        qzz[0] = qzz[1]; qzz[1] = qzz[2]; qzz[2] = qzz[3]; qzz[3] = nzz;
+        r0 = r1; r1 = nr;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// (S) stress pass, tiled.  Same arithmetic per sample as stress_cell.
+template <typename T, int TX, int TY, bool FS>
+__global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
+{
+    constexpr int NT = TX * TY;
+    // vx x(-2,+1) y(-1,+2); vy x(-1,+2) y(-2,+1); vz x(-1,+2) y(-1,+2); mu x(+1) y(+1) corner
+    constexpr int W3 = TX + 3, H3 = TY + 3, WM = TX + 1, HM = TY + 1;
+    constexpr int NV = H3 * W3, NM = HM * WM;
+    __shared__ T s_vx[2][NV + 1];
+    __shared__ T s_vy[2][NV + 1];
+    __shared__ T s_vz[2][NV + 1];
+    __shared__ T s_mu[3][NM + 1];
+
+    int i0, j0, k0, k1;
+    tile_coords(tm, i0, j0, k0, k1, TX, TY, G.nz);
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const int sy = (int)G.sy;
+    const long sz = G.sz;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool in = i < nx && j < ny;
+    const unsigned oc = in ? (unsigned)(i + sy * j) * (unsigned)sizeof(T) : kOOB;
+
+    const int ex = NT - 1 - tid;
+    const Slot hvxx = xslot<T, TX, TY, 2, 1, 1>(ex, i0, j0, nx, ny, sy, NV);
+    const Slot hvxy = yslot<T, TX, TY, 1, 2, 2, W3>(tid, i0, j0, nx, ny, sy, NV);
+    const Slot hvyx = xslot<T, TX, TY, 1, 2, 2>(ex, i0, j0, nx, ny, sy, NV);
+    const Slot hvyy = yslot<T, TX, TY, 2, 1, 1, W3>(tid, i0, j0, nx, ny, sy, NV);
+    const Slot hvzx = xslot<T, TX, TY, 1, 2, 1>(ex, i0, j0, nx, ny, sy, NV);
+    const Slot hvzy = yslot<T, TX, TY, 1, 2, 1, W3>(tid, i0, j0, nx, ny, sy, NV);
+    const Slot hmx = xslot<T, TX, TY, 0, 1, 0>(ex, i0, j0, nx, ny, sy, NM);
+    const Slot hmy = yslot<T, TX, TY, 0, 1, 0, WM>(tid, i0, j0, nx, ny, sy, NM);
+    const Slot hmc = cslot<T, TX, TY>(tid == NT / 2, i0, j0, nx, ny, sy, NM);
+    // own positions in the planes
+    const int ovx = (ty + 1) * W3 + tx + 2;
+    const int ovy = (ty + 2) * W3 + tx + 1;
+    const int ovz = (ty + 1) * W3 + tx + 1;
+    const int om = ty * WM + tx;
+
+    const T *fvx = G.f[VX], *fvy = G.f[VY], *fvz = G.f[VZ];
+    const T *mu = G.mu, *lam = G.lam;
+    const T rdx = G.rdx, dt = G.dt;
+    const T s = src.on ? sload(src.wavelet, n) : T(0);
+    const T gxh = in ? G.g[0][1][i] : T(0), gxi = in ? G.g[0][0][i] : T(0);
+    const T gyh = in ? G.g[1][1][j] : T(0), gyi = in ? G.g[1][0][j] : T(0);
+    const unsigned st_xy = (in && i <= nx - 2 && j <= ny - 2) ? oc : kOOB;
+    const unsigned st_xz = (in && i <= nx - 2) ? oc : kOOB;
+    const unsigned st_yz = (in && j <= ny - 2) ? oc : kOOB;
+
+    auto zld = [&](const T *f, int kk, bool ok) -> T { return ld<T>(plane(f, kk, sz, ok && kk >= 0 && kk < nz), oc); };
+
+    // z queues: vx, vy at k-1..k+2; vz at k-2..k+1 (zero above k = 0: never used with FS)
+    T qvx[4], qvy[4], qvz[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        qvx[m] = zld(fvx, k0 - 1 + m, true);
+        qvy[m] = zld(fvy, k0 - 1 + m, true);
+        qvz[m] = zld(fvz, k0 - 2 + m, true);
+    }
+    T m1 = zld(mu, k0 + 1, true);  // own mu one plane below
+
+    struct Plane {
+        T cl, cm, sxx, syy, szz, sxy, sxz, syz, vxx, vxy, vyx, vyy, vzx, vzy;
+    };
+    auto loadplane = [&](int kk, bool ok, Plane &P) {
+        const rsrc_t bx = plane(fvx, kk, sz, ok), by = plane(fvy, kk, sz, ok), bz = plane(fvz, kk, sz, ok);
+        P.cl = ld<T>(plane(lam, kk, sz, ok), oc);
+        P.cm = ld<T>(plane(mu, kk, sz, ok), oc);
+        P.sxx = ld<T>(plane(G.f[SXX], kk, sz, ok), oc);
+        P.syy = ld<T>(plane(G.f[SYY], kk, sz, ok), oc);
+        P.szz = ld<T>(plane(G.f[SZZ], kk, sz, ok), oc);
+        P.sxy = ld<T>(plane(G.f[SXY], kk, sz, ok), oc);
+        P.sxz = ld<T>(plane(G.f[SXZ], kk, sz, ok), oc);
+        P.syz = ld<T>(plane(G.f[SYZ], kk, sz, ok), oc);
+        P.vxx = ld<T>(bx, hvxx.off);
+        P.vxy = ld<T>(bx, hvxy.off);
+        P.vyx = ld<T>(by, hvyx.off);
+        P.vyy = ld<T>(by, hvyy.off);
+        P.vzx = ld<T>(bz, hvzx.off);
+        P.vzy = ld<T>(bz, hvzy.off);
+    };
+    struct MuHalo {
+        T x, y, c;
+    };
+    auto loadmu = [&](int kk, bool ok, MuHalo &H) {
+        const rsrc_t bm = plane(mu, kk, sz, ok && kk < nz);
+        H.x = ld<T>(bm, hmx.off);
+        H.y = ld<T>(bm, hmy.off);
+        H.c = ld<T>(bm, hmc.off);
+    };
+
+    Plane P;
+    loadplane(k0, true, P);
+    MuHalo H;
+    loadmu(k0, true, H);
+    {
+        T *M = s_mu[k0 % 3];
+        M[om] = P.cm;
+        M[hmx.lds] = H.x;
+        M[hmy.lds] = H.y;
+        M[hmc.lds] = H.c;
+    }
+    loadmu(k0 + 1, true, H);
+
+    for (int k = k0; k < k1; ++k) {
+        const int b = (k - k0) & 1;
+        T *Lx = s_vx[b], *Ly = s_vy[b], *Lz = s_vz[b];
+        T *M0 = s_mu[k % 3], *M1 = s_mu[(k + 1) % 3];
+        Lx[ovx] = qvx[1];
+        Ly[ovy] = qvy[1];
+        Lz[ovz] = qvz[2];
+        Lx[hvxx.lds] = P.vxx;
+        Lx[hvxy.lds] = P.vxy;
+        Ly[hvyx.lds] = P.vyx;
+        Ly[hvyy.lds] = P.vyy;
+        Lz[hvzx.lds] = P.vzx;
+        Lz[hvzy.lds] = P.vzy;
+        M1[om] = m1;
+        M1[hmx.lds] = H.x;
+        M1[hmy.lds] = H.y;
+        M1[hmc.lds] = H.c;
+        const T l = P.cl, mm = P.cm;
+        const T o_xx = P.sxx, o_yy = P.syy, o_zz = P.szz, o_xy = P.sxy, o_xz = P.sxz, o_yz = P.syz;
+        const bool more = k + 1 < k1;
+        loadplane(k + 1, more, P);
+        const T nvx = zld(fvx, k + 3, more), nvy = zld(fvy, k + 3, more), nvz = zld(fvz, k + 2, more);
+        const T nm1 = zld(mu, k + 2, more);
+        loadmu(k + 2, more, H);
+        const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
+        __syncthreads();
+
+        const T exx = dstag(Lx[ovx], Lx[ovx - 1], Lx[ovx + 1], Lx[ovx - 2], rdx);
+        const T eyy = dstag(Ly[ovy], Ly[ovy - W3], Ly[ovy + W3], Ly[ovy - 2 * W3], rdx);
+        T ezz;
+        if (FS && k == 0) ezz = -l / (l + T(2) * mm) * (exx + eyy);
+        else if (FS && k == 1) ezz = (qvz[2] - qvz[1]) * rdx;
+        else ezz = dstag(qvz[2], qvz[1], qvz[3], qvz[0], rdx);
+        const T tr = exx + eyy + ezz;
+        const T gn = gxi * gyi * gz_i;
+        T nxx = o_xx + dt * (l * tr + T(2) * mm * exx);
+        T nyy = o_yy + dt * (l * tr + T(2) * mm * eyy);
+        T nzz = o_zz + dt * (l * tr + T(2) * mm * ezz);
+        const int t = tap_of(src, SXX, i, j, k);
+        nxx += pick(src.c[SXX], t) * s;
+        nyy += pick(src.c[SYY], t) * s;
+        nzz += pick(src.c[SZZ], t) * s;
+        st(plane(G.f[SXX], k, sz, true), oc, nxx * gn);
+        st(plane(G.f[SYY], k, sz, true), oc, nyy * gn);
+        st(plane(G.f[SZZ], k, sz, true), oc, (FS && k == 0) ? T(0) : nzz * gn);
+        {
+            const T e = dstag(Lx[ovx + W3], Lx[ovx], Lx[ovx + 2 * W3], Lx[ovx - W3], rdx)
+                      + dstag(Ly[ovy + 1], Ly[ovy], Ly[ovy + 2], Ly[ovy - 1], rdx);
+            const T mxy = ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
+            T v = o_xy + dt * mxy * e;
+            v += pick(src.c[SXY], tap_of(src, SXY, i, j, k)) * s;
+            st(plane(G.f[SXY], k, sz, true), st_xy, v * (gxh * gyh * gz_i));
+        }
+        {
+            const T dzvx = (FS && k == 0) ? (qvx[2] - qvx[1]) * rdx : dstag(qvx[2], qvx[1], qvx[3], qvx[0], rdx);
+            const T e = dzvx + dstag(Lz[ovz + 1], Lz[ovz], Lz[ovz + 2], Lz[ovz - 1], rdx);
+            const T mxz = ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
+            T v = o_xz + dt * mxz * e;
+            v += pick(src.c[SXZ], tap_of(src, SXZ, i, j, k)) * s;
+            st(plane(G.f[SXZ], k, sz, true), k <= nz - 2 ? st_xz : kOOB, v * (gxh * gyi * gz_h));
+        }
+        {
+            const T dzvy = (FS && k == 0) ? (qvy[2] - qvy[1]) * rdx : dstag(qvy[2], qvy[1], qvy[3], qvy[0], rdx);
+            const T e = dzvy + dstag(Lz[ovz + W3], Lz[ovz], Lz[ovz + 2 * W3], Lz[ovz - W3], rdx);
+            const T myz = ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);
+            T v = o_yz + dt * myz * e;
+            v += pick(src.c[SYZ], tap_of(src, SYZ, i, j, k)) * s;
+            st(plane(G.f[SYZ], k, sz, true), k <= nz - 2 ? st_yz : kOOB, v * (gxi * gyh * gz_h));
+        }
+        qvx[0] = qvx[1]; qvx[1] = qvx[2]; qvx[2] = qvx[3]; qvx[3] = nvx;
+        qvy[0] = qvy[1]; qvy[1] = qvy[2]; qvy[2] = qvy[3]; qvy[3] = nvy;
+        qvz[0] = qvz[1]; qvz[1] = qvz[2]; qvz[2] = qvz[3]; qvz[3] = nvz;
+        m1 = nm1;
+    }
+}
+
+} // namespace fd3d

@@ -99,6 +99,19 @@ class Simulator:
     def ctx(self) -> int:
         return self._ctx
 
+    def set_kernel(self, variant: str = "tile", tile_y: int = 8, zchunk: int = 32, tile_x: int = 64) -> None:
+        """Select the step-loop kernels: "cell" (one thread per cell) or "tile"
+        (LDS halo planes + register z sweep over tile_x x tile_y columns, zchunk planes)."""
+        k = _abi.fd3d_kernel()
+        k.variant = {"cell": _abi.FD3D_KERNEL_CELL, "tile": _abi.FD3D_KERNEL_TILE}[variant]
+        k.tile_x, k.tile_y, k.zchunk = int(tile_x), int(tile_y), int(zchunk)
+        _abi.fd3d_set_kernel(self._ctx, k)
+
+    def kernel(self) -> dict:
+        k = _abi.fd3d_get_kernel(self._ctx)
+        return {"variant": "cell" if k.variant == _abi.FD3D_KERNEL_CELL else "tile", "tile_x": k.tile_x,
+                "tile_y": k.tile_y, "zchunk": k.zchunk}
+
     def info(self):
         """(vp_max, vs_min, rho_min, dt_max) read back at creation."""
         return _abi.fd3d_model_info(self._ctx)

@@ -16,12 +16,14 @@ def oracle_run(shot, nt=None, state=None):
     return oracle.forward(cfg, shot.lam, shot.mu, shot.rho, src, shot.wavelet[:nt], shot.rec_pos, state=state)
 
 
-def gpu_run(shot, dtype, nt=None, **kw):
+def gpu_run(shot, dtype, nt=None, kernel=None, **kw):
     from paper_2112_15071_amd import Simulator
 
     nt = shot.nt if nt is None else nt
     sim = Simulator(shot.lam, shot.mu, shot.rho, shot.h, shot.dt, nt, dtype=dtype, sponge=shot.sponge,
                     sponge_alpha=shot.alpha, free_surface=shot.free_surface, **kw)
+    if kernel is not None:
+        sim.set_kernel(*kernel)
     tr = sim.forward(shot.src_pos, shot.moment, shot.force, shot.wavelet[:nt], shot.rec_pos)
     st = sim.state()
     torch.cuda.synchronize()

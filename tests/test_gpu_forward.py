@@ -70,15 +70,41 @@ def ragged_shot(free_surface, seed, force=False):
                   sponge=sponge, free_surface=free_surface)
 
 
+# (variant, tile_y, zchunk, tile_x)
+KERNELS = [("cell", 8, 32), ("tile", 4, 8), ("tile", 8, 5), ("tile", 16, 32), ("tile", 4, 6, 128),
+           ("tile", 8, 9, 128), ("tile", 4, 7, 256)]
+
+
+def fp64_ok(kern):
+    if kern[0] == "cell":
+        return True
+    tx = kern[3] if len(kern) > 3 else 64
+    return (tx == 64 and kern[1] in (4, 8)) or (tx == 128 and kern[1] == 4)
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 @pytest.mark.parametrize("free_surface", [False, True])
 @pytest.mark.parametrize("force", [False, True])
 def test_ragged_grids(dtype, free_surface, force):
+    """37 x 29 x 23: ragged in x (< 64), y (not a tile multiple) and z (last chunk short),
+    through every kernel variant."""
     shot = ragged_shot(free_surface, 2024 + int(free_surface) + 2 * int(force), force)
-    print(f"[ragged] fs={free_surface} force={force} {dtype}", flush=True)
     ref = oracle_run(shot)
-    got = gpu_run(shot, dtype)
-    compare(got, ref, TOL[dtype], f"ragged fs={free_surface} force={force}")
+    for kern in KERNELS:
+        if dtype == torch.float64 and not fp64_ok(kern):
+            continue
+        print(f"[ragged] fs={free_surface} force={force} {dtype} {kern}", flush=True)
+        got = gpu_run(shot, dtype, kernel=kern)
+        compare(got, ref, TOL[dtype], f"ragged fs={free_surface} force={force} {kern}")
+
+
+@pytest.mark.parametrize("kern", KERNELS)
+def test_variants_agree_bitwise(kern):
+    """Every variant performs the same operations per sample: FP32 results are identical."""
+    shot = ragged_shot(True, 99, True)
+    base = gpu_run(shot, torch.float32, kernel=("cell", 8, 32))
+    got = gpu_run(shot, torch.float32, kernel=kern)
+    assert np.array_equal(got[0], base[0]) and np.array_equal(got[1], base[1])
 
 
 C1_NT = 16
