@@ -121,6 +121,48 @@ int fd3d_set_state(fd3d_ctx *ctx, const void *const fields[9], void *hip_stream)
  * (0 if none), out[2] = rho_min, out[3] = largest stable dt (m/s, m/s, kg/m^3, s). */
 int fd3d_model_info(const fd3d_ctx *ctx, double out[4]);
 
+/* ---- FWI gradient: discrete adjoint with snapshot checkpointing -------------------
+ *
+ * J = 1/2 sum_{r,c,n} (d - d_obs)^2 over the traces of one shot; residual = dJ/dd.
+ * The gradient is the exact transpose of the forward steps (velocity pass, sampling,
+ * stress pass) taken in reverse order, with respect to the node arrays lambda, mu, rho
+ * given to fd3d_create (chain rule through the Sec. 2.2.1 means).  The forward state is
+ * checkpointed every ckpt_every steps; the reverse sweep restores a checkpoint,
+ * recomputes its segment while storing v^{n+1/2} and sigma^n per step, then runs the
+ * adjoint steps of the segment backwards.  Damped boundaries only (FD3D_EINVAL with the
+ * free surface).  The gradient workspace gws is caller-owned device memory, 256-byte
+ * aligned: 17 + 9 (ceil(nt / ckpt_every) + ckpt_every) field slots plus a residual buffer.
+ */
+
+/* Bytes of gradient workspace for checkpoints every ckpt_every steps (1 <= k <= nt). */
+int fd3d_grad_workspace_bytes(const fd3d_ctx *ctx, int ckpt_every, size_t *bytes);
+
+/* fd3d_forward that also writes the checkpoints into gws (flags as in fd3d_forward).
+ * Must precede fd3d_adjoint on the same gws. */
+int fd3d_forward_ckpt(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *rec_pos,
+                      void *traces, int flags, void *gws, size_t gws_bytes, int ckpt_every,
+                      void *hip_stream);
+
+/* Reverse sweep.  residual: device T[nrec][3][nt] (dJ/dd); src and receivers must be those
+ * of the fd3d_forward_ckpt call.  Accumulates (+=) into g_lam, g_mu, g_rho (device
+ * T[nz][ny][nx]).  Leaves the adjoint of the initial state in gws (see below).  Uses and
+ * overwrites the context's forward state.  FD3D_ESTATE without a preceding checkpointed
+ * forward on this gws. */
+int fd3d_adjoint(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *rec_pos,
+                 const void *residual, void *g_lam, void *g_mu, void *g_rho, void *gws,
+                 size_t gws_bytes, void *hip_stream);
+
+/* One shot of the L2 misfit: fd3d_forward_ckpt (traces written), residual = traces - d_obs,
+ * misfit[0] = J (device T, or NULL), then fd3d_adjoint (gradients accumulated). */
+int fd3d_gradient(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *rec_pos,
+                  const void *d_obs, void *traces, void *misfit, void *g_lam, void *g_mu,
+                  void *g_rho, void *gws, size_t gws_bytes, int ckpt_every, void *hip_stream);
+
+/* After fd3d_adjoint: the adjoint of the initial state (v^{-1/2}, sigma^0) into fields[9]
+ * (device T[nz][ny][nx], order as fd3d_get_state) -- the dot-product test quantity. */
+int fd3d_get_adjoint_state(fd3d_ctx *ctx, const void *gws, void *const fields[9],
+                           void *hip_stream);
+
 /* Kernel selection for the step loop of later calls on this context.  All variants
  * compute the same update with the same operation order per sample. */
 typedef struct fd3d_kernel {

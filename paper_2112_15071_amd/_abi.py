@@ -89,6 +89,11 @@ _SIGS = {
     "fd3d_get_state": ([_vp, ctypes.POINTER(_vp), _vp], _i),
     "fd3d_set_state": ([_vp, ctypes.POINTER(_vp), _vp], _i),
     "fd3d_model_info": ([_vp, _dp], _i),
+    "fd3d_grad_workspace_bytes": ([_vp, _i, ctypes.POINTER(_sz)], _i),
+    "fd3d_forward_ckpt": ([_vp, ctypes.POINTER(fd3d_source), _i, _dp, _vp, _i, _vp, _sz, _i, _vp], _i),
+    "fd3d_adjoint": ([_vp, ctypes.POINTER(fd3d_source), _i, _dp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
+    "fd3d_gradient": ([_vp, ctypes.POINTER(fd3d_source), _i, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i, _vp], _i),
+    "fd3d_get_adjoint_state": ([_vp, _vp, ctypes.POINTER(_vp), _vp], _i),
     "fd3d_set_kernel": ([_vp, ctypes.POINTER(fd3d_kernel)], _i),
     "fd3d_get_kernel": ([_vp, ctypes.POINTER(fd3d_kernel)], _i),
     "fd3d_profile": ([_vp, _i], _i),
@@ -155,6 +160,40 @@ def fd3d_model_info(ctx):
     out = (ctypes.c_double * 4)()
     _check(_lib.fd3d_model_info(ctx, out))
     return list(out)
+
+
+def _src(src):
+    return ctypes.byref(src) if src is not None else None
+
+
+def _dpp(p):
+    return ctypes.cast(p, _dp) if p else None
+
+
+def fd3d_grad_workspace_bytes(ctx, ckpt_every: int) -> int:
+    out = _sz(0)
+    _check(_lib.fd3d_grad_workspace_bytes(ctx, int(ckpt_every), ctypes.byref(out)))
+    return int(out.value)
+
+
+def fd3d_forward_ckpt(ctx, src, nrec, rec_pos_ptr, traces, flags, gws, gws_bytes, ckpt_every, stream) -> None:
+    _check(_lib.fd3d_forward_ckpt(ctx, _src(src), nrec, _dpp(rec_pos_ptr), traces, flags, gws, gws_bytes,
+                                  int(ckpt_every), stream))
+
+
+def fd3d_adjoint(ctx, src, nrec, rec_pos_ptr, residual, g_lam, g_mu, g_rho, gws, gws_bytes, stream) -> None:
+    _check(_lib.fd3d_adjoint(ctx, _src(src), nrec, _dpp(rec_pos_ptr), residual, g_lam, g_mu, g_rho, gws, gws_bytes,
+                             stream))
+
+
+def fd3d_gradient(ctx, src, nrec, rec_pos_ptr, d_obs, traces, misfit, g_lam, g_mu, g_rho, gws, gws_bytes,
+                  ckpt_every, stream) -> None:
+    _check(_lib.fd3d_gradient(ctx, _src(src), nrec, _dpp(rec_pos_ptr), d_obs, traces, misfit, g_lam, g_mu, g_rho,
+                              gws, gws_bytes, int(ckpt_every), stream))
+
+
+def fd3d_get_adjoint_state(ctx, gws, fields, stream) -> None:
+    _check(_lib.fd3d_get_adjoint_state(ctx, gws, _ptr9(fields), stream))
 
 
 def fd3d_set_kernel(ctx, k: fd3d_kernel) -> None:

@@ -1,0 +1,283 @@
+// Discrete adjoint of one step (velocity pass, receiver sampling, stress pass) and the
+// chain rule to the node arrays lambda, mu, rho.  One thread per cell.
+//
+// Adjoint arrays (same layout as the state): A_v (3 components), A_s (6).  Each pass
+// applies its damping factor lazily, so that no pass rewrites an array that a
+// neighbouring thread still reads:
+//   start of step n:  adjoint(sigma^{n+1}) = A_s,  adjoint(v^{n+1/2}) so far = G_v A_v
+//   adj_stress:  T = G_s A_s;  A_v <- G_v A_v - dt D_S(C T);  gradients of C from E v^{n+1/2}
+//   residual:    A_v += W^T r^n
+//   adj_vel:     U = G_v A_v;  A_s <- G_s A_s - dt E(b U);  gradient of b from D_S sigma^n
+// leaving adjoint(sigma^n) = A_s and adjoint(v^{n-1/2}) = G_v A_v.  D_S is the
+// divergence stencil of the velocity pass and E the strain-rate stencil of the stress
+// pass; under the zero-halo rules D_S = -E^T, so these are the transposed passes.
+#pragma once
+
+#include "common.h"
+
+namespace fd3d {
+
+// Adjoint of one grid: adjoint state, gradient accumulators at staggered points and the
+// stored forward fields of the step being reversed.
+template <typename T> struct AdjGrid {
+    T *a[NFIELD];      // A_v, A_s
+    T *gl, *gm;        // lambda, mu at nodes (normal-stress part)
+    T *gs[3];          // mu_xy, mu_xz, mu_yz at the shear-stress points
+    T *gb[3];          // buoyancy at vx, vy, vz points
+    const T *vst[3];   // stored v^{n+1/2}
+    const T *sst[6];   // stored sigma^n
+};
+
+template <typename T>
+__device__ __forceinline__ T rdc(const T *f, int c, int i, int j, int k, const Grid<T> &G)
+{
+    const int lx = G.nx - 1 - stag(c, 0), ly = G.ny - 1 - stag(c, 1), lz = G.nz - 1 - stag(c, 2);
+    const bool ok = (unsigned)i <= (unsigned)lx && (unsigned)j <= (unsigned)ly && (unsigned)k <= (unsigned)lz;
+    return ok ? f[i + G.sy * j + G.sz * k] : T(0);
+}
+
+template <typename T> __device__ __forceinline__ T damp(const Grid<T> &G, int c, int i, int j, int k)
+{
+    return G.g[0][stag(c, 0)][i] * G.g[1][stag(c, 1)][j] * G.g[2][stag(c, 2)][k];
+}
+
+template <typename T> __device__ __forceinline__ bool in_grid(const Grid<T> &G, int i, int j, int k)
+{
+    return (unsigned)i < (unsigned)G.nx && (unsigned)j < (unsigned)G.ny && (unsigned)k < (unsigned)G.nz;
+}
+
+// C applied to T = G_s A_s at a stress sample (zero outside the active range).
+template <typename T>
+__device__ __forceinline__ T xval(const Grid<T> &G, const AdjGrid<T> &A, int c, int i, int j, int k)
+{
+    const int lx = G.nx - 1 - stag(c, 0), ly = G.ny - 1 - stag(c, 1), lz = G.nz - 1 - stag(c, 2);
+    if (!((unsigned)i <= (unsigned)lx && (unsigned)j <= (unsigned)ly && (unsigned)k <= (unsigned)lz)) return T(0);
+    const long p = i + G.sy * j + G.sz * k;
+    if (c <= SZZ) {
+        const T g = damp(G, SXX, i, j, k);
+        const T txx = g * A.a[SXX][p], tyy = g * A.a[SYY][p], tzz = g * A.a[SZZ][p];
+        const T tc = c == SXX ? txx : (c == SYY ? tyy : tzz);
+        return G.lam[p] * ((txx + tyy) + tzz) + T(2) * G.mu[p] * tc;
+    }
+    long u = 0, w = 0;
+    if (c == SXY) { u = 1; w = G.sy; }
+    if (c == SXZ) { u = 1; w = G.sz; }
+    if (c == SYZ) { u = G.sy; w = G.sz; }
+    const T me = ((G.mu[p] + G.mu[p + u]) + (G.mu[p + w] + G.mu[p + u + w])) / T(4);
+    return me * (damp(G, c, i, j, k) * A.a[c][p]);
+}
+
+// (a10) adjoint of the stress pass, at the samples of node (i,j,k).
+template <typename T>
+__global__ void __launch_bounds__(256) adj_stress_cell(Grid<T> G, AdjGrid<T> A)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= G.nx || j >= G.ny) return;
+    const long p = i + G.sy * j + G.sz * k;
+    const T rdx = G.rdx, dt = G.dt;
+
+    // A_v <- G_v A_v - dt D_S(C T)
+    if (i <= G.nx - 2) {
+        const T d = dstag(xval(G, A, SXX, i + 1, j, k), xval(G, A, SXX, i, j, k), xval(G, A, SXX, i + 2, j, k), xval(G, A, SXX, i - 1, j, k), rdx)
+                  + dstag(xval(G, A, SXY, i, j, k), xval(G, A, SXY, i, j - 1, k), xval(G, A, SXY, i, j + 1, k), xval(G, A, SXY, i, j - 2, k), rdx)
+                  + dstag(xval(G, A, SXZ, i, j, k), xval(G, A, SXZ, i, j, k - 1), xval(G, A, SXZ, i, j, k + 1), xval(G, A, SXZ, i, j, k - 2), rdx);
+        A.a[VX][p] = damp(G, VX, i, j, k) * A.a[VX][p] - dt * d;
+    }
+    if (j <= G.ny - 2) {
+        const T d = dstag(xval(G, A, SXY, i, j, k), xval(G, A, SXY, i - 1, j, k), xval(G, A, SXY, i + 1, j, k), xval(G, A, SXY, i - 2, j, k), rdx)
+                  + dstag(xval(G, A, SYY, i, j + 1, k), xval(G, A, SYY, i, j, k), xval(G, A, SYY, i, j + 2, k), xval(G, A, SYY, i, j - 1, k), rdx)
+                  + dstag(xval(G, A, SYZ, i, j, k), xval(G, A, SYZ, i, j, k - 1), xval(G, A, SYZ, i, j, k + 1), xval(G, A, SYZ, i, j, k - 2), rdx);
+        A.a[VY][p] = damp(G, VY, i, j, k) * A.a[VY][p] - dt * d;
+    }
+    if (k <= G.nz - 2) {
+        const T d = dstag(xval(G, A, SXZ, i, j, k), xval(G, A, SXZ, i - 1, j, k), xval(G, A, SXZ, i + 1, j, k), xval(G, A, SXZ, i - 2, j, k), rdx)
+                  + dstag(xval(G, A, SYZ, i, j, k), xval(G, A, SYZ, i, j - 1, k), xval(G, A, SYZ, i, j + 1, k), xval(G, A, SYZ, i, j - 2, k), rdx)
+                  + dstag(xval(G, A, SZZ, i, j, k + 1), xval(G, A, SZZ, i, j, k), xval(G, A, SZZ, i, j, k + 2), xval(G, A, SZZ, i, j, k - 1), rdx);
+        A.a[VZ][p] = damp(G, VZ, i, j, k) * A.a[VZ][p] - dt * d;
+    }
+
+    // gradients of C: strain rates of the stored v^{n+1/2} against T
+    const T *vx = A.vst[0], *vy = A.vst[1], *vz = A.vst[2];
+    const T exx = dstag(rdc(vx, VX, i, j, k, G), rdc(vx, VX, i - 1, j, k, G), rdc(vx, VX, i + 1, j, k, G), rdc(vx, VX, i - 2, j, k, G), rdx);
+    const T eyy = dstag(rdc(vy, VY, i, j, k, G), rdc(vy, VY, i, j - 1, k, G), rdc(vy, VY, i, j + 1, k, G), rdc(vy, VY, i, j - 2, k, G), rdx);
+    const T ezz = dstag(rdc(vz, VZ, i, j, k, G), rdc(vz, VZ, i, j, k - 1, G), rdc(vz, VZ, i, j, k + 1, G), rdc(vz, VZ, i, j, k - 2, G), rdx);
+    const T gn = damp(G, SXX, i, j, k);
+    const T txx = gn * A.a[SXX][p], tyy = gn * A.a[SYY][p], tzz = gn * A.a[SZZ][p];
+    A.gl[p] += dt * ((exx + eyy) + ezz) * ((txx + tyy) + tzz);
+    A.gm[p] += dt * T(2) * ((exx * txx + eyy * tyy) + ezz * tzz);
+    if (i <= G.nx - 2 && j <= G.ny - 2) {
+        const T e = dstag(rdc(vx, VX, i, j + 1, k, G), rdc(vx, VX, i, j, k, G), rdc(vx, VX, i, j + 2, k, G), rdc(vx, VX, i, j - 1, k, G), rdx)
+                  + dstag(rdc(vy, VY, i + 1, j, k, G), rdc(vy, VY, i, j, k, G), rdc(vy, VY, i + 2, j, k, G), rdc(vy, VY, i - 1, j, k, G), rdx);
+        A.gs[0][p] += dt * e * (damp(G, SXY, i, j, k) * A.a[SXY][p]);
+    }
+    if (i <= G.nx - 2 && k <= G.nz - 2) {
+        const T e = dstag(rdc(vx, VX, i, j, k + 1, G), rdc(vx, VX, i, j, k, G), rdc(vx, VX, i, j, k + 2, G), rdc(vx, VX, i, j, k - 1, G), rdx)
+                  + dstag(rdc(vz, VZ, i + 1, j, k, G), rdc(vz, VZ, i, j, k, G), rdc(vz, VZ, i + 2, j, k, G), rdc(vz, VZ, i - 1, j, k, G), rdx);
+        A.gs[1][p] += dt * e * (damp(G, SXZ, i, j, k) * A.a[SXZ][p]);
+    }
+    if (j <= G.ny - 2 && k <= G.nz - 2) {
+        const T e = dstag(rdc(vy, VY, i, j, k + 1, G), rdc(vy, VY, i, j, k, G), rdc(vy, VY, i, j, k + 2, G), rdc(vy, VY, i, j, k - 1, G), rdx)
+                  + dstag(rdc(vz, VZ, i, j + 1, k, G), rdc(vz, VZ, i, j, k, G), rdc(vz, VZ, i, j + 2, k, G), rdc(vz, VZ, i, j - 1, k, G), rdx);
+        A.gs[2][p] += dt * e * (damp(G, SYZ, i, j, k) * A.a[SYZ][p]);
+    }
+}
+
+// b U at a velocity sample: G_v A_v / rho_eff (zero outside the active range).
+template <typename T>
+__device__ __forceinline__ T yval(const Grid<T> &G, const AdjGrid<T> &A, int c, int i, int j, int k)
+{
+    const int lx = G.nx - 1 - stag(c, 0), ly = G.ny - 1 - stag(c, 1), lz = G.nz - 1 - stag(c, 2);
+    if (!((unsigned)i <= (unsigned)lx && (unsigned)j <= (unsigned)ly && (unsigned)k <= (unsigned)lz)) return T(0);
+    const long p = i + G.sy * j + G.sz * k;
+    const long e = c == VX ? 1 : (c == VY ? G.sy : G.sz);
+    return (damp(G, c, i, j, k) * A.a[c][p]) / ((G.rho[p] + G.rho[p + e]) / T(2));
+}
+
+// Stored sigma^n for the divergence stencil (zero outside the active range).
+template <typename T>
+__device__ __forceinline__ T sv(const Grid<T> &G, const AdjGrid<T> &A, int c, int i, int j, int k)
+{
+    return rdc(A.sst[c - SXX], c, i, j, k, G);
+}
+
+// (a12) adjoint of the velocity pass, at the samples of node (i,j,k).
+template <typename T>
+__global__ void __launch_bounds__(256) adj_vel_cell(Grid<T> G, AdjGrid<T> A, Inject<T> src, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= G.nx || j >= G.ny) return;
+    const long p = i + G.sy * j + G.sz * k;
+    const T rdx = G.rdx, dt = G.dt;
+    const T s = src.on ? src.wavelet[n] : T(0);
+
+    // A_s <- G_s A_s - dt E(b U)
+    {
+        const T gn = damp(G, SXX, i, j, k);
+        const T exx = dstag(yval(G, A, VX, i, j, k), yval(G, A, VX, i - 1, j, k), yval(G, A, VX, i + 1, j, k), yval(G, A, VX, i - 2, j, k), rdx);
+        const T eyy = dstag(yval(G, A, VY, i, j, k), yval(G, A, VY, i, j - 1, k), yval(G, A, VY, i, j + 1, k), yval(G, A, VY, i, j - 2, k), rdx);
+        const T ezz = dstag(yval(G, A, VZ, i, j, k), yval(G, A, VZ, i, j, k - 1), yval(G, A, VZ, i, j, k + 1), yval(G, A, VZ, i, j, k - 2), rdx);
+        A.a[SXX][p] = gn * A.a[SXX][p] - dt * exx;
+        A.a[SYY][p] = gn * A.a[SYY][p] - dt * eyy;
+        A.a[SZZ][p] = gn * A.a[SZZ][p] - dt * ezz;
+    }
+    if (i <= G.nx - 2 && j <= G.ny - 2) {
+        const T e = dstag(yval(G, A, VX, i, j + 1, k), yval(G, A, VX, i, j, k), yval(G, A, VX, i, j + 2, k), yval(G, A, VX, i, j - 1, k), rdx)
+                  + dstag(yval(G, A, VY, i + 1, j, k), yval(G, A, VY, i, j, k), yval(G, A, VY, i + 2, j, k), yval(G, A, VY, i - 1, j, k), rdx);
+        A.a[SXY][p] = damp(G, SXY, i, j, k) * A.a[SXY][p] - dt * e;
+    }
+    if (i <= G.nx - 2 && k <= G.nz - 2) {
+        const T e = dstag(yval(G, A, VX, i, j, k + 1), yval(G, A, VX, i, j, k), yval(G, A, VX, i, j, k + 2), yval(G, A, VX, i, j, k - 1), rdx)
+                  + dstag(yval(G, A, VZ, i + 1, j, k), yval(G, A, VZ, i, j, k), yval(G, A, VZ, i + 2, j, k), yval(G, A, VZ, i - 1, j, k), rdx);
+        A.a[SXZ][p] = damp(G, SXZ, i, j, k) * A.a[SXZ][p] - dt * e;
+    }
+    if (j <= G.ny - 2 && k <= G.nz - 2) {
+        const T e = dstag(yval(G, A, VY, i, j, k + 1), yval(G, A, VY, i, j, k), yval(G, A, VY, i, j, k + 2), yval(G, A, VY, i, j, k - 1), rdx)
+                  + dstag(yval(G, A, VZ, i, j + 1, k), yval(G, A, VZ, i, j, k), yval(G, A, VZ, i, j + 2, k), yval(G, A, VZ, i, j - 1, k), rdx);
+        A.a[SYZ][p] = damp(G, SYZ, i, j, k) * A.a[SYZ][p] - dt * e;
+    }
+
+    // gradient of b: dt (D_S sigma^n + w F s / dx^3) U at the velocity samples
+    if (i <= G.nx - 2) {
+        const T d = dstag(sv(G, A, SXX, i + 1, j, k), sv(G, A, SXX, i, j, k), sv(G, A, SXX, i + 2, j, k), sv(G, A, SXX, i - 1, j, k), rdx)
+                  + dstag(sv(G, A, SXY, i, j, k), sv(G, A, SXY, i, j - 1, k), sv(G, A, SXY, i, j + 1, k), sv(G, A, SXY, i, j - 2, k), rdx)
+                  + dstag(sv(G, A, SXZ, i, j, k), sv(G, A, SXZ, i, j, k - 1), sv(G, A, SXZ, i, j, k + 1), sv(G, A, SXZ, i, j, k - 2), rdx);
+        const T u = damp(G, VX, i, j, k) * A.a[VX][p];
+        T g = dt * d * u;
+        const int t = tap_of(src, VX, i, j, k);
+        if (t >= 0) g += src.c[VX][t] * s * u;
+        A.gb[0][p] += g;
+    }
+    if (j <= G.ny - 2) {
+        const T d = dstag(sv(G, A, SXY, i, j, k), sv(G, A, SXY, i - 1, j, k), sv(G, A, SXY, i + 1, j, k), sv(G, A, SXY, i - 2, j, k), rdx)
+                  + dstag(sv(G, A, SYY, i, j + 1, k), sv(G, A, SYY, i, j, k), sv(G, A, SYY, i, j + 2, k), sv(G, A, SYY, i, j - 1, k), rdx)
+                  + dstag(sv(G, A, SYZ, i, j, k), sv(G, A, SYZ, i, j, k - 1), sv(G, A, SYZ, i, j, k + 1), sv(G, A, SYZ, i, j, k - 2), rdx);
+        const T u = damp(G, VY, i, j, k) * A.a[VY][p];
+        T g = dt * d * u;
+        const int t = tap_of(src, VY, i, j, k);
+        if (t >= 0) g += src.c[VY][t] * s * u;
+        A.gb[1][p] += g;
+    }
+    if (k <= G.nz - 2) {
+        const T d = dstag(sv(G, A, SXZ, i, j, k), sv(G, A, SXZ, i - 1, j, k), sv(G, A, SXZ, i + 1, j, k), sv(G, A, SXZ, i - 2, j, k), rdx)
+                  + dstag(sv(G, A, SYZ, i, j, k), sv(G, A, SYZ, i, j - 1, k), sv(G, A, SYZ, i, j + 1, k), sv(G, A, SYZ, i, j - 2, k), rdx)
+                  + dstag(sv(G, A, SZZ, i, j, k + 1), sv(G, A, SZZ, i, j, k), sv(G, A, SZZ, i, j, k + 2), sv(G, A, SZZ, i, j, k - 1), rdx);
+        const T u = damp(G, VZ, i, j, k) * A.a[VZ][p];
+        T g = dt * d * u;
+        const int t = tap_of(src, VZ, i, j, k);
+        if (t >= 0) g += src.c[VZ][t] * s * u;
+        A.gb[2][p] += g;
+    }
+}
+
+// (a11) adjoint of the sampling for the receivers of one colour (no two of them share a
+// tap): A_v[tap] += w r[r][c][n].
+template <typename T>
+__global__ void __launch_bounds__(256) inject_residual(T *__restrict__ ax, T *__restrict__ ay, T *__restrict__ az,
+                                                       const RecTap<T> *__restrict__ taps, const int *__restrict__ list,
+                                                       int count, const T *__restrict__ res, int nt, int n)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 3 * count) return;
+    const int r = list[q / 3], c = q % 3;
+    T *f = c == 0 ? ax : (c == 1 ? ay : az);
+    const RecTap<T> &t = taps[r * 3 + c];
+    const T v = res[((long)r * 3 + c) * nt + n];
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+        if (t.idx[m] >= 0) f[t.idx[m]] += t.w[m] * v;
+}
+
+// (a13) chain rule from the staggered-point gradients to the node arrays (gathers, no
+// atomics): g_lam += gl; g_mu += gm + 1/4 sum of the shear gradients whose mean uses the
+// node; g_rho += sum over the adjacent velocity samples of -b^2/2 g_b.
+template <typename T>
+__global__ void __launch_bounds__(256) grad_finalize(Grid<T> G, AdjGrid<T> A, T *__restrict__ g_lam,
+                                                     T *__restrict__ g_mu, T *__restrict__ g_rho)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= G.nx || j >= G.ny) return;
+    const long p = i + G.sy * j + G.sz * k;
+    g_lam[p] += A.gl[p];
+    T sh = T(0);
+    for (int di = -1; di <= 0; ++di)
+        for (int dj = -1; dj <= 0; ++dj) sh += rdc(A.gs[0], SXY, i + di, j + dj, k, G);
+    for (int di = -1; di <= 0; ++di)
+        for (int dk = -1; dk <= 0; ++dk) sh += rdc(A.gs[1], SXZ, i + di, j, k + dk, G);
+    for (int dj = -1; dj <= 0; ++dj)
+        for (int dk = -1; dk <= 0; ++dk) sh += rdc(A.gs[2], SYZ, i, j + dj, k + dk, G);
+    g_mu[p] += A.gm[p] + sh / T(4);
+    T gr = T(0);
+    for (int c = 0; c < 3; ++c) {
+        const long e = c == 0 ? 1 : (c == 1 ? G.sy : G.sz);
+        for (int d = -1; d <= 0; ++d) {
+            const int ii = i + (c == 0 ? d : 0), jj = j + (c == 1 ? d : 0), kk = k + (c == 2 ? d : 0);
+            const T g = rdc(A.gb[c], VX + c, ii, jj, kk, G);
+            if (g != T(0)) {
+                const long q = ii + G.sy * jj + G.sz * kk;
+                const T re = (G.rho[q] + G.rho[q + e]) / T(2);
+                gr += -g / (re * re) / T(2);
+            }
+        }
+    }
+    g_rho[p] += gr;
+}
+
+// Adjoint of the initial velocity: the pending damping factor of A_v applied into out.
+template <typename T>
+__global__ void __launch_bounds__(256) scale_velocity(Grid<T> G, const T *__restrict__ a, int c, T *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= G.nx || j >= G.ny) return;
+    const long p = i + G.sy * j + G.sz * k;
+    out[p] = damp(G, c, i, j, k) * a[p];
+}
+
+} // namespace fd3d

@@ -42,6 +42,8 @@ template <typename T> struct Grid {
     const T *lam, *mu, *rho;
     T *f[NFIELD];
     const T *g[3][2];      // damping profile per axis at integer [0] / half [1] positions
+    T *save[NFIELD];       // optional copies written by the passes (gradient recompute):
+                           // the velocity pass stores v^{n+1/2}, the stress pass sigma^n
 };
 
 // A point source as kernel argument: per component, the base of its 2x2x2 tap box

@@ -16,7 +16,10 @@
 #include "common.h"
 #include "fwd_cell.h"
 #include "fwd_tile.h"
+#include "adj_cell.h"
 #include "util_kernels.h"
+
+#include <unordered_set>
 
 using namespace fd3d;
 
@@ -49,6 +52,7 @@ struct Layout {
     size_t field[NFIELD];
     size_t prof[3][2];
     size_t rec;
+    size_t colors;  // receiver order grouped by colour (tap-disjoint sets), int[max_rec]
     size_t part;
     size_t stats;
     size_t flag;
@@ -74,6 +78,8 @@ Layout make_layout(int nx, int ny, int nz, int tsize, int max_rec)
         }
     L.rec = off;
     off += round_up((size_t)max_rec * 3 * rectap_bytes(tsize), kAlign);
+    L.colors = off;
+    off += round_up((size_t)max_rec * sizeof(int), kAlign);
     L.part = off;
     off += round_up((size_t)kReduceBlocks * kStats * sizeof(double), kAlign);
     L.stats = off;
@@ -150,6 +156,8 @@ struct fd3d_ctx {
     double info[4];
     std::vector<unsigned char> prof_host;  // typed profiles, kept for the async upload
     std::vector<unsigned char> rec_host;   // receiver descriptors, kept for the async upload
+    std::vector<int> color_host;           // receivers grouped by colour, kept for the async upload
+    std::vector<int> color_off;            // colour c holds color_host[color_off[c] .. color_off[c+1])
     hipEvent_t staged;
     bool staged_pending;
     // optional per-kernel timing of the step loop
@@ -162,6 +170,10 @@ struct fd3d_ctx {
     int tile_x;   // columns of a tile (64, 128, 256)
     int tile_y;   // rows of a tile (4, 8, 16)
     int zchunk;   // z planes per workgroup sweep
+    // gradient state: checkpoints written by fd3d_forward_ckpt into a caller workspace
+    const char *grad_ws;
+    int grad_k;
+    int grad_ready;
 };
 
 namespace {
@@ -182,6 +194,7 @@ template <typename T> Grid<T> make_grid(const fd3d_ctx *c)
     for (int f = 0; f < NFIELD; ++f) G.f[f] = (T *)(c->ws + c->L.field[f]);
     for (int a = 0; a < 3; ++a)
         for (int h = 0; h < 2; ++h) G.g[a][h] = (const T *)(c->ws + c->L.prof[a][h]);
+    for (int f = 0; f < NFIELD; ++f) G.save[f] = nullptr;
     return G;
 }
 
@@ -313,7 +326,36 @@ template <typename T> int stage_receivers(fd3d_ctx *c, int nrec, const double *r
                         ++m;
                     }
         }
+    // colours: receivers in one colour share no tap, so their adjoint injections can run
+    // as one launch without write conflicts (greedy, in receiver order)
+    std::vector<std::unordered_set<long>> used;
+    std::vector<std::vector<int>> members;
+    const long N = (long)c->n[0] * c->n[1] * c->n[2];
+    for (int r = 0; r < nrec; ++r) {
+        size_t col = 0;
+        for (;; ++col) {
+            if (col == used.size()) {
+                used.emplace_back();
+                members.emplace_back();
+            }
+            bool clash = false;
+            for (int q = 0; q < 3 && !clash; ++q)
+                for (int m = 0; m < 8 && !clash; ++m) clash = used[col].count(q * N + t[r * 3 + q].idx[m]) > 0;
+            if (!clash) break;
+        }
+        for (int q = 0; q < 3; ++q)
+            for (int m = 0; m < 8; ++m) used[col].insert(q * N + t[r * 3 + q].idx[m]);
+        members[col].push_back(r);
+    }
+    c->color_host.clear();
+    c->color_off.assign(1, 0);
+    for (auto &mm : members) {
+        c->color_host.insert(c->color_host.end(), mm.begin(), mm.end());
+        c->color_off.push_back((int)c->color_host.size());
+    }
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.rec, c->rec_host.data(), c->rec_host.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.colors, c->color_host.data(), c->color_host.size() * sizeof(int),
+                           hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(c->staged, st));
     c->staged_pending = true;
     return FD3D_OK;
@@ -419,9 +461,47 @@ void step(fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int nrec, 
     tm.end();
 }
 
+// Gradient workspace (byte offsets): adjoint state, staggered-point gradient
+// accumulators, checkpoints every k steps, one k-step segment of stored fields, and the
+// residual buffer of fd3d_gradient.
+struct GradLayout {
+    size_t stride;  // bytes per field slot
+    size_t adj;     // 9 fields: A_v, A_s
+    size_t acc;     // 8 fields: gl, gm, g_mu_xy, g_mu_xz, g_mu_yz, g_bx, g_by, g_bz
+    size_t ckpt;    // nseg x 9 fields: state at the start of steps 0, k, 2k, ...
+    size_t seg;     // k x 9 fields: v^{n+1/2} (3) then sigma^n (6) per step of a segment
+    size_t res;     // residual [max_rec][3][nt]
+    size_t misfit;  // one T
+    size_t total;
+    int nseg, k;
+};
+
+GradLayout make_grad_layout(const fd3d_ctx *c, int k)
+{
+    GradLayout g{};
+    g.k = k;
+    g.nseg = (c->nt + k - 1) / k;
+    g.stride = round_up(c->L.field_bytes, 4096) + 1024;
+    size_t off = 0;
+    g.adj = off;
+    off += 9 * g.stride;
+    g.acc = off;
+    off += 8 * g.stride;
+    g.ckpt = off;
+    off += (size_t)g.nseg * 9 * g.stride;
+    g.seg = off;
+    off += (size_t)k * 9 * g.stride;
+    g.res = off;
+    off += round_up((size_t)c->opts.max_receivers * 3 * (size_t)(c->nt > 0 ? c->nt : 1) * c->tsize, kAlign);
+    g.misfit = off;
+    off += kAlign;
+    g.total = off;
+    return g;
+}
+
 template <typename T>
 int forward_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *rec_pos, void *traces, int flags,
-                 hipStream_t st)
+                 hipStream_t st, char *gws = nullptr, const GradLayout *GL = nullptr)
 {
     Inject<T> inj;
     int rc = build_source<T>(c, src, inj);
@@ -434,6 +514,11 @@ int forward_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
     Timer tm{c, st};
     c->prof_used = 0;
     for (int n = 0; n < c->nt; ++n) {
+        if (GL && n % GL->k == 0) {
+            char *dst = gws + GL->ckpt + (size_t)(n / GL->k) * 9 * GL->stride;
+            for (int f = 0; f < NFIELD; ++f)
+                HIP_TRY(hipMemcpyAsync(dst + f * GL->stride, G.f[f], c->L.field_bytes, hipMemcpyDeviceToDevice, st));
+        }
         if (c->opts.free_surface) step<T, true>(c, G, inj, n, nrec, taps, (T *)traces, st, tm);
         else step<T, false>(c, G, inj, n, nrec, taps, (T *)traces, st, tm);
     }
@@ -449,6 +534,106 @@ int forward_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
         if (h) return fail(FD3D_ENONFINITE, "non-finite value in the final state");
     }
     return FD3D_OK;
+}
+
+template <typename T> AdjGrid<T> make_adj(char *gws, const GradLayout &GL)
+{
+    AdjGrid<T> A;
+    for (int f = 0; f < NFIELD; ++f) A.a[f] = (T *)(gws + GL.adj + f * GL.stride);
+    T *acc[8];
+    for (int q = 0; q < 8; ++q) acc[q] = (T *)(gws + GL.acc + q * GL.stride);
+    A.gl = acc[0];
+    A.gm = acc[1];
+    for (int q = 0; q < 3; ++q) {
+        A.gs[q] = acc[2 + q];
+        A.gb[q] = acc[5 + q];
+    }
+    for (int q = 0; q < 3; ++q) A.vst[q] = nullptr;
+    for (int q = 0; q < 6; ++q) A.sst[q] = nullptr;
+    return A;
+}
+
+// Reverse sweep over the checkpointed segments: recompute each segment (storing
+// v^{n+1/2} and sigma^n per step), then run the adjoint steps backwards; finally map
+// the staggered-point gradients to the node arrays (accumulated into g_*).
+template <typename T>
+int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *rec_pos, const T *residual, T *g_lam,
+                 T *g_mu, T *g_rho, char *gws, const GradLayout &GL, hipStream_t st)
+{
+    Inject<T> inj;
+    int rc = build_source<T>(c, src, inj);
+    if (rc) return rc;
+    rc = stage_receivers<T>(c, nrec, rec_pos, st);
+    if (rc) return rc;
+    Grid<T> G = make_grid<T>(c);
+    AdjGrid<T> A = make_adj<T>(gws, GL);
+    // zero the adjoint state and the accumulators (17 consecutive field slots)
+    fill_zero<T><<<2048, 256, 0, st>>>((T *)(gws + GL.adj), (long)(17 * GL.stride / sizeof(T)));
+    const RecTap<T> *taps = (const RecTap<T> *)(c->ws + c->L.rec);
+    const int *colors = (const int *)(c->ws + c->L.colors);
+    const dim3 blk(64, 4, 1), grd((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
+    Timer tm{c, st};
+    Inject<T> none;
+    std::memset(&none, 0, sizeof none);
+    for (int f = 0; f < NFIELD; ++f) none.i0[f] = none.j0[f] = none.k0[f] = -(1 << 28);
+    for (int sgi = GL.nseg - 1; sgi >= 0; --sgi) {
+        const int n0 = sgi * GL.k, n1 = std::min(n0 + GL.k, c->nt);
+        const char *ck = gws + GL.ckpt + (size_t)sgi * 9 * GL.stride;
+        for (int f = 0; f < NFIELD; ++f)
+            HIP_TRY(hipMemcpyAsync(G.f[f], ck + f * GL.stride, c->L.field_bytes, hipMemcpyDeviceToDevice, st));
+        for (int n = n0; n < n1; ++n) {
+            char *slot = gws + GL.seg + (size_t)(n - n0) * 9 * GL.stride;
+            Grid<T> Gs = G;
+            for (int f = 0; f < NFIELD; ++f) Gs.save[f] = (T *)(slot + f * GL.stride);
+            if (c->opts.free_surface) step<T, true>(c, Gs, inj, n, 0, taps, nullptr, st, tm);
+            else step<T, false>(c, Gs, inj, n, 0, taps, nullptr, st, tm);
+        }
+        for (int n = n1 - 1; n >= n0; --n) {
+            const char *slot = gws + GL.seg + (size_t)(n - n0) * 9 * GL.stride;
+            for (int q = 0; q < 3; ++q) A.vst[q] = (const T *)(slot + q * GL.stride);
+            for (int q = 0; q < 6; ++q) A.sst[q] = (const T *)(slot + (3 + q) * GL.stride);
+            adj_stress_cell<T><<<grd, blk, 0, st>>>(G, A);
+            for (size_t col = 0; col + 1 < c->color_off.size(); ++col) {
+                const int cnt = c->color_off[col + 1] - c->color_off[col];
+                inject_residual<T><<<(3 * cnt + 255) / 256, 256, 0, st>>>(A.a[VX], A.a[VY], A.a[VZ], taps,
+                                                                         colors + c->color_off[col], cnt, residual,
+                                                                         c->nt, n);
+            }
+            adj_vel_cell<T><<<grd, blk, 0, st>>>(G, A, inj, n);
+        }
+    }
+    grad_finalize<T><<<grd, blk, 0, st>>>(G, A, g_lam, g_mu, g_rho);
+    HIP_TRY(hipGetLastError());
+    return FD3D_OK;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) residual_misfit(const T *__restrict__ d, const T *__restrict__ obs,
+                                                       T *__restrict__ r, long n, double *__restrict__ part)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
+        const T v = d[q] - obs[q];
+        r[q] = v;
+        acc += (double)v * (double)v;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) misfit_final(const double *__restrict__ part, int nb, T *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b];
+    out[0] = (T)(0.5 * s);
 }
 
 template <typename T> int set_state_impl(fd3d_ctx *c, const void *const fields[9], hipStream_t st)
@@ -512,6 +697,9 @@ int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const v
     c->staged_pending = false;
     c->prof_on = 0;
     c->prof_used = 0;
+    c->grad_ws = nullptr;
+    c->grad_k = 0;
+    c->grad_ready = 0;
     // default tile shape by row length (measured on MI355X at 256^3: 256x4 tiles with
     // 64-plane sweeps keep one 1024-thread workgroup per CU and 1 KiB row segments)
     c->variant = FD3D_KERNEL_TILE;
@@ -580,6 +768,123 @@ int fd3d_model_info(const fd3d_ctx *ctx, double out[4])
 {
     if (!ctx || !out) return fail(FD3D_EINVAL, "ctx/out is NULL");
     for (int q = 0; q < 4; ++q) out[q] = ctx->info[q];
+    return FD3D_OK;
+}
+
+int fd3d_grad_workspace_bytes(const fd3d_ctx *ctx, int ckpt_every, size_t *bytes)
+{
+    if (!ctx || !bytes) return fail(FD3D_EINVAL, "ctx/bytes is NULL");
+    if (ctx->nt < 1) return fail(FD3D_EINVAL, "gradient needs nt >= 1");
+    if (ckpt_every < 1 || ckpt_every > ctx->nt) return fail(FD3D_EINVAL, "ckpt_every must be in [1, nt]");
+    *bytes = make_grad_layout(ctx, ckpt_every).total;
+    return FD3D_OK;
+}
+
+static int check_gws(const fd3d_ctx *ctx, void *gws, size_t gws_bytes, int k)
+{
+    if (ctx->opts.free_surface) return fail(FD3D_EINVAL, "the gradient supports damped boundaries only (no free surface)");
+    if (ctx->nt < 1) return fail(FD3D_EINVAL, "gradient needs nt >= 1");
+    if (k < 1 || k > ctx->nt) return fail(FD3D_EINVAL, "ckpt_every must be in [1, nt]");
+    if (!gws || ((uintptr_t)gws % kAlign)) return fail(FD3D_EINVAL, "gradient workspace must be 256-byte aligned");
+    const size_t need = make_grad_layout(ctx, k).total;
+    if (gws_bytes < need) return fail(FD3D_EWS, "gradient workspace too small: need " + std::to_string(need) + " bytes");
+    return FD3D_OK;
+}
+
+int fd3d_forward_ckpt(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *rec_pos, void *traces,
+                      int flags, void *gws, size_t gws_bytes, int ckpt_every, void *hip_stream)
+{
+    if (!ctx) return fail(FD3D_EINVAL, "ctx is NULL");
+    int rc = check_gws(ctx, gws, gws_bytes, ckpt_every);
+    if (rc) return rc;
+    if (nrec < 0 || nrec > ctx->opts.max_receivers) return fail(FD3D_EINVAL, "nrec out of range");
+    if (nrec > 0 && (!rec_pos || !traces)) return fail(FD3D_EINVAL, "rec_pos/traces is NULL");
+    const GradLayout GL = make_grad_layout(ctx, ckpt_every);
+    hipStream_t st = (hipStream_t)hip_stream;
+    ctx->grad_ready = 0;
+    rc = ctx->tsize == 8 ? forward_impl<double>(ctx, src, nrec, rec_pos, traces, flags, st, (char *)gws, &GL)
+                         : forward_impl<float>(ctx, src, nrec, rec_pos, traces, flags, st, (char *)gws, &GL);
+    if (rc) return rc;
+    ctx->grad_ws = (const char *)gws;
+    ctx->grad_k = ckpt_every;
+    ctx->grad_ready = 1;
+    return FD3D_OK;
+}
+
+int fd3d_adjoint(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *rec_pos, const void *residual,
+                 void *g_lam, void *g_mu, void *g_rho, void *gws, size_t gws_bytes, void *hip_stream)
+{
+    if (!ctx) return fail(FD3D_EINVAL, "ctx is NULL");
+    if (!ctx->grad_ready || gws != ctx->grad_ws)
+        return fail(FD3D_ESTATE, "fd3d_adjoint needs fd3d_forward_ckpt on the same gradient workspace first");
+    int rc = check_gws(ctx, gws, gws_bytes, ctx->grad_k);
+    if (rc) return rc;
+    if (nrec < 0 || nrec > ctx->opts.max_receivers) return fail(FD3D_EINVAL, "nrec out of range");
+    if (nrec > 0 && (!rec_pos || !residual)) return fail(FD3D_EINVAL, "rec_pos/residual is NULL");
+    if (!g_lam || !g_mu || !g_rho) return fail(FD3D_EINVAL, "gradient pointer is NULL");
+    const GradLayout GL = make_grad_layout(ctx, ctx->grad_k);
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (ctx->tsize == 8)
+        return adjoint_impl<double>(ctx, src, nrec, rec_pos, (const double *)residual, (double *)g_lam,
+                                    (double *)g_mu, (double *)g_rho, (char *)gws, GL, st);
+    return adjoint_impl<float>(ctx, src, nrec, rec_pos, (const float *)residual, (float *)g_lam, (float *)g_mu,
+                               (float *)g_rho, (char *)gws, GL, st);
+}
+
+extern "C++" {
+template <typename T>
+static int gradient_impl(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *rec_pos, const void *d_obs,
+                         void *traces, void *misfit, void *g_lam, void *g_mu, void *g_rho, void *gws,
+                         size_t gws_bytes, int ckpt_every, hipStream_t st)
+{
+    int rc = fd3d_forward_ckpt(ctx, src, nrec, rec_pos, traces, 0, gws, gws_bytes, ckpt_every, st);
+    if (rc) return rc;
+    const GradLayout GL = make_grad_layout(ctx, ckpt_every);
+    T *res = (T *)((char *)gws + GL.res);
+    const long n = (long)nrec * 3 * ctx->nt;
+    double *part = (double *)(ctx->ws + ctx->L.part);
+    residual_misfit<T><<<kReduceBlocks, 256, 0, st>>>((const T *)traces, (const T *)d_obs, res, n, part);
+    misfit_final<T><<<1, 64, 0, st>>>(part, kReduceBlocks, misfit ? (T *)misfit : (T *)((char *)gws + GL.misfit));
+    HIP_TRY(hipGetLastError());
+    return fd3d_adjoint(ctx, src, nrec, rec_pos, res, g_lam, g_mu, g_rho, gws, gws_bytes, st);
+}
+
+} // extern "C++"
+
+int fd3d_gradient(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *rec_pos, const void *d_obs,
+                  void *traces, void *misfit, void *g_lam, void *g_mu, void *g_rho, void *gws, size_t gws_bytes,
+                  int ckpt_every, void *hip_stream)
+{
+    if (!ctx) return fail(FD3D_EINVAL, "ctx is NULL");
+    if (nrec < 1 || !d_obs || !traces) return fail(FD3D_EINVAL, "fd3d_gradient needs receivers, d_obs and traces");
+    hipStream_t st = (hipStream_t)hip_stream;
+    return ctx->tsize == 8 ? gradient_impl<double>(ctx, src, nrec, rec_pos, d_obs, traces, misfit, g_lam, g_mu, g_rho,
+                                                   gws, gws_bytes, ckpt_every, st)
+                           : gradient_impl<float>(ctx, src, nrec, rec_pos, d_obs, traces, misfit, g_lam, g_mu, g_rho,
+                                                  gws, gws_bytes, ckpt_every, st);
+}
+
+int fd3d_get_adjoint_state(fd3d_ctx *ctx, const void *gws, void *const fields[9], void *hip_stream)
+{
+    if (!ctx || !gws || !fields) return fail(FD3D_EINVAL, "ctx/gws/fields is NULL");
+    if (!ctx->grad_ready || gws != ctx->grad_ws) return fail(FD3D_ESTATE, "no adjoint state in this workspace");
+    for (int f = 0; f < NFIELD; ++f)
+        if (!fields[f]) return fail(FD3D_EINVAL, "field pointer is NULL");
+    const GradLayout GL = make_grad_layout(ctx, ctx->grad_k);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const dim3 blk(64, 4, 1), grd((ctx->n[0] + 63) / 64, (ctx->n[1] + 3) / 4, ctx->n[2]);
+    for (int f = 0; f < NFIELD; ++f) {
+        const char *a = (const char *)gws + GL.adj + f * GL.stride;
+        if (f <= VZ) {
+            if (ctx->tsize == 8)
+                scale_velocity<double><<<grd, blk, 0, st>>>(make_grid<double>(ctx), (const double *)a, f, (double *)fields[f]);
+            else
+                scale_velocity<float><<<grd, blk, 0, st>>>(make_grid<float>(ctx), (const float *)a, f, (float *)fields[f]);
+        } else {
+            HIP_TRY(hipMemcpyAsync(fields[f], a, ctx->L.field_bytes, hipMemcpyDeviceToDevice, st));
+        }
+    }
+    HIP_TRY(hipGetLastError());
     return FD3D_OK;
 }
 

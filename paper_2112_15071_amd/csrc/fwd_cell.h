@@ -51,7 +51,9 @@ __global__ void __launch_bounds__(256) vel_cell(Grid<T> G, Inject<T> src, int n)
         T v = G.f[VX][p] + G.dt * b * d;
         const int t = tap_of(src, VX, i, j, k);
         if (t >= 0) v += b * src.c[VX][t] * s;
-        G.f[VX][p] = v * (G.g[0][1][i] * G.g[1][0][j] * G.g[2][0][k]);
+        v = v * (G.g[0][1][i] * G.g[1][0][j] * G.g[2][0][k]);
+        G.f[VX][p] = v;
+        if (G.save[VX]) G.save[VX][p] = v;
     }
     if (j <= G.ny - 2) {
         T d = dstag(rds<SXY, FS>(G, i, j, k), rds<SXY, FS>(G, i - 1, j, k), rds<SXY, FS>(G, i + 1, j, k), rds<SXY, FS>(G, i - 2, j, k), rdx)
@@ -61,7 +63,9 @@ __global__ void __launch_bounds__(256) vel_cell(Grid<T> G, Inject<T> src, int n)
         T v = G.f[VY][p] + G.dt * b * d;
         const int t = tap_of(src, VY, i, j, k);
         if (t >= 0) v += b * src.c[VY][t] * s;
-        G.f[VY][p] = v * (G.g[0][0][i] * G.g[1][1][j] * G.g[2][0][k]);
+        v = v * (G.g[0][0][i] * G.g[1][1][j] * G.g[2][0][k]);
+        G.f[VY][p] = v;
+        if (G.save[VY]) G.save[VY][p] = v;
     }
     if (k <= G.nz - 2) {
         T d = dstag(rds<SXZ, FS>(G, i, j, k), rds<SXZ, FS>(G, i - 1, j, k), rds<SXZ, FS>(G, i + 1, j, k), rds<SXZ, FS>(G, i - 2, j, k), rdx)
@@ -71,7 +75,9 @@ __global__ void __launch_bounds__(256) vel_cell(Grid<T> G, Inject<T> src, int n)
         T v = G.f[VZ][p] + G.dt * b * d;
         const int t = tap_of(src, VZ, i, j, k);
         if (t >= 0) v += b * src.c[VZ][t] * s;
-        G.f[VZ][p] = v * (G.g[0][0][i] * G.g[1][0][j] * G.g[2][1][k]);
+        v = v * (G.g[0][0][i] * G.g[1][0][j] * G.g[2][1][k]);
+        G.f[VZ][p] = v;
+        if (G.save[VZ]) G.save[VZ][p] = v;
     }
 }
 
@@ -98,6 +104,10 @@ __global__ void __launch_bounds__(256) stress_cell(Grid<T> G, Inject<T> src, int
     else ezz = dstag(rd<VZ>(G, i, j, k), rd<VZ>(G, i, j, k - 1), rd<VZ>(G, i, j, k + 1), rd<VZ>(G, i, j, k - 2), rdx);
     const T tr = exx + eyy + ezz;
     const T gn = G.g[0][0][i] * G.g[1][0][j] * G.g[2][0][k];
+    if (G.save[SXX]) {
+#pragma unroll
+        for (int c = SXX; c <= SYZ; ++c) G.save[c][p] = G.f[c][p];
+    }
     {
         T sxx = G.f[SXX][p] + dt * (l * tr + T(2) * m * exx);
         T syy = G.f[SYY][p] + dt * (l * tr + T(2) * m * eyy);

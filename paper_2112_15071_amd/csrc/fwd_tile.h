@@ -200,6 +200,7 @@ __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int
     const T gyh = in ? G.g[1][1][j] : T(0), gyi = in ? G.g[1][0][j] : T(0);
     const unsigned st_vx = (in && i <= nx - 2) ? oc : kOOB;
     const unsigned st_vy = (in && j <= ny - 2) ? oc : kOOB;
+    const bool save = G.save[VX] != nullptr;
 
     auto zld = [&](const T *f, int kk, bool ok) -> T { return ld<T>(plane(f, kk, sz, ok && kk >= 0 && kk < nz), oc); };
 
@@ -285,7 +286,9 @@ __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int
             const T bb = T(1) / ((r0 + Lr[ty * WR + tx + 1]) / T(2));
             T v = vx0 + dt * bb * d;
             v += bb * pick(src.c[VX], tap_of(src, VX, i, j, k)) * s;
-            st(ovx, st_vx, v * (gxh * gyi * gz_i));
+            v = v * (gxh * gyi * gz_i);
+            st(ovx, st_vx, v);
+            st(plane(G.save[VX], k, sz, save), st_vx, v);
         }
         {
             const int ox = (ty + 2) * W3 + tx + 2;
@@ -296,7 +299,9 @@ __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int
             const T bb = T(1) / ((r0 + Lr[(ty + 1) * WR + tx]) / T(2));
             T v = vy0 + dt * bb * d;
             v += bb * pick(src.c[VY], tap_of(src, VY, i, j, k)) * s;
-            st(ovy, st_vy, v * (gxi * gyh * gz_i));
+            v = v * (gxi * gyh * gz_i);
+            st(ovy, st_vy, v);
+            st(plane(G.save[VY], k, sz, save), st_vy, v);
         }
         {
             const int o = own_c3 + tx + 2;
@@ -307,7 +312,9 @@ __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int
             const T bb = T(1) / ((r0 + r1) / T(2));
             T v = vz0 + dt * bb * d;
             v += bb * pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s;
-            st(ovz, k <= nz - 2 ? oc : kOOB, v * (gxi * gyi * gz_h));
+            v = v * (gxi * gyi * gz_h);
+            st(ovz, k <= nz - 2 ? oc : kOOB, v);
+            st(plane(G.save[VZ], k, sz, save), k <= nz - 2 ? oc : kOOB, v);
         }
         qxz[0] = qxz[1]; qxz[1] = qxz[2]; qxz[2] = qxz[3]; qxz[3] = nxz;
         qyz[0] = qyz[1]; qyz[1] = qyz[2]; qyz[2] = qyz[3]; qyz[3] = nyz;
@@ -366,6 +373,7 @@ __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, 
     const unsigned st_xy = (in && i <= nx - 2 && j <= ny - 2) ? oc : kOOB;
     const unsigned st_xz = (in && i <= nx - 2) ? oc : kOOB;
     const unsigned st_yz = (in && j <= ny - 2) ? oc : kOOB;
+    const bool save = G.save[SXX] != nullptr;
 
     auto zld = [&](const T *f, int kk, bool ok) -> T { return ld<T>(plane(f, kk, sz, ok && kk >= 0 && kk < nz), oc); };
 
@@ -449,6 +457,12 @@ __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, 
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         __syncthreads();
 
+        st(plane(G.save[SXX], k, sz, save), oc, o_xx);
+        st(plane(G.save[SYY], k, sz, save), oc, o_yy);
+        st(plane(G.save[SZZ], k, sz, save), oc, o_zz);
+        st(plane(G.save[SXY], k, sz, save), oc, o_xy);
+        st(plane(G.save[SXZ], k, sz, save), oc, o_xz);
+        st(plane(G.save[SYZ], k, sz, save), oc, o_yz);
         const T exx = dstag(Lx[ovx], Lx[ovx - 1], Lx[ovx + 1], Lx[ovx - 2], rdx);
         const T eyy = dstag(Ly[ovy], Ly[ovy - W3], Ly[ovy + W3], Ly[ovy - 2 * W3], rdx);
         T ezz;

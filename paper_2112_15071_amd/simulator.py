@@ -130,6 +130,76 @@ class Simulator:
         self._rec_keep = (rp, w)  # host/device inputs stay referenced until the next call
         return traces
 
+    # -- gradient --------------------------------------------------------------
+    def grad_workspace(self, ckpt_every: int) -> torch.Tensor:
+        """Device buffer for checkpoints, adjoint state and gradient accumulators."""
+        nbytes = _abi.fd3d_grad_workspace_bytes(self._ctx, int(ckpt_every))
+        gws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        gws.ckpt_every = int(ckpt_every)
+        return gws
+
+    def forward_ckpt(self, gws: torch.Tensor, src_pos=None, moment=(0.0,) * 6, force=(0.0,) * 3, wavelet=None,
+                     rec_pos=None, keep_state: bool = False, traces: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Forward run that also stores checkpoints in ``gws`` for a later adjoint."""
+        w = self._wavelet(wavelet)
+        src = make_source(src_pos, moment, force, w) if src_pos is not None else None
+        rp, nrec = self._rec(rec_pos)
+        if traces is None:
+            traces = torch.empty((nrec, 3, self.nt), dtype=self.dtype, device=self.device)
+        flags = _abi.FD3D_KEEP_STATE if keep_state else 0
+        _abi.fd3d_forward_ckpt(self._ctx, src, nrec, rp.ctypes.data if nrec else None,
+                               traces.data_ptr() if nrec else None, flags, gws.data_ptr(), gws.numel(),
+                               gws.ckpt_every, _stream())
+        self._rec_keep = (rp, w)
+        return traces
+
+    def adjoint(self, gws: torch.Tensor, residual: torch.Tensor, g_lam: torch.Tensor, g_mu: torch.Tensor,
+                g_rho: torch.Tensor, src_pos=None, moment=(0.0,) * 6, force=(0.0,) * 3, wavelet=None,
+                rec_pos=None) -> None:
+        """Reverse sweep; accumulates dJ/dlambda, dJ/dmu, dJ/drho (node arrays) into g_*."""
+        w = self._wavelet(wavelet)
+        src = make_source(src_pos, moment, force, w) if src_pos is not None else None
+        rp, nrec = self._rec(rec_pos)
+        res = residual.to(device=self.device, dtype=self.dtype).contiguous()
+        if tuple(res.shape) != (nrec, 3, self.nt):
+            raise ValueError(f"residual must be [nrec, 3, nt] = {(nrec, 3, self.nt)}")
+        for g in (g_lam, g_mu, g_rho):
+            if g.dtype != self.dtype or not g.is_contiguous() or tuple(g.shape) != tuple(self.lam.shape):
+                raise ValueError("gradient buffers must be contiguous [nz, ny, nx] tensors of the context dtype")
+        _abi.fd3d_adjoint(self._ctx, src, nrec, rp.ctypes.data if nrec else None, res.data_ptr(),
+                          g_lam.data_ptr(), g_mu.data_ptr(), g_rho.data_ptr(), gws.data_ptr(), gws.numel(),
+                          _stream())
+        self._rec_keep = (rp, w, res)
+
+    def gradient(self, gws: torch.Tensor, d_obs: torch.Tensor, g_lam: torch.Tensor, g_mu: torch.Tensor,
+                 g_rho: torch.Tensor, src_pos=None, moment=(0.0,) * 6, force=(0.0,) * 3, wavelet=None,
+                 rec_pos=None):
+        """One shot of J = 1/2 |d - d_obs|^2: returns (traces, J as a 1-element tensor);
+        the gradient is accumulated into g_*."""
+        w = self._wavelet(wavelet)
+        src = make_source(src_pos, moment, force, w) if src_pos is not None else None
+        rp, nrec = self._rec(rec_pos)
+        obs = d_obs.to(device=self.device, dtype=self.dtype).contiguous()
+        if tuple(obs.shape) != (nrec, 3, self.nt):
+            raise ValueError(f"d_obs must be [nrec, 3, nt] = {(nrec, 3, self.nt)}")
+        for g in (g_lam, g_mu, g_rho):
+            if g.dtype != self.dtype or not g.is_contiguous() or tuple(g.shape) != tuple(self.lam.shape):
+                raise ValueError("gradient buffers must be contiguous [nz, ny, nx] tensors of the context dtype")
+        traces = torch.empty((nrec, 3, self.nt), dtype=self.dtype, device=self.device)
+        J = torch.empty(1, dtype=self.dtype, device=self.device)
+        _abi.fd3d_gradient(self._ctx, src, nrec, rp.ctypes.data, obs.data_ptr(), traces.data_ptr(), J.data_ptr(),
+                           g_lam.data_ptr(), g_mu.data_ptr(), g_rho.data_ptr(), gws.data_ptr(), gws.numel(),
+                           gws.ckpt_every, _stream())
+        self._rec_keep = (rp, w, obs)
+        return traces, J
+
+    def adjoint_state(self, gws: torch.Tensor) -> torch.Tensor:
+        """Adjoint of the initial state (v^{-1/2}, sigma^0) after ``adjoint``."""
+        nx, ny, nz = self.shape
+        out = torch.empty((9, nz, ny, nx), dtype=self.dtype, device=self.device)
+        _abi.fd3d_get_adjoint_state(self._ctx, gws.data_ptr(), [out[f].data_ptr() for f in range(9)], _stream())
+        return out
+
     def state(self) -> torch.Tensor:
         nx, ny, nz = self.shape
         out = torch.empty((9, nz, ny, nx), dtype=self.dtype, device=self.device)

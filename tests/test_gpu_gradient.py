@@ -1,0 +1,172 @@
+"""GPU FWI gradient (checkpointed discrete adjoint) against the oracle: the dot-product
+test of the adjoint propagation, the model gradient against the oracle's store-all
+adjoint and against central finite differences of the oracle forward, checkpointing
+against store-all, and the autograd Functions."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from helpers import random_state, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+NT, DT, H = 160, 1e-3, 10.0
+SPONGE, ALPHA = (6,) * 6, 0.05
+
+
+def fd_case():
+    lam, mu, rho, srcs, rec = W.small_fd_case(nt=NT)
+    nz, ny, nx = lam.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    blob = np.exp(-((x - 16) ** 2 + (y - 15) ** 2 + (z - 17) ** 2) / 20.0)
+    vp = np.sqrt((lam + 2 * mu) / rho) * (1.0 - 0.04 * blob)
+    true = W.elastic_from_vp(vp)
+    shots = [dict(src_pos=srcs[0], moment=W.explosion(1e15), force=(0.0, 0.0, 0.0), wavelet=W.ricker(25.0, NT, DT)),
+             dict(src_pos=srcs[1], moment=(0.0,) * 6, force=(3e9, -2e9, 4e9),
+                  wavelet=W.ricker(25.0, NT, DT, at_half=False))]
+    for s in shots:
+        s["rec_pos"] = rec
+    return (lam, mu, rho), true, shots
+
+
+def ocfg():
+    return oracle.Config((32, 32, 32), H, DT, NT, sponge=SPONGE, alpha=ALPHA)
+
+
+def osrc(s):
+    return oracle.Source(s["src_pos"], moment=s["moment"], force=s["force"])
+
+
+@pytest.fixture(scope="module")
+def case():
+    model, true, shots = fd_case()
+    d_obs = [oracle.forward(ocfg(), *true, osrc(s), s["wavelet"], s["rec_pos"])[0] for s in shots]
+    g = [np.zeros_like(model[0]) for _ in range(3)]
+    for s, obs in zip(shots, d_obs):
+        tr, _ = oracle.forward(ocfg(), *model, osrc(s), s["wavelet"], s["rec_pos"])
+        gl, gm, gr, _ = oracle.gradient(ocfg(), *model, osrc(s), s["wavelet"], s["rec_pos"], tr - obs)
+        g[0] += gl
+        g[1] += gm
+        g[2] += gr
+    return model, shots, d_obs, g
+
+
+def gpu_gradient(model, shots, d_obs, dtype, ckpt_every):
+    from paper_2112_15071_amd import Simulator
+
+    sim = Simulator(*model, H, DT, NT, dtype=dtype, sponge=SPONGE, sponge_alpha=ALPHA)
+    gws = sim.grad_workspace(ckpt_every)
+    g = [torch.zeros(model[0].shape, dtype=dtype, device="cuda") for _ in range(3)]
+    J = 0.0
+    for s, obs in zip(shots, d_obs):
+        _, j = sim.gradient(gws, torch.as_tensor(obs), *g, **s)
+        J += float(j.item())
+    torch.cuda.synchronize()
+    sim.close()
+    return J, [x.double().cpu().numpy() for x in g]
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 2e-4), (torch.float64, 1e-10)])
+def test_gradient_matches_oracle(case, dtype, tol):
+    model, shots, d_obs, g_ref = case
+    print(f"[grad] 32^3 x {NT}, 2 shots, {dtype}", flush=True)
+    J, g = gpu_gradient(model, shots, d_obs, dtype, ckpt_every=7)
+    for p in range(3):
+        assert rel_l2(g[p], g_ref[p]) <= tol, (p, rel_l2(g[p], g_ref[p]))
+
+
+def test_checkpointing_equals_store_all(case):
+    model, shots, d_obs, _ = case
+    _, a = gpu_gradient(model, shots, d_obs, torch.float32, ckpt_every=7)
+    _, b = gpu_gradient(model, shots, d_obs, torch.float32, ckpt_every=NT)
+    for p in range(3):
+        assert np.array_equal(a[p], b[p])
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-3), (torch.float64, 1e-6)])
+def test_gradient_against_oracle_finite_differences(case, dtype, tol):
+    model, shots, d_obs, _ = case
+    _, g = gpu_gradient(model, shots, d_obs, dtype, ckpt_every=13)
+    rng = np.random.default_rng(31)
+    for p in range(3):
+        d = rng.standard_normal(model[p].shape) * model[p]
+        eps = 1e-5
+        Js = []
+        for sgn in (1.0, -1.0):
+            m = [x.copy() for x in model]
+            m[p] = m[p] + sgn * eps * d
+            Js.append(sum(oracle.misfit(oracle.forward(ocfg(), *m, osrc(s), s["wavelet"], s["rec_pos"])[0], obs)
+                          for s, obs in zip(shots, d_obs)))
+        fd = (Js[0] - Js[1]) / (2 * eps)
+        an = float(np.sum(g[p] * d))
+        assert abs(fd - an) <= tol * abs(fd), (p, fd, an)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.float64, 1e-12)])
+def test_dot_product(dtype, tol):
+    """<P x0, r> = <x0, P^T r>: forward from a random state with sources off, adjoint of a
+    random residual, adjoint of the initial state read back."""
+    from paper_2112_15071_amd import Simulator
+
+    shape = (18, 16, 14)
+    rng = np.random.default_rng(22)
+    lam, mu, rho = W.elastic_from_vp(3000.0 * (1 + 0.2 * rng.random((14, 16, 18))))
+    nt = 50
+    x0 = random_state(shape, rng)
+    rec = np.array([[4.2, 5.5, 6.1], [12.7, 9.3, 3.3], [8.0, 8.0, 8.0], [8.3, 8.6, 8.1]])
+    sim = Simulator(lam, mu, rho, H, DT, nt, dtype=dtype, sponge=(4, 5, 3, 4, 5, 3))
+    sim.set_state(torch.as_tensor(x0, dtype=dtype))
+    x0_dev = sim.state().double().cpu().numpy()
+    gws = sim.grad_workspace(9)
+    d = sim.forward_ckpt(gws, rec_pos=rec, keep_state=True).double().cpu().numpy()
+    r = rng.standard_normal(d.shape)
+    g = [torch.zeros((14, 16, 18), dtype=dtype, device="cuda") for _ in range(3)]
+    sim.adjoint(gws, torch.as_tensor(r, dtype=dtype), *g, rec_pos=rec)
+    adj = sim.adjoint_state(gws).double().cpu().numpy()
+    r_dev = torch.as_tensor(r, dtype=dtype).double().numpy()
+    lhs = float(np.sum(d * r_dev))
+    rhs = float(np.sum(x0_dev * adj))
+    assert abs(lhs - rhs) <= tol * abs(lhs), (lhs, rhs)
+    sim.close()
+
+
+def test_autograd_functions_agree(case):
+    from paper_2112_15071_amd.fwi import Misfit, Traces
+
+    model, shots, d_obs, _ = case
+    opts = dict(dx=H, dt=DT, nt=NT, sponge=SPONGE, sponge_alpha=ALPHA, ckpt_every=11, dtype=torch.float64)
+    params = [torch.tensor(m, dtype=torch.float64, device="cuda", requires_grad=True) for m in model]
+    J = Misfit.apply(*params, shots, [torch.as_tensor(o, device="cuda") for o in d_obs], opts)
+    J.backward()
+    g_mis = [p.grad.clone() for p in params]
+    for p in params:
+        p.grad = None
+    loss = 0.0
+    for s, obs in zip(shots, d_obs):
+        tr = Traces.apply(*params, s, opts)
+        loss = loss + 0.5 * ((tr - torch.as_tensor(obs, device="cuda")) ** 2).sum()
+    loss.backward()
+    assert abs(float(loss) - float(J)) <= 1e-12 * abs(float(J))
+    for p, gm in zip(params, g_mis):
+        assert torch.allclose(p.grad, gm, rtol=1e-12, atol=0), float((p.grad - gm).abs().max())
+
+
+def test_adjoint_needs_checkpoints_and_damped_top():
+    from paper_2112_15071_amd import Simulator
+    from paper_2112_15071_amd._abi import FD3DError, FD3D_EINVAL, FD3D_ESTATE
+
+    lam, mu, rho = W.homogeneous((16, 16, 16))
+    sim = Simulator(lam, mu, rho, H, DT, 10)
+    gws = sim.grad_workspace(5)
+    g = [torch.zeros((16, 16, 16), device="cuda") for _ in range(3)]
+    with pytest.raises(FD3DError) as e:
+        sim.adjoint(gws, torch.zeros((1, 3, 10)), *g, rec_pos=[[8.0, 8.0, 8.0]])
+    assert e.value.code == FD3D_ESTATE
+    sim.close()
+    fs = Simulator(lam, mu, rho, H, DT, 10, free_surface=True)
+    with pytest.raises(FD3DError) as e:
+        fs.forward_ckpt(fs.grad_workspace(5), rec_pos=[[8.0, 8.0, 8.0]])
+    assert e.value.code == FD3D_EINVAL
+    fs.close()
