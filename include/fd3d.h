@@ -163,6 +163,35 @@ int fd3d_gradient(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double 
 int fd3d_get_adjoint_state(fd3d_ctx *ctx, const void *gws, void *const fields[9],
                            void *hip_stream);
 
+/* ---- Batches: many shots stepped together ------------------------------------------
+ *
+ * A batch groups contexts (each with its own grid size, model, workspace, source and
+ * receivers; one dtype, one nt and one free-surface option for all).  Each pass of each
+ * step runs as ONE persistent launch over the flat list of every shot's tiles (the list
+ * is split into 8 contiguous chunks, one per XCD); with use_graph the whole nt-step
+ * sequence is captured once into a hipGraph and replayed by one hipGraphLaunch on the
+ * caller's stream (recaptured when the tiling or receiver counts change).  Per-shot
+ * results are identical to fd3d_forward on each context with the same tile shape.
+ * The batch workspace holds the per-shot descriptors (caller-owned device memory).
+ * The contexts must outlive the batch. */
+typedef struct fd3d_batch fd3d_batch;
+
+int fd3d_batch_workspace_bytes(int nshot, fd3d_ctx *const *ctxs, size_t *bytes);
+int fd3d_batch_create(fd3d_batch **out, int nshot, fd3d_ctx *const *ctxs, void *workspace,
+                      size_t ws_bytes);
+
+/* Tile shape for every shot of the batch (fd3d_kernel shapes) and the number of
+ * persistent workgroups (0: CUs x occupancy, rounded to a multiple of 8). */
+int fd3d_batch_set_kernel(fd3d_batch *b, int tile_x, int tile_y, int workgroups);
+
+/* srcs[nshot] (or NULL), nrec[nshot], rec_pos[nshot] (host double[nrec][3] each),
+ * traces[nshot] (device T[nrec][3][nt] each); flags as fd3d_forward. */
+int fd3d_batch_forward(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
+                       const double *const *rec_pos, void *const *traces, int flags, int use_graph,
+                       void *hip_stream);
+
+void fd3d_batch_destroy(fd3d_batch *b);
+
 /* Kernel selection for the step loop of later calls on this context.  All variants
  * compute the same update with the same operation order per sample. */
 typedef struct fd3d_kernel {

@@ -94,6 +94,12 @@ _SIGS = {
     "fd3d_adjoint": ([_vp, ctypes.POINTER(fd3d_source), _i, _dp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
     "fd3d_gradient": ([_vp, ctypes.POINTER(fd3d_source), _i, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i, _vp], _i),
     "fd3d_get_adjoint_state": ([_vp, _vp, ctypes.POINTER(_vp), _vp], _i),
+    "fd3d_batch_workspace_bytes": ([_i, ctypes.POINTER(_vp), ctypes.POINTER(_sz)], _i),
+    "fd3d_batch_create": ([ctypes.POINTER(_vp), _i, ctypes.POINTER(_vp), _vp, _sz], _i),
+    "fd3d_batch_set_kernel": ([_vp, _i, _i, _i], _i),
+    "fd3d_batch_forward": ([_vp, ctypes.POINTER(fd3d_source), ctypes.POINTER(_i), ctypes.POINTER(_dp),
+                            ctypes.POINTER(_vp), _i, _i, _vp], _i),
+    "fd3d_batch_destroy": ([_vp], None),
     "fd3d_set_kernel": ([_vp, ctypes.POINTER(fd3d_kernel)], _i),
     "fd3d_get_kernel": ([_vp, ctypes.POINTER(fd3d_kernel)], _i),
     "fd3d_profile": ([_vp, _i], _i),
@@ -194,6 +200,39 @@ def fd3d_gradient(ctx, src, nrec, rec_pos_ptr, d_obs, traces, misfit, g_lam, g_m
 
 def fd3d_get_adjoint_state(ctx, gws, fields, stream) -> None:
     _check(_lib.fd3d_get_adjoint_state(ctx, gws, _ptr9(fields), stream))
+
+
+def fd3d_batch_workspace_bytes(ctxs) -> int:
+    arr = (_vp * len(ctxs))(*ctxs)
+    out = _sz(0)
+    _check(_lib.fd3d_batch_workspace_bytes(len(ctxs), arr, ctypes.byref(out)))
+    return int(out.value)
+
+
+def fd3d_batch_create(ctxs, workspace, ws_bytes) -> int:
+    arr = (_vp * len(ctxs))(*ctxs)
+    b = _vp(0)
+    _check(_lib.fd3d_batch_create(ctypes.byref(b), len(ctxs), arr, workspace, ws_bytes))
+    return int(b.value)
+
+
+def fd3d_batch_set_kernel(batch, tile_x: int, tile_y: int, workgroups: int = 0) -> None:
+    _check(_lib.fd3d_batch_set_kernel(batch, int(tile_x), int(tile_y), int(workgroups)))
+
+
+def fd3d_batch_forward(batch, srcs, nrec, rec_ptrs, traces, flags, use_graph, stream) -> None:
+    """srcs: list of fd3d_source (or None); nrec: list of int; rec_ptrs: host addresses of
+    double[nrec][3]; traces: device addresses of T[nrec][3][nt]."""
+    n = len(nrec)
+    sarr = (fd3d_source * n)(*srcs) if srcs is not None else None
+    narr = (_i * n)(*nrec)
+    rarr = (_dp * n)(*[ctypes.cast(p, _dp) if p else None for p in rec_ptrs])
+    tarr = (_vp * n)(*traces)
+    _check(_lib.fd3d_batch_forward(batch, sarr, narr, rarr, tarr, int(flags), int(bool(use_graph)), stream))
+
+
+def fd3d_batch_destroy(batch) -> None:
+    _lib.fd3d_batch_destroy(batch)
 
 
 def fd3d_set_kernel(ctx, k: fd3d_kernel) -> None:

@@ -648,6 +648,196 @@ template <typename T> int set_state_impl(fd3d_ctx *c, const void *const fields[9
 
 } // namespace
 
+// ---------------------------------------------------------------------------------
+// Batches: many contexts (uneven grids, own models, sources and receivers) stepped
+// together, one persistent launch per pass for all shots, optionally captured once as
+// a hipGraph holding the whole nt-step sequence.
+
+struct fd3d_batch {
+    int nshot;
+    std::vector<fd3d_ctx *> ctx;
+    int tsize, nt, fs;
+    char *ws;
+    size_t ws_bytes;
+    size_t off_fwd, off_rec;
+    int tile_x, tile_y, wgs_req;
+    std::vector<unsigned char> fwd_host, rec_host;
+    hipEvent_t staged;
+    bool staged_pending;
+    hipStream_t cap;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    bool graph_valid;
+    long graph_key;
+    int total_tiles, total_rec, wgs;
+};
+
+namespace {
+
+size_t batch_desc_bytes(int nshot, int tsize)
+{
+    const size_t f = tsize == 8 ? sizeof(ShotFwd<double>) : sizeof(ShotFwd<float>);
+    const size_t r = tsize == 8 ? sizeof(ShotRec<double>) : sizeof(ShotRec<float>);
+    return round_up((size_t)nshot * f, kAlign) + round_up((size_t)nshot * r, kAlign);
+}
+
+template <typename T, int TX, int TY, bool FS>
+int launch_multi(fd3d_batch *b, int n, int pass, hipStream_t st)
+{
+    const ShotFwd<T> *d = (const ShotFwd<T> *)(b->ws + b->off_fwd);
+    if (pass == 0) vel_tile_multi<T, TX, TY, FS><<<b->wgs, TX * TY, 0, st>>>(d, b->nshot, b->total_tiles, n);
+    else stress_tile_multi<T, TX, TY, FS><<<b->wgs, TX * TY, 0, st>>>(d, b->nshot, b->total_tiles, n);
+    return FD3D_OK;
+}
+
+template <typename T, bool FS> int multi_pass(fd3d_batch *b, int n, int pass, hipStream_t st)
+{
+    const int key = b->tile_x * 100 + b->tile_y;
+    if (sizeof(T) == 8) {
+        switch (key) {
+        case 6404: return launch_multi<T, 64, 4, FS>(b, n, pass, st);
+        case 12804: return launch_multi<T, 128, 4, FS>(b, n, pass, st);
+        default: return launch_multi<T, 64, 8, FS>(b, n, pass, st);
+        }
+    }
+    switch (key) {
+    case 6404: return launch_multi<T, 64, 4, FS>(b, n, pass, st);
+    case 6416: return launch_multi<T, 64, 16, FS>(b, n, pass, st);
+    case 12804: return launch_multi<T, 128, 4, FS>(b, n, pass, st);
+    case 12808: return launch_multi<T, 128, 8, FS>(b, n, pass, st);
+    case 25604: return launch_multi<T, 256, 4, FS>(b, n, pass, st);
+    default: return launch_multi<T, 64, 8, FS>(b, n, pass, st);
+    }
+}
+
+template <typename T, int TX, int TY, bool FS> int occupancy_of()
+{
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, vel_tile_multi<T, TX, TY, FS>, TX * TY, 0) != hipSuccess)
+        occ = 1;
+    return occ > 0 ? occ : 1;
+}
+
+template <typename T, bool FS> int multi_occupancy(const fd3d_batch *b)
+{
+    const int key = b->tile_x * 100 + b->tile_y;
+    if (sizeof(T) == 8) {
+        switch (key) {
+        case 6404: return occupancy_of<T, 64, 4, FS>();
+        case 12804: return occupancy_of<T, 128, 4, FS>();
+        default: return occupancy_of<T, 64, 8, FS>();
+        }
+    }
+    switch (key) {
+    case 6404: return occupancy_of<T, 64, 4, FS>();
+    case 6416: return occupancy_of<T, 64, 16, FS>();
+    case 12804: return occupancy_of<T, 128, 4, FS>();
+    case 12808: return occupancy_of<T, 128, 8, FS>();
+    case 25604: return occupancy_of<T, 256, 4, FS>();
+    default: return occupancy_of<T, 64, 8, FS>();
+    }
+}
+
+// The whole nt-step sequence of a batch on one stream (also what a graph captures).
+template <typename T> int batch_sequence(fd3d_batch *b, int flags, hipStream_t st)
+{
+    if (!(flags & FD3D_KEEP_STATE))
+        for (fd3d_ctx *c : b->ctx) zero_fields<T>(c, st);
+    const ShotRec<T> *r = (const ShotRec<T> *)(b->ws + b->off_rec);
+    for (int n = 0; n < b->nt; ++n) {
+        if (b->fs) multi_pass<T, true>(b, n, 0, st);
+        else multi_pass<T, false>(b, n, 0, st);
+        if (b->total_rec > 0)
+            record_multi<T><<<(b->total_rec + 255) / 256, 256, 0, st>>>(r, b->nshot, b->total_rec, b->nt, n);
+        if (b->fs) multi_pass<T, true>(b, n, 1, st);
+        else multi_pass<T, false>(b, n, 1, st);
+    }
+    HIP_TRY(hipGetLastError());
+    return FD3D_OK;
+}
+
+template <typename T>
+int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, const double *const *rec_pos,
+                       void *const *traces, int flags, int use_graph, hipStream_t st)
+{
+    std::vector<ShotFwd<T>> fw(b->nshot);
+    std::vector<ShotRec<T>> rr(b->nshot);
+    int tiles = 0, recs = 0;
+    for (int s = 0; s < b->nshot; ++s) {
+        fd3d_ctx *c = b->ctx[s];
+        const int nr = nrec ? nrec[s] : 0;
+        if (nr < 0 || nr > c->opts.max_receivers) return fail(FD3D_EINVAL, "shot " + std::to_string(s) + ": bad nrec");
+        if (nr > 0 && (!rec_pos || !rec_pos[s] || !traces || !traces[s]))
+            return fail(FD3D_EINVAL, "shot " + std::to_string(s) + ": rec_pos/traces is NULL");
+        int rc = build_source<T>(c, srcs ? &srcs[s] : nullptr, fw[s].src);
+        if (rc) return fail(rc, "shot " + std::to_string(s) + ": " + g_err);
+        rc = stage_receivers<T>(c, nr, nr ? rec_pos[s] : nullptr, st);
+        if (rc) return fail(rc, "shot " + std::to_string(s) + ": " + g_err);
+        fw[s].G = make_grid<T>(c);
+        TileMap tm;
+        tm.ntx = (c->n[0] + b->tile_x - 1) / b->tile_x;
+        tm.nty = (c->n[1] + b->tile_y - 1) / b->tile_y;
+        tm.zc = c->zchunk;
+        tm.nzc = (c->n[2] + c->zchunk - 1) / c->zchunk;
+        fw[s].tm = tm;
+        fw[s].base = tiles;
+        fw[s].pad = 0;
+        tiles += tm.ntx * tm.nty * tm.nzc;
+        for (int q = 0; q < 3; ++q) rr[s].v[q] = fw[s].G.f[VX + q];
+        rr[s].taps = (const RecTap<T> *)(c->ws + c->L.rec);
+        rr[s].traces = nr ? (T *)traces[s] : nullptr;
+        rr[s].nrec = nr;
+        rr[s].base = recs;
+        recs += 3 * nr;
+    }
+    if (b->staged_pending) {
+        HIP_TRY(hipEventSynchronize(b->staged));
+        b->staged_pending = false;
+    }
+    b->fwd_host.assign((const unsigned char *)fw.data(), (const unsigned char *)(fw.data() + b->nshot));
+    b->rec_host.assign((const unsigned char *)rr.data(), (const unsigned char *)(rr.data() + b->nshot));
+    HIP_TRY(hipMemcpyAsync(b->ws + b->off_fwd, b->fwd_host.data(), b->fwd_host.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b->ws + b->off_rec, b->rec_host.data(), b->rec_host.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(b->staged, st));
+    b->staged_pending = true;
+
+    // persistent grid: a multiple of 8 workgroups (one chunk of the list per XCD)
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int occ = b->fs ? multi_occupancy<T, true>(b) : multi_occupancy<T, false>(b);
+    int wgs = b->wgs_req > 0 ? b->wgs_req : cus * occ;
+    wgs = std::min(wgs, ((tiles + 7) / 8) * 8);
+    wgs = std::max(8, (wgs + 7) / 8 * 8);
+    const long key = ((long)tiles << 32) ^ ((long)recs << 16) ^ ((long)wgs << 4) ^ (flags & FD3D_KEEP_STATE) ^
+                     ((long)b->tile_x << 40) ^ ((long)b->tile_y << 52);
+    b->total_tiles = tiles;
+    b->total_rec = recs;
+    b->wgs = wgs;
+    if (!use_graph) return batch_sequence<T>(b, flags, st);
+    if (!b->graph_valid || b->graph_key != key) {
+        if (b->graph_valid) {
+            (void)hipGraphExecDestroy(b->gexec);
+            (void)hipGraphDestroy(b->graph);
+            b->graph_valid = false;
+        }
+        HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+        const int rc = batch_sequence<T>(b, flags, b->cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->cap, &g);
+        if (rc) return rc;
+        if (e != hipSuccess) return fail(FD3D_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+        b->graph_valid = true;
+        b->graph_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(b->gexec, st));
+    return FD3D_OK;
+}
+
+} // namespace
+
 extern "C" {
 
 const char *fd3d_version(void) { return "fd3d 0.1.0 (gfx950)"; }
@@ -912,6 +1102,101 @@ int fd3d_get_kernel(const fd3d_ctx *ctx, fd3d_kernel *k)
     k->tile_y = ctx->tile_y;
     k->zchunk = ctx->zchunk;
     return FD3D_OK;
+}
+
+int fd3d_batch_workspace_bytes(int nshot, fd3d_ctx *const *ctxs, size_t *bytes)
+{
+    if (nshot < 1 || !ctxs || !bytes) return fail(FD3D_EINVAL, "nshot/ctxs/bytes");
+    if (!ctxs[0]) return fail(FD3D_EINVAL, "context 0 is NULL");
+    *bytes = batch_desc_bytes(nshot, ctxs[0]->tsize);
+    return FD3D_OK;
+}
+
+int fd3d_batch_create(fd3d_batch **out, int nshot, fd3d_ctx *const *ctxs, void *workspace, size_t ws_bytes)
+{
+    if (!out) return fail(FD3D_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    int rc = fd3d_batch_workspace_bytes(nshot, ctxs, &need);
+    if (rc) return rc;
+    for (int s = 0; s < nshot; ++s) {
+        if (!ctxs[s]) return fail(FD3D_EINVAL, "context " + std::to_string(s) + " is NULL");
+        if (ctxs[s]->tsize != ctxs[0]->tsize) return fail(FD3D_EINVAL, "all shots must share one dtype");
+        if (ctxs[s]->nt != ctxs[0]->nt) return fail(FD3D_EINVAL, "all shots must share nt");
+        if (ctxs[s]->opts.free_surface != ctxs[0]->opts.free_surface)
+            return fail(FD3D_EINVAL, "all shots must share the free-surface option");
+        for (int q = 0; q < s; ++q)
+            if (ctxs[q] == ctxs[s]) return fail(FD3D_EINVAL, "a context appears twice in the batch");
+    }
+    if (!workspace || ((uintptr_t)workspace % kAlign)) return fail(FD3D_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return fail(FD3D_EWS, "batch workspace too small: need " + std::to_string(need) + " bytes");
+    fd3d_batch *b = new (std::nothrow) fd3d_batch();
+    if (!b) return fail(FD3D_EINVAL, "out of host memory");
+    b->nshot = nshot;
+    b->ctx.assign(ctxs, ctxs + nshot);
+    b->tsize = ctxs[0]->tsize;
+    b->nt = ctxs[0]->nt;
+    b->fs = ctxs[0]->opts.free_surface;
+    b->ws = (char *)workspace;
+    b->ws_bytes = ws_bytes;
+    b->off_fwd = 0;
+    b->off_rec = round_up((size_t)nshot * (b->tsize == 8 ? sizeof(ShotFwd<double>) : sizeof(ShotFwd<float>)), kAlign);
+    // tile shape of the batch: the widest default among the shots that every shot supports
+    int minx = ctxs[0]->n[0];
+    for (int s = 1; s < nshot; ++s) minx = std::min(minx, ctxs[s]->n[0]);
+    if (b->tsize == 4 && minx >= 256) { b->tile_x = 256; b->tile_y = 4; }
+    else if (minx >= 128) { b->tile_x = 128; b->tile_y = 4; }
+    else { b->tile_x = 64; b->tile_y = 8; }
+    b->wgs_req = 0;
+    b->staged_pending = false;
+    b->graph_valid = false;
+    b->graph_key = 0;
+    b->total_tiles = b->total_rec = b->wgs = 0;
+    if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
+        delete b;
+        return fail(FD3D_EHIP, "hipEventCreateWithFlags failed");
+    }
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipEventDestroy(b->staged);
+        delete b;
+        return fail(FD3D_EHIP, "hipStreamCreateWithFlags failed");
+    }
+    *out = b;
+    return FD3D_OK;
+}
+
+int fd3d_batch_set_kernel(fd3d_batch *b, int tile_x, int tile_y, int workgroups)
+{
+    if (!b) return fail(FD3D_EINVAL, "batch is NULL");
+    if (!tile_supported(b->tsize, tile_x, tile_y))
+        return fail(FD3D_EINVAL, "unsupported tile shape " + std::to_string(tile_x) + "x" + std::to_string(tile_y));
+    if (workgroups < 0) return fail(FD3D_EINVAL, "workgroups must be >= 0");
+    b->tile_x = tile_x;
+    b->tile_y = tile_y;
+    b->wgs_req = workgroups;
+    return FD3D_OK;
+}
+
+int fd3d_batch_forward(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, const double *const *rec_pos,
+                       void *const *traces, int flags, int use_graph, void *hip_stream)
+{
+    if (!b) return fail(FD3D_EINVAL, "batch is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    return b->tsize == 8 ? batch_forward_impl<double>(b, srcs, nrec, rec_pos, traces, flags, use_graph, st)
+                         : batch_forward_impl<float>(b, srcs, nrec, rec_pos, traces, flags, use_graph, st);
+}
+
+void fd3d_batch_destroy(fd3d_batch *b)
+{
+    if (!b) return;
+    if (b->staged_pending) (void)hipEventSynchronize(b->staged);
+    if (b->graph_valid) {
+        (void)hipGraphExecDestroy(b->gexec);
+        (void)hipGraphDestroy(b->graph);
+    }
+    (void)hipStreamDestroy(b->cap);
+    (void)hipEventDestroy(b->staged);
+    delete b;
 }
 
 int fd3d_profile(fd3d_ctx *ctx, int enable)

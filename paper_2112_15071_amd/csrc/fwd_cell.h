@@ -171,4 +171,33 @@ __global__ void __launch_bounds__(256) record(const T *__restrict__ vx, const T 
     traces[(long)q * nt + n] = s;
 }
 
+// Receiver sampling of many shots in one launch: shot s owns work items
+// [base, base + 3 nrec) of the flat list.
+template <typename T> struct ShotRec {
+    const T *v[3];
+    const RecTap<T> *taps;
+    T *traces;
+    int nrec, base;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) record_multi(const ShotRec<T> *__restrict__ shots, int nshot, int total, int nt,
+                                                    int n)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    int s = 0;
+    while (s + 1 < nshot && shots[s + 1].base <= q) ++s;
+    const ShotRec<T> &d = shots[s];
+    const int l = q - d.base;
+    const int c = l % 3;
+    const T *f = d.v[c];
+    const RecTap<T> &t = d.taps[l];
+    T acc = T(0);
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+        if (t.idx[m] >= 0) acc += t.w[m] * f[t.idx[m]];
+    d.traces[(long)l * nt + n] = acc;
+}
+
 } // namespace fd3d

@@ -128,10 +128,9 @@ __device__ __forceinline__ Slot cslot(bool mine, int i0, int j0, int nx, int ny,
     return s;
 }
 
-__device__ __forceinline__ void tile_coords(const TileMap &tm, int &i0, int &j0, int &k0, int &k1, int TX, int TY,
-                                            int nz)
+__device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, int &j0, int &k0, int &k1, int TX,
+                                            int TY, int nz)
 {
-    int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tz = t % tm.nzc;
     t /= tm.nzc;
     const int bx = t % tm.ntx, by = t / tm.ntx;
@@ -153,7 +152,8 @@ template <typename T> __device__ __forceinline__ T pick(const T (&c)[8], int t)
 // ---------------------------------------------------------------------------------
 // (V) velocity pass, tiled.  Same arithmetic per sample as vel_cell.
 template <typename T, int TX, int TY, bool FS>
-__global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
+__device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0, int k0,
+                                              int k1)
 {
     constexpr int NT = TX * TY;
     // LDS plane shapes: sxx x(-1,+2); sxy x(-2,+1) y(-2,+1); sxz x(-2,+1); syy y(-1,+2);
@@ -167,8 +167,6 @@ __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int
     __shared__ T s_yz[2][NYZ + 1];
     __shared__ T s_r[2][NR + 1];
 
-    int i0, j0, k0, k1;
-    tile_coords(tm, i0, j0, k0, k1, TX, TY, G.nz);
     const int nx = G.nx, ny = G.ny, nz = G.nz;
     const int sy = (int)G.sy;
     const long sz = G.sz;
@@ -326,7 +324,8 @@ __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int
 // ---------------------------------------------------------------------------------
 // (S) stress pass, tiled.  Same arithmetic per sample as stress_cell.
 template <typename T, int TX, int TY, bool FS>
-__global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
+__device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0,
+                                                 int k0, int k1)
 {
     constexpr int NT = TX * TY;
     // vx x(-2,+1) y(-1,+2); vy x(-1,+2) y(-2,+1); vz x(-1,+2) y(-1,+2); mu x(+1) y(+1) corner
@@ -337,8 +336,6 @@ __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, 
     __shared__ T s_vz[2][NV + 1];
     __shared__ T s_mu[3][NM + 1];
 
-    int i0, j0, k0, k1;
-    tile_coords(tm, i0, j0, k0, k1, TX, TY, G.nz);
     const int nx = G.nx, ny = G.ny, nz = G.nz;
     const int sy = (int)G.sy;
     const long sz = G.sz;
@@ -509,6 +506,94 @@ __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, 
         qvy[0] = qvy[1]; qvy[1] = qvy[2]; qvy[2] = qvy[3]; qvy[3] = nvy;
         qvz[0] = qvz[1]; qvz[1] = qvz[2]; qvz[2] = qvz[3]; qvz[3] = nvz;
         m1 = nm1;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Single-grid launches: one workgroup per tile.
+template <typename T, int TX, int TY, bool FS>
+__global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
+{
+    int i0, j0, k0, k1;
+    tile_coords(tm, xcd_remap(blockIdx.x, gridDim.x), i0, j0, k0, k1, TX, TY, G.nz);
+    vel_tile_body<T, TX, TY, FS>(G, src, n, i0, j0, k0, k1);
+}
+
+template <typename T, int TX, int TY, bool FS>
+__global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
+{
+    int i0, j0, k0, k1;
+    tile_coords(tm, xcd_remap(blockIdx.x, gridDim.x), i0, j0, k0, k1, TX, TY, G.nz);
+    stress_tile_body<T, TX, TY, FS>(G, src, n, i0, j0, k0, k1);
+}
+
+// ---------------------------------------------------------------------------------
+// Many grids in one persistent launch.  Every shot contributes its tiles to one flat
+// work list (shot-major); the list is cut into 8 contiguous chunks, one per XCD, and
+// the workgroups of an XCD walk their chunk with a stride of the XCD's workgroup count.
+// A workgroup loads the descriptor of the shot its tile belongs to (uniform, scalar).
+template <typename T> struct ShotFwd {
+    Grid<T> G;
+    Inject<T> src;
+    TileMap tm;
+    int base;  // first work item of this shot
+    int pad;
+};
+
+// Work item range [lo, hi) and stride of this workgroup in the XCD-chunked order.
+__device__ __forceinline__ void work_range(int total, int &w0, int &hi, int &stride)
+{
+    const int x = blockIdx.x & 7, l = blockIdx.x >> 3;
+    const int per = (int)(gridDim.x >> 3);  // gridDim.x is a multiple of 8
+    const int lo = (int)((long)total * x / 8);
+    hi = (int)((long)total * (x + 1) / 8);
+    w0 = lo + l;
+    stride = per;
+}
+
+template <typename T>
+__device__ __forceinline__ int find_shot(const ShotFwd<T> *__restrict__ shots, int nshot, int w)
+{
+    int s = 0;
+    while (s + 1 < nshot && shots[s + 1].base <= w) ++s;
+    return s;
+}
+
+template <typename T, int TX, int TY, bool FS>
+__global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
+                                                          int n)
+{
+    int w, hi, stride;
+    work_range(total, w, hi, stride);
+    for (; w < hi; w += stride) {
+        const int s = find_shot(shots, nshot, w);
+        const ShotFwd<T> &d = shots[s];
+        const Grid<T> G = d.G;
+        const Inject<T> src = d.src;
+        const TileMap tm = d.tm;
+        int i0, j0, k0, k1;
+        tile_coords(tm, w - d.base, i0, j0, k0, k1, TX, TY, G.nz);
+        vel_tile_body<T, TX, TY, FS>(G, src, n, i0, j0, k0, k1);
+        __syncthreads();
+    }
+}
+
+template <typename T, int TX, int TY, bool FS>
+__global__ void __launch_bounds__(TX *TY) stress_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
+                                                          int n)
+{
+    int w, hi, stride;
+    work_range(total, w, hi, stride);
+    for (; w < hi; w += stride) {
+        const int s = find_shot(shots, nshot, w);
+        const ShotFwd<T> &d = shots[s];
+        const Grid<T> G = d.G;
+        const Inject<T> src = d.src;
+        const TileMap tm = d.tm;
+        int i0, j0, k0, k1;
+        tile_coords(tm, w - d.base, i0, j0, k0, k1, TX, TY, G.nz);
+        stress_tile_body<T, TX, TY, FS>(G, src, n, i0, j0, k0, k1);
+        __syncthreads();
     }
 }
 

@@ -1,0 +1,128 @@
+"""Batched stepping: many uneven shots in one persistent launch per pass, eager or
+replayed from one hipGraph, give per-shot results identical to single-shot runs with the
+same tile shape (and so the oracle's)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_cases import compare, oracle_run
+from helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(40, 36, 28), (52, 33, 30), (37, 29, 23), (64, 40, 32)]
+NT, DT = 80, 5e-4
+
+
+def make_shots(seed, fs=False):
+    shots = []
+    for s, shape in enumerate(SHAPES):
+        rng = np.random.Generator(np.random.PCG64(seed + s))
+        lam, mu, rho = W.layered_perturbed(shape, 10.0, seed + 10 + s)
+        nx, ny, nz = shape
+        pos = (float(rng.uniform(8, nx - 9)), float(rng.uniform(8, ny - 9)), float(rng.uniform(6, nz - 7)))
+        rec = np.stack([rng.uniform(3, nx - 4, 5), rng.uniform(3, ny - 4, 5), rng.uniform(1, nz - 4, 5)], axis=1)
+        sponge = (5, 5, 5, 5, 0 if fs else 5, 5)
+        shots.append(W.Shot(f"b{s}", shape, 10.0, DT, NT, lam, mu, rho, pos, W.random_mt(rng),
+                            tuple(rng.standard_normal(3) * 1e9), W.ricker(40.0, NT, DT), rec, sponge=sponge,
+                            free_surface=fs))
+    return shots
+
+
+def sims_for(shots, dtype=torch.float32):
+    from paper_2112_15071_amd import Simulator
+
+    return [Simulator(s.lam, s.mu, s.rho, s.h, s.dt, s.nt, dtype=dtype, sponge=s.sponge,
+                      free_surface=s.free_surface) for s in shots]
+
+
+def desc(s, scale=1.0):
+    return dict(src_pos=s.src_pos, moment=tuple(scale * m for m in s.moment), force=s.force, wavelet=s.wavelet,
+                rec_pos=s.rec_pos)
+
+
+def single_runs(shots, tile, scale=1.0, dtype=torch.float32):
+    out = []
+    for sim, s in zip(sims_for(shots, dtype), shots):
+        sim.set_kernel("tile", tile[1], sim.kernel()["zchunk"], tile[0])
+        tr = sim.forward(**desc(s, scale))
+        out.append((tr.double().cpu().numpy(), sim.state().double().cpu().numpy()))
+        sim.close()
+    return out
+
+
+@pytest.mark.parametrize("fs", [False, True])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_equals_single_shots(fs, use_graph):
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    shots = make_shots(500 + int(fs), fs)
+    tile = (64, 8)
+    ref = single_runs(shots, tile)
+    sims = sims_for(shots)
+    batch = BatchSimulator(sims)
+    batch.set_kernel(*tile)
+    print(f"[batch] fs={fs} graph={use_graph}", flush=True)
+    trs = batch.forward([desc(s) for s in shots], use_graph=use_graph)
+    torch.cuda.synchronize()
+    for k, (sim, tr) in enumerate(zip(sims, trs)):
+        assert np.array_equal(tr.double().cpu().numpy(), ref[k][0]), k
+        assert np.array_equal(sim.state().double().cpu().numpy(), ref[k][1]), k
+    # one shot against the oracle as well
+    compare((trs[2].double().cpu().numpy(), sims[2].state().double().cpu().numpy()), oracle_run(shots[2]), 1e-4,
+            "batched shot 2")
+    batch.close()
+    for s in sims:
+        s.close()
+
+
+def test_graph_replays_with_new_sources():
+    """Replays of the captured graph, with eager work and synchronisation in between,
+    each match eager single-shot runs for the sources of that replay."""
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    shots = make_shots(700)
+    tile = (64, 8)
+    sims = sims_for(shots)
+    batch = BatchSimulator(sims)
+    batch.set_kernel(*tile)
+    for rep, scale in enumerate((1.0, -0.5, 2.0)):
+        trs = batch.forward([desc(s, scale) for s in shots], use_graph=True)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        ref = single_runs(shots, tile, scale)
+        for k, (sim, tr) in enumerate(zip(sims, trs)):
+            assert np.array_equal(tr.double().cpu().numpy(), ref[k][0]), (rep, k)
+            assert np.array_equal(sim.state().double().cpu().numpy(), ref[k][1]), (rep, k)
+        del junk
+    batch.close()
+    for s in sims:
+        s.close()
+
+
+def test_full_size_uneven_batch_truncated():
+    """The 24-shot uneven batch at full size (128^3 .. 256x256x128), 12 steps, in the
+    launch configuration of the benchmark: every shot equals its single-shot run."""
+    from paper_2112_15071_amd import Simulator
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    nt = 12
+    shots = W.c3(nt=nt)
+    print(f"[batch] 24 uneven shots x {nt}", flush=True)
+    sims = [Simulator(s.lam, s.mu, s.rho, s.h, s.dt, nt, sponge=s.sponge) for s in shots]
+    batch = BatchSimulator(sims)
+    trs = batch.forward([desc(s) for s in shots], use_graph=True)
+    torch.cuda.synchronize()
+    tile = (128, 4)  # the batch default for these widths
+    for k, s in enumerate(shots):
+        one = Simulator(s.lam, s.mu, s.rho, s.h, s.dt, nt, sponge=s.sponge)
+        one.set_kernel("tile", tile[1], one.kernel()["zchunk"], tile[0])
+        tr = one.forward(**desc(s))
+        assert torch.equal(tr, trs[k]), k
+        assert torch.equal(one.state(), sims[k].state()), k
+        one.close()
+    batch.close()
+    for s in sims:
+        s.close()
