@@ -190,6 +190,22 @@ int fd3d_batch_forward(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
                        const double *const *rec_pos, void *const *traces, int flags, int use_graph,
                        void *hip_stream);
 
+/* Batched L2-misfit gradient: fd3d_gradient for every shot of the batch, stepped
+ * together (forward with checkpoints, then per segment a batched recompute and batched
+ * adjoint steps; residual injection per tap-disjoint colour, at most 4 colours per shot).
+ * Per shot s: d_obs[s], traces[s] (written), misfit[s] (device T or NULL), g_*[s]
+ * (accumulated; shots may share output arrays, they are added in shot order), gws[s]
+ * (a gradient workspace of fd3d_grad_workspace_bytes(ctx_s, ckpt_every) bytes).  bws is a
+ * batch gradient workspace of fd3d_batch_grad_workspace_bytes bytes.  flags: 0 or
+ * FD3D_KEEP_STATE (start every shot from its context's current state).  Results per shot
+ * equal fd3d_gradient's. */
+int fd3d_batch_grad_workspace_bytes(const fd3d_batch *b, int ckpt_every, size_t *bytes);
+int fd3d_batch_gradient(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
+                        const double *const *rec_pos, const void *const *d_obs, void *const *traces,
+                        void *const *misfit, void *const *g_lam, void *const *g_mu,
+                        void *const *g_rho, void *const *gws, const size_t *gws_bytes,
+                        int ckpt_every, int flags, void *bws, size_t bws_bytes, void *hip_stream);
+
 void fd3d_batch_destroy(fd3d_batch *b);
 
 /* Kernel selection for the step loop of later calls on this context.  All variants

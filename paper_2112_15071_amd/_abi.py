@@ -99,6 +99,11 @@ _SIGS = {
     "fd3d_batch_set_kernel": ([_vp, _i, _i, _i], _i),
     "fd3d_batch_forward": ([_vp, ctypes.POINTER(fd3d_source), ctypes.POINTER(_i), ctypes.POINTER(_dp),
                             ctypes.POINTER(_vp), _i, _i, _vp], _i),
+    "fd3d_batch_grad_workspace_bytes": ([_vp, _i, ctypes.POINTER(_sz)], _i),
+    "fd3d_batch_gradient": ([_vp, ctypes.POINTER(fd3d_source), ctypes.POINTER(_i), ctypes.POINTER(_dp),
+                             ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                             ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_sz), _i, _i,
+                             _vp, _sz, _vp], _i),
     "fd3d_batch_destroy": ([_vp], None),
     "fd3d_set_kernel": ([_vp, ctypes.POINTER(fd3d_kernel)], _i),
     "fd3d_get_kernel": ([_vp, ctypes.POINTER(fd3d_kernel)], _i),
@@ -229,6 +234,22 @@ def fd3d_batch_forward(batch, srcs, nrec, rec_ptrs, traces, flags, use_graph, st
     rarr = (_dp * n)(*[ctypes.cast(p, _dp) if p else None for p in rec_ptrs])
     tarr = (_vp * n)(*traces)
     _check(_lib.fd3d_batch_forward(batch, sarr, narr, rarr, tarr, int(flags), int(bool(use_graph)), stream))
+
+
+def fd3d_batch_grad_workspace_bytes(batch, ckpt_every: int) -> int:
+    out = _sz(0)
+    _check(_lib.fd3d_batch_grad_workspace_bytes(batch, int(ckpt_every), ctypes.byref(out)))
+    return int(out.value)
+
+
+def fd3d_batch_gradient(batch, srcs, nrec, rec_ptrs, d_obs, traces, misfit, g_lam, g_mu, g_rho, gws, gws_bytes,
+                        ckpt_every, flags, bws, bws_bytes, stream) -> None:
+    n = len(nrec)
+    vp = lambda xs: (_vp * n)(*xs)
+    _check(_lib.fd3d_batch_gradient(batch, (fd3d_source * n)(*srcs), (_i * n)(*nrec),
+                                    (_dp * n)(*[ctypes.cast(p, _dp) for p in rec_ptrs]), vp(d_obs), vp(traces),
+                                    vp(misfit), vp(g_lam), vp(g_mu), vp(g_rho), vp(gws), (_sz * n)(*gws_bytes),
+                                    int(ckpt_every), int(flags), bws, bws_bytes, stream))
 
 
 def fd3d_batch_destroy(batch) -> None:

@@ -56,6 +56,47 @@ class BatchSimulator:
         self._keep = keep
         return out
 
+    def gradient(self, shots: List[Dict], d_obs: List[torch.Tensor], g_lam, g_mu, g_rho, ckpt_every: int = 50,
+                 gws: List[torch.Tensor] = None, keep_state: bool = False):
+        """Batched L2-misfit gradient.  g_* are one tensor (shared by all shots) or a list
+        of per-shot tensors, accumulated.  Returns (traces list, misfit tensor [nshot])."""
+        S = len(self.sims)
+        if len(shots) != S or len(d_obs) != S:
+            raise ValueError("one shot description and one d_obs per simulator")
+        as_list = lambda g: list(g) if isinstance(g, (list, tuple)) else [g] * S
+        gl, gm, gr = as_list(g_lam), as_list(g_mu), as_list(g_rho)
+        if gws is None:
+            gws = [sim.grad_workspace(ckpt_every) for sim in self.sims]
+        bbytes = _abi.fd3d_batch_grad_workspace_bytes(self._b, ckpt_every)
+        if getattr(self, "_bws", None) is None or self._bws.numel() < bbytes:
+            self._bws = torch.empty(bbytes, dtype=torch.uint8, device=self.sims[0].device)
+        srcs, nrec, rptr, keep, traces, obs = [], [], [], [], [], []
+        for sim, sh, ob, g1, g2, g3 in zip(self.sims, shots, d_obs, gl, gm, gr):
+            w = sim._wavelet(sh.get("wavelet"))
+            srcs.append(make_source(sh["src_pos"], sh.get("moment", (0.0,) * 6), sh.get("force", (0.0,) * 3), w)
+                        if sh.get("src_pos") is not None else _abi.fd3d_source())
+            rp, nr = Simulator._rec(sh.get("rec_pos"))
+            o = ob.to(device=sim.device, dtype=sim.dtype).contiguous()
+            if tuple(o.shape) != (nr, 3, sim.nt):
+                raise ValueError("d_obs must be [nrec, 3, nt]")
+            for g in (g1, g2, g3):
+                if g.dtype != sim.dtype or not g.is_contiguous() or tuple(g.shape) != tuple(sim.lam.shape):
+                    raise ValueError("gradient buffers must be contiguous [nz, ny, nx] tensors of the context dtype")
+            nrec.append(nr)
+            rptr.append(rp.ctypes.data)
+            keep.append((rp, w, o))
+            obs.append(o)
+            traces.append(torch.empty((nr, 3, sim.nt), dtype=sim.dtype, device=sim.device))
+        misfit = torch.zeros(S, dtype=self.sims[0].dtype, device=self.sims[0].device)
+        flags = _abi.FD3D_KEEP_STATE if keep_state else 0
+        _abi.fd3d_batch_gradient(self._b, srcs, nrec, rptr, [o.data_ptr() for o in obs],
+                                 [t.data_ptr() for t in traces], [misfit[s:s + 1].data_ptr() for s in range(S)],
+                                 [g.data_ptr() for g in gl], [g.data_ptr() for g in gm], [g.data_ptr() for g in gr],
+                                 [g.data_ptr() for g in gws], [g.numel() for g in gws], ckpt_every, flags,
+                                 self._bws.data_ptr(), self._bws.numel(), _stream())
+        self._keep = (keep, gws)
+        return traces, misfit
+
     def close(self) -> None:
         if getattr(self, "_b", 0):
             torch.cuda.current_stream().synchronize()

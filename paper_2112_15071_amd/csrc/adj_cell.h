@@ -69,12 +69,8 @@ __device__ __forceinline__ T xval(const Grid<T> &G, const AdjGrid<T> &A, int c, 
 
 // (a10) adjoint of the stress pass, at the samples of node (i,j,k).
 template <typename T>
-__global__ void __launch_bounds__(256) adj_stress_cell(Grid<T> G, AdjGrid<T> A)
+__device__ __forceinline__ void adj_stress_body(const Grid<T> &G, const AdjGrid<T> &A, int i, int j, int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= G.nx || j >= G.ny) return;
     const long p = i + G.sy * j + G.sz * k;
     const T rdx = G.rdx, dt = G.dt;
 
@@ -144,12 +140,9 @@ __device__ __forceinline__ T sv(const Grid<T> &G, const AdjGrid<T> &A, int c, in
 
 // (a12) adjoint of the velocity pass, at the samples of node (i,j,k).
 template <typename T>
-__global__ void __launch_bounds__(256) adj_vel_cell(Grid<T> G, AdjGrid<T> A, Inject<T> src, int n)
+__device__ __forceinline__ void adj_vel_body(const Grid<T> &G, const AdjGrid<T> &A, const Inject<T> &src, int n, int i,
+                                             int j, int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= G.nx || j >= G.ny) return;
     const long p = i + G.sy * j + G.sz * k;
     const T rdx = G.rdx, dt = G.dt;
     const T s = src.on ? src.wavelet[n] : T(0);
@@ -213,8 +206,38 @@ __global__ void __launch_bounds__(256) adj_vel_cell(Grid<T> G, AdjGrid<T> A, Inj
     }
 }
 
+// Single-grid launches of the two adjoint passes (64 x 4 threads per block, one z plane).
+template <typename T> __global__ void __launch_bounds__(256) adj_stress_cell(Grid<T> G, AdjGrid<T> A)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= G.nx || j >= G.ny) return;
+    adj_stress_body(G, A, i, j, (int)blockIdx.z);
+}
+
+template <typename T> __global__ void __launch_bounds__(256) adj_vel_cell(Grid<T> G, AdjGrid<T> A, Inject<T> src, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= G.nx || j >= G.ny) return;
+    adj_vel_body(G, A, src, n, i, j, (int)blockIdx.z);
+}
+
 // (a11) adjoint of the sampling for the receivers of one colour (no two of them share a
 // tap): A_v[tap] += w r[r][c][n].
+template <typename T>
+__device__ __forceinline__ void inject_one(T *__restrict__ ax, T *__restrict__ ay, T *__restrict__ az,
+                                           const RecTap<T> *__restrict__ taps, int r, int c,
+                                           const T *__restrict__ res, int nt, int n)
+{
+    T *f = c == 0 ? ax : (c == 1 ? ay : az);
+    const RecTap<T> &t = taps[r * 3 + c];
+    const T v = res[((long)r * 3 + c) * nt + n];
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+        if (t.idx[m] >= 0) f[t.idx[m]] += t.w[m] * v;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) inject_residual(T *__restrict__ ax, T *__restrict__ ay, T *__restrict__ az,
                                                        const RecTap<T> *__restrict__ taps, const int *__restrict__ list,
@@ -222,13 +245,7 @@ __global__ void __launch_bounds__(256) inject_residual(T *__restrict__ ax, T *__
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= 3 * count) return;
-    const int r = list[q / 3], c = q % 3;
-    T *f = c == 0 ? ax : (c == 1 ? ay : az);
-    const RecTap<T> &t = taps[r * 3 + c];
-    const T v = res[((long)r * 3 + c) * nt + n];
-#pragma unroll
-    for (int m = 0; m < 8; ++m)
-        if (t.idx[m] >= 0) f[t.idx[m]] += t.w[m] * v;
+    inject_one(ax, ay, az, taps, list[q / 3], q % 3, res, nt, n);
 }
 
 // (a13) chain rule from the staggered-point gradients to the node arrays (gathers, no
@@ -278,6 +295,88 @@ __global__ void __launch_bounds__(256) scale_velocity(Grid<T> G, const T *__rest
     if (i >= G.nx || j >= G.ny) return;
     const long p = i + G.sy * j + G.sz * k;
     out[p] = damp(G, c, i, j, k) * a[p];
+}
+
+// ---------------------------------------------------------------------------------
+// Many shots per launch.  A shot's cells are covered by nbx x nby x nz blocks of 64 x 4
+// threads; the blocks of all shots form one flat list (shot-major).  Receiver injection
+// of colour c covers the colour-c receivers of every shot (shots never share arrays).
+constexpr int kMaxBatchColors = 4;
+
+template <typename T> struct ShotAdj {
+    Grid<T> G;
+    AdjGrid<T> A;
+    Inject<T> src;
+    int nbx, nby, base;
+    const RecTap<T> *taps;
+    const int *colors;
+    const T *res;
+    int coff[kMaxBatchColors + 1];  // colour c: colors[coff[c] .. coff[c+1])
+    int rbase[kMaxBatchColors];     // first work item of this shot in colour c's flat list
+};
+
+template <typename T>
+__device__ __forceinline__ int find_adj(const ShotAdj<T> *__restrict__ d, int nshot, int w)
+{
+    int s = 0;
+    while (s + 1 < nshot && d[s + 1].base <= w) ++s;
+    return s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) adj_stress_multi(const ShotAdj<T> *__restrict__ d, int nshot)
+{
+    const int s = find_adj(d, nshot, (int)blockIdx.x);
+    const ShotAdj<T> &sh = d[s];
+    const int b = (int)blockIdx.x - sh.base;
+    const int bz = b / (sh.nbx * sh.nby), r = b % (sh.nbx * sh.nby);
+    const int i = (r % sh.nbx) * 64 + (int)(threadIdx.x & 63), j = (r / sh.nbx) * 4 + (int)(threadIdx.x >> 6);
+    const Grid<T> G = sh.G;
+    if (i >= G.nx || j >= G.ny) return;
+    const AdjGrid<T> A = sh.A;
+    adj_stress_body(G, A, i, j, bz);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) adj_vel_multi(const ShotAdj<T> *__restrict__ d, int nshot, int n)
+{
+    const int s = find_adj(d, nshot, (int)blockIdx.x);
+    const ShotAdj<T> &sh = d[s];
+    const int b = (int)blockIdx.x - sh.base;
+    const int bz = b / (sh.nbx * sh.nby), r = b % (sh.nbx * sh.nby);
+    const int i = (r % sh.nbx) * 64 + (int)(threadIdx.x & 63), j = (r / sh.nbx) * 4 + (int)(threadIdx.x >> 6);
+    const Grid<T> G = sh.G;
+    if (i >= G.nx || j >= G.ny) return;
+    const AdjGrid<T> A = sh.A;
+    adj_vel_body(G, A, sh.src, n, i, j, bz);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) inject_residual_multi(const ShotAdj<T> *__restrict__ d, int nshot, int color,
+                                                             int total, int nt, int n)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    int s = 0;
+    while (s + 1 < nshot && d[s + 1].rbase[color] <= q) ++s;
+    const ShotAdj<T> &sh = d[s];
+    const int l = q - sh.rbase[color];
+    const int r = sh.colors[sh.coff[color] + l / 3];
+    inject_one(sh.A.a[VX], sh.A.a[VY], sh.A.a[VZ], sh.taps, r, l % 3, sh.res, nt, n);
+}
+
+// Copies of many equally long arrays (checkpoint save / restore of every shot).
+template <typename T> struct CopyDesc {
+    const T *src;
+    T *dst;
+    long n;
+};
+
+template <typename T> __global__ void __launch_bounds__(256) copy_multi(const CopyDesc<T> *__restrict__ d)
+{
+    const CopyDesc<T> &c = d[blockIdx.y];
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < c.n; q += (long)gridDim.x * blockDim.x)
+        c.dst[q] = c.src[q];
 }
 
 } // namespace fd3d

@@ -665,6 +665,7 @@ struct fd3d_batch {
     hipEvent_t staged;
     bool staged_pending;
     hipStream_t cap;
+    std::vector<unsigned char> grad_host;  // batched-gradient descriptors, kept for the async upload
     hipGraph_t graph;
     hipGraphExec_t gexec;
     bool graph_valid;
@@ -682,31 +683,30 @@ size_t batch_desc_bytes(int nshot, int tsize)
 }
 
 template <typename T, int TX, int TY, bool FS>
-int launch_multi(fd3d_batch *b, int n, int pass, hipStream_t st)
+int launch_multi(fd3d_batch *b, const ShotFwd<T> *d, int n, int pass, hipStream_t st)
 {
-    const ShotFwd<T> *d = (const ShotFwd<T> *)(b->ws + b->off_fwd);
     if (pass == 0) vel_tile_multi<T, TX, TY, FS><<<b->wgs, TX * TY, 0, st>>>(d, b->nshot, b->total_tiles, n);
     else stress_tile_multi<T, TX, TY, FS><<<b->wgs, TX * TY, 0, st>>>(d, b->nshot, b->total_tiles, n);
     return FD3D_OK;
 }
 
-template <typename T, bool FS> int multi_pass(fd3d_batch *b, int n, int pass, hipStream_t st)
+template <typename T, bool FS> int multi_pass(fd3d_batch *b, const ShotFwd<T> *d, int n, int pass, hipStream_t st)
 {
     const int key = b->tile_x * 100 + b->tile_y;
     if (sizeof(T) == 8) {
         switch (key) {
-        case 6404: return launch_multi<T, 64, 4, FS>(b, n, pass, st);
-        case 12804: return launch_multi<T, 128, 4, FS>(b, n, pass, st);
-        default: return launch_multi<T, 64, 8, FS>(b, n, pass, st);
+        case 6404: return launch_multi<T, 64, 4, FS>(b, d, n, pass, st);
+        case 12804: return launch_multi<T, 128, 4, FS>(b, d, n, pass, st);
+        default: return launch_multi<T, 64, 8, FS>(b, d, n, pass, st);
         }
     }
     switch (key) {
-    case 6404: return launch_multi<T, 64, 4, FS>(b, n, pass, st);
-    case 6416: return launch_multi<T, 64, 16, FS>(b, n, pass, st);
-    case 12804: return launch_multi<T, 128, 4, FS>(b, n, pass, st);
-    case 12808: return launch_multi<T, 128, 8, FS>(b, n, pass, st);
-    case 25604: return launch_multi<T, 256, 4, FS>(b, n, pass, st);
-    default: return launch_multi<T, 64, 8, FS>(b, n, pass, st);
+    case 6404: return launch_multi<T, 64, 4, FS>(b, d, n, pass, st);
+    case 6416: return launch_multi<T, 64, 16, FS>(b, d, n, pass, st);
+    case 12804: return launch_multi<T, 128, 4, FS>(b, d, n, pass, st);
+    case 12808: return launch_multi<T, 128, 8, FS>(b, d, n, pass, st);
+    case 25604: return launch_multi<T, 256, 4, FS>(b, d, n, pass, st);
+    default: return launch_multi<T, 64, 8, FS>(b, d, n, pass, st);
     }
 }
 
@@ -744,13 +744,14 @@ template <typename T> int batch_sequence(fd3d_batch *b, int flags, hipStream_t s
     if (!(flags & FD3D_KEEP_STATE))
         for (fd3d_ctx *c : b->ctx) zero_fields<T>(c, st);
     const ShotRec<T> *r = (const ShotRec<T> *)(b->ws + b->off_rec);
+    const ShotFwd<T> *d = (const ShotFwd<T> *)(b->ws + b->off_fwd);
     for (int n = 0; n < b->nt; ++n) {
-        if (b->fs) multi_pass<T, true>(b, n, 0, st);
-        else multi_pass<T, false>(b, n, 0, st);
+        if (b->fs) multi_pass<T, true>(b, d, n, 0, st);
+        else multi_pass<T, false>(b, d, n, 0, st);
         if (b->total_rec > 0)
             record_multi<T><<<(b->total_rec + 255) / 256, 256, 0, st>>>(r, b->nshot, b->total_rec, b->nt, n);
-        if (b->fs) multi_pass<T, true>(b, n, 1, st);
-        else multi_pass<T, false>(b, n, 1, st);
+        if (b->fs) multi_pass<T, true>(b, d, n, 1, st);
+        else multi_pass<T, false>(b, d, n, 1, st);
     }
     HIP_TRY(hipGetLastError());
     return FD3D_OK;
@@ -833,6 +834,222 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
         b->graph_key = key;
     }
     HIP_TRY(hipGraphLaunch(b->gexec, st));
+    return FD3D_OK;
+}
+
+int check_gws(const fd3d_ctx *ctx, void *gws, size_t gws_bytes, int k)
+{
+    if (ctx->opts.free_surface) return fail(FD3D_EINVAL, "the gradient supports damped boundaries only (no free surface)");
+    if (ctx->nt < 1) return fail(FD3D_EINVAL, "gradient needs nt >= 1");
+    if (k < 1 || k > ctx->nt) return fail(FD3D_EINVAL, "ckpt_every must be in [1, nt]");
+    if (!gws || ((uintptr_t)gws % kAlign)) return fail(FD3D_EINVAL, "gradient workspace must be 256-byte aligned");
+    const size_t need = make_grad_layout(ctx, k).total;
+    if (gws_bytes < need) return fail(FD3D_EWS, "gradient workspace too small: need " + std::to_string(need) + " bytes");
+    return FD3D_OK;
+}
+
+// ---- batched gradient ----------------------------------------------------------
+// Batch workspace of fd3d_batch_gradient: per segment slot m the forward descriptors
+// (with the slot's store pointers) and the adjoint descriptors (with the slot's stored
+// fields); per checkpoint the save and restore copy lists.
+struct BatchGradLayout {
+    size_t fwd0, fwd_slot, adj_slot, save_copy, rest_copy, total;
+    size_t fwd_bytes, adj_bytes, copy_bytes;  // one array of nshot (x9) descriptors
+    int k, nseg;
+};
+
+template <typename T> BatchGradLayout make_batch_grad_layout(const fd3d_batch *b, int k)
+{
+    BatchGradLayout L{};
+    L.k = k;
+    L.nseg = (b->nt + k - 1) / k;
+    L.fwd_bytes = round_up((size_t)b->nshot * sizeof(ShotFwd<T>), kAlign);
+    L.adj_bytes = round_up((size_t)b->nshot * sizeof(ShotAdj<T>), kAlign);
+    L.copy_bytes = round_up((size_t)b->nshot * 9 * sizeof(CopyDesc<T>), kAlign);
+    size_t off = 0;
+    L.fwd0 = off;
+    off += L.fwd_bytes;
+    L.fwd_slot = off;
+    off += (size_t)k * L.fwd_bytes;
+    L.adj_slot = off;
+    off += (size_t)k * L.adj_bytes;
+    L.save_copy = off;
+    off += (size_t)L.nseg * L.copy_bytes;
+    L.rest_copy = off;
+    off += (size_t)L.nseg * L.copy_bytes;
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, const double *const *rec_pos,
+                        const void *const *d_obs, void *const *traces, void *const *misfit, void *const *g_lam,
+                        void *const *g_mu, void *const *g_rho, void *const *gws, const size_t *gws_bytes, int k,
+                        int flags, char *bws, size_t bws_bytes, hipStream_t st)
+{
+    const int S = b->nshot;
+    const BatchGradLayout BL = make_batch_grad_layout<T>(b, k);
+    if (!bws || ((uintptr_t)bws % kAlign)) return fail(FD3D_EINVAL, "batch gradient workspace must be 256-byte aligned");
+    if (bws_bytes < BL.total) return fail(FD3D_EWS, "batch gradient workspace too small: need " + std::to_string(BL.total));
+    std::vector<GradLayout> GL(S);
+    std::vector<ShotFwd<T>> fw(S);
+    std::vector<ShotRec<T>> rr(S);
+    std::vector<ShotAdj<T>> ad(S);
+    int tiles = 0, recs = 0, blocks = 0, ncol = 0;
+    int cbase[kMaxBatchColors] = {0, 0, 0, 0};
+    for (int s = 0; s < S; ++s) {
+        fd3d_ctx *c = b->ctx[s];
+        const std::string tag = "shot " + std::to_string(s) + ": ";
+        if (!gws || !gws[s]) return fail(FD3D_EINVAL, tag + "gradient workspace is NULL");
+        int rc = check_gws(c, gws[s], gws_bytes[s], k);
+        if (rc) return fail(rc, tag + g_err);
+        const int nr = nrec ? nrec[s] : 0;
+        if (nr < 1 || nr > c->opts.max_receivers) return fail(FD3D_EINVAL, tag + "needs 1..max_receivers receivers");
+        if (!rec_pos || !rec_pos[s] || !traces || !traces[s] || !d_obs || !d_obs[s] || !g_lam || !g_lam[s] || !g_mu ||
+            !g_mu[s] || !g_rho || !g_rho[s])
+            return fail(FD3D_EINVAL, tag + "NULL pointer");
+        rc = build_source<T>(c, srcs ? &srcs[s] : nullptr, fw[s].src);
+        if (rc) return fail(rc, tag + g_err);
+        rc = stage_receivers<T>(c, nr, rec_pos[s], st);
+        if (rc) return fail(rc, tag + g_err);
+        const int cols = (int)c->color_off.size() - 1;
+        if (cols > kMaxBatchColors) return fail(FD3D_EINVAL, tag + "receivers need more than 4 tap-disjoint colours");
+        ncol = std::max(ncol, cols);
+        GL[s] = make_grad_layout(c, k);
+        fw[s].G = make_grid<T>(c);
+        TileMap tm;
+        tm.ntx = (c->n[0] + b->tile_x - 1) / b->tile_x;
+        tm.nty = (c->n[1] + b->tile_y - 1) / b->tile_y;
+        tm.zc = c->zchunk;
+        tm.nzc = (c->n[2] + c->zchunk - 1) / c->zchunk;
+        fw[s].tm = tm;
+        fw[s].base = tiles;
+        fw[s].pad = 0;
+        tiles += tm.ntx * tm.nty * tm.nzc;
+        for (int q = 0; q < 3; ++q) rr[s].v[q] = fw[s].G.f[VX + q];
+        rr[s].taps = (const RecTap<T> *)(c->ws + c->L.rec);
+        rr[s].traces = (T *)traces[s];
+        rr[s].nrec = nr;
+        rr[s].base = recs;
+        recs += 3 * nr;
+        ShotAdj<T> &a = ad[s];
+        a.G = fw[s].G;
+        a.A = make_adj<T>((char *)gws[s], GL[s]);
+        a.src = fw[s].src;
+        a.nbx = (c->n[0] + 63) / 64;
+        a.nby = (c->n[1] + 3) / 4;
+        a.base = blocks;
+        blocks += a.nbx * a.nby * c->n[2];
+        a.taps = rr[s].taps;
+        a.colors = (const int *)(c->ws + c->L.colors);
+        a.res = (const T *)((char *)gws[s] + GL[s].res);
+        for (int q = 0; q <= kMaxBatchColors; ++q) a.coff[q] = c->color_off[std::min(q, cols)];
+        for (int q = 0; q < kMaxBatchColors; ++q) {
+            a.rbase[q] = cbase[q];
+            cbase[q] += 3 * (a.coff[q + 1] - a.coff[q]);
+        }
+    }
+    // host images of every descriptor array
+    if (b->staged_pending) {
+        HIP_TRY(hipEventSynchronize(b->staged));
+        b->staged_pending = false;
+    }
+    b->grad_host.assign(BL.total, 0);
+    unsigned char *h = b->grad_host.data();
+    std::memcpy(h + BL.fwd0, fw.data(), S * sizeof(ShotFwd<T>));
+    for (int m = 0; m < k; ++m) {
+        std::vector<ShotFwd<T>> f2 = fw;
+        std::vector<ShotAdj<T>> a2 = ad;
+        for (int s = 0; s < S; ++s) {
+            char *slot = (char *)gws[s] + GL[s].seg + (size_t)m * 9 * GL[s].stride;
+            for (int f = 0; f < NFIELD; ++f) f2[s].G.save[f] = (T *)(slot + f * GL[s].stride);
+            for (int q = 0; q < 3; ++q) a2[s].A.vst[q] = (const T *)(slot + q * GL[s].stride);
+            for (int q = 0; q < 6; ++q) a2[s].A.sst[q] = (const T *)(slot + (3 + q) * GL[s].stride);
+        }
+        std::memcpy(h + BL.fwd_slot + m * BL.fwd_bytes, f2.data(), S * sizeof(ShotFwd<T>));
+        std::memcpy(h + BL.adj_slot + m * BL.adj_bytes, a2.data(), S * sizeof(ShotAdj<T>));
+    }
+    for (int cidx = 0; cidx < BL.nseg; ++cidx) {
+        std::vector<CopyDesc<T>> sv(S * 9), rs(S * 9);
+        for (int s = 0; s < S; ++s) {
+            const char *ck = (const char *)gws[s] + GL[s].ckpt + (size_t)cidx * 9 * GL[s].stride;
+            const long n = (long)(b->ctx[s]->L.field_bytes / sizeof(T));
+            for (int f = 0; f < NFIELD; ++f) {
+                sv[s * 9 + f] = CopyDesc<T>{fw[s].G.f[f], (T *)(ck + f * GL[s].stride), n};
+                rs[s * 9 + f] = CopyDesc<T>{(const T *)(ck + f * GL[s].stride), fw[s].G.f[f], n};
+            }
+        }
+        std::memcpy(h + BL.save_copy + cidx * BL.copy_bytes, sv.data(), sv.size() * sizeof(CopyDesc<T>));
+        std::memcpy(h + BL.rest_copy + cidx * BL.copy_bytes, rs.data(), rs.size() * sizeof(CopyDesc<T>));
+    }
+    b->rec_host.assign((const unsigned char *)rr.data(), (const unsigned char *)(rr.data() + S));
+    HIP_TRY(hipMemcpyAsync(bws, h, BL.total, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b->ws + b->off_rec, b->rec_host.data(), b->rec_host.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(b->staged, st));
+    b->staged_pending = true;
+
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int occ = b->fs ? multi_occupancy<T, true>(b) : multi_occupancy<T, false>(b);
+    int wgs = b->wgs_req > 0 ? b->wgs_req : cus * occ;
+    wgs = std::max(8, (std::min(wgs, ((tiles + 7) / 8) * 8) + 7) / 8 * 8);
+    b->total_tiles = tiles;
+    b->total_rec = recs;
+    b->wgs = wgs;
+
+    // forward with checkpoints
+    const ShotFwd<T> *fwd0 = (const ShotFwd<T> *)(bws + BL.fwd0);
+    const ShotRec<T> *rdesc = (const ShotRec<T> *)(b->ws + b->off_rec);
+    const dim3 cgrid(256, 9 * S);
+    if (!(flags & FD3D_KEEP_STATE))
+        for (fd3d_ctx *c : b->ctx) zero_fields<T>(c, st);
+    auto fpass = [&](const ShotFwd<T> *d, int n, int pass) { multi_pass<T, false>(b, d, n, pass, st); };
+    for (int n = 0; n < b->nt; ++n) {
+        if (n % k == 0)
+            copy_multi<T><<<cgrid, 256, 0, st>>>((const CopyDesc<T> *)(bws + BL.save_copy + (n / k) * BL.copy_bytes));
+        fpass(fwd0, n, 0);
+        record_multi<T><<<(recs + 255) / 256, 256, 0, st>>>(rdesc, S, recs, b->nt, n);
+        fpass(fwd0, n, 1);
+    }
+    // residuals and misfits, zeroed adjoint state and accumulators
+    for (int s = 0; s < S; ++s) {
+        fd3d_ctx *c = b->ctx[s];
+        const long nn = (long)nrec[s] * 3 * b->nt;
+        double *part = (double *)(c->ws + c->L.part);
+        T *res = (T *)((char *)gws[s] + GL[s].res);
+        residual_misfit<T><<<kReduceBlocks, 256, 0, st>>>((const T *)traces[s], (const T *)d_obs[s], res, nn, part);
+        misfit_final<T><<<1, 64, 0, st>>>(part, kReduceBlocks,
+                                          misfit && misfit[s] ? (T *)misfit[s] : (T *)((char *)gws[s] + GL[s].misfit));
+        fill_zero<T><<<2048, 256, 0, st>>>((T *)((char *)gws[s] + GL[s].adj), (long)(17 * GL[s].stride / sizeof(T)));
+    }
+    // reverse sweep over the segments
+    for (int sg = BL.nseg - 1; sg >= 0; --sg) {
+        const int n0 = sg * k, n1 = std::min(n0 + k, b->nt);
+        copy_multi<T><<<cgrid, 256, 0, st>>>((const CopyDesc<T> *)(bws + BL.rest_copy + sg * BL.copy_bytes));
+        for (int n = n0; n < n1; ++n) {
+            const ShotFwd<T> *d = (const ShotFwd<T> *)(bws + BL.fwd_slot + (n - n0) * BL.fwd_bytes);
+            fpass(d, n, 0);
+            fpass(d, n, 1);
+        }
+        for (int n = n1 - 1; n >= n0; --n) {
+            const ShotAdj<T> *d = (const ShotAdj<T> *)(bws + BL.adj_slot + (n - n0) * BL.adj_bytes);
+            adj_stress_multi<T><<<blocks, 256, 0, st>>>(d, S);
+            for (int q = 0; q < ncol; ++q)
+                if (cbase[q] > 0) inject_residual_multi<T><<<(cbase[q] + 255) / 256, 256, 0, st>>>(d, S, q, cbase[q], b->nt, n);
+            adj_vel_multi<T><<<blocks, 256, 0, st>>>(d, S, n);
+        }
+    }
+    // chain rule per shot, in shot order (shots may share the output arrays)
+    for (int s = 0; s < S; ++s) {
+        fd3d_ctx *c = b->ctx[s];
+        const dim3 blk(64, 4, 1), grd((c->n[0] + 63) / 64, (c->n[1] + 3) / 4, c->n[2]);
+        grad_finalize<T><<<grd, blk, 0, st>>>(fw[s].G, ad[s].A, (T *)g_lam[s], (T *)g_mu[s], (T *)g_rho[s]);
+        c->grad_ws = (const char *)gws[s];
+        c->grad_k = k;
+        c->grad_ready = 1;
+    }
+    HIP_TRY(hipGetLastError());
     return FD3D_OK;
 }
 
@@ -967,17 +1184,6 @@ int fd3d_grad_workspace_bytes(const fd3d_ctx *ctx, int ckpt_every, size_t *bytes
     if (ctx->nt < 1) return fail(FD3D_EINVAL, "gradient needs nt >= 1");
     if (ckpt_every < 1 || ckpt_every > ctx->nt) return fail(FD3D_EINVAL, "ckpt_every must be in [1, nt]");
     *bytes = make_grad_layout(ctx, ckpt_every).total;
-    return FD3D_OK;
-}
-
-static int check_gws(const fd3d_ctx *ctx, void *gws, size_t gws_bytes, int k)
-{
-    if (ctx->opts.free_surface) return fail(FD3D_EINVAL, "the gradient supports damped boundaries only (no free surface)");
-    if (ctx->nt < 1) return fail(FD3D_EINVAL, "gradient needs nt >= 1");
-    if (k < 1 || k > ctx->nt) return fail(FD3D_EINVAL, "ckpt_every must be in [1, nt]");
-    if (!gws || ((uintptr_t)gws % kAlign)) return fail(FD3D_EINVAL, "gradient workspace must be 256-byte aligned");
-    const size_t need = make_grad_layout(ctx, k).total;
-    if (gws_bytes < need) return fail(FD3D_EWS, "gradient workspace too small: need " + std::to_string(need) + " bytes");
     return FD3D_OK;
 }
 
@@ -1184,6 +1390,31 @@ int fd3d_batch_forward(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
     hipStream_t st = (hipStream_t)hip_stream;
     return b->tsize == 8 ? batch_forward_impl<double>(b, srcs, nrec, rec_pos, traces, flags, use_graph, st)
                          : batch_forward_impl<float>(b, srcs, nrec, rec_pos, traces, flags, use_graph, st);
+}
+
+int fd3d_batch_grad_workspace_bytes(const fd3d_batch *b, int ckpt_every, size_t *bytes)
+{
+    if (!b || !bytes) return fail(FD3D_EINVAL, "batch/bytes is NULL");
+    if (ckpt_every < 1 || ckpt_every > b->nt) return fail(FD3D_EINVAL, "ckpt_every must be in [1, nt]");
+    *bytes = b->tsize == 8 ? make_batch_grad_layout<double>(b, ckpt_every).total
+                           : make_batch_grad_layout<float>(b, ckpt_every).total;
+    return FD3D_OK;
+}
+
+int fd3d_batch_gradient(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, const double *const *rec_pos,
+                        const void *const *d_obs, void *const *traces, void *const *misfit, void *const *g_lam,
+                        void *const *g_mu, void *const *g_rho, void *const *gws, const size_t *gws_bytes,
+                        int ckpt_every, int flags, void *bws, size_t bws_bytes, void *hip_stream)
+{
+    if (!b || !gws_bytes) return fail(FD3D_EINVAL, "batch/gws_bytes is NULL");
+    if (b->fs) return fail(FD3D_EINVAL, "the gradient supports damped boundaries only (no free surface)");
+    if (ckpt_every < 1 || ckpt_every > b->nt) return fail(FD3D_EINVAL, "ckpt_every must be in [1, nt]");
+    hipStream_t st = (hipStream_t)hip_stream;
+    return b->tsize == 8
+               ? batch_gradient_impl<double>(b, srcs, nrec, rec_pos, d_obs, traces, misfit, g_lam, g_mu, g_rho, gws,
+                                             gws_bytes, ckpt_every, flags, (char *)bws, bws_bytes, st)
+               : batch_gradient_impl<float>(b, srcs, nrec, rec_pos, d_obs, traces, misfit, g_lam, g_mu, g_rho, gws,
+                                            gws_bytes, ckpt_every, flags, (char *)bws, bws_bytes, st);
 }
 
 void fd3d_batch_destroy(fd3d_batch *b)

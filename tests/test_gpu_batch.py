@@ -126,3 +126,86 @@ def test_full_size_uneven_batch_truncated():
     batch.close()
     for s in sims:
         s.close()
+
+
+GSHAPES = [(32, 32, 32), (36, 30, 28), (40, 34, 30)]
+
+
+def grad_shots(seed, nt):
+    shots = []
+    for s, shape in enumerate(GSHAPES):
+        rng = np.random.Generator(np.random.PCG64(seed + s))
+        lam, mu, rho = W.layered_perturbed(shape, 10.0, seed + 20 + s)
+        nx, ny, nz = shape
+        pos = (float(rng.uniform(8, nx - 9)), float(rng.uniform(8, ny - 9)), float(rng.uniform(6, nz - 7)))
+        rec = np.stack([rng.uniform(4, nx - 5, 6), rng.uniform(4, ny - 5, 6), np.full(6, 6.0)], axis=1)
+        shots.append(W.Shot(f"g{s}", shape, 10.0, DT, nt, lam, mu, rho, pos, W.explosion(1e15),
+                            tuple(rng.standard_normal(3) * 1e9), W.ricker(40.0, nt, DT), rec, sponge=(6,) * 6))
+    return shots
+
+
+def test_batched_gradient_equals_per_shot():
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    nt, k = 60, 7
+    shots = grad_shots(900, nt)
+    rng = np.random.default_rng(5)
+    d_obs = [torch.as_tensor(rng.standard_normal((len(s.rec_pos), 3, nt)) * 1e-6, dtype=torch.float32) for s in shots]
+    tile = (64, 8)
+    ref = []
+    for s, obs in zip(shots, d_obs):
+        sim = sims_for([s])[0]
+        sim.set_kernel("tile", tile[1], sim.kernel()["zchunk"], tile[0])
+        g = [torch.zeros(s.lam.shape, dtype=torch.float32, device="cuda") for _ in range(3)]
+        tr, J = sim.gradient(sim.grad_workspace(k), obs, *g, **desc(s))
+        ref.append((tr.cpu(), J.cpu(), [x.cpu() for x in g]))
+        sim.close()
+    sims = sims_for(shots)
+    batch = BatchSimulator(sims)
+    batch.set_kernel(*tile)
+    gl = [torch.zeros(s.lam.shape, dtype=torch.float32, device="cuda") for s in shots]
+    gm = [torch.zeros_like(x) for x in gl]
+    gr = [torch.zeros_like(x) for x in gl]
+    print("[batch-grad] 3 shots", flush=True)
+    trs, J = batch.gradient([desc(s) for s in shots], d_obs, gl, gm, gr, ckpt_every=k)
+    torch.cuda.synchronize()
+    for q in range(3):
+        assert torch.equal(trs[q].cpu(), ref[q][0]), q
+        assert torch.equal(J[q:q + 1].cpu(), ref[q][1]), q
+        for a, b in zip((gl[q], gm[q], gr[q]), ref[q][2]):
+            assert torch.equal(a.cpu(), b), q
+    batch.close()
+    for s in sims:
+        s.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.float64, 1e-12)])
+def test_batched_gradient_dot_product(dtype, tol):
+    """Per shot, sources off, start from a random state x0, d_obs = 0 (so the residual is
+    d = P x0): <d, d> = <x0, P^T d> with P^T d the adjoint of the initial state."""
+    from paper_2112_15071_amd.batch import BatchSimulator
+    from helpers import random_state
+
+    nt, k = 40, 9
+    shots = grad_shots(950, nt)
+    rng = np.random.default_rng(6)
+    sims = sims_for(shots, dtype)
+    x0 = []
+    for sim, s in zip(sims, shots):
+        sim.set_state(torch.as_tensor(random_state(s.shape, rng), dtype=dtype))
+        x0.append(sim.state().double().cpu().numpy())
+    batch = BatchSimulator(sims)
+    d_obs = [torch.zeros((len(s.rec_pos), 3, nt), dtype=dtype) for s in shots]
+    g = [torch.zeros(s.lam.shape, dtype=dtype, device="cuda") for s in shots]
+    gws = [sim.grad_workspace(k) for sim in sims]
+    nosrc = [dict(src_pos=None, rec_pos=s.rec_pos) for s in shots]
+    trs, J = batch.gradient(nosrc, d_obs, g, [torch.zeros_like(x) for x in g], [torch.zeros_like(x) for x in g],
+                            ckpt_every=k, gws=gws, keep_state=True)
+    for q, sim in enumerate(sims):
+        d = trs[q].double().cpu().numpy()
+        adj = sim.adjoint_state(gws[q]).double().cpu().numpy()
+        lhs, rhs = float(np.sum(d * d)), float(np.sum(x0[q] * adj))
+        assert lhs > 0 and abs(lhs - rhs) <= tol * abs(lhs), (q, lhs, rhs)
+    batch.close()
+    for s in sims:
+        s.close()
