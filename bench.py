@@ -1,15 +1,20 @@
-"""Benchmark: forward elastic FD throughput (Gcell-steps/s) on one MI355X.
+"""Benchmark of the elastic FD hot path on one MI355X.
 
-Workload: the 256^3 six-layer + 5 % Gaussian-perturbed model (h 10 m, dt 0.5 ms),
-random moment-tensor source with a 12 Hz Ricker wavelet, 256 receivers, 20-cell
-sponge, FP32.  A "step" is one time step of the whole forward path: velocity pass
-(force source, damping), receiver sampling, stress pass (moment source, damping).
+Headline (``value``): forward throughput in Gcell-steps/s on the 256^3 six-layer +
+5 % Gaussian-perturbed model (h 10 m, dt 0.5 ms, 2000 steps), random moment-tensor
+source, 12 Hz Ricker, 256 receivers, 20-cell sponge, FP32.  A "step" is one time step of
+the whole forward path: velocity pass (force source, damping), receiver sampling, stress
+pass (moment source, damping).
 
-    python bench.py [--steps 2000] [--warmup 100] [--gpus 1]
+Also reported (same JSON line):
+  batched  -- the 24-shot uneven batch (128^3 .. 256x256x128, 1500 steps): per-shot loop
+              vs one persistent launch per pass replayed from a hipGraph (Gcell-steps/s);
+  gradient -- the 8-shot 256^3 FWI gradient (1500 steps, checkpoints every 50): per-shot
+              loop vs batched waves (shots/s);
+  roofline -- the dominant forward kernel's algorithmic bytes / its HIP-event duration;
+  cpu_baseline -- the FP64 oracle on a bounded sample on this host's cores.
 
-Prints ONE JSON line.  Per-kernel durations come from HIP events recorded on the
-stream the kernels run on; the CPU baseline is the FP64 oracle on a bounded sample
-of the same workload (first few steps at full size) on this host's cores.
+    python bench.py [--steps 2000] [--warmup 100] [--gpus 1] [--no-batch] [--no-grad]
 """
 from __future__ import annotations
 
@@ -24,16 +29,209 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-# algorithmic (compulsory) bytes per cell per launch, FP32: every field read once and
-# every updated field written once
+# algorithmic (compulsory) bytes per cell per launch, FP32: every input field read once
+# and every updated field written once
 BYTES_PER_CELL = {
-    "velocity": 4 * (6 + 3 + 1 + 3),   # read 6 stress, 3 velocity, rho; write 3 velocity
-    "stress": 4 * (3 + 6 + 2 + 6),     # read 3 velocity, 6 stress, lambda, mu; write 6 stress
+    "velocity": 4 * (6 + 3 + 1 + 3),  # read 6 stress, 3 velocity, rho; write 3 velocity
+    "stress": 4 * (3 + 6 + 2 + 6),  # read 3 velocity, 6 stress, lambda, mu; write 6 stress
 }
+# gradient, per shot and time step: forward with checkpoints (120), segment recompute
+# storing v^{n+1/2} and sigma^n (156), the four adjoint passes: stress-A 27 fields,
+# velocity-A 12, velocity-B 19, stress-B 15 (292)
+GRAD_BYTES_PER_CELL_STEP = 120 + 156 + 4 * (27 + 12 + 19 + 15)
+# measured counter calibration (plain 1 GiB copy): FETCH_SIZE reads 0.5x, WRITE_SIZE 1.0x
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
+def shot_desc(s):
+    return dict(src_pos=s.src_pos, moment=s.moment, force=s.force, wavelet=s.wavelet, rec_pos=s.rec_pos)
+
+
+def bench_forward(K, Wm):
+    import torch
+
+    import workloads as W
+    from paper_2112_15071_amd import Simulator, _abi
+
+    dev = torch.device("cuda:0")
+    log(f"[bench] 256^3 workload: steps {K}, warmup {Wm}")
+    shot = W.c1(nt=max(K, Wm))
+    nx, ny, nz = shot.shape
+    cells = nx * ny * nz
+    lam, mu, rho = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (shot.lam, shot.mu, shot.rho))
+    wav = torch.as_tensor(shot.wavelet, dtype=torch.float32).to(dev)
+    kw = dict(dtype=torch.float32, sponge=shot.sponge, device=dev)
+    sim = Simulator(lam, mu, rho, shot.h, shot.dt, K, **kw)
+    tune = sim.autotune(steps=20)
+    log(f"[bench] kernel {sim.kernel()} (autotune {'cached' if tune['cached'] else 'run'})")
+    if Wm > 0:
+        warm = Simulator(lam, mu, rho, shot.h, shot.dt, Wm, **kw)
+        k = sim.kernel()
+        warm.set_kernel(k["variant"], k["tile_y"], k["zchunk"], k["tile_x"])
+        warm.forward(shot.src_pos, shot.moment, shot.force, wav[:Wm], shot.rec_pos)
+        sync()
+        warm.close()
+    traces = torch.empty((shot.rec_pos.shape[0], 3, K), dtype=torch.float32, device=dev)
+    sync()
+    t0 = time.perf_counter()
+    sim.forward(shot.src_pos, shot.moment, shot.force, wav[:K], shot.rec_pos, traces=traces)
+    sync()
+    elapsed = time.perf_counter() - t0
+    gcs = cells * K / elapsed / 1e9
+    log(f"[bench] forward {elapsed:.3f} s -> {gcs:.2f} Gcell-steps/s")
+    # the same run again with per-kernel HIP events on the launch stream
+    _abi.fd3d_profile(sim.ctx, True)
+    sim.forward(shot.src_pos, shot.moment, shot.force, wav[:K], shot.rec_pos, traces=traces)
+    ms, launches = _abi.fd3d_profile_read(sim.ctx)
+    sync()
+    _abi.fd3d_profile(sim.ctx, False)
+    names = ("velocity", "record", "stress")
+    per = {names[i]: ms[i] / max(launches[i], 1) for i in range(3)}
+    dom = "stress" if ms[2] >= ms[0] else "velocity"
+    bytes_launch = BYTES_PER_CELL[dom] * cells
+    achieved = bytes_launch / (per[dom] * 1e-3) / 1e9
+    both = (BYTES_PER_CELL["velocity"] + BYTES_PER_CELL["stress"]) * cells * K / (elapsed * 1e9)
+    log(f"[bench] avg kernel ms {per}; dominant {dom} {achieved:.0f} GB/s; whole step {both:.0f} GB/s")
+    kern = sim.kernel()
+    sim.close()
+    return shot, dict(gcs=gcs, elapsed=elapsed, per=per, dom=dom, achieved=achieved, bytes_launch=bytes_launch,
+                      both=both, kernel=kern)
+
+
+def bench_batch():
+    import torch
+
+    import workloads as W
+    from paper_2112_15071_amd import Simulator
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    log("[bench] 24-shot uneven batch, 1500 steps")
+    shots = W.c3()
+    cells_steps = sum(s.cells * s.nt for s in shots)
+    sims = [Simulator(s.lam, s.mu, s.rho, s.h, s.dt, s.nt, sponge=s.sponge) for s in shots]
+    batch = BatchSimulator(sims)
+    tune = batch.autotune(steps=10)
+    descs = [shot_desc(s) for s in shots]
+    traces = [torch.empty((len(s.rec_pos), 3, s.nt), device="cuda") for s in shots]
+    # plain per-shot loop (each shot with its own tuned kernel)
+    for sim, d, tr in zip(sims, descs, traces):
+        sim.forward(**d, traces=tr)
+    sync()
+    t0 = time.perf_counter()
+    for sim, d, tr in zip(sims, descs, traces):
+        sim.forward(**d, traces=tr)
+    sync()
+    t_loop = time.perf_counter() - t0
+    batch.forward(descs, use_graph=True, traces=traces)  # capture + first replay
+    sync()
+    t0 = time.perf_counter()
+    batch.forward(descs, use_graph=True, traces=traces)
+    sync()
+    t_graph = time.perf_counter() - t0
+    log(f"[bench] batch: loop {t_loop:.3f} s, graph {t_graph:.3f} s")
+    batch.close()
+    for s in sims:
+        s.close()
+    return dict(loop_gcs=round(cells_steps / t_loop / 1e9, 3), batched_gcs=round(cells_steps / t_graph / 1e9, 3),
+                loop_s=round(t_loop, 3), batched_s=round(t_graph, 3), speedup=round(t_loop / t_graph, 3),
+                tile=[tune["tile_x"], tune["tile_y"]], cell_steps=cells_steps)
+
+
+def bench_gradient(wave=4):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2112_15071_amd import Simulator
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    log("[bench] FWI gradient: 8 shots, 256^3, 1500 steps, checkpoints every 50")
+    (tl, tm, tr_), start = W.c4_models()
+    dev = torch.device("cuda:0")
+    true = [torch.as_tensor(a, dtype=torch.float32, device=dev) for a in (tl, tm, tr_)]
+    model = [torch.as_tensor(a, dtype=torch.float32, device=dev) for a in start]
+    shots = W.c4_shots(*start)
+    k = 50
+    # observed data from the true model
+    obs_sim = Simulator(*true, 10.0, 5e-4, 1500, sponge=20, device=dev)
+    obs_sim.autotune(steps=10)
+    d_obs = [obs_sim.forward(**shot_desc(s)).clone() for s in shots]
+    sync()
+    obs_sim.close()
+    del true
+    # per-shot loop through one gradient workspace
+    sim = Simulator(*model, 10.0, 5e-4, 1500, sponge=20, device=dev)
+    sim.autotune(steps=10)
+    gws = sim.grad_workspace(k)
+    g_loop = [torch.zeros_like(model[0]) for _ in range(3)]
+    sync()
+    t0 = time.perf_counter()
+    J_loop = 0.0
+    for s, o in zip(shots, d_obs):
+        _, j = sim.gradient(gws, o, *g_loop, **shot_desc(s))
+        J_loop = J_loop + j
+    sync()
+    t_loop = time.perf_counter() - t0
+    kern = sim.kernel()
+    sim.close()
+    del gws
+    torch.cuda.empty_cache()
+    log(f"[bench] gradient loop {t_loop:.2f} s")
+    # batched waves sharing the model and the gradient arrays
+    sims = [Simulator(*model, 10.0, 5e-4, 1500, sponge=20, device=dev) for _ in range(wave)]
+    for x in sims:
+        x.set_kernel(kern["variant"], kern["tile_y"], kern["zchunk"], kern["tile_x"])
+    batch = BatchSimulator(sims)
+    batch.set_kernel(kern["tile_x"], kern["tile_y"])
+    gws_b = [x.grad_workspace(k) for x in sims]
+    g_b = [torch.zeros_like(model[0]) for _ in range(3)]
+    sync()
+    t0 = time.perf_counter()
+    J_b = 0.0
+    for w0 in range(0, len(shots), wave):
+        grp = shots[w0:w0 + wave]
+        _, J = batch.gradient([shot_desc(s) for s in grp], d_obs[w0:w0 + wave], *g_b, ckpt_every=k, gws=gws_b)
+        J_b = J_b + J.sum()
+    sync()
+    t_b = time.perf_counter() - t0
+    log(f"[bench] gradient batched {t_b:.2f} s")
+    diff = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip(g_b, g_loop))
+    batch.close()
+    for x in sims:
+        x.close()
+    del gws_b
+    torch.cuda.empty_cache()
+    n = len(shots)
+    return dict(loop_shots_per_s=round(n / t_loop, 4), batched_shots_per_s=round(n / t_b, 4),
+                loop_s=round(t_loop, 2), batched_s=round(t_b, 2), speedup=round(t_loop / t_b, 3), wave=wave,
+                misfit=float(J_loop), max_rel_diff_batched_vs_loop=diff,
+                bytes_per_cell_step_per_shot=GRAD_BYTES_PER_CELL_STEP)
+
+
+def cpu_baseline(shot, ns):
+    import oracle
+
+    oracle.build(force=False)
+    cfg = oracle.Config(shot.shape, shot.h, shot.dt, ns, sponge=shot.sponge)
+    src = oracle.Source(shot.src_pos, moment=shot.moment, force=shot.force)
+    log(f"[bench] oracle baseline: {ns} steps at full size on {oracle.get_threads()} threads")
+    t0 = time.perf_counter()
+    oracle.forward(cfg, shot.lam, shot.mu, shot.rho, src, shot.wavelet[:ns], shot.rec_pos)
+    dt = time.perf_counter() - t0
+    cells = int(shot.cells)
+    return {"value": round(cells * ns / dt / 1e9, 5), "unit": "Gcell-steps/s", "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle on the 256^3 workload at full size, first {ns} of 2000 steps ({dt:.1f} s)"}
 
 
 def main():
@@ -42,90 +240,27 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps for the CPU baseline sample (0: skip)")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built.",
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-
-    import workloads as W
-    from paper_2112_15071_amd import Simulator, _abi
-
-    dev = torch.device("cuda:0")
-    K, Wm = args.steps, args.warmup
-    log(f"[bench] generating the 256^3 workload (steps {K}, warmup {Wm})")
-    shot = W.c1(nt=max(K, Wm))
+    shot, f = bench_forward(args.steps, args.warmup)
+    batch = None if args.no_batch else bench_batch()
+    grad = None if args.no_grad else bench_gradient()
+    cpu = cpu_baseline(shot, args.cpu_steps) if args.cpu_steps > 0 else None
     nx, ny, nz = shot.shape
-    cells = nx * ny * nz
-    lam, mu, rho = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (shot.lam, shot.mu, shot.rho))
-    wav = torch.as_tensor(shot.wavelet, dtype=torch.float32).to(dev)
-    kw = dict(dtype=torch.float32, sponge=shot.sponge, device=dev)
-
-    if Wm > 0:
-        warm = Simulator(lam, mu, rho, shot.h, shot.dt, Wm, **kw)
-        warm.forward(shot.src_pos, shot.moment, shot.force, wav[:Wm], shot.rec_pos)
-        torch.cuda.synchronize()
-        warm.close()
-        del warm
-
-    sim = Simulator(lam, mu, rho, shot.h, shot.dt, K, **kw)
-    traces = torch.empty((shot.rec_pos.shape[0], 3, K), dtype=torch.float32, device=dev)
-    log(f"[bench] timed forward: {K} steps on {nx}x{ny}x{nz}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.forward(shot.src_pos, shot.moment, shot.force, wav[:K], shot.rec_pos, traces=traces)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    gcs = cells * K / elapsed / 1e9
-    log(f"[bench] {elapsed:.3f} s -> {gcs:.2f} Gcell-steps/s")
-
-    # same run again with per-kernel HIP events on the launch stream
-    _abi.fd3d_profile(sim.ctx, True)
-    torch.cuda.synchronize()
-    p0 = time.perf_counter()
-    sim.forward(shot.src_pos, shot.moment, shot.force, wav[:K], shot.rec_pos, traces=traces)
-    ms, launches = _abi.fd3d_profile_read(sim.ctx)
-    torch.cuda.synchronize()
-    p1 = time.perf_counter()
-    _abi.fd3d_profile(sim.ctx, False)
-    names = ("velocity", "record", "stress")
-    per = {names[i]: (ms[i] / max(launches[i], 1)) for i in range(3)}
-    log(f"[bench] profiled run {p1 - p0:.3f} s; avg kernel ms: " + ", ".join(f"{k} {v:.4f}" for k, v in per.items()))
-    dom = "stress" if ms[2] >= ms[0] else "velocity"
-    bytes_launch = BYTES_PER_CELL[dom] * cells
-    achieved = bytes_launch / (per[dom] * 1e-3) / 1e9
-    both = (BYTES_PER_CELL["velocity"] + BYTES_PER_CELL["stress"]) * cells * K / (elapsed * 1e9)
-    log(f"[bench] dominant {dom}: {achieved:.0f} GB/s; whole step {both:.0f} GB/s")
-    sim.close()
-
-    cpu = None
-    if args.cpu_steps > 0:
-        import oracle
-
-        oracle.build(force=False)
-        ns = args.cpu_steps
-        cfg = oracle.Config(shot.shape, shot.h, shot.dt, ns, sponge=shot.sponge)
-        src = oracle.Source(shot.src_pos, moment=shot.moment, force=shot.force)
-        log(f"[bench] oracle baseline: {ns} steps at full size on {oracle.get_threads()} threads")
-        c0 = time.perf_counter()
-        oracle.forward(cfg, shot.lam, shot.mu, shot.rho, src, shot.wavelet[:ns], shot.rec_pos)
-        c1 = time.perf_counter()
-        cpu = {"value": cells * ns / (c1 - c0) / 1e9, "unit": "Gcell-steps/s", "cores": oracle.get_threads(),
-               "kind": "oracle", "sample": f"FP64 oracle, 256^3 workload, first {ns} of 2000 steps ({c1 - c0:.1f} s)"}
-        log(f"[bench] oracle {cpu['value']:.4f} Gcell-steps/s")
-
     out = {
         "metric": "FD Gcell-steps/s (forward, 256^3, FP32)",
-        "value": round(gcs, 3),
+        "value": round(f["gcs"], 3),
         "unit": "Gcell-steps/s",
         "n_gpus": 1,
-        "steps": K,
-        "warmup": Wm,
-        "ms_per_step": round(elapsed / K * 1e3, 4),
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f["elapsed"] / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -135,22 +270,26 @@ def main():
             "workload": "256^3 six-layer + 5% Gaussian-correlated perturbation, h 10 m, dt 0.5 ms, random MT "
                         "source, 12 Hz Ricker, 256 receivers, 20-cell Cerjan sponge, O(2,4) velocity-stress",
             "grid": [nx, ny, nz],
-            "cells": cells,
-            "time_steps": K,
-            "hbm_gbs_whole_step": round(both, 1),
+            "cells": int(shot.cells),
+            "time_steps": args.steps,
+            "kernel": f["kernel"],
+            "hbm_gbs_whole_step": round(f["both"], 1),
+            "hbm_frac_whole_step": round(f["both"] / HBM_PEAK_GBS, 4),
             "bytes_per_cell_step": BYTES_PER_CELL["velocity"] + BYTES_PER_CELL["stress"],
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": dom,
-            "achieved": round(achieved, 1),
+            "kernel": f["dom"],
+            "achieved": round(f["achieved"], 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac": round(f["achieved"] / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "avg_kernel_ms": {k: round(v, 5) for k, v in per.items()},
-            "bytes_per_launch": bytes_launch,
+            "avg_kernel_ms": {k: round(v, 5) for k, v in f["per"].items()},
+            "bytes_per_launch": f["bytes_launch"],
         },
+        "batched_forward": batch,
+        "gradient": grad,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

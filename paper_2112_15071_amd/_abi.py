@@ -105,6 +105,7 @@ _SIGS = {
                              ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_sz), _i, _i,
                              _vp, _sz, _vp], _i),
     "fd3d_batch_destroy": ([_vp], None),
+    "fd3d_autotune": ([_vp, _i, ctypes.POINTER(fd3d_kernel), _dp, _vp], _i),
     "fd3d_set_kernel": ([_vp, ctypes.POINTER(fd3d_kernel)], _i),
     "fd3d_get_kernel": ([_vp, ctypes.POINTER(fd3d_kernel)], _i),
     "fd3d_profile": ([_vp, _i], _i),
@@ -254,6 +255,13 @@ def fd3d_batch_gradient(batch, srcs, nrec, rec_ptrs, d_obs, traces, misfit, g_la
 
 def fd3d_batch_destroy(batch) -> None:
     _lib.fd3d_batch_destroy(batch)
+
+
+def fd3d_autotune(ctx, steps: int, stream):
+    k = fd3d_kernel()
+    ms = ctypes.c_double(0.0)
+    _check(_lib.fd3d_autotune(ctx, int(steps), ctypes.byref(k), ctypes.byref(ms), stream))
+    return k, float(ms.value)
 
 
 def fd3d_set_kernel(ctx, k: fd3d_kernel) -> None:

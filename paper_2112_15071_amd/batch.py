@@ -34,6 +34,25 @@ class BatchSimulator:
     def set_kernel(self, tile_x: int, tile_y: int, workgroups: int = 0) -> None:
         _abi.fd3d_batch_set_kernel(self._b, tile_x, tile_y, workgroups)
 
+    def autotune(self, steps: int = 20, cache: bool = True) -> dict:
+        """Autotune every distinct grid shape of the batch (each context keeps its own z
+        chunk); the batch takes the tile shape that won for the most cells."""
+        votes = {}
+        seen = {}
+        for sim in self.sims:
+            key = (sim.shape, sim.dtype)
+            if key not in seen:
+                seen[key] = sim.autotune(steps, cache)
+            else:
+                e = seen[key]
+                sim.set_kernel("tile", e["tile_y"], e["zchunk"], e["tile_x"])
+            e = seen[key]
+            cells = int(np.prod(sim.shape))
+            votes[(e["tile_x"], e["tile_y"])] = votes.get((e["tile_x"], e["tile_y"]), 0) + cells
+        tx, ty = max(votes.items(), key=lambda kv: kv[1])[0]
+        self.set_kernel(tx, ty)
+        return {"tile_x": tx, "tile_y": ty, "per_shape": {f"{k[0]}": v for k, v in seen.items()}}
+
     def forward(self, shots: List[Dict], use_graph: bool = True, keep_state: bool = False,
                 traces: List[torch.Tensor] = None) -> List[torch.Tensor]:
         if len(shots) != len(self.sims):

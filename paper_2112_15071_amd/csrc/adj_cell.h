@@ -298,16 +298,13 @@ __global__ void __launch_bounds__(256) scale_velocity(Grid<T> G, const T *__rest
 }
 
 // ---------------------------------------------------------------------------------
-// Many shots per launch.  A shot's cells are covered by nbx x nby x nz blocks of 64 x 4
-// threads; the blocks of all shots form one flat list (shot-major).  Receiver injection
-// of colour c covers the colour-c receivers of every shot (shots never share arrays).
+// Residual injection for many shots per launch.  Colour c's receivers of every shot form
+// one flat work list (shot-major, three components per receiver); shots never share
+// adjoint arrays, so one launch per colour is free of races.
 constexpr int kMaxBatchColors = 4;
 
-template <typename T> struct ShotAdj {
-    Grid<T> G;
-    AdjGrid<T> A;
-    Inject<T> src;
-    int nbx, nby, base;
+template <typename T> struct ShotInject {
+    T *a[3];  // A_v
     const RecTap<T> *taps;
     const int *colors;
     const T *res;
@@ -316,53 +313,20 @@ template <typename T> struct ShotAdj {
 };
 
 template <typename T>
-__device__ __forceinline__ int find_adj(const ShotAdj<T> *__restrict__ d, int nshot, int w)
-{
-    int s = 0;
-    while (s + 1 < nshot && d[s + 1].base <= w) ++s;
-    return s;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) adj_stress_multi(const ShotAdj<T> *__restrict__ d, int nshot)
-{
-    const int s = find_adj(d, nshot, (int)blockIdx.x);
-    const ShotAdj<T> &sh = d[s];
-    const int b = (int)blockIdx.x - sh.base;
-    const int bz = b / (sh.nbx * sh.nby), r = b % (sh.nbx * sh.nby);
-    const int i = (r % sh.nbx) * 64 + (int)(threadIdx.x & 63), j = (r / sh.nbx) * 4 + (int)(threadIdx.x >> 6);
-    const Grid<T> G = sh.G;
-    if (i >= G.nx || j >= G.ny) return;
-    const AdjGrid<T> A = sh.A;
-    adj_stress_body(G, A, i, j, bz);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) adj_vel_multi(const ShotAdj<T> *__restrict__ d, int nshot, int n)
-{
-    const int s = find_adj(d, nshot, (int)blockIdx.x);
-    const ShotAdj<T> &sh = d[s];
-    const int b = (int)blockIdx.x - sh.base;
-    const int bz = b / (sh.nbx * sh.nby), r = b % (sh.nbx * sh.nby);
-    const int i = (r % sh.nbx) * 64 + (int)(threadIdx.x & 63), j = (r / sh.nbx) * 4 + (int)(threadIdx.x >> 6);
-    const Grid<T> G = sh.G;
-    if (i >= G.nx || j >= G.ny) return;
-    const AdjGrid<T> A = sh.A;
-    adj_vel_body(G, A, sh.src, n, i, j, bz);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) inject_residual_multi(const ShotAdj<T> *__restrict__ d, int nshot, int color,
+__global__ void __launch_bounds__(256) inject_residual_multi(const ShotInject<T> *__restrict__ d, int nshot, int color,
                                                              int total, int nt, int n)
 {
+    __shared__ int s_base[kMaxShots];
+    for (int t = threadIdx.x; t < nshot; t += blockDim.x) s_base[t] = d[t].rbase[color];
+    __syncthreads();
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= total) return;
     int s = 0;
-    while (s + 1 < nshot && d[s + 1].rbase[color] <= q) ++s;
-    const ShotAdj<T> &sh = d[s];
+    while (s + 1 < nshot && s_base[s + 1] <= q) ++s;
+    const ShotInject<T> &sh = d[s];
     const int l = q - sh.rbase[color];
     const int r = sh.colors[sh.coff[color] + l / 3];
-    inject_one(sh.A.a[VX], sh.A.a[VY], sh.A.a[VZ], sh.taps, r, l % 3, sh.res, nt, n);
+    inject_one(sh.a[0], sh.a[1], sh.a[2], sh.taps, r, l % 3, sh.res, nt, n);
 }
 
 // Copies of many equally long arrays (checkpoint save / restore of every shot).

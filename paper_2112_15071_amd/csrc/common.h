@@ -63,6 +63,24 @@ template <typename T> struct RecTap {
     T w[8];
 };
 
+// Largest number of shots in one batched launch (per-workgroup LDS table of shot bases).
+constexpr int kMaxShots = 256;
+
+// Per-workgroup copy of the shots' first work items; the shot of item w is then found
+// in LDS and made wave-uniform, so the shot's descriptor is read through scalar loads.
+__device__ __forceinline__ void load_bases(int *s_base, const int *base, int stride_ints, int nshot)
+{
+    for (int s = threadIdx.x; s < nshot; s += blockDim.x) s_base[s] = base[(long)s * stride_ints];
+    __syncthreads();
+}
+
+__device__ __forceinline__ int shot_of(const int *s_base, int nshot, int w)
+{
+    int s = 0;
+    while (s + 1 < nshot && s_base[s + 1] <= w) ++s;
+    return __builtin_amdgcn_readfirstlane(s);
+}
+
 // Tap number of (i,j,k) in a source box, or -1.
 template <typename T>
 __device__ __forceinline__ int tap_of(const Inject<T> &s, int c, int i, int j, int k)

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -256,6 +257,8 @@ template <typename T> void zero_fields(fd3d_ctx *c, hipStream_t st)
     fill_zero<T><<<2048, 256, 0, st>>>((T *)c->ws, n);
 }
 
+void zero_fields_any(fd3d_ctx *c, hipStream_t st);
+
 template <typename T> int build_source(const fd3d_ctx *c, const fd3d_source *src, Inject<T> &inj)
 {
     std::memset(&inj, 0, sizeof inj);
@@ -388,6 +391,12 @@ struct Timer {
     }
 };
 
+void zero_fields_any(fd3d_ctx *c, hipStream_t st)
+{
+    if (c->tsize == 8) zero_fields<double>(c, st);
+    else zero_fields<float>(c, st);
+}
+
 TileMap tile_map(const fd3d_ctx *c)
 {
     TileMap tm;
@@ -398,14 +407,6 @@ TileMap tile_map(const fd3d_ctx *c)
     return tm;
 }
 
-template <typename T, int TX, int TY, bool FS>
-void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &tm, int pass, hipStream_t st)
-{
-    const int nwg = tm.ntx * tm.nty * tm.nzc;
-    if (pass == 0) vel_tile<T, TX, TY, FS><<<nwg, TX * TY, 0, st>>>(G, inj, n, tm);
-    else stress_tile<T, TX, TY, FS><<<nwg, TX * TY, 0, st>>>(G, inj, n, tm);
-}
-
 // Supported tile shapes: 64x{4,8,16}, 128x{4,8}, 256x4 (FP64: 64x{4,8}, 128x4).
 bool tile_supported(int tsize, int tx, int ty)
 {
@@ -414,34 +415,71 @@ bool tile_supported(int tsize, int tx, int ty)
            (tx == 256 && ty == 4);
 }
 
+// Calls f(TX, TY) with the tile shape as integral constants (64x8 for a shape that is
+// not compiled for T).
+template <typename T, typename F> decltype(auto) with_tile(int tx, int ty, F &&f)
+{
+    using X64 = std::integral_constant<int, 64>;
+    using X128 = std::integral_constant<int, 128>;
+    using X256 = std::integral_constant<int, 256>;
+    using Y4 = std::integral_constant<int, 4>;
+    using Y8 = std::integral_constant<int, 8>;
+    using Y16 = std::integral_constant<int, 16>;
+    const int key = tx * 100 + ty;
+    if constexpr (sizeof(T) == 8) {
+        switch (key) {
+        case 6404: return f(X64{}, Y4{});
+        case 12804: return f(X128{}, Y4{});
+        default: return f(X64{}, Y8{});
+        }
+    } else {
+        switch (key) {
+        case 6404: return f(X64{}, Y4{});
+        case 6416: return f(X64{}, Y16{});
+        case 12804: return f(X128{}, Y4{});
+        case 12808: return f(X128{}, Y8{});
+        case 25604: return f(X256{}, Y4{});
+        default: return f(X64{}, Y8{});
+        }
+    }
+}
+
+// Passes of a step.  Forward: velocity, stress.  Adjoint step (reverse order of the
+// forward step): stress-A (C gradients, X = C G_s A_s), velocity-A (A_v update),
+// velocity-B (b gradient, Y = G_v A_v / rho_eff), stress-B (A_s update).
+enum Pass { kPassVel = 0, kPassStress = 1, kPassStressA, kPassVelA, kPassVelB, kPassStressB };
+
+template <typename T, int TX, int TY, bool FS>
+void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &tm, int pass, hipStream_t st,
+                  const TileIO<T> &io = TileIO<T>{})
+{
+    const int nwg = tm.ntx * tm.nty * tm.nzc;
+    constexpr int NT = TX * TY;
+    switch (pass) {
+    case kPassVel: vel_tile<T, TX, TY, FS><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
+    case kPassStress: stress_tile<T, TX, TY, FS><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
+    case kPassStressA: stress_tile_adj<T, TX, TY, kAdjA><<<nwg, NT, 0, st>>>(G, inj, tm, io); break;
+    case kPassVelA: vel_tile_adj<T, TX, TY, kAdjA><<<nwg, NT, 0, st>>>(G, inj, n, tm, io); break;
+    case kPassVelB: vel_tile_adj<T, TX, TY, kAdjB><<<nwg, NT, 0, st>>>(G, inj, n, tm, io); break;
+    default: stress_tile_adj<T, TX, TY, kAdjB><<<nwg, NT, 0, st>>>(G, inj, tm, io); break;
+    }
+}
+
 template <typename T, bool FS>
-void launch_pass(const fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int pass, hipStream_t st)
+void launch_pass(const fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int pass, hipStream_t st,
+                 const TileIO<T> &io = TileIO<T>{})
 {
     if (c->variant == FD3D_KERNEL_CELL) {
         const dim3 blk(64, 4, 1);
         const dim3 grd((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
-        if (pass == 0) vel_cell<T, FS><<<grd, blk, 0, st>>>(G, inj, n);
+        if (pass == kPassVel) vel_cell<T, FS><<<grd, blk, 0, st>>>(G, inj, n);
         else stress_cell<T, FS><<<grd, blk, 0, st>>>(G, inj, n);
         return;
     }
     const TileMap tm = tile_map(c);
-    const int key = c->tile_x * 100 + c->tile_y;
-    if (sizeof(T) == 8) {
-        switch (key) {
-        case 6404: launch_tiles<T, 64, 4, FS>(G, inj, n, tm, pass, st); break;
-        case 12804: launch_tiles<T, 128, 4, FS>(G, inj, n, tm, pass, st); break;
-        default: launch_tiles<T, 64, 8, FS>(G, inj, n, tm, pass, st); break;
-        }
-        return;
-    }
-    switch (key) {
-    case 6404: launch_tiles<T, 64, 4, FS>(G, inj, n, tm, pass, st); break;
-    case 6416: launch_tiles<T, 64, 16, FS>(G, inj, n, tm, pass, st); break;
-    case 12804: launch_tiles<T, 128, 4, FS>(G, inj, n, tm, pass, st); break;
-    case 12808: launch_tiles<T, 128, 8, FS>(G, inj, n, tm, pass, st); break;
-    case 25604: launch_tiles<T, 256, 4, FS>(G, inj, n, tm, pass, st); break;
-    default: launch_tiles<T, 64, 8, FS>(G, inj, n, tm, pass, st); break;
-    }
+    with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
+        launch_tiles<T, decltype(tx)::value, decltype(ty)::value, FS>(G, inj, n, tm, pass, st, io);
+    });
 }
 
 template <typename T, bool FS>
@@ -449,7 +487,7 @@ void step(fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int nrec, 
           hipStream_t st, Timer &tm)
 {
     tm.begin(0);
-    launch_pass<T, FS>(c, G, inj, n, 0, st);
+    launch_pass<T, FS>(c, G, inj, n, kPassVel, st);
     tm.end();
     if (nrec > 0) {
         tm.begin(1);
@@ -457,17 +495,18 @@ void step(fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int nrec, 
         tm.end();
     }
     tm.begin(2);
-    launch_pass<T, FS>(c, G, inj, n, 1, st);
+    launch_pass<T, FS>(c, G, inj, n, kPassStress, st);
     tm.end();
 }
 
 // Gradient workspace (byte offsets): adjoint state, staggered-point gradient
-// accumulators, checkpoints every k steps, one k-step segment of stored fields, and the
-// residual buffer of fd3d_gradient.
+// accumulators, the tiled adjoint's intermediate fields, checkpoints every k steps, one
+// k-step segment of stored fields, and the residual buffer of fd3d_gradient.
 struct GradLayout {
     size_t stride;  // bytes per field slot
     size_t adj;     // 9 fields: A_v, A_s
     size_t acc;     // 8 fields: gl, gm, g_mu_xy, g_mu_xz, g_mu_yz, g_bx, g_by, g_bz
+    size_t scr;     // 9 fields: X = C G_s A_s (6, stress layout), Y = G_v A_v / rho_eff (3)
     size_t ckpt;    // nseg x 9 fields: state at the start of steps 0, k, 2k, ...
     size_t seg;     // k x 9 fields: v^{n+1/2} (3) then sigma^n (6) per step of a segment
     size_t res;     // residual [max_rec][3][nt]
@@ -487,6 +526,8 @@ GradLayout make_grad_layout(const fd3d_ctx *c, int k)
     off += 9 * g.stride;
     g.acc = off;
     off += 8 * g.stride;
+    g.scr = off;
+    off += 9 * g.stride;
     g.ckpt = off;
     off += (size_t)g.nseg * 9 * g.stride;
     g.seg = off;
@@ -553,6 +594,49 @@ template <typename T> AdjGrid<T> make_adj(char *gws, const GradLayout &GL)
     return A;
 }
 
+// Fields of the four tiled adjoint passes of one step whose stored v^{n+1/2}, sigma^n
+// sit in segment slot `slot`: grids (f[] re-pointed) and tile outputs.
+template <typename T> struct AdjTiles {
+    Grid<T> g[4];     // stress-A, velocity-A, velocity-B, stress-B
+    TileIO<T> io[4];
+};
+
+template <typename T> AdjTiles<T> adj_tiles(const Grid<T> &G, char *gws, const GradLayout &GL, const char *slot)
+{
+    auto fld = [&](size_t base, int q) { return (T *)(gws + base + q * GL.stride); };
+    AdjTiles<T> P;
+    for (int p = 0; p < 4; ++p) {
+        P.g[p] = G;
+        for (int f = 0; f < NFIELD; ++f) P.g[p].save[f] = nullptr;
+        std::memset(&P.io[p], 0, sizeof P.io[p]);
+    }
+    for (int q = 0; q < 3; ++q) {
+        P.g[0].f[VX + q] = (T *)(slot + q * GL.stride);  // stored v^{n+1/2}
+        P.g[1].f[VX + q] = fld(GL.adj, VX + q);           // A_v
+        P.g[2].f[VX + q] = fld(GL.adj, VX + q);
+        P.g[3].f[VX + q] = fld(GL.scr, 6 + q);            // Y
+        P.io[2].acc[q] = fld(GL.acc, 5 + q);              // g_b
+        P.io[2].out[q] = fld(GL.scr, 6 + q);
+    }
+    for (int q = 0; q < 6; ++q) {
+        P.g[0].f[SXX + q] = fld(GL.adj, SXX + q);           // A_s
+        P.g[1].f[SXX + q] = fld(GL.scr, q);                 // X
+        P.g[2].f[SXX + q] = (T *)(slot + (3 + q) * GL.stride);  // stored sigma^n
+        P.g[3].f[SXX + q] = fld(GL.adj, SXX + q);
+        P.io[0].out[q] = fld(GL.scr, q);
+    }
+    for (int q = 0; q < 5; ++q) P.io[0].acc[q] = fld(GL.acc, q);  // gl, gm, g_mu_xy, g_mu_xz, g_mu_yz
+    return P;
+}
+
+// Zero the adjoint state, accumulators and intermediate fields, and the segment slots
+// (whose samples at the pinned staggered positions are never stored and must read 0).
+template <typename T> void zero_grad_fields(char *gws, const GradLayout &GL, hipStream_t st)
+{
+    fill_zero<T><<<2048, 256, 0, st>>>((T *)(gws + GL.adj), (long)(26 * GL.stride / sizeof(T)));
+    fill_zero<T><<<2048, 256, 0, st>>>((T *)(gws + GL.seg), (long)((size_t)GL.k * 9 * GL.stride / sizeof(T)));
+}
+
 // Reverse sweep over the checkpointed segments: recompute each segment (storing
 // v^{n+1/2} and sigma^n per step), then run the adjoint steps backwards; finally map
 // the staggered-point gradients to the node arrays (accumulated into g_*).
@@ -567,15 +651,23 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
     if (rc) return rc;
     Grid<T> G = make_grid<T>(c);
     AdjGrid<T> A = make_adj<T>(gws, GL);
-    // zero the adjoint state and the accumulators (17 consecutive field slots)
-    fill_zero<T><<<2048, 256, 0, st>>>((T *)(gws + GL.adj), (long)(17 * GL.stride / sizeof(T)));
+    zero_grad_fields<T>(gws, GL, st);
     const RecTap<T> *taps = (const RecTap<T> *)(c->ws + c->L.rec);
     const int *colors = (const int *)(c->ws + c->L.colors);
     const dim3 blk(64, 4, 1), grd((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
+    const bool tiled = c->variant == FD3D_KERNEL_TILE;
     Timer tm{c, st};
     Inject<T> none;
     std::memset(&none, 0, sizeof none);
     for (int f = 0; f < NFIELD; ++f) none.i0[f] = none.j0[f] = none.k0[f] = -(1 << 28);
+    auto inject = [&](int n) {
+        for (size_t col = 0; col + 1 < c->color_off.size(); ++col) {
+            const int cnt = c->color_off[col + 1] - c->color_off[col];
+            inject_residual<T><<<(3 * cnt + 255) / 256, 256, 0, st>>>(A.a[VX], A.a[VY], A.a[VZ], taps,
+                                                                     colors + c->color_off[col], cnt, residual,
+                                                                     c->nt, n);
+        }
+    };
     for (int sgi = GL.nseg - 1; sgi >= 0; --sgi) {
         const int n0 = sgi * GL.k, n1 = std::min(n0 + GL.k, c->nt);
         const char *ck = gws + GL.ckpt + (size_t)sgi * 9 * GL.stride;
@@ -590,16 +682,20 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
         }
         for (int n = n1 - 1; n >= n0; --n) {
             const char *slot = gws + GL.seg + (size_t)(n - n0) * 9 * GL.stride;
-            for (int q = 0; q < 3; ++q) A.vst[q] = (const T *)(slot + q * GL.stride);
-            for (int q = 0; q < 6; ++q) A.sst[q] = (const T *)(slot + (3 + q) * GL.stride);
-            adj_stress_cell<T><<<grd, blk, 0, st>>>(G, A);
-            for (size_t col = 0; col + 1 < c->color_off.size(); ++col) {
-                const int cnt = c->color_off[col + 1] - c->color_off[col];
-                inject_residual<T><<<(3 * cnt + 255) / 256, 256, 0, st>>>(A.a[VX], A.a[VY], A.a[VZ], taps,
-                                                                         colors + c->color_off[col], cnt, residual,
-                                                                         c->nt, n);
+            if (tiled) {
+                const AdjTiles<T> P = adj_tiles<T>(G, gws, GL, slot);
+                launch_pass<T, false>(c, P.g[0], none, n, kPassStressA, st, P.io[0]);
+                launch_pass<T, false>(c, P.g[1], none, n, kPassVelA, st, P.io[1]);
+                inject(n);
+                launch_pass<T, false>(c, P.g[2], inj, n, kPassVelB, st, P.io[2]);
+                launch_pass<T, false>(c, P.g[3], none, n, kPassStressB, st, P.io[3]);
+            } else {
+                for (int q = 0; q < 3; ++q) A.vst[q] = (const T *)(slot + q * GL.stride);
+                for (int q = 0; q < 6; ++q) A.sst[q] = (const T *)(slot + (3 + q) * GL.stride);
+                adj_stress_cell<T><<<grd, blk, 0, st>>>(G, A);
+                inject(n);
+                adj_vel_cell<T><<<grd, blk, 0, st>>>(G, A, inj, n);
             }
-            adj_vel_cell<T><<<grd, blk, 0, st>>>(G, A, inj, n);
         }
     }
     grad_finalize<T><<<grd, blk, 0, st>>>(G, A, g_lam, g_mu, g_rho);
@@ -685,57 +781,35 @@ size_t batch_desc_bytes(int nshot, int tsize)
 template <typename T, int TX, int TY, bool FS>
 int launch_multi(fd3d_batch *b, const ShotFwd<T> *d, int n, int pass, hipStream_t st)
 {
-    if (pass == 0) vel_tile_multi<T, TX, TY, FS><<<b->wgs, TX * TY, 0, st>>>(d, b->nshot, b->total_tiles, n);
-    else stress_tile_multi<T, TX, TY, FS><<<b->wgs, TX * TY, 0, st>>>(d, b->nshot, b->total_tiles, n);
+    const int g = b->wgs, S = b->nshot, W = b->total_tiles;
+    constexpr int NT = TX * TY;
+    switch (pass) {
+    case kPassVel: vel_tile_multi<T, TX, TY, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassStress: stress_tile_multi<T, TX, TY, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassStressA: stress_tile_multi<T, TX, TY, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassVelA: vel_tile_multi<T, TX, TY, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassVelB: vel_tile_multi<T, TX, TY, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n); break;
+    default: stress_tile_multi<T, TX, TY, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n); break;
+    }
     return FD3D_OK;
 }
 
 template <typename T, bool FS> int multi_pass(fd3d_batch *b, const ShotFwd<T> *d, int n, int pass, hipStream_t st)
 {
-    const int key = b->tile_x * 100 + b->tile_y;
-    if (sizeof(T) == 8) {
-        switch (key) {
-        case 6404: return launch_multi<T, 64, 4, FS>(b, d, n, pass, st);
-        case 12804: return launch_multi<T, 128, 4, FS>(b, d, n, pass, st);
-        default: return launch_multi<T, 64, 8, FS>(b, d, n, pass, st);
-        }
-    }
-    switch (key) {
-    case 6404: return launch_multi<T, 64, 4, FS>(b, d, n, pass, st);
-    case 6416: return launch_multi<T, 64, 16, FS>(b, d, n, pass, st);
-    case 12804: return launch_multi<T, 128, 4, FS>(b, d, n, pass, st);
-    case 12808: return launch_multi<T, 128, 8, FS>(b, d, n, pass, st);
-    case 25604: return launch_multi<T, 256, 4, FS>(b, d, n, pass, st);
-    default: return launch_multi<T, 64, 8, FS>(b, d, n, pass, st);
-    }
-}
-
-template <typename T, int TX, int TY, bool FS> int occupancy_of()
-{
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, vel_tile_multi<T, TX, TY, FS>, TX * TY, 0) != hipSuccess)
-        occ = 1;
-    return occ > 0 ? occ : 1;
+    return with_tile<T>(b->tile_x, b->tile_y, [&](auto tx, auto ty) {
+        return launch_multi<T, decltype(tx)::value, decltype(ty)::value, FS>(b, d, n, pass, st);
+    });
 }
 
 template <typename T, bool FS> int multi_occupancy(const fd3d_batch *b)
 {
-    const int key = b->tile_x * 100 + b->tile_y;
-    if (sizeof(T) == 8) {
-        switch (key) {
-        case 6404: return occupancy_of<T, 64, 4, FS>();
-        case 12804: return occupancy_of<T, 128, 4, FS>();
-        default: return occupancy_of<T, 64, 8, FS>();
-        }
-    }
-    switch (key) {
-    case 6404: return occupancy_of<T, 64, 4, FS>();
-    case 6416: return occupancy_of<T, 64, 16, FS>();
-    case 12804: return occupancy_of<T, 128, 4, FS>();
-    case 12808: return occupancy_of<T, 128, 8, FS>();
-    case 25604: return occupancy_of<T, 256, 4, FS>();
-    default: return occupancy_of<T, 64, 8, FS>();
-    }
+    return with_tile<T>(b->tile_x, b->tile_y, [&](auto tx, auto ty) {
+        constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, vel_tile_multi<T, TX, TY, FS>, TX * TY, 0) != hipSuccess)
+            occ = 1;
+        return occ > 0 ? occ : 1;
+    });
 }
 
 // The whole nt-step sequence of a batch on one stream (also what a graph captures).
@@ -746,12 +820,12 @@ template <typename T> int batch_sequence(fd3d_batch *b, int flags, hipStream_t s
     const ShotRec<T> *r = (const ShotRec<T> *)(b->ws + b->off_rec);
     const ShotFwd<T> *d = (const ShotFwd<T> *)(b->ws + b->off_fwd);
     for (int n = 0; n < b->nt; ++n) {
-        if (b->fs) multi_pass<T, true>(b, d, n, 0, st);
-        else multi_pass<T, false>(b, d, n, 0, st);
+        if (b->fs) multi_pass<T, true>(b, d, n, kPassVel, st);
+        else multi_pass<T, false>(b, d, n, kPassVel, st);
         if (b->total_rec > 0)
             record_multi<T><<<(b->total_rec + 255) / 256, 256, 0, st>>>(r, b->nshot, b->total_rec, b->nt, n);
-        if (b->fs) multi_pass<T, true>(b, d, n, 1, st);
-        else multi_pass<T, false>(b, d, n, 1, st);
+        if (b->fs) multi_pass<T, true>(b, d, n, kPassStress, st);
+        else multi_pass<T, false>(b, d, n, kPassStress, st);
     }
     HIP_TRY(hipGetLastError());
     return FD3D_OK;
@@ -849,12 +923,14 @@ int check_gws(const fd3d_ctx *ctx, void *gws, size_t gws_bytes, int k)
 }
 
 // ---- batched gradient ----------------------------------------------------------
-// Batch workspace of fd3d_batch_gradient: per segment slot m the forward descriptors
-// (with the slot's store pointers) and the adjoint descriptors (with the slot's stored
-// fields); per checkpoint the save and restore copy lists.
+// Batch workspace of fd3d_batch_gradient: descriptor arrays (nshot entries each) of the
+// forward pass, of the segment recompute per segment slot m (store pointers of slot m),
+// of the adjoint passes (stress-A and velocity-B per slot m, which read the fields
+// stored in slot m; velocity-A and stress-B once), of the residual injection, and per
+// checkpoint the save and restore copy lists.
 struct BatchGradLayout {
-    size_t fwd0, fwd_slot, adj_slot, save_copy, rest_copy, total;
-    size_t fwd_bytes, adj_bytes, copy_bytes;  // one array of nshot (x9) descriptors
+    size_t fwd0, fwd_slot, sa_slot, vb_slot, va, sb, inj, save_copy, rest_copy, total;
+    size_t fwd_bytes, inj_bytes, copy_bytes;
     int k, nseg;
 };
 
@@ -864,15 +940,23 @@ template <typename T> BatchGradLayout make_batch_grad_layout(const fd3d_batch *b
     L.k = k;
     L.nseg = (b->nt + k - 1) / k;
     L.fwd_bytes = round_up((size_t)b->nshot * sizeof(ShotFwd<T>), kAlign);
-    L.adj_bytes = round_up((size_t)b->nshot * sizeof(ShotAdj<T>), kAlign);
+    L.inj_bytes = round_up((size_t)b->nshot * sizeof(ShotInject<T>), kAlign);
     L.copy_bytes = round_up((size_t)b->nshot * 9 * sizeof(CopyDesc<T>), kAlign);
     size_t off = 0;
     L.fwd0 = off;
     off += L.fwd_bytes;
     L.fwd_slot = off;
     off += (size_t)k * L.fwd_bytes;
-    L.adj_slot = off;
-    off += (size_t)k * L.adj_bytes;
+    L.sa_slot = off;
+    off += (size_t)k * L.fwd_bytes;
+    L.vb_slot = off;
+    off += (size_t)k * L.fwd_bytes;
+    L.va = off;
+    off += L.fwd_bytes;
+    L.sb = off;
+    off += L.fwd_bytes;
+    L.inj = off;
+    off += L.inj_bytes;
     L.save_copy = off;
     off += (size_t)L.nseg * L.copy_bytes;
     L.rest_copy = off;
@@ -894,8 +978,9 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     std::vector<GradLayout> GL(S);
     std::vector<ShotFwd<T>> fw(S);
     std::vector<ShotRec<T>> rr(S);
-    std::vector<ShotAdj<T>> ad(S);
-    int tiles = 0, recs = 0, blocks = 0, ncol = 0;
+    std::vector<ShotInject<T>> ij(S);
+    std::vector<AdjGrid<T>> ag(S);
+    int tiles = 0, recs = 0, ncol = 0;
     int cbase[kMaxBatchColors] = {0, 0, 0, 0};
     for (int s = 0; s < S; ++s) {
         fd3d_ctx *c = b->ctx[s];
@@ -917,6 +1002,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         ncol = std::max(ncol, cols);
         GL[s] = make_grad_layout(c, k);
         fw[s].G = make_grid<T>(c);
+        std::memset(&fw[s].io, 0, sizeof fw[s].io);
         TileMap tm;
         tm.ntx = (c->n[0] + b->tile_x - 1) / b->tile_x;
         tm.nty = (c->n[1] + b->tile_y - 1) / b->tile_y;
@@ -932,14 +1018,9 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         rr[s].nrec = nr;
         rr[s].base = recs;
         recs += 3 * nr;
-        ShotAdj<T> &a = ad[s];
-        a.G = fw[s].G;
-        a.A = make_adj<T>((char *)gws[s], GL[s]);
-        a.src = fw[s].src;
-        a.nbx = (c->n[0] + 63) / 64;
-        a.nby = (c->n[1] + 3) / 4;
-        a.base = blocks;
-        blocks += a.nbx * a.nby * c->n[2];
+        ag[s] = make_adj<T>((char *)gws[s], GL[s]);
+        ShotInject<T> &a = ij[s];
+        for (int q = 0; q < 3; ++q) a.a[q] = ag[s].a[VX + q];
         a.taps = rr[s].taps;
         a.colors = (const int *)(c->ws + c->L.colors);
         a.res = (const T *)((char *)gws[s] + GL[s].res);
@@ -956,19 +1037,40 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     }
     b->grad_host.assign(BL.total, 0);
     unsigned char *h = b->grad_host.data();
-    std::memcpy(h + BL.fwd0, fw.data(), S * sizeof(ShotFwd<T>));
+    const size_t fbytes = S * sizeof(ShotFwd<T>);
+    std::memcpy(h + BL.fwd0, fw.data(), fbytes);
+    // descriptors of one adjoint pass: the shot's tile map and sources, the pass's grid and outputs
+    auto adj_desc = [&](int s, const AdjTiles<T> &P, int p, bool with_src) {
+        ShotFwd<T> d = fw[s];
+        d.G = P.g[p];
+        d.io = P.io[p];
+        if (!with_src) {
+            std::memset(&d.src, 0, sizeof d.src);
+            for (int f = 0; f < NFIELD; ++f) d.src.i0[f] = d.src.j0[f] = d.src.k0[f] = -(1 << 28);
+        }
+        return d;
+    };
+    std::vector<ShotFwd<T>> va(S), sb(S);
     for (int m = 0; m < k; ++m) {
-        std::vector<ShotFwd<T>> f2 = fw;
-        std::vector<ShotAdj<T>> a2 = ad;
+        std::vector<ShotFwd<T>> f2 = fw, sa(S), vb(S);
         for (int s = 0; s < S; ++s) {
             char *slot = (char *)gws[s] + GL[s].seg + (size_t)m * 9 * GL[s].stride;
             for (int f = 0; f < NFIELD; ++f) f2[s].G.save[f] = (T *)(slot + f * GL[s].stride);
-            for (int q = 0; q < 3; ++q) a2[s].A.vst[q] = (const T *)(slot + q * GL[s].stride);
-            for (int q = 0; q < 6; ++q) a2[s].A.sst[q] = (const T *)(slot + (3 + q) * GL[s].stride);
+            const AdjTiles<T> P = adj_tiles<T>(fw[s].G, (char *)gws[s], GL[s], slot);
+            sa[s] = adj_desc(s, P, 0, false);
+            vb[s] = adj_desc(s, P, 2, true);
+            if (m == 0) {
+                va[s] = adj_desc(s, P, 1, false);
+                sb[s] = adj_desc(s, P, 3, false);
+            }
         }
-        std::memcpy(h + BL.fwd_slot + m * BL.fwd_bytes, f2.data(), S * sizeof(ShotFwd<T>));
-        std::memcpy(h + BL.adj_slot + m * BL.adj_bytes, a2.data(), S * sizeof(ShotAdj<T>));
+        std::memcpy(h + BL.fwd_slot + m * BL.fwd_bytes, f2.data(), fbytes);
+        std::memcpy(h + BL.sa_slot + m * BL.fwd_bytes, sa.data(), fbytes);
+        std::memcpy(h + BL.vb_slot + m * BL.fwd_bytes, vb.data(), fbytes);
     }
+    std::memcpy(h + BL.va, va.data(), fbytes);
+    std::memcpy(h + BL.sb, sb.data(), fbytes);
+    std::memcpy(h + BL.inj, ij.data(), S * sizeof(ShotInject<T>));
     for (int cidx = 0; cidx < BL.nseg; ++cidx) {
         std::vector<CopyDesc<T>> sv(S * 9), rs(S * 9);
         for (int s = 0; s < S; ++s) {
@@ -999,20 +1101,21 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     b->wgs = wgs;
 
     // forward with checkpoints
-    const ShotFwd<T> *fwd0 = (const ShotFwd<T> *)(bws + BL.fwd0);
+    auto desc = [&](size_t off) { return (const ShotFwd<T> *)(bws + off); };
     const ShotRec<T> *rdesc = (const ShotRec<T> *)(b->ws + b->off_rec);
+    const ShotInject<T> *idesc = (const ShotInject<T> *)(bws + BL.inj);
     const dim3 cgrid(256, 9 * S);
     if (!(flags & FD3D_KEEP_STATE))
         for (fd3d_ctx *c : b->ctx) zero_fields<T>(c, st);
-    auto fpass = [&](const ShotFwd<T> *d, int n, int pass) { multi_pass<T, false>(b, d, n, pass, st); };
+    auto pass = [&](const ShotFwd<T> *d, int n, int p) { multi_pass<T, false>(b, d, n, p, st); };
     for (int n = 0; n < b->nt; ++n) {
         if (n % k == 0)
             copy_multi<T><<<cgrid, 256, 0, st>>>((const CopyDesc<T> *)(bws + BL.save_copy + (n / k) * BL.copy_bytes));
-        fpass(fwd0, n, 0);
+        pass(desc(BL.fwd0), n, kPassVel);
         record_multi<T><<<(recs + 255) / 256, 256, 0, st>>>(rdesc, S, recs, b->nt, n);
-        fpass(fwd0, n, 1);
+        pass(desc(BL.fwd0), n, kPassStress);
     }
-    // residuals and misfits, zeroed adjoint state and accumulators
+    // residuals and misfits, zeroed adjoint state, accumulators and segment slots
     for (int s = 0; s < S; ++s) {
         fd3d_ctx *c = b->ctx[s];
         const long nn = (long)nrec[s] * 3 * b->nt;
@@ -1021,30 +1124,32 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         residual_misfit<T><<<kReduceBlocks, 256, 0, st>>>((const T *)traces[s], (const T *)d_obs[s], res, nn, part);
         misfit_final<T><<<1, 64, 0, st>>>(part, kReduceBlocks,
                                           misfit && misfit[s] ? (T *)misfit[s] : (T *)((char *)gws[s] + GL[s].misfit));
-        fill_zero<T><<<2048, 256, 0, st>>>((T *)((char *)gws[s] + GL[s].adj), (long)(17 * GL[s].stride / sizeof(T)));
+        zero_grad_fields<T>((char *)gws[s], GL[s], st);
     }
     // reverse sweep over the segments
     for (int sg = BL.nseg - 1; sg >= 0; --sg) {
         const int n0 = sg * k, n1 = std::min(n0 + k, b->nt);
         copy_multi<T><<<cgrid, 256, 0, st>>>((const CopyDesc<T> *)(bws + BL.rest_copy + sg * BL.copy_bytes));
         for (int n = n0; n < n1; ++n) {
-            const ShotFwd<T> *d = (const ShotFwd<T> *)(bws + BL.fwd_slot + (n - n0) * BL.fwd_bytes);
-            fpass(d, n, 0);
-            fpass(d, n, 1);
+            const ShotFwd<T> *d = desc(BL.fwd_slot + (n - n0) * BL.fwd_bytes);
+            pass(d, n, kPassVel);
+            pass(d, n, kPassStress);
         }
         for (int n = n1 - 1; n >= n0; --n) {
-            const ShotAdj<T> *d = (const ShotAdj<T> *)(bws + BL.adj_slot + (n - n0) * BL.adj_bytes);
-            adj_stress_multi<T><<<blocks, 256, 0, st>>>(d, S);
+            pass(desc(BL.sa_slot + (n - n0) * BL.fwd_bytes), n, kPassStressA);
+            pass(desc(BL.va), n, kPassVelA);
             for (int q = 0; q < ncol; ++q)
-                if (cbase[q] > 0) inject_residual_multi<T><<<(cbase[q] + 255) / 256, 256, 0, st>>>(d, S, q, cbase[q], b->nt, n);
-            adj_vel_multi<T><<<blocks, 256, 0, st>>>(d, S, n);
+                if (cbase[q] > 0)
+                    inject_residual_multi<T><<<(cbase[q] + 255) / 256, 256, 0, st>>>(idesc, S, q, cbase[q], b->nt, n);
+            pass(desc(BL.vb_slot + (n - n0) * BL.fwd_bytes), n, kPassVelB);
+            pass(desc(BL.sb), n, kPassStressB);
         }
     }
     // chain rule per shot, in shot order (shots may share the output arrays)
     for (int s = 0; s < S; ++s) {
         fd3d_ctx *c = b->ctx[s];
         const dim3 blk(64, 4, 1), grd((c->n[0] + 63) / 64, (c->n[1] + 3) / 4, c->n[2]);
-        grad_finalize<T><<<grd, blk, 0, st>>>(fw[s].G, ad[s].A, (T *)g_lam[s], (T *)g_mu[s], (T *)g_rho[s]);
+        grad_finalize<T><<<grd, blk, 0, st>>>(fw[s].G, ag[s], (T *)g_lam[s], (T *)g_mu[s], (T *)g_rho[s]);
         c->grad_ws = (const char *)gws[s];
         c->grad_k = k;
         c->grad_ready = 1;
@@ -1312,7 +1417,8 @@ int fd3d_get_kernel(const fd3d_ctx *ctx, fd3d_kernel *k)
 
 int fd3d_batch_workspace_bytes(int nshot, fd3d_ctx *const *ctxs, size_t *bytes)
 {
-    if (nshot < 1 || !ctxs || !bytes) return fail(FD3D_EINVAL, "nshot/ctxs/bytes");
+    if (nshot < 1 || nshot > kMaxShots || !ctxs || !bytes)
+        return fail(FD3D_EINVAL, "nshot must be in [1, " + std::to_string(kMaxShots) + "]");
     if (!ctxs[0]) return fail(FD3D_EINVAL, "context 0 is NULL");
     *bytes = batch_desc_bytes(nshot, ctxs[0]->tsize);
     return FD3D_OK;
@@ -1428,6 +1534,66 @@ void fd3d_batch_destroy(fd3d_batch *b)
     (void)hipStreamDestroy(b->cap);
     (void)hipEventDestroy(b->staged);
     delete b;
+}
+
+int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, void *hip_stream)
+{
+    if (!ctx) return fail(FD3D_EINVAL, "ctx is NULL");
+    if (steps < 1) return fail(FD3D_EINVAL, "steps must be >= 1");
+    hipStream_t st = (hipStream_t)hip_stream;
+    static const int shapes[][2] = {{64, 4}, {64, 8}, {64, 16}, {128, 4}, {128, 8}, {256, 4}};
+    static const int chunks[] = {16, 32, 64, 128};
+    const int nt_save = ctx->nt;
+    const fd3d_kernel keep = {ctx->variant, ctx->tile_x, ctx->tile_y, ctx->zchunk};
+    fd3d_kernel win = keep;
+    double win_ms = 1e300;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(FD3D_EHIP, "hipEventCreate failed");
+    ctx->nt = steps;
+    int rc = FD3D_OK;
+    for (const auto &sh : shapes) {
+        if (!tile_supported(ctx->tsize, sh[0], sh[1])) continue;
+        if (sh[0] > 64 && ctx->n[0] < sh[0] / 2) continue;  // mostly idle lanes
+        for (int zc : chunks) {
+            if (zc > ctx->n[2] && zc != chunks[0]) continue;
+            ctx->variant = FD3D_KERNEL_TILE;
+            ctx->tile_x = sh[0];
+            ctx->tile_y = sh[1];
+            ctx->zchunk = zc;
+            // one warm-up run, one timed run, both from the current (clobbered) state
+            for (int rep = 0; rep < 2 && !rc; ++rep) {
+                if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(FD3D_EHIP, "hipEventRecord");
+                if (!rc) rc = ctx->tsize == 8 ? forward_impl<double>(ctx, nullptr, 0, nullptr, nullptr, FD3D_KEEP_STATE, st)
+                                             : forward_impl<float>(ctx, nullptr, 0, nullptr, nullptr, FD3D_KEEP_STATE, st);
+            }
+            if (rc) break;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(FD3D_EHIP, "timing events failed");
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < win_ms) {
+                win_ms = ms;
+                win = fd3d_kernel{FD3D_KERNEL_TILE, sh[0], sh[1], zc};
+            }
+        }
+        if (rc) break;
+    }
+    ctx->nt = nt_save;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const fd3d_kernel &use = rc ? keep : win;
+    ctx->variant = use.variant;
+    ctx->tile_x = use.tile_x;
+    ctx->tile_y = use.tile_y;
+    ctx->zchunk = use.zchunk;
+    if (rc) return rc;
+    zero_fields_any(ctx, st);
+    if (best) *best = win;
+    if (best_ms) *best_ms = win_ms / steps;
+    return FD3D_OK;
 }
 
 int fd3d_profile(fd3d_ctx *ctx, int enable)

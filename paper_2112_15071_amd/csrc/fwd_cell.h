@@ -184,10 +184,13 @@ template <typename T>
 __global__ void __launch_bounds__(256) record_multi(const ShotRec<T> *__restrict__ shots, int nshot, int total, int nt,
                                                     int n)
 {
+    __shared__ int s_base[kMaxShots];
+    for (int t = threadIdx.x; t < nshot; t += blockDim.x) s_base[t] = shots[t].base;
+    __syncthreads();
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= total) return;
     int s = 0;
-    while (s + 1 < nshot && shots[s + 1].base <= q) ++s;
+    while (s + 1 < nshot && s_base[s + 1] <= q) ++s;
     const ShotRec<T> &d = shots[s];
     const int l = q - d.base;
     const int c = l % 3;

@@ -140,6 +140,19 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
     k1 = min(k0 + tm.zc, nz);
 }
 
+// What a tile body computes.  kFwd: the forward pass.  For the velocity-type body,
+// kAdjA: A_v <- G_v A_v - dt D_S(X) (X = C G_s A_s, precomputed) and kAdjB:
+// g_b += dt D_S(sigma^n) U + force term, Y = U / rho_eff (U = G_v A_v).  For the
+// stress-type body, kAdjA: gradients of C from E(v^{n+1/2}) and T = G_s A_s, X = C T;
+// kAdjB: A_s <- G_s A_s - dt E(Y).  The adjoint modes read and write the arrays named
+// by the grid (f[] pointing at the adjoint, stored or scratch fields) and by TileIO.
+enum { kFwd = 0, kAdjA = 1, kAdjB = 2 };
+
+template <typename T> struct TileIO {
+    T *out[6];  // X (6) or Y (3) scratch
+    T *acc[5];  // gradient accumulators: (gl, gm, g_mu_xy, g_mu_xz, g_mu_yz) or (g_bx, g_by, g_bz)
+};
+
 // Coefficient of tap t (or 0) without a data-dependent memory access.
 template <typename T> __device__ __forceinline__ T pick(const T (&c)[8], int t)
 {
@@ -151,9 +164,9 @@ template <typename T> __device__ __forceinline__ T pick(const T (&c)[8], int t)
 
 // ---------------------------------------------------------------------------------
 // (V) velocity pass, tiled.  Same arithmetic per sample as vel_cell.
-template <typename T, int TX, int TY, bool FS>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
 __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0, int k0,
-                                              int k1)
+                                              int k1, const TileIO<T> &io = TileIO<T>{})
 {
     constexpr int NT = TX * TY;
     // LDS plane shapes: sxx x(-1,+2); sxy x(-2,+1) y(-2,+1); sxz x(-2,+1); syy y(-1,+2);
@@ -198,7 +211,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     const T gyh = in ? G.g[1][1][j] : T(0), gyi = in ? G.g[1][0][j] : T(0);
     const unsigned st_vx = (in && i <= nx - 2) ? oc : kOOB;
     const unsigned st_vy = (in && j <= ny - 2) ? oc : kOOB;
-    const bool save = G.save[VX] != nullptr;
+    const bool save = MODE == kFwd && G.save[VX] != nullptr;
+    constexpr bool use_rho = MODE != kAdjA;
 
     auto zld = [&](const T *f, int kk, bool ok) -> T { return ld<T>(plane(f, kk, sz, ok && kk >= 0 && kk < nz), oc); };
 
@@ -217,15 +231,21 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         const int kz = k0 - 1 + m;
         qzz[m] = (FS && kz < 0) ? -zld(fzz, -kz, true) : zld(fzz, kz, true);
     }
-    T r0 = zld(rho, k0, true), r1 = zld(rho, k0 + 1, true);
+    T r0 = zld(rho, k0, use_rho), r1 = zld(rho, k0 + 1, use_rho);
 
     // plane registers, loaded one plane ahead
     struct Plane {
-        T cxx, cyy, cxy, vx, vy, vz, xx, xyx, xz, yy, xyy, yz, rx, ry, rc;
+        T cxx, cyy, cxy, vx, vy, vz, xx, xyx, xz, yy, xyy, yz, rx, ry, rc, g0, g1, g2;
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const rsrc_t bxx = plane(fxx, kk, sz, ok), byy = plane(fyy, kk, sz, ok), bxy = plane(fxy, kk, sz, ok);
-        const rsrc_t bxz = plane(fxz, kk, sz, ok), byz = plane(fyz, kk, sz, ok), br = plane(rho, kk, sz, ok);
+        const rsrc_t bxz = plane(fxz, kk, sz, ok), byz = plane(fyz, kk, sz, ok);
+        const rsrc_t br = plane(rho, kk, sz, ok && use_rho);
+        if constexpr (MODE == kAdjB) {
+            P.g0 = ld<T>(plane(io.acc[0], kk, sz, ok), oc);
+            P.g1 = ld<T>(plane(io.acc[1], kk, sz, ok), oc);
+            P.g2 = ld<T>(plane(io.acc[2], kk, sz, ok), oc);
+        }
         P.cxx = ld<T>(bxx, oc);
         P.cyy = ld<T>(byy, oc);
         P.cxy = ld<T>(bxy, oc);
@@ -265,11 +285,12 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         Lr[hry.lds] = P.ry;
         Lr[hrc.lds] = P.rc;
         const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
+        const T ga0 = P.g0, ga1 = P.g1, ga2 = P.g2;
         // loads of plane k+1 and the queue heads (empty descriptors past the chunk)
         const bool more = k + 1 < k1;
         loadplane(k + 1, more, P);
         const T nxz = zld(fxz, k + 2, more), nyz = zld(fyz, k + 2, more);
-        const T nzz = zld(fzz, k + 3, more), nr = zld(rho, k + 2, more);
+        const T nzz = zld(fzz, k + 3, more), nr = zld(rho, k + 2, more && use_rho);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         __syncthreads();
 
@@ -281,12 +302,22 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const T d = dstag(Lxx[o + 1], Lxx[o], Lxx[o + 2], Lxx[o - 1], rdx)
                       + dstag(Lxy[ox], Lxy[ox - W3], Lxy[ox + W3], Lxy[ox - 2 * W3], rdx)
                       + dstag(qxz[2], qxz[1], qxz[3], qxz[0], rdx);
-            const T bb = T(1) / ((r0 + Lr[ty * WR + tx + 1]) / T(2));
-            T v = vx0 + dt * bb * d;
-            v += bb * pick(src.c[VX], tap_of(src, VX, i, j, k)) * s;
-            v = v * (gxh * gyi * gz_i);
-            st(ovx, st_vx, v);
-            st(plane(G.save[VX], k, sz, save), st_vx, v);
+            if constexpr (MODE == kFwd) {
+                const T bb = T(1) / ((r0 + Lr[ty * WR + tx + 1]) / T(2));
+                T v = vx0 + dt * bb * d;
+                v += bb * pick(src.c[VX], tap_of(src, VX, i, j, k)) * s;
+                v = v * (gxh * gyi * gz_i);
+                st(ovx, st_vx, v);
+                st(plane(G.save[VX], k, sz, save), st_vx, v);
+            } else if constexpr (MODE == kAdjA) {
+                st(ovx, st_vx, (gxh * gyi * gz_i) * vx0 - dt * d);
+            } else {
+                const T u = (gxh * gyi * gz_i) * vx0;
+                T g = dt * d * u;
+                g += pick(src.c[VX], tap_of(src, VX, i, j, k)) * s * u;
+                st(plane(io.acc[0], k, sz, true), st_vx, ga0 + g);
+                st(plane(io.out[0], k, sz, true), st_vx, u / ((r0 + Lr[ty * WR + tx + 1]) / T(2)));
+            }
         }
         {
             const int ox = (ty + 2) * W3 + tx + 2;
@@ -294,12 +325,22 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const T d = dstag(Lxy[ox], Lxy[ox - 1], Lxy[ox + 1], Lxy[ox - 2], rdx)
                       + dstag(Lyy[oy + TX], Lyy[oy], Lyy[oy + 2 * TX], Lyy[oy - TX], rdx)
                       + dstag(qyz[2], qyz[1], qyz[3], qyz[0], rdx);
-            const T bb = T(1) / ((r0 + Lr[(ty + 1) * WR + tx]) / T(2));
-            T v = vy0 + dt * bb * d;
-            v += bb * pick(src.c[VY], tap_of(src, VY, i, j, k)) * s;
-            v = v * (gxi * gyh * gz_i);
-            st(ovy, st_vy, v);
-            st(plane(G.save[VY], k, sz, save), st_vy, v);
+            if constexpr (MODE == kFwd) {
+                const T bb = T(1) / ((r0 + Lr[(ty + 1) * WR + tx]) / T(2));
+                T v = vy0 + dt * bb * d;
+                v += bb * pick(src.c[VY], tap_of(src, VY, i, j, k)) * s;
+                v = v * (gxi * gyh * gz_i);
+                st(ovy, st_vy, v);
+                st(plane(G.save[VY], k, sz, save), st_vy, v);
+            } else if constexpr (MODE == kAdjA) {
+                st(ovy, st_vy, (gxi * gyh * gz_i) * vy0 - dt * d);
+            } else {
+                const T u = (gxi * gyh * gz_i) * vy0;
+                T g = dt * d * u;
+                g += pick(src.c[VY], tap_of(src, VY, i, j, k)) * s * u;
+                st(plane(io.acc[1], k, sz, true), st_vy, ga1 + g);
+                st(plane(io.out[1], k, sz, true), st_vy, u / ((r0 + Lr[(ty + 1) * WR + tx]) / T(2)));
+            }
         }
         {
             const int o = own_c3 + tx + 2;
@@ -307,12 +348,23 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const T d = dstag(Lxz[o], Lxz[o - 1], Lxz[o + 1], Lxz[o - 2], rdx)
                       + dstag(Lyz[oy], Lyz[oy - TX], Lyz[oy + TX], Lyz[oy - 2 * TX], rdx)
                       + dstag(qzz[2], qzz[1], qzz[3], qzz[0], rdx);
-            const T bb = T(1) / ((r0 + r1) / T(2));
-            T v = vz0 + dt * bb * d;
-            v += bb * pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s;
-            v = v * (gxi * gyi * gz_h);
-            st(ovz, k <= nz - 2 ? oc : kOOB, v);
-            st(plane(G.save[VZ], k, sz, save), k <= nz - 2 ? oc : kOOB, v);
+            const unsigned st_vz = k <= nz - 2 ? oc : kOOB;
+            if constexpr (MODE == kFwd) {
+                const T bb = T(1) / ((r0 + r1) / T(2));
+                T v = vz0 + dt * bb * d;
+                v += bb * pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s;
+                v = v * (gxi * gyi * gz_h);
+                st(ovz, st_vz, v);
+                st(plane(G.save[VZ], k, sz, save), st_vz, v);
+            } else if constexpr (MODE == kAdjA) {
+                st(ovz, st_vz, (gxi * gyi * gz_h) * vz0 - dt * d);
+            } else {
+                const T u = (gxi * gyi * gz_h) * vz0;
+                T g = dt * d * u;
+                g += pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s * u;
+                st(plane(io.acc[2], k, sz, true), st_vz, ga2 + g);
+                st(plane(io.out[2], k, sz, true), st_vz, u / ((r0 + r1) / T(2)));
+            }
         }
         qxz[0] = qxz[1]; qxz[1] = qxz[2]; qxz[2] = qxz[3]; qxz[3] = nxz;
         qyz[0] = qyz[1]; qyz[1] = qyz[2]; qyz[2] = qyz[3]; qyz[3] = nyz;
@@ -323,9 +375,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 
 // ---------------------------------------------------------------------------------
 // (S) stress pass, tiled.  Same arithmetic per sample as stress_cell.
-template <typename T, int TX, int TY, bool FS>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
 __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0,
-                                                 int k0, int k1)
+                                                 int k0, int k1, const TileIO<T> &io = TileIO<T>{})
 {
     constexpr int NT = TX * TY;
     // vx x(-2,+1) y(-1,+2); vy x(-1,+2) y(-2,+1); vz x(-1,+2) y(-1,+2); mu x(+1) y(+1) corner
@@ -370,7 +422,8 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     const unsigned st_xy = (in && i <= nx - 2 && j <= ny - 2) ? oc : kOOB;
     const unsigned st_xz = (in && i <= nx - 2) ? oc : kOOB;
     const unsigned st_yz = (in && j <= ny - 2) ? oc : kOOB;
-    const bool save = G.save[SXX] != nullptr;
+    const bool save = MODE == kFwd && G.save[SXX] != nullptr;
+    constexpr bool use_model = MODE != kAdjB;
 
     auto zld = [&](const T *f, int kk, bool ok) -> T { return ld<T>(plane(f, kk, sz, ok && kk >= 0 && kk < nz), oc); };
 
@@ -382,15 +435,22 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         qvy[m] = zld(fvy, k0 - 1 + m, true);
         qvz[m] = zld(fvz, k0 - 2 + m, true);
     }
-    T m1 = zld(mu, k0 + 1, true);  // own mu one plane below
+    T m1 = zld(mu, k0 + 1, use_model);  // own mu one plane below
 
     struct Plane {
-        T cl, cm, sxx, syy, szz, sxy, sxz, syz, vxx, vxy, vyx, vyy, vzx, vzy;
+        T cl, cm, sxx, syy, szz, sxy, sxz, syz, vxx, vxy, vyx, vyy, vzx, vzy, a0, a1, a2, a3, a4;
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const rsrc_t bx = plane(fvx, kk, sz, ok), by = plane(fvy, kk, sz, ok), bz = plane(fvz, kk, sz, ok);
-        P.cl = ld<T>(plane(lam, kk, sz, ok), oc);
-        P.cm = ld<T>(plane(mu, kk, sz, ok), oc);
+        P.cl = ld<T>(plane(lam, kk, sz, ok && use_model), oc);
+        P.cm = ld<T>(plane(mu, kk, sz, ok && use_model), oc);
+        if constexpr (MODE == kAdjA) {
+            P.a0 = ld<T>(plane(io.acc[0], kk, sz, ok), oc);
+            P.a1 = ld<T>(plane(io.acc[1], kk, sz, ok), oc);
+            P.a2 = ld<T>(plane(io.acc[2], kk, sz, ok), oc);
+            P.a3 = ld<T>(plane(io.acc[3], kk, sz, ok), oc);
+            P.a4 = ld<T>(plane(io.acc[4], kk, sz, ok), oc);
+        }
         P.sxx = ld<T>(plane(G.f[SXX], kk, sz, ok), oc);
         P.syy = ld<T>(plane(G.f[SYY], kk, sz, ok), oc);
         P.szz = ld<T>(plane(G.f[SZZ], kk, sz, ok), oc);
@@ -408,7 +468,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         T x, y, c;
     };
     auto loadmu = [&](int kk, bool ok, MuHalo &H) {
-        const rsrc_t bm = plane(mu, kk, sz, ok && kk < nz);
+        const rsrc_t bm = plane(mu, kk, sz, ok && kk < nz && use_model);
         H.x = ld<T>(bm, hmx.off);
         H.y = ld<T>(bm, hmy.off);
         H.c = ld<T>(bm, hmc.off);
@@ -446,61 +506,95 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         M1[hmc.lds] = H.c;
         const T l = P.cl, mm = P.cm;
         const T o_xx = P.sxx, o_yy = P.syy, o_zz = P.szz, o_xy = P.sxy, o_xz = P.sxz, o_yz = P.syz;
+        const T a0 = P.a0, a1 = P.a1, a2 = P.a2, a3 = P.a3, a4 = P.a4;
         const bool more = k + 1 < k1;
         loadplane(k + 1, more, P);
         const T nvx = zld(fvx, k + 3, more), nvy = zld(fvy, k + 3, more), nvz = zld(fvz, k + 2, more);
-        const T nm1 = zld(mu, k + 2, more);
+        const T nm1 = zld(mu, k + 2, more && use_model);
         loadmu(k + 2, more, H);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         __syncthreads();
 
-        st(plane(G.save[SXX], k, sz, save), oc, o_xx);
-        st(plane(G.save[SYY], k, sz, save), oc, o_yy);
-        st(plane(G.save[SZZ], k, sz, save), oc, o_zz);
-        st(plane(G.save[SXY], k, sz, save), oc, o_xy);
-        st(plane(G.save[SXZ], k, sz, save), oc, o_xz);
-        st(plane(G.save[SYZ], k, sz, save), oc, o_yz);
+        if constexpr (MODE == kFwd) {
+            st(plane(G.save[SXX], k, sz, save), oc, o_xx);
+            st(plane(G.save[SYY], k, sz, save), oc, o_yy);
+            st(plane(G.save[SZZ], k, sz, save), oc, o_zz);
+            st(plane(G.save[SXY], k, sz, save), oc, o_xy);
+            st(plane(G.save[SXZ], k, sz, save), oc, o_xz);
+            st(plane(G.save[SYZ], k, sz, save), oc, o_yz);
+        }
         const T exx = dstag(Lx[ovx], Lx[ovx - 1], Lx[ovx + 1], Lx[ovx - 2], rdx);
         const T eyy = dstag(Ly[ovy], Ly[ovy - W3], Ly[ovy + W3], Ly[ovy - 2 * W3], rdx);
         T ezz;
         if (FS && k == 0) ezz = -l / (l + T(2) * mm) * (exx + eyy);
         else if (FS && k == 1) ezz = (qvz[2] - qvz[1]) * rdx;
         else ezz = dstag(qvz[2], qvz[1], qvz[3], qvz[0], rdx);
-        const T tr = exx + eyy + ezz;
         const T gn = gxi * gyi * gz_i;
-        T nxx = o_xx + dt * (l * tr + T(2) * mm * exx);
-        T nyy = o_yy + dt * (l * tr + T(2) * mm * eyy);
-        T nzz = o_zz + dt * (l * tr + T(2) * mm * ezz);
-        const int t = tap_of(src, SXX, i, j, k);
-        nxx += pick(src.c[SXX], t) * s;
-        nyy += pick(src.c[SYY], t) * s;
-        nzz += pick(src.c[SZZ], t) * s;
-        st(plane(G.f[SXX], k, sz, true), oc, nxx * gn);
-        st(plane(G.f[SYY], k, sz, true), oc, nyy * gn);
-        st(plane(G.f[SZZ], k, sz, true), oc, (FS && k == 0) ? T(0) : nzz * gn);
-        {
-            const T e = dstag(Lx[ovx + W3], Lx[ovx], Lx[ovx + 2 * W3], Lx[ovx - W3], rdx)
-                      + dstag(Ly[ovy + 1], Ly[ovy], Ly[ovy + 2], Ly[ovy - 1], rdx);
+        const T exy = dstag(Lx[ovx + W3], Lx[ovx], Lx[ovx + 2 * W3], Lx[ovx - W3], rdx)
+                    + dstag(Ly[ovy + 1], Ly[ovy], Ly[ovy + 2], Ly[ovy - 1], rdx);
+        const T dzvx = (FS && k == 0) ? (qvx[2] - qvx[1]) * rdx : dstag(qvx[2], qvx[1], qvx[3], qvx[0], rdx);
+        const T exz = dzvx + dstag(Lz[ovz + 1], Lz[ovz], Lz[ovz + 2], Lz[ovz - 1], rdx);
+        const T dzvy = (FS && k == 0) ? (qvy[2] - qvy[1]) * rdx : dstag(qvy[2], qvy[1], qvy[3], qvy[0], rdx);
+        const T eyz = dzvy + dstag(Lz[ovz + W3], Lz[ovz], Lz[ovz + 2 * W3], Lz[ovz - W3], rdx);
+        const T g_xy = gxh * gyh * gz_i, g_xz = gxh * gyi * gz_h, g_yz = gxi * gyh * gz_h;
+        const unsigned o_stxz = k <= nz - 2 ? st_xz : kOOB, o_styz = k <= nz - 2 ? st_yz : kOOB;
+        if constexpr (MODE == kFwd) {
+            const T tr = exx + eyy + ezz;
+            T nxx = o_xx + dt * (l * tr + T(2) * mm * exx);
+            T nyy = o_yy + dt * (l * tr + T(2) * mm * eyy);
+            T nzz = o_zz + dt * (l * tr + T(2) * mm * ezz);
+            const int t = tap_of(src, SXX, i, j, k);
+            nxx += pick(src.c[SXX], t) * s;
+            nyy += pick(src.c[SYY], t) * s;
+            nzz += pick(src.c[SZZ], t) * s;
+            st(plane(G.f[SXX], k, sz, true), oc, nxx * gn);
+            st(plane(G.f[SYY], k, sz, true), oc, nyy * gn);
+            st(plane(G.f[SZZ], k, sz, true), oc, (FS && k == 0) ? T(0) : nzz * gn);
+            {
+                const T mxy = ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
+                T v = o_xy + dt * mxy * exy;
+                v += pick(src.c[SXY], tap_of(src, SXY, i, j, k)) * s;
+                st(plane(G.f[SXY], k, sz, true), st_xy, v * g_xy);
+            }
+            {
+                const T mxz = ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
+                T v = o_xz + dt * mxz * exz;
+                v += pick(src.c[SXZ], tap_of(src, SXZ, i, j, k)) * s;
+                st(plane(G.f[SXZ], k, sz, true), o_stxz, v * g_xz);
+            }
+            {
+                const T myz = ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);
+                T v = o_yz + dt * myz * eyz;
+                v += pick(src.c[SYZ], tap_of(src, SYZ, i, j, k)) * s;
+                st(plane(G.f[SYZ], k, sz, true), o_styz, v * g_yz);
+            }
+        } else if constexpr (MODE == kAdjA) {
+            // gradients of C and X = C T with T = G_s A_s
+            const T txx = gn * o_xx, tyy = gn * o_yy, tzz = gn * o_zz;
+            const T trT = (txx + tyy) + tzz;
+            st(plane(io.acc[0], k, sz, true), oc, a0 + dt * ((exx + eyy) + ezz) * trT);
+            st(plane(io.acc[1], k, sz, true), oc, a1 + dt * T(2) * ((exx * txx + eyy * tyy) + ezz * tzz));
+            st(plane(io.out[0], k, sz, true), oc, l * trT + T(2) * mm * txx);
+            st(plane(io.out[1], k, sz, true), oc, l * trT + T(2) * mm * tyy);
+            st(plane(io.out[2], k, sz, true), oc, l * trT + T(2) * mm * tzz);
+            const T txy = g_xy * o_xy, txz = g_xz * o_xz, tyz = g_yz * o_yz;
+            st(plane(io.acc[2], k, sz, true), st_xy, a2 + dt * exy * txy);
+            st(plane(io.acc[3], k, sz, true), o_stxz, a3 + dt * exz * txz);
+            st(plane(io.acc[4], k, sz, true), o_styz, a4 + dt * eyz * tyz);
             const T mxy = ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
-            T v = o_xy + dt * mxy * e;
-            v += pick(src.c[SXY], tap_of(src, SXY, i, j, k)) * s;
-            st(plane(G.f[SXY], k, sz, true), st_xy, v * (gxh * gyh * gz_i));
-        }
-        {
-            const T dzvx = (FS && k == 0) ? (qvx[2] - qvx[1]) * rdx : dstag(qvx[2], qvx[1], qvx[3], qvx[0], rdx);
-            const T e = dzvx + dstag(Lz[ovz + 1], Lz[ovz], Lz[ovz + 2], Lz[ovz - 1], rdx);
             const T mxz = ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
-            T v = o_xz + dt * mxz * e;
-            v += pick(src.c[SXZ], tap_of(src, SXZ, i, j, k)) * s;
-            st(plane(G.f[SXZ], k, sz, true), k <= nz - 2 ? st_xz : kOOB, v * (gxh * gyi * gz_h));
-        }
-        {
-            const T dzvy = (FS && k == 0) ? (qvy[2] - qvy[1]) * rdx : dstag(qvy[2], qvy[1], qvy[3], qvy[0], rdx);
-            const T e = dzvy + dstag(Lz[ovz + W3], Lz[ovz], Lz[ovz + 2 * W3], Lz[ovz - W3], rdx);
             const T myz = ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);
-            T v = o_yz + dt * myz * e;
-            v += pick(src.c[SYZ], tap_of(src, SYZ, i, j, k)) * s;
-            st(plane(G.f[SYZ], k, sz, true), k <= nz - 2 ? st_yz : kOOB, v * (gxi * gyh * gz_h));
+            st(plane(io.out[3], k, sz, true), st_xy, mxy * txy);
+            st(plane(io.out[4], k, sz, true), o_stxz, mxz * txz);
+            st(plane(io.out[5], k, sz, true), o_styz, myz * tyz);
+        } else {
+            // A_s <- G_s A_s - dt E(Y)
+            st(plane(G.f[SXX], k, sz, true), oc, gn * o_xx - dt * exx);
+            st(plane(G.f[SYY], k, sz, true), oc, gn * o_yy - dt * eyy);
+            st(plane(G.f[SZZ], k, sz, true), oc, gn * o_zz - dt * ezz);
+            st(plane(G.f[SXY], k, sz, true), st_xy, g_xy * o_xy - dt * exy);
+            st(plane(G.f[SXZ], k, sz, true), o_stxz, g_xz * o_xz - dt * exz);
+            st(plane(G.f[SYZ], k, sz, true), o_styz, g_yz * o_yz - dt * eyz);
         }
         qvx[0] = qvx[1]; qvx[1] = qvx[2]; qvx[2] = qvx[3]; qvx[3] = nvx;
         qvy[0] = qvy[1]; qvy[1] = qvy[2]; qvy[2] = qvy[3]; qvy[3] = nvy;
@@ -527,6 +621,23 @@ __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, 
     stress_tile_body<T, TX, TY, FS>(G, src, n, i0, j0, k0, k1);
 }
 
+// Adjoint passes, one workgroup per tile (no free surface).
+template <typename T, int TX, int TY, int MODE>
+__global__ void __launch_bounds__(TX *TY) vel_tile_adj(Grid<T> G, Inject<T> src, int n, TileMap tm, TileIO<T> io)
+{
+    int i0, j0, k0, k1;
+    tile_coords(tm, xcd_remap(blockIdx.x, gridDim.x), i0, j0, k0, k1, TX, TY, G.nz);
+    vel_tile_body<T, TX, TY, false, MODE>(G, src, n, i0, j0, k0, k1, io);
+}
+
+template <typename T, int TX, int TY, int MODE>
+__global__ void __launch_bounds__(TX *TY) stress_tile_adj(Grid<T> G, Inject<T> src, TileMap tm, TileIO<T> io)
+{
+    int i0, j0, k0, k1;
+    tile_coords(tm, xcd_remap(blockIdx.x, gridDim.x), i0, j0, k0, k1, TX, TY, G.nz);
+    stress_tile_body<T, TX, TY, false, MODE>(G, src, 0, i0, j0, k0, k1, io);
+}
+
 // ---------------------------------------------------------------------------------
 // Many grids in one persistent launch.  Every shot contributes its tiles to one flat
 // work list (shot-major); the list is cut into 8 contiguous chunks, one per XCD, and
@@ -535,6 +646,7 @@ __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, 
 template <typename T> struct ShotFwd {
     Grid<T> G;
     Inject<T> src;
+    TileIO<T> io;
     TileMap tm;
     int base;  // first work item of this shot
     int pad;
@@ -551,48 +663,49 @@ __device__ __forceinline__ void work_range(int total, int &w0, int &hi, int &str
     stride = per;
 }
 
-template <typename T>
-__device__ __forceinline__ int find_shot(const ShotFwd<T> *__restrict__ shots, int nshot, int w)
-{
-    int s = 0;
-    while (s + 1 < nshot && shots[s + 1].base <= w) ++s;
-    return s;
-}
+// Stride in ints between the .base members of consecutive descriptors.
+template <typename D> constexpr int base_stride() { return (int)(sizeof(D) / sizeof(int)); }
 
-template <typename T, int TX, int TY, bool FS>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
 __global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
                                                           int n)
 {
+    __shared__ int s_base[kMaxShots];
+    load_bases(s_base, &shots[0].base, base_stride<ShotFwd<T>>(), nshot);
     int w, hi, stride;
     work_range(total, w, hi, stride);
     for (; w < hi; w += stride) {
-        const int s = find_shot(shots, nshot, w);
+        const int s = shot_of(s_base, nshot, w);
         const ShotFwd<T> &d = shots[s];
         const Grid<T> G = d.G;
         const Inject<T> src = d.src;
         const TileMap tm = d.tm;
         int i0, j0, k0, k1;
         tile_coords(tm, w - d.base, i0, j0, k0, k1, TX, TY, G.nz);
-        vel_tile_body<T, TX, TY, FS>(G, src, n, i0, j0, k0, k1);
+        const TileIO<T> io = d.io;
+        vel_tile_body<T, TX, TY, FS, MODE>(G, src, n, i0, j0, k0, k1, io);
         __syncthreads();
     }
 }
 
-template <typename T, int TX, int TY, bool FS>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
 __global__ void __launch_bounds__(TX *TY) stress_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
                                                           int n)
 {
+    __shared__ int s_base[kMaxShots];
+    load_bases(s_base, &shots[0].base, base_stride<ShotFwd<T>>(), nshot);
     int w, hi, stride;
     work_range(total, w, hi, stride);
     for (; w < hi; w += stride) {
-        const int s = find_shot(shots, nshot, w);
+        const int s = shot_of(s_base, nshot, w);
         const ShotFwd<T> &d = shots[s];
         const Grid<T> G = d.G;
         const Inject<T> src = d.src;
         const TileMap tm = d.tm;
         int i0, j0, k0, k1;
         tile_coords(tm, w - d.base, i0, j0, k0, k1, TX, TY, G.nz);
-        stress_tile_body<T, TX, TY, FS>(G, src, n, i0, j0, k0, k1);
+        const TileIO<T> io = d.io;
+        stress_tile_body<T, TX, TY, FS, MODE>(G, src, n, i0, j0, k0, k1, io);
         __syncthreads();
     }
 }

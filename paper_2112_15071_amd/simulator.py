@@ -10,6 +10,9 @@ from __future__ import annotations
 
 from typing import Optional, Sequence
 
+import json
+import os
+
 import numpy as np
 import torch
 
@@ -111,6 +114,39 @@ class Simulator:
         k = _abi.fd3d_get_kernel(self._ctx)
         return {"variant": "cell" if k.variant == _abi.FD3D_KERNEL_CELL else "tile", "tile_x": k.tile_x,
                 "tile_y": k.tile_y, "zchunk": k.zchunk}
+
+    def autotune(self, steps: int = 20, cache: bool = True) -> dict:
+        """Pick the fastest tile shape and z chunk for this grid (fd3d_autotune), with a
+        JSON cache keyed by grid shape, dtype, free surface and device name
+        ($FD3D_AUTOTUNE_CACHE, default ~/.cache/fd3d/autotune.json).  Zeroes the state."""
+        nx, ny, nz = self.shape
+        dev = torch.cuda.get_device_name(self.device)
+        key = f"{nx}x{ny}x{nz}/{str(self.dtype)}/fs{int(self.opts.free_surface)}/{dev}"
+        path = os.environ.get("FD3D_AUTOTUNE_CACHE", os.path.expanduser("~/.cache/fd3d/autotune.json"))
+        table = {}
+        if cache and os.path.exists(path):
+            try:
+                with open(path) as f:
+                    table = json.load(f)
+            except (OSError, ValueError):
+                table = {}
+        if cache and key in table:
+            e = table[key]
+            self.set_kernel("tile", e["tile_y"], e["zchunk"], e["tile_x"])
+            return dict(e, cached=True)
+        k, ms = _abi.fd3d_autotune(self._ctx, steps, _stream())
+        e = {"tile_x": k.tile_x, "tile_y": k.tile_y, "zchunk": k.zchunk, "ms_per_step": ms}
+        if cache:
+            table[key] = e
+            try:
+                os.makedirs(os.path.dirname(path), exist_ok=True)
+                tmp = path + f".{os.getpid()}.tmp"
+                with open(tmp, "w") as f:
+                    json.dump(table, f, indent=1, sort_keys=True)
+                os.replace(tmp, path)
+            except OSError:
+                pass
+        return dict(e, cached=False)
 
     def info(self):
         """(vp_max, vs_min, rho_min, dt_max) read back at creation."""
