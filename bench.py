@@ -57,7 +57,29 @@ def shot_desc(s):
     return dict(src_pos=s.src_pos, moment=s.moment, force=s.force, wavelet=s.wavelet, rec_pos=s.rec_pos)
 
 
-def bench_forward(K, Wm):
+def measured_traffic(kern, dom):
+    """HBM bytes per launch of the dominant forward kernel from the committed counter
+    table (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated), or None when the table
+    has no entry for this kernel configuration or the kernel sources changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "forward_tile_hbm_traffic.json")
+    try:
+        with open(path) as f:
+            table = json.load(f)
+        h = hashlib.sha256()
+        for src in table["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != table["sources_sha256"]:
+            return None
+        key = f"{kern['variant']},{kern['tile_x']},{kern['tile_y']},{kern['zchunk']}"
+        return table["kernels"][key][dom]["hbm_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def bench_forward(K, Wm, kernel=None):
     import torch
 
     import workloads as W
@@ -72,8 +94,13 @@ def bench_forward(K, Wm):
     wav = torch.as_tensor(shot.wavelet, dtype=torch.float32).to(dev)
     kw = dict(dtype=torch.float32, sponge=shot.sponge, device=dev)
     sim = Simulator(lam, mu, rho, shot.h, shot.dt, K, **kw)
-    tune = sim.autotune(steps=20)
-    log(f"[bench] kernel {sim.kernel()} (autotune {'cached' if tune['cached'] else 'run'})")
+    if kernel:
+        variant, tx, ty, zc = kernel.split(",")
+        sim.set_kernel(variant, int(ty), int(zc), int(tx))
+        log(f"[bench] kernel {sim.kernel()} (given)")
+    else:
+        tune = sim.autotune(steps=20)
+        log(f"[bench] kernel {sim.kernel()} (autotune {'cached' if tune['cached'] else 'run'})")
     if Wm > 0:
         warm = Simulator(lam, mu, rho, shot.h, shot.dt, Wm, **kw)
         k = sim.kernel()
@@ -105,7 +132,7 @@ def bench_forward(K, Wm):
     kern = sim.kernel()
     sim.close()
     return shot, dict(gcs=gcs, elapsed=elapsed, per=per, dom=dom, achieved=achieved, bytes_launch=bytes_launch,
-                      both=both, kernel=kern)
+                      both=both, kernel=kern, traffic=measured_traffic(kern, dom))
 
 
 def bench_batch():
@@ -144,10 +171,10 @@ def bench_batch():
         s.close()
     return dict(loop_gcs=round(cells_steps / t_loop / 1e9, 3), batched_gcs=round(cells_steps / t_graph / 1e9, 3),
                 loop_s=round(t_loop, 3), batched_s=round(t_graph, 3), speedup=round(t_loop / t_graph, 3),
-                tile=[tune["tile_x"], tune["tile_y"]], cell_steps=cells_steps)
+                tile=[tune["tile_x"], tune["tile_y"]], workgroups=tune["workgroups"], cell_steps=cells_steps)
 
 
-def bench_gradient(wave=4):
+def bench_gradient(wave=4, nshots=8):
     import numpy as np
     import torch
 
@@ -155,12 +182,12 @@ def bench_gradient(wave=4):
     from paper_2112_15071_amd import Simulator
     from paper_2112_15071_amd.batch import BatchSimulator
 
-    log("[bench] FWI gradient: 8 shots, 256^3, 1500 steps, checkpoints every 50")
+    log(f"[bench] FWI gradient: {nshots} shots, 256^3, 1500 steps, checkpoints every 50")
     (tl, tm, tr_), start = W.c4_models()
     dev = torch.device("cuda:0")
     true = [torch.as_tensor(a, dtype=torch.float32, device=dev) for a in (tl, tm, tr_)]
     model = [torch.as_tensor(a, dtype=torch.float32, device=dev) for a in start]
-    shots = W.c4_shots(*start)
+    shots = W.c4_shots(*start)[:nshots]
     k = 50
     # observed data from the true model
     obs_sim = Simulator(*true, 10.0, 5e-4, 1500, sponge=20, device=dev)
@@ -188,6 +215,7 @@ def bench_gradient(wave=4):
     torch.cuda.empty_cache()
     log(f"[bench] gradient loop {t_loop:.2f} s")
     # batched waves sharing the model and the gradient arrays
+    wave = min(wave, len(shots))
     sims = [Simulator(*model, 10.0, 5e-4, 1500, sponge=20, device=dev) for _ in range(wave)]
     for x in sims:
         x.set_kernel(kern["variant"], kern["tile_y"], kern["zchunk"], kern["tile_x"])
@@ -218,6 +246,35 @@ def bench_gradient(wave=4):
                 bytes_per_cell_step_per_shot=GRAD_BYTES_PER_CELL_STEP)
 
 
+def counters_run(kernels, K):
+    """Forward steps on the 256^3 workload with each kernel configuration in turn, then
+    three copies of 1 GiB with torch (a plain copy kernel of known size, which calibrates
+    the HBM byte counters).  Meant to run under rocprofv3 --pmc."""
+    import torch
+
+    import workloads as W
+    from paper_2112_15071_amd import Simulator
+
+    dev = torch.device("cuda:0")
+    shot = W.c1(nt=K)
+    lam, mu, rho = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (shot.lam, shot.mu, shot.rho))
+    wav = torch.as_tensor(shot.wavelet, dtype=torch.float32).to(dev)
+    for spec in kernels:
+        variant, tx, ty, zc = spec.split(",")
+        sim = Simulator(lam, mu, rho, shot.h, shot.dt, K, dtype=torch.float32, sponge=shot.sponge, device=dev)
+        sim.set_kernel(variant, int(ty), int(zc), int(tx))
+        log(f"[counters] {spec}: {K} steps")
+        sim.forward(shot.src_pos, shot.moment, shot.force, wav[:K], shot.rec_pos)
+        sync()
+        sim.close()
+    a = torch.ones(1 << 28, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    sync()
+    log("[counters] 3 x 1 GiB copies done")
+
+
 def cpu_baseline(shot, ns):
     import oracle
 
@@ -242,15 +299,24 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps for the CPU baseline sample (0: skip)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--kernel", metavar="VARIANT,TX,TY,ZC", default=None,
+                    help="forward kernel configuration (default: autotuned, cached per grid)")
+    ap.add_argument("--grad-shots", type=int, default=8, help="shots of the gradient section (profiling runs: fewer)")
+    ap.add_argument("--counters", metavar="VARIANT,TX,TY,ZC", action="append", default=[],
+                    help="counter-collection run: --steps forward steps per kernel given (repeatable), then a "
+                         "1 GiB device copy that calibrates FETCH_SIZE / WRITE_SIZE; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built.",
               file=sys.stderr)
         sys.exit(2)
 
-    shot, f = bench_forward(args.steps, args.warmup)
+    if args.counters:
+        counters_run(args.counters, args.steps)
+        return
+    shot, f = bench_forward(args.steps, args.warmup, args.kernel)
     batch = None if args.no_batch else bench_batch()
-    grad = None if args.no_grad else bench_gradient()
+    grad = None if args.no_grad else bench_gradient(nshots=args.grad_shots)
     cpu = cpu_baseline(shot, args.cpu_steps) if args.cpu_steps > 0 else None
     nx, ny, nz = shot.shape
     out = {
@@ -284,7 +350,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(f["achieved"] / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": f["traffic"],
             "avg_kernel_ms": {k: round(v, 5) for k, v in f["per"].items()},
             "bytes_per_launch": f["bytes_launch"],
         },

@@ -184,6 +184,14 @@ int fd3d_batch_create(fd3d_batch **out, int nshot, fd3d_ctx *const *ctxs, void *
  * persistent workgroups (0: CUs x occupancy, rounded to a multiple of 8). */
 int fd3d_batch_set_kernel(fd3d_batch *b, int tile_x, int tile_y, int workgroups);
 
+/* Times `steps` batched steps (sources and receivers off, one warm-up run each) for
+ * every supported tile shape, with the persistent grid and with one workgroup per tile,
+ * keeps the fastest for later batch calls and writes it to *tile_x, *tile_y,
+ * *workgroups (0 = persistent) and its ms per step to *best_ms (each when non-NULL).
+ * Every shot's forward state is zeroed afterwards.  Synchronises the stream. */
+int fd3d_batch_autotune(fd3d_batch *b, int steps, int *tile_x, int *tile_y, int *workgroups, double *best_ms,
+                        void *hip_stream);
+
 /* srcs[nshot] (or NULL), nrec[nshot], rec_pos[nshot] (host double[nrec][3] each),
  * traces[nshot] (device T[nrec][3][nt] each); flags as fd3d_forward. */
 int fd3d_batch_forward(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,

@@ -34,10 +34,10 @@ class BatchSimulator:
     def set_kernel(self, tile_x: int, tile_y: int, workgroups: int = 0) -> None:
         _abi.fd3d_batch_set_kernel(self._b, tile_x, tile_y, workgroups)
 
-    def autotune(self, steps: int = 20, cache: bool = True) -> dict:
-        """Autotune every distinct grid shape of the batch (each context keeps its own z
-        chunk); the batch takes the tile shape that won for the most cells."""
-        votes = {}
+    def autotune(self, steps: int = 10, cache: bool = True) -> dict:
+        """Autotune every distinct grid shape of the batch for single-shot runs (each
+        context also keeps its own z chunk, which the batch uses), then time the batched
+        launch itself for every tile shape and grid mode and keep the fastest."""
         seen = {}
         for sim in self.sims:
             key = (sim.shape, sim.dtype)
@@ -46,12 +46,9 @@ class BatchSimulator:
             else:
                 e = seen[key]
                 sim.set_kernel("tile", e["tile_y"], e["zchunk"], e["tile_x"])
-            e = seen[key]
-            cells = int(np.prod(sim.shape))
-            votes[(e["tile_x"], e["tile_y"])] = votes.get((e["tile_x"], e["tile_y"]), 0) + cells
-        tx, ty = max(votes.items(), key=lambda kv: kv[1])[0]
-        self.set_kernel(tx, ty)
-        return {"tile_x": tx, "tile_y": ty, "per_shape": {f"{k[0]}": v for k, v in seen.items()}}
+        best = _abi.fd3d_batch_autotune(self._b, steps, _stream())
+        best["per_shape"] = {f"{k[0]}": v for k, v in seen.items()}
+        return best
 
     def forward(self, shots: List[Dict], use_graph: bool = True, keep_state: bool = False,
                 traces: List[torch.Tensor] = None) -> List[torch.Tensor]:

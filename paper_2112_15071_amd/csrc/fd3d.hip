@@ -1489,6 +1489,74 @@ int fd3d_batch_set_kernel(fd3d_batch *b, int tile_x, int tile_y, int workgroups)
     return FD3D_OK;
 }
 
+int fd3d_batch_autotune(fd3d_batch *b, int steps, int *tile_x, int *tile_y, int *workgroups, double *best_ms,
+                        void *hip_stream)
+{
+    if (!b) return fail(FD3D_EINVAL, "batch is NULL");
+    if (steps < 1) return fail(FD3D_EINVAL, "steps must be >= 1");
+    hipStream_t st = (hipStream_t)hip_stream;
+    static const int shapes[][2] = {{64, 4}, {64, 8}, {64, 16}, {128, 4}, {128, 8}, {256, 4}};
+    const int nt_save = b->nt;
+    const int keep[3] = {b->tile_x, b->tile_y, b->wgs_req};
+    int win[3] = {keep[0], keep[1], keep[2]};
+    double win_ms = 1e300;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(FD3D_EHIP, "hipEventCreate failed");
+    b->nt = steps;
+    int rc = FD3D_OK;
+    for (const auto &sh : shapes) {
+        if (!tile_supported(b->tsize, sh[0], sh[1])) continue;
+        // persistent grid (CUs x occupancy) or one workgroup per tile
+        for (int mode = 0; mode < 2 && !rc; ++mode) {
+            b->tile_x = sh[0];
+            b->tile_y = sh[1];
+            b->wgs_req = 0;
+            if (mode == 1) {
+                long tiles = 0;
+                for (const fd3d_ctx *c : b->ctx)
+                    tiles += (long)((c->n[0] + sh[0] - 1) / sh[0]) * ((c->n[1] + sh[1] - 1) / sh[1]) *
+                             ((c->n[2] + c->zchunk - 1) / c->zchunk);
+                b->wgs_req = (int)std::min<long>((tiles + 7) / 8 * 8, 1L << 30);
+            }
+            for (int rep = 0; rep < 2 && !rc; ++rep) {
+                if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(FD3D_EHIP, "hipEventRecord");
+                if (!rc)
+                    rc = b->tsize == 8 ? batch_forward_impl<double>(b, nullptr, nullptr, nullptr, nullptr, FD3D_KEEP_STATE, 0, st)
+                                       : batch_forward_impl<float>(b, nullptr, nullptr, nullptr, nullptr, FD3D_KEEP_STATE, 0, st);
+            }
+            if (rc) break;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(FD3D_EHIP, "timing events failed");
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < win_ms) {
+                win_ms = ms;
+                win[0] = b->tile_x;
+                win[1] = b->tile_y;
+                win[2] = b->wgs_req;
+            }
+        }
+        if (rc) break;
+    }
+    b->nt = nt_save;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const int *use = rc ? keep : win;
+    b->tile_x = use[0];
+    b->tile_y = use[1];
+    b->wgs_req = use[2];
+    if (rc) return rc;
+    for (fd3d_ctx *c : b->ctx) zero_fields_any(c, st);
+    if (tile_x) *tile_x = win[0];
+    if (tile_y) *tile_y = win[1];
+    if (workgroups) *workgroups = win[2];
+    if (best_ms) *best_ms = win_ms / steps;
+    return FD3D_OK;
+}
+
 int fd3d_batch_forward(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, const double *const *rec_pos,
                        void *const *traces, int flags, int use_graph, void *hip_stream)
 {

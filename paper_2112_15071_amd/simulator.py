@@ -117,10 +117,11 @@ class Simulator:
 
     def autotune(self, steps: int = 20, cache: bool = True) -> dict:
         """Pick the fastest tile shape and z chunk for this grid (fd3d_autotune), with a
-        JSON cache keyed by grid shape, dtype, free surface and device name
+        JSON cache keyed by grid shape, dtype, free surface and device (CU count, memory size)
         ($FD3D_AUTOTUNE_CACHE, default ~/.cache/fd3d/autotune.json).  Zeroes the state."""
         nx, ny, nz = self.shape
-        dev = torch.cuda.get_device_name(self.device)
+        props = torch.cuda.get_device_properties(self.device)
+        dev = f"{props.multi_processor_count}cu-{props.total_memory >> 30}gib"
         key = f"{nx}x{ny}x{nz}/{str(self.dtype)}/fs{int(self.opts.free_surface)}/{dev}"
         path = os.environ.get("FD3D_AUTOTUNE_CACHE", os.path.expanduser("~/.cache/fd3d/autotune.json"))
         table = {}

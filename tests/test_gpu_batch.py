@@ -77,6 +77,47 @@ def test_batch_equals_single_shots(fs, use_graph):
         s.close()
 
 
+def test_batch_autotune_then_forward():
+    """After the batch autotuner (which runs sourceless steps on every shot), a batched
+    forward on the chosen tile shape and grid mode equals single-shot runs."""
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    shots = make_shots(600)
+    sims = sims_for(shots)
+    batch = BatchSimulator(sims)
+    best = batch.autotune(steps=3, cache=False)
+    print(f"[batch] autotune -> {best['tile_x']}x{best['tile_y']} wg={best['workgroups']}", flush=True)
+    assert best["ms_per_step"] > 0
+    trs = batch.forward([desc(s) for s in shots], use_graph=True)
+    torch.cuda.synchronize()
+    ref = single_runs(shots, (best["tile_x"], best["tile_y"]))
+    for k, (sim, tr) in enumerate(zip(sims, trs)):
+        assert np.array_equal(tr.double().cpu().numpy(), ref[k][0]), k
+        assert np.array_equal(sim.state().double().cpu().numpy(), ref[k][1]), k
+    batch.close()
+    for s in sims:
+        s.close()
+
+
+def test_one_workgroup_per_tile_equals_persistent():
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    shots = make_shots(650)
+    out = []
+    for wg in (8, 4096):  # 8 workgroups: many tiles each; 4096: one tile each
+        sims = sims_for(shots)
+        batch = BatchSimulator(sims)
+        batch.set_kernel(64, 8, wg)
+        trs = batch.forward([desc(s) for s in shots], use_graph=False)
+        torch.cuda.synchronize()
+        out.append([(t.cpu(), s.state().cpu()) for t, s in zip(trs, sims)])
+        batch.close()
+        for s in sims:
+            s.close()
+    for (ta, sa), (tb, sb) in zip(*out):
+        assert torch.equal(ta, tb) and torch.equal(sa, sb)
+
+
 def test_graph_replays_with_new_sources():
     """Replays of the captured graph, with eager work and synchronisation in between,
     each match eager single-shot runs for the sources of that replay."""
