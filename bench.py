@@ -34,7 +34,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_CELL = {
     "velocity": 4 * (6 + 3 + 1 + 3),  # read 6 stress, 3 velocity, rho; write 3 velocity
     "stress": 4 * (3 + 6 + 2 + 6),  # read 3 velocity, 6 stress, lambda, mu; write 6 stress
+    "fused": 4 * (6 + 3 + 3 + 9),  # read 6 stress, 3 velocity, rho, lambda, mu; write 9
 }
+
+
+def step_bytes(kern):
+    """Algorithmic bytes per cell and time step of the forward path with this kernel."""
+    if kern["variant"] == "fused":
+        return BYTES_PER_CELL["fused"]
+    return BYTES_PER_CELL["velocity"] + BYTES_PER_CELL["stress"]
 # gradient, per shot and time step: forward with checkpoints (120), segment recompute
 # storing v^{n+1/2} and sigma^n (156), the four adjoint passes: stress-A 27 fields,
 # velocity-A 12, velocity-B 19, stress-B 15 (292)
@@ -122,12 +130,15 @@ def bench_forward(K, Wm, kernel=None):
     ms, launches = _abi.fd3d_profile_read(sim.ctx)
     sync()
     _abi.fd3d_profile(sim.ctx, False)
-    names = ("velocity", "record", "stress")
-    per = {names[i]: ms[i] / max(launches[i], 1) for i in range(3)}
-    dom = "stress" if ms[2] >= ms[0] else "velocity"
+    names = ("velocity", "record", "stress", "fused")
+    per = {names[i]: ms[i] / launches[i] for i in range(4) if launches[i] > 0}
+    if "fused" in per:
+        dom = "fused"
+    else:
+        dom = "stress" if per["stress"] >= per["velocity"] else "velocity"
     bytes_launch = BYTES_PER_CELL[dom] * cells
     achieved = bytes_launch / (per[dom] * 1e-3) / 1e9
-    both = (BYTES_PER_CELL["velocity"] + BYTES_PER_CELL["stress"]) * cells * K / (elapsed * 1e9)
+    both = step_bytes(sim.kernel()) * cells * K / (elapsed * 1e9)
     log(f"[bench] avg kernel ms {per}; dominant {dom} {achieved:.0f} GB/s; whole step {both:.0f} GB/s")
     kern = sim.kernel()
     sim.close()
@@ -341,7 +352,7 @@ def main():
             "kernel": f["kernel"],
             "hbm_gbs_whole_step": round(f["both"], 1),
             "hbm_frac_whole_step": round(f["both"] / HBM_PEAK_GBS, 4),
-            "bytes_per_cell_step": BYTES_PER_CELL["velocity"] + BYTES_PER_CELL["stress"],
+            "bytes_per_cell_step": step_bytes(f["kernel"]),
         },
         "roofline": {
             "bound": "hbm",

@@ -62,6 +62,8 @@ extern "C" {
 /* kernel variants of the step loop (fd3d_set_kernel) */
 #define FD3D_KERNEL_CELL 0 /* one thread per cell, neighbours from global memory */
 #define FD3D_KERNEL_TILE 1 /* LDS-staged x/y halo planes + register z sweep (default) */
+#define FD3D_KERNEL_FUSED 2 /* velocity and stress of a step in one z sweep over a double-buffered
+                               state; tiles 64x4 and 64x8 (FP32), 64x4 (FP64) */
 
 /* fd3d_forward flags */
 #define FD3D_KEEP_STATE 1 /* start from the current state instead of zeros */
@@ -219,19 +221,22 @@ void fd3d_batch_destroy(fd3d_batch *b);
 /* Kernel selection for the step loop of later calls on this context.  All variants
  * compute the same update with the same operation order per sample. */
 typedef struct fd3d_kernel {
-    int variant;  /* FD3D_KERNEL_CELL or FD3D_KERNEL_TILE */
+    int variant;  /* FD3D_KERNEL_CELL, FD3D_KERNEL_TILE or FD3D_KERNEL_FUSED */
     int tile_x;   /* tile columns: 64, 128 or 256 */
-    int tile_y;   /* tile rows: FP32 64x{4,8,16}, 128x{4,8}, 256x4; FP64 64x{4,8}, 128x4 */
+    int tile_y;   /* tile rows: FP32 64x{4,8,16}, 128x{4,8}, 256x4; FP64 64x{4,8}, 128x4;
+                     fused: FP32 64x{4,8}, FP64 64x4 */
     int zchunk;   /* z planes swept by one workgroup, >= 4 */
 } fd3d_kernel;
 
 /* Default at create: FD3D_KERNEL_TILE with 256x4 tiles (FP32, nx >= 256), 128x4
  * (nx >= 128) or 64x8, and 64-plane sweeps (nz >= 128) or 32.  FD3D_EINVAL for an
- * unsupported shape. */
+ * unsupported shape.  The fused variant keeps two copies of the state and swaps them
+ * every step; the state accessors always address the current copy, and the gradient's
+ * segment recompute and adjoint passes use the tile kernels of the same tile shape. */
 int fd3d_set_kernel(fd3d_ctx *ctx, const fd3d_kernel *k);
 int fd3d_get_kernel(const fd3d_ctx *ctx, fd3d_kernel *k);
 
-/* Autotuner: times every supported tile shape and z-chunk for `steps` steps on this
+/* Autotuner: times every supported tile and fused shape and z-chunk for `steps` steps on this
  * context (a warm-up and a timed run each, no source, on the caller's stream; waits for
  * each timing), keeps the fastest for later calls and writes it to *best (and its ms per
  * step to *best_ms) when non-NULL.  The forward state is zeroed afterwards. */
@@ -240,10 +245,11 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
 /* Per-kernel timing of the step loop.  With enable = 1, later forward calls record a
  * HIP event pair on the caller's stream around every kernel launch of the loop (the
  * kernels themselves are unchanged).  fd3d_profile_read waits for the last recorded
- * event and returns, per pass (0 = velocity, 1 = receiver sampling, 2 = stress), the
- * summed kernel time in ms and the number of launches of the last profiled call. */
+ * event and returns, per pass (0 = velocity, 1 = receiver sampling, 2 = stress,
+ * 3 = fused step), the summed kernel time in ms and the number of launches of the last
+ * profiled call. */
 int fd3d_profile(fd3d_ctx *ctx, int enable);
-int fd3d_profile_read(fd3d_ctx *ctx, double ms[3], int launches[3]);
+int fd3d_profile_read(fd3d_ctx *ctx, double ms[4], int launches[4]);
 
 void fd3d_destroy(fd3d_ctx *ctx);
 

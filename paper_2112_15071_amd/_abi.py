@@ -27,6 +27,7 @@ FD3D_F64 = 1
 FD3D_KEEP_STATE = 1
 FD3D_KERNEL_CELL = 0
 FD3D_KERNEL_TILE = 1
+FD3D_KERNEL_FUSED = 2
 
 ERRNAMES = {
     FD3D_EINVAL: "FD3D_EINVAL", FD3D_ECFL: "FD3D_ECFL", FD3D_EMODEL: "FD3D_EMODEL", FD3D_ERANGE: "FD3D_ERANGE",
@@ -289,9 +290,10 @@ def fd3d_profile(ctx, enable: bool) -> None:
 
 
 def fd3d_profile_read(ctx):
-    """Summed ms and launch counts per pass (velocity, record, stress) of the last call."""
-    ms = (ctypes.c_double * 3)()
-    n = (ctypes.c_int * 3)()
+    """Summed ms and launch counts per pass (velocity, record, stress, fused step) of the
+    last call."""
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_int * 4)()
     _check(_lib.fd3d_profile_read(ctx, ms, n))
     return list(ms), list(n)
 

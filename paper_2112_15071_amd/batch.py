@@ -45,7 +45,7 @@ class BatchSimulator:
                 seen[key] = sim.autotune(steps, cache)
             else:
                 e = seen[key]
-                sim.set_kernel("tile", e["tile_y"], e["zchunk"], e["tile_x"])
+                sim.set_kernel(e["variant"], e["tile_y"], e["zchunk"], e["tile_x"])
         best = _abi.fd3d_batch_autotune(self._b, steps, _stream())
         best["per_shape"] = {f"{k[0]}": v for k, v in seen.items()}
         return best

@@ -19,6 +19,9 @@ FLAGS = [
     "-shared",
     # no packed FP32 instructions in any kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-add fusion decided per source expression, never across statements, so
+    # that the same expression rounds the same way in every kernel variant
+    "-ffp-contract=on",
     "-Wall",
     "-Wno-unused-function",
 ]

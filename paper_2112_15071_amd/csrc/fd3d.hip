@@ -17,6 +17,7 @@
 #include "common.h"
 #include "fwd_cell.h"
 #include "fwd_tile.h"
+#include "fwd_fused.h"
 #include "adj_cell.h"
 #include "util_kernels.h"
 
@@ -48,9 +49,10 @@ size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 size_t rectap_bytes(int tsize) { return 8 * sizeof(int) + 8 * (size_t)tsize; }
 
 // Workspace layout (byte offsets).  Fields are padded to 4 KiB plus a 1 KiB skew so
-// that the nine streams of a pass do not start on the same HBM channel.
+// that the nine streams of a pass do not start on the same HBM channel.  Two copies of
+// the state: the fused step reads one and writes the other.
 struct Layout {
-    size_t field[NFIELD];
+    size_t field[2][NFIELD];
     size_t prof[3][2];
     size_t rec;
     size_t colors;  // receiver order grouped by colour (tap-disjoint sets), int[max_rec]
@@ -67,10 +69,11 @@ Layout make_layout(int nx, int ny, int nz, int tsize, int max_rec)
     size_t off = 0;
     L.field_bytes = (size_t)nx * ny * nz * tsize;
     const size_t stride = round_up(L.field_bytes, 4096) + 1024;
-    for (int f = 0; f < NFIELD; ++f) {
-        L.field[f] = off;
-        off += stride;
-    }
+    for (int b = 0; b < 2; ++b)
+        for (int f = 0; f < NFIELD; ++f) {
+            L.field[b][f] = off;
+            off += stride;
+        }
     const int n[3] = {nx, ny, nz};
     for (int a = 0; a < 3; ++a)
         for (int h = 0; h < 2; ++h) {
@@ -167,7 +170,8 @@ struct fd3d_ctx {
     std::vector<int> prof_pass;       // pass of launch q
     int prof_used;
     // kernel selection for the step loop
-    int variant;  // FD3D_KERNEL_CELL or FD3D_KERNEL_TILE
+    int variant;  // FD3D_KERNEL_CELL, FD3D_KERNEL_TILE or FD3D_KERNEL_FUSED
+    int cur;      // state copy holding the current state (0 or 1)
     int tile_x;   // columns of a tile (64, 128, 256)
     int tile_y;   // rows of a tile (4, 8, 16)
     int zchunk;   // z planes per workgroup sweep
@@ -192,7 +196,7 @@ template <typename T> Grid<T> make_grid(const fd3d_ctx *c)
     G.lam = (const T *)c->lam;
     G.mu = (const T *)c->mu;
     G.rho = (const T *)c->rho;
-    for (int f = 0; f < NFIELD; ++f) G.f[f] = (T *)(c->ws + c->L.field[f]);
+    for (int f = 0; f < NFIELD; ++f) G.f[f] = (T *)(c->ws + c->L.field[c->cur][f]);
     for (int a = 0; a < 3; ++a)
         for (int h = 0; h < 2; ++h) G.g[a][h] = (const T *)(c->ws + c->L.prof[a][h]);
     for (int f = 0; f < NFIELD; ++f) G.save[f] = nullptr;
@@ -253,7 +257,7 @@ template <typename T> int model_check(fd3d_ctx *c, hipStream_t st)
 
 template <typename T> void zero_fields(fd3d_ctx *c, hipStream_t st)
 {
-    const long n = (long)((c->L.field[NFIELD - 1] + c->L.field_bytes) / sizeof(T));
+    const long n = (long)((c->L.field[1][NFIELD - 1] + c->L.field_bytes) / sizeof(T));
     fill_zero<T><<<2048, 256, 0, st>>>((T *)c->ws, n);
 }
 
@@ -499,6 +503,80 @@ void step(fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int nrec, 
     tm.end();
 }
 
+// Fused tile shapes: FP32 64x4 and 64x8, FP64 64x4.
+bool fused_supported(const fd3d_ctx *c, int tx, int ty) { return tx == 64 && (ty == 4 || (ty == 8 && c->tsize == 4)); }
+
+// Arguments of one fused step from the current state copy into the other one.
+template <typename T> FusedArgs<T> fused_args(const fd3d_ctx *c, const Inject<T> &inj, int n)
+{
+    FusedArgs<T> A;
+    std::memset(&A, 0, sizeof A);
+    const Grid<T> G = make_grid<T>(c);
+    A.in = G.f[0];
+    A.out = (T *)(c->ws + c->L.field[1 - c->cur][0]);
+    A.fs = (long)((c->L.field[0][1] - c->L.field[0][0]) / sizeof(T));
+    A.nx = G.nx;
+    A.ny = G.ny;
+    A.nz = G.nz;
+    A.sy = (int)G.sy;
+    A.sz = G.sz;
+    A.dt = G.dt;
+    A.rdx = G.rdx;
+    A.lam = G.lam;
+    A.mu = G.mu;
+    A.rho = G.rho;
+    for (int h = 0; h < 2; ++h) {
+        A.gx[h] = G.g[0][h];
+        A.gy[h] = G.g[1][h];
+        A.gz[h] = G.g[2][h];
+    }
+    A.wavelet = inj.on ? inj.wavelet : nullptr;
+    A.n = n;
+    for (int a = 0; a < 3; ++a) A.origin[a][0] = A.origin[a][1] = -(1 << 28);
+    for (int q = 0; q < NFIELD; ++q) {
+        if (inj.i0[q] == -(1 << 28)) continue;  // component without source taps
+        A.mask |= 1 << q;
+        A.origin[0][stag(q, 0)] = inj.i0[q];
+        A.origin[1][stag(q, 1)] = inj.j0[q];
+        A.origin[2][stag(q, 2)] = inj.k0[q];
+        for (int m = 0; m < 8; ++m) A.coef[q][m] = inj.c[q][m];
+    }
+    return A;
+}
+
+template <typename T, bool FS>
+void launch_fused(const fd3d_ctx *c, const FusedArgs<T> &A, hipStream_t st)
+{
+    const TileMap tm = tile_map(c);
+    const int nwg = tm.ntx * tm.nty * tm.nzc;
+    if constexpr (sizeof(T) == 4) {
+        if (c->tile_y == 8) {
+            step_fused<T, 64, 8, FS><<<nwg, Fused<64, 8>::NT, 0, st>>>(A, tm);
+            return;
+        }
+    }
+    step_fused<T, 64, 4, FS><<<nwg, Fused<64, 4>::NT, 0, st>>>(A, tm);
+}
+
+// One fused step from the current state copy into the other one (which becomes current);
+// the receivers sample the new velocity.
+template <typename T, bool FS>
+void fused_step(fd3d_ctx *c, const Inject<T> &inj, int n, int nrec, const RecTap<T> *taps, T *traces,
+                hipStream_t st, Timer &tm)
+{
+    const FusedArgs<T> A = fused_args<T>(c, inj, n);
+    tm.begin(3);
+    launch_fused<T, FS>(c, A, st);
+    tm.end();
+    if (nrec > 0) {
+        tm.begin(1);
+        record<T><<<(3 * nrec + 255) / 256, 256, 0, st>>>(A.out + VX * A.fs, A.out + VY * A.fs, A.out + VZ * A.fs,
+                                                          taps, nrec, c->nt, n, traces);
+        tm.end();
+    }
+    c->cur ^= 1;
+}
+
 // Gradient workspace (byte offsets): adjoint state, staggered-point gradient
 // accumulators, the tiled adjoint's intermediate fields, checkpoints every k steps, one
 // k-step segment of stored fields, and the residual buffer of fd3d_gradient.
@@ -550,20 +628,24 @@ int forward_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
     rc = stage_receivers<T>(c, nrec, rec_pos, st);
     if (rc) return rc;
     if (!(flags & FD3D_KEEP_STATE)) zero_fields<T>(c, st);
-    const Grid<T> G = make_grid<T>(c);
     const RecTap<T> *taps = (const RecTap<T> *)(c->ws + c->L.rec);
+    const bool fused = c->variant == FD3D_KERNEL_FUSED;
     Timer tm{c, st};
     c->prof_used = 0;
     for (int n = 0; n < c->nt; ++n) {
+        const Grid<T> G = make_grid<T>(c);
         if (GL && n % GL->k == 0) {
             char *dst = gws + GL->ckpt + (size_t)(n / GL->k) * 9 * GL->stride;
             for (int f = 0; f < NFIELD; ++f)
                 HIP_TRY(hipMemcpyAsync(dst + f * GL->stride, G.f[f], c->L.field_bytes, hipMemcpyDeviceToDevice, st));
         }
-        if (c->opts.free_surface) step<T, true>(c, G, inj, n, nrec, taps, (T *)traces, st, tm);
+        if (fused && c->opts.free_surface) fused_step<T, true>(c, inj, n, nrec, taps, (T *)traces, st, tm);
+        else if (fused) fused_step<T, false>(c, inj, n, nrec, taps, (T *)traces, st, tm);
+        else if (c->opts.free_surface) step<T, true>(c, G, inj, n, nrec, taps, (T *)traces, st, tm);
         else step<T, false>(c, G, inj, n, nrec, taps, (T *)traces, st, tm);
     }
     HIP_TRY(hipGetLastError());
+    const Grid<T> G = make_grid<T>(c);
     if (c->opts.check_finite) {
         int *flag = (int *)(c->ws + c->L.flag);
         fill_zero<int><<<1, 64, 0, st>>>(flag, 1);
@@ -655,7 +737,7 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
     const RecTap<T> *taps = (const RecTap<T> *)(c->ws + c->L.rec);
     const int *colors = (const int *)(c->ws + c->L.colors);
     const dim3 blk(64, 4, 1), grd((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
-    const bool tiled = c->variant == FD3D_KERNEL_TILE;
+    const bool tiled = c->variant != FD3D_KERNEL_CELL;  // the fused variant recomputes with tiles
     Timer tm{c, st};
     Inject<T> none;
     std::memset(&none, 0, sizeof none);
@@ -1215,6 +1297,7 @@ int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const v
     // default tile shape by row length (measured on MI355X at 256^3: 256x4 tiles with
     // 64-plane sweeps keep one 1024-thread workgroup per CU and 1 KiB row segments)
     c->variant = FD3D_KERNEL_TILE;
+    c->cur = 0;
     if (c->tsize == 4 && nx >= 256) { c->tile_x = 256; c->tile_y = 4; }
     else if (nx >= 128) { c->tile_x = 128; c->tile_y = 4; }
     else { c->tile_x = 64; c->tile_y = 8; }
@@ -1263,7 +1346,8 @@ int fd3d_get_state(fd3d_ctx *ctx, void *const fields[9], void *hip_stream)
         if (!fields[f]) return fail(FD3D_EINVAL, "field pointer is NULL");
     hipStream_t st = (hipStream_t)hip_stream;
     for (int f = 0; f < NFIELD; ++f)
-        HIP_TRY(hipMemcpyAsync(fields[f], ctx->ws + ctx->L.field[f], ctx->L.field_bytes, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(fields[f], ctx->ws + ctx->L.field[ctx->cur][f], ctx->L.field_bytes,
+                               hipMemcpyDeviceToDevice, st));
     return FD3D_OK;
 }
 
@@ -1392,12 +1476,16 @@ int fd3d_get_adjoint_state(fd3d_ctx *ctx, const void *gws, void *const fields[9]
 int fd3d_set_kernel(fd3d_ctx *ctx, const fd3d_kernel *k)
 {
     if (!ctx || !k) return fail(FD3D_EINVAL, "ctx/k is NULL");
-    if (k->variant != FD3D_KERNEL_CELL && k->variant != FD3D_KERNEL_TILE) return fail(FD3D_EINVAL, "unknown kernel variant");
+    if (k->variant != FD3D_KERNEL_CELL && k->variant != FD3D_KERNEL_TILE && k->variant != FD3D_KERNEL_FUSED)
+        return fail(FD3D_EINVAL, "unknown kernel variant");
     if (k->variant == FD3D_KERNEL_TILE && !tile_supported(ctx->tsize, k->tile_x, k->tile_y))
         return fail(FD3D_EINVAL, "unsupported tile shape " + std::to_string(k->tile_x) + "x" + std::to_string(k->tile_y));
+    if (k->variant == FD3D_KERNEL_FUSED && !fused_supported(ctx, k->tile_x, k->tile_y))
+        return fail(FD3D_EINVAL, "unsupported fused tile shape " + std::to_string(k->tile_x) + "x" +
+                                     std::to_string(k->tile_y));
     if (k->zchunk < 4) return fail(FD3D_EINVAL, "zchunk must be >= 4");
     ctx->variant = k->variant;
-    if (k->variant == FD3D_KERNEL_TILE) {
+    if (k->variant != FD3D_KERNEL_CELL) {
         ctx->tile_x = k->tile_x;
         ctx->tile_y = k->tile_y;
     }
@@ -1609,7 +1697,9 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
     if (!ctx) return fail(FD3D_EINVAL, "ctx is NULL");
     if (steps < 1) return fail(FD3D_EINVAL, "steps must be >= 1");
     hipStream_t st = (hipStream_t)hip_stream;
-    static const int shapes[][2] = {{64, 4}, {64, 8}, {64, 16}, {128, 4}, {128, 8}, {256, 4}};
+    static const int shapes[][3] = {{FD3D_KERNEL_TILE, 64, 4},   {FD3D_KERNEL_TILE, 64, 8},   {FD3D_KERNEL_TILE, 64, 16},
+                                    {FD3D_KERNEL_TILE, 128, 4},  {FD3D_KERNEL_TILE, 128, 8},  {FD3D_KERNEL_TILE, 256, 4},
+                                    {FD3D_KERNEL_FUSED, 64, 4},  {FD3D_KERNEL_FUSED, 64, 8}};
     static const int chunks[] = {16, 32, 64, 128};
     const int nt_save = ctx->nt;
     const fd3d_kernel keep = {ctx->variant, ctx->tile_x, ctx->tile_y, ctx->zchunk};
@@ -1621,13 +1711,14 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
     ctx->nt = steps;
     int rc = FD3D_OK;
     for (const auto &sh : shapes) {
-        if (!tile_supported(ctx->tsize, sh[0], sh[1])) continue;
-        if (sh[0] > 64 && ctx->n[0] < sh[0] / 2) continue;  // mostly idle lanes
+        if (sh[0] == FD3D_KERNEL_TILE && !tile_supported(ctx->tsize, sh[1], sh[2])) continue;
+        if (sh[0] == FD3D_KERNEL_FUSED && !fused_supported(ctx, sh[1], sh[2])) continue;
+        if (sh[1] > 64 && ctx->n[0] < sh[1] / 2) continue;  // mostly idle lanes
         for (int zc : chunks) {
             if (zc > ctx->n[2] && zc != chunks[0]) continue;
-            ctx->variant = FD3D_KERNEL_TILE;
-            ctx->tile_x = sh[0];
-            ctx->tile_y = sh[1];
+            ctx->variant = sh[0];
+            ctx->tile_x = sh[1];
+            ctx->tile_y = sh[2];
             ctx->zchunk = zc;
             // one warm-up run, one timed run, both from the current (clobbered) state
             for (int rep = 0; rep < 2 && !rc; ++rep) {
@@ -1644,7 +1735,7 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
             (void)hipEventElapsedTime(&ms, e0, e1);
             if (ms < win_ms) {
                 win_ms = ms;
-                win = fd3d_kernel{FD3D_KERNEL_TILE, sh[0], sh[1], zc};
+                win = fd3d_kernel{sh[0], sh[1], sh[2], zc};
             }
         }
         if (rc) break;
@@ -1671,17 +1762,17 @@ int fd3d_profile(fd3d_ctx *ctx, int enable)
     return FD3D_OK;
 }
 
-int fd3d_profile_read(fd3d_ctx *ctx, double ms[3], int launches[3])
+int fd3d_profile_read(fd3d_ctx *ctx, double ms[4], int launches[4])
 {
     if (!ctx || !ms || !launches) return fail(FD3D_EINVAL, "ctx/ms/launches is NULL");
-    for (int p = 0; p < 3; ++p) { ms[p] = 0.0; launches[p] = 0; }
+    for (int p = 0; p < 4; ++p) { ms[p] = 0.0; launches[p] = 0; }
     if (ctx->prof_used == 0) return FD3D_OK;
     HIP_TRY(hipEventSynchronize(ctx->prof_ev[2 * ctx->prof_used - 1]));
     for (int q = 0; q < ctx->prof_used; ++q) {
         float t = 0.0f;
         HIP_TRY(hipEventElapsedTime(&t, ctx->prof_ev[2 * q], ctx->prof_ev[2 * q + 1]));
         const int p = ctx->prof_pass[q];
-        if (p >= 0 && p < 3) { ms[p] += t; launches[p] += 1; }
+        if (p >= 0 && p < 4) { ms[p] += t; launches[p] += 1; }
     }
     return FD3D_OK;
 }

@@ -102,21 +102,24 @@ class Simulator:
     def ctx(self) -> int:
         return self._ctx
 
+    _VARIANTS = {"cell": 0, "tile": 1, "fused": 2}
+
     def set_kernel(self, variant: str = "tile", tile_y: int = 8, zchunk: int = 32, tile_x: int = 64) -> None:
-        """Select the step-loop kernels: "cell" (one thread per cell) or "tile"
-        (LDS halo planes + register z sweep over tile_x x tile_y columns, zchunk planes)."""
+        """Select the step-loop kernels: "cell" (one thread per cell), "tile" (LDS halo
+        planes + register z sweep over tile_x x tile_y columns, zchunk planes) or "fused"
+        (velocity and stress of a step in one sweep, tile_x = 64)."""
         k = _abi.fd3d_kernel()
-        k.variant = {"cell": _abi.FD3D_KERNEL_CELL, "tile": _abi.FD3D_KERNEL_TILE}[variant]
+        k.variant = self._VARIANTS[variant]
         k.tile_x, k.tile_y, k.zchunk = int(tile_x), int(tile_y), int(zchunk)
         _abi.fd3d_set_kernel(self._ctx, k)
 
     def kernel(self) -> dict:
         k = _abi.fd3d_get_kernel(self._ctx)
-        return {"variant": "cell" if k.variant == _abi.FD3D_KERNEL_CELL else "tile", "tile_x": k.tile_x,
-                "tile_y": k.tile_y, "zchunk": k.zchunk}
+        name = {v: n for n, v in self._VARIANTS.items()}[k.variant]
+        return {"variant": name, "tile_x": k.tile_x, "tile_y": k.tile_y, "zchunk": k.zchunk}
 
     def autotune(self, steps: int = 20, cache: bool = True) -> dict:
-        """Pick the fastest tile shape and z chunk for this grid (fd3d_autotune), with a
+        """Pick the fastest kernel variant, tile shape and z chunk for this grid (fd3d_autotune), with a
         JSON cache keyed by grid shape, dtype, free surface and device (CU count, memory size)
         ($FD3D_AUTOTUNE_CACHE, default ~/.cache/fd3d/autotune.json).  Zeroes the state."""
         nx, ny, nz = self.shape
@@ -131,12 +134,12 @@ class Simulator:
                     table = json.load(f)
             except (OSError, ValueError):
                 table = {}
-        if cache and key in table:
+        if cache and key in table and "variant" in table[key]:
             e = table[key]
-            self.set_kernel("tile", e["tile_y"], e["zchunk"], e["tile_x"])
+            self.set_kernel(e["variant"], e["tile_y"], e["zchunk"], e["tile_x"])
             return dict(e, cached=True)
-        k, ms = _abi.fd3d_autotune(self._ctx, steps, _stream())
-        e = {"tile_x": k.tile_x, "tile_y": k.tile_y, "zchunk": k.zchunk, "ms_per_step": ms}
+        _, ms = _abi.fd3d_autotune(self._ctx, steps, _stream())
+        e = dict(self.kernel(), ms_per_step=ms)
         if cache:
             table[key] = e
             try:

@@ -81,24 +81,33 @@ def test_workspace_too_small():
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-def test_resume_and_determinism(dtype):
-    """m steps, export, import, nt - m steps == nt straight, bitwise; reruns are bitwise."""
+@pytest.mark.parametrize("fused", [False, True])
+def test_resume_and_determinism(dtype, fused):
+    """m steps, export, import, nt - m steps == nt straight, bitwise; reruns are bitwise.
+    With the fused kernel the state swaps buffers every step (17 is odd)."""
     from paper_2112_15071_amd import Simulator
 
     lam, mu, rho, nt = small(nt=50)
     w = W.ricker(30.0, nt, 5e-4)
     src = ((11.3, 9.7, 8.2), (1e15, -3e14, 2e14, 5e14, -1e14, 3e14), (1e9, 0, -2e9))
     rec = [[5.5, 6.0, 7.25], [14.0, 9.5, 10.0]]
-    full = Simulator(lam, mu, rho, 10.0, 5e-4, nt, dtype=dtype, sponge=4)
+
+    def make(n):
+        sim = Simulator(lam, mu, rho, 10.0, 5e-4, n, dtype=dtype, sponge=4)
+        if fused:
+            sim.set_kernel("fused", 4, 8, 64)
+        return sim
+
+    full = make(nt)
     t_full = full.forward(*src, w, rec).clone()
     s_full = full.state()
     t_again = full.forward(*src, w, rec).clone()
     assert torch.equal(t_full, t_again)
     assert torch.equal(s_full, full.state())
     m = 17
-    a = Simulator(lam, mu, rho, 10.0, 5e-4, m, dtype=dtype, sponge=4)
+    a = make(m)
     ta = a.forward(*src, w[:m], rec)
-    b = Simulator(lam, mu, rho, 10.0, 5e-4, nt - m, dtype=dtype, sponge=4)
+    b = make(nt - m)
     b.set_state(a.state())
     tb = b.forward(*src, w[m:], rec, keep_state=True)
     assert torch.equal(torch.cat([ta, tb], dim=2), t_full)

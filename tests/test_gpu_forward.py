@@ -72,12 +72,14 @@ def ragged_shot(free_surface, seed, force=False):
 
 # (variant, tile_y, zchunk, tile_x)
 KERNELS = [("cell", 8, 32), ("tile", 4, 8), ("tile", 8, 5), ("tile", 16, 32), ("tile", 4, 6, 128),
-           ("tile", 8, 9, 128), ("tile", 4, 7, 256)]
+           ("tile", 8, 9, 128), ("tile", 4, 7, 256), ("fused", 4, 8), ("fused", 8, 5), ("fused", 8, 32)]
 
 
 def fp64_ok(kern):
     if kern[0] == "cell":
         return True
+    if kern[0] == "fused":
+        return kern[1] == 4
     tx = kern[3] if len(kern) > 3 else 64
     return (tx == 64 and kern[1] in (4, 8)) or (tx == 128 and kern[1] == 4)
 
@@ -117,23 +119,26 @@ def c1_ref():
     return shot, oracle_run(shot, nt=C1_NT)
 
 
-@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-def test_c1_full_size_truncated(c1_ref, dtype):
-    """256^3 layered model, the launch configuration of the benchmark, 16 steps."""
+@pytest.mark.parametrize("dtype,kern", [(torch.float32, None), (torch.float64, None), (torch.float32, ("fused", 8, 64)),
+                                        (torch.float32, ("fused", 4, 32)), (torch.float64, ("fused", 4, 64))])
+def test_c1_full_size_truncated(c1_ref, dtype, kern):
+    """256^3 layered model, 16 steps: the default kernel and the fused configurations the
+    benchmark's autotuner chooses among."""
     shot, ref = c1_ref
-    print(f"[c1] gpu 256^3 x {C1_NT} {dtype}", flush=True)
-    got = gpu_run(shot, dtype, nt=C1_NT)
-    compare(got, ref, TOL[dtype], "c1 truncated")
+    print(f"[c1] gpu 256^3 x {C1_NT} {dtype} {kern}", flush=True)
+    got = gpu_run(shot, dtype, nt=C1_NT, kernel=kern)
+    compare(got, ref, TOL[dtype], f"c1 truncated {kern}")
 
 
-def test_c2_full_size_truncated():
+@pytest.mark.parametrize("kern", [None, ("fused", 8, 64)])
+def test_c2_full_size_truncated(kern):
     """512x512x256 with the free surface and the 30-cell sponge, 6 steps, FP32."""
     shot = W.c2()
     nt = 6
-    print(f"[c2] 512x512x256 x {nt}", flush=True)
+    print(f"[c2] 512x512x256 x {nt} {kern}", flush=True)
     ref = oracle_run(shot, nt=nt)
-    got = gpu_run(shot, torch.float32, nt=nt)
-    compare(got, ref, TOL[torch.float32], "c2 truncated")
+    got = gpu_run(shot, torch.float32, nt=nt, kernel=kern)
+    compare(got, ref, TOL[torch.float32], f"c2 truncated {kern}")
 
 
 def test_c1_full_length_mirror_symmetry():

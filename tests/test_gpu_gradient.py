@@ -132,6 +132,28 @@ def test_dot_product(dtype, tol):
     sim.close()
 
 
+def test_fused_forward_gives_the_same_gradient(case):
+    """The fused kernel (double-buffered state) in the checkpointed forward, with the tile
+    kernels of the same tile shape in the recompute and the adjoint: bitwise the gradient
+    of the tile variant."""
+    from paper_2112_15071_amd import Simulator
+
+    model, shots, d_obs, _ = case
+    out = []
+    for variant in ("tile", "fused"):
+        sim = Simulator(*model, H, DT, NT, sponge=SPONGE, sponge_alpha=ALPHA)
+        sim.set_kernel(variant, 8, 16, 64)
+        gws = sim.grad_workspace(9)
+        g = [torch.zeros(model[0].shape, device="cuda") for _ in range(3)]
+        for s, obs in zip(shots, d_obs):
+            sim.gradient(gws, torch.as_tensor(obs, dtype=torch.float32), *g, **s)
+        torch.cuda.synchronize()
+        out.append([x.cpu() for x in g])
+        sim.close()
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
+
+
 def test_autograd_functions_agree(case):
     from paper_2112_15071_amd.fwi import Misfit, Traces
 
