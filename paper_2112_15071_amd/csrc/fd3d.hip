@@ -451,7 +451,17 @@ template <typename T, typename F> decltype(auto) with_tile(int tx, int ty, F &&f
 // Passes of a step.  Forward: velocity, stress.  Adjoint step (reverse order of the
 // forward step): stress-A (C gradients, X = C G_s A_s), velocity-A (A_v update),
 // velocity-B (b gradient, Y = G_v A_v / rho_eff), stress-B (A_s update).
-enum Pass { kPassVel = 0, kPassStress = 1, kPassStressA, kPassVelA, kPassVelB, kPassStressB };
+// The forward passes also come in a variant that stores v^{n+1/2} and sigma^n through the
+// grid's save pointers (the gradient's segment recompute).
+enum Pass { kPassVel = 0, kPassStress = 1, kPassStressA, kPassVelA, kPassVelB, kPassStressB, kPassVelSave,
+            kPassStressSave };
+
+// Tile and fused sweeps address a window of (zchunk + 8) planes through one buffer
+// descriptor per field, of at most 1 GiB.
+bool window_ok(const fd3d_ctx *c, int zc)
+{
+    return (long)(zc + 8) * (long)c->n[0] * (long)c->n[1] * (long)c->tsize <= kMaxWindowBytes;
+}
 
 template <typename T, int TX, int TY, bool FS>
 void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &tm, int pass, hipStream_t st,
@@ -459,9 +469,13 @@ void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &
 {
     const int nwg = tm.ntx * tm.nty * tm.nzc;
     constexpr int NT = TX * TY;
+    if (G.save[VX] != nullptr && pass == kPassVel) pass = kPassVelSave;
+    if (G.save[VX] != nullptr && pass == kPassStress) pass = kPassStressSave;
     switch (pass) {
     case kPassVel: vel_tile<T, TX, TY, FS><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
     case kPassStress: stress_tile<T, TX, TY, FS><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
+    case kPassVelSave: vel_tile<T, TX, TY, FS, kFwdSave><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
+    case kPassStressSave: stress_tile<T, TX, TY, FS, kFwdSave><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
     case kPassStressA: stress_tile_adj<T, TX, TY, kAdjA><<<nwg, NT, 0, st>>>(G, inj, tm, io); break;
     case kPassVelA: vel_tile_adj<T, TX, TY, kAdjA><<<nwg, NT, 0, st>>>(G, inj, n, tm, io); break;
     case kPassVelB: vel_tile_adj<T, TX, TY, kAdjB><<<nwg, NT, 0, st>>>(G, inj, n, tm, io); break;
@@ -868,6 +882,8 @@ int launch_multi(fd3d_batch *b, const ShotFwd<T> *d, int n, int pass, hipStream_
     switch (pass) {
     case kPassVel: vel_tile_multi<T, TX, TY, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
     case kPassStress: stress_tile_multi<T, TX, TY, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassVelSave: vel_tile_multi<T, TX, TY, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassStressSave: stress_tile_multi<T, TX, TY, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n); break;
     case kPassStressA: stress_tile_multi<T, TX, TY, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
     case kPassVelA: vel_tile_multi<T, TX, TY, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
     case kPassVelB: vel_tile_multi<T, TX, TY, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n); break;
@@ -1214,8 +1230,8 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         copy_multi<T><<<cgrid, 256, 0, st>>>((const CopyDesc<T> *)(bws + BL.rest_copy + sg * BL.copy_bytes));
         for (int n = n0; n < n1; ++n) {
             const ShotFwd<T> *d = desc(BL.fwd_slot + (n - n0) * BL.fwd_bytes);
-            pass(d, n, kPassVel);
-            pass(d, n, kPassStress);
+            pass(d, n, kPassVelSave);
+            pass(d, n, kPassStressSave);
         }
         for (int n = n1 - 1; n >= n0; --n) {
             pass(desc(BL.sa_slot + (n - n0) * BL.fwd_bytes), n, kPassStressA);
@@ -1302,6 +1318,8 @@ int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const v
     else if (nx >= 128) { c->tile_x = 128; c->tile_y = 4; }
     else { c->tile_x = 64; c->tile_y = 8; }
     c->zchunk = nz >= 128 ? 64 : 32;
+    while (!window_ok(c, c->zchunk) && c->zchunk > 4) c->zchunk /= 2;
+    if (!window_ok(c, c->zchunk)) c->variant = FD3D_KERNEL_CELL;  // planes too large for a tile sweep
     if (hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess) {
         delete c;
         return fail(FD3D_EHIP, "hipEventCreateWithFlags failed");
@@ -1484,6 +1502,8 @@ int fd3d_set_kernel(fd3d_ctx *ctx, const fd3d_kernel *k)
         return fail(FD3D_EINVAL, "unsupported fused tile shape " + std::to_string(k->tile_x) + "x" +
                                      std::to_string(k->tile_y));
     if (k->zchunk < 4) return fail(FD3D_EINVAL, "zchunk must be >= 4");
+    if (k->variant != FD3D_KERNEL_CELL && !window_ok(ctx, k->zchunk))
+        return fail(FD3D_EINVAL, "zchunk too large: (zchunk + 8) planes must fit in 1 GiB");
     ctx->variant = k->variant;
     if (k->variant != FD3D_KERNEL_CELL) {
         ctx->tile_x = k->tile_x;
@@ -1525,6 +1545,8 @@ int fd3d_batch_create(fd3d_batch **out, int nshot, fd3d_ctx *const *ctxs, void *
         if (ctxs[s]->nt != ctxs[0]->nt) return fail(FD3D_EINVAL, "all shots must share nt");
         if (ctxs[s]->opts.free_surface != ctxs[0]->opts.free_surface)
             return fail(FD3D_EINVAL, "all shots must share the free-surface option");
+        if (!window_ok(ctxs[s], ctxs[s]->zchunk))
+            return fail(FD3D_EINVAL, "context " + std::to_string(s) + ": zchunk too large for a tile sweep");
         for (int q = 0; q < s; ++q)
             if (ctxs[q] == ctxs[s]) return fail(FD3D_EINVAL, "a context appears twice in the batch");
     }
@@ -1716,6 +1738,7 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
         if (sh[1] > 64 && ctx->n[0] < sh[1] / 2) continue;  // mostly idle lanes
         for (int zc : chunks) {
             if (zc > ctx->n[2] && zc != chunks[0]) continue;
+            if (!window_ok(ctx, zc)) continue;
             ctx->variant = sh[0];
             ctx->tile_x = sh[1];
             ctx->tile_y = sh[2];

@@ -210,26 +210,39 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
     const bool mvx = in && i <= nx - 2, mvy = in && j <= ny - 2;
     const bool pxy = i <= nx - 2 && j <= ny - 2, pxz = i <= nx - 2, pyz = j <= ny - 2;
 
-    // source tap of component q at (i, j, k) (-1: none) and its coefficient
+    // source tap of component q at (i, j, k) (-1: none) and its coefficient; srcw: a tap
+    // of some component lies in this workgroup's columns and planes (uniform)
     auto tap = [&](int q, int kk) -> int {
         const unsigned a = (unsigned)(i - A.origin[0][stag(q, 0)]), b = (unsigned)(j - A.origin[1][stag(q, 1)]);
         const unsigned d = (unsigned)(kk - A.origin[2][stag(q, 2)]);
         return (((A.mask >> q) & 1) && a < 2u && b < 2u && d < 2u) ? (int)(a + 2u * b + 4u * d) : -1;
     };
     auto coef = [&](int q, int tp) -> T { return tp >= 0 ? s_coef[q * 8 + (tp & 7)] : T(0); };
+    bool srcw = A.mask != 0 && A.wavelet != nullptr;
+    {
+        const int lo[3] = {i0 - 2, j0 - 2, k0 - 2}, hi[3] = {i0 + TX + 1, j0 + TY + 1, k1 + 1};
+        for (int a = 0; a < 3; ++a) {
+            const int o0 = min(A.origin[a][0], A.origin[a][1]), o1 = max(A.origin[a][0], A.origin[a][1]) + 1;
+            srcw = srcw && o1 >= lo[a] && o0 <= hi[a];
+        }
+    }
 
-    // descriptor of plane kk of a model array or of field q of a state copy
-    auto pl = [&](const T *f, int kk, bool ok) { return plane(f, kk, sz, ok && kk >= 0 && kk < nz); };
-    auto ldq = [&](int q, int kk, bool ok, unsigned off) -> T { return ld<T>(pl(A.in + q * fs, kk, ok), off); };
-    auto stq = [&](int q, int kk, bool ok, unsigned off, T v) { st(pl(A.out + q * fs, kk, ok), off, v); };
+    // descriptors of the inputs over the sweep's planes; offset of plane kk (kSkip: skipped)
+    const Window w = window<T>(k0, k1, nz, sz);
+    rsrc_t Fin[NFIELD];
+#pragma unroll
+    for (int q = 0; q < NFIELD; ++q) Fin[q] = wfield(A.in + q * fs, w);
+    const rsrc_t Flam = wfield(A.lam, w), Fmu = wfield(A.mu, w), Frho = wfield(A.rho, w);
+    auto po = [&](int kk, bool ok) -> unsigned { return wplane(w, kk, ok); };
+    auto stq = [&](int q, int kk, bool ok, unsigned off, T v) { st(wfield(A.out + q * fs, w), off + po(kk, ok), v); };
     // old sxz / syz / szz at plane kk, with the odd images above a free surface
     auto zsh = [&](int q, int kk, bool ok) -> T {
-        if (FS && kk < 0) return -ldq(q, -1 - kk, ok, oc);
-        return ldq(q, kk, ok, oc);
+        if (FS && kk < 0) return -ld<T>(Fin[q], oc + po(-1 - kk, ok));
+        return ld<T>(Fin[q], oc + po(kk, ok));
     };
     auto zzz = [&](int kk, bool ok) -> T {
-        if (FS && kk < 0) return -ldq(SZZ, -kk, ok, oc);
-        return ldq(SZZ, kk, ok, oc);
+        if (FS && kk < 0) return -ld<T>(Fin[SZZ], oc + po(-kk, ok));
+        return ld<T>(Fin[SZZ], oc + po(kk, ok));
     };
 
     // loads of velocity plane q: old stress of plane q (own column and ring), queue heads,
@@ -238,27 +251,27 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
         T xx, yy, xy, xz1, yz1, zz2, r1, vx, vy, vz, hxx, hyy, hxy, hxz, hyz, hr, lam, mu, hmu;
     };
     auto load = [&](int q, bool ok, Pre &P) {
-        const rsrc_t brh = pl(A.rho, q, ok);
-        P.xx = ldq(SXX, q, ok, oc);
-        P.yy = ldq(SYY, q, ok, oc);
-        P.xy = ldq(SXY, q, ok, oc);
+        const unsigned pq = po(q, ok), o = oc + pq;
+        P.xx = ld<T>(Fin[SXX], o);
+        P.yy = ld<T>(Fin[SYY], o);
+        P.xy = ld<T>(Fin[SXY], o);
         P.xz1 = zsh(SXZ, q + 1, ok);
         P.yz1 = zsh(SYZ, q + 1, ok);
         P.zz2 = zzz(q + 2, ok);
-        P.r1 = ld<T>(pl(A.rho, q + 1, ok), oc);
-        P.vx = ldq(VX, q, ok, oc);
-        P.vy = ldq(VY, q, ok, oc);
-        P.vz = ldq(VZ, q, ok, oc);
-        P.hxx = ldq(SXX, q, ok, hxx.off);
-        P.hyy = ldq(SYY, q, ok, hyy.off);
-        P.hxy = ldq(SXY, q, ok, hxy.off);
-        P.hxz = ldq(SXZ, q, ok, hxz.off);
-        P.hyz = ldq(SYZ, q, ok, hyz.off);
-        P.hr = ld<T>(brh, hr.off);
-        P.lam = ld<T>(pl(A.lam, q - 2, ok), ow);
-        const rsrc_t bm = pl(A.mu, q - 1, ok);
-        P.mu = ld<T>(bm, ow);
-        P.hmu = ld<T>(bm, hm.off);
+        P.r1 = ld<T>(Frho, oc + po(q + 1, ok));
+        P.vx = ld<T>(Fin[VX], o);
+        P.vy = ld<T>(Fin[VY], o);
+        P.vz = ld<T>(Fin[VZ], o);
+        P.hxx = ld<T>(Fin[SXX], hxx.off + pq);
+        P.hyy = ld<T>(Fin[SYY], hyy.off + pq);
+        P.hxy = ld<T>(Fin[SXY], hxy.off + pq);
+        P.hxz = ld<T>(Fin[SXZ], hxz.off + pq);
+        P.hyz = ld<T>(Fin[SYZ], hyz.off + pq);
+        P.hr = ld<T>(Frho, hr.off + pq);
+        P.lam = ld<T>(Flam, ow + po(q - 2, ok));
+        const unsigned pm = po(q - 1, ok);
+        P.mu = ld<T>(Fmu, ow + pm);
+        P.hmu = ld<T>(Fmu, hm.off + pm);
     };
 
     // register queues (entry m holds plane p - 2 + m of the current velocity plane p)
@@ -275,7 +288,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
     T dxx[3] = {T(0), T(0), T(0)}, dyy[3] = {T(0), T(0), T(0)}, dxy[3] = {T(0), T(0), T(0)};  // planes p-2, p-1, p
     T qvx[4] = {T(0), T(0), T(0), T(0)}, qvy[4] = {T(0), T(0), T(0), T(0)};  // new v, planes p-3 .. p
     T qvz[5] = {T(0), T(0), T(0), T(0), T(0)};                               // new vz, planes p-4 .. p
-    T r0 = ld<T>(pl(A.rho, p0, true), oc), r1 = T(0);
+    T r0 = ld<T>(Frho, oc + po(p0, true)), r1 = T(0);
     Pre P;
     load(p0, true, P);
 
@@ -323,7 +336,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
                       + dstag(qxz[2], qxz[1], qxz[3], qxz[0], rdx);
             const T bb = T(1) / ((r0 + Lr[br + 1]) / T(2));
             T v = vx0 + dt * bb * d;
-            v += bb * coef(VX, tap(VX, p)) * s;
+            if (srcw) v += bb * coef(VX, tap(VX, p)) * s;
             v = v * (gxh * gyi * gz_i);
             vxn = (pin && mvx) ? v : T(0);
         }
@@ -333,7 +346,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
                       + dstag(qyz[2], qyz[1], qyz[3], qyz[0], rdx);
             const T bb = T(1) / ((r0 + Lr[br + BX]) / T(2));
             T v = vy0 + dt * bb * d;
-            v += bb * coef(VY, tap(VY, p)) * s;
+            if (srcw) v += bb * coef(VY, tap(VY, p)) * s;
             v = v * (gxi * gyh * gz_i);
             vyn = (pin && mvy) ? v : T(0);
         }
@@ -343,7 +356,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
                       + dstag(qzz[3], qzz[2], qzz[4], qzz[1], rdx);
             const T bb = T(1) / ((r0 + r1) / T(2));
             T v = vz0 + dt * bb * d;
-            v += bb * coef(VZ, tap(VZ, p)) * s;
+            if (srcw) v += bb * coef(VZ, tap(VZ, p)) * s;
             v = v * (gxi * gyi * gz_h);
             vzn = (in && p >= 0 && p <= nz - 2) ? v : T(0);
         }
@@ -379,29 +392,31 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
             T nxx = dxx[0] + dt * (l * tr + T(2) * mm * exx);
             T nyy = dyy[0] + dt * (l * tr + T(2) * mm * eyy);
             T nzz = qzz[0] + dt * (l * tr + T(2) * mm * ezz);
-            const int tp = tap(SXX, k);
-            nxx += coef(SXX, tp) * s;
-            nyy += coef(SYY, tp) * s;
-            nzz += coef(SZZ, tp) * s;
+            if (srcw) {
+                const int tp = tap(SXX, k);
+                nxx += coef(SXX, tp) * s;
+                nyy += coef(SYY, tp) * s;
+                nzz += coef(SZZ, tp) * s;
+            }
             stq(SXX, k, true, ow, nxx * gn);
             stq(SYY, k, true, ow, nyy * gn);
             stq(SZZ, k, true, ow, (FS && k == 0) ? T(0) : nzz * gn);
             {
                 const T mxy = ((M0[om] + M0[om + 1]) + (M0[om + MX] + M0[om + MX + 1])) / T(4);
                 T v = dxy[0] + dt * mxy * exy;
-                v += coef(SXY, tap(SXY, k)) * s;
+                if (srcw) v += coef(SXY, tap(SXY, k)) * s;
                 stq(SXY, k, true, ow, pxy ? v * g_xy : T(0));
             }
             {
                 const T mxz = ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
                 T v = qxz[0] + dt * mxz * exz;
-                v += coef(SXZ, tap(SXZ, k)) * s;
+                if (srcw) v += coef(SXZ, tap(SXZ, k)) * s;
                 stq(SXZ, k, true, ow, (pxz && k <= nz - 2) ? v * g_xz : T(0));
             }
             {
                 const T myz = ((M0[om] + M0[om + MX]) + (M1[om] + M1[om + MX])) / T(4);
                 T v = qyz[0] + dt * myz * eyz;
-                v += coef(SYZ, tap(SYZ, k)) * s;
+                if (srcw) v += coef(SYZ, tap(SYZ, k)) * s;
                 stq(SYZ, k, true, ow, (pyz && k <= nz - 2) ? v * g_yz : T(0));
             }
         }

@@ -41,6 +41,45 @@ __device__ __forceinline__ rsrc_t plane(const T *f, int kk, long sz, bool ok)
                                              ok ? (int)(sz * (long)sizeof(T)) : 0, kRsrcWord3);
 }
 
+// The planes one z sweep of a workgroup touches, [max(k0-4, 0), min(k1+4, nz)): one
+// descriptor per field covers them and a plane is selected by the lane offset, so a
+// plane costs a vector add per distinct offset instead of a scalar descriptor per field.
+// For windows of at most 1 GiB the offsets need no selects: kOOB (a sample outside the
+// grid) plus any plane offset stays out of range, a skipped plane gets the plane offset
+// kSkip, and a plane below the window wraps around to the top of the 32-bit range.
+constexpr unsigned kSkip = 0x40000000u;
+constexpr long kMaxWindowBytes = 1L << 30;
+
+struct Window {
+    int b0;       // first plane
+    int bytes;    // descriptor size
+    unsigned pb;  // bytes per plane
+    long sz;      // samples per plane
+};
+
+template <typename T> __device__ __forceinline__ Window window(int k0, int k1, int nz, long sz)
+{
+    Window w;
+    w.b0 = max(k0 - 4, 0);
+    w.pb = (unsigned)(sz * (long)sizeof(T));
+    w.bytes = (int)((long)(min(k1 + 4, nz) - w.b0) * (long)w.pb);
+    w.sz = sz;
+    return w;
+}
+
+// Descriptor of field f over the window (empty unless ok).
+template <typename T> __device__ __forceinline__ rsrc_t wfield(const T *f, const Window &w, bool ok = true)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(f + (ok ? w.b0 * w.sz : 0)), (short)0, ok ? w.bytes : 0,
+                                             kRsrcWord3);
+}
+
+// Offset of plane kk in the window (kSkip: every sample out of range).
+__device__ __forceinline__ unsigned wplane(const Window &w, int kk, bool ok)
+{
+    return ok ? (unsigned)(kk - w.b0) * w.pb : kSkip;
+}
+
 __device__ __forceinline__ float bload(rsrc_t r, unsigned off, float)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
@@ -128,6 +167,11 @@ __device__ __forceinline__ Slot cslot(bool mine, int i0, int j0, int nx, int ny,
     return s;
 }
 
+// The halo slot of a field that this thread actually holds, when the x-halo threads (the
+// last ones), the y-halo threads (the first ones) and the corner thread are disjoint,
+// which holds for every supported tile shape (3 TX + 3 TY < TX TY).
+__device__ __forceinline__ Slot either(const Slot &a, const Slot &b, int dummy) { return a.lds != dummy ? a : b; }
+
 __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, int &j0, int &k0, int &k1, int TX,
                                             int TY, int nz)
 {
@@ -140,13 +184,15 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
     k1 = min(k0 + tm.zc, nz);
 }
 
-// What a tile body computes.  kFwd: the forward pass.  For the velocity-type body,
+// What a tile body computes.  kFwd: the forward pass; kFwdSave: the forward pass that
+// also stores v^{n+1/2} and sigma^n through the grid's save pointers (the gradient's
+// segment recompute).  For the velocity-type body,
 // kAdjA: A_v <- G_v A_v - dt D_S(X) (X = C G_s A_s, precomputed) and kAdjB:
 // g_b += dt D_S(sigma^n) U + force term, Y = U / rho_eff (U = G_v A_v).  For the
 // stress-type body, kAdjA: gradients of C from E(v^{n+1/2}) and T = G_s A_s, X = C T;
 // kAdjB: A_s <- G_s A_s - dt E(Y).  The adjoint modes read and write the arrays named
 // by the grid (f[] pointing at the adjoint, stored or scratch fields) and by TileIO.
-enum { kFwd = 0, kAdjA = 1, kAdjB = 2 };
+enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3 };
 
 template <typename T> struct TileIO {
     T *out[6];  // X (6) or Y (3) scratch
@@ -192,14 +238,14 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     // halo slots (fixed over the sweep); x-halo work on the last threads, y-halo on the first
     const int ex = NT - 1 - tid;
     const Slot hxx = xslot<T, TX, TY, 1, 2, 0>(ex, i0, j0, nx, ny, sy, NXX);
-    const Slot hxyx = xslot<T, TX, TY, 2, 1, 2>(ex, i0, j0, nx, ny, sy, NXY);
+    const Slot hxy = either(xslot<T, TX, TY, 2, 1, 2>(ex, i0, j0, nx, ny, sy, NXY),
+                            yslot<T, TX, TY, 2, 1, 2, W3>(tid, i0, j0, nx, ny, sy, NXY), NXY);
     const Slot hxz = xslot<T, TX, TY, 2, 1, 0>(ex, i0, j0, nx, ny, sy, NXZ);
     const Slot hyy = yslot<T, TX, TY, 1, 2, 0, TX>(tid, i0, j0, nx, ny, sy, NYY);
-    const Slot hxyy = yslot<T, TX, TY, 2, 1, 2, W3>(tid, i0, j0, nx, ny, sy, NXY);
     const Slot hyz = yslot<T, TX, TY, 2, 1, 0, TX>(tid, i0, j0, nx, ny, sy, NYZ);
-    const Slot hrx = xslot<T, TX, TY, 0, 1, 0>(ex, i0, j0, nx, ny, sy, NR);
-    const Slot hry = yslot<T, TX, TY, 0, 1, 0, WR>(tid, i0, j0, nx, ny, sy, NR);
-    const Slot hrc = cslot<T, TX, TY>(tid == NT / 2, i0, j0, nx, ny, sy, NR);
+    const Slot hr = either(either(xslot<T, TX, TY, 0, 1, 0>(ex, i0, j0, nx, ny, sy, NR),
+                                  yslot<T, TX, TY, 0, 1, 0, WR>(tid, i0, j0, nx, ny, sy, NR), NR),
+                           cslot<T, TX, TY>(tid == NT / 2, i0, j0, nx, ny, sy, NR), NR);
     const int own_c3 = ty * W3;  // row base in the x-halo planes without y halo
 
     const T *fxx = G.f[SXX], *fyy = G.f[SYY], *fzz = G.f[SZZ];
@@ -211,10 +257,11 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     const T gyh = in ? G.g[1][1][j] : T(0), gyi = in ? G.g[1][0][j] : T(0);
     const unsigned st_vx = (in && i <= nx - 2) ? oc : kOOB;
     const unsigned st_vy = (in && j <= ny - 2) ? oc : kOOB;
-    const bool save = MODE == kFwd && G.save[VX] != nullptr;
+    constexpr bool fwd = MODE == kFwd || MODE == kFwdSave;
     constexpr bool use_rho = MODE != kAdjA;
 
-    auto zld = [&](const T *f, int kk, bool ok) -> T { return ld<T>(plane(f, kk, sz, ok && kk >= 0 && kk < nz), oc); };
+    const Window w = window<T>(k0, k1, nz, sz);
+    auto zld = [&](const T *f, int kk, bool ok) -> T { return ld<T>(wfield(f, w), oc + wplane(w, kk, ok)); };
 
     // z queues at the first plane (with the free-surface odd images above k = 0)
     T qxz[4], qyz[4], qzz[4];
@@ -235,32 +282,29 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 
     // plane registers, loaded one plane ahead
     struct Plane {
-        T cxx, cyy, cxy, vx, vy, vz, xx, xyx, xz, yy, xyy, yz, rx, ry, rc, g0, g1, g2;
+        T cxx, cyy, cxy, vx, vy, vz, xx, xy, xz, yy, yz, r, g0, g1, g2;
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
-        const rsrc_t bxx = plane(fxx, kk, sz, ok), byy = plane(fyy, kk, sz, ok), bxy = plane(fxy, kk, sz, ok);
-        const rsrc_t bxz = plane(fxz, kk, sz, ok), byz = plane(fyz, kk, sz, ok);
-        const rsrc_t br = plane(rho, kk, sz, ok && use_rho);
+        const unsigned pk = wplane(w, kk, ok), pr = wplane(w, kk, ok && use_rho), o = oc + pk;
+        const rsrc_t bxx = wfield(fxx, w), byy = wfield(fyy, w), bxy = wfield(fxy, w);
+        const rsrc_t bxz = wfield(fxz, w), byz = wfield(fyz, w), br = wfield(rho, w);
         if constexpr (MODE == kAdjB) {
-            P.g0 = ld<T>(plane(io.acc[0], kk, sz, ok), oc);
-            P.g1 = ld<T>(plane(io.acc[1], kk, sz, ok), oc);
-            P.g2 = ld<T>(plane(io.acc[2], kk, sz, ok), oc);
+            P.g0 = ld<T>(wfield(io.acc[0], w), o);
+            P.g1 = ld<T>(wfield(io.acc[1], w), o);
+            P.g2 = ld<T>(wfield(io.acc[2], w), o);
         }
-        P.cxx = ld<T>(bxx, oc);
-        P.cyy = ld<T>(byy, oc);
-        P.cxy = ld<T>(bxy, oc);
-        P.vx = ld<T>(plane(G.f[VX], kk, sz, ok), oc);
-        P.vy = ld<T>(plane(G.f[VY], kk, sz, ok), oc);
-        P.vz = ld<T>(plane(G.f[VZ], kk, sz, ok), oc);
-        P.xx = ld<T>(bxx, hxx.off);
-        P.xyx = ld<T>(bxy, hxyx.off);
-        P.xz = ld<T>(bxz, hxz.off);
-        P.yy = ld<T>(byy, hyy.off);
-        P.xyy = ld<T>(bxy, hxyy.off);
-        P.yz = ld<T>(byz, hyz.off);
-        P.rx = ld<T>(br, hrx.off);
-        P.ry = ld<T>(br, hry.off);
-        P.rc = ld<T>(br, hrc.off);
+        P.cxx = ld<T>(bxx, o);
+        P.cyy = ld<T>(byy, o);
+        P.cxy = ld<T>(bxy, o);
+        P.vx = ld<T>(wfield(G.f[VX], w), o);
+        P.vy = ld<T>(wfield(G.f[VY], w), o);
+        P.vz = ld<T>(wfield(G.f[VZ], w), o);
+        P.xx = ld<T>(bxx, hxx.off + pk);
+        P.xy = ld<T>(bxy, hxy.off + pk);
+        P.xz = ld<T>(bxz, hxz.off + pk);
+        P.yy = ld<T>(byy, hyy.off + pk);
+        P.yz = ld<T>(byz, hyz.off + pk);
+        P.r = ld<T>(br, hr.off + pr);
     };
     Plane P;
     loadplane(k0, true, P);
@@ -276,14 +320,11 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         Lyz[(ty + 2) * TX + tx] = qyz[2];
         Lr[ty * WR + tx] = r0;
         Lxx[hxx.lds] = P.xx;
-        Lxy[hxyx.lds] = P.xyx;
+        Lxy[hxy.lds] = P.xy;
         Lxz[hxz.lds] = P.xz;
         Lyy[hyy.lds] = P.yy;
-        Lxy[hxyy.lds] = P.xyy;
         Lyz[hyz.lds] = P.yz;
-        Lr[hrx.lds] = P.rx;
-        Lr[hry.lds] = P.ry;
-        Lr[hrc.lds] = P.rc;
+        Lr[hr.lds] = P.r;
         const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
         const T ga0 = P.g0, ga1 = P.g1, ga2 = P.g2;
         // loads of plane k+1 and the queue heads (empty descriptors past the chunk)
@@ -294,29 +335,29 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         __syncthreads();
 
-        const rsrc_t ovx = plane(G.f[VX], k, sz, true), ovy = plane(G.f[VY], k, sz, true);
-        const rsrc_t ovz = plane(G.f[VZ], k, sz, true);
+        const unsigned pw = wplane(w, k, true);
+        const rsrc_t ovx = wfield(G.f[VX], w), ovy = wfield(G.f[VY], w), ovz = wfield(G.f[VZ], w);
         {
             const int o = own_c3 + tx + 1;
             const int ox = (ty + 2) * W3 + tx + 2;
             const T d = dstag(Lxx[o + 1], Lxx[o], Lxx[o + 2], Lxx[o - 1], rdx)
                       + dstag(Lxy[ox], Lxy[ox - W3], Lxy[ox + W3], Lxy[ox - 2 * W3], rdx)
                       + dstag(qxz[2], qxz[1], qxz[3], qxz[0], rdx);
-            if constexpr (MODE == kFwd) {
+            if constexpr (fwd) {
                 const T bb = T(1) / ((r0 + Lr[ty * WR + tx + 1]) / T(2));
                 T v = vx0 + dt * bb * d;
                 v += bb * pick(src.c[VX], tap_of(src, VX, i, j, k)) * s;
                 v = v * (gxh * gyi * gz_i);
-                st(ovx, st_vx, v);
-                st(plane(G.save[VX], k, sz, save), st_vx, v);
+                st(ovx, st_vx + pw, v);
+                if constexpr (MODE == kFwdSave) st(wfield(G.save[VX], w), st_vx + pw, v);
             } else if constexpr (MODE == kAdjA) {
-                st(ovx, st_vx, (gxh * gyi * gz_i) * vx0 - dt * d);
+                st(ovx, st_vx + pw, (gxh * gyi * gz_i) * vx0 - dt * d);
             } else {
                 const T u = (gxh * gyi * gz_i) * vx0;
                 T g = dt * d * u;
                 g += pick(src.c[VX], tap_of(src, VX, i, j, k)) * s * u;
-                st(plane(io.acc[0], k, sz, true), st_vx, ga0 + g);
-                st(plane(io.out[0], k, sz, true), st_vx, u / ((r0 + Lr[ty * WR + tx + 1]) / T(2)));
+                st(wfield(io.acc[0], w), st_vx + pw, ga0 + g);
+                st(wfield(io.out[0], w), st_vx + pw, u / ((r0 + Lr[ty * WR + tx + 1]) / T(2)));
             }
         }
         {
@@ -325,21 +366,21 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const T d = dstag(Lxy[ox], Lxy[ox - 1], Lxy[ox + 1], Lxy[ox - 2], rdx)
                       + dstag(Lyy[oy + TX], Lyy[oy], Lyy[oy + 2 * TX], Lyy[oy - TX], rdx)
                       + dstag(qyz[2], qyz[1], qyz[3], qyz[0], rdx);
-            if constexpr (MODE == kFwd) {
+            if constexpr (fwd) {
                 const T bb = T(1) / ((r0 + Lr[(ty + 1) * WR + tx]) / T(2));
                 T v = vy0 + dt * bb * d;
                 v += bb * pick(src.c[VY], tap_of(src, VY, i, j, k)) * s;
                 v = v * (gxi * gyh * gz_i);
-                st(ovy, st_vy, v);
-                st(plane(G.save[VY], k, sz, save), st_vy, v);
+                st(ovy, st_vy + pw, v);
+                if constexpr (MODE == kFwdSave) st(wfield(G.save[VY], w), st_vy + pw, v);
             } else if constexpr (MODE == kAdjA) {
-                st(ovy, st_vy, (gxi * gyh * gz_i) * vy0 - dt * d);
+                st(ovy, st_vy + pw, (gxi * gyh * gz_i) * vy0 - dt * d);
             } else {
                 const T u = (gxi * gyh * gz_i) * vy0;
                 T g = dt * d * u;
                 g += pick(src.c[VY], tap_of(src, VY, i, j, k)) * s * u;
-                st(plane(io.acc[1], k, sz, true), st_vy, ga1 + g);
-                st(plane(io.out[1], k, sz, true), st_vy, u / ((r0 + Lr[(ty + 1) * WR + tx]) / T(2)));
+                st(wfield(io.acc[1], w), st_vy + pw, ga1 + g);
+                st(wfield(io.out[1], w), st_vy + pw, u / ((r0 + Lr[(ty + 1) * WR + tx]) / T(2)));
             }
         }
         {
@@ -349,21 +390,21 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                       + dstag(Lyz[oy], Lyz[oy - TX], Lyz[oy + TX], Lyz[oy - 2 * TX], rdx)
                       + dstag(qzz[2], qzz[1], qzz[3], qzz[0], rdx);
             const unsigned st_vz = k <= nz - 2 ? oc : kOOB;
-            if constexpr (MODE == kFwd) {
+            if constexpr (fwd) {
                 const T bb = T(1) / ((r0 + r1) / T(2));
                 T v = vz0 + dt * bb * d;
                 v += bb * pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s;
                 v = v * (gxi * gyi * gz_h);
-                st(ovz, st_vz, v);
-                st(plane(G.save[VZ], k, sz, save), st_vz, v);
+                st(ovz, st_vz + pw, v);
+                if constexpr (MODE == kFwdSave) st(wfield(G.save[VZ], w), st_vz + pw, v);
             } else if constexpr (MODE == kAdjA) {
-                st(ovz, st_vz, (gxi * gyi * gz_h) * vz0 - dt * d);
+                st(ovz, st_vz + pw, (gxi * gyi * gz_h) * vz0 - dt * d);
             } else {
                 const T u = (gxi * gyi * gz_h) * vz0;
                 T g = dt * d * u;
                 g += pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s * u;
-                st(plane(io.acc[2], k, sz, true), st_vz, ga2 + g);
-                st(plane(io.out[2], k, sz, true), st_vz, u / ((r0 + r1) / T(2)));
+                st(wfield(io.acc[2], w), st_vz + pw, ga2 + g);
+                st(wfield(io.out[2], w), st_vz + pw, u / ((r0 + r1) / T(2)));
             }
         }
         qxz[0] = qxz[1]; qxz[1] = qxz[2]; qxz[2] = qxz[3]; qxz[3] = nxz;
@@ -398,15 +439,15 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     const unsigned oc = in ? (unsigned)(i + sy * j) * (unsigned)sizeof(T) : kOOB;
 
     const int ex = NT - 1 - tid;
-    const Slot hvxx = xslot<T, TX, TY, 2, 1, 1>(ex, i0, j0, nx, ny, sy, NV);
-    const Slot hvxy = yslot<T, TX, TY, 1, 2, 2, W3>(tid, i0, j0, nx, ny, sy, NV);
-    const Slot hvyx = xslot<T, TX, TY, 1, 2, 2>(ex, i0, j0, nx, ny, sy, NV);
-    const Slot hvyy = yslot<T, TX, TY, 2, 1, 1, W3>(tid, i0, j0, nx, ny, sy, NV);
-    const Slot hvzx = xslot<T, TX, TY, 1, 2, 1>(ex, i0, j0, nx, ny, sy, NV);
-    const Slot hvzy = yslot<T, TX, TY, 1, 2, 1, W3>(tid, i0, j0, nx, ny, sy, NV);
-    const Slot hmx = xslot<T, TX, TY, 0, 1, 0>(ex, i0, j0, nx, ny, sy, NM);
-    const Slot hmy = yslot<T, TX, TY, 0, 1, 0, WM>(tid, i0, j0, nx, ny, sy, NM);
-    const Slot hmc = cslot<T, TX, TY>(tid == NT / 2, i0, j0, nx, ny, sy, NM);
+    const Slot hvx = either(xslot<T, TX, TY, 2, 1, 1>(ex, i0, j0, nx, ny, sy, NV),
+                            yslot<T, TX, TY, 1, 2, 2, W3>(tid, i0, j0, nx, ny, sy, NV), NV);
+    const Slot hvy = either(xslot<T, TX, TY, 1, 2, 2>(ex, i0, j0, nx, ny, sy, NV),
+                            yslot<T, TX, TY, 2, 1, 1, W3>(tid, i0, j0, nx, ny, sy, NV), NV);
+    const Slot hvz = either(xslot<T, TX, TY, 1, 2, 1>(ex, i0, j0, nx, ny, sy, NV),
+                            yslot<T, TX, TY, 1, 2, 1, W3>(tid, i0, j0, nx, ny, sy, NV), NV);
+    const Slot hm = either(either(xslot<T, TX, TY, 0, 1, 0>(ex, i0, j0, nx, ny, sy, NM),
+                                  yslot<T, TX, TY, 0, 1, 0, WM>(tid, i0, j0, nx, ny, sy, NM), NM),
+                           cslot<T, TX, TY>(tid == NT / 2, i0, j0, nx, ny, sy, NM), NM);
     // own positions in the planes
     const int ovx = (ty + 1) * W3 + tx + 2;
     const int ovy = (ty + 2) * W3 + tx + 1;
@@ -422,10 +463,11 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     const unsigned st_xy = (in && i <= nx - 2 && j <= ny - 2) ? oc : kOOB;
     const unsigned st_xz = (in && i <= nx - 2) ? oc : kOOB;
     const unsigned st_yz = (in && j <= ny - 2) ? oc : kOOB;
-    const bool save = MODE == kFwd && G.save[SXX] != nullptr;
+    constexpr bool fwd = MODE == kFwd || MODE == kFwdSave;
     constexpr bool use_model = MODE != kAdjB;
 
-    auto zld = [&](const T *f, int kk, bool ok) -> T { return ld<T>(plane(f, kk, sz, ok && kk >= 0 && kk < nz), oc); };
+    const Window w = window<T>(k0, k1, nz, sz);
+    auto zld = [&](const T *f, int kk, bool ok) -> T { return ld<T>(wfield(f, w), oc + wplane(w, kk, ok)); };
 
     // z queues: vx, vy at k-1..k+2; vz at k-2..k+1 (zero above k = 0: never used with FS)
     T qvx[4], qvy[4], qvz[4];
@@ -438,54 +480,40 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     T m1 = zld(mu, k0 + 1, use_model);  // own mu one plane below
 
     struct Plane {
-        T cl, cm, sxx, syy, szz, sxy, sxz, syz, vxx, vxy, vyx, vyy, vzx, vzy, a0, a1, a2, a3, a4;
+        T cl, cm, sxx, syy, szz, sxy, sxz, syz, hx, hy, hz, a0, a1, a2, a3, a4;
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
-        const rsrc_t bx = plane(fvx, kk, sz, ok), by = plane(fvy, kk, sz, ok), bz = plane(fvz, kk, sz, ok);
-        P.cl = ld<T>(plane(lam, kk, sz, ok && use_model), oc);
-        P.cm = ld<T>(plane(mu, kk, sz, ok && use_model), oc);
+        const unsigned pk = wplane(w, kk, ok), o = oc + pk, om_ = oc + wplane(w, kk, ok && use_model);
+        const rsrc_t bx = wfield(fvx, w), by = wfield(fvy, w), bz = wfield(fvz, w);
+        P.cl = ld<T>(wfield(lam, w), om_);
+        P.cm = ld<T>(wfield(mu, w), om_);
         if constexpr (MODE == kAdjA) {
-            P.a0 = ld<T>(plane(io.acc[0], kk, sz, ok), oc);
-            P.a1 = ld<T>(plane(io.acc[1], kk, sz, ok), oc);
-            P.a2 = ld<T>(plane(io.acc[2], kk, sz, ok), oc);
-            P.a3 = ld<T>(plane(io.acc[3], kk, sz, ok), oc);
-            P.a4 = ld<T>(plane(io.acc[4], kk, sz, ok), oc);
+            P.a0 = ld<T>(wfield(io.acc[0], w), o);
+            P.a1 = ld<T>(wfield(io.acc[1], w), o);
+            P.a2 = ld<T>(wfield(io.acc[2], w), o);
+            P.a3 = ld<T>(wfield(io.acc[3], w), o);
+            P.a4 = ld<T>(wfield(io.acc[4], w), o);
         }
-        P.sxx = ld<T>(plane(G.f[SXX], kk, sz, ok), oc);
-        P.syy = ld<T>(plane(G.f[SYY], kk, sz, ok), oc);
-        P.szz = ld<T>(plane(G.f[SZZ], kk, sz, ok), oc);
-        P.sxy = ld<T>(plane(G.f[SXY], kk, sz, ok), oc);
-        P.sxz = ld<T>(plane(G.f[SXZ], kk, sz, ok), oc);
-        P.syz = ld<T>(plane(G.f[SYZ], kk, sz, ok), oc);
-        P.vxx = ld<T>(bx, hvxx.off);
-        P.vxy = ld<T>(bx, hvxy.off);
-        P.vyx = ld<T>(by, hvyx.off);
-        P.vyy = ld<T>(by, hvyy.off);
-        P.vzx = ld<T>(bz, hvzx.off);
-        P.vzy = ld<T>(bz, hvzy.off);
+        P.sxx = ld<T>(wfield(G.f[SXX], w), o);
+        P.syy = ld<T>(wfield(G.f[SYY], w), o);
+        P.szz = ld<T>(wfield(G.f[SZZ], w), o);
+        P.sxy = ld<T>(wfield(G.f[SXY], w), o);
+        P.sxz = ld<T>(wfield(G.f[SXZ], w), o);
+        P.syz = ld<T>(wfield(G.f[SYZ], w), o);
+        P.hx = ld<T>(bx, hvx.off + pk);
+        P.hy = ld<T>(by, hvy.off + pk);
+        P.hz = ld<T>(bz, hvz.off + pk);
     };
-    struct MuHalo {
-        T x, y, c;
-    };
-    auto loadmu = [&](int kk, bool ok, MuHalo &H) {
-        const rsrc_t bm = plane(mu, kk, sz, ok && kk < nz && use_model);
-        H.x = ld<T>(bm, hmx.off);
-        H.y = ld<T>(bm, hmy.off);
-        H.c = ld<T>(bm, hmc.off);
-    };
+    auto loadmu = [&](int kk, bool ok) -> T { return ld<T>(wfield(mu, w), hm.off + wplane(w, kk, ok && use_model)); };
 
     Plane P;
     loadplane(k0, true, P);
-    MuHalo H;
-    loadmu(k0, true, H);
     {
         T *M = s_mu[k0 % 3];
         M[om] = P.cm;
-        M[hmx.lds] = H.x;
-        M[hmy.lds] = H.y;
-        M[hmc.lds] = H.c;
+        M[hm.lds] = loadmu(k0, true);
     }
-    loadmu(k0 + 1, true, H);
+    T hmu = loadmu(k0 + 1, true);
 
     for (int k = k0; k < k1; ++k) {
         const int b = (k - k0) & 1;
@@ -494,16 +522,11 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         Lx[ovx] = qvx[1];
         Ly[ovy] = qvy[1];
         Lz[ovz] = qvz[2];
-        Lx[hvxx.lds] = P.vxx;
-        Lx[hvxy.lds] = P.vxy;
-        Ly[hvyx.lds] = P.vyx;
-        Ly[hvyy.lds] = P.vyy;
-        Lz[hvzx.lds] = P.vzx;
-        Lz[hvzy.lds] = P.vzy;
+        Lx[hvx.lds] = P.hx;
+        Ly[hvy.lds] = P.hy;
+        Lz[hvz.lds] = P.hz;
         M1[om] = m1;
-        M1[hmx.lds] = H.x;
-        M1[hmy.lds] = H.y;
-        M1[hmc.lds] = H.c;
+        M1[hm.lds] = hmu;
         const T l = P.cl, mm = P.cm;
         const T o_xx = P.sxx, o_yy = P.syy, o_zz = P.szz, o_xy = P.sxy, o_xz = P.sxz, o_yz = P.syz;
         const T a0 = P.a0, a1 = P.a1, a2 = P.a2, a3 = P.a3, a4 = P.a4;
@@ -511,17 +534,18 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         loadplane(k + 1, more, P);
         const T nvx = zld(fvx, k + 3, more), nvy = zld(fvy, k + 3, more), nvz = zld(fvz, k + 2, more);
         const T nm1 = zld(mu, k + 2, more && use_model);
-        loadmu(k + 2, more, H);
+        hmu = loadmu(k + 2, more);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
+        const unsigned pw = wplane(w, k, true);
         __syncthreads();
 
-        if constexpr (MODE == kFwd) {
-            st(plane(G.save[SXX], k, sz, save), oc, o_xx);
-            st(plane(G.save[SYY], k, sz, save), oc, o_yy);
-            st(plane(G.save[SZZ], k, sz, save), oc, o_zz);
-            st(plane(G.save[SXY], k, sz, save), oc, o_xy);
-            st(plane(G.save[SXZ], k, sz, save), oc, o_xz);
-            st(plane(G.save[SYZ], k, sz, save), oc, o_yz);
+        if constexpr (MODE == kFwdSave) {
+            st(wfield(G.save[SXX], w), oc + pw, o_xx);
+            st(wfield(G.save[SYY], w), oc + pw, o_yy);
+            st(wfield(G.save[SZZ], w), oc + pw, o_zz);
+            st(wfield(G.save[SXY], w), oc + pw, o_xy);
+            st(wfield(G.save[SXZ], w), oc + pw, o_xz);
+            st(wfield(G.save[SYZ], w), oc + pw, o_yz);
         }
         const T exx = dstag(Lx[ovx], Lx[ovx - 1], Lx[ovx + 1], Lx[ovx - 2], rdx);
         const T eyy = dstag(Ly[ovy], Ly[ovy - W3], Ly[ovy + W3], Ly[ovy - 2 * W3], rdx);
@@ -538,7 +562,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         const T eyz = dzvy + dstag(Lz[ovz + W3], Lz[ovz], Lz[ovz + 2 * W3], Lz[ovz - W3], rdx);
         const T g_xy = gxh * gyh * gz_i, g_xz = gxh * gyi * gz_h, g_yz = gxi * gyh * gz_h;
         const unsigned o_stxz = k <= nz - 2 ? st_xz : kOOB, o_styz = k <= nz - 2 ? st_yz : kOOB;
-        if constexpr (MODE == kFwd) {
+        if constexpr (fwd) {
             const T tr = exx + eyy + ezz;
             T nxx = o_xx + dt * (l * tr + T(2) * mm * exx);
             T nyy = o_yy + dt * (l * tr + T(2) * mm * eyy);
@@ -547,54 +571,54 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             nxx += pick(src.c[SXX], t) * s;
             nyy += pick(src.c[SYY], t) * s;
             nzz += pick(src.c[SZZ], t) * s;
-            st(plane(G.f[SXX], k, sz, true), oc, nxx * gn);
-            st(plane(G.f[SYY], k, sz, true), oc, nyy * gn);
-            st(plane(G.f[SZZ], k, sz, true), oc, (FS && k == 0) ? T(0) : nzz * gn);
+            st(wfield(G.f[SXX], w), oc + pw, nxx * gn);
+            st(wfield(G.f[SYY], w), oc + pw, nyy * gn);
+            st(wfield(G.f[SZZ], w), oc + pw, (FS && k == 0) ? T(0) : nzz * gn);
             {
                 const T mxy = ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
                 T v = o_xy + dt * mxy * exy;
                 v += pick(src.c[SXY], tap_of(src, SXY, i, j, k)) * s;
-                st(plane(G.f[SXY], k, sz, true), st_xy, v * g_xy);
+                st(wfield(G.f[SXY], w), st_xy + pw, v * g_xy);
             }
             {
                 const T mxz = ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
                 T v = o_xz + dt * mxz * exz;
                 v += pick(src.c[SXZ], tap_of(src, SXZ, i, j, k)) * s;
-                st(plane(G.f[SXZ], k, sz, true), o_stxz, v * g_xz);
+                st(wfield(G.f[SXZ], w), o_stxz + pw, v * g_xz);
             }
             {
                 const T myz = ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);
                 T v = o_yz + dt * myz * eyz;
                 v += pick(src.c[SYZ], tap_of(src, SYZ, i, j, k)) * s;
-                st(plane(G.f[SYZ], k, sz, true), o_styz, v * g_yz);
+                st(wfield(G.f[SYZ], w), o_styz + pw, v * g_yz);
             }
         } else if constexpr (MODE == kAdjA) {
             // gradients of C and X = C T with T = G_s A_s
             const T txx = gn * o_xx, tyy = gn * o_yy, tzz = gn * o_zz;
             const T trT = (txx + tyy) + tzz;
-            st(plane(io.acc[0], k, sz, true), oc, a0 + dt * ((exx + eyy) + ezz) * trT);
-            st(plane(io.acc[1], k, sz, true), oc, a1 + dt * T(2) * ((exx * txx + eyy * tyy) + ezz * tzz));
-            st(plane(io.out[0], k, sz, true), oc, l * trT + T(2) * mm * txx);
-            st(plane(io.out[1], k, sz, true), oc, l * trT + T(2) * mm * tyy);
-            st(plane(io.out[2], k, sz, true), oc, l * trT + T(2) * mm * tzz);
+            st(wfield(io.acc[0], w), oc + pw, a0 + dt * ((exx + eyy) + ezz) * trT);
+            st(wfield(io.acc[1], w), oc + pw, a1 + dt * T(2) * ((exx * txx + eyy * tyy) + ezz * tzz));
+            st(wfield(io.out[0], w), oc + pw, l * trT + T(2) * mm * txx);
+            st(wfield(io.out[1], w), oc + pw, l * trT + T(2) * mm * tyy);
+            st(wfield(io.out[2], w), oc + pw, l * trT + T(2) * mm * tzz);
             const T txy = g_xy * o_xy, txz = g_xz * o_xz, tyz = g_yz * o_yz;
-            st(plane(io.acc[2], k, sz, true), st_xy, a2 + dt * exy * txy);
-            st(plane(io.acc[3], k, sz, true), o_stxz, a3 + dt * exz * txz);
-            st(plane(io.acc[4], k, sz, true), o_styz, a4 + dt * eyz * tyz);
+            st(wfield(io.acc[2], w), st_xy + pw, a2 + dt * exy * txy);
+            st(wfield(io.acc[3], w), o_stxz + pw, a3 + dt * exz * txz);
+            st(wfield(io.acc[4], w), o_styz + pw, a4 + dt * eyz * tyz);
             const T mxy = ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
             const T mxz = ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
             const T myz = ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);
-            st(plane(io.out[3], k, sz, true), st_xy, mxy * txy);
-            st(plane(io.out[4], k, sz, true), o_stxz, mxz * txz);
-            st(plane(io.out[5], k, sz, true), o_styz, myz * tyz);
+            st(wfield(io.out[3], w), st_xy + pw, mxy * txy);
+            st(wfield(io.out[4], w), o_stxz + pw, mxz * txz);
+            st(wfield(io.out[5], w), o_styz + pw, myz * tyz);
         } else {
             // A_s <- G_s A_s - dt E(Y)
-            st(plane(G.f[SXX], k, sz, true), oc, gn * o_xx - dt * exx);
-            st(plane(G.f[SYY], k, sz, true), oc, gn * o_yy - dt * eyy);
-            st(plane(G.f[SZZ], k, sz, true), oc, gn * o_zz - dt * ezz);
-            st(plane(G.f[SXY], k, sz, true), st_xy, g_xy * o_xy - dt * exy);
-            st(plane(G.f[SXZ], k, sz, true), o_stxz, g_xz * o_xz - dt * exz);
-            st(plane(G.f[SYZ], k, sz, true), o_styz, g_yz * o_yz - dt * eyz);
+            st(wfield(G.f[SXX], w), oc + pw, gn * o_xx - dt * exx);
+            st(wfield(G.f[SYY], w), oc + pw, gn * o_yy - dt * eyy);
+            st(wfield(G.f[SZZ], w), oc + pw, gn * o_zz - dt * ezz);
+            st(wfield(G.f[SXY], w), st_xy + pw, g_xy * o_xy - dt * exy);
+            st(wfield(G.f[SXZ], w), o_stxz + pw, g_xz * o_xz - dt * exz);
+            st(wfield(G.f[SYZ], w), o_styz + pw, g_yz * o_yz - dt * eyz);
         }
         qvx[0] = qvx[1]; qvx[1] = qvx[2]; qvx[2] = qvx[3]; qvx[3] = nvx;
         qvy[0] = qvy[1]; qvy[1] = qvy[2]; qvy[2] = qvy[3]; qvy[3] = nvy;
@@ -604,21 +628,21 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
 }
 
 // ---------------------------------------------------------------------------------
-// Single-grid launches: one workgroup per tile.
-template <typename T, int TX, int TY, bool FS>
+// Single-grid launches: one workgroup per tile (MODE kFwd or kFwdSave).
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
 __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
 {
     int i0, j0, k0, k1;
     tile_coords(tm, xcd_remap(blockIdx.x, gridDim.x), i0, j0, k0, k1, TX, TY, G.nz);
-    vel_tile_body<T, TX, TY, FS>(G, src, n, i0, j0, k0, k1);
+    vel_tile_body<T, TX, TY, FS, MODE>(G, src, n, i0, j0, k0, k1);
 }
 
-template <typename T, int TX, int TY, bool FS>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
 __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
 {
     int i0, j0, k0, k1;
     tile_coords(tm, xcd_remap(blockIdx.x, gridDim.x), i0, j0, k0, k1, TX, TY, G.nz);
-    stress_tile_body<T, TX, TY, FS>(G, src, n, i0, j0, k0, k1);
+    stress_tile_body<T, TX, TY, FS, MODE>(G, src, n, i0, j0, k0, k1);
 }
 
 // Adjoint passes, one workgroup per tile (no free surface).
