@@ -128,7 +128,7 @@ __device__ __forceinline__ T yval(const Grid<T> &G, const AdjGrid<T> &A, int c, 
     if (!((unsigned)i <= (unsigned)lx && (unsigned)j <= (unsigned)ly && (unsigned)k <= (unsigned)lz)) return T(0);
     const long p = i + G.sy * j + G.sz * k;
     const long e = c == VX ? 1 : (c == VY ? G.sy : G.sz);
-    return (damp(G, c, i, j, k) * A.a[c][p]) / ((G.rho[p] + G.rho[p + e]) / T(2));
+    return (damp(G, c, i, j, k) * A.a[c][p]) * buoy(G.rho[p], G.rho[p + e]);
 }
 
 // Stored sigma^n for the divergence stencil (zero outside the active range).
@@ -277,8 +277,8 @@ __global__ void __launch_bounds__(256) grad_finalize(Grid<T> G, AdjGrid<T> A, T 
             const T g = rdc(A.gb[c], VX + c, ii, jj, kk, G);
             if (g != T(0)) {
                 const long q = ii + G.sy * jj + G.sz * kk;
-                const T re = (G.rho[q] + G.rho[q + e]) / T(2);
-                gr += -g / (re * re) / T(2);
+                const T b = buoy(G.rho[q], G.rho[q + e]);
+                gr += -g * (b * b) / T(2);
             }
         }
     }

@@ -82,6 +82,19 @@ __device__ __forceinline__ int shot_of(const int *s_base, int nshot, int w)
 }
 
 // Tap number of (i,j,k) in a source box, or -1.
+// Effective buoyancy between two density samples, 1 / ((a + b) / 2) (Sec. 2.2.1).  FP32
+// uses the hardware reciprocal (within 1 ulp); FP64 the correctly rounded division.
+__device__ __forceinline__ float buoy(float a, float b) { return __builtin_amdgcn_rcpf((a + b) * 0.5f); }
+__device__ __forceinline__ double buoy(double a, double b) { return 1.0 / ((a + b) * 0.5); }
+
+// True when some tap of source component c lies in the box [i0, i1) x [j0, j1) x [k0, k1).
+template <typename T>
+__device__ __forceinline__ bool taps_in(const Inject<T> &s, int c, int i0, int i1, int j0, int j1, int k0, int k1)
+{
+    return s.i0[c] + 1 >= i0 && s.i0[c] < i1 && s.j0[c] + 1 >= j0 && s.j0[c] < j1 && s.k0[c] + 1 >= k0 &&
+           s.k0[c] < k1;
+}
+
 template <typename T>
 __device__ __forceinline__ int tap_of(const Inject<T> &s, int c, int i, int j, int k)
 {

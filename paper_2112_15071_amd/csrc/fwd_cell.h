@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) vel_cell(Grid<T> G, Inject<T> src, int n)
         T d = dstag(rds<SXX, FS>(G, i + 1, j, k), rds<SXX, FS>(G, i, j, k), rds<SXX, FS>(G, i + 2, j, k), rds<SXX, FS>(G, i - 1, j, k), rdx)
             + dstag(rds<SXY, FS>(G, i, j, k), rds<SXY, FS>(G, i, j - 1, k), rds<SXY, FS>(G, i, j + 1, k), rds<SXY, FS>(G, i, j - 2, k), rdx)
             + dstag(rds<SXZ, FS>(G, i, j, k), rds<SXZ, FS>(G, i, j, k - 1), rds<SXZ, FS>(G, i, j, k + 1), rds<SXZ, FS>(G, i, j, k - 2), rdx);
-        const T b = T(1) / ((G.rho[p] + G.rho[p + 1]) / T(2));
+        const T b = buoy(G.rho[p], G.rho[p + 1]);
         T v = G.f[VX][p] + G.dt * b * d;
         const int t = tap_of(src, VX, i, j, k);
         if (t >= 0) v += b * src.c[VX][t] * s;
@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) vel_cell(Grid<T> G, Inject<T> src, int n)
         T d = dstag(rds<SXY, FS>(G, i, j, k), rds<SXY, FS>(G, i - 1, j, k), rds<SXY, FS>(G, i + 1, j, k), rds<SXY, FS>(G, i - 2, j, k), rdx)
             + dstag(rds<SYY, FS>(G, i, j + 1, k), rds<SYY, FS>(G, i, j, k), rds<SYY, FS>(G, i, j + 2, k), rds<SYY, FS>(G, i, j - 1, k), rdx)
             + dstag(rds<SYZ, FS>(G, i, j, k), rds<SYZ, FS>(G, i, j, k - 1), rds<SYZ, FS>(G, i, j, k + 1), rds<SYZ, FS>(G, i, j, k - 2), rdx);
-        const T b = T(1) / ((G.rho[p] + G.rho[p + G.sy]) / T(2));
+        const T b = buoy(G.rho[p], G.rho[p + G.sy]);
         T v = G.f[VY][p] + G.dt * b * d;
         const int t = tap_of(src, VY, i, j, k);
         if (t >= 0) v += b * src.c[VY][t] * s;
@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(256) vel_cell(Grid<T> G, Inject<T> src, int n)
         T d = dstag(rds<SXZ, FS>(G, i, j, k), rds<SXZ, FS>(G, i - 1, j, k), rds<SXZ, FS>(G, i + 1, j, k), rds<SXZ, FS>(G, i - 2, j, k), rdx)
             + dstag(rds<SYZ, FS>(G, i, j, k), rds<SYZ, FS>(G, i, j - 1, k), rds<SYZ, FS>(G, i, j + 1, k), rds<SYZ, FS>(G, i, j - 2, k), rdx)
             + dstag(rds<SZZ, FS>(G, i, j, k + 1), rds<SZZ, FS>(G, i, j, k), rds<SZZ, FS>(G, i, j, k + 2), rds<SZZ, FS>(G, i, j, k - 1), rdx);
-        const T b = T(1) / ((G.rho[p] + G.rho[p + G.sz]) / T(2));
+        const T b = buoy(G.rho[p], G.rho[p + G.sz]);
         T v = G.f[VZ][p] + G.dt * b * d;
         const int t = tap_of(src, VZ, i, j, k);
         if (t >= 0) v += b * src.c[VZ][t] * s;

@@ -334,7 +334,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
             const T d = dstag(Lxx[br + 1], Lxx[br], Lxx[br + 2], Lxx[br - 1], rdx)
                       + dstag(Lxy[br], Lxy[br - BX], Lxy[br + BX], Lxy[br - 2 * BX], rdx)
                       + dstag(qxz[2], qxz[1], qxz[3], qxz[0], rdx);
-            const T bb = T(1) / ((r0 + Lr[br + 1]) / T(2));
+            const T bb = buoy(r0, Lr[br + 1]);
             T v = vx0 + dt * bb * d;
             if (srcw) v += bb * coef(VX, tap(VX, p)) * s;
             v = v * (gxh * gyi * gz_i);
@@ -344,7 +344,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
             const T d = dstag(Lxy[br], Lxy[br - 1], Lxy[br + 1], Lxy[br - 2], rdx)
                       + dstag(Lyy[br + BX], Lyy[br], Lyy[br + 2 * BX], Lyy[br - BX], rdx)
                       + dstag(qyz[2], qyz[1], qyz[3], qyz[0], rdx);
-            const T bb = T(1) / ((r0 + Lr[br + BX]) / T(2));
+            const T bb = buoy(r0, Lr[br + BX]);
             T v = vy0 + dt * bb * d;
             if (srcw) v += bb * coef(VY, tap(VY, p)) * s;
             v = v * (gxi * gyh * gz_i);
@@ -354,7 +354,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
             const T d = dstag(Lxz[br], Lxz[br - 1], Lxz[br + 1], Lxz[br - 2], rdx)
                       + dstag(Lyz[br], Lyz[br - BX], Lyz[br + BX], Lyz[br - 2 * BX], rdx)
                       + dstag(qzz[3], qzz[2], qzz[4], qzz[1], rdx);
-            const T bb = T(1) / ((r0 + r1) / T(2));
+            const T bb = buoy(r0, r1);
             T v = vz0 + dt * bb * d;
             if (srcw) v += bb * coef(VZ, tap(VZ, p)) * s;
             v = v * (gxi * gyi * gz_h);

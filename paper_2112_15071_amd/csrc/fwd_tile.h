@@ -257,6 +257,10 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     const T gyh = in ? G.g[1][1][j] : T(0), gyi = in ? G.g[1][0][j] : T(0);
     const unsigned st_vx = (in && i <= nx - 2) ? oc : kOOB;
     const unsigned st_vy = (in && j <= ny - 2) ? oc : kOOB;
+    // a force-source tap in this tile (uniform): elsewhere the source terms are skipped
+    const bool srcv = src.on && (taps_in(src, VX, i0, i0 + TX, j0, j0 + TY, k0, k1) ||
+                                 taps_in(src, VY, i0, i0 + TX, j0, j0 + TY, k0, k1) ||
+                                 taps_in(src, VZ, i0, i0 + TX, j0, j0 + TY, k0, k1));
     constexpr bool fwd = MODE == kFwd || MODE == kFwdSave;
     constexpr bool use_rho = MODE != kAdjA;
 
@@ -344,9 +348,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                       + dstag(Lxy[ox], Lxy[ox - W3], Lxy[ox + W3], Lxy[ox - 2 * W3], rdx)
                       + dstag(qxz[2], qxz[1], qxz[3], qxz[0], rdx);
             if constexpr (fwd) {
-                const T bb = T(1) / ((r0 + Lr[ty * WR + tx + 1]) / T(2));
+                const T bb = buoy(r0, Lr[ty * WR + tx + 1]);
                 T v = vx0 + dt * bb * d;
-                v += bb * pick(src.c[VX], tap_of(src, VX, i, j, k)) * s;
+                if (srcv) v += bb * pick(src.c[VX], tap_of(src, VX, i, j, k)) * s;
                 v = v * (gxh * gyi * gz_i);
                 st(ovx, st_vx + pw, v);
                 if constexpr (MODE == kFwdSave) st(wfield(G.save[VX], w), st_vx + pw, v);
@@ -355,9 +359,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             } else {
                 const T u = (gxh * gyi * gz_i) * vx0;
                 T g = dt * d * u;
-                g += pick(src.c[VX], tap_of(src, VX, i, j, k)) * s * u;
+                if (srcv) g += pick(src.c[VX], tap_of(src, VX, i, j, k)) * s * u;
                 st(wfield(io.acc[0], w), st_vx + pw, ga0 + g);
-                st(wfield(io.out[0], w), st_vx + pw, u / ((r0 + Lr[ty * WR + tx + 1]) / T(2)));
+                st(wfield(io.out[0], w), st_vx + pw, u * buoy(r0, Lr[ty * WR + tx + 1]));
             }
         }
         {
@@ -367,9 +371,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                       + dstag(Lyy[oy + TX], Lyy[oy], Lyy[oy + 2 * TX], Lyy[oy - TX], rdx)
                       + dstag(qyz[2], qyz[1], qyz[3], qyz[0], rdx);
             if constexpr (fwd) {
-                const T bb = T(1) / ((r0 + Lr[(ty + 1) * WR + tx]) / T(2));
+                const T bb = buoy(r0, Lr[(ty + 1) * WR + tx]);
                 T v = vy0 + dt * bb * d;
-                v += bb * pick(src.c[VY], tap_of(src, VY, i, j, k)) * s;
+                if (srcv) v += bb * pick(src.c[VY], tap_of(src, VY, i, j, k)) * s;
                 v = v * (gxi * gyh * gz_i);
                 st(ovy, st_vy + pw, v);
                 if constexpr (MODE == kFwdSave) st(wfield(G.save[VY], w), st_vy + pw, v);
@@ -378,9 +382,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             } else {
                 const T u = (gxi * gyh * gz_i) * vy0;
                 T g = dt * d * u;
-                g += pick(src.c[VY], tap_of(src, VY, i, j, k)) * s * u;
+                if (srcv) g += pick(src.c[VY], tap_of(src, VY, i, j, k)) * s * u;
                 st(wfield(io.acc[1], w), st_vy + pw, ga1 + g);
-                st(wfield(io.out[1], w), st_vy + pw, u / ((r0 + Lr[(ty + 1) * WR + tx]) / T(2)));
+                st(wfield(io.out[1], w), st_vy + pw, u * buoy(r0, Lr[(ty + 1) * WR + tx]));
             }
         }
         {
@@ -391,9 +395,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                       + dstag(qzz[2], qzz[1], qzz[3], qzz[0], rdx);
             const unsigned st_vz = k <= nz - 2 ? oc : kOOB;
             if constexpr (fwd) {
-                const T bb = T(1) / ((r0 + r1) / T(2));
+                const T bb = buoy(r0, r1);
                 T v = vz0 + dt * bb * d;
-                v += bb * pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s;
+                if (srcv) v += bb * pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s;
                 v = v * (gxi * gyi * gz_h);
                 st(ovz, st_vz + pw, v);
                 if constexpr (MODE == kFwdSave) st(wfield(G.save[VZ], w), st_vz + pw, v);
@@ -402,9 +406,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             } else {
                 const T u = (gxi * gyi * gz_h) * vz0;
                 T g = dt * d * u;
-                g += pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s * u;
+                if (srcv) g += pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s * u;
                 st(wfield(io.acc[2], w), st_vz + pw, ga2 + g);
-                st(wfield(io.out[2], w), st_vz + pw, u / ((r0 + r1) / T(2)));
+                st(wfield(io.out[2], w), st_vz + pw, u * buoy(r0, r1));
             }
         }
         qxz[0] = qxz[1]; qxz[1] = qxz[2]; qxz[2] = qxz[3]; qxz[3] = nxz;
