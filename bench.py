@@ -12,6 +12,8 @@ Also reported (same JSON line):
   gradient -- the 8-shot 256^3 FWI gradient (1500 steps, checkpoints every 50): per-shot
               loop vs batched waves (shots/s);
   roofline -- the dominant forward kernel's algorithmic bytes / its HIP-event duration;
+  c2_forward -- the 512x512x256 free-surface workload (300 steps);
+  stream_copy_gbs -- a plain 1 GiB device copy (read + write GB/s), the practical ceiling;
   cpu_baseline -- the FP64 oracle on a bounded sample on this host's cores.
 
     python bench.py [--steps 2000] [--warmup 100] [--gpus 1] [--no-batch] [--no-grad]
@@ -146,6 +148,56 @@ def bench_forward(K, Wm, kernel=None):
                       both=both, kernel=kern, traffic=measured_traffic(kern, dom))
 
 
+def bench_c2(K=300):
+    """The 512 x 512 x 256 free-surface workload (30-cell sponge on five faces), K steps."""
+    import torch
+
+    import workloads as W
+    from paper_2112_15071_amd import Simulator
+
+    dev = torch.device("cuda:0")
+    log(f"[bench] 512x512x256 free-surface workload: {K} steps")
+    shot = W.c2(nt=K)
+    lam, mu, rho = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (shot.lam, shot.mu, shot.rho))
+    wav = torch.as_tensor(shot.wavelet, dtype=torch.float32).to(dev)
+    sim = Simulator(lam, mu, rho, shot.h, shot.dt, K, sponge=shot.sponge, free_surface=True, device=dev)
+    sim.autotune(steps=10)
+    traces = torch.empty((shot.rec_pos.shape[0], 3, K), dtype=torch.float32, device=dev)
+    sim.forward(shot.src_pos, shot.moment, shot.force, wav, shot.rec_pos, traces=traces)  # warm-up
+    sync()
+    t0 = time.perf_counter()
+    sim.forward(shot.src_pos, shot.moment, shot.force, wav, shot.rec_pos, traces=traces)
+    sync()
+    el = time.perf_counter() - t0
+    kern = sim.kernel()
+    sim.close()
+    gcs = shot.cells * K / el / 1e9
+    gbs = step_bytes(kern) * shot.cells * K / el / 1e9
+    log(f"[bench] c2: {el:.3f} s -> {gcs:.2f} Gcell-steps/s, {gbs:.0f} GB/s")
+    return dict(gcs=round(gcs, 3), steps=K, seconds=round(el, 4), kernel=kern, hbm_gbs_whole_step=round(gbs, 1),
+                hbm_frac_whole_step=round(gbs / HBM_PEAK_GBS, 4))
+
+
+def stream_copy_ceiling(reps=20):
+    """Device-to-device copy of 1 GiB with torch, timed with HIP events on the current
+    stream: read + write bytes per second (the practical HBM ceiling of a plain stream)."""
+    import torch
+
+    n = 1 << 28
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    log(f"[bench] 1 GiB device copy: {gbs:.0f} GB/s")
+    return round(gbs, 1)
+
+
 def bench_batch():
     import torch
 
@@ -182,7 +234,8 @@ def bench_batch():
         s.close()
     return dict(loop_gcs=round(cells_steps / t_loop / 1e9, 3), batched_gcs=round(cells_steps / t_graph / 1e9, 3),
                 loop_s=round(t_loop, 3), batched_s=round(t_graph, 3), speedup=round(t_loop / t_graph, 3),
-                tile=[tune["tile_x"], tune["tile_y"]], workgroups=tune["workgroups"], cell_steps=cells_steps)
+                tile=[tune["tile_x"], tune["tile_y"]], tile2=[tune["tile2_x"], tune["tile2_y"]],
+                workgroups=tune["workgroups"], cell_steps=cells_steps)
 
 
 def bench_gradient(wave=4, nshots=8):
@@ -297,8 +350,14 @@ def cpu_baseline(shot, ns):
     oracle.forward(cfg, shot.lam, shot.mu, shot.rho, src, shot.wavelet[:ns], shot.rec_pos)
     dt = time.perf_counter() - t0
     cells = int(shot.cells)
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
+    except OSError:
+        pass
     return {"value": round(cells * ns / dt / 1e9, 5), "unit": "Gcell-steps/s", "cores": oracle.get_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu,
             "sample": f"FP64 oracle on the 256^3 workload at full size, first {ns} of 2000 steps ({dt:.1f} s)"}
 
 
@@ -307,7 +366,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps for the CPU baseline sample (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=24, help="oracle steps for the CPU baseline sample (0: skip)")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 512x512x256 free-surface section")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--kernel", metavar="VARIANT,TX,TY,ZC", default=None,
@@ -326,6 +386,8 @@ def main():
         counters_run(args.counters, args.steps)
         return
     shot, f = bench_forward(args.steps, args.warmup, args.kernel)
+    copy_gbs = stream_copy_ceiling()
+    c2 = None if args.no_c2 else bench_c2()
     batch = None if args.no_batch else bench_batch()
     grad = None if args.no_grad else bench_gradient(nshots=args.grad_shots)
     cpu = cpu_baseline(shot, args.cpu_steps) if args.cpu_steps > 0 else None
@@ -365,6 +427,8 @@ def main():
             "avg_kernel_ms": {k: round(v, 5) for k, v in f["per"].items()},
             "bytes_per_launch": f["bytes_launch"],
         },
+        "stream_copy_gbs": copy_gbs,
+        "c2_forward": c2,
         "batched_forward": batch,
         "gradient": grad,
         "cpu_baseline": cpu,

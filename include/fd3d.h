@@ -186,13 +186,19 @@ int fd3d_batch_create(fd3d_batch **out, int nshot, fd3d_ctx *const *ctxs, void *
  * persistent workgroups (0: CUs x occupancy, rounded to a multiple of 8). */
 int fd3d_batch_set_kernel(fd3d_batch *b, int tile_x, int tile_y, int workgroups);
 
+/* A second tile shape with the same workgroup size for the shots whose rows it covers
+ * with fewer idle columns (tile2_x = tile2_y = 0: none).  Supported pairs: FP32 256x4 +
+ * 64x16, 128x8 + 64x16, 256x4 + 128x8, 128x4 + 64x8; FP64 128x4 + 64x8.  FD3D_EINVAL
+ * otherwise.  fd3d_batch_set_kernel sets one shape. */
+int fd3d_batch_set_tiles(fd3d_batch *b, int tile_x, int tile_y, int tile2_x, int tile2_y, int workgroups);
+
 /* Times `steps` batched steps (sources and receivers off, one warm-up run each) for
- * every supported tile shape, with the persistent grid and with one workgroup per tile,
- * keeps the fastest for later batch calls and writes it to *tile_x, *tile_y,
- * *workgroups (0 = persistent) and its ms per step to *best_ms (each when non-NULL).
- * Every shot's forward state is zeroed afterwards.  Synchronises the stream. */
-int fd3d_batch_autotune(fd3d_batch *b, int steps, int *tile_x, int *tile_y, int *workgroups, double *best_ms,
-                        void *hip_stream);
+ * every supported tile shape and pair of shapes, with the persistent grid and with one
+ * workgroup per tile, keeps the fastest for later batch calls and writes it to best =
+ * {tile_x, tile_y, tile2_x, tile2_y, workgroups (0 = persistent)} and its ms per step to
+ * *best_ms (each when non-NULL).  Every shot's forward state is zeroed afterwards.
+ * Synchronises the stream. */
+int fd3d_batch_autotune(fd3d_batch *b, int steps, int best[5], double *best_ms, void *hip_stream);
 
 /* srcs[nshot] (or NULL), nrec[nshot], rec_pos[nshot] (host double[nrec][3] each),
  * traces[nshot] (device T[nrec][3][nt] each); flags as fd3d_forward. */

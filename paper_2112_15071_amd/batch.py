@@ -31,8 +31,11 @@ class BatchSimulator:
     def handle(self) -> int:
         return self._b
 
-    def set_kernel(self, tile_x: int, tile_y: int, workgroups: int = 0) -> None:
-        _abi.fd3d_batch_set_kernel(self._b, tile_x, tile_y, workgroups)
+    def set_kernel(self, tile_x: int, tile_y: int, workgroups: int = 0, tile2=None) -> None:
+        """Tile shape of the batched launches; tile2 = (tile_x, tile_y) of a second shape
+        with the same workgroup size for the shots it covers with fewer idle columns."""
+        t2 = tile2 or (0, 0)
+        _abi.fd3d_batch_set_tiles(self._b, tile_x, tile_y, t2[0], t2[1], workgroups)
 
     def autotune(self, steps: int = 10, cache: bool = True) -> dict:
         """Autotune every distinct grid shape of the batch for single-shot runs (each

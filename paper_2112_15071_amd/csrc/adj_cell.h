@@ -181,7 +181,7 @@ __device__ __forceinline__ void adj_vel_body(const Grid<T> &G, const AdjGrid<T> 
         const T u = damp(G, VX, i, j, k) * A.a[VX][p];
         T g = dt * d * u;
         const int t = tap_of(src, VX, i, j, k);
-        if (t >= 0) g += src.c[VX][t] * s * u;
+        if (t >= 0) g += src.coef[VX * 8 + t] * s * u;
         A.gb[0][p] += g;
     }
     if (j <= G.ny - 2) {
@@ -191,7 +191,7 @@ __device__ __forceinline__ void adj_vel_body(const Grid<T> &G, const AdjGrid<T> 
         const T u = damp(G, VY, i, j, k) * A.a[VY][p];
         T g = dt * d * u;
         const int t = tap_of(src, VY, i, j, k);
-        if (t >= 0) g += src.c[VY][t] * s * u;
+        if (t >= 0) g += src.coef[VY * 8 + t] * s * u;
         A.gb[1][p] += g;
     }
     if (k <= G.nz - 2) {
@@ -201,7 +201,7 @@ __device__ __forceinline__ void adj_vel_body(const Grid<T> &G, const AdjGrid<T> 
         const T u = damp(G, VZ, i, j, k) * A.a[VZ][p];
         T g = dt * d * u;
         const int t = tap_of(src, VZ, i, j, k);
-        if (t >= 0) g += src.c[VZ][t] * s * u;
+        if (t >= 0) g += src.coef[VZ * 8 + t] * s * u;
         A.gb[2][p] += g;
     }
 }

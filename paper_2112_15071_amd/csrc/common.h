@@ -47,13 +47,14 @@ template <typename T> struct Grid {
 };
 
 // A point source as kernel argument: per component, the base of its 2x2x2 tap box
-// on that component's subgrid and the eight coefficients (x fastest, then y, z).
+// on that component's subgrid, and in device memory the eight coefficients per
+// component (x fastest, then y, z), read only where a tap lies.
 // Velocity components: dt w F / dx^3 (times b and s[n] in the kernel).
 // Stress components:  -dt w M / dx^3 (times s[n] in the kernel).
 template <typename T> struct Inject {
     int on;
     int i0[NFIELD], j0[NFIELD], k0[NFIELD];
-    T c[NFIELD][8];
+    const T *coef;  // [NFIELD][8]
     const T *wavelet;
 };
 
@@ -81,7 +82,6 @@ __device__ __forceinline__ int shot_of(const int *s_base, int nshot, int w)
     return __builtin_amdgcn_readfirstlane(s);
 }
 
-// Tap number of (i,j,k) in a source box, or -1.
 // Effective buoyancy between two density samples, 1 / ((a + b) / 2) (Sec. 2.2.1).  FP32
 // uses the hardware reciprocal (within 1 ulp); FP64 the correctly rounded division.
 __device__ __forceinline__ float buoy(float a, float b) { return __builtin_amdgcn_rcpf((a + b) * 0.5f); }
@@ -95,6 +95,13 @@ __device__ __forceinline__ bool taps_in(const Inject<T> &s, int c, int i0, int i
            s.k0[c] < k1;
 }
 
+// Coefficient of tap t (-1: none) of source component c.
+template <typename T> __device__ __forceinline__ T coef_of(const Inject<T> &s, int c, int t)
+{
+    return t >= 0 ? s.coef[c * 8 + t] : T(0);
+}
+
+// Tap number of (i,j,k) in a source box, or -1.
 template <typename T>
 __device__ __forceinline__ int tap_of(const Inject<T> &s, int c, int i, int j, int k)
 {

@@ -54,6 +54,7 @@ size_t rectap_bytes(int tsize) { return 8 * sizeof(int) + 8 * (size_t)tsize; }
 struct Layout {
     size_t field[2][NFIELD];
     size_t prof[3][2];
+    size_t src;     // source coefficients [NFIELD][8]
     size_t rec;
     size_t colors;  // receiver order grouped by colour (tap-disjoint sets), int[max_rec]
     size_t part;
@@ -80,6 +81,8 @@ Layout make_layout(int nx, int ny, int nz, int tsize, int max_rec)
             L.prof[a][h] = off;
             off += round_up((size_t)n[a] * tsize, kAlign);
         }
+    L.src = off;
+    off += round_up((size_t)NFIELD * 8 * tsize, kAlign);
     L.rec = off;
     off += round_up((size_t)max_rec * 3 * rectap_bytes(tsize), kAlign);
     L.colors = off;
@@ -159,6 +162,7 @@ struct fd3d_ctx {
     Layout L;
     double info[4];
     std::vector<unsigned char> prof_host;  // typed profiles, kept for the async upload
+    std::vector<unsigned char> src_host;   // source coefficients, kept for the async upload
     std::vector<unsigned char> rec_host;   // receiver descriptors, kept for the async upload
     std::vector<int> color_host;           // receivers grouped by colour, kept for the async upload
     std::vector<int> color_off;            // colour c holds color_host[color_off[c] .. color_off[c+1])
@@ -263,9 +267,14 @@ template <typename T> void zero_fields(fd3d_ctx *c, hipStream_t st)
 
 void zero_fields_any(fd3d_ctx *c, hipStream_t st);
 
-template <typename T> int build_source(const fd3d_ctx *c, const fd3d_source *src, Inject<T> &inj)
+// The source's tap boxes into inj and its coefficients into the host staging buffer
+// (uploaded by stage_inputs).
+template <typename T> int build_source(fd3d_ctx *c, const fd3d_source *src, Inject<T> &inj)
 {
     std::memset(&inj, 0, sizeof inj);
+    c->src_host.assign((size_t)NFIELD * 8 * sizeof(T), 0);
+    T *coef = (T *)c->src_host.data();
+    inj.coef = (const T *)(c->ws + c->L.src);
     for (int f = 0; f < NFIELD; ++f) inj.i0[f] = inj.j0[f] = inj.k0[f] = -(1 << 28);
     if (!src) return FD3D_OK;
     const double h3 = c->dx * c->dx * c->dx;
@@ -278,7 +287,7 @@ template <typename T> int build_source(const fd3d_ctx *c, const fd3d_source *src
         if (!point_taps(VX + q, src->pos, c->n, base, w))
             return fail(FD3D_ERANGE, "force source taps leave the active samples of v" + std::string(1, "xyz"[q]));
         inj.i0[VX + q] = base[0]; inj.j0[VX + q] = base[1]; inj.k0[VX + q] = base[2];
-        for (int m = 0; m < 8; ++m) inj.c[VX + q][m] = (T)(c->dt * w[m] * src->force[q] / h3);
+        for (int m = 0; m < 8; ++m) coef[(VX + q) * 8 + m] = (T)(c->dt * w[m] * src->force[q] / h3);
         any = true;
     }
     for (int q = 0; q < 6; ++q)
@@ -288,7 +297,7 @@ template <typename T> int build_source(const fd3d_ctx *c, const fd3d_source *src
             return fail(FD3D_ERANGE, "moment source taps leave the normal-stress grid");
         for (int q = 0; q < 3; ++q) {
             inj.i0[SXX + q] = base[0]; inj.j0[SXX + q] = base[1]; inj.k0[SXX + q] = base[2];
-            for (int m = 0; m < 8; ++m) inj.c[SXX + q][m] = (T)(-c->dt * w[m] * src->moment[q] / h3);
+            for (int m = 0; m < 8; ++m) coef[(SXX + q) * 8 + m] = (T)(-c->dt * w[m] * src->moment[q] / h3);
         }
         any = true;
     }
@@ -298,7 +307,7 @@ template <typename T> int build_source(const fd3d_ctx *c, const fd3d_source *src
         if (!point_taps(comp, src->pos, c->n, base, w))
             return fail(FD3D_ERANGE, "moment source taps leave the shear-stress grid");
         inj.i0[comp] = base[0]; inj.j0[comp] = base[1]; inj.k0[comp] = base[2];
-        for (int m = 0; m < 8; ++m) inj.c[comp][m] = (T)(-c->dt * w[m] * src->moment[q] / h3);
+        for (int m = 0; m < 8; ++m) coef[(comp) * 8 + m] = (T)(-c->dt * w[m] * src->moment[q] / h3);
         any = true;
     }
     if (any && !src->wavelet) return fail(FD3D_EINVAL, "source wavelet pointer is NULL");
@@ -307,13 +316,23 @@ template <typename T> int build_source(const fd3d_ctx *c, const fd3d_source *src
     return FD3D_OK;
 }
 
-template <typename T> int stage_receivers(fd3d_ctx *c, int nrec, const double *rec_pos, hipStream_t st)
+// Builds the source (tap boxes into inj) and the receiver descriptors and colours, and
+// uploads them from the context's host staging buffers (after the previous call's
+// uploads from those buffers are done).
+template <typename T>
+int stage_inputs(fd3d_ctx *c, const fd3d_source *src, Inject<T> &inj, int nrec, const double *rec_pos,
+                 hipStream_t st)
 {
-    if (nrec == 0) return FD3D_OK;
     if (c->staged_pending) {
         HIP_TRY(hipEventSynchronize(c->staged));
         c->staged_pending = false;
     }
+    int rc = build_source<T>(c, src, inj);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.src, c->src_host.data(), c->src_host.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(c->staged, st));
+    c->staged_pending = true;
+    if (nrec == 0) return FD3D_OK;
     c->rec_host.assign((size_t)nrec * 3 * sizeof(RecTap<T>), 0);
     RecTap<T> *t = (RecTap<T> *)c->rec_host.data();
     int base[3];
@@ -553,7 +572,7 @@ template <typename T> FusedArgs<T> fused_args(const fd3d_ctx *c, const Inject<T>
         A.origin[0][stag(q, 0)] = inj.i0[q];
         A.origin[1][stag(q, 1)] = inj.j0[q];
         A.origin[2][stag(q, 2)] = inj.k0[q];
-        for (int m = 0; m < 8; ++m) A.coef[q][m] = inj.c[q][m];
+        for (int m = 0; m < 8; ++m) A.coef[q][m] = ((const T *)c->src_host.data())[q * 8 + m];
     }
     return A;
 }
@@ -637,9 +656,7 @@ int forward_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
                  hipStream_t st, char *gws = nullptr, const GradLayout *GL = nullptr)
 {
     Inject<T> inj;
-    int rc = build_source<T>(c, src, inj);
-    if (rc) return rc;
-    rc = stage_receivers<T>(c, nrec, rec_pos, st);
+    int rc = stage_inputs<T>(c, src, inj, nrec, rec_pos, st);
     if (rc) return rc;
     if (!(flags & FD3D_KEEP_STATE)) zero_fields<T>(c, st);
     const RecTap<T> *taps = (const RecTap<T> *)(c->ws + c->L.rec);
@@ -741,9 +758,7 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
                  T *g_mu, T *g_rho, char *gws, const GradLayout &GL, hipStream_t st)
 {
     Inject<T> inj;
-    int rc = build_source<T>(c, src, inj);
-    if (rc) return rc;
-    rc = stage_receivers<T>(c, nrec, rec_pos, st);
+    int rc = stage_inputs<T>(c, src, inj, nrec, rec_pos, st);
     if (rc) return rc;
     Grid<T> G = make_grid<T>(c);
     AdjGrid<T> A = make_adj<T>(gws, GL);
@@ -853,6 +868,7 @@ struct fd3d_batch {
     size_t ws_bytes;
     size_t off_fwd, off_rec;
     int tile_x, tile_y, wgs_req;
+    int tile2_x, tile2_y;  // optional second tile shape (same workgroup size), 0: none
     std::vector<unsigned char> fwd_host, rec_host;
     hipEvent_t staged;
     bool staged_pending;
@@ -874,37 +890,93 @@ size_t batch_desc_bytes(int nshot, int tsize)
     return round_up((size_t)nshot * f, kAlign) + round_up((size_t)nshot * r, kAlign);
 }
 
-template <typename T, int TX, int TY, bool FS>
+// Supported pairs of batch tile shapes (primary, second; equal workgroup sizes): FP32
+// 256x4 + 64x16, 128x8 + 64x16, 256x4 + 128x8, 128x4 + 64x8; FP64 128x4 + 64x8.
+bool pair_supported(int tsize, int tx, int ty, int tx2, int ty2)
+{
+    const long key = ((long)tx * 1000 + ty) * 1000000 + tx2 * 1000 + ty2;
+    if (key == 128004064008L) return true;
+    if (tsize == 8) return false;
+    return key == 256004064016L || key == 128008064016L || key == 256004128008L;
+}
+
+// Calls f(TX, TY, TX2, TY2) with the batch's tile shapes as integral constants (TX2 = 0:
+// one shape).
+template <typename T, typename F> decltype(auto) with_batch_tiles(const fd3d_batch *b, F &&f)
+{
+    using Z = std::integral_constant<int, 0>;
+    if (b->tile2_x == 0)
+        return with_tile<T>(b->tile_x, b->tile_y, [&](auto tx, auto ty) { return f(tx, ty, Z{}, Z{}); });
+    using X64 = std::integral_constant<int, 64>;
+    using X128 = std::integral_constant<int, 128>;
+    using X256 = std::integral_constant<int, 256>;
+    using Y4 = std::integral_constant<int, 4>;
+    using Y8 = std::integral_constant<int, 8>;
+    using Y16 = std::integral_constant<int, 16>;
+    if constexpr (sizeof(T) == 4) {
+        if (b->tile_x == 256 && b->tile2_x == 64) return f(X256{}, Y4{}, X64{}, Y16{});
+        if (b->tile_x == 128 && b->tile_y == 8) return f(X128{}, Y8{}, X64{}, Y16{});
+        if (b->tile_x == 256 && b->tile2_x == 128) return f(X256{}, Y4{}, X128{}, Y8{});
+    }
+    return f(X128{}, Y4{}, X64{}, Y8{});
+}
+
+// Tile map of one shot of the batch, and whether it uses the batch's second tile shape
+// (when that covers its rows with fewer idle columns).
+TileMap shot_tiles(const fd3d_batch *b, const fd3d_ctx *c, int &alt)
+{
+    int tx = b->tile_x, ty = b->tile_y;
+    alt = 0;
+    if (b->tile2_x > 0) {
+        const int pad1 = (c->n[0] + tx - 1) / tx * tx, pad2 = (c->n[0] + b->tile2_x - 1) / b->tile2_x * b->tile2_x;
+        if (pad2 < pad1) {
+            alt = 1;
+            tx = b->tile2_x;
+            ty = b->tile2_y;
+        }
+    }
+    TileMap tm;
+    tm.ntx = (c->n[0] + tx - 1) / tx;
+    tm.nty = (c->n[1] + ty - 1) / ty;
+    tm.zc = c->zchunk;
+    tm.nzc = (c->n[2] + c->zchunk - 1) / c->zchunk;
+    return tm;
+}
+
+template <typename T, int TX, int TY, int TX2, int TY2, bool FS>
 int launch_multi(fd3d_batch *b, const ShotFwd<T> *d, int n, int pass, hipStream_t st)
 {
     const int g = b->wgs, S = b->nshot, W = b->total_tiles;
     constexpr int NT = TX * TY;
     switch (pass) {
-    case kPassVel: vel_tile_multi<T, TX, TY, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
-    case kPassStress: stress_tile_multi<T, TX, TY, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
-    case kPassVelSave: vel_tile_multi<T, TX, TY, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n); break;
-    case kPassStressSave: stress_tile_multi<T, TX, TY, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n); break;
-    case kPassStressA: stress_tile_multi<T, TX, TY, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
-    case kPassVelA: vel_tile_multi<T, TX, TY, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
-    case kPassVelB: vel_tile_multi<T, TX, TY, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n); break;
-    default: stress_tile_multi<T, TX, TY, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassVel: vel_tile_multi<T, TX, TY, TX2, TY2, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassStress: stress_tile_multi<T, TX, TY, TX2, TY2, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassVelSave: vel_tile_multi<T, TX, TY, TX2, TY2, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassStressSave: stress_tile_multi<T, TX, TY, TX2, TY2, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassStressA: stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassVelA: vel_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassVelB: vel_tile_multi<T, TX, TY, TX2, TY2, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n); break;
+    default: stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n); break;
     }
     return FD3D_OK;
 }
 
 template <typename T, bool FS> int multi_pass(fd3d_batch *b, const ShotFwd<T> *d, int n, int pass, hipStream_t st)
 {
-    return with_tile<T>(b->tile_x, b->tile_y, [&](auto tx, auto ty) {
-        return launch_multi<T, decltype(tx)::value, decltype(ty)::value, FS>(b, d, n, pass, st);
+    return with_batch_tiles<T>(b, [&](auto tx, auto ty, auto tx2, auto ty2) {
+        return launch_multi<T, decltype(tx)::value, decltype(ty)::value, decltype(tx2)::value, decltype(ty2)::value,
+                            FS>(b, d, n, pass, st);
     });
 }
 
 template <typename T, bool FS> int multi_occupancy(const fd3d_batch *b)
 {
-    return with_tile<T>(b->tile_x, b->tile_y, [&](auto tx, auto ty) {
+    return with_batch_tiles<T>(b, [&](auto tx, auto ty, auto tx2, auto ty2) {
         constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
+        constexpr int TX2 = decltype(tx2)::value, TY2 = decltype(ty2)::value;
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, vel_tile_multi<T, TX, TY, FS>, TX * TY, 0) != hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, vel_tile_multi<T, TX, TY, TX2, TY2, FS>, TX * TY, 0) !=
+            hipSuccess)
             occ = 1;
         return occ > 0 ? occ : 1;
     });
@@ -942,19 +1014,12 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
         if (nr < 0 || nr > c->opts.max_receivers) return fail(FD3D_EINVAL, "shot " + std::to_string(s) + ": bad nrec");
         if (nr > 0 && (!rec_pos || !rec_pos[s] || !traces || !traces[s]))
             return fail(FD3D_EINVAL, "shot " + std::to_string(s) + ": rec_pos/traces is NULL");
-        int rc = build_source<T>(c, srcs ? &srcs[s] : nullptr, fw[s].src);
-        if (rc) return fail(rc, "shot " + std::to_string(s) + ": " + g_err);
-        rc = stage_receivers<T>(c, nr, nr ? rec_pos[s] : nullptr, st);
+        const int rc = stage_inputs<T>(c, srcs ? &srcs[s] : nullptr, fw[s].src, nr, nr ? rec_pos[s] : nullptr, st);
         if (rc) return fail(rc, "shot " + std::to_string(s) + ": " + g_err);
         fw[s].G = make_grid<T>(c);
-        TileMap tm;
-        tm.ntx = (c->n[0] + b->tile_x - 1) / b->tile_x;
-        tm.nty = (c->n[1] + b->tile_y - 1) / b->tile_y;
-        tm.zc = c->zchunk;
-        tm.nzc = (c->n[2] + c->zchunk - 1) / c->zchunk;
+        const TileMap tm = shot_tiles(b, c, fw[s].alt);
         fw[s].tm = tm;
         fw[s].base = tiles;
-        fw[s].pad = 0;
         tiles += tm.ntx * tm.nty * tm.nzc;
         for (int q = 0; q < 3; ++q) rr[s].v[q] = fw[s].G.f[VX + q];
         rr[s].taps = (const RecTap<T> *)(c->ws + c->L.rec);
@@ -983,7 +1048,8 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
     wgs = std::min(wgs, ((tiles + 7) / 8) * 8);
     wgs = std::max(8, (wgs + 7) / 8 * 8);
     const long key = ((long)tiles << 32) ^ ((long)recs << 16) ^ ((long)wgs << 4) ^ (flags & FD3D_KEEP_STATE) ^
-                     ((long)b->tile_x << 40) ^ ((long)b->tile_y << 52);
+                     ((long)b->tile_x << 40) ^ ((long)b->tile_y << 52) ^ ((long)b->tile2_x << 28) ^
+                     ((long)b->tile2_y << 34);
     b->total_tiles = tiles;
     b->total_rec = recs;
     b->wgs = wgs;
@@ -1091,9 +1157,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         if (!rec_pos || !rec_pos[s] || !traces || !traces[s] || !d_obs || !d_obs[s] || !g_lam || !g_lam[s] || !g_mu ||
             !g_mu[s] || !g_rho || !g_rho[s])
             return fail(FD3D_EINVAL, tag + "NULL pointer");
-        rc = build_source<T>(c, srcs ? &srcs[s] : nullptr, fw[s].src);
-        if (rc) return fail(rc, tag + g_err);
-        rc = stage_receivers<T>(c, nr, rec_pos[s], st);
+        rc = stage_inputs<T>(c, srcs ? &srcs[s] : nullptr, fw[s].src, nr, rec_pos[s], st);
         if (rc) return fail(rc, tag + g_err);
         const int cols = (int)c->color_off.size() - 1;
         if (cols > kMaxBatchColors) return fail(FD3D_EINVAL, tag + "receivers need more than 4 tap-disjoint colours");
@@ -1101,14 +1165,9 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         GL[s] = make_grad_layout(c, k);
         fw[s].G = make_grid<T>(c);
         std::memset(&fw[s].io, 0, sizeof fw[s].io);
-        TileMap tm;
-        tm.ntx = (c->n[0] + b->tile_x - 1) / b->tile_x;
-        tm.nty = (c->n[1] + b->tile_y - 1) / b->tile_y;
-        tm.zc = c->zchunk;
-        tm.nzc = (c->n[2] + c->zchunk - 1) / c->zchunk;
+        const TileMap tm = shot_tiles(b, c, fw[s].alt);
         fw[s].tm = tm;
         fw[s].base = tiles;
-        fw[s].pad = 0;
         tiles += tm.ntx * tm.nty * tm.nzc;
         for (int q = 0; q < 3; ++q) rr[s].v[q] = fw[s].G.f[VX + q];
         rr[s].taps = (const RecTap<T> *)(c->ws + c->L.rec);
@@ -1570,6 +1629,7 @@ int fd3d_batch_create(fd3d_batch **out, int nshot, fd3d_ctx *const *ctxs, void *
     else if (minx >= 128) { b->tile_x = 128; b->tile_y = 4; }
     else { b->tile_x = 64; b->tile_y = 8; }
     b->wgs_req = 0;
+    b->tile2_x = b->tile2_y = 0;
     b->staged_pending = false;
     b->graph_valid = false;
     b->graph_key = 0;
@@ -1589,26 +1649,37 @@ int fd3d_batch_create(fd3d_batch **out, int nshot, fd3d_ctx *const *ctxs, void *
 
 int fd3d_batch_set_kernel(fd3d_batch *b, int tile_x, int tile_y, int workgroups)
 {
+    return fd3d_batch_set_tiles(b, tile_x, tile_y, 0, 0, workgroups);
+}
+
+int fd3d_batch_set_tiles(fd3d_batch *b, int tile_x, int tile_y, int tile2_x, int tile2_y, int workgroups)
+{
     if (!b) return fail(FD3D_EINVAL, "batch is NULL");
     if (!tile_supported(b->tsize, tile_x, tile_y))
         return fail(FD3D_EINVAL, "unsupported tile shape " + std::to_string(tile_x) + "x" + std::to_string(tile_y));
+    if ((tile2_x || tile2_y) && !pair_supported(b->tsize, tile_x, tile_y, tile2_x, tile2_y))
+        return fail(FD3D_EINVAL, "unsupported pair of tile shapes");
     if (workgroups < 0) return fail(FD3D_EINVAL, "workgroups must be >= 0");
     b->tile_x = tile_x;
     b->tile_y = tile_y;
+    b->tile2_x = tile2_x;
+    b->tile2_y = tile2_y;
     b->wgs_req = workgroups;
     return FD3D_OK;
 }
 
-int fd3d_batch_autotune(fd3d_batch *b, int steps, int *tile_x, int *tile_y, int *workgroups, double *best_ms,
-                        void *hip_stream)
+int fd3d_batch_autotune(fd3d_batch *b, int steps, int best[5], double *best_ms, void *hip_stream)
 {
     if (!b) return fail(FD3D_EINVAL, "batch is NULL");
     if (steps < 1) return fail(FD3D_EINVAL, "steps must be >= 1");
     hipStream_t st = (hipStream_t)hip_stream;
-    static const int shapes[][2] = {{64, 4}, {64, 8}, {64, 16}, {128, 4}, {128, 8}, {256, 4}};
+    // single shapes, then pairs (primary, second)
+    static const int shapes[][4] = {{64, 4, 0, 0},    {64, 8, 0, 0},   {64, 16, 0, 0},   {128, 4, 0, 0},
+                                    {128, 8, 0, 0},   {256, 4, 0, 0},  {256, 4, 64, 16}, {128, 8, 64, 16},
+                                    {256, 4, 128, 8}, {128, 4, 64, 8}};
     const int nt_save = b->nt;
-    const int keep[3] = {b->tile_x, b->tile_y, b->wgs_req};
-    int win[3] = {keep[0], keep[1], keep[2]};
+    const int keep[5] = {b->tile_x, b->tile_y, b->tile2_x, b->tile2_y, b->wgs_req};
+    int win[5] = {keep[0], keep[1], keep[2], keep[3], keep[4]};
     double win_ms = 1e300;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -1617,16 +1688,21 @@ int fd3d_batch_autotune(fd3d_batch *b, int steps, int *tile_x, int *tile_y, int 
     int rc = FD3D_OK;
     for (const auto &sh : shapes) {
         if (!tile_supported(b->tsize, sh[0], sh[1])) continue;
+        if (sh[2] && !pair_supported(b->tsize, sh[0], sh[1], sh[2], sh[3])) continue;
         // persistent grid (CUs x occupancy) or one workgroup per tile
         for (int mode = 0; mode < 2 && !rc; ++mode) {
             b->tile_x = sh[0];
             b->tile_y = sh[1];
+            b->tile2_x = sh[2];
+            b->tile2_y = sh[3];
             b->wgs_req = 0;
             if (mode == 1) {
                 long tiles = 0;
-                for (const fd3d_ctx *c : b->ctx)
-                    tiles += (long)((c->n[0] + sh[0] - 1) / sh[0]) * ((c->n[1] + sh[1] - 1) / sh[1]) *
-                             ((c->n[2] + c->zchunk - 1) / c->zchunk);
+                for (const fd3d_ctx *c : b->ctx) {
+                    int alt = 0;
+                    const TileMap tm = shot_tiles(b, c, alt);
+                    tiles += (long)tm.ntx * tm.nty * tm.nzc;
+                }
                 b->wgs_req = (int)std::min<long>((tiles + 7) / 8 * 8, 1L << 30);
             }
             for (int rep = 0; rep < 2 && !rc; ++rep) {
@@ -1646,7 +1722,9 @@ int fd3d_batch_autotune(fd3d_batch *b, int steps, int *tile_x, int *tile_y, int 
                 win_ms = ms;
                 win[0] = b->tile_x;
                 win[1] = b->tile_y;
-                win[2] = b->wgs_req;
+                win[2] = b->tile2_x;
+                win[3] = b->tile2_y;
+                win[4] = b->wgs_req;
             }
         }
         if (rc) break;
@@ -1657,12 +1735,13 @@ int fd3d_batch_autotune(fd3d_batch *b, int steps, int *tile_x, int *tile_y, int 
     const int *use = rc ? keep : win;
     b->tile_x = use[0];
     b->tile_y = use[1];
-    b->wgs_req = use[2];
+    b->tile2_x = use[2];
+    b->tile2_y = use[3];
+    b->wgs_req = use[4];
     if (rc) return rc;
     for (fd3d_ctx *c : b->ctx) zero_fields_any(c, st);
-    if (tile_x) *tile_x = win[0];
-    if (tile_y) *tile_y = win[1];
-    if (workgroups) *workgroups = win[2];
+    if (best)
+        for (int q = 0; q < 5; ++q) best[q] = win[q];
     if (best_ms) *best_ms = win_ms / steps;
     return FD3D_OK;
 }

@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) vel_cell(Grid<T> G, Inject<T> src, int n)
         const T b = buoy(G.rho[p], G.rho[p + 1]);
         T v = G.f[VX][p] + G.dt * b * d;
         const int t = tap_of(src, VX, i, j, k);
-        if (t >= 0) v += b * src.c[VX][t] * s;
+        if (t >= 0) v += b * src.coef[VX * 8 + t] * s;
         v = v * (G.g[0][1][i] * G.g[1][0][j] * G.g[2][0][k]);
         G.f[VX][p] = v;
         if (G.save[VX]) G.save[VX][p] = v;
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) vel_cell(Grid<T> G, Inject<T> src, int n)
         const T b = buoy(G.rho[p], G.rho[p + G.sy]);
         T v = G.f[VY][p] + G.dt * b * d;
         const int t = tap_of(src, VY, i, j, k);
-        if (t >= 0) v += b * src.c[VY][t] * s;
+        if (t >= 0) v += b * src.coef[VY * 8 + t] * s;
         v = v * (G.g[0][0][i] * G.g[1][1][j] * G.g[2][0][k]);
         G.f[VY][p] = v;
         if (G.save[VY]) G.save[VY][p] = v;
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256) vel_cell(Grid<T> G, Inject<T> src, int n)
         const T b = buoy(G.rho[p], G.rho[p + G.sz]);
         T v = G.f[VZ][p] + G.dt * b * d;
         const int t = tap_of(src, VZ, i, j, k);
-        if (t >= 0) v += b * src.c[VZ][t] * s;
+        if (t >= 0) v += b * src.coef[VZ * 8 + t] * s;
         v = v * (G.g[0][0][i] * G.g[1][0][j] * G.g[2][1][k]);
         G.f[VZ][p] = v;
         if (G.save[VZ]) G.save[VZ][p] = v;
@@ -114,9 +114,9 @@ __global__ void __launch_bounds__(256) stress_cell(Grid<T> G, Inject<T> src, int
         T szz = G.f[SZZ][p] + dt * (l * tr + T(2) * m * ezz);
         int t = tap_of(src, SXX, i, j, k);
         if (t >= 0) {
-            sxx += src.c[SXX][t] * s;
-            syy += src.c[SYY][t] * s;
-            szz += src.c[SZZ][t] * s;
+            sxx += src.coef[SXX * 8 + t] * s;
+            syy += src.coef[SYY * 8 + t] * s;
+            szz += src.coef[SZZ * 8 + t] * s;
         }
         G.f[SXX][p] = sxx * gn;
         G.f[SYY][p] = syy * gn;
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(256) stress_cell(Grid<T> G, Inject<T> src, int
         const T mxy = ((G.mu[p] + G.mu[p + 1]) + (G.mu[p + G.sy] + G.mu[p + 1 + G.sy])) / T(4);
         T v = G.f[SXY][p] + dt * mxy * e;
         const int t = tap_of(src, SXY, i, j, k);
-        if (t >= 0) v += src.c[SXY][t] * s;
+        if (t >= 0) v += src.coef[SXY * 8 + t] * s;
         G.f[SXY][p] = v * (G.g[0][1][i] * G.g[1][1][j] * G.g[2][0][k]);
     }
     if (i <= G.nx - 2 && k <= G.nz - 2) {
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(256) stress_cell(Grid<T> G, Inject<T> src, int
         const T mxz = ((G.mu[p] + G.mu[p + 1]) + (G.mu[p + G.sz] + G.mu[p + 1 + G.sz])) / T(4);
         T v = G.f[SXZ][p] + dt * mxz * e;
         const int t = tap_of(src, SXZ, i, j, k);
-        if (t >= 0) v += src.c[SXZ][t] * s;
+        if (t >= 0) v += src.coef[SXZ * 8 + t] * s;
         G.f[SXZ][p] = v * (G.g[0][1][i] * G.g[1][0][j] * G.g[2][1][k]);
     }
     if (j <= G.ny - 2 && k <= G.nz - 2) {
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(256) stress_cell(Grid<T> G, Inject<T> src, int
         const T myz = ((G.mu[p] + G.mu[p + G.sy]) + (G.mu[p + G.sz] + G.mu[p + G.sy + G.sz])) / T(4);
         T v = G.f[SYZ][p] + dt * myz * e;
         const int t = tap_of(src, SYZ, i, j, k);
-        if (t >= 0) v += src.c[SYZ][t] * s;
+        if (t >= 0) v += src.coef[SYZ * 8 + t] * s;
         G.f[SYZ][p] = v * (G.g[0][0][i] * G.g[1][1][j] * G.g[2][1][k]);
     }
 }

@@ -199,13 +199,14 @@ template <typename T> struct TileIO {
     T *acc[5];  // gradient accumulators: (gl, gm, g_mu_xy, g_mu_xz, g_mu_yz) or (g_bx, g_by, g_bz)
 };
 
-// Coefficient of tap t (or 0) without a data-dependent memory access.
-template <typename T> __device__ __forceinline__ T pick(const T (&c)[8], int t)
+// Source coefficients of NC consecutive components starting at C0, staged in LDS when a
+// tap lies in the tile (on, uniform), so that the sweep reads them with LDS loads: a
+// global load inside the loop would make the wait for it also wait for the next plane's
+// prefetched loads.  Visible after the sweep's first barrier.
+template <typename T, int C0, int NC>
+__device__ __forceinline__ void stage_coef(T *lds, const Inject<T> &src, bool on, int tid)
 {
-    T v = T(0);
-#pragma unroll
-    for (int m = 0; m < 8; ++m) v = (t == m) ? c[m] : v;
-    return v;
+    if (on && tid < NC * 8) lds[tid] = src.coef[C0 * 8 + tid];
 }
 
 // ---------------------------------------------------------------------------------
@@ -261,6 +262,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     const bool srcv = src.on && (taps_in(src, VX, i0, i0 + TX, j0, j0 + TY, k0, k1) ||
                                  taps_in(src, VY, i0, i0 + TX, j0, j0 + TY, k0, k1) ||
                                  taps_in(src, VZ, i0, i0 + TX, j0, j0 + TY, k0, k1));
+    __shared__ T s_coef[3 * 8];
+    stage_coef<T, VX, 3>(s_coef, src, srcv, tid);
+    auto cf = [&](int c, int t) -> T { return t >= 0 ? s_coef[(c - VX) * 8 + (t & 7)] : T(0); };
     constexpr bool fwd = MODE == kFwd || MODE == kFwdSave;
     constexpr bool use_rho = MODE != kAdjA;
 
@@ -331,7 +335,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         Lr[hr.lds] = P.r;
         const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
         const T ga0 = P.g0, ga1 = P.g1, ga2 = P.g2;
-        // loads of plane k+1 and the queue heads (empty descriptors past the chunk)
+        // loads of plane k+1 and the queue heads (skipped past the chunk)
         const bool more = k + 1 < k1;
         loadplane(k + 1, more, P);
         const T nxz = zld(fxz, k + 2, more), nyz = zld(fyz, k + 2, more);
@@ -350,7 +354,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             if constexpr (fwd) {
                 const T bb = buoy(r0, Lr[ty * WR + tx + 1]);
                 T v = vx0 + dt * bb * d;
-                if (srcv) v += bb * pick(src.c[VX], tap_of(src, VX, i, j, k)) * s;
+                if (srcv) v += bb * cf(VX, tap_of(src, VX, i, j, k)) * s;
                 v = v * (gxh * gyi * gz_i);
                 st(ovx, st_vx + pw, v);
                 if constexpr (MODE == kFwdSave) st(wfield(G.save[VX], w), st_vx + pw, v);
@@ -359,7 +363,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             } else {
                 const T u = (gxh * gyi * gz_i) * vx0;
                 T g = dt * d * u;
-                if (srcv) g += pick(src.c[VX], tap_of(src, VX, i, j, k)) * s * u;
+                if (srcv) g += cf(VX, tap_of(src, VX, i, j, k)) * s * u;
                 st(wfield(io.acc[0], w), st_vx + pw, ga0 + g);
                 st(wfield(io.out[0], w), st_vx + pw, u * buoy(r0, Lr[ty * WR + tx + 1]));
             }
@@ -373,7 +377,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             if constexpr (fwd) {
                 const T bb = buoy(r0, Lr[(ty + 1) * WR + tx]);
                 T v = vy0 + dt * bb * d;
-                if (srcv) v += bb * pick(src.c[VY], tap_of(src, VY, i, j, k)) * s;
+                if (srcv) v += bb * cf(VY, tap_of(src, VY, i, j, k)) * s;
                 v = v * (gxi * gyh * gz_i);
                 st(ovy, st_vy + pw, v);
                 if constexpr (MODE == kFwdSave) st(wfield(G.save[VY], w), st_vy + pw, v);
@@ -382,7 +386,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             } else {
                 const T u = (gxi * gyh * gz_i) * vy0;
                 T g = dt * d * u;
-                if (srcv) g += pick(src.c[VY], tap_of(src, VY, i, j, k)) * s * u;
+                if (srcv) g += cf(VY, tap_of(src, VY, i, j, k)) * s * u;
                 st(wfield(io.acc[1], w), st_vy + pw, ga1 + g);
                 st(wfield(io.out[1], w), st_vy + pw, u * buoy(r0, Lr[(ty + 1) * WR + tx]));
             }
@@ -397,7 +401,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             if constexpr (fwd) {
                 const T bb = buoy(r0, r1);
                 T v = vz0 + dt * bb * d;
-                if (srcv) v += bb * pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s;
+                if (srcv) v += bb * cf(VZ, tap_of(src, VZ, i, j, k)) * s;
                 v = v * (gxi * gyi * gz_h);
                 st(ovz, st_vz + pw, v);
                 if constexpr (MODE == kFwdSave) st(wfield(G.save[VZ], w), st_vz + pw, v);
@@ -406,7 +410,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             } else {
                 const T u = (gxi * gyi * gz_h) * vz0;
                 T g = dt * d * u;
-                if (srcv) g += pick(src.c[VZ], tap_of(src, VZ, i, j, k)) * s * u;
+                if (srcv) g += cf(VZ, tap_of(src, VZ, i, j, k)) * s * u;
                 st(wfield(io.acc[2], w), st_vz + pw, ga2 + g);
                 st(wfield(io.out[2], w), st_vz + pw, u * buoy(r0, r1));
             }
@@ -465,6 +469,14 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     const T gxh = in ? G.g[0][1][i] : T(0), gxi = in ? G.g[0][0][i] : T(0);
     const T gyh = in ? G.g[1][1][j] : T(0), gyi = in ? G.g[1][0][j] : T(0);
     const unsigned st_xy = (in && i <= nx - 2 && j <= ny - 2) ? oc : kOOB;
+    // a moment-source tap in this tile (uniform): elsewhere the source terms are skipped
+    const bool srcs = src.on && (taps_in(src, SXX, i0, i0 + TX, j0, j0 + TY, k0, k1) ||
+                                 taps_in(src, SXY, i0, i0 + TX, j0, j0 + TY, k0, k1) ||
+                                 taps_in(src, SXZ, i0, i0 + TX, j0, j0 + TY, k0, k1) ||
+                                 taps_in(src, SYZ, i0, i0 + TX, j0, j0 + TY, k0, k1));
+    __shared__ T s_coef[6 * 8];
+    stage_coef<T, SXX, 6>(s_coef, src, srcs, tid);
+    auto cf = [&](int c, int t) -> T { return t >= 0 ? s_coef[(c - SXX) * 8 + (t & 7)] : T(0); };
     const unsigned st_xz = (in && i <= nx - 2) ? oc : kOOB;
     const unsigned st_yz = (in && j <= ny - 2) ? oc : kOOB;
     constexpr bool fwd = MODE == kFwd || MODE == kFwdSave;
@@ -538,7 +550,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         loadplane(k + 1, more, P);
         const T nvx = zld(fvx, k + 3, more), nvy = zld(fvy, k + 3, more), nvz = zld(fvz, k + 2, more);
         const T nm1 = zld(mu, k + 2, more && use_model);
-        hmu = loadmu(k + 2, more);
+        const T nhm = loadmu(k + 2, more);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         const unsigned pw = wplane(w, k, true);
         __syncthreads();
@@ -571,31 +583,27 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             T nxx = o_xx + dt * (l * tr + T(2) * mm * exx);
             T nyy = o_yy + dt * (l * tr + T(2) * mm * eyy);
             T nzz = o_zz + dt * (l * tr + T(2) * mm * ezz);
-            const int t = tap_of(src, SXX, i, j, k);
-            nxx += pick(src.c[SXX], t) * s;
-            nyy += pick(src.c[SYY], t) * s;
-            nzz += pick(src.c[SZZ], t) * s;
+            const T mxy = ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
+            const T mxz = ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
+            const T myz = ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);
+            T nxy = o_xy + dt * mxy * exy;
+            T nxz = o_xz + dt * mxz * exz;
+            T nyz = o_yz + dt * myz * eyz;
+            if (srcs) {  // one uniform branch for all six source terms
+                const int t = tap_of(src, SXX, i, j, k);
+                nxx += cf(SXX, t) * s;
+                nyy += cf(SYY, t) * s;
+                nzz += cf(SZZ, t) * s;
+                nxy += cf(SXY, tap_of(src, SXY, i, j, k)) * s;
+                nxz += cf(SXZ, tap_of(src, SXZ, i, j, k)) * s;
+                nyz += cf(SYZ, tap_of(src, SYZ, i, j, k)) * s;
+            }
             st(wfield(G.f[SXX], w), oc + pw, nxx * gn);
             st(wfield(G.f[SYY], w), oc + pw, nyy * gn);
             st(wfield(G.f[SZZ], w), oc + pw, (FS && k == 0) ? T(0) : nzz * gn);
-            {
-                const T mxy = ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
-                T v = o_xy + dt * mxy * exy;
-                v += pick(src.c[SXY], tap_of(src, SXY, i, j, k)) * s;
-                st(wfield(G.f[SXY], w), st_xy + pw, v * g_xy);
-            }
-            {
-                const T mxz = ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
-                T v = o_xz + dt * mxz * exz;
-                v += pick(src.c[SXZ], tap_of(src, SXZ, i, j, k)) * s;
-                st(wfield(G.f[SXZ], w), o_stxz + pw, v * g_xz);
-            }
-            {
-                const T myz = ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);
-                T v = o_yz + dt * myz * eyz;
-                v += pick(src.c[SYZ], tap_of(src, SYZ, i, j, k)) * s;
-                st(wfield(G.f[SYZ], w), o_styz + pw, v * g_yz);
-            }
+            st(wfield(G.f[SXY], w), st_xy + pw, nxy * g_xy);
+            st(wfield(G.f[SXZ], w), o_stxz + pw, nxz * g_xz);
+            st(wfield(G.f[SYZ], w), o_styz + pw, nyz * g_yz);
         } else if constexpr (MODE == kAdjA) {
             // gradients of C and X = C T with T = G_s A_s
             const T txx = gn * o_xx, tyy = gn * o_yy, tzz = gn * o_zz;
@@ -628,6 +636,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         qvy[0] = qvy[1]; qvy[1] = qvy[2]; qvy[2] = qvy[3]; qvy[3] = nvy;
         qvz[0] = qvz[1]; qvz[1] = qvz[2]; qvz[2] = qvz[3]; qvz[3] = nvz;
         m1 = nm1;
+        hmu = nhm;
     }
 }
 
@@ -677,7 +686,7 @@ template <typename T> struct ShotFwd {
     TileIO<T> io;
     TileMap tm;
     int base;  // first work item of this shot
-    int pad;
+    int alt;   // the batch's second tile shape covers this shot
 };
 
 // Work item range [lo, hi) and stride of this workgroup in the XCD-chunked order.
@@ -694,10 +703,14 @@ __device__ __forceinline__ void work_range(int total, int &w0, int &hi, int &str
 // Stride in ints between the .base members of consecutive descriptors.
 template <typename D> constexpr int base_stride() { return (int)(sizeof(D) / sizeof(int)); }
 
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
+// A batch may use a second tile shape with the same workgroup size (TX2 x TY2, 0: none)
+// for the shots whose descriptor sets `alt`, so that grids of different widths all get a
+// tile shape that covers them without idle columns.
+template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd>
 __global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
                                                           int n)
 {
+    static_assert(TX2 == 0 || TX2 * TY2 == TX * TY, "both tile shapes need the same workgroup size");
     __shared__ int s_base[kMaxShots];
     load_bases(s_base, &shots[0].base, base_stride<ShotFwd<T>>(), nshot);
     int w, hi, stride;
@@ -708,18 +721,27 @@ __global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__res
         const Grid<T> G = d.G;
         const Inject<T> src = d.src;
         const TileMap tm = d.tm;
-        int i0, j0, k0, k1;
-        tile_coords(tm, w - d.base, i0, j0, k0, k1, TX, TY, G.nz);
         const TileIO<T> io = d.io;
+        int i0, j0, k0, k1;
+        if constexpr (TX2 != 0) {
+            if (d.alt) {
+                tile_coords(tm, w - d.base, i0, j0, k0, k1, TX2, TY2, G.nz);
+                vel_tile_body<T, TX2, TY2, FS, MODE>(G, src, n, i0, j0, k0, k1, io);
+                __syncthreads();
+                continue;
+            }
+        }
+        tile_coords(tm, w - d.base, i0, j0, k0, k1, TX, TY, G.nz);
         vel_tile_body<T, TX, TY, FS, MODE>(G, src, n, i0, j0, k0, k1, io);
         __syncthreads();
     }
 }
 
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
+template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd>
 __global__ void __launch_bounds__(TX *TY) stress_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
                                                           int n)
 {
+    static_assert(TX2 == 0 || TX2 * TY2 == TX * TY, "both tile shapes need the same workgroup size");
     __shared__ int s_base[kMaxShots];
     load_bases(s_base, &shots[0].base, base_stride<ShotFwd<T>>(), nshot);
     int w, hi, stride;
@@ -730,9 +752,17 @@ __global__ void __launch_bounds__(TX *TY) stress_tile_multi(const ShotFwd<T> *__
         const Grid<T> G = d.G;
         const Inject<T> src = d.src;
         const TileMap tm = d.tm;
-        int i0, j0, k0, k1;
-        tile_coords(tm, w - d.base, i0, j0, k0, k1, TX, TY, G.nz);
         const TileIO<T> io = d.io;
+        int i0, j0, k0, k1;
+        if constexpr (TX2 != 0) {
+            if (d.alt) {
+                tile_coords(tm, w - d.base, i0, j0, k0, k1, TX2, TY2, G.nz);
+                stress_tile_body<T, TX2, TY2, FS, MODE>(G, src, n, i0, j0, k0, k1, io);
+                __syncthreads();
+                continue;
+            }
+        }
+        tile_coords(tm, w - d.base, i0, j0, k0, k1, TX, TY, G.nz);
         stress_tile_body<T, TX, TY, FS, MODE>(G, src, n, i0, j0, k0, k1, io);
         __syncthreads();
     }

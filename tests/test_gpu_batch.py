@@ -42,10 +42,21 @@ def desc(s, scale=1.0):
                 rec_pos=s.rec_pos)
 
 
-def single_runs(shots, tile, scale=1.0, dtype=torch.float32):
+def shot_tile(shape, tile, tile2=None):
+    """The tile shape a batch gives a shot: the second shape when it covers the rows with
+    fewer idle columns."""
+    if tile2 and tile2[0]:
+        pad = lambda tx: -(-shape[0] // tx) * tx
+        if pad(tile2[0]) < pad(tile[0]):
+            return tile2
+    return tile
+
+
+def single_runs(shots, tile, scale=1.0, dtype=torch.float32, tile2=None):
     out = []
     for sim, s in zip(sims_for(shots, dtype), shots):
-        sim.set_kernel("tile", tile[1], sim.kernel()["zchunk"], tile[0])
+        t = shot_tile(s.shape, tile, tile2)
+        sim.set_kernel("tile", t[1], sim.kernel()["zchunk"], t[0])
         tr = sim.forward(**desc(s, scale))
         out.append((tr.double().cpu().numpy(), sim.state().double().cpu().numpy()))
         sim.close()
@@ -90,7 +101,42 @@ def test_batch_autotune_then_forward():
     assert best["ms_per_step"] > 0
     trs = batch.forward([desc(s) for s in shots], use_graph=True)
     torch.cuda.synchronize()
-    ref = single_runs(shots, (best["tile_x"], best["tile_y"]))
+    ref = single_runs(shots, (best["tile_x"], best["tile_y"]), tile2=(best["tile2_x"], best["tile2_y"]))
+    for k, (sim, tr) in enumerate(zip(sims, trs)):
+        assert np.array_equal(tr.double().cpu().numpy(), ref[k][0]), k
+        assert np.array_equal(sim.state().double().cpu().numpy(), ref[k][1]), k
+    batch.close()
+    for s in sims:
+        s.close()
+
+
+PAIR_SHAPES = [(128, 20, 18), (64, 24, 20), (192, 18, 16), (100, 22, 19)]
+
+
+@pytest.mark.parametrize("pair,use_graph", [(((128, 8), (64, 16)), True), (((256, 4), (64, 16)), False),
+                                            (((256, 4), (128, 8)), True), (((128, 4), (64, 8)), False)])
+def test_batch_two_tile_shapes(pair, use_graph):
+    """Rows of 128, 64, 192 and 100 samples in one batch with two tile shapes: each shot
+    takes the shape with fewer idle columns and equals its single-shot run."""
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    shots = []
+    for s, shape in enumerate(PAIR_SHAPES):
+        rng = np.random.Generator(np.random.PCG64(1300 + s))
+        lam, mu, rho = W.layered_perturbed(shape, 10.0, 1310 + s)
+        nx, ny, nz = shape
+        pos = (float(rng.uniform(8, nx - 9)), float(rng.uniform(6, ny - 7)), float(rng.uniform(6, nz - 7)))
+        rec = np.stack([rng.uniform(3, nx - 4, 4), rng.uniform(3, ny - 4, 4), rng.uniform(2, nz - 4, 4)], axis=1)
+        shots.append(W.Shot(f"p{s}", shape, 10.0, DT, 60, lam, mu, rho, pos, W.random_mt(rng),
+                            tuple(rng.standard_normal(3) * 1e9), W.ricker(40.0, 60, DT), rec, sponge=(4,) * 6))
+    tile, tile2 = pair
+    ref = single_runs(shots, tile, tile2=tile2)
+    sims = sims_for(shots)
+    batch = BatchSimulator(sims)
+    batch.set_kernel(*tile, tile2=tile2)
+    print(f"[batch] pair {tile} + {tile2} graph={use_graph}", flush=True)
+    trs = batch.forward([desc(s) for s in shots], use_graph=use_graph)
+    torch.cuda.synchronize()
     for k, (sim, tr) in enumerate(zip(sims, trs)):
         assert np.array_equal(tr.double().cpu().numpy(), ref[k][0]), k
         assert np.array_equal(sim.state().double().cpu().numpy(), ref[k][1]), k
@@ -185,7 +231,10 @@ def grad_shots(seed, nt):
     return shots
 
 
-def test_batched_gradient_equals_per_shot():
+@pytest.mark.parametrize("tile2", [None, (64, 8)])
+def test_batched_gradient_equals_per_shot(tile2):
+    """Every shot's gradient equals its single-shot gradient bitwise; with tile2 the batch
+    runs 128x4 + 64x8 and every (narrow) shot takes the second shape."""
     from paper_2112_15071_amd.batch import BatchSimulator
 
     nt, k = 60, 7
@@ -203,7 +252,10 @@ def test_batched_gradient_equals_per_shot():
         sim.close()
     sims = sims_for(shots)
     batch = BatchSimulator(sims)
-    batch.set_kernel(*tile)
+    if tile2:
+        batch.set_kernel(128, 4, tile2=tile2)
+    else:
+        batch.set_kernel(*tile)
     gl = [torch.zeros(s.lam.shape, dtype=torch.float32, device="cuda") for s in shots]
     gm = [torch.zeros_like(x) for x in gl]
     gr = [torch.zeros_like(x) for x in gl]
