@@ -228,12 +228,24 @@ def bench_batch():
     batch.forward(descs, use_graph=True, traces=traces)
     sync()
     t_graph = time.perf_counter() - t0
-    log(f"[bench] batch: loop {t_loop:.3f} s, graph {t_graph:.3f} s")
+    log(f"[bench] batch: loop {t_loop:.3f} s, graph {t_graph:.3f} s (group budget {tune['group_mib']} MiB)")
+    t_lock = t_graph
+    if tune["group_mib"]:
+        # the lockstep schedule with the same tile shapes, for comparison
+        batch.set_schedule(0)
+        batch.forward(descs, use_graph=True, traces=traces)
+        sync()
+        t0 = time.perf_counter()
+        batch.forward(descs, use_graph=True, traces=traces)
+        sync()
+        t_lock = time.perf_counter() - t0
+        log(f"[bench] batch lockstep: graph {t_lock:.3f} s")
     batch.close()
     for s in sims:
         s.close()
     return dict(loop_gcs=round(cells_steps / t_loop / 1e9, 3), batched_gcs=round(cells_steps / t_graph / 1e9, 3),
                 loop_s=round(t_loop, 3), batched_s=round(t_graph, 3), speedup=round(t_loop / t_graph, 3),
+                lockstep_gcs=round(cells_steps / t_lock / 1e9, 3), group_mib=tune["group_mib"],
                 tile=[tune["tile_x"], tune["tile_y"]], tile2=[tune["tile2_x"], tune["tile2_y"]],
                 workgroups=tune["workgroups"], cell_steps=cells_steps)
 

@@ -174,6 +174,8 @@ int fd3d_get_adjoint_state(fd3d_ctx *ctx, const void *gws, void *const fields[9]
  * sequence is captured once into a hipGraph and replayed by one hipGraphLaunch on the
  * caller's stream (recaptured when the tiling or receiver counts change).  Per-shot
  * results are identical to fd3d_forward on each context with the same tile shape.
+ * fd3d_batch_set_schedule switches the forward from this lockstep order to
+ * cache-blocked groups (the gradient always runs lockstep).
  * The batch workspace holds the per-shot descriptors (caller-owned device memory).
  * The contexts must outlive the batch. */
 typedef struct fd3d_batch fd3d_batch;
@@ -192,13 +194,26 @@ int fd3d_batch_set_kernel(fd3d_batch *b, int tile_x, int tile_y, int workgroups)
  * otherwise.  fd3d_batch_set_kernel sets one shape. */
 int fd3d_batch_set_tiles(fd3d_batch *b, int tile_x, int tile_y, int tile2_x, int tile2_y, int workgroups);
 
+/* Order of the batched forward.  group_bytes = 0 (default): lockstep, every launch covers
+ * every shot and all shots advance one step at a time.  group_bytes > 0: cache-blocked
+ * groups -- runs of consecutive shots (in batch order) whose working sets (9 fields and
+ * 3 model arrays each, 12 x cells x sizeof(T) bytes per shot) add up to at most
+ * group_bytes (a group holds at least one shot); each group runs all nt steps, one launch
+ * per pass over its shots, before the next group starts, so that a group sized to the
+ * last-level cache (256 MB Infinity Cache on MI355X) keeps its fields resident between
+ * steps.  A group whose shots all use the tile kernel with one shape of their own
+ * (fd3d_set_kernel / fd3d_autotune on each context) launches with that shape; other
+ * groups use the batch's shapes.  Results per shot are the same in both orders. */
+int fd3d_batch_set_schedule(fd3d_batch *b, size_t group_bytes);
+
 /* Times `steps` batched steps (sources and receivers off, one warm-up run each) for
- * every supported tile shape and pair of shapes, with the persistent grid and with one
- * workgroup per tile, keeps the fastest for later batch calls and writes it to best =
- * {tile_x, tile_y, tile2_x, tile2_y, workgroups (0 = persistent)} and its ms per step to
- * *best_ms (each when non-NULL).  Every shot's forward state is zeroed afterwards.
- * Synchronises the stream. */
-int fd3d_batch_autotune(fd3d_batch *b, int steps, int best[5], double *best_ms, void *hip_stream);
+ * every supported tile shape and pair of shapes in lockstep, with the persistent grid
+ * and with one workgroup per tile, then the cache-blocked schedule with group budgets of
+ * 128 and 256 MiB; keeps the fastest for later batch calls and writes it to best =
+ * {tile_x, tile_y, tile2_x, tile2_y, workgroups (0 = persistent), group MiB (0 =
+ * lockstep)} and its ms per step to *best_ms (each when non-NULL).  Every shot's forward
+ * state is zeroed afterwards.  Synchronises the stream. */
+int fd3d_batch_autotune(fd3d_batch *b, int steps, int best[6], double *best_ms, void *hip_stream);
 
 /* srcs[nshot] (or NULL), nrec[nshot], rec_pos[nshot] (host double[nrec][3] each),
  * traces[nshot] (device T[nrec][3][nt] each); flags as fd3d_forward. */

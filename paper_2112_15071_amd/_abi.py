@@ -99,6 +99,7 @@ _SIGS = {
     "fd3d_batch_create": ([ctypes.POINTER(_vp), _i, ctypes.POINTER(_vp), _vp, _sz], _i),
     "fd3d_batch_set_kernel": ([_vp, _i, _i, _i], _i),
     "fd3d_batch_set_tiles": ([_vp, _i, _i, _i, _i, _i], _i),
+    "fd3d_batch_set_schedule": ([_vp, _sz], _i),
     "fd3d_batch_autotune": ([_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_double), _vp], _i),
     "fd3d_batch_forward": ([_vp, ctypes.POINTER(fd3d_source), ctypes.POINTER(_i), ctypes.POINTER(_dp),
                             ctypes.POINTER(_vp), _i, _i, _vp], _i),
@@ -234,12 +235,16 @@ def fd3d_batch_set_tiles(batch, tile_x: int, tile_y: int, tile2_x: int = 0, tile
     _check(_lib.fd3d_batch_set_tiles(batch, int(tile_x), int(tile_y), int(tile2_x), int(tile2_y), int(workgroups)))
 
 
+def fd3d_batch_set_schedule(batch, group_bytes: int) -> None:
+    _check(_lib.fd3d_batch_set_schedule(batch, int(group_bytes)))
+
+
 def fd3d_batch_autotune(batch, steps: int, stream):
-    best = (_i * 5)()
+    best = (_i * 6)()
     ms = ctypes.c_double(0.0)
     _check(_lib.fd3d_batch_autotune(batch, int(steps), best, ctypes.byref(ms), stream))
     return dict(tile_x=best[0], tile_y=best[1], tile2_x=best[2], tile2_y=best[3], workgroups=best[4],
-                ms_per_step=ms.value)
+                group_mib=best[5], ms_per_step=ms.value)
 
 
 def fd3d_batch_forward(batch, srcs, nrec, rec_ptrs, traces, flags, use_graph, stream) -> None:

@@ -37,10 +37,17 @@ class BatchSimulator:
         t2 = tile2 or (0, 0)
         _abi.fd3d_batch_set_tiles(self._b, tile_x, tile_y, t2[0], t2[1], workgroups)
 
+    def set_schedule(self, group_bytes: int = 0) -> None:
+        """Order of the batched forward: 0 = lockstep (every launch covers every shot);
+        otherwise cache-blocked groups of shots whose fields and models add up to at most
+        group_bytes, each group stepped through all its steps before the next."""
+        _abi.fd3d_batch_set_schedule(self._b, group_bytes)
+
     def autotune(self, steps: int = 10, cache: bool = True) -> dict:
         """Autotune every distinct grid shape of the batch for single-shot runs (each
         context also keeps its own z chunk, which the batch uses), then time the batched
-        launch itself for every tile shape and grid mode and keep the fastest."""
+        launch itself for every tile shape and grid mode in lockstep, then the
+        cache-blocked schedule, and keep the fastest."""
         seen = {}
         for sim in self.sims:
             key = (sim.shape, sim.dtype)

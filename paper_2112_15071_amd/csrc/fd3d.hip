@@ -859,6 +859,22 @@ template <typename T> int set_state_impl(fd3d_ctx *c, const void *const fields[9
 // Batches: many contexts (uneven grids, own models, sources and receivers) stepped
 // together, one persistent launch per pass for all shots, optionally captured once as
 // a hipGraph holding the whole nt-step sequence.
+//
+// Schedules.  Lockstep: every launch covers every shot, and the shots advance one step
+// at a time together.  Cache-blocked groups: the shots, taken from the smallest working
+// set (nine fields and three model arrays) to the largest, are cut into runs whose
+// working sets add up to at most a given number of bytes; one group runs all its nt
+// steps (one launch per pass over the group's shots) before the next group starts.  Sized to the last-level (Infinity)
+// cache, a group's fields stay resident from one step to the next.  Shots are
+// independent, so both schedules give every shot the same result bit for bit.
+
+// Shots at positions [s0, s0 + ns) of the batch's schedule order, stepped by one launch per pass: their work items and
+// receiver components (counted from the group's first), the persistent grid size and
+// the tile shapes of the launch (tx2 = 0: one shape).
+struct BatchGroup {
+    int s0, ns, tiles, recs, wgs;
+    int tx, ty, tx2, ty2;
+};
 
 struct fd3d_batch {
     int nshot;
@@ -869,6 +885,9 @@ struct fd3d_batch {
     size_t off_fwd, off_rec;
     int tile_x, tile_y, wgs_req;
     int tile2_x, tile2_y;  // optional second tile shape (same workgroup size), 0: none
+    size_t group_bytes;    // 0: lockstep; otherwise the cache-blocked group budget
+    std::vector<BatchGroup> groups;
+    std::vector<int> order;  // shot at each position of the descriptor arrays
     std::vector<unsigned char> fwd_host, rec_host;
     hipEvent_t staged;
     bool staged_pending;
@@ -878,7 +897,6 @@ struct fd3d_batch {
     hipGraphExec_t gexec;
     bool graph_valid;
     long graph_key;
-    int total_tiles, total_rec, wgs;
 };
 
 namespace {
@@ -900,13 +918,13 @@ bool pair_supported(int tsize, int tx, int ty, int tx2, int ty2)
     return key == 256004064016L || key == 128008064016L || key == 256004128008L;
 }
 
-// Calls f(TX, TY, TX2, TY2) with the batch's tile shapes as integral constants (TX2 = 0:
+// Calls f(TX, TY, TX2, TY2) with a launch's tile shapes as integral constants (TX2 = 0:
 // one shape).
-template <typename T, typename F> decltype(auto) with_batch_tiles(const fd3d_batch *b, F &&f)
+template <typename T, typename F> decltype(auto) with_batch_tiles(const BatchGroup &b, F &&f)
 {
     using Z = std::integral_constant<int, 0>;
-    if (b->tile2_x == 0)
-        return with_tile<T>(b->tile_x, b->tile_y, [&](auto tx, auto ty) { return f(tx, ty, Z{}, Z{}); });
+    if (b.tx2 == 0)
+        return with_tile<T>(b.tx, b.ty, [&](auto tx, auto ty) { return f(tx, ty, Z{}, Z{}); });
     using X64 = std::integral_constant<int, 64>;
     using X128 = std::integral_constant<int, 128>;
     using X256 = std::integral_constant<int, 256>;
@@ -914,25 +932,38 @@ template <typename T, typename F> decltype(auto) with_batch_tiles(const fd3d_bat
     using Y8 = std::integral_constant<int, 8>;
     using Y16 = std::integral_constant<int, 16>;
     if constexpr (sizeof(T) == 4) {
-        if (b->tile_x == 256 && b->tile2_x == 64) return f(X256{}, Y4{}, X64{}, Y16{});
-        if (b->tile_x == 128 && b->tile_y == 8) return f(X128{}, Y8{}, X64{}, Y16{});
-        if (b->tile_x == 256 && b->tile2_x == 128) return f(X256{}, Y4{}, X128{}, Y8{});
+        if (b.tx == 256 && b.tx2 == 64) return f(X256{}, Y4{}, X64{}, Y16{});
+        if (b.tx == 128 && b.ty == 8) return f(X128{}, Y8{}, X64{}, Y16{});
+        if (b.tx == 256 && b.tx2 == 128) return f(X256{}, Y4{}, X128{}, Y8{});
     }
     return f(X128{}, Y4{}, X64{}, Y8{});
 }
 
-// Tile map of one shot of the batch, and whether it uses the batch's second tile shape
-// (when that covers its rows with fewer idle columns).
-TileMap shot_tiles(const fd3d_batch *b, const fd3d_ctx *c, int &alt)
+// The batch's own tile shapes as one group covering every shot (counts not filled in).
+BatchGroup whole_batch(const fd3d_batch *b)
 {
-    int tx = b->tile_x, ty = b->tile_y;
+    BatchGroup g{};
+    g.s0 = 0;
+    g.ns = b->nshot;
+    g.tx = b->tile_x;
+    g.ty = b->tile_y;
+    g.tx2 = b->tile2_x;
+    g.ty2 = b->tile2_y;
+    return g;
+}
+
+// Tile map of one shot of a launch, and whether it uses the launch's second tile shape
+// (when that covers its rows with fewer idle columns).
+TileMap shot_tiles(const BatchGroup &b, const fd3d_ctx *c, int &alt)
+{
+    int tx = b.tx, ty = b.ty;
     alt = 0;
-    if (b->tile2_x > 0) {
-        const int pad1 = (c->n[0] + tx - 1) / tx * tx, pad2 = (c->n[0] + b->tile2_x - 1) / b->tile2_x * b->tile2_x;
+    if (b.tx2 > 0) {
+        const int pad1 = (c->n[0] + tx - 1) / tx * tx, pad2 = (c->n[0] + b.tx2 - 1) / b.tx2 * b.tx2;
         if (pad2 < pad1) {
             alt = 1;
-            tx = b->tile2_x;
-            ty = b->tile2_y;
+            tx = b.tx2;
+            ty = b.ty2;
         }
     }
     TileMap tm;
@@ -943,10 +974,11 @@ TileMap shot_tiles(const fd3d_batch *b, const fd3d_ctx *c, int &alt)
     return tm;
 }
 
+// One pass over the shots of group gr; d points at the group's first descriptor.
 template <typename T, int TX, int TY, int TX2, int TY2, bool FS>
-int launch_multi(fd3d_batch *b, const ShotFwd<T> *d, int n, int pass, hipStream_t st)
+int launch_multi(const BatchGroup &gr, const ShotFwd<T> *d, int n, int pass, hipStream_t st)
 {
-    const int g = b->wgs, S = b->nshot, W = b->total_tiles;
+    const int g = gr.wgs, S = gr.ns, W = gr.tiles;
     constexpr int NT = TX * TY;
     switch (pass) {
     case kPassVel: vel_tile_multi<T, TX, TY, TX2, TY2, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
@@ -961,7 +993,7 @@ int launch_multi(fd3d_batch *b, const ShotFwd<T> *d, int n, int pass, hipStream_
     return FD3D_OK;
 }
 
-template <typename T, bool FS> int multi_pass(fd3d_batch *b, const ShotFwd<T> *d, int n, int pass, hipStream_t st)
+template <typename T, bool FS> int multi_pass(const BatchGroup &b, const ShotFwd<T> *d, int n, int pass, hipStream_t st)
 {
     return with_batch_tiles<T>(b, [&](auto tx, auto ty, auto tx2, auto ty2) {
         return launch_multi<T, decltype(tx)::value, decltype(ty)::value, decltype(tx2)::value, decltype(ty2)::value,
@@ -969,7 +1001,7 @@ template <typename T, bool FS> int multi_pass(fd3d_batch *b, const ShotFwd<T> *d
     });
 }
 
-template <typename T, bool FS> int multi_occupancy(const fd3d_batch *b)
+template <typename T, bool FS> int multi_occupancy(const BatchGroup &b)
 {
     return with_batch_tiles<T>(b, [&](auto tx, auto ty, auto tx2, auto ty2) {
         constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
@@ -982,23 +1014,67 @@ template <typename T, bool FS> int multi_occupancy(const fd3d_batch *b)
     });
 }
 
-// The whole nt-step sequence of a batch on one stream (also what a graph captures).
+// The whole nt-step sequence of a batch on one stream (also what a graph captures):
+// group after group, each through all its steps.
 template <typename T> int batch_sequence(fd3d_batch *b, int flags, hipStream_t st)
 {
     if (!(flags & FD3D_KEEP_STATE))
         for (fd3d_ctx *c : b->ctx) zero_fields<T>(c, st);
-    const ShotRec<T> *r = (const ShotRec<T> *)(b->ws + b->off_rec);
-    const ShotFwd<T> *d = (const ShotFwd<T> *)(b->ws + b->off_fwd);
-    for (int n = 0; n < b->nt; ++n) {
-        if (b->fs) multi_pass<T, true>(b, d, n, kPassVel, st);
-        else multi_pass<T, false>(b, d, n, kPassVel, st);
-        if (b->total_rec > 0)
-            record_multi<T><<<(b->total_rec + 255) / 256, 256, 0, st>>>(r, b->nshot, b->total_rec, b->nt, n);
-        if (b->fs) multi_pass<T, true>(b, d, n, kPassStress, st);
-        else multi_pass<T, false>(b, d, n, kPassStress, st);
+    for (const BatchGroup &g : b->groups) {
+        const ShotRec<T> *r = (const ShotRec<T> *)(b->ws + b->off_rec) + g.s0;
+        const ShotFwd<T> *d = (const ShotFwd<T> *)(b->ws + b->off_fwd) + g.s0;
+        for (int n = 0; n < b->nt; ++n) {
+            if (b->fs) multi_pass<T, true>(g, d, n, kPassVel, st);
+            else multi_pass<T, false>(g, d, n, kPassVel, st);
+            if (g.recs > 0) record_multi<T><<<(g.recs + 255) / 256, 256, 0, st>>>(r, g.ns, g.recs, b->nt, n);
+            if (b->fs) multi_pass<T, true>(g, d, n, kPassStress, st);
+            else multi_pass<T, false>(g, d, n, kPassStress, st);
+        }
     }
     HIP_TRY(hipGetLastError());
     return FD3D_OK;
+}
+
+// Working set of one shot in the step loop: nine fields and the three model arrays.
+size_t shot_footprint(const fd3d_ctx *c) { return (size_t)12 * c->n[0] * c->n[1] * c->n[2] * c->tsize; }
+
+// Groups of the batch's schedule and their tile shapes.  A cache-blocked group whose
+// shots all run the tile kernel with one shape of their own uses that shape (each
+// shot's tuned kernel); otherwise a group uses the batch's shapes.
+void make_groups(fd3d_batch *b)
+{
+    b->groups.clear();
+    b->order.resize(b->nshot);
+    for (int s = 0; s < b->nshot; ++s) b->order[s] = s;
+    const BatchGroup all = whole_batch(b);
+    if (b->group_bytes == 0) {
+        b->groups.push_back(all);
+        return;
+    }
+    std::stable_sort(b->order.begin(), b->order.end(),
+                     [&](int x, int y) { return shot_footprint(b->ctx[x]) < shot_footprint(b->ctx[y]); });
+    auto ctx_at = [&](int p) { return b->ctx[b->order[p]]; };
+    int s = 0;
+    while (s < b->nshot) {
+        BatchGroup g = all;
+        g.s0 = s;
+        size_t bytes = shot_footprint(ctx_at(s));
+        int e = s + 1;
+        while (e < b->nshot && bytes + shot_footprint(ctx_at(e)) <= b->group_bytes) bytes += shot_footprint(ctx_at(e++));
+        g.ns = e - s;
+        const fd3d_ctx *c0 = ctx_at(s);
+        bool same = c0->variant == FD3D_KERNEL_TILE;
+        for (int q = s + 1; q < e && same; ++q)
+            same = ctx_at(q)->variant == FD3D_KERNEL_TILE && ctx_at(q)->tile_x == c0->tile_x &&
+                   ctx_at(q)->tile_y == c0->tile_y;
+        if (same && tile_supported(b->tsize, c0->tile_x, c0->tile_y)) {
+            g.tx = c0->tile_x;
+            g.ty = c0->tile_y;
+            g.tx2 = g.ty2 = 0;
+        }
+        b->groups.push_back(g);
+        s = e;
+    }
 }
 
 template <typename T>
@@ -1007,26 +1083,38 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
 {
     std::vector<ShotFwd<T>> fw(b->nshot);
     std::vector<ShotRec<T>> rr(b->nshot);
+    make_groups(b);
+    size_t gi = 0;
     int tiles = 0, recs = 0;
-    for (int s = 0; s < b->nshot; ++s) {
+    for (int p = 0; p < b->nshot; ++p) {  // position p of the schedule order holds shot s
+        const int s = b->order[p];
         fd3d_ctx *c = b->ctx[s];
+        BatchGroup &grp = b->groups[gi];
+        if (p == grp.s0) tiles = recs = 0;  // work items and receivers count from the group's first
+        if (!window_ok(c, c->zchunk))
+            return fail(FD3D_EINVAL, "shot " + std::to_string(s) + ": zchunk too large for a tile sweep");
         const int nr = nrec ? nrec[s] : 0;
         if (nr < 0 || nr > c->opts.max_receivers) return fail(FD3D_EINVAL, "shot " + std::to_string(s) + ": bad nrec");
         if (nr > 0 && (!rec_pos || !rec_pos[s] || !traces || !traces[s]))
             return fail(FD3D_EINVAL, "shot " + std::to_string(s) + ": rec_pos/traces is NULL");
-        const int rc = stage_inputs<T>(c, srcs ? &srcs[s] : nullptr, fw[s].src, nr, nr ? rec_pos[s] : nullptr, st);
+        const int rc = stage_inputs<T>(c, srcs ? &srcs[s] : nullptr, fw[p].src, nr, nr ? rec_pos[s] : nullptr, st);
         if (rc) return fail(rc, "shot " + std::to_string(s) + ": " + g_err);
-        fw[s].G = make_grid<T>(c);
-        const TileMap tm = shot_tiles(b, c, fw[s].alt);
-        fw[s].tm = tm;
-        fw[s].base = tiles;
+        fw[p].G = make_grid<T>(c);
+        const TileMap tm = shot_tiles(grp, c, fw[p].alt);
+        fw[p].tm = tm;
+        fw[p].base = tiles;
         tiles += tm.ntx * tm.nty * tm.nzc;
-        for (int q = 0; q < 3; ++q) rr[s].v[q] = fw[s].G.f[VX + q];
-        rr[s].taps = (const RecTap<T> *)(c->ws + c->L.rec);
-        rr[s].traces = nr ? (T *)traces[s] : nullptr;
-        rr[s].nrec = nr;
-        rr[s].base = recs;
+        for (int q = 0; q < 3; ++q) rr[p].v[q] = fw[p].G.f[VX + q];
+        rr[p].taps = (const RecTap<T> *)(c->ws + c->L.rec);
+        rr[p].traces = nr ? (T *)traces[s] : nullptr;
+        rr[p].nrec = nr;
+        rr[p].base = recs;
         recs += 3 * nr;
+        if (p == grp.s0 + grp.ns - 1) {
+            grp.tiles = tiles;
+            grp.recs = recs;
+            ++gi;
+        }
     }
     if (b->staged_pending) {
         HIP_TRY(hipEventSynchronize(b->staged));
@@ -1039,22 +1127,25 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
     HIP_TRY(hipEventRecord(b->staged, st));
     b->staged_pending = true;
 
-    // persistent grid: a multiple of 8 workgroups (one chunk of the list per XCD)
+    // persistent grid per group: a multiple of 8 workgroups (one chunk of the list per XCD)
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int occ = b->fs ? multi_occupancy<T, true>(b) : multi_occupancy<T, false>(b);
-    int wgs = b->wgs_req > 0 ? b->wgs_req : cus * occ;
-    wgs = std::min(wgs, ((tiles + 7) / 8) * 8);
-    wgs = std::max(8, (wgs + 7) / 8 * 8);
-    const long key = ((long)tiles << 32) ^ ((long)recs << 16) ^ ((long)wgs << 4) ^ (flags & FD3D_KEEP_STATE) ^
-                     ((long)b->tile_x << 40) ^ ((long)b->tile_y << 52) ^ ((long)b->tile2_x << 28) ^
-                     ((long)b->tile2_y << 34);
-    b->total_tiles = tiles;
-    b->total_rec = recs;
-    b->wgs = wgs;
+    // the graph is reused while every launch of the sequence is unchanged
+    uint64_t key = 1469598103934665603ull;
+    auto mix = [&](long v) { key = (key ^ (uint64_t)v) * 1099511628211ull; };
+    mix(flags & FD3D_KEEP_STATE);
+    for (BatchGroup &g : b->groups) {
+        const int occ = b->fs ? multi_occupancy<T, true>(g) : multi_occupancy<T, false>(g);
+        int wgs = b->wgs_req > 0 ? b->wgs_req : cus * occ;
+        wgs = std::min(wgs, ((g.tiles + 7) / 8) * 8);
+        g.wgs = std::max(8, (wgs + 7) / 8 * 8);
+        for (long v : {(long)g.s0, (long)g.ns, (long)g.tiles, (long)g.recs, (long)g.wgs, (long)g.tx, (long)g.ty,
+                       (long)g.tx2, (long)g.ty2})
+            mix(v);
+    }
     if (!use_graph) return batch_sequence<T>(b, flags, st);
-    if (!b->graph_valid || b->graph_key != key) {
+    if (!b->graph_valid || b->graph_key != (long)key) {
         if (b->graph_valid) {
             (void)hipGraphExecDestroy(b->gexec);
             (void)hipGraphDestroy(b->graph);
@@ -1069,7 +1160,7 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
         b->graph = g;
         HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
         b->graph_valid = true;
-        b->graph_key = key;
+        b->graph_key = (long)key;
     }
     HIP_TRY(hipGraphLaunch(b->gexec, st));
     return FD3D_OK;
@@ -1146,9 +1237,11 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     std::vector<AdjGrid<T>> ag(S);
     int tiles = 0, recs = 0, ncol = 0;
     int cbase[kMaxBatchColors] = {0, 0, 0, 0};
+    BatchGroup all = whole_batch(b);  // every shot in each launch (lockstep)
     for (int s = 0; s < S; ++s) {
         fd3d_ctx *c = b->ctx[s];
         const std::string tag = "shot " + std::to_string(s) + ": ";
+        if (!window_ok(c, c->zchunk)) return fail(FD3D_EINVAL, tag + "zchunk too large for a tile sweep");
         if (!gws || !gws[s]) return fail(FD3D_EINVAL, tag + "gradient workspace is NULL");
         int rc = check_gws(c, gws[s], gws_bytes[s], k);
         if (rc) return fail(rc, tag + g_err);
@@ -1165,7 +1258,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         GL[s] = make_grad_layout(c, k);
         fw[s].G = make_grid<T>(c);
         std::memset(&fw[s].io, 0, sizeof fw[s].io);
-        const TileMap tm = shot_tiles(b, c, fw[s].alt);
+        const TileMap tm = shot_tiles(all, c, fw[s].alt);
         fw[s].tm = tm;
         fw[s].base = tiles;
         tiles += tm.ntx * tm.nty * tm.nzc;
@@ -1250,12 +1343,11 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int occ = b->fs ? multi_occupancy<T, true>(b) : multi_occupancy<T, false>(b);
+    const int occ = multi_occupancy<T, false>(all);
     int wgs = b->wgs_req > 0 ? b->wgs_req : cus * occ;
-    wgs = std::max(8, (std::min(wgs, ((tiles + 7) / 8) * 8) + 7) / 8 * 8);
-    b->total_tiles = tiles;
-    b->total_rec = recs;
-    b->wgs = wgs;
+    all.wgs = std::max(8, (std::min(wgs, ((tiles + 7) / 8) * 8) + 7) / 8 * 8);
+    all.tiles = tiles;
+    all.recs = recs;
 
     // forward with checkpoints
     auto desc = [&](size_t off) { return (const ShotFwd<T> *)(bws + off); };
@@ -1264,7 +1356,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     const dim3 cgrid(256, 9 * S);
     if (!(flags & FD3D_KEEP_STATE))
         for (fd3d_ctx *c : b->ctx) zero_fields<T>(c, st);
-    auto pass = [&](const ShotFwd<T> *d, int n, int p) { multi_pass<T, false>(b, d, n, p, st); };
+    auto pass = [&](const ShotFwd<T> *d, int n, int p) { multi_pass<T, false>(all, d, n, p, st); };
     for (int n = 0; n < b->nt; ++n) {
         if (n % k == 0)
             copy_multi<T><<<cgrid, 256, 0, st>>>((const CopyDesc<T> *)(bws + BL.save_copy + (n / k) * BL.copy_bytes));
@@ -1633,7 +1725,7 @@ int fd3d_batch_create(fd3d_batch **out, int nshot, fd3d_ctx *const *ctxs, void *
     b->staged_pending = false;
     b->graph_valid = false;
     b->graph_key = 0;
-    b->total_tiles = b->total_rec = b->wgs = 0;
+    b->group_bytes = 0;
     if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
         delete b;
         return fail(FD3D_EHIP, "hipEventCreateWithFlags failed");
@@ -1668,7 +1760,14 @@ int fd3d_batch_set_tiles(fd3d_batch *b, int tile_x, int tile_y, int tile2_x, int
     return FD3D_OK;
 }
 
-int fd3d_batch_autotune(fd3d_batch *b, int steps, int best[5], double *best_ms, void *hip_stream)
+int fd3d_batch_set_schedule(fd3d_batch *b, size_t group_bytes)
+{
+    if (!b) return fail(FD3D_EINVAL, "batch is NULL");
+    b->group_bytes = group_bytes;
+    return FD3D_OK;
+}
+
+int fd3d_batch_autotune(fd3d_batch *b, int steps, int best[6], double *best_ms, void *hip_stream)
 {
     if (!b) return fail(FD3D_EINVAL, "batch is NULL");
     if (steps < 1) return fail(FD3D_EINVAL, "steps must be >= 1");
@@ -1677,15 +1776,36 @@ int fd3d_batch_autotune(fd3d_batch *b, int steps, int best[5], double *best_ms, 
     static const int shapes[][4] = {{64, 4, 0, 0},    {64, 8, 0, 0},   {64, 16, 0, 0},   {128, 4, 0, 0},
                                     {128, 8, 0, 0},   {256, 4, 0, 0},  {256, 4, 64, 16}, {128, 8, 64, 16},
                                     {256, 4, 128, 8}, {128, 4, 64, 8}};
+    // cache-blocked group budgets tried after the shapes (MiB; 0: lockstep)
+    static const int budgets[] = {128, 256};
     const int nt_save = b->nt;
+    const size_t keep_group = b->group_bytes;
     const int keep[5] = {b->tile_x, b->tile_y, b->tile2_x, b->tile2_y, b->wgs_req};
     int win[5] = {keep[0], keep[1], keep[2], keep[3], keep[4]};
+    int win_mib = 0;
     double win_ms = 1e300;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(FD3D_EHIP, "hipEventCreate failed");
     b->nt = steps;
+    b->group_bytes = 0;
     int rc = FD3D_OK;
+    // times `steps` steps of the current settings (after one untimed run)
+    auto time_it = [&](float &ms) {
+        for (int rep = 0; rep < 2 && !rc; ++rep) {
+            if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(FD3D_EHIP, "hipEventRecord");
+            if (!rc)
+                rc = b->tsize == 8 ? batch_forward_impl<double>(b, nullptr, nullptr, nullptr, nullptr, FD3D_KEEP_STATE, 0, st)
+                                   : batch_forward_impl<float>(b, nullptr, nullptr, nullptr, nullptr, FD3D_KEEP_STATE, 0, st);
+        }
+        if (rc) return;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(FD3D_EHIP, "timing events failed");
+            return;
+        }
+        ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+    };
     for (const auto &sh : shapes) {
         if (!tile_supported(b->tsize, sh[0], sh[1])) continue;
         if (sh[2] && !pair_supported(b->tsize, sh[0], sh[1], sh[2], sh[3])) continue;
@@ -1698,26 +1818,17 @@ int fd3d_batch_autotune(fd3d_batch *b, int steps, int best[5], double *best_ms, 
             b->wgs_req = 0;
             if (mode == 1) {
                 long tiles = 0;
+                const BatchGroup all = whole_batch(b);
                 for (const fd3d_ctx *c : b->ctx) {
                     int alt = 0;
-                    const TileMap tm = shot_tiles(b, c, alt);
+                    const TileMap tm = shot_tiles(all, c, alt);
                     tiles += (long)tm.ntx * tm.nty * tm.nzc;
                 }
                 b->wgs_req = (int)std::min<long>((tiles + 7) / 8 * 8, 1L << 30);
             }
-            for (int rep = 0; rep < 2 && !rc; ++rep) {
-                if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(FD3D_EHIP, "hipEventRecord");
-                if (!rc)
-                    rc = b->tsize == 8 ? batch_forward_impl<double>(b, nullptr, nullptr, nullptr, nullptr, FD3D_KEEP_STATE, 0, st)
-                                       : batch_forward_impl<float>(b, nullptr, nullptr, nullptr, nullptr, FD3D_KEEP_STATE, 0, st);
-            }
-            if (rc) break;
-            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                rc = fail(FD3D_EHIP, "timing events failed");
-                break;
-            }
             float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
+            time_it(ms);
+            if (rc) break;
             if (ms < win_ms) {
                 win_ms = ms;
                 win[0] = b->tile_x;
@@ -1729,6 +1840,24 @@ int fd3d_batch_autotune(fd3d_batch *b, int steps, int best[5], double *best_ms, 
         }
         if (rc) break;
     }
+    // the schedule, with the winning shapes for the launches that use the batch's shapes
+    if (!rc) {
+        b->tile_x = win[0];
+        b->tile_y = win[1];
+        b->tile2_x = win[2];
+        b->tile2_y = win[3];
+        b->wgs_req = win[4];
+        for (int mib : budgets) {
+            b->group_bytes = (size_t)mib << 20;
+            float ms = 0.0f;
+            time_it(ms);
+            if (rc) break;
+            if (ms < win_ms) {
+                win_ms = ms;
+                win_mib = mib;
+            }
+        }
+    }
     b->nt = nt_save;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1738,10 +1867,13 @@ int fd3d_batch_autotune(fd3d_batch *b, int steps, int best[5], double *best_ms, 
     b->tile2_x = use[2];
     b->tile2_y = use[3];
     b->wgs_req = use[4];
+    b->group_bytes = rc ? keep_group : (size_t)win_mib << 20;
     if (rc) return rc;
     for (fd3d_ctx *c : b->ctx) zero_fields_any(c, st);
-    if (best)
+    if (best) {
         for (int q = 0; q < 5; ++q) best[q] = win[q];
+        best[5] = win_mib;
+    }
     if (best_ms) *best_ms = win_ms / steps;
     return FD3D_OK;
 }
