@@ -482,6 +482,13 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     constexpr bool fwd = MODE == kFwd || MODE == kFwdSave;
     constexpr bool use_model = MODE != kAdjB;
 
+    // The forward sweeps run from the bottom of the chunk up (decreasing k): the velocity
+    // pass before it ends at the bottom, so the planes this pass reads first are the ones
+    // most recently written and read, still in the last-level cache.  The next velocity
+    // pass starts at the top, where this one ends.  Same arithmetic per sample either way.
+    constexpr bool up = fwd;
+    const int kfirst = up ? k1 - 1 : k0;
+
     const Window w = window<T>(k0, k1, nz, sz);
     auto zld = [&](const T *f, int kk, bool ok) -> T { return ld<T>(wfield(f, w), oc + wplane(w, kk, ok)); };
 
@@ -489,11 +496,11 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     T qvx[4], qvy[4], qvz[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        qvx[m] = zld(fvx, k0 - 1 + m, true);
-        qvy[m] = zld(fvy, k0 - 1 + m, true);
-        qvz[m] = zld(fvz, k0 - 2 + m, true);
+        qvx[m] = zld(fvx, kfirst - 1 + m, true);
+        qvy[m] = zld(fvy, kfirst - 1 + m, true);
+        qvz[m] = zld(fvz, kfirst - 2 + m, true);
     }
-    T m1 = zld(mu, k0 + 1, use_model);  // own mu one plane below
+    T m1 = up ? T(0) : zld(mu, k0 + 1, use_model);  // own mu one plane below (downward sweep)
 
     struct Plane {
         T cl, cm, sxx, syy, szz, sxy, sxz, syz, hx, hy, hz, a0, a1, a2, a3, a4;
@@ -523,16 +530,24 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     auto loadmu = [&](int kk, bool ok) -> T { return ld<T>(wfield(mu, w), hm.off + wplane(w, kk, ok && use_model)); };
 
     Plane P;
-    loadplane(k0, true, P);
-    {
+    loadplane(kfirst, true, P);
+    T hmu;
+    if constexpr (up) {
+        // mu plane k1 (below the first plane) complete; plane k1 - 1's halo one ahead
+        T *M = s_mu[k1 % 3];
+        M[om] = zld(mu, k1, use_model);
+        M[hm.lds] = loadmu(k1, true);
+        hmu = loadmu(k1 - 1, true);
+    } else {
         T *M = s_mu[k0 % 3];
         M[om] = P.cm;
         M[hm.lds] = loadmu(k0, true);
+        hmu = loadmu(k0 + 1, true);
     }
-    T hmu = loadmu(k0 + 1, true);
 
-    for (int k = k0; k < k1; ++k) {
-        const int b = (k - k0) & 1;
+    for (int it = 0; it < k1 - k0; ++it) {
+        const int k = up ? k1 - 1 - it : k0 + it;
+        const int b = it & 1;
         T *Lx = s_vx[b], *Ly = s_vy[b], *Lz = s_vz[b];
         T *M0 = s_mu[k % 3], *M1 = s_mu[(k + 1) % 3];
         Lx[ovx] = qvx[1];
@@ -541,16 +556,24 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         Lx[hvx.lds] = P.hx;
         Ly[hvy.lds] = P.hy;
         Lz[hvz.lds] = P.hz;
-        M1[om] = m1;
-        M1[hm.lds] = hmu;
+        if constexpr (up) {  // mu plane k enters the ring (plane k + 1 is there)
+            M0[om] = P.cm;
+            M0[hm.lds] = hmu;
+        } else {  // mu plane k + 1 enters the ring (plane k is there)
+            M1[om] = m1;
+            M1[hm.lds] = hmu;
+        }
         const T l = P.cl, mm = P.cm;
         const T o_xx = P.sxx, o_yy = P.syy, o_zz = P.szz, o_xy = P.sxy, o_xz = P.sxz, o_yz = P.syz;
         const T a0 = P.a0, a1 = P.a1, a2 = P.a2, a3 = P.a3, a4 = P.a4;
-        const bool more = k + 1 < k1;
-        loadplane(k + 1, more, P);
-        const T nvx = zld(fvx, k + 3, more), nvy = zld(fvy, k + 3, more), nvz = zld(fvz, k + 2, more);
-        const T nm1 = zld(mu, k + 2, more && use_model);
-        const T nhm = loadmu(k + 2, more);
+        // loads of the next plane of the sweep and the queue heads (skipped past the chunk)
+        const int kn = up ? k - 1 : k + 1;
+        const bool more = it + 1 < k1 - k0;
+        loadplane(kn, more, P);
+        const T nvx = zld(fvx, up ? k - 2 : k + 3, more), nvy = zld(fvy, up ? k - 2 : k + 3, more);
+        const T nvz = zld(fvz, up ? k - 3 : k + 2, more);
+        const T nm1 = up ? T(0) : zld(mu, k + 2, more && use_model);
+        const T nhm = loadmu(up ? k - 1 : k + 2, more);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         const unsigned pw = wplane(w, k, true);
         __syncthreads();
@@ -632,10 +655,16 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             st(wfield(G.f[SXZ], w), o_stxz + pw, g_xz * o_xz - dt * exz);
             st(wfield(G.f[SYZ], w), o_styz + pw, g_yz * o_yz - dt * eyz);
         }
-        qvx[0] = qvx[1]; qvx[1] = qvx[2]; qvx[2] = qvx[3]; qvx[3] = nvx;
-        qvy[0] = qvy[1]; qvy[1] = qvy[2]; qvy[2] = qvy[3]; qvy[3] = nvy;
-        qvz[0] = qvz[1]; qvz[1] = qvz[2]; qvz[2] = qvz[3]; qvz[3] = nvz;
-        m1 = nm1;
+        if constexpr (up) {
+            qvx[3] = qvx[2]; qvx[2] = qvx[1]; qvx[1] = qvx[0]; qvx[0] = nvx;
+            qvy[3] = qvy[2]; qvy[2] = qvy[1]; qvy[1] = qvy[0]; qvy[0] = nvy;
+            qvz[3] = qvz[2]; qvz[2] = qvz[1]; qvz[1] = qvz[0]; qvz[0] = nvz;
+        } else {
+            qvx[0] = qvx[1]; qvx[1] = qvx[2]; qvx[2] = qvx[3]; qvx[3] = nvx;
+            qvy[0] = qvy[1]; qvy[1] = qvy[2]; qvy[2] = qvy[3]; qvy[3] = nvy;
+            qvz[0] = qvz[1]; qvz[1] = qvz[2]; qvz[2] = qvz[3]; qvz[3] = nvz;
+            m1 = nm1;
+        }
         hmu = nhm;
     }
 }
