@@ -267,6 +267,12 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     auto cf = [&](int c, int t) -> T { return t >= 0 ? s_coef[(c - VX) * 8 + (t & 7)] : T(0); };
     constexpr bool fwd = MODE == kFwd || MODE == kFwdSave;
     constexpr bool use_rho = MODE != kAdjA;
+    // Sweep direction: velocity-A runs upward (decreasing k) from where the stress-A pass
+    // before it ended, so that it starts on planes still in the last-level cache; all
+    // other velocity passes run downward.
+    constexpr bool up = MODE == kAdjA;
+    static_assert(!(up && FS), "upward velocity sweeps have no free-surface images");
+    const int kfirst = up ? k1 - 1 : k0;
 
     const Window w = window<T>(k0, k1, nz, sz);
     auto zld = [&](const T *f, int kk, bool ok) -> T { return ld<T>(wfield(f, w), oc + wplane(w, kk, ok)); };
@@ -275,7 +281,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     T qxz[4], qyz[4], qzz[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        const int kk = k0 - 2 + m;
+        const int kk = kfirst - 2 + m;
         if (FS && kk < 0) {
             qxz[m] = -zld(fxz, -1 - kk, true);
             qyz[m] = -zld(fyz, -1 - kk, true);
@@ -283,10 +289,10 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             qxz[m] = zld(fxz, kk, true);
             qyz[m] = zld(fyz, kk, true);
         }
-        const int kz = k0 - 1 + m;
+        const int kz = kfirst - 1 + m;
         qzz[m] = (FS && kz < 0) ? -zld(fzz, -kz, true) : zld(fzz, kz, true);
     }
-    T r0 = zld(rho, k0, use_rho), r1 = zld(rho, k0 + 1, use_rho);
+    T r0 = zld(rho, kfirst, use_rho), r1 = zld(rho, kfirst + 1, use_rho);
 
     // plane registers, loaded one plane ahead
     struct Plane {
@@ -315,10 +321,11 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         P.r = ld<T>(br, hr.off + pr);
     };
     Plane P;
-    loadplane(k0, true, P);
+    loadplane(kfirst, true, P);
 
-    for (int k = k0; k < k1; ++k) {
-        const int b = (k - k0) & 1;
+    for (int it = 0; it < k1 - k0; ++it) {
+        const int k = up ? k1 - 1 - it : k0 + it;
+        const int b = it & 1;
         T *Lxx = s_xx[b], *Lxy = s_xy[b], *Lxz = s_xz[b], *Lyy = s_yy[b], *Lyz = s_yz[b], *Lr = s_r[b];
         // own samples and halos of plane k
         Lxx[own_c3 + tx + 1] = P.cxx;
@@ -335,11 +342,11 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         Lr[hr.lds] = P.r;
         const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
         const T ga0 = P.g0, ga1 = P.g1, ga2 = P.g2;
-        // loads of plane k+1 and the queue heads (skipped past the chunk)
-        const bool more = k + 1 < k1;
-        loadplane(k + 1, more, P);
-        const T nxz = zld(fxz, k + 2, more), nyz = zld(fyz, k + 2, more);
-        const T nzz = zld(fzz, k + 3, more), nr = zld(rho, k + 2, more && use_rho);
+        // loads of the next plane of the sweep and the queue heads (skipped past the chunk)
+        const bool more = it + 1 < k1 - k0;
+        loadplane(up ? k - 1 : k + 1, more, P);
+        const T nxz = zld(fxz, up ? k - 3 : k + 2, more), nyz = zld(fyz, up ? k - 3 : k + 2, more);
+        const T nzz = zld(fzz, up ? k - 2 : k + 3, more), nr = zld(rho, up ? k - 1 : k + 2, more && use_rho);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         __syncthreads();
 
@@ -415,10 +422,17 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 st(wfield(io.out[2], w), st_vz + pw, u * buoy(r0, r1));
             }
         }
-        qxz[0] = qxz[1]; qxz[1] = qxz[2]; qxz[2] = qxz[3]; qxz[3] = nxz;
-        qyz[0] = qyz[1]; qyz[1] = qyz[2]; qyz[2] = qyz[3]; qyz[3] = nyz;
-        qzz[0] = qzz[1]; qzz[1] = qzz[2]; qzz[2] = qzz[3]; qzz[3] = nzz;
-        r0 = r1; r1 = nr;
+        if constexpr (up) {
+            qxz[3] = qxz[2]; qxz[2] = qxz[1]; qxz[1] = qxz[0]; qxz[0] = nxz;
+            qyz[3] = qyz[2]; qyz[2] = qyz[1]; qyz[1] = qyz[0]; qyz[0] = nyz;
+            qzz[3] = qzz[2]; qzz[2] = qzz[1]; qzz[1] = qzz[0]; qzz[0] = nzz;
+            r1 = r0; r0 = nr;
+        } else {
+            qxz[0] = qxz[1]; qxz[1] = qxz[2]; qxz[2] = qxz[3]; qxz[3] = nxz;
+            qyz[0] = qyz[1]; qyz[1] = qyz[2]; qyz[2] = qyz[3]; qyz[3] = nyz;
+            qzz[0] = qzz[1]; qzz[1] = qzz[2]; qzz[2] = qzz[3]; qzz[3] = nzz;
+            r0 = r1; r1 = nr;
+        }
     }
 }
 
@@ -482,11 +496,13 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     constexpr bool fwd = MODE == kFwd || MODE == kFwdSave;
     constexpr bool use_model = MODE != kAdjB;
 
-    // The forward sweeps run from the bottom of the chunk up (decreasing k): the velocity
-    // pass before it ends at the bottom, so the planes this pass reads first are the ones
-    // most recently written and read, still in the last-level cache.  The next velocity
-    // pass starts at the top, where this one ends.  Same arithmetic per sample either way.
-    constexpr bool up = fwd;
+    // Sweep direction.  The forward stress passes run from the bottom of the chunk up
+    // (decreasing k): the velocity pass before them ends at the bottom, so the planes read
+    // first are the ones most recently written and read, still in the last-level cache,
+    // and the next velocity pass starts at the top, where this one ends.  In the adjoint
+    // step the passes alternate the same way: stress-A down, velocity-A up, velocity-B
+    // down, stress-B up.  Same arithmetic per sample either way.
+    constexpr bool up = fwd || MODE == kAdjB;
     const int kfirst = up ? k1 - 1 : k0;
 
     const Window w = window<T>(k0, k1, nz, sz);
