@@ -166,3 +166,32 @@ def test_c1_full_length_mirror_symmetry():
             err = (core - sign * mir).abs().max().item()
             assert err <= 1e-6 * scale, (a, f, err, scale)
     sim.close()
+
+
+def tiny_shot(nt, rec=True, zero_wavelet=False):
+    """7 x 6 x 5 nodes: smaller than every tile and z chunk in every direction."""
+    shape = (7, 6, 5)
+    lam, mu, rho = W.layered_perturbed(shape, 10.0, 77)
+    rng = np.random.Generator(np.random.PCG64(77))
+    wav = np.zeros(nt) if zero_wavelet else W.ricker(40.0, nt, 5e-4, t0=0.0)
+    recs = np.array([[2.25, 2.5, 1.5], [4.4, 3.1, 2.2]]) if rec else np.zeros((0, 3))
+    return W.Shot("tiny", shape, 10.0, 5e-4, nt, lam, mu, rho, (3.3, 2.6, 2.2), W.random_mt(rng), (1e9, -2e9, 5e8),
+                  wav, recs, sponge=(2, 2, 2, 2, 1, 1))
+
+
+@pytest.mark.parametrize("kern", KERNELS)
+def test_degenerate_sizes(kern):
+    """A grid smaller than any tile, one time step, no receivers, and a zero source, through
+    every kernel variant: the oracle's result (a zero source leaves the state exactly 0)."""
+    for nt in (1, 25):
+        shot = tiny_shot(nt)
+        print(f"[tiny] {kern} nt={nt}", flush=True)
+        compare(gpu_run(shot, torch.float32, kernel=kern), oracle_run(shot), 1e-4, f"tiny {kern} nt={nt}")
+    shot = tiny_shot(25, rec=False)
+    tr, st = gpu_run(shot, torch.float32, kernel=kern)
+    assert tr.shape == (0, 3, 25)
+    _, rst = oracle_run(shot)
+    for f in range(9):
+        assert rel_l2(st[f], rst[f]) <= 1e-4, f
+    tr, st = gpu_run(tiny_shot(25, zero_wavelet=True), torch.float32, kernel=kern)
+    assert not tr.any() and not st.any()
