@@ -44,7 +44,7 @@ def build(force: bool = True) -> str:
 class _Cfg(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int * 3),
-        ("h", ctypes.c_double),
+        ("h", ctypes.c_double * 3),
         ("dt", ctypes.c_double),
         ("nt", ctypes.c_int),
         ("periodic", ctypes.c_int * 3),
@@ -90,10 +90,11 @@ def _load():
 
 @dataclass
 class Config:
-    """Grid and scheme options.  ``shape`` is (nx, ny, nz)."""
+    """Grid and scheme options.  ``shape`` is (nx, ny, nz); ``h`` is one spacing for all
+    axes or (dx, dy, dz)."""
 
     shape: Sequence[int]
-    h: float
+    h: object
     dt: float
     nt: int
     sponge: Sequence[int] = (0, 0, 0, 0, 0, 0)  # x-, x+, y-, y+, z- (top), z+
@@ -106,7 +107,9 @@ class Config:
         for a in range(3):
             c.n[a] = int(self.shape[a])
             c.periodic[a] = int(bool(self.periodic[a]))
-        c.h = float(self.h)
+        hs = tuple(self.h) if np.ndim(self.h) else (self.h,) * 3
+        for a in range(3):
+            c.h[a] = float(hs[a])
         c.dt = float(self.dt)
         c.nt = int(self.nt)
         c.free_surface = int(bool(self.free_surface))

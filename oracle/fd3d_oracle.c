@@ -12,7 +12,8 @@
  *   Sec. 2.1, Eq.(2)   dsigma/dt = C : (1/2)(grad v + grad v^T), isotropic C(lambda, mu)
  *   Sec. 2.1, Eq.(3)   symmetric stress tensor, six independent components
  *   Sec. 2.1.1         Graves staggered positions of the nine fields
- *   Sec. 2.1.2, Eq.(4) fourth-order staggered first derivative (read as divided by h)
+ *   Sec. 2.1.2, Eq.(4) fourth-order staggered first derivative (read as divided by the
+ *                      spacing of its axis; Table 5 uses different cell sizes per axis)
  *   Sec. 2.2           one copy of each field, updated in place; velocity pass, then stress pass
  *   Sec. 2.2.1         effective rho, lambda, mu at staggered points by trilinear
  *                      interpolation of node values (= arithmetic means at half offsets)
@@ -26,8 +27,9 @@
  *   - nodes (i,j,k), x fastest: idx = i + nx*(j + ny*k); z points down, k = 0 is the top.
  *   - a component staggered along an axis holds n-1 active samples there (slot n-1 is
  *     pinned to zero); every sample outside the active range reads as zero.
- *   - D+ f[i] = (c1 (f[i+1]-f[i]) + c2 (f[i+2]-f[i-1])) / h    (integer -> half)
- *     D- g[i] = (c1 (g[i]-g[i-1]) + c2 (g[i+1]-g[i-2])) / h    (half -> integer)
+ *   - D+ f[i] = (c1 (f[i+1]-f[i]) + c2 (f[i+2]-f[i-1])) / h_a  (integer -> half)
+ *     D- g[i] = (c1 (g[i]-g[i-1]) + c2 (g[i+1]-g[i-2])) / h_a  (half -> integer)
+ *     with h_a the spacing of the derivative's axis a
  *     c1 = 9/8, c2 = -1/24.
  *
  * Optional periodic axes exist for the dispersion pins only; the GPU path has none.
@@ -61,7 +63,7 @@ static const double C2 = -1.0 / 24.0;
 
 typedef struct {
     int n[3];          /* nx, ny, nz */
-    double h;          /* grid spacing (m) */
+    double h[3];       /* grid spacing per axis (m): dx, dy, dz */
     double dt;         /* time step (s) */
     int nt;            /* number of steps */
     int periodic[3];   /* oracle-only periodic axes */
@@ -137,7 +139,7 @@ static double dplus_s(const oracle_cfg *c, double *const *F, int comp, int axis,
     double fp1 = sget(c, F, comp, i + e0, j + e1, k + e2);
     double fp2 = sget(c, F, comp, i + 2 * e0, j + 2 * e1, k + 2 * e2);
     double fm1 = sget(c, F, comp, i - e0, j - e1, k - e2);
-    return (C1 * (fp1 - f0) + C2 * (fp2 - fm1)) / c->h;
+    return (C1 * (fp1 - f0) + C2 * (fp2 - fm1)) / c->h[axis];
 }
 
 /* Eq.(4), half samples -> integer point i. */
@@ -148,7 +150,7 @@ static double dminus_s(const oracle_cfg *c, double *const *F, int comp, int axis
     double gm1 = sget(c, F, comp, i - e0, j - e1, k - e2);
     double gp1 = sget(c, F, comp, i + e0, j + e1, k + e2);
     double gm2 = sget(c, F, comp, i - 2 * e0, j - 2 * e1, k - 2 * e2);
-    return (C1 * (g0 - gm1) + C2 * (gp1 - gm2)) / c->h;
+    return (C1 * (g0 - gm1) + C2 * (gp1 - gm2)) / c->h[axis];
 }
 
 /* Same operators on velocity-like fields (no images; never read above the surface). */
@@ -159,7 +161,7 @@ static double dplus_v(const oracle_cfg *c, const double *f, int comp, int axis, 
     double fp1 = get(c, f, comp, i + e0, j + e1, k + e2);
     double fp2 = get(c, f, comp, i + 2 * e0, j + 2 * e1, k + 2 * e2);
     double fm1 = get(c, f, comp, i - e0, j - e1, k - e2);
-    return (C1 * (fp1 - f0) + C2 * (fp2 - fm1)) / c->h;
+    return (C1 * (fp1 - f0) + C2 * (fp2 - fm1)) / c->h[axis];
 }
 
 static double dminus_v(const oracle_cfg *c, const double *f, int comp, int axis, long i, long j, long k)
@@ -169,7 +171,7 @@ static double dminus_v(const oracle_cfg *c, const double *f, int comp, int axis,
     double gm1 = get(c, f, comp, i - e0, j - e1, k - e2);
     double gp1 = get(c, f, comp, i + e0, j + e1, k + e2);
     double gm2 = get(c, f, comp, i - 2 * e0, j - 2 * e1, k - 2 * e2);
-    return (C1 * (g0 - gm1) + C2 * (gp1 - gm2)) / c->h;
+    return (C1 * (g0 - gm1) + C2 * (gp1 - gm2)) / c->h[axis];
 }
 
 /* Model value at a node (wrapping on periodic axes). */
@@ -321,7 +323,7 @@ static void normal_strain(const ctx_t *x, const double *const *V, long i, long j
         double l = node(c, x->lam, i, j, k), m = node(c, x->mu, i, j, k);
         e[2] = -l / (l + 2.0 * m) * (e[0] + e[1]);
     } else if (c->free_surface && k == 1) {
-        e[2] = (get(c, V[VZ], VZ, i, j, 1) - get(c, V[VZ], VZ, i, j, 0)) / c->h;
+        e[2] = (get(c, V[VZ], VZ, i, j, 1) - get(c, V[VZ], VZ, i, j, 0)) / c->h[2];
     } else {
         e[2] = dminus_v(c, V[VZ], VZ, 2, i, j, k);
     }
@@ -334,19 +336,22 @@ static double shear_strain(const ctx_t *x, const double *const *V, int comp, lon
     if (comp == SXY) return dplus_v(c, V[VX], VX, 1, i, j, k) + dplus_v(c, V[VY], VY, 0, i, j, k);
     if (comp == SXZ) {
         double dzvx = (c->free_surface && k == 0)
-                          ? (get(c, V[VX], VX, i, j, 1) - get(c, V[VX], VX, i, j, 0)) / c->h
+                          ? (get(c, V[VX], VX, i, j, 1) - get(c, V[VX], VX, i, j, 0)) / c->h[2]
                           : dplus_v(c, V[VX], VX, 2, i, j, k);
         return dzvx + dplus_v(c, V[VZ], VZ, 0, i, j, k);
     }
     double dzvy = (c->free_surface && k == 0)
-                      ? (get(c, V[VY], VY, i, j, 1) - get(c, V[VY], VY, i, j, 0)) / c->h
+                      ? (get(c, V[VY], VY, i, j, 1) - get(c, V[VY], VY, i, j, 0)) / c->h[2]
                       : dplus_v(c, V[VY], VY, 2, i, j, k);
     return dzvy + dplus_v(c, V[VZ], VZ, 1, i, j, k);
 }
 
 /* ---------------- one time step ---------------- */
 
-/* (V) velocity pass: v <- G (v + dt b div(sigma) + dt b w F s / h^3). */
+/* Volume of one cell, dx dy dz (the point sources inject per unit volume). */
+static double cell_volume(const oracle_cfg *c) { return c->h[0] * c->h[1] * c->h[2]; }
+
+/* (V) velocity pass: v <- G (v + dt b div(sigma) + dt b w F s / (dx dy dz)). */
 static void velocity_pass(const ctx_t *x, double *const *F, const oracle_src *src, double s)
 {
     const oracle_cfg *c = x->c;
@@ -366,7 +371,7 @@ static void velocity_pass(const ctx_t *x, double *const *F, const oracle_src *sr
             double amp[8];
             for (int m = 0; m < 8; ++m) {
                 double b = active(c, comp, t.i[m], t.j[m], t.k[m]) ? 1.0 / rho_eff(x, comp, t.i[m], t.j[m], t.k[m]) : 0.0;
-                amp[m] = c->dt * b * src->force[comp] * s / (c->h * c->h * c->h);
+                amp[m] = c->dt * b * src->force[comp] * s / cell_volume(c);
             }
             inject(c, F[comp], comp, src->pos, amp);
         }
@@ -377,7 +382,7 @@ static void velocity_pass(const ctx_t *x, double *const *F, const oracle_src *sr
     }
 }
 
-/* (S) stress pass: sigma <- G (sigma + dt C:eps(v) - dt w M s / h^3); szz(k=0) = 0 with
+/* (S) stress pass: sigma <- G (sigma + dt C:eps(v) - dt w M s / (dx dy dz)); szz(k=0) = 0 with
  * the free surface. Reads only velocities, so all six components update in place. */
 static void stress_pass(const ctx_t *x, double *const *F, const oracle_src *src, double s)
 {
@@ -406,7 +411,7 @@ static void stress_pass(const ctx_t *x, double *const *F, const oracle_src *src,
             int comp = SXX + q;
             if (src->moment[q] == 0.0) continue;
             double amp[8];
-            for (int m = 0; m < 8; ++m) amp[m] = -c->dt * src->moment[q] * s / (c->h * c->h * c->h);
+            for (int m = 0; m < 8; ++m) amp[m] = -c->dt * src->moment[q] * s / cell_volume(c);
             inject(c, F[comp], comp, src->pos, amp);
         }
     }
@@ -426,7 +431,7 @@ static int check_cfg(const oracle_cfg *c)
 {
     for (int a = 0; a < 3; ++a)
         if (c->n[a] < 2) return -1;
-    if (!(c->h > 0.0) || !(c->dt > 0.0) || c->nt < 0) return -1;
+    if (!(c->h[0] > 0.0) || !(c->h[1] > 0.0) || !(c->h[2] > 0.0) || !(c->dt > 0.0) || c->nt < 0) return -1;
     if (c->free_surface && c->periodic[2]) return -1;
     return 0;
 }
@@ -485,7 +490,7 @@ int oracle_gradient(const oracle_cfg *cfg, const double *lam, const double *mu, 
     build_profiles(&x);
     long N = nodes(c), nx = c->n[0], ny = c->n[1], nz = c->n[2];
     int nt = c->nt;
-    double h3 = c->h * c->h * c->h;
+    double h3 = cell_volume(c);
 
     /* forward, storing sigma^n (before step n) and v^{n+1/2} (after the velocity pass) */
     double *Sst = (double *)malloc(sizeof(double) * 6 * N * (size_t)nt);
@@ -572,7 +577,7 @@ int oracle_gradient(const oracle_cfg *cfg, const double *lam, const double *mu, 
                 inject(c, Ab[VX + cc], VX + cc, rec_pos + 3 * r, amp);
             }
 
-        /* adjoint of the velocity pass: U = G_v vbar; g_b += dt (D_S sigma^n + w F s/h^3) U;
+        /* adjoint of the velocity pass: U = G_v vbar; g_b += dt (D_S sigma^n + w F s/(dx dy dz)) U;
          * sbar -= dt E(b U); vbar = U */
         for (int comp = VX; comp <= VZ; ++comp) {
 #pragma omp parallel for schedule(static)
@@ -679,7 +684,7 @@ int oracle_deriv1d(int n, double h, int plus, const double *in, double *out)
 {
     oracle_cfg c;
     memset(&c, 0, sizeof c);
-    c.n[0] = n; c.n[1] = 1; c.n[2] = 1; c.h = h; c.dt = 1.0;
+    c.n[0] = n; c.n[1] = 1; c.n[2] = 1; c.h[0] = c.h[1] = c.h[2] = h; c.dt = 1.0;
     for (long i = 0; i < n; ++i) {
         if (plus) out[i] = (i <= n - 2) ? dplus_v(&c, in, SXX, 0, i, 0, 0) : 0.0;
         else out[i] = dminus_v(&c, in, VX, 0, i, 0, 0);

@@ -28,12 +28,14 @@ def active_mask(comp: int, shape_xyz, periodic=(False, False, False)) -> np.ndar
     return m
 
 
-def coords(comp: int, shape_xyz, h: float):
-    """(X, Y, Z) coordinates in metres of every sample of a component, [nz,ny,nx]."""
+def coords(comp: int, shape_xyz, h):
+    """(X, Y, Z) coordinates in metres of every sample of a component, [nz,ny,nx]; h is
+    one spacing or (dx, dy, dz)."""
     nx, ny, nz = shape_xyz
+    hx, hy, hz = (h, h, h) if np.ndim(h) == 0 else h
     s = STAG[comp]
-    z, y, x = np.meshgrid((np.arange(nz) + 0.5 * s[2]) * h, (np.arange(ny) + 0.5 * s[1]) * h,
-                          (np.arange(nx) + 0.5 * s[0]) * h, indexing="ij")
+    z, y, x = np.meshgrid((np.arange(nz) + 0.5 * s[2]) * hz, (np.arange(ny) + 0.5 * s[1]) * hy,
+                          (np.arange(nx) + 0.5 * s[0]) * hx, indexing="ij")
     return x, y, z
 
 

@@ -15,10 +15,10 @@ SPONGE = (6,) * 6
 ALPHA = 0.05
 
 
-def fd_setup():
+def fd_setup(h=H):
     lam, mu, rho, srcs, rec = W.small_fd_case(nt=NT)
     shape = (lam.shape[2], lam.shape[1], lam.shape[0])
-    cfg = oracle.Config(shape, H, DT, NT, sponge=SPONGE, alpha=ALPHA)
+    cfg = oracle.Config(shape, h, DT, NT, sponge=SPONGE, alpha=ALPHA)
     wav = W.ricker(25.0, NT, DT)
     # observed data from a model with a slow blob
     nz, ny, nx = lam.shape
@@ -52,9 +52,9 @@ def misfit_only(cfg, model, srcs_obs, rec, wav, srcs):
     return J
 
 
-@pytest.mark.parametrize("kind", ["moment", "force"])
-def test_gradient_matches_central_differences(kind):
-    cfg, model, true, src_pos, rec, wav = fd_setup()
+@pytest.mark.parametrize("kind,h", [("moment", H), ("force", H), ("force", (10.0, 12.0, 8.0))])
+def test_gradient_matches_central_differences(kind, h):
+    cfg, model, true, src_pos, rec, wav = fd_setup(h)
     if kind == "moment":
         srcs = [oracle.Source(p, moment=W.explosion(1e15)) for p in src_pos]
     else:
@@ -82,14 +82,15 @@ def test_gradient_matches_central_differences(kind):
             assert abs(fd - an) <= 1e-6 * abs(an), (p, direction, fd, an)
 
 
-def test_adjoint_state_dot_product():
+@pytest.mark.parametrize("h", [H, (10.0, 8.0, 12.0)])
+def test_adjoint_state_dot_product(h):
     """Sources off, random initial state x0 and random residual r:
     <P x0, r> = <x0, P^T r> where P^T r is the adjoint of the initial state."""
     shape = (18, 16, 14)
     rng = np.random.default_rng(22)
     lam, mu, rho = W.elastic_from_vp(3000.0 * (1 + 0.2 * rng.random((14, 16, 18))))
     nt = 50
-    cfg = oracle.Config(shape, H, DT, nt, sponge=(4, 5, 3, 4, 5, 3))
+    cfg = oracle.Config(shape, h, DT, nt, sponge=(4, 5, 3, 4, 5, 3))
     x0 = random_state(shape, rng)
     rec = np.array([[4.2, 5.5, 6.1], [12.7, 9.3, 3.3], [8.0, 8.0, 8.0]])
     d, _ = oracle.forward(cfg, lam, mu, rho, None, None, rec, state=x0)

@@ -124,9 +124,11 @@ def test_mirror_symmetry():
             assert np.max(np.abs(core - sign * mir)) <= 1e-14 * scale, (a, c)
 
 
-def test_axis_permutation():
-    """Swapping x and y in the model and source swaps the fields exactly (up to
-    summation order): catches index mix-ups between axes."""
+@pytest.mark.parametrize("h", [10.0, (10.0, 8.0, 12.0)])
+def test_axis_permutation(h):
+    """Swapping x and y in the model, source and spacing swaps the fields exactly (up to
+    summation order): catches index mix-ups between axes, including a spacing taken
+    from the wrong axis."""
     shape = (12, 15, 11)
     lam, mu, rho = hetero_model(shape, 11)
     nt = 25
@@ -134,13 +136,14 @@ def test_axis_permutation():
     pos = (5.3, 7.6, 4.9)
     wav = W.ricker(30.0, nt, 1e-3)
     sponge = (3, 4, 5, 2, 3, 6)
-    cfg = oracle.Config(shape, 10.0, 1e-3, nt, sponge=sponge)
+    hs = (h, h, h) if np.ndim(h) == 0 else h
+    cfg = oracle.Config(shape, hs, 1e-3, nt, sponge=sponge)
     rec = np.array([[3.2, 9.1, 6.6], [8.4, 4.7, 2.2]])
     ta, a = oracle.forward(cfg, lam, mu, rho, oracle.Source(pos, moment=mt), wav, rec)
     T = lambda f: np.ascontiguousarray(np.swapaxes(f, 1, 2))
     shape_b = (15, 12, 11)
     sponge_b = (5, 2, 3, 4, 3, 6)
-    cfg_b = oracle.Config(shape_b, 10.0, 1e-3, nt, sponge=sponge_b)
+    cfg_b = oracle.Config(shape_b, (hs[1], hs[0], hs[2]), 1e-3, nt, sponge=sponge_b)
     mt_b = (mt[1], mt[0], mt[2], mt[3], mt[5], mt[4])
     tb, b = oracle.forward(cfg_b, T(lam), T(mu), T(rho), oracle.Source((pos[1], pos[0], pos[2]), moment=mt_b),
                            wav, rec[:, [1, 0, 2]])
