@@ -14,9 +14,11 @@ Also reported (same JSON line):
   roofline -- the dominant forward kernel's algorithmic bytes / its HIP-event duration;
   c2_forward -- the 512x512x256 free-surface workload (300 steps);
   stream_copy_gbs -- a plain 1 GiB device copy (read + write GB/s), the practical ceiling;
+  levels   -- the paper's Table 5 level sweep (64x64x32 .. 512^3, anisotropic cells, one
+              coarse medium upsampled to every grid), 100 timed steps per level;
   cpu_baseline -- the FP64 oracle on a bounded sample on this host's cores.
 
-    python bench.py [--steps 2000] [--warmup 100] [--gpus 1] [--no-batch] [--no-grad]
+    python bench.py [--steps 2000] [--warmup 100] [--gpus 1] [--no-batch] [--no-grad] [--no-levels]
 """
 from __future__ import annotations
 
@@ -250,6 +252,85 @@ def bench_batch():
                 workgroups=tune["workgroups"], cell_steps=cells_steps)
 
 
+# The paper's levels of detail (Table 5): grid (nx, ny, nz), cell size (km per axis), dt (s),
+# time steps of the full simulation.
+TABLE5 = [
+    ((64, 64, 32), (6.67, 10.61, 3.75), 0.1, 1700),
+    ((64, 64, 64), (6.67, 10.61, 1.87), 0.1, 1700),
+    ((128, 64, 64), (3.33, 10.61, 1.87), 0.1, 1700),
+    ((128, 128, 64), (3.33, 5.30, 1.87), 0.1, 1700),
+    ((128, 128, 128), (3.33, 5.30, 0.93), 0.05, 3400),
+    ((256, 128, 128), (1.66, 5.30, 0.93), 0.05, 3400),
+    ((256, 256, 128), (1.66, 2.65, 0.93), 0.05, 3400),
+    ((256, 256, 256), (1.66, 2.65, 0.46), 0.01, 17000),
+    ((512, 256, 256), (0.83, 2.65, 0.46), 0.01, 17000),
+    ((512, 512, 256), (0.83, 1.32, 0.46), 0.01, 17000),
+    ((512, 512, 512), (0.83, 1.32, 0.23), 0.01, 17000),
+]
+
+
+def bench_levels(K=100):
+    """The Table 5 level sweep: one medium given on the level-0 node grid (64 x 64 x 32; a
+    layered crust, 5.8 / 6.5 / 8.0 km/s with a 5 % Gaussian-correlated perturbation) is
+    upsampled on the GPU to every level's grid; each level runs with its own anisotropic
+    cells and dt (explosion at the centre, 16 receivers below the top, 10-cell sponge),
+    K timed steps after autotuning: the single-shot forward (one launch per pass) and the
+    same steps replayed from a hipGraph (a one-shot batch whose one group uses the shot's
+    own tuned kernel), which removes the host launch cost on the small levels."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2112_15071_amd import Simulator, upsample
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    dev = torch.device("cuda:0")
+    (mx, my, mz), dp0 = TABLE5[0][0], TABLE5[0][1]
+    rng = np.random.Generator(np.random.PCG64(1005))
+    depth = np.arange(mz) * dp0[2]
+    vp = np.where(depth < 20.0, 5800.0, np.where(depth < 35.0, 6500.0, 8000.0))[:, None, None] * np.ones((mz, my, mx))
+    vp = vp * (1.0 + 0.05 * W.gaussian_field((mz, my, mx), 2.0 * dp0[0] * 1e3, dp0[0] * 1e3, rng))
+    coarse = [torch.as_tensor(a, dtype=torch.float32, device=dev) for a in W.elastic_from_vp(vp)]
+    out = []
+    for lev, (shape, dp, dt, nt_full) in enumerate(TABLE5):
+        nx, ny, nz = shape
+        lam, mu, rho = (upsample(c, shape) for c in coarse)
+        h = tuple(v * 1e3 for v in dp)
+        sim = Simulator(lam, mu, rho, h, dt, K, sponge=10, device=dev)
+        sim.autotune(steps=5)
+        src = (nx / 2, ny / 2, nz / 2)
+        rec = W.receiver_grid(np.linspace(12, nx - 13, 4), np.linspace(12, ny - 13, 4), 12.0)
+        wav = torch.as_tensor(W.ricker(0.05 if lev < 3 else 0.1, K, dt), dtype=torch.float32, device=dev)
+        traces = torch.empty((len(rec), 3, K), dtype=torch.float32, device=dev)
+        sim.forward(src, W.explosion(1e15), (0.0, 0.0, 0.0), wav, rec, traces=traces)
+        sync()
+        t0 = time.perf_counter()
+        sim.forward(src, W.explosion(1e15), (0.0, 0.0, 0.0), wav, rec, traces=traces)
+        sync()
+        el = time.perf_counter() - t0
+        batch = BatchSimulator([sim])
+        batch.set_schedule(1 << 50)  # one group: the shot's own kernel shape
+        desc = [dict(src_pos=src, moment=W.explosion(1e15), wavelet=wav, rec_pos=rec)]
+        batch.forward(desc, use_graph=True, traces=[traces])  # capture + first replay
+        sync()
+        t0 = time.perf_counter()
+        batch.forward(desc, use_graph=True, traces=[traces])
+        sync()
+        el_g = time.perf_counter() - t0
+        batch.close()
+        cells = nx * ny * nz
+        best = min(el, el_g)
+        row = dict(level=lev, grid=list(shape), cell_m=list(h), dt=dt, steps_timed=K,
+                   gcs=round(cells * K / el / 1e9, 3), gcs_graph=round(cells * K / el_g / 1e9, 3),
+                   ms_per_step=round(best / K * 1e3, 4), full_run_s=round(best / K * nt_full, 2), kernel=sim.kernel())
+        log(f"[bench] level {lev} {shape}: {row['gcs']} Gcell-steps/s ({row['gcs_graph']} from a graph), "
+            f"{row['ms_per_step']} ms/step, {nt_full} steps in {row['full_run_s']} s")
+        out.append(row)
+        sim.close()
+        del lam, mu, rho
+    return out
+
+
 def bench_gradient(wave=4, nshots=8):
     import numpy as np
     import torch
@@ -382,6 +463,7 @@ def main():
     ap.add_argument("--no-c2", action="store_true", help="skip the 512x512x256 free-surface section")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-levels", action="store_true", help="skip the Table 5 level sweep")
     ap.add_argument("--kernel", metavar="VARIANT,TX,TY,ZC", default=None,
                     help="forward kernel configuration (default: autotuned, cached per grid)")
     ap.add_argument("--grad-shots", type=int, default=8, help="shots of the gradient section (profiling runs: fewer)")
@@ -402,6 +484,7 @@ def main():
     c2 = None if args.no_c2 else bench_c2()
     batch = None if args.no_batch else bench_batch()
     grad = None if args.no_grad else bench_gradient(nshots=args.grad_shots)
+    levels = None if args.no_levels else bench_levels()
     cpu = cpu_baseline(shot, args.cpu_steps) if args.cpu_steps > 0 else None
     nx, ny, nz = shot.shape
     out = {
@@ -443,6 +526,7 @@ def main():
         "c2_forward": c2,
         "batched_forward": batch,
         "gradient": grad,
+        "levels": levels,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

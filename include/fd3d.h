@@ -75,12 +75,17 @@ typedef struct fd3d_opts {
     int free_surface;    /* 1: stress-imaging free surface at k = 0 (top width ignored) */
     int check_finite;    /* 1: forward returns FD3D_ENONFINITE if the final state blew up */
     int max_receivers;   /* receiver capacity of the workspace; <= 0 selects 4096 */
+    double dy, dz;       /* spacing along y and z (m); 0 selects dx (cubic cells).  Table 5
+                          * runs cells of different size per axis: each Eq.(4) derivative
+                          * divides by its own axis' spacing, point sources inject per
+                          * cell volume dx dy dz, and the stability bound becomes
+                          * dt <= (6/7) / (vp_max sqrt(1/dx^2 + 1/dy^2 + 1/dz^2)). */
 } fd3d_opts;
 
 typedef struct fd3d_source {
     double pos[3];       /* grid units */
-    double moment[6];    /* Mxx Myy Mzz Mxy Mxz Myz (N m): sigma_ij -= dt w M_ij s[n] / dx^3 */
-    double force[3];     /* Fx Fy Fz (N): v_i += dt b w F_i s[n] / dx^3 */
+    double moment[6];    /* Mxx Myy Mzz Mxy Mxz Myz (N m): sigma_ij -= dt w M_ij s[n] / (dx dy dz) */
+    double force[3];     /* Fx Fy Fz (N): v_i += dt b w F_i s[n] / (dx dy dz) */
     const void *wavelet; /* device T[nt]: s[n] (moment rate, 1/s, for moment sources) */
 } fd3d_source;
 
@@ -97,9 +102,10 @@ const char *fd3d_last_error(void);
 int fd3d_workspace_bytes(int nx, int ny, int nz, const fd3d_opts *opts, size_t *bytes);
 
 /* Create a context over caller-owned device node arrays lam, mu, rho (T[nz][ny][nx],
- * Sec. 2.2 / 2.2.1) with spacing dx (m), step dt (s) and nt steps.  Validates the model
- * on the device (FD3D_EMODEL), checks dt against 6/(7 sqrt 3) dx / vp_max (FD3D_ECFL;
- * Eq.(5) prints the rounded 0.495), builds the damping profiles on the host in double
+ * Sec. 2.2 / 2.2.1) with spacing dx (m; dy, dz in opts), step dt (s) and nt steps.
+ * Validates the model on the device (FD3D_EMODEL), checks dt against
+ * (6/7) / (vp_max sqrt(1/dx^2 + 1/dy^2 + 1/dz^2)), i.e. 6/(7 sqrt 3) dx / vp_max for cubic
+ * cells (FD3D_ECFL; Eq.(5) prints the rounded 0.495), builds the damping profiles on the host in double
  * and uploads them.  workspace: device, >= fd3d_workspace_bytes, 256-byte aligned.
  * Synchronises the stream once (model statistics). */
 int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const void *mu,
@@ -271,6 +277,17 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
  * profiled call. */
 int fd3d_profile(fd3d_ctx *ctx, int enable);
 int fd3d_profile_read(fd3d_ctx *ctx, double ms[4], int launches[4]);
+
+/* Coarse medium grid (Sec. 2.2.1: the medium textures may be smaller than the simulation
+ * grid, every read being a trilinear sample).  Samples coarse (device T[mz][my][mx]) at
+ * every node of the simulation grid, fine (device T[nz][ny][nx]): both grids span the same
+ * box corner node to corner node, so fine node i sits at coarse coordinate
+ * i (m - 1) / (n - 1) per axis (m = 1: constant along that axis).  Weights and sums in
+ * double.  Use it for lam, mu and rho before fd3d_create.  Caller-owned, non-overlapping
+ * buffers; enqueued on the stream.  FD3D_EINVAL for NULL, sizes < 1, a bad dtype or
+ * overlapping buffers. */
+int fd3d_upsample(const void *coarse, int mx, int my, int mz, void *fine, int nx, int ny,
+                  int nz, int dtype, void *hip_stream);
 
 void fd3d_destroy(fd3d_ctx *ctx);
 

@@ -244,3 +244,31 @@ def misfit(traces, d_obs) -> float:
     """J = 1/2 sum (d - d_obs)^2 (no dt weighting)."""
     r = np.asarray(traces) - np.asarray(d_obs)
     return 0.5 * float(np.sum(r * r))
+
+
+def upsample(coarse, shape) -> np.ndarray:
+    """Medium parameters given on a coarse node grid, sampled trilinearly at the nodes of
+    the simulation grid (Sec. 2.2.1: the medium textures may be smaller than the
+    simulation grid; every read is a trilinear sample).  ``coarse`` is [mz, my, mx],
+    ``shape`` the simulation grid (nx, ny, nz); both grids span the same box, corner node
+    to corner node, so fine node i sits at coarse coordinate i (m - 1) / (n - 1).
+    Written out per axis as the textbook formula, no library interpolator."""
+    c = _f64(coarse)
+    mz, my, mx = c.shape
+    nx, ny, nz = (int(v) for v in shape)
+
+    def axis(n, m):
+        """Lower coarse index and weight of the upper one for each fine node."""
+        q = np.arange(n) * ((m - 1) / (n - 1)) if n > 1 else np.zeros(1)
+        lo = np.minimum(np.floor(q).astype(np.int64), max(m - 2, 0))
+        return lo, q - lo
+
+    (ix, wx), (iy, wy), (iz, wz) = axis(nx, mx), axis(ny, my), axis(nz, mz)
+    ix1, iy1, iz1 = np.minimum(ix + 1, mx - 1), np.minimum(iy + 1, my - 1), np.minimum(iz + 1, mz - 1)
+    out = np.zeros((nz, ny, nx))
+    for k in range(nz):
+        for dz, fz in ((iz[k], 1.0 - wz[k]), (iz1[k], wz[k])):
+            for dy, fy in ((iy, 1.0 - wy), (iy1, wy)):
+                for dx, fx in ((ix, 1.0 - wx), (ix1, wx)):
+                    out[k] += fz * fy[:, None] * fx[None, :] * c[dz][np.ix_(dy, dx)]
+    return out

@@ -49,6 +49,8 @@ class fd3d_opts(ctypes.Structure):
         ("free_surface", ctypes.c_int),
         ("check_finite", ctypes.c_int),
         ("max_receivers", ctypes.c_int),
+        ("dy", ctypes.c_double),
+        ("dz", ctypes.c_double),
     ]
 
 
@@ -114,6 +116,7 @@ _SIGS = {
     "fd3d_get_kernel": ([_vp, ctypes.POINTER(fd3d_kernel)], _i),
     "fd3d_profile": ([_vp, _i], _i),
     "fd3d_profile_read": ([_vp, _dp, ctypes.POINTER(_i)], _i),
+    "fd3d_upsample": ([_vp, _i, _i, _i, _vp, _i, _i, _i, _i, _vp], _i),
     "fd3d_destroy": ([_vp], None),
 }
 
@@ -310,3 +313,9 @@ def fd3d_profile_read(ctx):
 
 def fd3d_destroy(ctx) -> None:
     _lib.fd3d_destroy(ctx)
+
+
+def fd3d_upsample(coarse_ptr, mshape, fine_ptr, nshape, dtype_code: int, stream) -> None:
+    """mshape, nshape: (x, y, z) sizes of the coarse and the simulation grid."""
+    _check(_lib.fd3d_upsample(coarse_ptr, int(mshape[0]), int(mshape[1]), int(mshape[2]), fine_ptr,
+                              int(nshape[0]), int(nshape[1]), int(nshape[2]), int(dtype_code), stream))

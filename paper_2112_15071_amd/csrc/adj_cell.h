@@ -72,50 +72,50 @@ template <typename T>
 __device__ __forceinline__ void adj_stress_body(const Grid<T> &G, const AdjGrid<T> &A, int i, int j, int k)
 {
     const long p = i + G.sy * j + G.sz * k;
-    const T rdx = G.rdx, dt = G.dt;
+    const T rdx = G.rdx, rdy = G.rdy, rdz = G.rdz, dt = G.dt;
 
     // A_v <- G_v A_v - dt D_S(C T)
     if (i <= G.nx - 2) {
         const T d = dstag(xval(G, A, SXX, i + 1, j, k), xval(G, A, SXX, i, j, k), xval(G, A, SXX, i + 2, j, k), xval(G, A, SXX, i - 1, j, k), rdx)
-                  + dstag(xval(G, A, SXY, i, j, k), xval(G, A, SXY, i, j - 1, k), xval(G, A, SXY, i, j + 1, k), xval(G, A, SXY, i, j - 2, k), rdx)
-                  + dstag(xval(G, A, SXZ, i, j, k), xval(G, A, SXZ, i, j, k - 1), xval(G, A, SXZ, i, j, k + 1), xval(G, A, SXZ, i, j, k - 2), rdx);
+                  + dstag(xval(G, A, SXY, i, j, k), xval(G, A, SXY, i, j - 1, k), xval(G, A, SXY, i, j + 1, k), xval(G, A, SXY, i, j - 2, k), rdy)
+                  + dstag(xval(G, A, SXZ, i, j, k), xval(G, A, SXZ, i, j, k - 1), xval(G, A, SXZ, i, j, k + 1), xval(G, A, SXZ, i, j, k - 2), rdz);
         A.a[VX][p] = damp(G, VX, i, j, k) * A.a[VX][p] - dt * d;
     }
     if (j <= G.ny - 2) {
         const T d = dstag(xval(G, A, SXY, i, j, k), xval(G, A, SXY, i - 1, j, k), xval(G, A, SXY, i + 1, j, k), xval(G, A, SXY, i - 2, j, k), rdx)
-                  + dstag(xval(G, A, SYY, i, j + 1, k), xval(G, A, SYY, i, j, k), xval(G, A, SYY, i, j + 2, k), xval(G, A, SYY, i, j - 1, k), rdx)
-                  + dstag(xval(G, A, SYZ, i, j, k), xval(G, A, SYZ, i, j, k - 1), xval(G, A, SYZ, i, j, k + 1), xval(G, A, SYZ, i, j, k - 2), rdx);
+                  + dstag(xval(G, A, SYY, i, j + 1, k), xval(G, A, SYY, i, j, k), xval(G, A, SYY, i, j + 2, k), xval(G, A, SYY, i, j - 1, k), rdy)
+                  + dstag(xval(G, A, SYZ, i, j, k), xval(G, A, SYZ, i, j, k - 1), xval(G, A, SYZ, i, j, k + 1), xval(G, A, SYZ, i, j, k - 2), rdz);
         A.a[VY][p] = damp(G, VY, i, j, k) * A.a[VY][p] - dt * d;
     }
     if (k <= G.nz - 2) {
         const T d = dstag(xval(G, A, SXZ, i, j, k), xval(G, A, SXZ, i - 1, j, k), xval(G, A, SXZ, i + 1, j, k), xval(G, A, SXZ, i - 2, j, k), rdx)
-                  + dstag(xval(G, A, SYZ, i, j, k), xval(G, A, SYZ, i, j - 1, k), xval(G, A, SYZ, i, j + 1, k), xval(G, A, SYZ, i, j - 2, k), rdx)
-                  + dstag(xval(G, A, SZZ, i, j, k + 1), xval(G, A, SZZ, i, j, k), xval(G, A, SZZ, i, j, k + 2), xval(G, A, SZZ, i, j, k - 1), rdx);
+                  + dstag(xval(G, A, SYZ, i, j, k), xval(G, A, SYZ, i, j - 1, k), xval(G, A, SYZ, i, j + 1, k), xval(G, A, SYZ, i, j - 2, k), rdy)
+                  + dstag(xval(G, A, SZZ, i, j, k + 1), xval(G, A, SZZ, i, j, k), xval(G, A, SZZ, i, j, k + 2), xval(G, A, SZZ, i, j, k - 1), rdz);
         A.a[VZ][p] = damp(G, VZ, i, j, k) * A.a[VZ][p] - dt * d;
     }
 
     // gradients of C: strain rates of the stored v^{n+1/2} against T
     const T *vx = A.vst[0], *vy = A.vst[1], *vz = A.vst[2];
     const T exx = dstag(rdc(vx, VX, i, j, k, G), rdc(vx, VX, i - 1, j, k, G), rdc(vx, VX, i + 1, j, k, G), rdc(vx, VX, i - 2, j, k, G), rdx);
-    const T eyy = dstag(rdc(vy, VY, i, j, k, G), rdc(vy, VY, i, j - 1, k, G), rdc(vy, VY, i, j + 1, k, G), rdc(vy, VY, i, j - 2, k, G), rdx);
-    const T ezz = dstag(rdc(vz, VZ, i, j, k, G), rdc(vz, VZ, i, j, k - 1, G), rdc(vz, VZ, i, j, k + 1, G), rdc(vz, VZ, i, j, k - 2, G), rdx);
+    const T eyy = dstag(rdc(vy, VY, i, j, k, G), rdc(vy, VY, i, j - 1, k, G), rdc(vy, VY, i, j + 1, k, G), rdc(vy, VY, i, j - 2, k, G), rdy);
+    const T ezz = dstag(rdc(vz, VZ, i, j, k, G), rdc(vz, VZ, i, j, k - 1, G), rdc(vz, VZ, i, j, k + 1, G), rdc(vz, VZ, i, j, k - 2, G), rdz);
     const T gn = damp(G, SXX, i, j, k);
     const T txx = gn * A.a[SXX][p], tyy = gn * A.a[SYY][p], tzz = gn * A.a[SZZ][p];
     A.gl[p] += dt * ((exx + eyy) + ezz) * ((txx + tyy) + tzz);
     A.gm[p] += dt * T(2) * ((exx * txx + eyy * tyy) + ezz * tzz);
     if (i <= G.nx - 2 && j <= G.ny - 2) {
-        const T e = dstag(rdc(vx, VX, i, j + 1, k, G), rdc(vx, VX, i, j, k, G), rdc(vx, VX, i, j + 2, k, G), rdc(vx, VX, i, j - 1, k, G), rdx)
+        const T e = dstag(rdc(vx, VX, i, j + 1, k, G), rdc(vx, VX, i, j, k, G), rdc(vx, VX, i, j + 2, k, G), rdc(vx, VX, i, j - 1, k, G), rdy)
                   + dstag(rdc(vy, VY, i + 1, j, k, G), rdc(vy, VY, i, j, k, G), rdc(vy, VY, i + 2, j, k, G), rdc(vy, VY, i - 1, j, k, G), rdx);
         A.gs[0][p] += dt * e * (damp(G, SXY, i, j, k) * A.a[SXY][p]);
     }
     if (i <= G.nx - 2 && k <= G.nz - 2) {
-        const T e = dstag(rdc(vx, VX, i, j, k + 1, G), rdc(vx, VX, i, j, k, G), rdc(vx, VX, i, j, k + 2, G), rdc(vx, VX, i, j, k - 1, G), rdx)
+        const T e = dstag(rdc(vx, VX, i, j, k + 1, G), rdc(vx, VX, i, j, k, G), rdc(vx, VX, i, j, k + 2, G), rdc(vx, VX, i, j, k - 1, G), rdz)
                   + dstag(rdc(vz, VZ, i + 1, j, k, G), rdc(vz, VZ, i, j, k, G), rdc(vz, VZ, i + 2, j, k, G), rdc(vz, VZ, i - 1, j, k, G), rdx);
         A.gs[1][p] += dt * e * (damp(G, SXZ, i, j, k) * A.a[SXZ][p]);
     }
     if (j <= G.ny - 2 && k <= G.nz - 2) {
-        const T e = dstag(rdc(vy, VY, i, j, k + 1, G), rdc(vy, VY, i, j, k, G), rdc(vy, VY, i, j, k + 2, G), rdc(vy, VY, i, j, k - 1, G), rdx)
-                  + dstag(rdc(vz, VZ, i, j + 1, k, G), rdc(vz, VZ, i, j, k, G), rdc(vz, VZ, i, j + 2, k, G), rdc(vz, VZ, i, j - 1, k, G), rdx);
+        const T e = dstag(rdc(vy, VY, i, j, k + 1, G), rdc(vy, VY, i, j, k, G), rdc(vy, VY, i, j, k + 2, G), rdc(vy, VY, i, j, k - 1, G), rdz)
+                  + dstag(rdc(vz, VZ, i, j + 1, k, G), rdc(vz, VZ, i, j, k, G), rdc(vz, VZ, i, j + 2, k, G), rdc(vz, VZ, i, j - 1, k, G), rdy);
         A.gs[2][p] += dt * e * (damp(G, SYZ, i, j, k) * A.a[SYZ][p]);
     }
 }
@@ -144,40 +144,40 @@ __device__ __forceinline__ void adj_vel_body(const Grid<T> &G, const AdjGrid<T> 
                                              int j, int k)
 {
     const long p = i + G.sy * j + G.sz * k;
-    const T rdx = G.rdx, dt = G.dt;
+    const T rdx = G.rdx, rdy = G.rdy, rdz = G.rdz, dt = G.dt;
     const T s = src.on ? src.wavelet[n] : T(0);
 
     // A_s <- G_s A_s - dt E(b U)
     {
         const T gn = damp(G, SXX, i, j, k);
         const T exx = dstag(yval(G, A, VX, i, j, k), yval(G, A, VX, i - 1, j, k), yval(G, A, VX, i + 1, j, k), yval(G, A, VX, i - 2, j, k), rdx);
-        const T eyy = dstag(yval(G, A, VY, i, j, k), yval(G, A, VY, i, j - 1, k), yval(G, A, VY, i, j + 1, k), yval(G, A, VY, i, j - 2, k), rdx);
-        const T ezz = dstag(yval(G, A, VZ, i, j, k), yval(G, A, VZ, i, j, k - 1), yval(G, A, VZ, i, j, k + 1), yval(G, A, VZ, i, j, k - 2), rdx);
+        const T eyy = dstag(yval(G, A, VY, i, j, k), yval(G, A, VY, i, j - 1, k), yval(G, A, VY, i, j + 1, k), yval(G, A, VY, i, j - 2, k), rdy);
+        const T ezz = dstag(yval(G, A, VZ, i, j, k), yval(G, A, VZ, i, j, k - 1), yval(G, A, VZ, i, j, k + 1), yval(G, A, VZ, i, j, k - 2), rdz);
         A.a[SXX][p] = gn * A.a[SXX][p] - dt * exx;
         A.a[SYY][p] = gn * A.a[SYY][p] - dt * eyy;
         A.a[SZZ][p] = gn * A.a[SZZ][p] - dt * ezz;
     }
     if (i <= G.nx - 2 && j <= G.ny - 2) {
-        const T e = dstag(yval(G, A, VX, i, j + 1, k), yval(G, A, VX, i, j, k), yval(G, A, VX, i, j + 2, k), yval(G, A, VX, i, j - 1, k), rdx)
+        const T e = dstag(yval(G, A, VX, i, j + 1, k), yval(G, A, VX, i, j, k), yval(G, A, VX, i, j + 2, k), yval(G, A, VX, i, j - 1, k), rdy)
                   + dstag(yval(G, A, VY, i + 1, j, k), yval(G, A, VY, i, j, k), yval(G, A, VY, i + 2, j, k), yval(G, A, VY, i - 1, j, k), rdx);
         A.a[SXY][p] = damp(G, SXY, i, j, k) * A.a[SXY][p] - dt * e;
     }
     if (i <= G.nx - 2 && k <= G.nz - 2) {
-        const T e = dstag(yval(G, A, VX, i, j, k + 1), yval(G, A, VX, i, j, k), yval(G, A, VX, i, j, k + 2), yval(G, A, VX, i, j, k - 1), rdx)
+        const T e = dstag(yval(G, A, VX, i, j, k + 1), yval(G, A, VX, i, j, k), yval(G, A, VX, i, j, k + 2), yval(G, A, VX, i, j, k - 1), rdz)
                   + dstag(yval(G, A, VZ, i + 1, j, k), yval(G, A, VZ, i, j, k), yval(G, A, VZ, i + 2, j, k), yval(G, A, VZ, i - 1, j, k), rdx);
         A.a[SXZ][p] = damp(G, SXZ, i, j, k) * A.a[SXZ][p] - dt * e;
     }
     if (j <= G.ny - 2 && k <= G.nz - 2) {
-        const T e = dstag(yval(G, A, VY, i, j, k + 1), yval(G, A, VY, i, j, k), yval(G, A, VY, i, j, k + 2), yval(G, A, VY, i, j, k - 1), rdx)
-                  + dstag(yval(G, A, VZ, i, j + 1, k), yval(G, A, VZ, i, j, k), yval(G, A, VZ, i, j + 2, k), yval(G, A, VZ, i, j - 1, k), rdx);
+        const T e = dstag(yval(G, A, VY, i, j, k + 1), yval(G, A, VY, i, j, k), yval(G, A, VY, i, j, k + 2), yval(G, A, VY, i, j, k - 1), rdz)
+                  + dstag(yval(G, A, VZ, i, j + 1, k), yval(G, A, VZ, i, j, k), yval(G, A, VZ, i, j + 2, k), yval(G, A, VZ, i, j - 1, k), rdy);
         A.a[SYZ][p] = damp(G, SYZ, i, j, k) * A.a[SYZ][p] - dt * e;
     }
 
     // gradient of b: dt (D_S sigma^n + w F s / dx^3) U at the velocity samples
     if (i <= G.nx - 2) {
         const T d = dstag(sv(G, A, SXX, i + 1, j, k), sv(G, A, SXX, i, j, k), sv(G, A, SXX, i + 2, j, k), sv(G, A, SXX, i - 1, j, k), rdx)
-                  + dstag(sv(G, A, SXY, i, j, k), sv(G, A, SXY, i, j - 1, k), sv(G, A, SXY, i, j + 1, k), sv(G, A, SXY, i, j - 2, k), rdx)
-                  + dstag(sv(G, A, SXZ, i, j, k), sv(G, A, SXZ, i, j, k - 1), sv(G, A, SXZ, i, j, k + 1), sv(G, A, SXZ, i, j, k - 2), rdx);
+                  + dstag(sv(G, A, SXY, i, j, k), sv(G, A, SXY, i, j - 1, k), sv(G, A, SXY, i, j + 1, k), sv(G, A, SXY, i, j - 2, k), rdy)
+                  + dstag(sv(G, A, SXZ, i, j, k), sv(G, A, SXZ, i, j, k - 1), sv(G, A, SXZ, i, j, k + 1), sv(G, A, SXZ, i, j, k - 2), rdz);
         const T u = damp(G, VX, i, j, k) * A.a[VX][p];
         T g = dt * d * u;
         const int t = tap_of(src, VX, i, j, k);
@@ -186,8 +186,8 @@ __device__ __forceinline__ void adj_vel_body(const Grid<T> &G, const AdjGrid<T> 
     }
     if (j <= G.ny - 2) {
         const T d = dstag(sv(G, A, SXY, i, j, k), sv(G, A, SXY, i - 1, j, k), sv(G, A, SXY, i + 1, j, k), sv(G, A, SXY, i - 2, j, k), rdx)
-                  + dstag(sv(G, A, SYY, i, j + 1, k), sv(G, A, SYY, i, j, k), sv(G, A, SYY, i, j + 2, k), sv(G, A, SYY, i, j - 1, k), rdx)
-                  + dstag(sv(G, A, SYZ, i, j, k), sv(G, A, SYZ, i, j, k - 1), sv(G, A, SYZ, i, j, k + 1), sv(G, A, SYZ, i, j, k - 2), rdx);
+                  + dstag(sv(G, A, SYY, i, j + 1, k), sv(G, A, SYY, i, j, k), sv(G, A, SYY, i, j + 2, k), sv(G, A, SYY, i, j - 1, k), rdy)
+                  + dstag(sv(G, A, SYZ, i, j, k), sv(G, A, SYZ, i, j, k - 1), sv(G, A, SYZ, i, j, k + 1), sv(G, A, SYZ, i, j, k - 2), rdz);
         const T u = damp(G, VY, i, j, k) * A.a[VY][p];
         T g = dt * d * u;
         const int t = tap_of(src, VY, i, j, k);
@@ -196,8 +196,8 @@ __device__ __forceinline__ void adj_vel_body(const Grid<T> &G, const AdjGrid<T> 
     }
     if (k <= G.nz - 2) {
         const T d = dstag(sv(G, A, SXZ, i, j, k), sv(G, A, SXZ, i - 1, j, k), sv(G, A, SXZ, i + 1, j, k), sv(G, A, SXZ, i - 2, j, k), rdx)
-                  + dstag(sv(G, A, SYZ, i, j, k), sv(G, A, SYZ, i, j - 1, k), sv(G, A, SYZ, i, j + 1, k), sv(G, A, SYZ, i, j - 2, k), rdx)
-                  + dstag(sv(G, A, SZZ, i, j, k + 1), sv(G, A, SZZ, i, j, k), sv(G, A, SZZ, i, j, k + 2), sv(G, A, SZZ, i, j, k - 1), rdx);
+                  + dstag(sv(G, A, SYZ, i, j, k), sv(G, A, SYZ, i, j - 1, k), sv(G, A, SYZ, i, j + 1, k), sv(G, A, SYZ, i, j - 2, k), rdy)
+                  + dstag(sv(G, A, SZZ, i, j, k + 1), sv(G, A, SZZ, i, j, k), sv(G, A, SZZ, i, j, k + 2), sv(G, A, SZZ, i, j, k - 1), rdz);
         const T u = damp(G, VZ, i, j, k) * A.a[VZ][p];
         T g = dt * d * u;
         const int t = tap_of(src, VZ, i, j, k);

@@ -27,18 +27,19 @@ __host__ __device__ constexpr int stag(int c, int axis)
 template <typename T> __host__ __device__ constexpr T c1() { return T(9.0 / 8.0); }
 template <typename T> __host__ __device__ constexpr T c2() { return T(-1.0 / 24.0); }
 
-// Staggered derivative from the two differences of Eq.(4), times 1/dx.
+// Staggered derivative from the two differences of Eq.(4), times the reciprocal spacing
+// of the derivative's axis.
 template <typename T>
-__device__ __forceinline__ T dstag(T near_hi, T near_lo, T far_hi, T far_lo, T rdx)
+__device__ __forceinline__ T dstag(T near_hi, T near_lo, T far_hi, T far_lo, T rd)
 {
-    return (c1<T>() * (near_hi - near_lo) + c2<T>() * (far_hi - far_lo)) * rdx;
+    return (c1<T>() * (near_hi - near_lo) + c2<T>() * (far_hi - far_lo)) * rd;
 }
 
 // Everything a pass needs about one grid.  Arrays are x-fastest, unpadded.
 template <typename T> struct Grid {
     int nx, ny, nz;
     long sy, sz;           // strides of y and z (nx, nx*ny)
-    T dt, rdx;             // time step and 1/dx
+    T dt, rdx, rdy, rdz;   // time step and 1/dx, 1/dy, 1/dz
     const T *lam, *mu, *rho;
     T *f[NFIELD];
     const T *g[3][2];      // damping profile per axis at integer [0] / half [1] positions

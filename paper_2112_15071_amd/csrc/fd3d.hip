@@ -103,6 +103,8 @@ int check_opts(const fd3d_opts *o)
     for (int f = 0; f < 6; ++f)
         if (o->sponge[f] < 0) return fail(FD3D_EINVAL, "opts.sponge widths must be >= 0");
     if (!std::isfinite(o->sponge_alpha)) return fail(FD3D_EINVAL, "opts.sponge_alpha must be finite");
+    if (!(o->dy >= 0.0) || !(o->dz >= 0.0) || !std::isfinite(o->dy) || !std::isfinite(o->dz))
+        return fail(FD3D_EINVAL, "opts.dy and opts.dz must be finite and >= 0 (0: dx)");
     return FD3D_OK;
 }
 
@@ -154,7 +156,7 @@ struct fd3d_ctx {
     int n[3];
     int nt;
     int tsize;
-    double dx, dt;
+    double dx, dy, dz, dt;  // spacing per axis (m), time step (s)
     fd3d_opts opts;
     const void *lam, *mu, *rho;
     char *ws;
@@ -197,6 +199,8 @@ template <typename T> Grid<T> make_grid(const fd3d_ctx *c)
     G.sz = (long)G.nx * G.ny;
     G.dt = (T)c->dt;
     G.rdx = (T)(1.0 / c->dx);
+    G.rdy = (T)(1.0 / c->dy);
+    G.rdz = (T)(1.0 / c->dz);
     G.lam = (const T *)c->lam;
     G.mu = (const T *)c->mu;
     G.rho = (const T *)c->rho;
@@ -248,14 +252,15 @@ template <typename T> int model_check(fd3d_ctx *c, hipStream_t st)
     if (!(s[2] > 0.0)) return fail(FD3D_EMODEL, "rho must be > 0 everywhere");
     if (s[3] < 0.0) return fail(FD3D_EMODEL, "mu must be >= 0 everywhere");
     if (!(s[4] > 0.0)) return fail(FD3D_EMODEL, "lambda + 2 mu must be > 0 everywhere");
-    const double bound = 6.0 / (7.0 * std::sqrt(3.0));  // 1 / (sqrt(3) (9/8 + 1/24))
+    // von Neumann bound of the O(2,4) scheme: dt vp sqrt(sum 1/h_a^2) <= 1 / (9/8 + 1/24)
+    const double inv = std::sqrt(1.0 / (c->dx * c->dx) + 1.0 / (c->dy * c->dy) + 1.0 / (c->dz * c->dz));
     c->info[0] = s[0];
     c->info[1] = s[1] < 1e299 ? s[1] : 0.0;
     c->info[2] = s[2];
-    c->info[3] = bound * c->dx / s[0];
+    c->info[3] = (6.0 / 7.0) / (s[0] * inv);
     if (c->dt > c->info[3] * (1.0 + 1e-12))
         return fail(FD3D_ECFL, "dt = " + std::to_string(c->dt) + " exceeds the stability bound " +
-                                   std::to_string(c->info[3]) + " (6/(7 sqrt 3) dx / vp_max)");
+                                   std::to_string(c->info[3]) + " ((6/7) / (vp_max sqrt(sum 1/h^2)))");
     return FD3D_OK;
 }
 
@@ -277,7 +282,7 @@ template <typename T> int build_source(fd3d_ctx *c, const fd3d_source *src, Inje
     inj.coef = (const T *)(c->ws + c->L.src);
     for (int f = 0; f < NFIELD; ++f) inj.i0[f] = inj.j0[f] = inj.k0[f] = -(1 << 28);
     if (!src) return FD3D_OK;
-    const double h3 = c->dx * c->dx * c->dx;
+    const double h3 = c->dx * c->dy * c->dz;  // cell volume
     int base[3];
     double w[8];
     bool any = false;
@@ -555,6 +560,8 @@ template <typename T> FusedArgs<T> fused_args(const fd3d_ctx *c, const Inject<T>
     A.sz = G.sz;
     A.dt = G.dt;
     A.rdx = G.rdx;
+    A.rdy = G.rdy;
+    A.rdz = G.rdz;
     A.lam = G.lam;
     A.mu = G.mu;
     A.rho = G.rho;
@@ -1450,6 +1457,8 @@ int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const v
     c->opts.max_receivers = max_rec_of(c->opts);
     c->tsize = c->opts.dtype == FD3D_F64 ? 8 : 4;
     c->dx = dx;
+    c->dy = c->opts.dy > 0.0 ? c->opts.dy : dx;
+    c->dz = c->opts.dz > 0.0 ? c->opts.dz : dx;
     c->dt = dt;
     c->lam = lam; c->mu = mu; c->rho = rho;
     c->ws = (char *)workspace;
@@ -1993,6 +2002,29 @@ int fd3d_profile(fd3d_ctx *ctx, int enable)
 {
     if (!ctx) return fail(FD3D_EINVAL, "ctx is NULL");
     ctx->prof_on = enable ? 1 : 0;
+    return FD3D_OK;
+}
+
+int fd3d_upsample(const void *coarse, int mx, int my, int mz, void *fine, int nx, int ny, int nz, int dtype,
+                  void *hip_stream)
+{
+    if (!coarse || !fine) return fail(FD3D_EINVAL, "coarse/fine is NULL");
+    if (mx < 1 || my < 1 || mz < 1 || nx < 1 || ny < 1 || nz < 1)
+        return fail(FD3D_EINVAL, "grid sizes must be >= 1");
+    if (dtype != FD3D_F32 && dtype != FD3D_F64) return fail(FD3D_EINVAL, "dtype must be FD3D_F32 or FD3D_F64");
+    const double nf = (double)nx * ny * nz, nc = (double)mx * my * mz;
+    if (nf >= 9.2e18 || nc >= 9.2e18) return fail(FD3D_EINVAL, "grid too large");
+    const int ts = dtype == FD3D_F64 ? 8 : 4;
+    const char *c0 = (const char *)coarse, *c1 = c0 + (size_t)nc * ts;
+    const char *f0 = (const char *)fine, *f1 = f0 + (size_t)nf * ts;
+    if (c0 < f1 && f0 < c1) return fail(FD3D_EINVAL, "coarse and fine overlap");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int blocks = (int)std::min<double>(8192.0, std::ceil(nf / 256.0));
+    if (dtype == FD3D_F64)
+        upsample_trilinear<double><<<blocks, 256, 0, st>>>((const double *)coarse, mx, my, mz, (double *)fine, nx, ny, nz);
+    else
+        upsample_trilinear<float><<<blocks, 256, 0, st>>>((const float *)coarse, mx, my, mz, (float *)fine, nx, ny, nz);
+    HIP_TRY(hipGetLastError());
     return FD3D_OK;
 }
 

@@ -155,7 +155,7 @@ template <typename T> struct FusedArgs {
     long fs;        // elements between consecutive fields
     int nx, ny, nz, sy;
     long sz;
-    T dt, rdx;
+    T dt, rdx, rdy, rdz;
     const T *lam, *mu, *rho;
     const T *gx[2], *gy[2], *gz[2];  // damping profiles at integer [0] / half [1] positions
     const T *wavelet;                // source time function; NULL: no source
@@ -203,7 +203,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
     const Slot hr = ring_slot<T, TX, TY, -2, TX + 3, -2, TY + 3, 448>(t, i0, j0, nx, ny, sy);
     const Slot hm = mu_slot<T, TX, TY, 640>(t, i0, j0, nx, ny, sy);
 
-    const T rdx = A.rdx, dt = A.dt;
+    const T rdx = A.rdx, rdy = A.rdy, rdz = A.rdz, dt = A.dt;
     const T s = A.wavelet ? sload(A.wavelet, A.n) : T(0);
     const T gxh = in ? A.gx[1][i] : T(0), gxi = in ? A.gx[0][i] : T(0);
     const T gyh = in ? A.gy[1][j] : T(0), gyi = in ? A.gy[0][j] : T(0);
@@ -332,8 +332,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
         T vxn, vyn, vzn;
         {
             const T d = dstag(Lxx[br + 1], Lxx[br], Lxx[br + 2], Lxx[br - 1], rdx)
-                      + dstag(Lxy[br], Lxy[br - BX], Lxy[br + BX], Lxy[br - 2 * BX], rdx)
-                      + dstag(qxz[2], qxz[1], qxz[3], qxz[0], rdx);
+                      + dstag(Lxy[br], Lxy[br - BX], Lxy[br + BX], Lxy[br - 2 * BX], rdy)
+                      + dstag(qxz[2], qxz[1], qxz[3], qxz[0], rdz);
             const T bb = buoy(r0, Lr[br + 1]);
             T v = vx0 + dt * bb * d;
             if (srcw) v += bb * coef(VX, tap(VX, p)) * s;
@@ -342,8 +342,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
         }
         {
             const T d = dstag(Lxy[br], Lxy[br - 1], Lxy[br + 1], Lxy[br - 2], rdx)
-                      + dstag(Lyy[br + BX], Lyy[br], Lyy[br + 2 * BX], Lyy[br - BX], rdx)
-                      + dstag(qyz[2], qyz[1], qyz[3], qyz[0], rdx);
+                      + dstag(Lyy[br + BX], Lyy[br], Lyy[br + 2 * BX], Lyy[br - BX], rdy)
+                      + dstag(qyz[2], qyz[1], qyz[3], qyz[0], rdz);
             const T bb = buoy(r0, Lr[br + BX]);
             T v = vy0 + dt * bb * d;
             if (srcw) v += bb * coef(VY, tap(VY, p)) * s;
@@ -352,8 +352,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
         }
         {
             const T d = dstag(Lxz[br], Lxz[br - 1], Lxz[br + 1], Lxz[br - 2], rdx)
-                      + dstag(Lyz[br], Lyz[br - BX], Lyz[br + BX], Lyz[br - 2 * BX], rdx)
-                      + dstag(qzz[3], qzz[2], qzz[4], qzz[1], rdx);
+                      + dstag(Lyz[br], Lyz[br - BX], Lyz[br + BX], Lyz[br - 2 * BX], rdy)
+                      + dstag(qzz[3], qzz[2], qzz[4], qzz[1], rdz);
             const T bb = buoy(r0, r1);
             T v = vz0 + dt * bb * d;
             if (srcw) v += bb * coef(VZ, tap(VZ, p)) * s;
@@ -375,18 +375,18 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T> &A, int i0, int j0
             const T *Vx = s_v[(it + 1) % 3][0], *Vy = s_v[(it + 1) % 3][1], *Vz = s_v[(it + 1) % 3][2];
             const T mm = M0[om];
             const T exx = dstag(Vx[er], Vx[er - 1], Vx[er + 1], Vx[er - 2], rdx);
-            const T eyy = dstag(Vy[er], Vy[er - EX], Vy[er + EX], Vy[er - 2 * EX], rdx);
+            const T eyy = dstag(Vy[er], Vy[er - EX], Vy[er + EX], Vy[er - 2 * EX], rdy);
             T ezz;
             if (FS && k == 0) ezz = -l / (l + T(2) * mm) * (exx + eyy);
-            else if (FS && k == 1) ezz = (qvz[2] - qvz[1]) * rdx;
-            else ezz = dstag(qvz[2], qvz[1], qvz[3], qvz[0], rdx);
+            else if (FS && k == 1) ezz = (qvz[2] - qvz[1]) * rdz;
+            else ezz = dstag(qvz[2], qvz[1], qvz[3], qvz[0], rdz);
             const T gn = gxi * gyi * gk_i;
-            const T exy = dstag(Vx[er + EX], Vx[er], Vx[er + 2 * EX], Vx[er - EX], rdx)
+            const T exy = dstag(Vx[er + EX], Vx[er], Vx[er + 2 * EX], Vx[er - EX], rdy)
                         + dstag(Vy[er + 1], Vy[er], Vy[er + 2], Vy[er - 1], rdx);
-            const T dzvx = (FS && k == 0) ? (qvx[2] - qvx[1]) * rdx : dstag(qvx[2], qvx[1], qvx[3], qvx[0], rdx);
+            const T dzvx = (FS && k == 0) ? (qvx[2] - qvx[1]) * rdz : dstag(qvx[2], qvx[1], qvx[3], qvx[0], rdz);
             const T exz = dzvx + dstag(Vz[er + 1], Vz[er], Vz[er + 2], Vz[er - 1], rdx);
-            const T dzvy = (FS && k == 0) ? (qvy[2] - qvy[1]) * rdx : dstag(qvy[2], qvy[1], qvy[3], qvy[0], rdx);
-            const T eyz = dzvy + dstag(Vz[er + EX], Vz[er], Vz[er + 2 * EX], Vz[er - EX], rdx);
+            const T dzvy = (FS && k == 0) ? (qvy[2] - qvy[1]) * rdz : dstag(qvy[2], qvy[1], qvy[3], qvy[0], rdz);
+            const T eyz = dzvy + dstag(Vz[er + EX], Vz[er], Vz[er + 2 * EX], Vz[er - EX], rdy);
             const T g_xy = gxh * gyh * gk_i, g_xz = gxh * gyi * gk_h, g_yz = gxi * gyh * gk_h;
             const T tr = exx + eyy + ezz;
             T nxx = dxx[0] + dt * (l * tr + T(2) * mm * exx);

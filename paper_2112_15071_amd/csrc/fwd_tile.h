@@ -252,7 +252,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     const T *fxx = G.f[SXX], *fyy = G.f[SYY], *fzz = G.f[SZZ];
     const T *fxy = G.f[SXY], *fxz = G.f[SXZ], *fyz = G.f[SYZ];
     const T *rho = G.rho;
-    const T rdx = G.rdx, dt = G.dt;
+    const T rdx = G.rdx, rdy = G.rdy, rdz = G.rdz, dt = G.dt;
     const T s = src.on ? sload(src.wavelet, n) : T(0);
     const T gxh = in ? G.g[0][1][i] : T(0), gxi = in ? G.g[0][0][i] : T(0);
     const T gyh = in ? G.g[1][1][j] : T(0), gyi = in ? G.g[1][0][j] : T(0);
@@ -356,8 +356,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const int o = own_c3 + tx + 1;
             const int ox = (ty + 2) * W3 + tx + 2;
             const T d = dstag(Lxx[o + 1], Lxx[o], Lxx[o + 2], Lxx[o - 1], rdx)
-                      + dstag(Lxy[ox], Lxy[ox - W3], Lxy[ox + W3], Lxy[ox - 2 * W3], rdx)
-                      + dstag(qxz[2], qxz[1], qxz[3], qxz[0], rdx);
+                      + dstag(Lxy[ox], Lxy[ox - W3], Lxy[ox + W3], Lxy[ox - 2 * W3], rdy)
+                      + dstag(qxz[2], qxz[1], qxz[3], qxz[0], rdz);
             if constexpr (fwd) {
                 const T bb = buoy(r0, Lr[ty * WR + tx + 1]);
                 T v = vx0 + dt * bb * d;
@@ -379,8 +379,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const int ox = (ty + 2) * W3 + tx + 2;
             const int oy = (ty + 1) * TX + tx;
             const T d = dstag(Lxy[ox], Lxy[ox - 1], Lxy[ox + 1], Lxy[ox - 2], rdx)
-                      + dstag(Lyy[oy + TX], Lyy[oy], Lyy[oy + 2 * TX], Lyy[oy - TX], rdx)
-                      + dstag(qyz[2], qyz[1], qyz[3], qyz[0], rdx);
+                      + dstag(Lyy[oy + TX], Lyy[oy], Lyy[oy + 2 * TX], Lyy[oy - TX], rdy)
+                      + dstag(qyz[2], qyz[1], qyz[3], qyz[0], rdz);
             if constexpr (fwd) {
                 const T bb = buoy(r0, Lr[(ty + 1) * WR + tx]);
                 T v = vy0 + dt * bb * d;
@@ -402,8 +402,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const int o = own_c3 + tx + 2;
             const int oy = (ty + 2) * TX + tx;
             const T d = dstag(Lxz[o], Lxz[o - 1], Lxz[o + 1], Lxz[o - 2], rdx)
-                      + dstag(Lyz[oy], Lyz[oy - TX], Lyz[oy + TX], Lyz[oy - 2 * TX], rdx)
-                      + dstag(qzz[2], qzz[1], qzz[3], qzz[0], rdx);
+                      + dstag(Lyz[oy], Lyz[oy - TX], Lyz[oy + TX], Lyz[oy - 2 * TX], rdy)
+                      + dstag(qzz[2], qzz[1], qzz[3], qzz[0], rdz);
             const unsigned st_vz = k <= nz - 2 ? oc : kOOB;
             if constexpr (fwd) {
                 const T bb = buoy(r0, r1);
@@ -478,7 +478,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
 
     const T *fvx = G.f[VX], *fvy = G.f[VY], *fvz = G.f[VZ];
     const T *mu = G.mu, *lam = G.lam;
-    const T rdx = G.rdx, dt = G.dt;
+    const T rdx = G.rdx, rdy = G.rdy, rdz = G.rdz, dt = G.dt;
     const T s = src.on ? sload(src.wavelet, n) : T(0);
     const T gxh = in ? G.g[0][1][i] : T(0), gxi = in ? G.g[0][0][i] : T(0);
     const T gyh = in ? G.g[1][1][j] : T(0), gyi = in ? G.g[1][0][j] : T(0);
@@ -603,18 +603,18 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             st(wfield(G.save[SYZ], w), oc + pw, o_yz);
         }
         const T exx = dstag(Lx[ovx], Lx[ovx - 1], Lx[ovx + 1], Lx[ovx - 2], rdx);
-        const T eyy = dstag(Ly[ovy], Ly[ovy - W3], Ly[ovy + W3], Ly[ovy - 2 * W3], rdx);
+        const T eyy = dstag(Ly[ovy], Ly[ovy - W3], Ly[ovy + W3], Ly[ovy - 2 * W3], rdy);
         T ezz;
         if (FS && k == 0) ezz = -l / (l + T(2) * mm) * (exx + eyy);
-        else if (FS && k == 1) ezz = (qvz[2] - qvz[1]) * rdx;
-        else ezz = dstag(qvz[2], qvz[1], qvz[3], qvz[0], rdx);
+        else if (FS && k == 1) ezz = (qvz[2] - qvz[1]) * rdz;
+        else ezz = dstag(qvz[2], qvz[1], qvz[3], qvz[0], rdz);
         const T gn = gxi * gyi * gz_i;
-        const T exy = dstag(Lx[ovx + W3], Lx[ovx], Lx[ovx + 2 * W3], Lx[ovx - W3], rdx)
+        const T exy = dstag(Lx[ovx + W3], Lx[ovx], Lx[ovx + 2 * W3], Lx[ovx - W3], rdy)
                     + dstag(Ly[ovy + 1], Ly[ovy], Ly[ovy + 2], Ly[ovy - 1], rdx);
-        const T dzvx = (FS && k == 0) ? (qvx[2] - qvx[1]) * rdx : dstag(qvx[2], qvx[1], qvx[3], qvx[0], rdx);
+        const T dzvx = (FS && k == 0) ? (qvx[2] - qvx[1]) * rdz : dstag(qvx[2], qvx[1], qvx[3], qvx[0], rdz);
         const T exz = dzvx + dstag(Lz[ovz + 1], Lz[ovz], Lz[ovz + 2], Lz[ovz - 1], rdx);
-        const T dzvy = (FS && k == 0) ? (qvy[2] - qvy[1]) * rdx : dstag(qvy[2], qvy[1], qvy[3], qvy[0], rdx);
-        const T eyz = dzvy + dstag(Lz[ovz + W3], Lz[ovz], Lz[ovz + 2 * W3], Lz[ovz - W3], rdx);
+        const T dzvy = (FS && k == 0) ? (qvy[2] - qvy[1]) * rdz : dstag(qvy[2], qvy[1], qvy[3], qvy[0], rdz);
+        const T eyz = dzvy + dstag(Lz[ovz + W3], Lz[ovz], Lz[ovz + 2 * W3], Lz[ovz - W3], rdy);
         const T g_xy = gxh * gyh * gz_i, g_xz = gxh * gyi * gz_h, g_yz = gxi * gyh * gz_h;
         const unsigned o_stxz = k <= nz - 2 ? st_xz : kOOB, o_styz = k <= nz - 2 ? st_yz : kOOB;
         if constexpr (fwd) {

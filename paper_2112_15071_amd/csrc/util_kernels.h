@@ -32,6 +32,43 @@ __global__ void __launch_bounds__(256) copy_masked(T *__restrict__ dst, const T 
     }
 }
 
+// Medium given on a coarse node grid c[mz][my][mx], sampled trilinearly at every node of
+// the simulation grid f[nz][ny][nx] (Sec. 2.2.1); both grids span the same box, so node i
+// sits at coarse coordinate i (m - 1) / (n - 1).  Weights and sums in double.
+__device__ __forceinline__ void coarse_axis(int i, int n, int m, int &lo, int &hi, double &t)
+{
+    const double q = n > 1 ? i * ((double)(m - 1) / (double)(n - 1)) : 0.0;
+    lo = (int)floor(q);
+    lo = lo < m - 2 ? lo : (m - 2 > 0 ? m - 2 : 0);
+    hi = lo + 1 < m - 1 ? lo + 1 : m - 1;
+    t = q - lo;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) upsample_trilinear(const T *__restrict__ c, int mx, int my, int mz,
+                                                          T *__restrict__ f, int nx, int ny, int nz)
+{
+    const long n = (long)nx * ny * nz;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(q % nx);
+        const int j = (int)((q / nx) % ny);
+        const int k = (int)(q / ((long)nx * ny));
+        int x0, x1, y0, y1, z0, z1;
+        double tx, ty, tz;
+        coarse_axis(i, nx, mx, x0, x1, tx);
+        coarse_axis(j, ny, my, y0, y1, ty);
+        coarse_axis(k, nz, mz, z0, z1, tz);
+        const int zs[2] = {z0, z1}, ys[2] = {y0, y1}, xs[2] = {x0, x1};
+        const double wz[2] = {1.0 - tz, tz}, wy[2] = {1.0 - ty, ty}, wx[2] = {1.0 - tx, tx};
+        double v = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int d = 0; d < 2; ++d)
+                    v += wz[a] * wy[b] * wx[d] * (double)c[xs[d] + (long)mx * (ys[b] + (long)my * zs[a])];
+        f[q] = (T)v;
+    }
+}
+
 __device__ __forceinline__ double dmin(double a, double b) { return a < b ? a : b; }
 __device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
 

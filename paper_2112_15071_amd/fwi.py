@@ -9,8 +9,8 @@ stay on the GPU between forward and backward.
 |d - d_obs|^2 and computes the gradient eagerly, one shot at a time through one
 gradient workspace (memory stays at one shot's checkpoints); backward scales it.
 
-A shot is a dict: src_pos, moment, force, wavelet, rec_pos.  opts: dx, dt, nt, sponge,
-sponge_alpha, ckpt_every, dtype.
+A shot is a dict: src_pos, moment, force, wavelet, rec_pos.  opts: dx (one spacing or
+(dx, dy, dz)), dt, nt, sponge, sponge_alpha, ckpt_every, dtype.
 """
 from __future__ import annotations
 

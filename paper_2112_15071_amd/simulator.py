@@ -34,7 +34,8 @@ def _stream() -> int:
 
 
 def make_opts(dtype: torch.dtype, sponge=0, sponge_alpha: float = 0.0, free_surface: bool = False,
-              check_finite: bool = False, max_receivers: int = 4096) -> _abi.fd3d_opts:
+              check_finite: bool = False, max_receivers: int = 4096, dy: float = 0.0,
+              dz: float = 0.0) -> _abi.fd3d_opts:
     o = _abi.fd3d_opts()
     o.dtype = _dtype_code(dtype)
     sp = [int(sponge)] * 6 if np.isscalar(sponge) else [int(v) for v in sponge]
@@ -46,6 +47,7 @@ def make_opts(dtype: torch.dtype, sponge=0, sponge_alpha: float = 0.0, free_surf
     o.free_surface = int(bool(free_surface))
     o.check_finite = int(bool(check_finite))
     o.max_receivers = int(max_receivers)
+    o.dy, o.dz = float(dy), float(dz)
     return o
 
 
@@ -58,6 +60,20 @@ def make_source(pos, moment=(0.0,) * 6, force=(0.0,) * 3, wavelet: Optional[torc
         s.moment[q] = float(moment[q])
     s.wavelet = int(wavelet.data_ptr()) if wavelet is not None else None
     return s
+
+
+def upsample(coarse: torch.Tensor, shape) -> torch.Tensor:
+    """A medium array given on a coarse node grid ([mz, my, mx] device tensor) sampled
+    trilinearly at the nodes of the simulation grid ``shape`` = (nx, ny, nz), both grids
+    spanning the same box (fd3d_upsample)."""
+    c = coarse.contiguous()
+    if c.dim() != 3 or not c.is_cuda:
+        raise ValueError("coarse must be a 3-D device tensor [mz, my, mx]")
+    nx, ny, nz = (int(v) for v in shape)
+    out = torch.empty((nz, ny, nx), dtype=c.dtype, device=c.device)
+    mz, my, mx = c.shape
+    _abi.fd3d_upsample(c.data_ptr(), (mx, my, mz), out.data_ptr(), (nx, ny, nz), _dtype_code(c.dtype), _stream())
+    return out
 
 
 class Simulator:
@@ -74,8 +90,11 @@ class Simulator:
             raise ValueError("lam, mu, rho must share one [nz, ny, nx] shape")
         nz, ny, nx = self.lam.shape
         self.shape = (nx, ny, nz)
-        self.dx, self.dt, self.nt = float(dx), float(dt), int(nt)
-        self.opts = make_opts(dtype, sponge, sponge_alpha, free_surface, check_finite, max_receivers)
+        # one spacing, or (dx, dy, dz) for cells of different size per axis
+        self.spacing = tuple(float(v) for v in (np.broadcast_to(np.asarray(dx, dtype=np.float64), (3,))))
+        self.dx, self.dt, self.nt = self.spacing[0], float(dt), int(nt)
+        self.opts = make_opts(dtype, sponge, sponge_alpha, free_surface, check_finite, max_receivers,
+                              self.spacing[1], self.spacing[2])
         nbytes = _abi.fd3d_workspace_bytes(nx, ny, nz, self.opts)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._ctx = _abi.fd3d_create(nx, ny, nz, self.lam.data_ptr(), self.mu.data_ptr(), self.rho.data_ptr(),

@@ -52,3 +52,17 @@ def test_host_only_calls():
     with pytest.raises(_abi.FD3DError):
         _abi.fd3d_workspace_bytes(64, 64, 64, o)
     assert "sponge" in _abi.fd3d_last_error()
+    o.sponge[2] = 0
+    o.dz = -1.0
+    with pytest.raises(_abi.FD3DError):
+        _abi.fd3d_workspace_bytes(64, 64, 64, o)
+    assert "dz" in _abi.fd3d_last_error()
+    # argument checks of the upsampler run before any device work
+    with pytest.raises(_abi.FD3DError) as e:
+        _abi.fd3d_upsample(None, (4, 4, 4), None, (8, 8, 8), _abi.FD3D_F32, None)
+    assert e.value.code == _abi.FD3D_EINVAL
+    with pytest.raises(_abi.FD3DError):
+        _abi.fd3d_upsample(256, (0, 4, 4), 1 << 20, (8, 8, 8), _abi.FD3D_F32, None)
+    with pytest.raises(_abi.FD3DError) as e:
+        _abi.fd3d_upsample(4096, (4, 4, 4), 4096 + 128, (8, 8, 8), _abi.FD3D_F32, None)
+    assert "overlap" in _abi.fd3d_last_error()
