@@ -80,6 +80,10 @@ def _load():
             ctypes.POINTER(_Cfg), dp, dp, dp, ctypes.POINTER(_Src), dp, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp,
         ]
         lib.oracle_gradient.restype = ctypes.c_int
+        lib.oracle_born.argtypes = [
+            ctypes.POINTER(_Cfg), dp, dp, dp, dp, dp, dp, ctypes.POINTER(_Src), dp, ctypes.c_int, dp, dp, dp,
+        ]
+        lib.oracle_born.restype = ctypes.c_int
         lib.oracle_profiles.argtypes = [ctypes.POINTER(_Cfg), dp]
         lib.oracle_deriv1d.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp]
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -215,6 +219,26 @@ def gradient(cfg: Config, lam, mu, rho, src: Optional[Source], wavelet, rec_pos,
     if rc:
         raise ValueError(f"oracle_gradient failed ({rc})")
     return gl, gm, gr, adj
+
+
+def born(cfg: Config, lam, mu, rho, dlam, dmu, drho, src: Optional[Source], wavelet, rec_pos):
+    """Tangent-linear (Born) forward: (traces, dtraces) [nrec,3,nt], the background traces
+    and their derivative along the model perturbation (dlam, dmu, drho).  No free surface."""
+    lib = _load()
+    zyx = cfg.zyx
+    arrs = [_f64(a, zyx) for a in (lam, mu, rho, dlam, dmu, drho)]
+    wav = None if wavelet is None else _f64(wavelet, (cfg.nt,))
+    rp = _f64(rec_pos).reshape(-1, 3)
+    nrec = rp.shape[0]
+    tr = np.zeros((nrec, 3, cfg.nt))
+    dtr = np.zeros((nrec, 3, cfg.nt))
+    c = cfg._c()
+    s = src._c() if src is not None else None
+    rc = lib.oracle_born(ctypes.byref(c), *(_ptr(a) for a in arrs), ctypes.byref(s) if s is not None else None,
+                         _ptr(wav), nrec, _ptr(rp), _ptr(tr), _ptr(dtr))
+    if rc:
+        raise ValueError(f"oracle_born failed ({rc})")
+    return tr, dtr
 
 
 def profiles(cfg: Config):

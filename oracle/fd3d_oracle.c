@@ -466,6 +466,101 @@ int oracle_forward(const oracle_cfg *cfg, const double *lam, const double *mu, c
     return 0;
 }
 
+/* ---------------- tangent-linear (Born) forward ---------------- */
+
+/*
+ * Derivative of oracle_forward's traces with respect to the node arrays lam, mu, rho
+ * along (dlam, dmu, drho), taken step by step through the same three steps (velocity
+ * pass, sampling, stress pass).  With b = 1/rho_eff and C(lam, mu) as in the forward:
+ *   velocity:  dv     <- G (dv + dt b D_S dsigma + dt db (D_S sigma + w F s / V))
+ *   sampling:  dd[n]   = W dv^{n+1/2}
+ *   stress:    dsigma <- G (dsigma + dt C E(dv) + dt dC E(v))
+ * where db = -b^2 drho_eff (drho_eff the two-node mean of drho), dC the same matrix as
+ * C built from dlam, dmu (dmu at shear points the four-node mean), and v, sigma the
+ * background at the same point of the step.  The perturbation starts at zero.  No free
+ * surface.  dtraces: [nrec][3][nt]; traces (may be NULL) receives the background.
+ */
+int oracle_born(const oracle_cfg *cfg, const double *lam, const double *mu, const double *rho,
+                const double *dlam, const double *dmu, const double *drho, const oracle_src *src,
+                const double *wavelet, int nrec, const double *rec_pos, double *traces, double *dtraces)
+{
+    if (check_cfg(cfg) || cfg->free_surface) return -1;
+    const oracle_cfg *c = cfg;
+    ctx_t x = {cfg, lam, mu, rho, {{0}}};
+    ctx_t dx = {cfg, dlam, dmu, drho, {{0}}};  /* perturbation arrays, for the same means */
+    build_profiles(&x);
+    long N = nodes(c), nx = c->n[0], ny = c->n[1], nz = c->n[2];
+    double *state = (double *)calloc((size_t)NF * N, sizeof(double));
+    double *dstate = (double *)calloc((size_t)NF * N, sizeof(double));
+    if (!state || !dstate) { free(state); free(dstate); free_profiles(&x); return -2; }
+    double *F[NF], *D[NF];
+    for (int f = 0; f < NF; ++f) { F[f] = state + (long)f * N; D[f] = dstate + (long)f * N; }
+    for (int n = 0; n < c->nt; ++n) {
+        double s = wavelet ? wavelet[n] : 0.0;
+        /* velocity: the buoyancy perturbation acting on the background stress and force */
+        for (int comp = VX; comp <= VZ; ++comp) {
+#pragma omp parallel for schedule(static)
+            for (long k = 0; k < nz; ++k)
+                for (long j = 0; j < ny; ++j)
+                    for (long i = 0; i < nx; ++i) {
+                        if (!active(c, comp, i, j, k)) continue;
+                        double b = 1.0 / rho_eff(&x, comp, i, j, k);
+                        double db = -b * b * rho_eff(&dx, comp, i, j, k);
+                        D[comp][lin(c, i, j, k)] += c->dt * db * div_sigma(c, F, comp, i, j, k);
+                    }
+            if (src && src->force[comp] != 0.0) {
+                taps_t t;
+                point_taps(comp, src->pos, &t);
+                double amp[8];
+                for (int m = 0; m < 8; ++m) {
+                    double db = 0.0;
+                    if (active(c, comp, t.i[m], t.j[m], t.k[m])) {
+                        double b = 1.0 / rho_eff(&x, comp, t.i[m], t.j[m], t.k[m]);
+                        db = -b * b * rho_eff(&dx, comp, t.i[m], t.j[m], t.k[m]);
+                    }
+                    amp[m] = c->dt * db * src->force[comp] * s / cell_volume(c);
+                }
+                inject(c, D[comp], comp, src->pos, amp);
+            }
+        }
+        velocity_pass(&x, D, NULL, 0.0); /* dv <- G (dv + ... + dt b D_S dsigma) */
+        velocity_pass(&x, F, src, s);
+        for (int r = 0; r < nrec; ++r)
+            for (int cc = 0; cc < 3; ++cc) {
+                long o = ((long)r * 3 + cc) * c->nt + n;
+                dtraces[o] = sample(c, D[VX + cc], VX + cc, rec_pos + 3 * r);
+                if (traces) traces[o] = sample(c, F[VX + cc], VX + cc, rec_pos + 3 * r);
+            }
+        /* stress: the stiffness perturbation acting on the new background velocity */
+        {
+            const double *const *V = (const double *const *)F;
+#pragma omp parallel for schedule(static)
+            for (long k = 0; k < nz; ++k)
+                for (long j = 0; j < ny; ++j)
+                    for (long i = 0; i < nx; ++i) {
+                        long p = lin(c, i, j, k);
+                        double e[3];
+                        normal_strain(&x, V, i, j, k, e);
+                        double l = node(c, dlam, i, j, k), m = node(c, dmu, i, j, k);
+                        double tr = e[0] + e[1] + e[2];
+                        D[SXX][p] += c->dt * (l * tr + 2.0 * m * e[0]);
+                        D[SYY][p] += c->dt * (l * tr + 2.0 * m * e[1]);
+                        D[SZZ][p] += c->dt * (l * tr + 2.0 * m * e[2]);
+                        for (int comp = SXY; comp <= SYZ; ++comp) {
+                            if (!active(c, comp, i, j, k)) continue;
+                            D[comp][p] += c->dt * mu_eff(&dx, comp, i, j, k) * shear_strain(&x, V, comp, i, j, k);
+                        }
+                    }
+        }
+        stress_pass(&x, D, NULL, 0.0); /* dsigma <- G (dsigma + ... + dt C E dv) */
+        stress_pass(&x, F, src, s);
+    }
+    free(state);
+    free(dstate);
+    free_profiles(&x);
+    return 0;
+}
+
 /* ---------------- discrete adjoint (store-all, small grids) ---------------- */
 
 /*
