@@ -1942,7 +1942,7 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
     static const int shapes[][3] = {{FD3D_KERNEL_TILE, 64, 4},   {FD3D_KERNEL_TILE, 64, 8},   {FD3D_KERNEL_TILE, 64, 16},
                                     {FD3D_KERNEL_TILE, 128, 4},  {FD3D_KERNEL_TILE, 128, 8},  {FD3D_KERNEL_TILE, 256, 4},
                                     {FD3D_KERNEL_FUSED, 64, 4},  {FD3D_KERNEL_FUSED, 64, 8}};
-    static const int chunks[] = {16, 32, 64, 128};
+    static const int chunks[] = {8, 16, 32, 64, 128};
     const int nt_save = ctx->nt;
     const fd3d_kernel keep = {ctx->variant, ctx->tile_x, ctx->tile_y, ctx->zchunk};
     fd3d_kernel win = keep;

@@ -194,6 +194,22 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
 // by the grid (f[] pointing at the adjoint, stored or scratch fields) and by TileIO.
 enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3 };
 
+// Sweep direction of each pass (true: upward, decreasing k), chosen so that every pass
+// starts where the pass before it ended and finds those planes still in the last-level
+// cache: forward velocity down, stress up; adjoint stress-A down, velocity-A up,
+// velocity-B down, stress-B up.  A pass that sweeps up also takes its tiles in reverse
+// order, so that when the tiles run in several rounds its first round covers the last
+// round of the pass before.
+template <int MODE> constexpr bool vel_sweeps_up() { return MODE == kAdjA; }
+template <int MODE> constexpr bool stress_sweeps_up() { return MODE == kFwd || MODE == kFwdSave || MODE == kAdjB; }
+
+// Tile of workgroup b of nwg (XCD-contiguous ranges), reversed for upward passes.
+__device__ __forceinline__ int tile_of(int b, int nwg, bool reverse)
+{
+    const int t = xcd_remap(b, nwg);
+    return reverse ? nwg - 1 - t : t;
+}
+
 template <typename T> struct TileIO {
     T *out[6];  // X (6) or Y (3) scratch
     T *acc[5];  // gradient accumulators: (gl, gm, g_mu_xy, g_mu_xz, g_mu_yz) or (g_bx, g_by, g_bz)
@@ -267,10 +283,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     auto cf = [&](int c, int t) -> T { return t >= 0 ? s_coef[(c - VX) * 8 + (t & 7)] : T(0); };
     constexpr bool fwd = MODE == kFwd || MODE == kFwdSave;
     constexpr bool use_rho = MODE != kAdjA;
-    // Sweep direction: velocity-A runs upward (decreasing k) from where the stress-A pass
-    // before it ended, so that it starts on planes still in the last-level cache; all
-    // other velocity passes run downward.
-    constexpr bool up = MODE == kAdjA;
+    constexpr bool up = vel_sweeps_up<MODE>();
     static_assert(!(up && FS), "upward velocity sweeps have no free-surface images");
     const int kfirst = up ? k1 - 1 : k0;
 
@@ -496,13 +509,10 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     constexpr bool fwd = MODE == kFwd || MODE == kFwdSave;
     constexpr bool use_model = MODE != kAdjB;
 
-    // Sweep direction.  The forward stress passes run from the bottom of the chunk up
-    // (decreasing k): the velocity pass before them ends at the bottom, so the planes read
-    // first are the ones most recently written and read, still in the last-level cache,
-    // and the next velocity pass starts at the top, where this one ends.  In the adjoint
-    // step the passes alternate the same way: stress-A down, velocity-A up, velocity-B
-    // down, stress-B up.  Same arithmetic per sample either way.
-    constexpr bool up = fwd || MODE == kAdjB;
+    // upward for the forward passes and stress-B (see stress_sweeps_up); the z queues shift
+    // the other way and the mu ring takes the new plane at the other end, with the same
+    // arithmetic per sample in both directions
+    constexpr bool up = stress_sweeps_up<MODE>();
     const int kfirst = up ? k1 - 1 : k0;
 
     const Window w = window<T>(k0, k1, nz, sz);
@@ -691,7 +701,7 @@ template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
 __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
 {
     int i0, j0, k0, k1;
-    tile_coords(tm, xcd_remap(blockIdx.x, gridDim.x), i0, j0, k0, k1, TX, TY, G.nz);
+    tile_coords(tm, tile_of(blockIdx.x, gridDim.x, vel_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
     vel_tile_body<T, TX, TY, FS, MODE>(G, src, n, i0, j0, k0, k1);
 }
 
@@ -699,7 +709,7 @@ template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
 __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
 {
     int i0, j0, k0, k1;
-    tile_coords(tm, xcd_remap(blockIdx.x, gridDim.x), i0, j0, k0, k1, TX, TY, G.nz);
+    tile_coords(tm, tile_of(blockIdx.x, gridDim.x, stress_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
     stress_tile_body<T, TX, TY, FS, MODE>(G, src, n, i0, j0, k0, k1);
 }
 
@@ -708,7 +718,7 @@ template <typename T, int TX, int TY, int MODE>
 __global__ void __launch_bounds__(TX *TY) vel_tile_adj(Grid<T> G, Inject<T> src, int n, TileMap tm, TileIO<T> io)
 {
     int i0, j0, k0, k1;
-    tile_coords(tm, xcd_remap(blockIdx.x, gridDim.x), i0, j0, k0, k1, TX, TY, G.nz);
+    tile_coords(tm, tile_of(blockIdx.x, gridDim.x, vel_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
     vel_tile_body<T, TX, TY, false, MODE>(G, src, n, i0, j0, k0, k1, io);
 }
 
@@ -716,7 +726,7 @@ template <typename T, int TX, int TY, int MODE>
 __global__ void __launch_bounds__(TX *TY) stress_tile_adj(Grid<T> G, Inject<T> src, TileMap tm, TileIO<T> io)
 {
     int i0, j0, k0, k1;
-    tile_coords(tm, xcd_remap(blockIdx.x, gridDim.x), i0, j0, k0, k1, TX, TY, G.nz);
+    tile_coords(tm, tile_of(blockIdx.x, gridDim.x, stress_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
     stress_tile_body<T, TX, TY, false, MODE>(G, src, 0, i0, j0, k0, k1, io);
 }
 
@@ -758,9 +768,10 @@ __global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__res
     static_assert(TX2 == 0 || TX2 * TY2 == TX * TY, "both tile shapes need the same workgroup size");
     __shared__ int s_base[kMaxShots];
     load_bases(s_base, &shots[0].base, base_stride<ShotFwd<T>>(), nshot);
-    int w, hi, stride;
-    work_range(total, w, hi, stride);
-    for (; w < hi; w += stride) {
+    int w0, hi, stride;
+    work_range(total, w0, hi, stride);
+    for (; w0 < hi; w0 += stride) {
+        const int w = vel_sweeps_up<MODE>() ? total - 1 - w0 : w0;
         const int s = shot_of(s_base, nshot, w);
         const ShotFwd<T> &d = shots[s];
         const Grid<T> G = d.G;
@@ -789,9 +800,10 @@ __global__ void __launch_bounds__(TX *TY) stress_tile_multi(const ShotFwd<T> *__
     static_assert(TX2 == 0 || TX2 * TY2 == TX * TY, "both tile shapes need the same workgroup size");
     __shared__ int s_base[kMaxShots];
     load_bases(s_base, &shots[0].base, base_stride<ShotFwd<T>>(), nshot);
-    int w, hi, stride;
-    work_range(total, w, hi, stride);
-    for (; w < hi; w += stride) {
+    int w0, hi, stride;
+    work_range(total, w0, hi, stride);
+    for (; w0 < hi; w0 += stride) {
+        const int w = stress_sweeps_up<MODE>() ? total - 1 - w0 : w0;
         const int s = shot_of(s_base, nshot, w);
         const ShotFwd<T> &d = shots[s];
         const Grid<T> G = d.G;
