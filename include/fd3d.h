@@ -166,6 +166,21 @@ int fd3d_gradient(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double 
                   const void *d_obs, void *traces, void *misfit, void *g_lam, void *g_mu,
                   void *g_rho, void *gws, size_t gws_bytes, int ckpt_every, void *hip_stream);
 
+/* Tangent-linear (Born) forward: the derivative of the traces along a model perturbation
+ * (dlam, dmu, drho: device node arrays T[nz][ny][nx]).  Each step differentiates the
+ * forward step (Sec. 2.1 Eq.(1)-(3) with Eq.(4)): the perturbation state takes the same
+ * velocity and stress passes as the background, fed before each pass by the
+ * perturbation's first-order effect on the background -- dt db (D_S sigma + force term)
+ * with db = -b^2 drho_eff, then dt dC E(v) with dC built from dlam, dmu (means as for C).
+ * ctx runs the background (src, traces: device T[nrec][3][nt] or NULL); dctx is a second
+ * context over the same model arrays, grid, dtype, nt, dt, spacing and damping, whose
+ * state holds the perturbation (dtraces: device T[nrec][3][nt]).  Both states start at
+ * zero and are overwritten.  Damped boundaries only; tile or cell kernels (not fused).
+ * FD3D_EINVAL when the contexts do not match. */
+int fd3d_born(fd3d_ctx *ctx, fd3d_ctx *dctx, const fd3d_source *src, const void *dlam,
+              const void *dmu, const void *drho, int nrec, const double *rec_pos, void *traces,
+              void *dtraces, void *hip_stream);
+
 /* After fd3d_adjoint: the adjoint of the initial state (v^{-1/2}, sigma^0) into fields[9]
  * (device T[nz][ny][nx], order as fd3d_get_state) -- the dot-product test quantity. */
 int fd3d_get_adjoint_state(fd3d_ctx *ctx, const void *gws, void *const fields[9],

@@ -96,6 +96,7 @@ _SIGS = {
     "fd3d_forward_ckpt": ([_vp, ctypes.POINTER(fd3d_source), _i, _dp, _vp, _i, _vp, _sz, _i, _vp], _i),
     "fd3d_adjoint": ([_vp, ctypes.POINTER(fd3d_source), _i, _dp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
     "fd3d_gradient": ([_vp, ctypes.POINTER(fd3d_source), _i, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i, _vp], _i),
+    "fd3d_born": ([_vp, _vp, ctypes.POINTER(fd3d_source), _vp, _vp, _vp, _i, _dp, _vp, _vp, _vp], _i),
     "fd3d_get_adjoint_state": ([_vp, _vp, ctypes.POINTER(_vp), _vp], _i),
     "fd3d_batch_workspace_bytes": ([_i, ctypes.POINTER(_vp), ctypes.POINTER(_sz)], _i),
     "fd3d_batch_create": ([ctypes.POINTER(_vp), _i, ctypes.POINTER(_vp), _vp, _sz], _i),
@@ -209,6 +210,10 @@ def fd3d_gradient(ctx, src, nrec, rec_pos_ptr, d_obs, traces, misfit, g_lam, g_m
                   ckpt_every, stream) -> None:
     _check(_lib.fd3d_gradient(ctx, _src(src), nrec, _dpp(rec_pos_ptr), d_obs, traces, misfit, g_lam, g_mu, g_rho,
                               gws, gws_bytes, int(ckpt_every), stream))
+
+
+def fd3d_born(ctx, dctx, src, dlam, dmu, drho, nrec, rec_pos_ptr, traces, dtraces, stream) -> None:
+    _check(_lib.fd3d_born(ctx, dctx, _src(src), dlam, dmu, drho, nrec, _dpp(rec_pos_ptr), traces, dtraces, stream))
 
 
 def fd3d_get_adjoint_state(ctx, gws, fields, stream) -> None:

@@ -19,6 +19,7 @@
 #include "fwd_tile.h"
 #include "fwd_fused.h"
 #include "adj_cell.h"
+#include "born_cell.h"
 #include "util_kernels.h"
 
 #include <unordered_set>
@@ -1414,6 +1415,45 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     return FD3D_OK;
 }
 
+// Tangent-linear (Born) forward: the background steps on c and, interleaved, the
+// perturbation's steps on dc (same grid and model) fed by the Born source kernels.
+template <typename T>
+int born_impl(fd3d_ctx *c, fd3d_ctx *dc, const fd3d_source *src, const void *dlam, const void *dmu,
+              const void *drho, int nrec, const double *rec_pos, void *traces, void *dtraces, hipStream_t st)
+{
+    Inject<T> inj, dinj;
+    int rc = stage_inputs<T>(c, src, inj, nrec, rec_pos, st);
+    if (rc) return rc;
+    rc = stage_inputs<T>(dc, nullptr, dinj, nrec, rec_pos, st);
+    if (rc) return rc;
+    zero_fields<T>(c, st);
+    zero_fields<T>(dc, st);
+    const RecTap<T> *taps = (const RecTap<T> *)(c->ws + c->L.rec);
+    const RecTap<T> *dtaps = (const RecTap<T> *)(dc->ws + dc->L.rec);
+    const dim3 blk(64, 4, 1), grd((c->n[0] + 63) / 64, (c->n[1] + 3) / 4, c->n[2]);
+    const Grid<T> G = make_grid<T>(c), D = make_grid<T>(dc);
+    BornOut<T> dv, ds;
+    for (int q = 0; q < 6; ++q) {
+        dv.f[q] = q < 3 ? D.f[VX + q] : nullptr;
+        ds.f[q] = D.f[SXX + q];
+    }
+    for (int n = 0; n < c->nt; ++n) {
+        born_vel_source<T><<<grd, blk, 0, st>>>(G, dv, (const T *)drho, inj, n);
+        launch_pass<T, false>(dc, D, dinj, n, kPassVel, st);
+        launch_pass<T, false>(c, G, inj, n, kPassVel, st);
+        if (nrec > 0) {
+            const int nb = (3 * nrec + 255) / 256;
+            if (traces) record<T><<<nb, 256, 0, st>>>(G.f[VX], G.f[VY], G.f[VZ], taps, nrec, c->nt, n, (T *)traces);
+            record<T><<<nb, 256, 0, st>>>(D.f[VX], D.f[VY], D.f[VZ], dtaps, nrec, c->nt, n, (T *)dtraces);
+        }
+        born_stress_source<T><<<grd, blk, 0, st>>>(G, ds, (const T *)dlam, (const T *)dmu);
+        launch_pass<T, false>(dc, D, dinj, n, kPassStress, st);
+        launch_pass<T, false>(c, G, inj, n, kPassStress, st);
+    }
+    HIP_TRY(hipGetLastError());
+    return FD3D_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -1613,6 +1653,34 @@ static int gradient_impl(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const 
 }
 
 } // extern "C++"
+
+int fd3d_born(fd3d_ctx *ctx, fd3d_ctx *dctx, const fd3d_source *src, const void *dlam, const void *dmu,
+              const void *drho, int nrec, const double *rec_pos, void *traces, void *dtraces, void *hip_stream)
+{
+    if (!ctx || !dctx) return fail(FD3D_EINVAL, "ctx/dctx is NULL");
+    if (ctx == dctx) return fail(FD3D_EINVAL, "the perturbation needs a context of its own");
+    if (!dlam || !dmu || !drho) return fail(FD3D_EINVAL, "model perturbation pointer is NULL");
+    if (nrec < 0 || nrec > ctx->opts.max_receivers || nrec > dctx->opts.max_receivers)
+        return fail(FD3D_EINVAL, "nrec out of range");
+    if (nrec > 0 && (!rec_pos || !dtraces)) return fail(FD3D_EINVAL, "rec_pos/dtraces is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (ctx->n[a] != dctx->n[a]) return fail(FD3D_EINVAL, "contexts differ in grid size");
+    if (ctx->tsize != dctx->tsize || ctx->nt != dctx->nt || ctx->dt != dctx->dt || ctx->dx != dctx->dx ||
+        ctx->dy != dctx->dy || ctx->dz != dctx->dz)
+        return fail(FD3D_EINVAL, "contexts differ in dtype, nt, dt or spacing");
+    if (ctx->lam != dctx->lam || ctx->mu != dctx->mu || ctx->rho != dctx->rho)
+        return fail(FD3D_EINVAL, "contexts must share the model arrays");
+    for (int f = 0; f < 6; ++f)
+        if (ctx->opts.sponge[f] != dctx->opts.sponge[f]) return fail(FD3D_EINVAL, "contexts differ in damping");
+    if (ctx->opts.sponge_alpha != dctx->opts.sponge_alpha) return fail(FD3D_EINVAL, "contexts differ in damping");
+    if (ctx->opts.free_surface || dctx->opts.free_surface)
+        return fail(FD3D_EINVAL, "the Born forward supports damped boundaries only (no free surface)");
+    if (ctx->variant == FD3D_KERNEL_FUSED || dctx->variant == FD3D_KERNEL_FUSED)
+        return fail(FD3D_EINVAL, "the Born forward runs the tile or cell kernels (set one with fd3d_set_kernel)");
+    hipStream_t st = (hipStream_t)hip_stream;
+    return ctx->tsize == 8 ? born_impl<double>(ctx, dctx, src, dlam, dmu, drho, nrec, rec_pos, traces, dtraces, st)
+                           : born_impl<float>(ctx, dctx, src, dlam, dmu, drho, nrec, rec_pos, traces, dtraces, st);
+}
 
 int fd3d_gradient(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *rec_pos, const void *d_obs,
                   void *traces, void *misfit, void *g_lam, void *g_mu, void *g_rho, void *gws, size_t gws_bytes,

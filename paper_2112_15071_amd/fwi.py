@@ -68,3 +68,35 @@ class Misfit(torch.autograd.Function):
     def backward(ctx, grad_J):
         gl, gm, gr = ctx.saved_tensors
         return grad_J * gl, grad_J * gm, grad_J * gr, None, None, None
+
+
+def descent(lam, mu, rho, shots: Sequence[Dict], d_obs: List[torch.Tensor], opts, iters: int = 3,
+            step: float = 0.02, shrink: float = 0.5, tries: int = 6):
+    """A plain FWI loop: steepest descent on J = 1/2 sum |d - d_obs|^2 over (lam, mu, rho),
+    each model array moved along its own gradient scaled so that the largest change is
+    ``step`` times the array's largest value, with backtracking (step times ``shrink``, at
+    most ``tries`` times) until J decreases.  Returns the final model and the misfit
+    history [J0, J1, ...]."""
+    model = [lam.detach().clone(), mu.detach().clone(), rho.detach().clone()]
+    m = [a.clone().requires_grad_(True) for a in model]
+    J = Misfit.apply(*m, shots, d_obs, opts)
+    J.backward()
+    hist = [float(J)]
+    for _ in range(iters):
+        g = [a.grad.detach() for a in m]
+        a = step
+        for _ in range(tries):
+            trial = [x - a * float(x.abs().max()) * gx / max(float(gx.abs().max()), 1e-300)
+                     for x, gx in zip(model, g)]
+            Jt = float(Misfit.apply(*trial, shots, d_obs, opts))
+            if Jt < hist[-1]:
+                break
+            a *= shrink
+        else:
+            break
+        model = trial
+        m = [x.clone().requires_grad_(True) for x in model]
+        J = Misfit.apply(*m, shots, d_obs, opts)
+        J.backward()
+        hist.append(float(J))
+    return model, hist

@@ -189,6 +189,35 @@ class Simulator:
         self._rec_keep = (rp, w)  # host/device inputs stay referenced until the next call
         return traces
 
+    # -- tangent-linear (Born) ----------------------------------------------------
+    def born(self, dlam, dmu, drho, src_pos=None, moment=(0.0,) * 6, force=(0.0,) * 3, wavelet=None, rec_pos=None):
+        """Tangent-linear forward (fd3d_born): returns (traces, dtraces), the background traces
+        and their derivative along the model perturbation (dlam, dmu, drho) (node arrays of
+        the model's shape).  The perturbation state lives in a second context over the same
+        model, created on first use with this one's options and kernel."""
+        if getattr(self, "_born_sim", None) is None:
+            o = self.opts
+            sp = [o.sponge[f] for f in range(6)]
+            self._born_sim = Simulator(self.lam, self.mu, self.rho, self.spacing, self.dt, self.nt, dtype=self.dtype,
+                                       sponge=sp, sponge_alpha=o.sponge_alpha, free_surface=bool(o.free_surface),
+                                       max_receivers=o.max_receivers, device=self.device)
+        d = self._born_sim
+        k = self.kernel()
+        d.set_kernel(k["variant"], k["tile_y"], k["zchunk"], k["tile_x"])
+        dm = [torch.as_tensor(a).to(device=self.device, dtype=self.dtype).contiguous() for a in (dlam, dmu, drho)]
+        for a in dm:
+            if a.shape != self.lam.shape:
+                raise ValueError("dlam, dmu, drho must have the model's shape")
+        w = self._wavelet(wavelet)
+        src = make_source(src_pos, moment, force, w) if src_pos is not None else None
+        rp, nrec = self._rec(rec_pos)
+        traces = torch.empty((nrec, 3, self.nt), dtype=self.dtype, device=self.device)
+        dtraces = torch.empty_like(traces)
+        _abi.fd3d_born(self._ctx, d._ctx, src, *(a.data_ptr() for a in dm), nrec, rp.ctypes.data if nrec else None,
+                       traces.data_ptr() if nrec else None, dtraces.data_ptr() if nrec else None, _stream())
+        self._rec_keep = (rp, w, dm)
+        return traces, dtraces
+
     # -- gradient --------------------------------------------------------------
     def grad_workspace(self, ckpt_every: int) -> torch.Tensor:
         """Device buffer for checkpoints, adjoint state and gradient accumulators."""
@@ -274,6 +303,9 @@ class Simulator:
         _abi.fd3d_set_state(self._ctx, [st[f].data_ptr() for f in range(9)], _stream())
 
     def close(self) -> None:
+        if getattr(self, "_born_sim", None) is not None:
+            self._born_sim.close()
+            self._born_sim = None
         if getattr(self, "_ctx", 0):
             torch.cuda.current_stream().synchronize()
             _abi.fd3d_destroy(self._ctx)

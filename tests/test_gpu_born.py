@@ -1,0 +1,133 @@
+"""Tangent-linear (Born) forward on the GPU: against the oracle's Born traces, the
+dot-product identity with the GPU adjoint gradient <J dm, r> = <dm, J^T r>, and a plain
+FWI loop (steepest descent) lowering the misfit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+NT, DT = 120, 1e-3
+SHAPE = (24, 22, 20)
+SPONGE, ALPHA = (5,) * 6, 0.05
+
+
+def setup(seed=808):
+    nx, ny, nz = SHAPE
+    rng = np.random.Generator(np.random.PCG64(seed))
+    vp = np.where(np.arange(nz) < nz // 2, 2500.0, 3200.0)[:, None, None] * np.ones((nz, ny, nx))
+    vp = vp * (1.0 + 0.03 * W.gaussian_field((nz, ny, nx), 30.0, 10.0, rng))
+    model = W.elastic_from_vp(vp)
+    rec = W.receiver_grid(np.linspace(7, nx - 8, 3), np.linspace(7, ny - 8, 3), 6.0)
+    dm = [a * rng.standard_normal(a.shape) * 0.1 for a in model]
+    return model, dm, rec, rng
+
+
+SOURCES = {
+    "moment": dict(src_pos=(11.3, 10.6, 9.2), moment=(1e15, -3e14, 5e14, 2e14, -1e14, 4e14), force=(0.0,) * 3,
+                   at_half=True),
+    "force": dict(src_pos=(12.7, 9.1, 10.8), moment=(0.0,) * 6, force=(3e9, -2e9, 4e9), at_half=False),
+}
+
+
+def shot_of(kind):
+    s = dict(SOURCES[kind])
+    s["wavelet"] = W.ricker(25.0, NT, DT, at_half=s.pop("at_half"))
+    return s
+
+
+def sim_for(model, dtype, h=10.0, kernel=None):
+    from paper_2112_15071_amd import Simulator
+
+    sim = Simulator(*model, h, DT, NT, dtype=dtype, sponge=SPONGE, sponge_alpha=ALPHA)
+    if kernel is not None:
+        sim.set_kernel(*kernel)
+    return sim
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-12)])
+@pytest.mark.parametrize("kind", ["moment", "force"])
+@pytest.mark.parametrize("kernel", [None, ("cell", 8, 32), ("tile", 4, 8, 64)])
+@pytest.mark.parametrize("h", [10.0, (10.0, 12.0, 8.0)])
+def test_born_matches_oracle(dtype, tol, kind, kernel, h):
+    model, dm, rec, _ = setup()
+    s = shot_of(kind)
+    cfg = oracle.Config(SHAPE, h, DT, NT, sponge=SPONGE, alpha=ALPHA)
+    osrc = oracle.Source(s["src_pos"], moment=s["moment"], force=s["force"])
+    tr_ref, dtr_ref = oracle.born(cfg, *model, *dm, osrc, s["wavelet"], rec)
+    print(f"[born] {kind} {dtype} {kernel} h={h}", flush=True)
+    sim = sim_for(model, dtype, h, kernel)
+    tr, dtr = sim.born(*dm, rec_pos=rec, **s)
+    tr, dtr = tr.double().cpu().numpy(), dtr.double().cpu().numpy()
+    for c in range(3):
+        assert rel_l2(dtr[:, c], dtr_ref[:, c]) <= tol, (c, rel_l2(dtr[:, c], dtr_ref[:, c]))
+        assert rel_l2(tr[:, c], tr_ref[:, c]) <= tol, c
+    # the background equals the plain forward run with the same kernel, bit for bit
+    fwd = sim.forward(rec_pos=rec, **s).double().cpu().numpy()
+    assert np.array_equal(fwd, tr)
+    sim.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.float64, 1e-12)])
+@pytest.mark.parametrize("kind", ["moment", "force"])
+def test_born_is_the_transpose_of_the_gpu_gradient(dtype, tol, kind):
+    model, dm, rec, rng = setup()
+    s = shot_of(kind)
+    sim = sim_for(model, dtype)
+    _, dtr = sim.born(*dm, rec_pos=rec, **s)
+    r = torch.as_tensor(rng.standard_normal(tuple(dtr.shape)), dtype=dtype, device="cuda")
+    gws = sim.grad_workspace(11)
+    sim.forward_ckpt(gws, rec_pos=rec, **s)
+    g = [torch.zeros(model[0].shape, dtype=dtype, device="cuda") for _ in range(3)]
+    sim.adjoint(gws, r, *g, rec_pos=rec, **s)
+    torch.cuda.synchronize()
+    lhs = float((dtr.double() * r.double()).sum())
+    rhs = sum(float((torch.as_tensor(d, device="cuda").double() * gp.double()).sum()) for d, gp in zip(dm, g))
+    print(f"[born dot] {kind} {dtype}: {lhs} vs {rhs}", flush=True)
+    assert abs(lhs - rhs) <= tol * abs(lhs)
+    sim.close()
+
+
+def test_born_rejects_mismatched_contexts():
+    from paper_2112_15071_amd import _abi
+
+    model, dm, rec, _ = setup()
+    a = sim_for(model, torch.float32)
+    b = sim_for(model, torch.float64)
+    dmt = [torch.as_tensor(x, dtype=torch.float32, device="cuda") for x in dm]
+    with pytest.raises(_abi.FD3DError):
+        _abi.fd3d_born(a.ctx, b.ctx, None, *(x.data_ptr() for x in dmt), 0, None, None, None, 0)
+    with pytest.raises(_abi.FD3DError):
+        _abi.fd3d_born(a.ctx, a.ctx, None, *(x.data_ptr() for x in dmt), 0, None, None, None, 0)
+    a.close()
+    b.close()
+
+
+def test_fwi_descent_lowers_the_misfit():
+    """Three steepest-descent iterations from a smoothed model towards the model that
+    made the data: the misfit falls at every iteration."""
+    from paper_2112_15071_amd import fwi
+
+    model, _, rec, _ = setup(909)
+    nz, ny, nx = model[0].shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    blob = np.exp(-((x - 12) ** 2 + (y - 11) ** 2 + (z - 10) ** 2) / 12.0)
+    vp = np.sqrt((model[0] + 2 * model[1]) / model[2]) * (1.0 - 0.05 * blob)
+    true = [torch.as_tensor(a, dtype=torch.float32, device="cuda") for a in W.elastic_from_vp(vp)]
+    start = [torch.as_tensor(a, dtype=torch.float32, device="cuda") for a in model]
+    shots = [dict(src_pos=(8.3, 9.6, 8.2), moment=W.explosion(1e15), wavelet=W.ricker(25.0, NT, DT), rec_pos=rec),
+             dict(src_pos=(15.7, 12.1, 9.8), moment=W.explosion(1e15), wavelet=W.ricker(25.0, NT, DT), rec_pos=rec)]
+    opts = dict(dx=10.0, dt=DT, nt=NT, sponge=SPONGE, sponge_alpha=ALPHA, ckpt_every=20)
+    from paper_2112_15071_amd import Simulator
+
+    obs_sim = Simulator(*true, 10.0, DT, NT, sponge=SPONGE, sponge_alpha=ALPHA)
+    d_obs = [obs_sim.forward(**s).clone() for s in shots]
+    obs_sim.close()
+    _, hist = fwi.descent(*start, shots, d_obs, opts, iters=3)
+    print(f"[fwi] misfit history {hist}", flush=True)
+    assert len(hist) == 4
+    assert all(b < a for a, b in zip(hist, hist[1:]))
