@@ -14,6 +14,7 @@ Also reported (same JSON line):
   roofline -- the dominant forward kernel's algorithmic bytes / its HIP-event duration;
   c2_forward -- the 512x512x256 free-surface workload (300 steps);
   stream_copy_gbs -- a plain 1 GiB device copy (read + write GB/s), the practical ceiling;
+  born     -- the tangent-linear (Born) forward on the 256^3 model, 300 steps;
   levels   -- the paper's Table 5 level sweep (64x64x32 .. 512^3, anisotropic cells, one
               coarse medium upsampled to every grid), 100 timed steps per level;
   cpu_baseline -- the FP64 oracle on a bounded sample on this host's cores.
@@ -252,6 +253,46 @@ def bench_batch():
                 workgroups=tune["workgroups"], cell_steps=cells_steps)
 
 
+# Born (tangent-linear) forward, per cell and step: background and perturbation passes
+# (120 each), the velocity source term (reads sigma 6, rho, drho; updates dv 3) and the
+# stress source term (reads v 3, dlam, dmu; updates dsigma 6)
+BORN_BYTES_PER_CELL_STEP = 120 + 120 + 4 * (6 + 1 + 1 + 2 * 3) + 4 * (3 + 2 + 2 * 6)
+
+
+def bench_born(K=300):
+    """Born forward on the 256^3 workload's model with a smooth 2 % perturbation of lam,
+    mu and rho, K steps (after a warm-up run of the same length)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2112_15071_amd import Simulator
+
+    dev = torch.device("cuda:0")
+    shot = W.c1(nt=K)
+    nx, ny, nz = shot.shape
+    model = [torch.as_tensor(a, dtype=torch.float32, device=dev) for a in (shot.lam, shot.mu, shot.rho)]
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    blob = np.exp(-((x - nx / 2) ** 2 + (y - ny / 2) ** 2 + (z - nz / 2) ** 2) / (2 * 20.0 ** 2))
+    dm = [m * torch.as_tensor(0.02 * blob, dtype=torch.float32, device=dev) for m in model]
+    sim = Simulator(*model, shot.h, shot.dt, K, sponge=shot.sponge, device=dev)
+    sim.autotune(steps=10)
+    args = dict(src_pos=shot.src_pos, moment=shot.moment, force=shot.force, wavelet=shot.wavelet[:K],
+                rec_pos=shot.rec_pos)
+    sim.born(*dm, **args)
+    sync()
+    t0 = time.perf_counter()
+    sim.born(*dm, **args)
+    sync()
+    el = time.perf_counter() - t0
+    cells = nx * ny * nz
+    gbs = BORN_BYTES_PER_CELL_STEP * cells * K / el / 1e9
+    log(f"[bench] born: {K} steps in {el:.3f} s -> {cells * K / el / 1e9:.2f} Gcell-steps/s, {gbs:.0f} GB/s")
+    sim.close()
+    return dict(gcs=round(cells * K / el / 1e9, 3), ms_per_step=round(el / K * 1e3, 4), steps=K,
+                bytes_per_cell_step=BORN_BYTES_PER_CELL_STEP, hbm_gbs=round(gbs, 1))
+
+
 # The paper's levels of detail (Table 5): grid (nx, ny, nz), cell size (km per axis), dt (s),
 # time steps of the full simulation.
 TABLE5 = [
@@ -464,6 +505,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-levels", action="store_true", help="skip the Table 5 level sweep")
+    ap.add_argument("--no-born", action="store_true", help="skip the Born (tangent-linear) section")
     ap.add_argument("--kernel", metavar="VARIANT,TX,TY,ZC", default=None,
                     help="forward kernel configuration (default: autotuned, cached per grid)")
     ap.add_argument("--grad-shots", type=int, default=8, help="shots of the gradient section (profiling runs: fewer)")
@@ -485,6 +527,7 @@ def main():
     batch = None if args.no_batch else bench_batch()
     grad = None if args.no_grad else bench_gradient(nshots=args.grad_shots)
     levels = None if args.no_levels else bench_levels()
+    born = None if args.no_born else bench_born()
     cpu = cpu_baseline(shot, args.cpu_steps) if args.cpu_steps > 0 else None
     nx, ny, nz = shot.shape
     out = {
@@ -527,6 +570,7 @@ def main():
         "batched_forward": batch,
         "gradient": grad,
         "levels": levels,
+        "born": born,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
