@@ -49,6 +49,7 @@ class _Cfg(ctypes.Structure):
         ("nt", ctypes.c_int),
         ("periodic", ctypes.c_int * 3),
         ("free_surface", ctypes.c_int),
+        ("vacuum_top", ctypes.c_int),
         ("sponge", ctypes.c_int * 6),
         ("alpha", ctypes.c_double),
     ]
@@ -105,6 +106,7 @@ class Config:
     alpha: float = 0.0  # <= 0: 0.3 / width per face
     free_surface: bool = False
     periodic: Sequence[bool] = (False, False, False)
+    vacuum_top: int = 0  # > 0: vacuum formulation, first solid node plane
 
     def _c(self) -> _Cfg:
         c = _Cfg()
@@ -117,6 +119,7 @@ class Config:
         c.dt = float(self.dt)
         c.nt = int(self.nt)
         c.free_surface = int(bool(self.free_surface))
+        c.vacuum_top = int(self.vacuum_top)
         sp = list(self.sponge)
         if len(sp) == 1:
             sp = sp * 6

@@ -68,6 +68,8 @@ typedef struct {
     int nt;            /* number of steps */
     int periodic[3];   /* oracle-only periodic axes */
     int free_surface;  /* stress-imaging free surface at k = 0 */
+    int vacuum_top;    /* > 0: vacuum formulation, first solid node plane (the model
+                          holds lam = mu = 0 above it); 0: off */
     int sponge[6];     /* damping width in cells: x-, x+, y-, y+, z- (top), z+ */
     double alpha;      /* Cerjan coefficient; <= 0 selects 0.3 / width per face */
 } oracle_cfg;
@@ -131,6 +133,20 @@ static double sget(const oracle_cfg *c, double *const *F, int comp, long i, long
     return get(c, F[comp], comp, i, j, k);
 }
 
+/* Vacuum formulation (Sec. 2.5): the z derivatives near the surface plane ks take the
+ * second-order difference.  Reading: every z derivative whose result lies within one cell
+ * of the surface, |z - ks| <= 1 -- half points ks - 1/2, ks + 1/2 (D+ from k = ks - 1, ks)
+ * and integer points ks - 1, ks, ks + 1 (D-). */
+static int o2_plus(const oracle_cfg *c, int axis, long k)
+{
+    return axis == 2 && c->vacuum_top > 0 && (k == c->vacuum_top - 1 || k == c->vacuum_top);
+}
+
+static int o2_minus(const oracle_cfg *c, int axis, long k)
+{
+    return axis == 2 && c->vacuum_top > 0 && k >= c->vacuum_top - 1 && k <= c->vacuum_top + 1;
+}
+
 /* Eq.(4), integer samples -> half point (slot i is position i+1/2 along the axis). */
 static double dplus_s(const oracle_cfg *c, double *const *F, int comp, int axis, long i, long j, long k)
 {
@@ -139,6 +155,7 @@ static double dplus_s(const oracle_cfg *c, double *const *F, int comp, int axis,
     double fp1 = sget(c, F, comp, i + e0, j + e1, k + e2);
     double fp2 = sget(c, F, comp, i + 2 * e0, j + 2 * e1, k + 2 * e2);
     double fm1 = sget(c, F, comp, i - e0, j - e1, k - e2);
+    if (o2_plus(c, axis, k)) return (fp1 - f0) / c->h[axis];
     return (C1 * (fp1 - f0) + C2 * (fp2 - fm1)) / c->h[axis];
 }
 
@@ -150,6 +167,7 @@ static double dminus_s(const oracle_cfg *c, double *const *F, int comp, int axis
     double gm1 = sget(c, F, comp, i - e0, j - e1, k - e2);
     double gp1 = sget(c, F, comp, i + e0, j + e1, k + e2);
     double gm2 = sget(c, F, comp, i - 2 * e0, j - 2 * e1, k - 2 * e2);
+    if (o2_minus(c, axis, k)) return (g0 - gm1) / c->h[axis];
     return (C1 * (g0 - gm1) + C2 * (gp1 - gm2)) / c->h[axis];
 }
 
@@ -161,6 +179,7 @@ static double dplus_v(const oracle_cfg *c, const double *f, int comp, int axis, 
     double fp1 = get(c, f, comp, i + e0, j + e1, k + e2);
     double fp2 = get(c, f, comp, i + 2 * e0, j + 2 * e1, k + 2 * e2);
     double fm1 = get(c, f, comp, i - e0, j - e1, k - e2);
+    if (o2_plus(c, axis, k)) return (fp1 - f0) / c->h[axis];
     return (C1 * (fp1 - f0) + C2 * (fp2 - fm1)) / c->h[axis];
 }
 
@@ -171,6 +190,7 @@ static double dminus_v(const oracle_cfg *c, const double *f, int comp, int axis,
     double gm1 = get(c, f, comp, i - e0, j - e1, k - e2);
     double gp1 = get(c, f, comp, i + e0, j + e1, k + e2);
     double gm2 = get(c, f, comp, i - 2 * e0, j - 2 * e1, k - 2 * e2);
+    if (o2_minus(c, axis, k)) return (g0 - gm1) / c->h[axis];
     return (C1 * (g0 - gm1) + C2 * (gp1 - gm2)) / c->h[axis];
 }
 
@@ -433,6 +453,8 @@ static int check_cfg(const oracle_cfg *c)
         if (c->n[a] < 2) return -1;
     if (!(c->h[0] > 0.0) || !(c->h[1] > 0.0) || !(c->h[2] > 0.0) || !(c->dt > 0.0) || c->nt < 0) return -1;
     if (c->free_surface && c->periodic[2]) return -1;
+    if (c->vacuum_top < 0 || c->vacuum_top >= c->n[2] || (c->vacuum_top > 0 && (c->free_surface || c->periodic[2])))
+        return -1;
     return 0;
 }
 
@@ -484,7 +506,7 @@ int oracle_born(const oracle_cfg *cfg, const double *lam, const double *mu, cons
                 const double *dlam, const double *dmu, const double *drho, const oracle_src *src,
                 const double *wavelet, int nrec, const double *rec_pos, double *traces, double *dtraces)
 {
-    if (check_cfg(cfg) || cfg->free_surface) return -1;
+    if (check_cfg(cfg) || cfg->free_surface || cfg->vacuum_top) return -1;
     const oracle_cfg *c = cfg;
     ctx_t x = {cfg, lam, mu, rho, {{0}}};
     ctx_t dx = {cfg, dlam, dmu, drho, {{0}}};  /* perturbation arrays, for the same means */
@@ -579,7 +601,7 @@ int oracle_gradient(const oracle_cfg *cfg, const double *lam, const double *mu, 
                     const double *residual, const double *state0, double *g_lam, double *g_mu,
                     double *g_rho, double *adj_state)
 {
-    if (check_cfg(cfg) || cfg->free_surface) return -1;
+    if (check_cfg(cfg) || cfg->free_surface || cfg->vacuum_top) return -1;
     const oracle_cfg *c = cfg;
     ctx_t x = {cfg, lam, mu, rho, {{0}}};
     build_profiles(&x);
