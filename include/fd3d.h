@@ -80,6 +80,15 @@ typedef struct fd3d_opts {
                           * divides by its own axis' spacing, point sources inject per
                           * cell volume dx dy dz, and the stability bound becomes
                           * dt <= (6/7) / (vp_max sqrt(1/dx^2 + 1/dy^2 + 1/dz^2)). */
+    int vacuum_top;      /* > 0: vacuum free surface (Sec. 2.5): the model holds low values
+                          * above the first solid node plane k = vacuum_top (typically
+                          * lam = mu = 0 and a small density, which the model check then
+                          * accepts), and every z derivative whose result lies within one
+                          * cell of that plane takes the second-order difference.  The
+                          * effective surface is half a cell above the plane.  The vacuum
+                          * density must keep the interface stable (a few per cent of the
+                          * solid's in the tests).  Excludes free_surface; forward only (no
+                          * gradient, no Born), tile and cell kernels.  0: off. */
 } fd3d_opts;
 
 typedef struct fd3d_source {

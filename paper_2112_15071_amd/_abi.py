@@ -51,6 +51,7 @@ class fd3d_opts(ctypes.Structure):
         ("max_receivers", ctypes.c_int),
         ("dy", ctypes.c_double),
         ("dz", ctypes.c_double),
+        ("vacuum_top", ctypes.c_int),
     ]
 
 

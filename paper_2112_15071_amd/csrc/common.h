@@ -45,7 +45,22 @@ template <typename T> struct Grid {
     const T *g[3][2];      // damping profile per axis at integer [0] / half [1] positions
     T *save[NFIELD];       // optional copies written by the passes (gradient recompute):
                            // the velocity pass stores v^{n+1/2}, the stress pass sigma^n
+    int ks;                // vacuum surface: first solid node plane (0: no vacuum)
 };
+
+// Vacuum surface (Sec. 2.5): z derivatives whose result lies within one cell of the first
+// solid plane ks take the second-order difference -- results at integer planes
+// ks - 1 .. ks + 1 and at half planes ks - 1/2, ks + 1/2 (k = ks - 1, ks).
+__host__ __device__ __forceinline__ bool o2_int(int ks, int k) { return ks > 0 && (unsigned)(k - ks + 1) <= 2u; }
+__host__ __device__ __forceinline__ bool o2_half(int ks, int k) { return ks > 0 && (unsigned)(k - ks + 1) <= 1u; }
+
+// z derivative of Eq.(4) from the queue q (q[1], q[2] the near pair), or its second-order
+// form next to a vacuum surface.
+template <typename T>
+__device__ __forceinline__ T dz_or_o2(bool o2, T near_hi, T near_lo, T far_hi, T far_lo, T rdz)
+{
+    return o2 ? (near_hi - near_lo) * rdz : dstag(near_hi, near_lo, far_hi, far_lo, rdz);
+}
 
 // A point source as kernel argument: per component, the base of its 2x2x2 tap box
 // on that component's subgrid, and in device memory the eight coefficients per

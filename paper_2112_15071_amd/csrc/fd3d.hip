@@ -106,6 +106,9 @@ int check_opts(const fd3d_opts *o)
     if (!std::isfinite(o->sponge_alpha)) return fail(FD3D_EINVAL, "opts.sponge_alpha must be finite");
     if (!(o->dy >= 0.0) || !(o->dz >= 0.0) || !std::isfinite(o->dy) || !std::isfinite(o->dz))
         return fail(FD3D_EINVAL, "opts.dy and opts.dz must be finite and >= 0 (0: dx)");
+    if (o->vacuum_top < 0) return fail(FD3D_EINVAL, "opts.vacuum_top must be >= 0");
+    if (o->vacuum_top > 0 && o->free_surface)
+        return fail(FD3D_EINVAL, "opts.vacuum_top and opts.free_surface exclude each other");
     return FD3D_OK;
 }
 
@@ -202,6 +205,7 @@ template <typename T> Grid<T> make_grid(const fd3d_ctx *c)
     G.rdx = (T)(1.0 / c->dx);
     G.rdy = (T)(1.0 / c->dy);
     G.rdz = (T)(1.0 / c->dz);
+    G.ks = c->opts.vacuum_top;
     G.lam = (const T *)c->lam;
     G.mu = (const T *)c->mu;
     G.rho = (const T *)c->rho;
@@ -252,7 +256,11 @@ template <typename T> int model_check(fd3d_ctx *c, hipStream_t st)
     if (s[5] != 0.0) return fail(FD3D_EMODEL, "model holds a non-finite value");
     if (!(s[2] > 0.0)) return fail(FD3D_EMODEL, "rho must be > 0 everywhere");
     if (s[3] < 0.0) return fail(FD3D_EMODEL, "mu must be >= 0 everywhere");
-    if (!(s[4] > 0.0)) return fail(FD3D_EMODEL, "lambda + 2 mu must be > 0 everywhere");
+    if (c->opts.vacuum_top > 0) {
+        if (!(s[4] >= 0.0)) return fail(FD3D_EMODEL, "lambda + 2 mu must be >= 0 everywhere");
+    } else if (!(s[4] > 0.0)) {
+        return fail(FD3D_EMODEL, "lambda + 2 mu must be > 0 everywhere");
+    }
     // von Neumann bound of the O(2,4) scheme: dt vp sqrt(sum 1/h_a^2) <= 1 / (9/8 + 1/24)
     const double inv = std::sqrt(1.0 / (c->dx * c->dx) + 1.0 / (c->dy * c->dy) + 1.0 / (c->dz * c->dz));
     c->info[0] = s[0];
@@ -543,7 +551,10 @@ void step(fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int nrec, 
 }
 
 // Fused tile shapes: FP32 64x4 and 64x8, FP64 64x4.
-bool fused_supported(const fd3d_ctx *c, int tx, int ty) { return tx == 64 && (ty == 4 || (ty == 8 && c->tsize == 4)); }
+bool fused_supported(const fd3d_ctx *c, int tx, int ty)
+{
+    return c->opts.vacuum_top == 0 && tx == 64 && (ty == 4 || (ty == 8 && c->tsize == 4));
+}
 
 // Arguments of one fused step from the current state copy into the other one.
 template <typename T> FusedArgs<T> fused_args(const fd3d_ctx *c, const Inject<T> &inj, int n)
@@ -1176,7 +1187,8 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
 
 int check_gws(const fd3d_ctx *ctx, void *gws, size_t gws_bytes, int k)
 {
-    if (ctx->opts.free_surface) return fail(FD3D_EINVAL, "the gradient supports damped boundaries only (no free surface)");
+    if (ctx->opts.free_surface || ctx->opts.vacuum_top)
+        return fail(FD3D_EINVAL, "the gradient supports damped boundaries only (no free surface)");
     if (ctx->nt < 1) return fail(FD3D_EINVAL, "gradient needs nt >= 1");
     if (k < 1 || k > ctx->nt) return fail(FD3D_EINVAL, "ckpt_every must be in [1, nt]");
     if (!gws || ((uintptr_t)gws % kAlign)) return fail(FD3D_EINVAL, "gradient workspace must be 256-byte aligned");
@@ -1483,6 +1495,7 @@ int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const v
     size_t need = 0;
     int rc = fd3d_workspace_bytes(nx, ny, nz, opts, &need);
     if (rc) return rc;
+    if (opts && opts->vacuum_top >= nz) return fail(FD3D_EINVAL, "opts.vacuum_top must be < nz");
     if (!lam || !mu || !rho) return fail(FD3D_EINVAL, "model pointer is NULL");
     if (!(dx > 0.0) || !std::isfinite(dx)) return fail(FD3D_EINVAL, "dx must be > 0");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FD3D_EINVAL, "dt must be > 0");
@@ -1673,7 +1686,7 @@ int fd3d_born(fd3d_ctx *ctx, fd3d_ctx *dctx, const fd3d_source *src, const void 
     for (int f = 0; f < 6; ++f)
         if (ctx->opts.sponge[f] != dctx->opts.sponge[f]) return fail(FD3D_EINVAL, "contexts differ in damping");
     if (ctx->opts.sponge_alpha != dctx->opts.sponge_alpha) return fail(FD3D_EINVAL, "contexts differ in damping");
-    if (ctx->opts.free_surface || dctx->opts.free_surface)
+    if (ctx->opts.free_surface || dctx->opts.free_surface || ctx->opts.vacuum_top || dctx->opts.vacuum_top)
         return fail(FD3D_EINVAL, "the Born forward supports damped boundaries only (no free surface)");
     if (ctx->variant == FD3D_KERNEL_FUSED || dctx->variant == FD3D_KERNEL_FUSED)
         return fail(FD3D_EINVAL, "the Born forward runs the tile or cell kernels (set one with fd3d_set_kernel)");

@@ -361,6 +361,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         const T nxz = zld(fxz, up ? k - 3 : k + 2, more), nyz = zld(fyz, up ? k - 3 : k + 2, more);
         const T nzz = zld(fzz, up ? k - 2 : k + 3, more), nr = zld(rho, up ? k - 1 : k + 2, more && use_rho);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
+        const bool vi = o2_int(G.ks, k), vh = o2_half(G.ks, k);  // second order next to a vacuum surface
         __syncthreads();
 
         const unsigned pw = wplane(w, k, true);
@@ -370,7 +371,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const int ox = (ty + 2) * W3 + tx + 2;
             const T d = dstag(Lxx[o + 1], Lxx[o], Lxx[o + 2], Lxx[o - 1], rdx)
                       + dstag(Lxy[ox], Lxy[ox - W3], Lxy[ox + W3], Lxy[ox - 2 * W3], rdy)
-                      + dstag(qxz[2], qxz[1], qxz[3], qxz[0], rdz);
+                      + dz_or_o2(vi, qxz[2], qxz[1], qxz[3], qxz[0], rdz);
             if constexpr (fwd) {
                 const T bb = buoy(r0, Lr[ty * WR + tx + 1]);
                 T v = vx0 + dt * bb * d;
@@ -393,7 +394,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const int oy = (ty + 1) * TX + tx;
             const T d = dstag(Lxy[ox], Lxy[ox - 1], Lxy[ox + 1], Lxy[ox - 2], rdx)
                       + dstag(Lyy[oy + TX], Lyy[oy], Lyy[oy + 2 * TX], Lyy[oy - TX], rdy)
-                      + dstag(qyz[2], qyz[1], qyz[3], qyz[0], rdz);
+                      + dz_or_o2(vi, qyz[2], qyz[1], qyz[3], qyz[0], rdz);
             if constexpr (fwd) {
                 const T bb = buoy(r0, Lr[(ty + 1) * WR + tx]);
                 T v = vy0 + dt * bb * d;
@@ -416,7 +417,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const int oy = (ty + 2) * TX + tx;
             const T d = dstag(Lxz[o], Lxz[o - 1], Lxz[o + 1], Lxz[o - 2], rdx)
                       + dstag(Lyz[oy], Lyz[oy - TX], Lyz[oy + TX], Lyz[oy - 2 * TX], rdy)
-                      + dstag(qzz[2], qzz[1], qzz[3], qzz[0], rdz);
+                      + dz_or_o2(vh, qzz[2], qzz[1], qzz[3], qzz[0], rdz);
             const unsigned st_vz = k <= nz - 2 ? oc : kOOB;
             if constexpr (fwd) {
                 const T bb = buoy(r0, r1);
@@ -601,6 +602,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         const T nm1 = up ? T(0) : zld(mu, k + 2, more && use_model);
         const T nhm = loadmu(up ? k - 1 : k + 2, more);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
+        const bool vi = o2_int(G.ks, k), vh = o2_half(G.ks, k);  // second order next to a vacuum surface
         const unsigned pw = wplane(w, k, true);
         __syncthreads();
 
@@ -617,13 +619,13 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         T ezz;
         if (FS && k == 0) ezz = -l / (l + T(2) * mm) * (exx + eyy);
         else if (FS && k == 1) ezz = (qvz[2] - qvz[1]) * rdz;
-        else ezz = dstag(qvz[2], qvz[1], qvz[3], qvz[0], rdz);
+        else ezz = dz_or_o2(vi, qvz[2], qvz[1], qvz[3], qvz[0], rdz);
         const T gn = gxi * gyi * gz_i;
         const T exy = dstag(Lx[ovx + W3], Lx[ovx], Lx[ovx + 2 * W3], Lx[ovx - W3], rdy)
                     + dstag(Ly[ovy + 1], Ly[ovy], Ly[ovy + 2], Ly[ovy - 1], rdx);
-        const T dzvx = (FS && k == 0) ? (qvx[2] - qvx[1]) * rdz : dstag(qvx[2], qvx[1], qvx[3], qvx[0], rdz);
+        const T dzvx = dz_or_o2((FS && k == 0) || vh, qvx[2], qvx[1], qvx[3], qvx[0], rdz);
         const T exz = dzvx + dstag(Lz[ovz + 1], Lz[ovz], Lz[ovz + 2], Lz[ovz - 1], rdx);
-        const T dzvy = (FS && k == 0) ? (qvy[2] - qvy[1]) * rdz : dstag(qvy[2], qvy[1], qvy[3], qvy[0], rdz);
+        const T dzvy = dz_or_o2((FS && k == 0) || vh, qvy[2], qvy[1], qvy[3], qvy[0], rdz);
         const T eyz = dzvy + dstag(Lz[ovz + W3], Lz[ovz], Lz[ovz + 2 * W3], Lz[ovz - W3], rdy);
         const T g_xy = gxh * gyh * gz_i, g_xz = gxh * gyi * gz_h, g_yz = gxi * gyh * gz_h;
         const unsigned o_stxz = k <= nz - 2 ? st_xz : kOOB, o_styz = k <= nz - 2 ? st_yz : kOOB;

@@ -35,7 +35,7 @@ def _stream() -> int:
 
 def make_opts(dtype: torch.dtype, sponge=0, sponge_alpha: float = 0.0, free_surface: bool = False,
               check_finite: bool = False, max_receivers: int = 4096, dy: float = 0.0,
-              dz: float = 0.0) -> _abi.fd3d_opts:
+              dz: float = 0.0, vacuum_top: int = 0) -> _abi.fd3d_opts:
     o = _abi.fd3d_opts()
     o.dtype = _dtype_code(dtype)
     sp = [int(sponge)] * 6 if np.isscalar(sponge) else [int(v) for v in sponge]
@@ -48,6 +48,7 @@ def make_opts(dtype: torch.dtype, sponge=0, sponge_alpha: float = 0.0, free_surf
     o.check_finite = int(bool(check_finite))
     o.max_receivers = int(max_receivers)
     o.dy, o.dz = float(dy), float(dz)
+    o.vacuum_top = int(vacuum_top)
     return o
 
 
@@ -81,7 +82,7 @@ class Simulator:
 
     def __init__(self, lam, mu, rho, dx: float, dt: float, nt: int, dtype: torch.dtype = torch.float32,
                  sponge=20, sponge_alpha: float = 0.0, free_surface: bool = False, check_finite: bool = False,
-                 max_receivers: int = 4096, device="cuda"):
+                 max_receivers: int = 4096, device="cuda", vacuum_top: int = 0):
         self.device = torch.device(device)
         self.dtype = dtype
         self.lam, self.mu, self.rho = (torch.as_tensor(a).to(device=self.device, dtype=dtype).contiguous()
@@ -94,7 +95,7 @@ class Simulator:
         self.spacing = tuple(float(v) for v in (np.broadcast_to(np.asarray(dx, dtype=np.float64), (3,))))
         self.dx, self.dt, self.nt = self.spacing[0], float(dt), int(nt)
         self.opts = make_opts(dtype, sponge, sponge_alpha, free_surface, check_finite, max_receivers,
-                              self.spacing[1], self.spacing[2])
+                              self.spacing[1], self.spacing[2], vacuum_top)
         nbytes = _abi.fd3d_workspace_bytes(nx, ny, nz, self.opts)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._ctx = _abi.fd3d_create(nx, ny, nz, self.lam.data_ptr(), self.mu.data_ptr(), self.rho.data_ptr(),

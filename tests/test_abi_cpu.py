@@ -57,6 +57,17 @@ def test_host_only_calls():
     with pytest.raises(_abi.FD3DError):
         _abi.fd3d_workspace_bytes(64, 64, 64, o)
     assert "dz" in _abi.fd3d_last_error()
+    o.dz = 0.0
+    o.vacuum_top = -1
+    with pytest.raises(_abi.FD3DError):
+        _abi.fd3d_workspace_bytes(64, 64, 64, o)
+    o.vacuum_top = 4
+    o.free_surface = 1
+    with pytest.raises(_abi.FD3DError):
+        _abi.fd3d_workspace_bytes(64, 64, 64, o)
+    assert "exclude" in _abi.fd3d_last_error()
+    o.free_surface = 0
+    assert _abi.fd3d_workspace_bytes(64, 64, 64, o) > 0
     # argument checks of the upsampler run before any device work
     with pytest.raises(_abi.FD3DError) as e:
         _abi.fd3d_upsample(None, (4, 4, 4), None, (8, 8, 8), _abi.FD3D_F32, None)
