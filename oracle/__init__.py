@@ -50,6 +50,7 @@ class _Cfg(ctypes.Structure):
         ("periodic", ctypes.c_int * 3),
         ("free_surface", ctypes.c_int),
         ("vacuum_top", ctypes.c_int),
+        ("vacuum_map", ctypes.POINTER(ctypes.c_int)),
         ("sponge", ctypes.c_int * 6),
         ("alpha", ctypes.c_double),
     ]
@@ -107,6 +108,7 @@ class Config:
     free_surface: bool = False
     periodic: Sequence[bool] = (False, False, False)
     vacuum_top: int = 0  # > 0: vacuum formulation, first solid node plane
+    vacuum_map: Optional[np.ndarray] = None  # [ny, nx] first solid plane per column (topography)
 
     def _c(self) -> _Cfg:
         c = _Cfg()
@@ -120,6 +122,13 @@ class Config:
         c.nt = int(self.nt)
         c.free_surface = int(bool(self.free_surface))
         c.vacuum_top = int(self.vacuum_top)
+        if self.vacuum_map is not None:
+            nx, ny = int(self.shape[0]), int(self.shape[1])
+            m = np.ascontiguousarray(np.asarray(self.vacuum_map, dtype=np.int32))
+            if m.shape != (ny, nx):
+                raise ValueError("vacuum_map must be [ny, nx]")
+            self._map_keep = m  # referenced by the struct for the call
+            c.vacuum_map = m.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
         sp = list(self.sponge)
         if len(sp) == 1:
             sp = sp * 6

@@ -70,6 +70,8 @@ typedef struct {
     int free_surface;  /* stress-imaging free surface at k = 0 */
     int vacuum_top;    /* > 0: vacuum formulation, first solid node plane (the model
                           holds lam = mu = 0 above it); 0: off */
+    const int *vacuum_map; /* optional [ny][nx]: first solid plane of each column
+                              (topography); NULL: vacuum_top everywhere */
     int sponge[6];     /* damping width in cells: x-, x+, y-, y+, z- (top), z+ */
     double alpha;      /* Cerjan coefficient; <= 0 selects 0.3 / width per face */
 } oracle_cfg;
@@ -137,14 +139,34 @@ static double sget(const oracle_cfg *c, double *const *F, int comp, long i, long
  * second-order difference.  Reading: every z derivative whose result lies within one cell
  * of the surface, |z - ks| <= 1 -- half points ks - 1/2, ks + 1/2 (D+ from k = ks - 1, ks)
  * and integer points ks - 1, ks, ks + 1 (D-). */
-static int o2_plus(const oracle_cfg *c, int axis, long k)
+/* Surface plane seen by a sample of component comp in column (i, j).  With topography
+ * (a plane per node column) a sample between node columns -- at a half position in x or
+ * y -- takes the deepest plane of the columns beside it (mirror-symmetric). */
+static long surface_of(const oracle_cfg *c, int comp, long i, long j)
 {
-    return axis == 2 && c->vacuum_top > 0 && (k == c->vacuum_top - 1 || k == c->vacuum_top);
+    if (!c->vacuum_map) return c->vacuum_top;
+    long ks = 0;
+    for (long a = 0; a <= STAG[comp][0]; ++a)
+        for (long b = 0; b <= STAG[comp][1]; ++b) {
+            long ii = i + a < c->n[0] ? i + a : c->n[0] - 1, jj = j + b < c->n[1] ? j + b : c->n[1] - 1;
+            long v = c->vacuum_map[ii + (long)c->n[0] * jj];
+            if (v > ks) ks = v;
+        }
+    return ks;
 }
 
-static int o2_minus(const oracle_cfg *c, int axis, long k)
+static int o2_plus(const oracle_cfg *c, int comp, int axis, long i, long j, long k)
 {
-    return axis == 2 && c->vacuum_top > 0 && k >= c->vacuum_top - 1 && k <= c->vacuum_top + 1;
+    if (axis != 2 || c->vacuum_top <= 0) return 0;
+    long ks = surface_of(c, comp, i, j);
+    return k == ks - 1 || k == ks;
+}
+
+static int o2_minus(const oracle_cfg *c, int comp, int axis, long i, long j, long k)
+{
+    if (axis != 2 || c->vacuum_top <= 0) return 0;
+    long ks = surface_of(c, comp, i, j);
+    return k >= ks - 1 && k <= ks + 1;
 }
 
 /* Eq.(4), integer samples -> half point (slot i is position i+1/2 along the axis). */
@@ -155,7 +177,7 @@ static double dplus_s(const oracle_cfg *c, double *const *F, int comp, int axis,
     double fp1 = sget(c, F, comp, i + e0, j + e1, k + e2);
     double fp2 = sget(c, F, comp, i + 2 * e0, j + 2 * e1, k + 2 * e2);
     double fm1 = sget(c, F, comp, i - e0, j - e1, k - e2);
-    if (o2_plus(c, axis, k)) return (fp1 - f0) / c->h[axis];
+    if (o2_plus(c, comp, axis, i, j, k)) return (fp1 - f0) / c->h[axis];
     return (C1 * (fp1 - f0) + C2 * (fp2 - fm1)) / c->h[axis];
 }
 
@@ -167,7 +189,7 @@ static double dminus_s(const oracle_cfg *c, double *const *F, int comp, int axis
     double gm1 = sget(c, F, comp, i - e0, j - e1, k - e2);
     double gp1 = sget(c, F, comp, i + e0, j + e1, k + e2);
     double gm2 = sget(c, F, comp, i - 2 * e0, j - 2 * e1, k - 2 * e2);
-    if (o2_minus(c, axis, k)) return (g0 - gm1) / c->h[axis];
+    if (o2_minus(c, comp, axis, i, j, k)) return (g0 - gm1) / c->h[axis];
     return (C1 * (g0 - gm1) + C2 * (gp1 - gm2)) / c->h[axis];
 }
 
@@ -179,7 +201,7 @@ static double dplus_v(const oracle_cfg *c, const double *f, int comp, int axis, 
     double fp1 = get(c, f, comp, i + e0, j + e1, k + e2);
     double fp2 = get(c, f, comp, i + 2 * e0, j + 2 * e1, k + 2 * e2);
     double fm1 = get(c, f, comp, i - e0, j - e1, k - e2);
-    if (o2_plus(c, axis, k)) return (fp1 - f0) / c->h[axis];
+    if (o2_plus(c, comp, axis, i, j, k)) return (fp1 - f0) / c->h[axis];
     return (C1 * (fp1 - f0) + C2 * (fp2 - fm1)) / c->h[axis];
 }
 
@@ -190,7 +212,7 @@ static double dminus_v(const oracle_cfg *c, const double *f, int comp, int axis,
     double gm1 = get(c, f, comp, i - e0, j - e1, k - e2);
     double gp1 = get(c, f, comp, i + e0, j + e1, k + e2);
     double gm2 = get(c, f, comp, i - 2 * e0, j - 2 * e1, k - 2 * e2);
-    if (o2_minus(c, axis, k)) return (g0 - gm1) / c->h[axis];
+    if (o2_minus(c, comp, axis, i, j, k)) return (g0 - gm1) / c->h[axis];
     return (C1 * (g0 - gm1) + C2 * (gp1 - gm2)) / c->h[axis];
 }
 
@@ -455,6 +477,11 @@ static int check_cfg(const oracle_cfg *c)
     if (c->free_surface && c->periodic[2]) return -1;
     if (c->vacuum_top < 0 || c->vacuum_top >= c->n[2] || (c->vacuum_top > 0 && (c->free_surface || c->periodic[2])))
         return -1;
+    if (c->vacuum_map) {
+        if (c->vacuum_top <= 0) return -1;
+        for (long q = 0; q < (long)c->n[0] * c->n[1]; ++q)
+            if (c->vacuum_map[q] < 1 || c->vacuum_map[q] >= c->n[2]) return -1;
+    }
     return 0;
 }
 

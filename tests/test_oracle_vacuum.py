@@ -102,3 +102,56 @@ def test_vacuum_mirror_symmetry():
     assert np.max(np.abs(vx + vx[:, :, ::-1])) <= 1e-12 * np.max(np.abs(vx))
     szz = st[5]
     assert np.max(np.abs(szz - szz[:, :, ::-1])) <= 1e-12 * np.max(np.abs(szz))
+
+
+def ridge_model(shape, depth=6, height=3):
+    """A ridge along y, symmetric about x = (nx - 1) / 2: the first solid plane rises from
+    `depth` to `depth - height` at the centre."""
+    nx, ny, nz = shape
+    x = np.arange(nx)
+    ks_col = depth - np.round(height * np.exp(-((x - (nx - 1) / 2) / 3.0) ** 2)).astype(int)
+    ks = np.broadcast_to(ks_col[None, :], (ny, nx)).astype(np.int32)
+    lam, mu, rho = W.homogeneous(shape, VP, VS, RHO)
+    z = np.arange(nz)[:, None, None]
+    vac = z < ks[None, :, :]
+    lam[vac] = 0.0
+    mu[vac] = 0.0
+    rho[vac] = RHO_VAC
+    return (lam, mu, rho), ks
+
+
+def test_flat_topography_equals_the_plane():
+    shape = (18, 16, 22)
+    lam, mu, rho = vacuum_model(shape, ks=5)
+    nt = 50
+    src = oracle.Source((8.3, 7.6, 11.4), moment=W.double_couple(0.3, 1.1, -0.7))
+    wav = W.ricker(25.0, nt, 1e-3)
+    a = oracle.forward(oracle.Config(shape, 10.0, 1e-3, nt, sponge=(4, 4, 4, 4, 0, 4), vacuum_top=5),
+                       lam, mu, rho, src, wav)[1]
+    b = oracle.forward(oracle.Config(shape, 10.0, 1e-3, nt, sponge=(4, 4, 4, 4, 0, 4), vacuum_top=5,
+                                     vacuum_map=np.full((16, 18), 5, np.int32)), lam, mu, rho, src, wav)[1]
+    assert np.array_equal(a, b)
+
+
+def test_topography_mirror_symmetry_and_stress_free_vacuum():
+    shape = (21, 14, 24)
+    (lam, mu, rho), ks = ridge_model(shape)
+    nt = 70
+    cfg = oracle.Config(shape, 10.0, 1e-3, nt, sponge=(4, 4, 4, 4, 0, 4), vacuum_top=int(ks.max()), vacuum_map=ks)
+    _, st = oracle.forward(cfg, lam, mu, rho, oracle.Source((10.0, 6.6, 12.4), moment=W.explosion(1e15)),
+                           W.ricker(25.0, nt, 1e-3))
+    assert np.all(np.isfinite(st))
+    vx = st[0][:, :, :20]
+    assert np.max(np.abs(vx + vx[:, :, ::-1])) <= 1e-12 * np.max(np.abs(vx))
+    for c in (1, 2, 3, 5):
+        f = st[c]
+        assert np.max(np.abs(f - f[:, :, ::-1])) <= 1e-12 * np.max(np.abs(f)), c
+    z = np.arange(shape[2])[:, None, None]
+    vac = z < ks[None, :, :]
+    assert np.all(st[3][vac] == 0.0) and np.all(st[4][vac] == 0.0) and np.all(st[5][vac] == 0.0)
+    # the ridge changes the wavefield against a flat surface at its foot
+    flat = oracle.Config(shape, 10.0, 1e-3, nt, sponge=(4, 4, 4, 4, 0, 4), vacuum_top=int(ks.max()))
+    (l2, m2, r2) = vacuum_model(shape, ks=int(ks.max()))
+    _, st2 = oracle.forward(flat, l2, m2, r2, oracle.Source((10.0, 6.6, 12.4), moment=W.explosion(1e15)),
+                            W.ricker(25.0, nt, 1e-3))
+    assert rel_l2(st[2], st2[2]) > 1e-3
