@@ -89,6 +89,12 @@ typedef struct fd3d_opts {
                           * density must keep the interface stable (a few per cent of the
                           * solid's in the tests).  Excludes free_surface; forward only (no
                           * gradient, no Born), tile and cell kernels.  0: off. */
+    const void *vacuum_map; /* with vacuum_top > 0, optional topography: device int32
+                          * [ny][nx], the first solid node plane of each column (1 .. nz-1,
+                          * checked at create, which copies it once to the host; the array
+                          * must stay alive and unchanged while the context is used).  A
+                          * sample between columns (half position in x or y) takes the
+                          * deepest plane beside it.  NULL: vacuum_top everywhere. */
 } fd3d_opts;
 
 typedef struct fd3d_source {

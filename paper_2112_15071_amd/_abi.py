@@ -52,6 +52,7 @@ class fd3d_opts(ctypes.Structure):
         ("dy", ctypes.c_double),
         ("dz", ctypes.c_double),
         ("vacuum_top", ctypes.c_int),
+        ("vacuum_map", ctypes.c_void_p),
     ]
 
 

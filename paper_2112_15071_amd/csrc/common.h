@@ -46,7 +46,24 @@ template <typename T> struct Grid {
     T *save[NFIELD];       // optional copies written by the passes (gradient recompute):
                            // the velocity pass stores v^{n+1/2}, the stress pass sigma^n
     int ks;                // vacuum surface: first solid node plane (0: no vacuum)
+    const int *ksmap;      // optional first solid plane per node column [ny][nx] (topography)
 };
+
+// First solid planes seen by the samples of column (i, j): at the node, and between
+// columns i, i+1 (x half positions) and rows j, j+1 (y half positions), where a sample
+// takes the deepest plane of the columns beside it.
+struct SurfacePlanes {
+    int n, x, y;
+};
+template <typename T>
+__device__ __forceinline__ SurfacePlanes surface_planes(const Grid<T> &G, int i, int j)
+{
+    if (!G.ksmap || i >= G.nx || j >= G.ny) return {G.ks, G.ks, G.ks};
+    const int a = G.ksmap[i + G.nx * j];
+    const int b = G.ksmap[(i + 1 < G.nx ? i + 1 : i) + G.nx * j];
+    const int c = G.ksmap[i + G.nx * (j + 1 < G.ny ? j + 1 : j)];
+    return {a, a > b ? a : b, a > c ? a : c};
+}
 
 // Vacuum surface (Sec. 2.5): z derivatives whose result lies within one cell of the first
 // solid plane ks take the second-order difference -- results at integer planes

@@ -109,6 +109,7 @@ int check_opts(const fd3d_opts *o)
     if (o->vacuum_top < 0) return fail(FD3D_EINVAL, "opts.vacuum_top must be >= 0");
     if (o->vacuum_top > 0 && o->free_surface)
         return fail(FD3D_EINVAL, "opts.vacuum_top and opts.free_surface exclude each other");
+    if (o->vacuum_map && o->vacuum_top <= 0) return fail(FD3D_EINVAL, "opts.vacuum_map needs opts.vacuum_top > 0");
     return FD3D_OK;
 }
 
@@ -206,6 +207,7 @@ template <typename T> Grid<T> make_grid(const fd3d_ctx *c)
     G.rdy = (T)(1.0 / c->dy);
     G.rdz = (T)(1.0 / c->dz);
     G.ks = c->opts.vacuum_top;
+    G.ksmap = (const int *)c->opts.vacuum_map;
     G.lam = (const T *)c->lam;
     G.mu = (const T *)c->mu;
     G.rho = (const T *)c->rho;
@@ -1496,6 +1498,13 @@ int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const v
     int rc = fd3d_workspace_bytes(nx, ny, nz, opts, &need);
     if (rc) return rc;
     if (opts && opts->vacuum_top >= nz) return fail(FD3D_EINVAL, "opts.vacuum_top must be < nz");
+    if (opts && opts->vacuum_map) {
+        std::vector<int> m((size_t)nx * ny);
+        if (hipMemcpy(m.data(), opts->vacuum_map, m.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(FD3D_EINVAL, "opts.vacuum_map is not readable device memory");
+        for (int v : m)
+            if (v < 1 || v >= nz) return fail(FD3D_EINVAL, "opts.vacuum_map entries must lie in [1, nz - 1]");
+    }
     if (!lam || !mu || !rho) return fail(FD3D_EINVAL, "model pointer is NULL");
     if (!(dx > 0.0) || !std::isfinite(dx)) return fail(FD3D_EINVAL, "dx must be > 0");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FD3D_EINVAL, "dt must be > 0");

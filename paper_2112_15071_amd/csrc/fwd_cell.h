@@ -41,12 +41,13 @@ __global__ void __launch_bounds__(256) vel_cell(Grid<T> G, Inject<T> src, int n)
     if (i >= G.nx || j >= G.ny) return;
     const long p = i + G.sy * j + G.sz * k;
     const T s = src.on ? src.wavelet[n] : T(0);
+    const SurfacePlanes sp = surface_planes(G, i, j);
     const T rdx = G.rdx, rdy = G.rdy, rdz = G.rdz;
 
     if (i <= G.nx - 2) {
         T d = dstag(rds<SXX, FS>(G, i + 1, j, k), rds<SXX, FS>(G, i, j, k), rds<SXX, FS>(G, i + 2, j, k), rds<SXX, FS>(G, i - 1, j, k), rdx)
             + dstag(rds<SXY, FS>(G, i, j, k), rds<SXY, FS>(G, i, j - 1, k), rds<SXY, FS>(G, i, j + 1, k), rds<SXY, FS>(G, i, j - 2, k), rdy)
-            + dz_or_o2(o2_int(G.ks, k), rds<SXZ, FS>(G, i, j, k), rds<SXZ, FS>(G, i, j, k - 1), rds<SXZ, FS>(G, i, j, k + 1), rds<SXZ, FS>(G, i, j, k - 2), rdz);
+            + dz_or_o2(o2_int(sp.x, k), rds<SXZ, FS>(G, i, j, k), rds<SXZ, FS>(G, i, j, k - 1), rds<SXZ, FS>(G, i, j, k + 1), rds<SXZ, FS>(G, i, j, k - 2), rdz);
         const T b = buoy(G.rho[p], G.rho[p + 1]);
         T v = G.f[VX][p] + G.dt * b * d;
         const int t = tap_of(src, VX, i, j, k);
@@ -58,7 +59,7 @@ __global__ void __launch_bounds__(256) vel_cell(Grid<T> G, Inject<T> src, int n)
     if (j <= G.ny - 2) {
         T d = dstag(rds<SXY, FS>(G, i, j, k), rds<SXY, FS>(G, i - 1, j, k), rds<SXY, FS>(G, i + 1, j, k), rds<SXY, FS>(G, i - 2, j, k), rdx)
             + dstag(rds<SYY, FS>(G, i, j + 1, k), rds<SYY, FS>(G, i, j, k), rds<SYY, FS>(G, i, j + 2, k), rds<SYY, FS>(G, i, j - 1, k), rdy)
-            + dz_or_o2(o2_int(G.ks, k), rds<SYZ, FS>(G, i, j, k), rds<SYZ, FS>(G, i, j, k - 1), rds<SYZ, FS>(G, i, j, k + 1), rds<SYZ, FS>(G, i, j, k - 2), rdz);
+            + dz_or_o2(o2_int(sp.y, k), rds<SYZ, FS>(G, i, j, k), rds<SYZ, FS>(G, i, j, k - 1), rds<SYZ, FS>(G, i, j, k + 1), rds<SYZ, FS>(G, i, j, k - 2), rdz);
         const T b = buoy(G.rho[p], G.rho[p + G.sy]);
         T v = G.f[VY][p] + G.dt * b * d;
         const int t = tap_of(src, VY, i, j, k);
@@ -70,7 +71,7 @@ __global__ void __launch_bounds__(256) vel_cell(Grid<T> G, Inject<T> src, int n)
     if (k <= G.nz - 2) {
         T d = dstag(rds<SXZ, FS>(G, i, j, k), rds<SXZ, FS>(G, i - 1, j, k), rds<SXZ, FS>(G, i + 1, j, k), rds<SXZ, FS>(G, i - 2, j, k), rdx)
             + dstag(rds<SYZ, FS>(G, i, j, k), rds<SYZ, FS>(G, i, j - 1, k), rds<SYZ, FS>(G, i, j + 1, k), rds<SYZ, FS>(G, i, j - 2, k), rdy)
-            + dz_or_o2(o2_half(G.ks, k), rds<SZZ, FS>(G, i, j, k + 1), rds<SZZ, FS>(G, i, j, k), rds<SZZ, FS>(G, i, j, k + 2), rds<SZZ, FS>(G, i, j, k - 1), rdz);
+            + dz_or_o2(o2_half(sp.n, k), rds<SZZ, FS>(G, i, j, k + 1), rds<SZZ, FS>(G, i, j, k), rds<SZZ, FS>(G, i, j, k + 2), rds<SZZ, FS>(G, i, j, k - 1), rdz);
         const T b = buoy(G.rho[p], G.rho[p + G.sz]);
         T v = G.f[VZ][p] + G.dt * b * d;
         const int t = tap_of(src, VZ, i, j, k);
@@ -93,6 +94,7 @@ __global__ void __launch_bounds__(256) stress_cell(Grid<T> G, Inject<T> src, int
     if (i >= G.nx || j >= G.ny) return;
     const long p = i + G.sy * j + G.sz * k;
     const T s = src.on ? src.wavelet[n] : T(0);
+    const SurfacePlanes sp = surface_planes(G, i, j);
     const T rdx = G.rdx, rdy = G.rdy, rdz = G.rdz, dt = G.dt;
 
     const T exx = dstag(rd<VX>(G, i, j, k), rd<VX>(G, i - 1, j, k), rd<VX>(G, i + 1, j, k), rd<VX>(G, i - 2, j, k), rdx);
@@ -101,7 +103,7 @@ __global__ void __launch_bounds__(256) stress_cell(Grid<T> G, Inject<T> src, int
     T ezz;
     if (FS && k == 0) ezz = -l / (l + T(2) * m) * (exx + eyy);
     else if (FS && k == 1) ezz = (rd<VZ>(G, i, j, 1) - rd<VZ>(G, i, j, 0)) * rdz;
-    else ezz = dz_or_o2(o2_int(G.ks, k), rd<VZ>(G, i, j, k), rd<VZ>(G, i, j, k - 1), rd<VZ>(G, i, j, k + 1), rd<VZ>(G, i, j, k - 2), rdz);
+    else ezz = dz_or_o2(o2_int(sp.n, k), rd<VZ>(G, i, j, k), rd<VZ>(G, i, j, k - 1), rd<VZ>(G, i, j, k + 1), rd<VZ>(G, i, j, k - 2), rdz);
     const T tr = exx + eyy + ezz;
     const T gn = G.g[0][0][i] * G.g[1][0][j] * G.g[2][0][k];
     if (G.save[SXX]) {
@@ -133,7 +135,7 @@ __global__ void __launch_bounds__(256) stress_cell(Grid<T> G, Inject<T> src, int
     }
     if (i <= G.nx - 2 && k <= G.nz - 2) {
         const T dzvx = (FS && k == 0) ? (rd<VX>(G, i, j, 1) - rd<VX>(G, i, j, 0)) * rdz
-                     : dz_or_o2(o2_half(G.ks, k), rd<VX>(G, i, j, k + 1), rd<VX>(G, i, j, k), rd<VX>(G, i, j, k + 2), rd<VX>(G, i, j, k - 1), rdz);
+                     : dz_or_o2(o2_half(sp.x, k), rd<VX>(G, i, j, k + 1), rd<VX>(G, i, j, k), rd<VX>(G, i, j, k + 2), rd<VX>(G, i, j, k - 1), rdz);
         const T e = dzvx + dstag(rd<VZ>(G, i + 1, j, k), rd<VZ>(G, i, j, k), rd<VZ>(G, i + 2, j, k), rd<VZ>(G, i - 1, j, k), rdx);
         const T mxz = ((G.mu[p] + G.mu[p + 1]) + (G.mu[p + G.sz] + G.mu[p + 1 + G.sz])) / T(4);
         T v = G.f[SXZ][p] + dt * mxz * e;
@@ -143,7 +145,7 @@ __global__ void __launch_bounds__(256) stress_cell(Grid<T> G, Inject<T> src, int
     }
     if (j <= G.ny - 2 && k <= G.nz - 2) {
         const T dzvy = (FS && k == 0) ? (rd<VY>(G, i, j, 1) - rd<VY>(G, i, j, 0)) * rdz
-                     : dz_or_o2(o2_half(G.ks, k), rd<VY>(G, i, j, k + 1), rd<VY>(G, i, j, k), rd<VY>(G, i, j, k + 2), rd<VY>(G, i, j, k - 1), rdz);
+                     : dz_or_o2(o2_half(sp.y, k), rd<VY>(G, i, j, k + 1), rd<VY>(G, i, j, k), rd<VY>(G, i, j, k + 2), rd<VY>(G, i, j, k - 1), rdz);
         const T e = dzvy + dstag(rd<VZ>(G, i, j + 1, k), rd<VZ>(G, i, j, k), rd<VZ>(G, i, j + 2, k), rd<VZ>(G, i, j - 1, k), rdy);
         const T myz = ((G.mu[p] + G.mu[p + G.sy]) + (G.mu[p + G.sz] + G.mu[p + G.sy + G.sz])) / T(4);
         T v = G.f[SYZ][p] + dt * myz * e;

@@ -250,6 +250,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     const int tx = tid % TX, ty = tid / TX;
     const int i = i0 + tx, j = j0 + ty;
     const bool in = i < nx && j < ny;
+    const SurfacePlanes sp = surface_planes(G, i, j);  // vacuum surface planes of this column
     const unsigned oc = in ? (unsigned)(i + sy * j) * (unsigned)sizeof(T) : kOOB;  // own column
 
     // halo slots (fixed over the sweep); x-halo work on the last threads, y-halo on the first
@@ -361,7 +362,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         const T nxz = zld(fxz, up ? k - 3 : k + 2, more), nyz = zld(fyz, up ? k - 3 : k + 2, more);
         const T nzz = zld(fzz, up ? k - 2 : k + 3, more), nr = zld(rho, up ? k - 1 : k + 2, more && use_rho);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
-        const bool vi = o2_int(G.ks, k), vh = o2_half(G.ks, k);  // second order next to a vacuum surface
+        // second order next to a vacuum surface: vx, vy at integer k, vz at k + 1/2
+        const bool vxo = o2_int(sp.x, k), vyo = o2_int(sp.y, k), vzo = o2_half(sp.n, k);
         __syncthreads();
 
         const unsigned pw = wplane(w, k, true);
@@ -371,7 +373,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const int ox = (ty + 2) * W3 + tx + 2;
             const T d = dstag(Lxx[o + 1], Lxx[o], Lxx[o + 2], Lxx[o - 1], rdx)
                       + dstag(Lxy[ox], Lxy[ox - W3], Lxy[ox + W3], Lxy[ox - 2 * W3], rdy)
-                      + dz_or_o2(vi, qxz[2], qxz[1], qxz[3], qxz[0], rdz);
+                      + dz_or_o2(vxo, qxz[2], qxz[1], qxz[3], qxz[0], rdz);
             if constexpr (fwd) {
                 const T bb = buoy(r0, Lr[ty * WR + tx + 1]);
                 T v = vx0 + dt * bb * d;
@@ -394,7 +396,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const int oy = (ty + 1) * TX + tx;
             const T d = dstag(Lxy[ox], Lxy[ox - 1], Lxy[ox + 1], Lxy[ox - 2], rdx)
                       + dstag(Lyy[oy + TX], Lyy[oy], Lyy[oy + 2 * TX], Lyy[oy - TX], rdy)
-                      + dz_or_o2(vi, qyz[2], qyz[1], qyz[3], qyz[0], rdz);
+                      + dz_or_o2(vyo, qyz[2], qyz[1], qyz[3], qyz[0], rdz);
             if constexpr (fwd) {
                 const T bb = buoy(r0, Lr[(ty + 1) * WR + tx]);
                 T v = vy0 + dt * bb * d;
@@ -417,7 +419,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const int oy = (ty + 2) * TX + tx;
             const T d = dstag(Lxz[o], Lxz[o - 1], Lxz[o + 1], Lxz[o - 2], rdx)
                       + dstag(Lyz[oy], Lyz[oy - TX], Lyz[oy + TX], Lyz[oy - 2 * TX], rdy)
-                      + dz_or_o2(vh, qzz[2], qzz[1], qzz[3], qzz[0], rdz);
+                      + dz_or_o2(vzo, qzz[2], qzz[1], qzz[3], qzz[0], rdz);
             const unsigned st_vz = k <= nz - 2 ? oc : kOOB;
             if constexpr (fwd) {
                 const T bb = buoy(r0, r1);
@@ -472,6 +474,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     const int tx = tid % TX, ty = tid / TX;
     const int i = i0 + tx, j = j0 + ty;
     const bool in = i < nx && j < ny;
+    const SurfacePlanes sp = surface_planes(G, i, j);  // vacuum surface planes of this column
     const unsigned oc = in ? (unsigned)(i + sy * j) * (unsigned)sizeof(T) : kOOB;
 
     const int ex = NT - 1 - tid;
@@ -602,7 +605,8 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         const T nm1 = up ? T(0) : zld(mu, k + 2, more && use_model);
         const T nhm = loadmu(up ? k - 1 : k + 2, more);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
-        const bool vi = o2_int(G.ks, k), vh = o2_half(G.ks, k);  // second order next to a vacuum surface
+        // second order next to a vacuum surface: ezz at integer k, dz vx / dz vy at k + 1/2
+        const bool vzo = o2_int(sp.n, k), vxo = o2_half(sp.x, k), vyo = o2_half(sp.y, k);
         const unsigned pw = wplane(w, k, true);
         __syncthreads();
 
@@ -619,13 +623,13 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         T ezz;
         if (FS && k == 0) ezz = -l / (l + T(2) * mm) * (exx + eyy);
         else if (FS && k == 1) ezz = (qvz[2] - qvz[1]) * rdz;
-        else ezz = dz_or_o2(vi, qvz[2], qvz[1], qvz[3], qvz[0], rdz);
+        else ezz = dz_or_o2(vzo, qvz[2], qvz[1], qvz[3], qvz[0], rdz);
         const T gn = gxi * gyi * gz_i;
         const T exy = dstag(Lx[ovx + W3], Lx[ovx], Lx[ovx + 2 * W3], Lx[ovx - W3], rdy)
                     + dstag(Ly[ovy + 1], Ly[ovy], Ly[ovy + 2], Ly[ovy - 1], rdx);
-        const T dzvx = dz_or_o2((FS && k == 0) || vh, qvx[2], qvx[1], qvx[3], qvx[0], rdz);
+        const T dzvx = dz_or_o2((FS && k == 0) || vxo, qvx[2], qvx[1], qvx[3], qvx[0], rdz);
         const T exz = dzvx + dstag(Lz[ovz + 1], Lz[ovz], Lz[ovz + 2], Lz[ovz - 1], rdx);
-        const T dzvy = dz_or_o2((FS && k == 0) || vh, qvy[2], qvy[1], qvy[3], qvy[0], rdz);
+        const T dzvy = dz_or_o2((FS && k == 0) || vyo, qvy[2], qvy[1], qvy[3], qvy[0], rdz);
         const T eyz = dzvy + dstag(Lz[ovz + W3], Lz[ovz], Lz[ovz + 2 * W3], Lz[ovz - W3], rdy);
         const T g_xy = gxh * gyh * gz_i, g_xz = gxh * gyi * gz_h, g_yz = gxi * gyh * gz_h;
         const unsigned o_stxz = k <= nz - 2 ? st_xz : kOOB, o_styz = k <= nz - 2 ? st_yz : kOOB;

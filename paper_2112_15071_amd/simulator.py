@@ -35,7 +35,7 @@ def _stream() -> int:
 
 def make_opts(dtype: torch.dtype, sponge=0, sponge_alpha: float = 0.0, free_surface: bool = False,
               check_finite: bool = False, max_receivers: int = 4096, dy: float = 0.0,
-              dz: float = 0.0, vacuum_top: int = 0) -> _abi.fd3d_opts:
+              dz: float = 0.0, vacuum_top: int = 0, vacuum_map: int = 0) -> _abi.fd3d_opts:
     o = _abi.fd3d_opts()
     o.dtype = _dtype_code(dtype)
     sp = [int(sponge)] * 6 if np.isscalar(sponge) else [int(v) for v in sponge]
@@ -49,6 +49,7 @@ def make_opts(dtype: torch.dtype, sponge=0, sponge_alpha: float = 0.0, free_surf
     o.max_receivers = int(max_receivers)
     o.dy, o.dz = float(dy), float(dz)
     o.vacuum_top = int(vacuum_top)
+    o.vacuum_map = int(vacuum_map) or None
     return o
 
 
@@ -82,7 +83,7 @@ class Simulator:
 
     def __init__(self, lam, mu, rho, dx: float, dt: float, nt: int, dtype: torch.dtype = torch.float32,
                  sponge=20, sponge_alpha: float = 0.0, free_surface: bool = False, check_finite: bool = False,
-                 max_receivers: int = 4096, device="cuda", vacuum_top: int = 0):
+                 max_receivers: int = 4096, device="cuda", vacuum_top: int = 0, vacuum_map=None):
         self.device = torch.device(device)
         self.dtype = dtype
         self.lam, self.mu, self.rho = (torch.as_tensor(a).to(device=self.device, dtype=dtype).contiguous()
@@ -94,8 +95,16 @@ class Simulator:
         # one spacing, or (dx, dy, dz) for cells of different size per axis
         self.spacing = tuple(float(v) for v in (np.broadcast_to(np.asarray(dx, dtype=np.float64), (3,))))
         self.dx, self.dt, self.nt = self.spacing[0], float(dt), int(nt)
+        # vacuum surface: one first-solid plane, or one per column ([ny, nx] integers)
+        self.vacuum_map = None
+        if vacuum_map is not None:
+            self.vacuum_map = torch.as_tensor(vacuum_map).to(device=self.device, dtype=torch.int32).contiguous()
+            if tuple(self.vacuum_map.shape) != (ny, nx):
+                raise ValueError("vacuum_map must be [ny, nx]")
+            vacuum_top = vacuum_top or int(self.vacuum_map.max())
         self.opts = make_opts(dtype, sponge, sponge_alpha, free_surface, check_finite, max_receivers,
-                              self.spacing[1], self.spacing[2], vacuum_top)
+                              self.spacing[1], self.spacing[2], vacuum_top,
+                              self.vacuum_map.data_ptr() if self.vacuum_map is not None else 0)
         nbytes = _abi.fd3d_workspace_bytes(nx, ny, nz, self.opts)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._ctx = _abi.fd3d_create(nx, ny, nz, self.lam.data_ptr(), self.mu.data_ptr(), self.rho.data_ptr(),

@@ -97,3 +97,46 @@ def test_batched_vacuum_equals_single():
     batch.close()
     for s in sims:
         s.close()
+
+
+def hill_shot(seed=43):
+    """The ragged grid with a hill: first solid plane 7 at the edges rising to 3."""
+    shot = vacuum_shot(True, 10.0, seed)
+    nx, ny, nz = shot.shape
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    ks = (7 - np.round(4 * np.exp(-(((x - 17.0) / 6.0) ** 2 + ((y - 13.0) / 5.0) ** 2)))).astype(np.int32)
+    lam, mu, rho = W.layered_perturbed(shot.shape, 10.0, seed)
+    vac = np.arange(nz)[:, None, None] < ks[None, :, :]
+    rho_vac = 0.04 * rho[~vac].min()
+    lam[vac], mu[vac], rho[vac] = 0.0, 0.0, rho_vac
+    return dataclasses.replace(shot, lam=lam, mu=mu, rho=rho), ks
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_topography_matches_oracle(dtype):
+    import oracle
+
+    shot, ks = hill_shot()
+    cfg = oracle.Config(shot.shape, shot.h, shot.dt, shot.nt, sponge=shot.sponge, vacuum_top=int(ks.max()),
+                        vacuum_map=ks)
+    ref = oracle.forward(cfg, shot.lam, shot.mu, shot.rho, oracle.Source(shot.src_pos, moment=shot.moment,
+                                                                          force=shot.force),
+                         shot.wavelet, shot.rec_pos)
+    for kern in KERNELS:
+        if kern[0] == "fused" or (dtype == torch.float64 and not fp64_ok(kern)):
+            continue
+        print(f"[topography] {dtype} {kern}", flush=True)
+        compare(gpu_run(shot, dtype, kernel=kern, vacuum_map=ks), ref, TOL[dtype], f"topography {kern}")
+
+
+def test_topography_checks():
+    from paper_2112_15071_amd import Simulator, _abi
+
+    shot, ks = hill_shot()
+    bad = ks.copy()
+    bad[3, 4] = 0
+    with pytest.raises(_abi.FD3DError):
+        Simulator(shot.lam, shot.mu, shot.rho, shot.h, shot.dt, shot.nt, sponge=shot.sponge, vacuum_map=bad)
+    bad[3, 4] = shot.shape[2]
+    with pytest.raises(_abi.FD3DError):
+        Simulator(shot.lam, shot.mu, shot.rho, shot.h, shot.dt, shot.nt, sponge=shot.sponge, vacuum_map=bad)
