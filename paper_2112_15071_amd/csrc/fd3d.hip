@@ -506,6 +506,16 @@ void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &
     constexpr int NT = TX * TY;
     if (G.save[VX] != nullptr && pass == kPassVel) pass = kPassVelSave;
     if (G.save[VX] != nullptr && pass == kPassStress) pass = kPassStressSave;
+    if constexpr (!FS) {  // the vacuum surface has instantiations of its own (forward only)
+        if (G.ks > 0 && pass == kPassVel) {
+            vel_tile<T, TX, TY, false, kFwd, true><<<nwg, NT, 0, st>>>(G, inj, n, tm);
+            return;
+        }
+        if (G.ks > 0 && pass == kPassStress) {
+            stress_tile<T, TX, TY, false, kFwd, true><<<nwg, NT, 0, st>>>(G, inj, n, tm);
+            return;
+        }
+    }
     switch (pass) {
     case kPassVel: vel_tile<T, TX, TY, FS><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
     case kPassStress: stress_tile<T, TX, TY, FS><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
@@ -895,6 +905,7 @@ template <typename T> int set_state_impl(fd3d_ctx *c, const void *const fields[9
 struct BatchGroup {
     int s0, ns, tiles, recs, wgs;
     int tx, ty, tx2, ty2;
+    int vac;  // some shot of the group has a vacuum surface
 };
 
 struct fd3d_batch {
@@ -1001,6 +1012,16 @@ int launch_multi(const BatchGroup &gr, const ShotFwd<T> *d, int n, int pass, hip
 {
     const int g = gr.wgs, S = gr.ns, W = gr.tiles;
     constexpr int NT = TX * TY;
+    if constexpr (!FS) {  // groups with a vacuum surface: the forward passes' own instantiations
+        if (gr.vac && pass == kPassVel) {
+            vel_tile_multi<T, TX, TY, TX2, TY2, false, kFwd, true><<<g, NT, 0, st>>>(d, S, W, n);
+            return FD3D_OK;
+        }
+        if (gr.vac && pass == kPassStress) {
+            stress_tile_multi<T, TX, TY, TX2, TY2, false, kFwd, true><<<g, NT, 0, st>>>(d, S, W, n);
+            return FD3D_OK;
+        }
+    }
     switch (pass) {
     case kPassVel: vel_tile_multi<T, TX, TY, TX2, TY2, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
     case kPassStress: stress_tile_multi<T, TX, TY, TX2, TY2, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
@@ -1111,7 +1132,8 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
         const int s = b->order[p];
         fd3d_ctx *c = b->ctx[s];
         BatchGroup &grp = b->groups[gi];
-        if (p == grp.s0) tiles = recs = 0;  // work items and receivers count from the group's first
+        if (p == grp.s0) tiles = recs = grp.vac = 0;  // work items and receivers count from the group's first
+        if (c->opts.vacuum_top > 0) grp.vac = 1;
         if (!window_ok(c, c->zchunk))
             return fail(FD3D_EINVAL, "shot " + std::to_string(s) + ": zchunk too large for a tile sweep");
         const int nr = nrec ? nrec[s] : 0;
@@ -1162,7 +1184,7 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
         wgs = std::min(wgs, ((g.tiles + 7) / 8) * 8);
         g.wgs = std::max(8, (wgs + 7) / 8 * 8);
         for (long v : {(long)g.s0, (long)g.ns, (long)g.tiles, (long)g.recs, (long)g.wgs, (long)g.tx, (long)g.ty,
-                       (long)g.tx2, (long)g.ty2})
+                       (long)g.tx2, (long)g.ty2, (long)g.vac})
             mix(v);
     }
     if (!use_graph) return batch_sequence<T>(b, flags, st);

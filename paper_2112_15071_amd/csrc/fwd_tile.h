@@ -227,7 +227,7 @@ __device__ __forceinline__ void stage_coef(T *lds, const Inject<T> &src, bool on
 
 // ---------------------------------------------------------------------------------
 // (V) velocity pass, tiled.  Same arithmetic per sample as vel_cell.
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false>
 __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0, int k0,
                                               int k1, const TileIO<T> &io = TileIO<T>{})
 {
@@ -250,7 +250,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     const int tx = tid % TX, ty = tid / TX;
     const int i = i0 + tx, j = j0 + ty;
     const bool in = i < nx && j < ny;
-    const SurfacePlanes sp = surface_planes(G, i, j);  // vacuum surface planes of this column
+    const SurfacePlanes sp = VAC ? surface_planes(G, i, j) : SurfacePlanes{0, 0, 0};  // vacuum planes of this column
     const unsigned oc = in ? (unsigned)(i + sy * j) * (unsigned)sizeof(T) : kOOB;  // own column
 
     // halo slots (fixed over the sweep); x-halo work on the last threads, y-halo on the first
@@ -362,8 +362,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         const T nxz = zld(fxz, up ? k - 3 : k + 2, more), nyz = zld(fyz, up ? k - 3 : k + 2, more);
         const T nzz = zld(fzz, up ? k - 2 : k + 3, more), nr = zld(rho, up ? k - 1 : k + 2, more && use_rho);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
-        // second order next to a vacuum surface: vx, vy at integer k, vz at k + 1/2
-        const bool vxo = o2_int(sp.x, k), vyo = o2_int(sp.y, k), vzo = o2_half(sp.n, k);
+        // second order next to a vacuum surface: vx, vy at integer k, vz at k + 1/2 (only in
+        // the instantiations for grids with a vacuum surface)
+        const bool vxo = VAC && o2_int(sp.x, k), vyo = VAC && o2_int(sp.y, k), vzo = VAC && o2_half(sp.n, k);
         __syncthreads();
 
         const unsigned pw = wplane(w, k, true);
@@ -454,7 +455,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 
 // ---------------------------------------------------------------------------------
 // (S) stress pass, tiled.  Same arithmetic per sample as stress_cell.
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false>
 __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0,
                                                  int k0, int k1, const TileIO<T> &io = TileIO<T>{})
 {
@@ -474,7 +475,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     const int tx = tid % TX, ty = tid / TX;
     const int i = i0 + tx, j = j0 + ty;
     const bool in = i < nx && j < ny;
-    const SurfacePlanes sp = surface_planes(G, i, j);  // vacuum surface planes of this column
+    const SurfacePlanes sp = VAC ? surface_planes(G, i, j) : SurfacePlanes{0, 0, 0};  // vacuum planes of this column
     const unsigned oc = in ? (unsigned)(i + sy * j) * (unsigned)sizeof(T) : kOOB;
 
     const int ex = NT - 1 - tid;
@@ -606,7 +607,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         const T nhm = loadmu(up ? k - 1 : k + 2, more);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         // second order next to a vacuum surface: ezz at integer k, dz vx / dz vy at k + 1/2
-        const bool vzo = o2_int(sp.n, k), vxo = o2_half(sp.x, k), vyo = o2_half(sp.y, k);
+        const bool vzo = VAC && o2_int(sp.n, k), vxo = VAC && o2_half(sp.x, k), vyo = VAC && o2_half(sp.y, k);
         const unsigned pw = wplane(w, k, true);
         __syncthreads();
 
@@ -703,20 +704,20 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
 
 // ---------------------------------------------------------------------------------
 // Single-grid launches: one workgroup per tile (MODE kFwd or kFwdSave).
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false>
 __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
 {
     int i0, j0, k0, k1;
     tile_coords(tm, tile_of(blockIdx.x, gridDim.x, vel_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
-    vel_tile_body<T, TX, TY, FS, MODE>(G, src, n, i0, j0, k0, k1);
+    vel_tile_body<T, TX, TY, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1);
 }
 
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false>
 __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
 {
     int i0, j0, k0, k1;
     tile_coords(tm, tile_of(blockIdx.x, gridDim.x, stress_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
-    stress_tile_body<T, TX, TY, FS, MODE>(G, src, n, i0, j0, k0, k1);
+    stress_tile_body<T, TX, TY, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1);
 }
 
 // Adjoint passes, one workgroup per tile (no free surface).
@@ -767,7 +768,7 @@ template <typename D> constexpr int base_stride() { return (int)(sizeof(D) / siz
 // A batch may use a second tile shape with the same workgroup size (TX2 x TY2, 0: none)
 // for the shots whose descriptor sets `alt`, so that grids of different widths all get a
 // tile shape that covers them without idle columns.
-template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd>
+template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd, bool VAC = false>
 __global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
                                                           int n)
 {
@@ -788,18 +789,18 @@ __global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__res
         if constexpr (TX2 != 0) {
             if (d.alt) {
                 tile_coords(tm, w - d.base, i0, j0, k0, k1, TX2, TY2, G.nz);
-                vel_tile_body<T, TX2, TY2, FS, MODE>(G, src, n, i0, j0, k0, k1, io);
+                vel_tile_body<T, TX2, TY2, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1, io);
                 __syncthreads();
                 continue;
             }
         }
         tile_coords(tm, w - d.base, i0, j0, k0, k1, TX, TY, G.nz);
-        vel_tile_body<T, TX, TY, FS, MODE>(G, src, n, i0, j0, k0, k1, io);
+        vel_tile_body<T, TX, TY, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1, io);
         __syncthreads();
     }
 }
 
-template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd>
+template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd, bool VAC = false>
 __global__ void __launch_bounds__(TX *TY) stress_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
                                                           int n)
 {
@@ -820,13 +821,13 @@ __global__ void __launch_bounds__(TX *TY) stress_tile_multi(const ShotFwd<T> *__
         if constexpr (TX2 != 0) {
             if (d.alt) {
                 tile_coords(tm, w - d.base, i0, j0, k0, k1, TX2, TY2, G.nz);
-                stress_tile_body<T, TX2, TY2, FS, MODE>(G, src, n, i0, j0, k0, k1, io);
+                stress_tile_body<T, TX2, TY2, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1, io);
                 __syncthreads();
                 continue;
             }
         }
         tile_coords(tm, w - d.base, i0, j0, k0, k1, TX, TY, G.nz);
-        stress_tile_body<T, TX, TY, FS, MODE>(G, src, n, i0, j0, k0, k1, io);
+        stress_tile_body<T, TX, TY, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1, io);
         __syncthreads();
     }
 }
