@@ -326,7 +326,7 @@ template <typename T> int build_source(fd3d_ctx *c, const fd3d_source *src, Inje
         for (int m = 0; m < 8; ++m) coef[(comp) * 8 + m] = (T)(-c->dt * w[m] * src->moment[q] / h3);
         any = true;
     }
-    if (any && !src->wavelet) return fail(FD3D_EINVAL, "source wavelet pointer is NULL");
+    if (any && !src->wavelet && c->nt > 0) return fail(FD3D_EINVAL, "source wavelet pointer is NULL");
     inj.on = any ? 1 : 0;
     inj.wavelet = (const T *)src->wavelet;
     return FD3D_OK;
@@ -1595,7 +1595,7 @@ int fd3d_forward(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *
     if (!ctx) return fail(FD3D_EINVAL, "ctx is NULL");
     if (nrec < 0 || nrec > ctx->opts.max_receivers)
         return fail(FD3D_EINVAL, "nrec must be in [0, max_receivers = " + std::to_string(ctx->opts.max_receivers) + "]");
-    if (nrec > 0 && (!rec_pos || !traces)) return fail(FD3D_EINVAL, "rec_pos/traces is NULL");
+    if (nrec > 0 && (!rec_pos || (!traces && ctx->nt > 0))) return fail(FD3D_EINVAL, "rec_pos/traces is NULL");
     hipStream_t st = (hipStream_t)hip_stream;
     return ctx->tsize == 8 ? forward_impl<double>(ctx, src, nrec, rec_pos, traces, flags, st)
                            : forward_impl<float>(ctx, src, nrec, rec_pos, traces, flags, st);

@@ -195,6 +195,9 @@ def test_degenerate_sizes(kern):
         assert rel_l2(st[f], rst[f]) <= 1e-4, f
     tr, st = gpu_run(tiny_shot(25, zero_wavelet=True), torch.float32, kernel=kern)
     assert not tr.any() and not st.any()
+    # no time steps at all: empty traces, zero state
+    tr, st = gpu_run(tiny_shot(1), torch.float32, nt=0, kernel=kern)
+    assert tr.shape == (2, 3, 0) and not st.any()
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
