@@ -1473,8 +1473,35 @@ int born_impl(fd3d_ctx *c, fd3d_ctx *dc, const fd3d_source *src, const void *dla
         dv.f[q] = q < 3 ? D.f[VX + q] : nullptr;
         ds.f[q] = D.f[SXX + q];
     }
+    // with the tile kernel the source terms are tile passes too (the Born modes of the
+    // bodies): on a grid that reads the background stress and density and updates the
+    // perturbation's velocity, and on one that reads the background velocity, dlam, dmu
+    // and updates the perturbation's stress
+    const bool tiled = c->variant == FD3D_KERNEL_TILE;
+    Grid<T> Gv = G, Gs = G;
+    for (int q = 0; q < 3; ++q) Gv.f[VX + q] = D.f[VX + q];
+    for (int q = 0; q < 6; ++q) Gs.f[SXX + q] = D.f[SXX + q];
+    Gs.lam = (const T *)dlam;
+    Gs.mu = (const T *)dmu;
+    TileIO<T> iov;
+    std::memset(&iov, 0, sizeof iov);
+    iov.acc[0] = (T *)drho;
+    const TileMap tm = tile_map(c);
+    const int nwg = tm.ntx * tm.nty * tm.nzc;
+    auto born_source = [&](int n, bool vel) {
+        if (!tiled) {
+            if (vel) born_vel_source<T><<<grd, blk, 0, st>>>(G, dv, (const T *)drho, inj, n);
+            else born_stress_source<T><<<grd, blk, 0, st>>>(G, ds, (const T *)dlam, (const T *)dmu);
+            return;
+        }
+        with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
+            constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
+            if (vel) vel_tile_adj<T, TX, TY, kBornV><<<nwg, TX * TY, 0, st>>>(Gv, inj, n, tm, iov);
+            else stress_tile<T, TX, TY, false, kBornS><<<nwg, TX * TY, 0, st>>>(Gs, dinj, n, tm);
+        });
+    };
     for (int n = 0; n < c->nt; ++n) {
-        born_vel_source<T><<<grd, blk, 0, st>>>(G, dv, (const T *)drho, inj, n);
+        born_source(n, true);
         launch_pass<T, false>(dc, D, dinj, n, kPassVel, st);
         launch_pass<T, false>(c, G, inj, n, kPassVel, st);
         if (nrec > 0) {
@@ -1482,7 +1509,7 @@ int born_impl(fd3d_ctx *c, fd3d_ctx *dc, const fd3d_source *src, const void *dla
             if (traces) record<T><<<nb, 256, 0, st>>>(G.f[VX], G.f[VY], G.f[VZ], taps, nrec, c->nt, n, (T *)traces);
             record<T><<<nb, 256, 0, st>>>(D.f[VX], D.f[VY], D.f[VZ], dtaps, nrec, c->nt, n, (T *)dtraces);
         }
-        born_stress_source<T><<<grd, blk, 0, st>>>(G, ds, (const T *)dlam, (const T *)dmu);
+        born_source(n, false);
         launch_pass<T, false>(dc, D, dinj, n, kPassStress, st);
         launch_pass<T, false>(c, G, inj, n, kPassStress, st);
     }

@@ -192,7 +192,13 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
 // stress-type body, kAdjA: gradients of C from E(v^{n+1/2}) and T = G_s A_s, X = C T;
 // kAdjB: A_s <- G_s A_s - dt E(Y).  The adjoint modes read and write the arrays named
 // by the grid (f[] pointing at the adjoint, stored or scratch fields) and by TileIO.
-enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3 };
+// Modes of the tile bodies: forward, adjoint A/B passes, forward that also stores the
+// state for the adjoint, and the Born (tangent-linear) source terms: kBornV adds
+// dt db (D_S sigma) + db c s to the perturbation's velocity (db = -b^2 drho_eff; sigma,
+// rho of the background, drho in io.acc[0], the perturbation's velocity in io.out);
+// kBornS is the forward stress update without damping on a grid whose velocity is the
+// background's, whose stress is the perturbation's and whose lam, mu are dlam, dmu.
+enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3, kBornV = 4, kBornS = 5 };
 
 // Sweep direction of each pass (true: upward, decreasing k), chosen so that every pass
 // starts where the pass before it ended and finds those planes still in the last-level
@@ -242,6 +248,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     __shared__ T s_yy[2][NYY + 1];
     __shared__ T s_yz[2][NYZ + 1];
     __shared__ T s_r[2][NR + 1];
+    constexpr bool born = MODE == kBornV;
+    __shared__ T s_dr[2][born ? NR + 1 : 1];  // drho plane of the Born source term
 
     const int nx = G.nx, ny = G.ny, nz = G.nz;
     const int sy = (int)G.sy;
@@ -307,10 +315,15 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         qzz[m] = (FS && kz < 0) ? -zld(fzz, -kz, true) : zld(fzz, kz, true);
     }
     T r0 = zld(rho, kfirst, use_rho), r1 = zld(rho, kfirst + 1, use_rho);
+    T dr0 = T(0), dr1 = T(0);
+    if constexpr (born) {
+        dr0 = zld(io.acc[0], kfirst, true);
+        dr1 = zld(io.acc[0], kfirst + 1, true);
+    }
 
     // plane registers, loaded one plane ahead
     struct Plane {
-        T cxx, cyy, cxy, vx, vy, vz, xx, xy, xz, yy, yz, r, g0, g1, g2;
+        T cxx, cyy, cxy, vx, vy, vz, xx, xy, xz, yy, yz, r, g0, g1, g2, dr;
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const unsigned pk = wplane(w, kk, ok), pr = wplane(w, kk, ok && use_rho), o = oc + pk;
@@ -333,6 +346,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         P.yy = ld<T>(byy, hyy.off + pk);
         P.yz = ld<T>(byz, hyz.off + pk);
         P.r = ld<T>(br, hr.off + pr);
+        if constexpr (born) P.dr = ld<T>(wfield(io.acc[0], w), hr.off + pr);
     };
     Plane P;
     loadplane(kfirst, true, P);
@@ -354,6 +368,11 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         Lyy[hyy.lds] = P.yy;
         Lyz[hyz.lds] = P.yz;
         Lr[hr.lds] = P.r;
+        T *Ldr = s_dr[b];
+        if constexpr (born) {
+            Ldr[ty * WR + tx] = dr0;
+            Ldr[hr.lds] = P.dr;
+        }
         const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
         const T ga0 = P.g0, ga1 = P.g1, ga2 = P.g2;
         // loads of the next plane of the sweep and the queue heads (skipped past the chunk)
@@ -361,6 +380,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         loadplane(up ? k - 1 : k + 1, more, P);
         const T nxz = zld(fxz, up ? k - 3 : k + 2, more), nyz = zld(fyz, up ? k - 3 : k + 2, more);
         const T nzz = zld(fzz, up ? k - 2 : k + 3, more), nr = zld(rho, up ? k - 1 : k + 2, more && use_rho);
+        const T ndr = born ? zld(io.acc[0], up ? k - 1 : k + 2, more) : T(0);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         // second order next to a vacuum surface: vx, vy at integer k, vz at k + 1/2 (only in
         // the instantiations for grids with a vacuum surface)
@@ -382,6 +402,12 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 v = v * (gxh * gyi * gz_i);
                 st(ovx, st_vx + pw, v);
                 if constexpr (MODE == kFwdSave) st(wfield(G.save[VX], w), st_vx + pw, v);
+            } else if constexpr (born) {
+                const T bb = buoy(r0, Lr[ty * WR + tx + 1]);
+                const T db = -(bb * bb) * ((dr0 + Ldr[ty * WR + tx + 1]) * T(0.5));
+                T add = dt * db * d;
+                if (srcv) add += db * cf(VX, tap_of(src, VX, i, j, k)) * s;
+                st(ovx, st_vx + pw, vx0 + add);
             } else if constexpr (MODE == kAdjA) {
                 st(ovx, st_vx + pw, (gxh * gyi * gz_i) * vx0 - dt * d);
             } else {
@@ -405,6 +431,12 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 v = v * (gxi * gyh * gz_i);
                 st(ovy, st_vy + pw, v);
                 if constexpr (MODE == kFwdSave) st(wfield(G.save[VY], w), st_vy + pw, v);
+            } else if constexpr (born) {
+                const T bb = buoy(r0, Lr[(ty + 1) * WR + tx]);
+                const T db = -(bb * bb) * ((dr0 + Ldr[(ty + 1) * WR + tx]) * T(0.5));
+                T add = dt * db * d;
+                if (srcv) add += db * cf(VY, tap_of(src, VY, i, j, k)) * s;
+                st(ovy, st_vy + pw, vy0 + add);
             } else if constexpr (MODE == kAdjA) {
                 st(ovy, st_vy + pw, (gxi * gyh * gz_i) * vy0 - dt * d);
             } else {
@@ -429,6 +461,12 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 v = v * (gxi * gyi * gz_h);
                 st(ovz, st_vz + pw, v);
                 if constexpr (MODE == kFwdSave) st(wfield(G.save[VZ], w), st_vz + pw, v);
+            } else if constexpr (born) {
+                const T bb = buoy(r0, r1);
+                const T db = -(bb * bb) * ((dr0 + dr1) * T(0.5));
+                T add = dt * db * d;
+                if (srcv) add += db * cf(VZ, tap_of(src, VZ, i, j, k)) * s;
+                st(ovz, st_vz + pw, vz0 + add);
             } else if constexpr (MODE == kAdjA) {
                 st(ovz, st_vz + pw, (gxi * gyi * gz_h) * vz0 - dt * d);
             } else {
@@ -444,11 +482,13 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             qyz[3] = qyz[2]; qyz[2] = qyz[1]; qyz[1] = qyz[0]; qyz[0] = nyz;
             qzz[3] = qzz[2]; qzz[2] = qzz[1]; qzz[1] = qzz[0]; qzz[0] = nzz;
             r1 = r0; r0 = nr;
+            dr1 = dr0; dr0 = ndr;
         } else {
             qxz[0] = qxz[1]; qxz[1] = qxz[2]; qxz[2] = qxz[3]; qxz[3] = nxz;
             qyz[0] = qyz[1]; qyz[1] = qyz[2]; qyz[2] = qyz[3]; qyz[3] = nyz;
             qzz[0] = qzz[1]; qzz[1] = qzz[2]; qzz[2] = qzz[3]; qzz[3] = nzz;
             r0 = r1; r1 = nr;
+            dr0 = dr1; dr1 = ndr;
         }
     }
 }
@@ -511,7 +551,9 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     auto cf = [&](int c, int t) -> T { return t >= 0 ? s_coef[(c - SXX) * 8 + (t & 7)] : T(0); };
     const unsigned st_xz = (in && i <= nx - 2) ? oc : kOOB;
     const unsigned st_yz = (in && j <= ny - 2) ? oc : kOOB;
-    constexpr bool fwd = MODE == kFwd || MODE == kFwdSave;
+    // kBornS runs the forward update without damping (see the mode list)
+    constexpr bool fwd = MODE == kFwd || MODE == kFwdSave || MODE == kBornS;
+    constexpr bool damp = MODE != kBornS;
     constexpr bool use_model = MODE != kAdjB;
 
     // upward for the forward passes and stress-B (see stress_sweeps_up); the z queues shift
@@ -625,14 +667,15 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         if (FS && k == 0) ezz = -l / (l + T(2) * mm) * (exx + eyy);
         else if (FS && k == 1) ezz = (qvz[2] - qvz[1]) * rdz;
         else ezz = dz_or_o2(vzo, qvz[2], qvz[1], qvz[3], qvz[0], rdz);
-        const T gn = gxi * gyi * gz_i;
+        const T gn = damp ? gxi * gyi * gz_i : T(1);
         const T exy = dstag(Lx[ovx + W3], Lx[ovx], Lx[ovx + 2 * W3], Lx[ovx - W3], rdy)
                     + dstag(Ly[ovy + 1], Ly[ovy], Ly[ovy + 2], Ly[ovy - 1], rdx);
         const T dzvx = dz_or_o2((FS && k == 0) || vxo, qvx[2], qvx[1], qvx[3], qvx[0], rdz);
         const T exz = dzvx + dstag(Lz[ovz + 1], Lz[ovz], Lz[ovz + 2], Lz[ovz - 1], rdx);
         const T dzvy = dz_or_o2((FS && k == 0) || vyo, qvy[2], qvy[1], qvy[3], qvy[0], rdz);
         const T eyz = dzvy + dstag(Lz[ovz + W3], Lz[ovz], Lz[ovz + 2 * W3], Lz[ovz - W3], rdy);
-        const T g_xy = gxh * gyh * gz_i, g_xz = gxh * gyi * gz_h, g_yz = gxi * gyh * gz_h;
+        const T g_xy = damp ? gxh * gyh * gz_i : T(1), g_xz = damp ? gxh * gyi * gz_h : T(1);
+        const T g_yz = damp ? gxi * gyh * gz_h : T(1);
         const unsigned o_stxz = k <= nz - 2 ? st_xz : kOOB, o_styz = k <= nz - 2 ? st_yz : kOOB;
         if constexpr (fwd) {
             const T tr = exx + eyy + ezz;
