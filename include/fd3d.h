@@ -245,7 +245,7 @@ int fd3d_batch_set_schedule(fd3d_batch *b, size_t group_bytes);
 /* Times `steps` batched steps (sources and receivers off, one warm-up run each) for
  * every supported tile shape and pair of shapes in lockstep, with the persistent grid
  * and with one workgroup per tile, then the cache-blocked schedule with group budgets of
- * 128 and 256 MiB; keeps the fastest for later batch calls and writes it to best =
+ * 96, 128, 192, 256 and 384 MiB; keeps the fastest for later batch calls and writes it to best =
  * {tile_x, tile_y, tile2_x, tile2_y, workgroups (0 = persistent), group MiB (0 =
  * lockstep)} and its ms per step to *best_ms (each when non-NULL).  Every shot's forward
  * state is zeroed afterwards.  Synchronises the stream. */

@@ -1925,7 +1925,7 @@ int fd3d_batch_autotune(fd3d_batch *b, int steps, int best[6], double *best_ms, 
                                     {128, 8, 0, 0},   {256, 4, 0, 0},  {256, 4, 64, 16}, {128, 8, 64, 16},
                                     {256, 4, 128, 8}, {128, 4, 64, 8}};
     // cache-blocked group budgets tried after the shapes (MiB; 0: lockstep)
-    static const int budgets[] = {128, 256};
+    static const int budgets[] = {96, 128, 192, 256, 384};
     const int nt_save = b->nt;
     const size_t keep_group = b->group_bytes;
     const int keep[5] = {b->tile_x, b->tile_y, b->tile2_x, b->tile2_y, b->wgs_req};
