@@ -304,7 +304,8 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
  * kernels themselves are unchanged).  fd3d_profile_read waits for the last recorded
  * event and returns, per pass (0 = velocity, 1 = receiver sampling, 2 = stress,
  * 3 = fused step), the summed kernel time in ms and the number of launches of the last
- * profiled call. */
+ * profiled call.  The stress launch of the tile and cell kernels also samples the
+ * receivers, so pass 1 is launched on its own only after a fused step. */
 int fd3d_profile(fd3d_ctx *ctx, int enable);
 int fd3d_profile_read(fd3d_ctx *ctx, double ms[4], int launches[4]);
 

@@ -498,12 +498,14 @@ bool window_ok(const fd3d_ctx *c, int zc)
     return (long)(zc + 8) * (long)c->n[0] * (long)c->n[1] * (long)c->tsize <= kMaxWindowBytes;
 }
 
+// rec: receiver sampling carried by a forward stress launch (extra workgroups).
 template <typename T, int TX, int TY, bool FS>
 void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &tm, int pass, hipStream_t st,
-                  const TileIO<T> &io = TileIO<T>{})
+                  const TileIO<T> &io = TileIO<T>{}, const RecJob<T> &rec = RecJob<T>{})
 {
     const int nwg = tm.ntx * tm.nty * tm.nzc;
     constexpr int NT = TX * TY;
+    const int nws = nwg + rec_blocks(rec, NT);
     if (G.save[VX] != nullptr && pass == kPassVel) pass = kPassVelSave;
     if (G.save[VX] != nullptr && pass == kPassStress) pass = kPassStressSave;
     if constexpr (!FS) {  // the vacuum surface has instantiations of its own (forward only)
@@ -512,15 +514,15 @@ void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &
             return;
         }
         if (G.ks > 0 && pass == kPassStress) {
-            stress_tile<T, TX, TY, false, kFwd, true><<<nwg, NT, 0, st>>>(G, inj, n, tm);
+            stress_tile<T, TX, TY, false, kFwd, true><<<nws, NT, 0, st>>>(G, inj, n, tm, rec);
             return;
         }
     }
     switch (pass) {
     case kPassVel: vel_tile<T, TX, TY, FS><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
-    case kPassStress: stress_tile<T, TX, TY, FS><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
+    case kPassStress: stress_tile<T, TX, TY, FS><<<nws, NT, 0, st>>>(G, inj, n, tm, rec); break;
     case kPassVelSave: vel_tile<T, TX, TY, FS, kFwdSave><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
-    case kPassStressSave: stress_tile<T, TX, TY, FS, kFwdSave><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
+    case kPassStressSave: stress_tile<T, TX, TY, FS, kFwdSave><<<nws, NT, 0, st>>>(G, inj, n, tm, rec); break;
     case kPassStressA: stress_tile_adj<T, TX, TY, kAdjA><<<nwg, NT, 0, st>>>(G, inj, tm, io); break;
     case kPassVelA: vel_tile_adj<T, TX, TY, kAdjA><<<nwg, NT, 0, st>>>(G, inj, n, tm, io); break;
     case kPassVelB: vel_tile_adj<T, TX, TY, kAdjB><<<nwg, NT, 0, st>>>(G, inj, n, tm, io); break;
@@ -528,21 +530,40 @@ void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &
     }
 }
 
+// rec (stress passes of the forward only): the step's receiver sampling, carried by the
+// tile launch or launched after the cell kernel.
 template <typename T, bool FS>
 void launch_pass(const fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int pass, hipStream_t st,
-                 const TileIO<T> &io = TileIO<T>{})
+                 const TileIO<T> &io = TileIO<T>{}, const RecJob<T> &rec = RecJob<T>{})
 {
     if (c->variant == FD3D_KERNEL_CELL) {
         const dim3 blk(64, 4, 1);
         const dim3 grd((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
         if (pass == kPassVel) vel_cell<T, FS><<<grd, blk, 0, st>>>(G, inj, n);
         else stress_cell<T, FS><<<grd, blk, 0, st>>>(G, inj, n);
+        if (rec.nq > 0) record<T><<<rec_blocks(rec, 256), 256, 0, st>>>(rec, n);
         return;
     }
     const TileMap tm = tile_map(c);
     with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
-        launch_tiles<T, decltype(tx)::value, decltype(ty)::value, FS>(G, inj, n, tm, pass, st, io);
+        launch_tiles<T, decltype(tx)::value, decltype(ty)::value, FS>(G, inj, n, tm, pass, st, io, rec);
     });
+}
+
+// The receiver sampling of a grid's velocity (none when nrec is 0).
+template <typename T> RecJob<T> rec_job(const T *vx, const T *vy, const T *vz, const RecTap<T> *taps, int nrec,
+                                        int nt, T *traces)
+{
+    RecJob<T> r{};
+    if (nrec <= 0) return r;
+    r.v[0] = vx;
+    r.v[1] = vy;
+    r.v[2] = vz;
+    r.taps = taps;
+    r.traces = traces;
+    r.nq = 3 * nrec;
+    r.nt = nt;
+    return r;
 }
 
 template <typename T, bool FS>
@@ -552,13 +573,9 @@ void step(fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int nrec, 
     tm.begin(0);
     launch_pass<T, FS>(c, G, inj, n, kPassVel, st);
     tm.end();
-    if (nrec > 0) {
-        tm.begin(1);
-        record<T><<<(3 * nrec + 255) / 256, 256, 0, st>>>(G.f[VX], G.f[VY], G.f[VZ], taps, nrec, c->nt, n, traces);
-        tm.end();
-    }
-    tm.begin(2);
-    launch_pass<T, FS>(c, G, inj, n, kPassStress, st);
+    tm.begin(2);  // the stress launch also samples the receivers
+    launch_pass<T, FS>(c, G, inj, n, kPassStress, st, TileIO<T>{},
+                       rec_job<T>(G.f[VX], G.f[VY], G.f[VZ], taps, nrec, c->nt, traces));
     tm.end();
 }
 
@@ -634,8 +651,9 @@ void fused_step(fd3d_ctx *c, const Inject<T> &inj, int n, int nrec, const RecTap
     tm.end();
     if (nrec > 0) {
         tm.begin(1);
-        record<T><<<(3 * nrec + 255) / 256, 256, 0, st>>>(A.out + VX * A.fs, A.out + VY * A.fs, A.out + VZ * A.fs,
-                                                          taps, nrec, c->nt, n, traces);
+        const RecJob<T> r = rec_job<T>(A.out + VX * A.fs, A.out + VY * A.fs, A.out + VZ * A.fs, taps, nrec, c->nt,
+                                       traces);
+        record<T><<<rec_blocks(r, 256), 256, 0, st>>>(r, n);
         tm.end();
     }
     c->cur ^= 1;
@@ -1497,21 +1515,19 @@ int born_impl(fd3d_ctx *c, fd3d_ctx *dc, const fd3d_source *src, const void *dla
         with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
             constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
             if (vel) vel_tile_adj<T, TX, TY, kBornV><<<nwg, TX * TY, 0, st>>>(Gv, inj, n, tm, iov);
-            else stress_tile<T, TX, TY, false, kBornS><<<nwg, TX * TY, 0, st>>>(Gs, dinj, n, tm);
+            else stress_tile<T, TX, TY, false, kBornS><<<nwg, TX * TY, 0, st>>>(Gs, dinj, n, tm, RecJob<T>{});
         });
     };
     for (int n = 0; n < c->nt; ++n) {
         born_source(n, true);
         launch_pass<T, false>(dc, D, dinj, n, kPassVel, st);
         launch_pass<T, false>(c, G, inj, n, kPassVel, st);
-        if (nrec > 0) {
-            const int nb = (3 * nrec + 255) / 256;
-            if (traces) record<T><<<nb, 256, 0, st>>>(G.f[VX], G.f[VY], G.f[VZ], taps, nrec, c->nt, n, (T *)traces);
-            record<T><<<nb, 256, 0, st>>>(D.f[VX], D.f[VY], D.f[VZ], dtaps, nrec, c->nt, n, (T *)dtraces);
-        }
         born_source(n, false);
-        launch_pass<T, false>(dc, D, dinj, n, kPassStress, st);
-        launch_pass<T, false>(c, G, inj, n, kPassStress, st);
+        // the stress launches sample the perturbation's and the background's receivers
+        launch_pass<T, false>(dc, D, dinj, n, kPassStress, st, TileIO<T>{},
+                              rec_job<T>(D.f[VX], D.f[VY], D.f[VZ], dtaps, nrec, c->nt, (T *)dtraces));
+        launch_pass<T, false>(c, G, inj, n, kPassStress, st, TileIO<T>{},
+                              rec_job<T>(G.f[VX], G.f[VY], G.f[VZ], taps, traces ? nrec : 0, c->nt, (T *)traces));
     }
     HIP_TRY(hipGetLastError());
     return FD3D_OK;

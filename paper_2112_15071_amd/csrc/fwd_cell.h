@@ -155,22 +155,34 @@ __global__ void __launch_bounds__(256) stress_cell(Grid<T> G, Inject<T> src, int
     }
 }
 
-// (R) of one step: traces[r][c][n] = sum_m w_m v_c[idx_m] (trilinear, Sec. 2.4).
-template <typename T>
-__global__ void __launch_bounds__(256) record(const T *__restrict__ vx, const T *__restrict__ vy,
-                                              const T *__restrict__ vz, const RecTap<T> *__restrict__ taps,
-                                              int nrec, int nt, int n, T *__restrict__ traces)
+// (R) of one step as a job that a launch can carry: work item q < nq (= 3 nrec) writes
+// traces[q][n] = sum_m w_m v_c[idx_m], c = q % 3 (trilinear, Sec. 2.4).
+template <typename T> struct RecJob {
+    const T *v[3];
+    const RecTap<T> *taps;
+    T *traces;
+    int nq, nt;
+};
+
+template <typename T> __device__ __forceinline__ void sample_receiver(const RecJob<T> &r, int q, int n)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= 3 * nrec) return;
     const int c = q % 3;
-    const T *f = c == 0 ? vx : (c == 1 ? vy : vz);
-    const RecTap<T> &t = taps[q];
+    const T *f = c == 0 ? r.v[0] : (c == 1 ? r.v[1] : r.v[2]);
+    const RecTap<T> &t = r.taps[q];
     T s = T(0);
 #pragma unroll
     for (int m = 0; m < 8; ++m)
         if (t.idx[m] >= 0) s += t.w[m] * f[t.idx[m]];
-    traces[(long)q * nt + n] = s;
+    r.traces[(long)q * r.nt + n] = s;
+}
+
+// Workgroups needed to carry a job with NT threads each.
+template <typename T> inline int rec_blocks(const RecJob<T> &r, int nt) { return (r.nq + nt - 1) / nt; }
+
+template <typename T> __global__ void __launch_bounds__(256) record(RecJob<T> r, int n)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < r.nq) sample_receiver(r, q, n);
 }
 
 // Receiver sampling of many shots in one launch: shot s owns work items

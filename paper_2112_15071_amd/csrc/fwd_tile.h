@@ -755,11 +755,19 @@ __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int
     vel_tile_body<T, TX, TY, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1);
 }
 
+// The stress pass only reads v^{n+1/2}, so workgroups past the grid's tiles sample the
+// receivers of the step (rec.nq work items) in the same launch.
 template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false>
-__global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
+__global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, int n, TileMap tm, RecJob<T> rec)
 {
+    const int nwg = tm.ntx * tm.nty * tm.nzc;
+    if ((int)blockIdx.x >= nwg) {
+        const int q = ((int)blockIdx.x - nwg) * (TX * TY) + (int)threadIdx.x;
+        if (q < rec.nq) sample_receiver(rec, q, n);
+        return;
+    }
     int i0, j0, k0, k1;
-    tile_coords(tm, tile_of(blockIdx.x, gridDim.x, stress_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
+    tile_coords(tm, tile_of(blockIdx.x, nwg, stress_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
     stress_tile_body<T, TX, TY, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1);
 }
 
