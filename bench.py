@@ -3,8 +3,8 @@
 Headline (``value``): forward throughput in Gcell-steps/s on the 256^3 six-layer +
 5 % Gaussian-perturbed model (h 10 m, dt 0.5 ms, 2000 steps), random moment-tensor
 source, 12 Hz Ricker, 256 receivers, 20-cell sponge, FP32.  A "step" is one time step of
-the whole forward path: velocity pass (force source, damping), receiver sampling, stress
-pass (moment source, damping).
+the whole forward path: velocity pass (force source, damping), then the stress pass
+(moment source, damping) whose launch also samples the receivers.
 
 Also reported (same JSON line):
   batched  -- the 24-shot uneven batch (128^3 .. 256x256x128, 1500 steps): per-shot loop
@@ -17,7 +17,8 @@ Also reported (same JSON line):
   born     -- the tangent-linear (Born) forward on the 256^3 model, 300 steps;
   levels   -- the paper's Table 5 level sweep (64x64x32 .. 512^3, anisotropic cells, one
               coarse medium upsampled to every grid), 100 timed steps per level;
-  cpu_baseline -- the FP64 oracle on a bounded sample on this host's cores.
+  cpu_baseline -- the FP64 oracle on a bounded sample on this host's cores (and, as
+              one_core, on a single core over an eighth of the steps).
 
     python bench.py [--steps 2000] [--warmup 100] [--gpus 1] [--no-batch] [--no-grad] [--no-levels]
 """
@@ -484,6 +485,18 @@ def cpu_baseline(shot, ns):
     oracle.forward(cfg, shot.lam, shot.mu, shot.rho, src, shot.wavelet[:ns], shot.rec_pos)
     dt = time.perf_counter() - t0
     cells = int(shot.cells)
+    # the same oracle on one core, over fewer steps (the cost per step is constant)
+    threads = oracle.get_threads()
+    ns1 = max(1, ns // 8)
+    oracle.set_threads(1)
+    try:
+        log(f"[bench] oracle baseline: {ns1} steps at full size on 1 thread")
+        t1 = time.perf_counter()
+        cfg1 = oracle.Config(shot.shape, shot.h, shot.dt, ns1, sponge=shot.sponge)
+        oracle.forward(cfg1, shot.lam, shot.mu, shot.rho, src, shot.wavelet[:ns1], shot.rec_pos)
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(threads)
     cpu = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -492,7 +505,8 @@ def cpu_baseline(shot, ns):
         pass
     return {"value": round(cells * ns / dt / 1e9, 5), "unit": "Gcell-steps/s", "cores": oracle.get_threads(),
             "kind": "oracle", "cpu": cpu,
-            "sample": f"FP64 oracle on the 256^3 workload at full size, first {ns} of 2000 steps ({dt:.1f} s)"}
+            "sample": f"FP64 oracle on the 256^3 workload at full size, first {ns} of 2000 steps ({dt:.1f} s)",
+            "one_core": {"value": round(cells * ns1 / dt1 / 1e9, 5), "steps": ns1, "seconds": round(dt1, 2)}}
 
 
 def main():

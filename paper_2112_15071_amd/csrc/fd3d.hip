@@ -1024,40 +1024,49 @@ TileMap shot_tiles(const BatchGroup &b, const fd3d_ctx *c, int &alt)
     return tm;
 }
 
-// One pass over the shots of group gr; d points at the group's first descriptor.
+// One pass over the shots of group gr; d points at the group's first descriptor.  A
+// forward stress pass given r (the group's receiver descriptors) also samples them.
 template <typename T, int TX, int TY, int TX2, int TY2, bool FS>
-int launch_multi(const BatchGroup &gr, const ShotFwd<T> *d, int n, int pass, hipStream_t st)
+int launch_multi(const BatchGroup &gr, const ShotFwd<T> *d, int n, int pass, hipStream_t st,
+                 const ShotRec<T> *r = nullptr, int nt = 0)
 {
     const int g = gr.wgs, S = gr.ns, W = gr.tiles;
     constexpr int NT = TX * TY;
+    const RecMulti<T> rec{r, S, (r && pass == kPassStress) ? gr.recs : 0, nt, g};
+    const RecMulti<T> none{nullptr, 0, 0, 0, g};
+    const int gs = g + rec_blocks(rec, NT);
     if constexpr (!FS) {  // groups with a vacuum surface: the forward passes' own instantiations
         if (gr.vac && pass == kPassVel) {
             vel_tile_multi<T, TX, TY, TX2, TY2, false, kFwd, true><<<g, NT, 0, st>>>(d, S, W, n);
             return FD3D_OK;
         }
         if (gr.vac && pass == kPassStress) {
-            stress_tile_multi<T, TX, TY, TX2, TY2, false, kFwd, true><<<g, NT, 0, st>>>(d, S, W, n);
+            stress_tile_multi<T, TX, TY, TX2, TY2, false, kFwd, true><<<gs, NT, 0, st>>>(d, S, W, n, rec);
             return FD3D_OK;
         }
     }
     switch (pass) {
     case kPassVel: vel_tile_multi<T, TX, TY, TX2, TY2, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
-    case kPassStress: stress_tile_multi<T, TX, TY, TX2, TY2, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassStress: stress_tile_multi<T, TX, TY, TX2, TY2, FS><<<gs, NT, 0, st>>>(d, S, W, n, rec); break;
     case kPassVelSave: vel_tile_multi<T, TX, TY, TX2, TY2, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n); break;
-    case kPassStressSave: stress_tile_multi<T, TX, TY, TX2, TY2, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n); break;
-    case kPassStressA: stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassStressSave:
+        stress_tile_multi<T, TX, TY, TX2, TY2, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n, none);
+        break;
+    case kPassStressA: stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n, none); break;
     case kPassVelA: vel_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
     case kPassVelB: vel_tile_multi<T, TX, TY, TX2, TY2, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n); break;
-    default: stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n); break;
+    default: stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n, none); break;
     }
     return FD3D_OK;
 }
 
-template <typename T, bool FS> int multi_pass(const BatchGroup &b, const ShotFwd<T> *d, int n, int pass, hipStream_t st)
+template <typename T, bool FS>
+int multi_pass(const BatchGroup &b, const ShotFwd<T> *d, int n, int pass, hipStream_t st, const ShotRec<T> *r = nullptr,
+               int nt = 0)
 {
     return with_batch_tiles<T>(b, [&](auto tx, auto ty, auto tx2, auto ty2) {
         return launch_multi<T, decltype(tx)::value, decltype(ty)::value, decltype(tx2)::value, decltype(ty2)::value,
-                            FS>(b, d, n, pass, st);
+                            FS>(b, d, n, pass, st, r, nt);
     });
 }
 
@@ -1086,9 +1095,9 @@ template <typename T> int batch_sequence(fd3d_batch *b, int flags, hipStream_t s
         for (int n = 0; n < b->nt; ++n) {
             if (b->fs) multi_pass<T, true>(g, d, n, kPassVel, st);
             else multi_pass<T, false>(g, d, n, kPassVel, st);
-            if (g.recs > 0) record_multi<T><<<(g.recs + 255) / 256, 256, 0, st>>>(r, g.ns, g.recs, b->nt, n);
-            if (b->fs) multi_pass<T, true>(g, d, n, kPassStress, st);
-            else multi_pass<T, false>(g, d, n, kPassStress, st);
+            // the stress launch also samples the receivers
+            if (b->fs) multi_pass<T, true>(g, d, n, kPassStress, st, r, b->nt);
+            else multi_pass<T, false>(g, d, n, kPassStress, st, r, b->nt);
         }
     }
     HIP_TRY(hipGetLastError());
@@ -1418,13 +1427,14 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     const dim3 cgrid(256, 9 * S);
     if (!(flags & FD3D_KEEP_STATE))
         for (fd3d_ctx *c : b->ctx) zero_fields<T>(c, st);
-    auto pass = [&](const ShotFwd<T> *d, int n, int p) { multi_pass<T, false>(all, d, n, p, st); };
+    auto pass = [&](const ShotFwd<T> *d, int n, int p, const ShotRec<T> *r = nullptr) {
+        multi_pass<T, false>(all, d, n, p, st, r, b->nt);
+    };
     for (int n = 0; n < b->nt; ++n) {
         if (n % k == 0)
             copy_multi<T><<<cgrid, 256, 0, st>>>((const CopyDesc<T> *)(bws + BL.save_copy + (n / k) * BL.copy_bytes));
         pass(desc(BL.fwd0), n, kPassVel);
-        record_multi<T><<<(recs + 255) / 256, 256, 0, st>>>(rdesc, S, recs, b->nt, n);
-        pass(desc(BL.fwd0), n, kPassStress);
+        pass(desc(BL.fwd0), n, kPassStress, rdesc);  // also samples the receivers
     }
     // residuals and misfits, zeroed adjoint state, accumulators and segment slots
     for (int s = 0; s < S; ++s) {

@@ -185,8 +185,8 @@ template <typename T> __global__ void __launch_bounds__(256) record(RecJob<T> r,
     if (q < r.nq) sample_receiver(r, q, n);
 }
 
-// Receiver sampling of many shots in one launch: shot s owns work items
-// [base, base + 3 nrec) of the flat list.
+// Receiver sampling of many shots: shot s owns work items [base, base + 3 nrec) of a
+// flat list.
 template <typename T> struct ShotRec {
     const T *v[3];
     const RecTap<T> *taps;
@@ -194,19 +194,8 @@ template <typename T> struct ShotRec {
     int nrec, base;
 };
 
-template <typename T>
-__global__ void __launch_bounds__(256) record_multi(const ShotRec<T> *__restrict__ shots, int nshot, int total, int nt,
-                                                    int n)
+template <typename T> __device__ __forceinline__ void sample_shot_receiver(const ShotRec<T> &d, int l, int nt, int n)
 {
-    __shared__ int s_base[kMaxShots];
-    for (int t = threadIdx.x; t < nshot; t += blockDim.x) s_base[t] = shots[t].base;
-    __syncthreads();
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= total) return;
-    int s = 0;
-    while (s + 1 < nshot && s_base[s + 1] <= q) ++s;
-    const ShotRec<T> &d = shots[s];
-    const int l = q - d.base;
     const int c = l % 3;
     const T *f = d.v[c];
     const RecTap<T> &t = d.taps[l];
@@ -215,6 +204,34 @@ __global__ void __launch_bounds__(256) record_multi(const ShotRec<T> *__restrict
     for (int m = 0; m < 8; ++m)
         if (t.idx[m] >= 0) acc += t.w[m] * f[t.idx[m]];
     d.traces[(long)l * nt + n] = acc;
+}
+
+// Shot of work item q: the last s with base[s] <= q (bases ascending, base[0] = 0).
+__device__ __forceinline__ int rec_shot(const int *s_base, int nshot, int q)
+{
+    int s = 0;
+    while (s + 1 < nshot && s_base[s + 1] <= q) ++s;
+    return s;
+}
+
+// Receiver sampling of a batch carried by a persistent launch of wgs workgroups: the
+// workgroups past the first wgs take the total work items of the flat list.
+template <typename T> struct RecMulti {
+    const ShotRec<T> *shots;
+    int nshot, total, nt, wgs;
+};
+
+template <typename T> inline int rec_blocks(const RecMulti<T> &r, int nt) { return (r.total + nt - 1) / nt; }
+
+// Body of one such workgroup (block-uniform; s_base: LDS scratch of kMaxShots ints).
+template <typename T> __device__ __forceinline__ void sample_batch_receivers(const RecMulti<T> &r, int *s_base, int n)
+{
+    for (int t = threadIdx.x; t < r.nshot; t += blockDim.x) s_base[t] = r.shots[t].base;
+    __syncthreads();
+    const int q = ((int)blockIdx.x - r.wgs) * (int)blockDim.x + (int)threadIdx.x;
+    if (q >= r.total) return;
+    const int s = rec_shot(s_base, r.nshot, q);
+    sample_shot_receiver(r.shots[s], q - r.shots[s].base, r.nt, n);
 }
 
 } // namespace fd3d

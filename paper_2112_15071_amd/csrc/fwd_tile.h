@@ -802,11 +802,12 @@ template <typename T> struct ShotFwd {
     int alt;   // the batch's second tile shape covers this shot
 };
 
-// Work item range [lo, hi) and stride of this workgroup in the XCD-chunked order.
-__device__ __forceinline__ void work_range(int total, int &w0, int &hi, int &stride)
+// Work item range [lo, hi) and stride of this workgroup in the XCD-chunked order of a
+// persistent grid of wgs workgroups.
+__device__ __forceinline__ void work_range(int total, int wgs, int &w0, int &hi, int &stride)
 {
     const int x = blockIdx.x & 7, l = blockIdx.x >> 3;
-    const int per = (int)(gridDim.x >> 3);  // gridDim.x is a multiple of 8
+    const int per = wgs >> 3;  // wgs is a multiple of 8
     const int lo = (int)((long)total * x / 8);
     hi = (int)((long)total * (x + 1) / 8);
     w0 = lo + l;
@@ -827,7 +828,7 @@ __global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__res
     __shared__ int s_base[kMaxShots];
     load_bases(s_base, &shots[0].base, base_stride<ShotFwd<T>>(), nshot);
     int w0, hi, stride;
-    work_range(total, w0, hi, stride);
+    work_range(total, (int)gridDim.x, w0, hi, stride);
     for (; w0 < hi; w0 += stride) {
         const int w = vel_sweeps_up<MODE>() ? total - 1 - w0 : w0;
         const int s = shot_of(s_base, nshot, w);
@@ -851,15 +852,21 @@ __global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__res
     }
 }
 
+// Workgroups past rec.wgs sample the receivers of the step (the stress pass only reads
+// the velocity).
 template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd, bool VAC = false>
 __global__ void __launch_bounds__(TX *TY) stress_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
-                                                          int n)
+                                                          int n, RecMulti<T> rec)
 {
     static_assert(TX2 == 0 || TX2 * TY2 == TX * TY, "both tile shapes need the same workgroup size");
     __shared__ int s_base[kMaxShots];
+    if ((int)blockIdx.x >= rec.wgs) {
+        sample_batch_receivers(rec, s_base, n);
+        return;
+    }
     load_bases(s_base, &shots[0].base, base_stride<ShotFwd<T>>(), nshot);
     int w0, hi, stride;
-    work_range(total, w0, hi, stride);
+    work_range(total, rec.wgs, w0, hi, stride);
     for (; w0 < hi; w0 += stride) {
         const int w = stress_sweeps_up<MODE>() ? total - 1 - w0 : w0;
         const int s = shot_of(s_base, nshot, w);

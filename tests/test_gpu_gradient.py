@@ -211,3 +211,61 @@ def test_anisotropic_gradient_matches_oracle(dtype, tol):
     _, g = gpu_gradient(model, shots, d_obs, dtype, ckpt_every=9, h=h)
     for p in range(3):
         assert rel_l2(g[p], g_ref[p]) <= tol, (p, rel_l2(g[p], g_ref[p]))
+
+
+def test_full_size_gradient_truncated():
+    """The 256^3 FWI gradient workload (smoothed starting model, explosions at z = 24,
+    16 x 16 receivers at z = 22, 20-cell sponge) in the benchmark's launch configuration
+    (256 x 4 tiles, 64-plane sweeps), truncated to 12 steps with checkpoints every 5 (two
+    whole segments and a partial one).  The Ricker is centred at 3 ms so that the source
+    acts inside the window.  Shot 0 against the oracle's store-all adjoint over the whole
+    grid; two shots batched equal to the per-shot loop bitwise."""
+    from paper_2112_15071_amd import Simulator
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    nt, k, dt, h = 12, 5, 5e-4, 10.0
+    true, start = W.c4_models()
+    shots = W.c4_shots(*start, nt=nt)[:2]
+    wav = W.ricker(10.0, nt, dt, t0=0.003)
+    cfg = oracle.Config(shots[0].shape, h, dt, nt, sponge=shots[0].sponge)
+    osrcs = [oracle.Source(s.src_pos, moment=s.moment, force=s.force) for s in shots]
+    print(f"[grad-full] oracle 256^3 x {nt}: observed data", flush=True)
+    d_obs = [oracle.forward(cfg, *true, o, wav, s.rec_pos)[0] for o, s in zip(osrcs, shots)]
+    del true
+    print("[grad-full] oracle gradient of shot 0", flush=True)
+    tr = oracle.forward(cfg, *start, osrcs[0], wav, shots[0].rec_pos)[0]
+    g_ref = oracle.gradient(cfg, *start, osrcs[0], wav, shots[0].rec_pos, tr - d_obs[0])[:3]
+
+    dev = torch.device("cuda")
+    model = [torch.as_tensor(a, dtype=torch.float32, device=dev) for a in start]
+    descs = [dict(src_pos=s.src_pos, moment=s.moment, force=s.force, wavelet=wav, rec_pos=s.rec_pos) for s in shots]
+    obs = [torch.as_tensor(o, dtype=torch.float32, device=dev) for o in d_obs]
+    print(f"[grad-full] gpu per-shot loop, tile 256x4, 64 planes, checkpoints every {k}", flush=True)
+    sim = Simulator(*model, h, dt, nt, dtype=torch.float32, sponge=shots[0].sponge)
+    sim.set_kernel("tile", 4, 64, 256)
+    gws = sim.grad_workspace(k)
+    g_loop = [[torch.zeros_like(model[0]) for _ in range(3)] for _ in shots]
+    for d, o, g in zip(descs, obs, g_loop):
+        sim.gradient(gws, o, *g, **d)
+    torch.cuda.synchronize()
+    sim.close()
+    del gws
+    for p in range(3):
+        err = rel_l2(g_loop[0][p].double().cpu().numpy(), g_ref[p])
+        assert err <= 2e-4, (p, err)
+
+    print("[grad-full] gpu batched, 2 shots", flush=True)
+    sims = [Simulator(*model, h, dt, nt, dtype=torch.float32, sponge=shots[0].sponge) for _ in shots]
+    for x in sims:
+        x.set_kernel("tile", 4, 64, 256)
+    batch = BatchSimulator(sims)
+    batch.set_kernel(256, 4)
+    g_b = [[torch.zeros_like(model[0]) for _ in range(3)] for _ in shots]
+    batch.gradient(descs, obs, *[[g[p] for g in g_b] for p in range(3)], ckpt_every=k)
+    torch.cuda.synchronize()
+    batch.close()
+    for x in sims:
+        x.close()
+    for s in range(len(shots)):
+        for p in range(3):
+            assert torch.equal(g_b[s][p], g_loop[s][p]), (s, p)
