@@ -337,3 +337,41 @@ def test_cache_blocked_groups_equal_single_shots(use_graph):
     batch.close()
     for s in sims:
         s.close()
+
+
+@pytest.mark.parametrize("group_bytes", [0, 4 << 20])
+def test_many_receivers_batch_equals_single_shots(group_bytes):
+    """Receiver counts of 700, 1, 350 and 45 per shot: the batched stress launches sample
+    3288 items over four 1024-thread workgroups, with shot boundaries inside a workgroup, in
+    the lockstep schedule and in cache-blocked groups; every shot equals its single-shot run
+    (whose stress launch samples its own receivers, 2100 items over three workgroups)."""
+    import dataclasses
+
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    shots = make_shots(720)
+    rng = np.random.default_rng(72)
+    for q, m in enumerate((700, 1, 350, 45)):
+        nx, ny, nz = shots[q].shape
+        rec = np.stack([rng.uniform(3, nx - 4, m), rng.uniform(3, ny - 4, m), rng.uniform(1, nz - 4, m)], axis=1)
+        shots[q] = dataclasses.replace(shots[q], rec_pos=rec)
+    tile = (128, 8)
+    ref = single_runs(shots, tile)
+    sims = sims_for(shots)
+    batch = BatchSimulator(sims)
+    batch.set_kernel(*tile)
+    batch.set_schedule(group_bytes)
+    print(f"[batch] many receivers, group bytes {group_bytes}", flush=True)
+    for use_graph in (False, True):
+        trs = batch.forward([desc(s) for s in shots], use_graph=use_graph)
+        torch.cuda.synchronize()
+        for k, (sim, tr) in enumerate(zip(sims, trs)):
+            assert tr.shape[0] == len(shots[k].rec_pos)
+            assert np.array_equal(tr.double().cpu().numpy(), ref[k][0]), (use_graph, k)
+            assert np.array_equal(sim.state().double().cpu().numpy(), ref[k][1]), (use_graph, k)
+    # the shot with the most receivers against the oracle as well
+    compare((trs[0].double().cpu().numpy(), sims[0].state().double().cpu().numpy()), oracle_run(shots[0]), 1e-4,
+            "batched shot 0, 700 receivers")
+    batch.close()
+    for s in sims:
+        s.close()
