@@ -293,10 +293,12 @@ typedef struct fd3d_kernel {
 int fd3d_set_kernel(fd3d_ctx *ctx, const fd3d_kernel *k);
 int fd3d_get_kernel(const fd3d_ctx *ctx, fd3d_kernel *k);
 
-/* Autotuner: times every supported tile and fused shape with z chunks of 8, 16, 32, 64 and
- * 128 planes (those that fit the grid) for `steps` steps on this context (a warm-up and a timed run each, no source, on the caller's stream; waits for
- * each timing), keeps the fastest for later calls and writes it to *best (and its ms per
- * step to *best_ms) when non-NULL.  The forward state is zeroed afterwards. */
+/* Autotuner: times the cell kernel and every supported tile shape with z chunks of 4, 8,
+ * 16, 32, 64 and 128 planes and fused shape with 8 ... 128 (the chunks that fit the grid)
+ * for `steps` steps on this context (a warm-up and a timed run each, no source, on the
+ * caller's stream; waits for each timing), keeps the fastest for later calls and writes
+ * it to *best (and its ms per step to *best_ms) when non-NULL.  The forward state is
+ * zeroed afterwards. */
 int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, void *hip_stream);
 
 /* Per-kernel timing of the step loop.  With enable = 1, later forward calls record a

@@ -2104,10 +2104,12 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
     if (!ctx) return fail(FD3D_EINVAL, "ctx is NULL");
     if (steps < 1) return fail(FD3D_EINVAL, "steps must be >= 1");
     hipStream_t st = (hipStream_t)hip_stream;
-    static const int shapes[][3] = {{FD3D_KERNEL_TILE, 64, 4},   {FD3D_KERNEL_TILE, 64, 8},   {FD3D_KERNEL_TILE, 64, 16},
-                                    {FD3D_KERNEL_TILE, 128, 4},  {FD3D_KERNEL_TILE, 128, 8},  {FD3D_KERNEL_TILE, 256, 4},
-                                    {FD3D_KERNEL_FUSED, 64, 4},  {FD3D_KERNEL_FUSED, 64, 8}};
-    static const int chunks[] = {8, 16, 32, 64, 128};
+    // the one-thread-per-cell kernel (no z sweep) can win on small grids, where a sweep's
+    // planes cost a memory round trip each
+    static const int shapes[][3] = {{FD3D_KERNEL_CELL, 64, 4},   {FD3D_KERNEL_TILE, 64, 4},   {FD3D_KERNEL_TILE, 64, 8},
+                                    {FD3D_KERNEL_TILE, 64, 16},  {FD3D_KERNEL_TILE, 128, 4},  {FD3D_KERNEL_TILE, 128, 8},
+                                    {FD3D_KERNEL_TILE, 256, 4},  {FD3D_KERNEL_FUSED, 64, 4},  {FD3D_KERNEL_FUSED, 64, 8}};
+    static const int chunks[] = {4, 8, 16, 32, 64, 128};
     const int nt_save = ctx->nt;
     const fd3d_kernel keep = {ctx->variant, ctx->tile_x, ctx->tile_y, ctx->zchunk};
     fd3d_kernel win = keep;
@@ -2122,6 +2124,8 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
         if (sh[0] == FD3D_KERNEL_FUSED && !fused_supported(ctx, sh[1], sh[2])) continue;
         if (sh[1] > 64 && ctx->n[0] < sh[1] / 2) continue;  // mostly idle lanes
         for (int zc : chunks) {
+            if (sh[0] == FD3D_KERNEL_CELL && zc != chunks[0]) break;  // no z chunks
+            if (sh[0] == FD3D_KERNEL_FUSED && zc < 8) continue;
             if (zc > ctx->n[2] && zc != chunks[0]) continue;
             if (!window_ok(ctx, zc)) continue;
             ctx->variant = sh[0];

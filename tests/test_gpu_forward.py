@@ -71,7 +71,7 @@ def ragged_shot(free_surface, seed, force=False):
 
 
 # (variant, tile_y, zchunk, tile_x)
-KERNELS = [("cell", 8, 32), ("tile", 4, 8), ("tile", 8, 5), ("tile", 16, 32), ("tile", 4, 6, 128),
+KERNELS = [("cell", 8, 32), ("tile", 4, 4), ("tile", 4, 8), ("tile", 8, 5), ("tile", 16, 32), ("tile", 4, 6, 128),
            ("tile", 8, 9, 128), ("tile", 4, 7, 256), ("fused", 4, 8), ("fused", 8, 5), ("fused", 8, 32)]
 
 

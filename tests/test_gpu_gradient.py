@@ -154,6 +154,30 @@ def test_fused_forward_gives_the_same_gradient(case):
         assert torch.equal(a, b)
 
 
+def test_gradient_tile_shapes_agree(case):
+    """The checkpointed gradient through other tile shapes and z chunks (4-plane sweeps,
+    the smallest the autotuner tries; 128-wide tiles with 7-plane sweeps): bitwise the
+    gradient of 64 x 8 tiles with 16-plane sweeps."""
+    from paper_2112_15071_amd import Simulator
+
+    model, shots, d_obs, _ = case
+    out = []
+    for kern in (("tile", 8, 16, 64), ("tile", 4, 4, 64), ("tile", 4, 7, 128)):
+        print(f"[grad] kernel {kern}", flush=True)
+        sim = Simulator(*model, H, DT, NT, sponge=SPONGE, sponge_alpha=ALPHA)
+        sim.set_kernel(*kern)
+        gws = sim.grad_workspace(9)
+        g = [torch.zeros(model[0].shape, device="cuda") for _ in range(3)]
+        for s, obs in zip(shots, d_obs):
+            sim.gradient(gws, torch.as_tensor(obs, dtype=torch.float32), *g, **s)
+        torch.cuda.synchronize()
+        out.append([x.cpu() for x in g])
+        sim.close()
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert torch.equal(a, b)
+
+
 def test_autograd_functions_agree(case):
     from paper_2112_15071_amd.fwi import Misfit, Traces
 
