@@ -255,10 +255,12 @@ def bench_batch():
                 workgroups=tune["workgroups"], cell_steps=cells_steps)
 
 
-# Born (tangent-linear) forward, per cell and step: background and perturbation passes
-# (120 each), the velocity source term (reads sigma 6, rho, drho; updates dv 3) and the
-# stress source term (reads v 3, dlam, dmu; updates dsigma 6)
-BORN_BYTES_PER_CELL_STEP = 120 + 120 + 4 * (6 + 1 + 1 + 2 * 3) + 4 * (3 + 2 + 2 * 6)
+# Born (tangent-linear) forward, per cell and step, with the tile kernels: the background's
+# and the perturbation's forward passes (120 each), plus what the source terms add to the
+# background's passes: the velocity pass reads drho and the perturbation's velocity and
+# writes it (7 values), the stress pass reads dlam, dmu and the perturbation's stress and
+# writes it (14 values)
+BORN_BYTES_PER_CELL_STEP = 120 + 120 + 4 * (1 + 2 * 3) + 4 * (2 + 2 * 6)
 
 
 def bench_born(K=300):
@@ -290,8 +292,9 @@ def bench_born(K=300):
     cells = nx * ny * nz
     gbs = BORN_BYTES_PER_CELL_STEP * cells * K / el / 1e9
     log(f"[bench] born: {K} steps in {el:.3f} s -> {cells * K / el / 1e9:.2f} Gcell-steps/s, {gbs:.0f} GB/s")
+    kern = sim.kernel()
     sim.close()
-    return dict(gcs=round(cells * K / el / 1e9, 3), ms_per_step=round(el / K * 1e3, 4), steps=K,
+    return dict(gcs=round(cells * K / el / 1e9, 3), ms_per_step=round(el / K * 1e3, 4), steps=K, kernel=kern,
                 bytes_per_cell_step=BORN_BYTES_PER_CELL_STEP, hbm_gbs=round(gbs, 1))
 
 

@@ -1501,43 +1501,52 @@ int born_impl(fd3d_ctx *c, fd3d_ctx *dc, const fd3d_source *src, const void *dla
         dv.f[q] = q < 3 ? D.f[VX + q] : nullptr;
         ds.f[q] = D.f[SXX + q];
     }
-    // with the tile kernel the source terms are tile passes too (the Born modes of the
-    // bodies): on a grid that reads the background stress and density and updates the
-    // perturbation's velocity, and on one that reads the background velocity, dlam, dmu
-    // and updates the perturbation's stress
+    // the one-thread-per-cell source kernels for the cell variant
+    auto born_source = [&](int n, bool vel) {
+        if (vel) born_vel_source<T><<<grd, blk, 0, st>>>(G, dv, (const T *)drho, inj, n);
+        else born_stress_source<T><<<grd, blk, 0, st>>>(G, ds, (const T *)dlam, (const T *)dmu);
+    };
     const bool tiled = c->variant == FD3D_KERNEL_TILE;
-    Grid<T> Gv = G, Gs = G;
-    for (int q = 0; q < 3; ++q) Gv.f[VX + q] = D.f[VX + q];
-    for (int q = 0; q < 6; ++q) Gs.f[SXX + q] = D.f[SXX + q];
-    Gs.lam = (const T *)dlam;
-    Gs.mu = (const T *)dmu;
-    TileIO<T> iov;
-    std::memset(&iov, 0, sizeof iov);
-    iov.acc[0] = (T *)drho;
     const TileMap tm = tile_map(c);
     const int nwg = tm.ntx * tm.nty * tm.nzc;
-    auto born_source = [&](int n, bool vel) {
-        if (!tiled) {
-            if (vel) born_vel_source<T><<<grd, blk, 0, st>>>(G, dv, (const T *)drho, inj, n);
-            else born_stress_source<T><<<grd, blk, 0, st>>>(G, ds, (const T *)dlam, (const T *)dmu);
-            return;
+    const RecJob<T> recd = rec_job<T>(D.f[VX], D.f[VY], D.f[VZ], dtaps, nrec, c->nt, (T *)dtraces);
+    const RecJob<T> recg = rec_job<T>(G.f[VX], G.f[VY], G.f[VZ], taps, traces ? nrec : 0, c->nt, (T *)traces);
+    if (tiled) {
+        // each source term in the background's pass that computes its derivatives (the Born
+        // modes of the tile bodies), then the perturbation's own pass; the stress launches
+        // sample the receivers
+        TileIO<T> iovf, iosf;
+        std::memset(&iovf, 0, sizeof iovf);
+        std::memset(&iosf, 0, sizeof iosf);
+        for (int q = 0; q < 3; ++q) iovf.out[q] = D.f[VX + q];
+        iovf.acc[0] = (T *)drho;
+        for (int q = 0; q < 6; ++q) iosf.out[q] = D.f[SXX + q];
+        iosf.acc[0] = (T *)dlam;
+        iosf.acc[1] = (T *)dmu;
+        for (int n = 0; n < c->nt; ++n) {
+            with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
+                constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
+                vel_tile_adj<T, TX, TY, kBornV><<<nwg, TX * TY, 0, st>>>(G, inj, n, tm, iovf);
+            });
+            launch_pass<T, false>(dc, D, dinj, n, kPassVel, st);
+            with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
+                constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
+                stress_tile_born<T, TX, TY><<<nwg + rec_blocks(recg, TX * TY), TX * TY, 0, st>>>(G, inj, n, tm, iosf,
+                                                                                                  recg);
+            });
+            launch_pass<T, false>(dc, D, dinj, n, kPassStress, st, TileIO<T>{}, recd);
         }
-        with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
-            constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
-            if (vel) vel_tile_adj<T, TX, TY, kBornV><<<nwg, TX * TY, 0, st>>>(Gv, inj, n, tm, iov);
-            else stress_tile<T, TX, TY, false, kBornS><<<nwg, TX * TY, 0, st>>>(Gs, dinj, n, tm, RecJob<T>{});
-        });
-    };
+        HIP_TRY(hipGetLastError());
+        return FD3D_OK;
+    }
     for (int n = 0; n < c->nt; ++n) {
         born_source(n, true);
         launch_pass<T, false>(dc, D, dinj, n, kPassVel, st);
         launch_pass<T, false>(c, G, inj, n, kPassVel, st);
         born_source(n, false);
         // the stress launches sample the perturbation's and the background's receivers
-        launch_pass<T, false>(dc, D, dinj, n, kPassStress, st, TileIO<T>{},
-                              rec_job<T>(D.f[VX], D.f[VY], D.f[VZ], dtaps, nrec, c->nt, (T *)dtraces));
-        launch_pass<T, false>(c, G, inj, n, kPassStress, st, TileIO<T>{},
-                              rec_job<T>(G.f[VX], G.f[VY], G.f[VZ], taps, traces ? nrec : 0, c->nt, (T *)traces));
+        launch_pass<T, false>(dc, D, dinj, n, kPassStress, st, TileIO<T>{}, recd);
+        launch_pass<T, false>(c, G, inj, n, kPassStress, st, TileIO<T>{}, recg);
     }
     HIP_TRY(hipGetLastError());
     return FD3D_OK;

@@ -193,11 +193,12 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
 // kAdjB: A_s <- G_s A_s - dt E(Y).  The adjoint modes read and write the arrays named
 // by the grid (f[] pointing at the adjoint, stored or scratch fields) and by TileIO.
 // Modes of the tile bodies: forward, adjoint A/B passes, forward that also stores the
-// state for the adjoint, and the Born (tangent-linear) source terms: kBornV adds
-// dt db (D_S sigma) + db c s to the perturbation's velocity (db = -b^2 drho_eff; sigma,
-// rho of the background, drho in io.acc[0], the perturbation's velocity in io.out);
-// kBornS is the forward stress update without damping on a grid whose velocity is the
-// background's, whose stress is the perturbation's and whose lam, mu are dlam, dmu.
+// state for the adjoint, and the Born (tangent-linear) forward, whose source terms use
+// the derivatives the background's own passes compute: kBornV is the background's
+// forward velocity update plus dt db (D_S sigma) + db c s added to the perturbation's
+// velocity in io.out[0..2] (db = -b^2 drho_eff, drho in io.acc[0]); kBornS is the
+// background's forward stress update plus dt (dC E v) added to the perturbation's stress
+// in io.out[0..5] (dlam, dmu in io.acc[0], io.acc[1]; no damping, no source).
 enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3, kBornV = 4, kBornS = 5 };
 
 // Sweep direction of each pass (true: upward, decreasing k), chosen so that every pass
@@ -207,7 +208,10 @@ enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3, kBornV = 4, kBornS = 5 };
 // order, so that when the tiles run in several rounds its first round covers the last
 // round of the pass before.
 template <int MODE> constexpr bool vel_sweeps_up() { return MODE == kAdjA; }
-template <int MODE> constexpr bool stress_sweeps_up() { return MODE == kFwd || MODE == kFwdSave || MODE == kAdjB; }
+template <int MODE> constexpr bool stress_sweeps_up()
+{
+    return MODE == kFwd || MODE == kFwdSave || MODE == kAdjB || MODE == kBornS;
+}
 
 // Tile of workgroup b of nwg (XCD-contiguous ranges), reversed for upward passes.
 __device__ __forceinline__ int tile_of(int b, int nwg, bool reverse)
@@ -290,7 +294,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     __shared__ T s_coef[3 * 8];
     stage_coef<T, VX, 3>(s_coef, src, srcv, tid);
     auto cf = [&](int c, int t) -> T { return t >= 0 ? s_coef[(c - VX) * 8 + (t & 7)] : T(0); };
-    constexpr bool fwd = MODE == kFwd || MODE == kFwdSave;
+    constexpr bool fwd = MODE == kFwd || MODE == kFwdSave || MODE == kBornV;
     constexpr bool use_rho = MODE != kAdjA;
     constexpr bool up = vel_sweeps_up<MODE>();
     static_assert(!(up && FS), "upward velocity sweeps have no free-surface images");
@@ -323,7 +327,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 
     // plane registers, loaded one plane ahead
     struct Plane {
-        T cxx, cyy, cxy, vx, vy, vz, xx, xy, xz, yy, yz, r, g0, g1, g2, dr;
+        T cxx, cyy, cxy, vx, vy, vz, xx, xy, xz, yy, yz, r, g0, g1, g2, dr, dvx, dvy, dvz;
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const unsigned pk = wplane(w, kk, ok), pr = wplane(w, kk, ok && use_rho), o = oc + pk;
@@ -333,6 +337,11 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             P.g0 = ld<T>(wfield(io.acc[0], w), o);
             P.g1 = ld<T>(wfield(io.acc[1], w), o);
             P.g2 = ld<T>(wfield(io.acc[2], w), o);
+        }
+        if constexpr (born) {
+            P.dvx = ld<T>(wfield(io.out[0], w), o);
+            P.dvy = ld<T>(wfield(io.out[1], w), o);
+            P.dvz = ld<T>(wfield(io.out[2], w), o);
         }
         P.cxx = ld<T>(bxx, o);
         P.cyy = ld<T>(byy, o);
@@ -375,6 +384,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         }
         const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
         const T ga0 = P.g0, ga1 = P.g1, ga2 = P.g2;
+        const T bvx0 = P.dvx, bvy0 = P.dvy, bvz0 = P.dvz;  // the perturbation's velocity (kBornV)
         // loads of the next plane of the sweep and the queue heads (skipped past the chunk)
         const bool more = it + 1 < k1 - k0;
         loadplane(up ? k - 1 : k + 1, more, P);
@@ -389,6 +399,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 
         const unsigned pw = wplane(w, k, true);
         const rsrc_t ovx = wfield(G.f[VX], w), ovy = wfield(G.f[VY], w), ovz = wfield(G.f[VZ], w);
+        const rsrc_t bvx = wfield(io.out[0], w), bvy = wfield(io.out[1], w), bvz = wfield(io.out[2], w);
         {
             const int o = own_c3 + tx + 1;
             const int ox = (ty + 2) * W3 + tx + 2;
@@ -402,15 +413,17 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 v = v * (gxh * gyi * gz_i);
                 st(ovx, st_vx + pw, v);
                 if constexpr (MODE == kFwdSave) st(wfield(G.save[VX], w), st_vx + pw, v);
-            } else if constexpr (born) {
+            }
+            if constexpr (born) {
                 const T bb = buoy(r0, Lr[ty * WR + tx + 1]);
                 const T db = -(bb * bb) * ((dr0 + Ldr[ty * WR + tx + 1]) * T(0.5));
                 T add = dt * db * d;
                 if (srcv) add += db * cf(VX, tap_of(src, VX, i, j, k)) * s;
-                st(ovx, st_vx + pw, vx0 + add);
-            } else if constexpr (MODE == kAdjA) {
+                st(bvx, st_vx + pw, bvx0 + add);
+            }
+            if constexpr (MODE == kAdjA) {
                 st(ovx, st_vx + pw, (gxh * gyi * gz_i) * vx0 - dt * d);
-            } else {
+            } else if constexpr (MODE == kAdjB) {
                 const T u = (gxh * gyi * gz_i) * vx0;
                 T g = dt * d * u;
                 if (srcv) g += cf(VX, tap_of(src, VX, i, j, k)) * s * u;
@@ -431,15 +444,17 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 v = v * (gxi * gyh * gz_i);
                 st(ovy, st_vy + pw, v);
                 if constexpr (MODE == kFwdSave) st(wfield(G.save[VY], w), st_vy + pw, v);
-            } else if constexpr (born) {
+            }
+            if constexpr (born) {
                 const T bb = buoy(r0, Lr[(ty + 1) * WR + tx]);
                 const T db = -(bb * bb) * ((dr0 + Ldr[(ty + 1) * WR + tx]) * T(0.5));
                 T add = dt * db * d;
                 if (srcv) add += db * cf(VY, tap_of(src, VY, i, j, k)) * s;
-                st(ovy, st_vy + pw, vy0 + add);
-            } else if constexpr (MODE == kAdjA) {
+                st(bvy, st_vy + pw, bvy0 + add);
+            }
+            if constexpr (MODE == kAdjA) {
                 st(ovy, st_vy + pw, (gxi * gyh * gz_i) * vy0 - dt * d);
-            } else {
+            } else if constexpr (MODE == kAdjB) {
                 const T u = (gxi * gyh * gz_i) * vy0;
                 T g = dt * d * u;
                 if (srcv) g += cf(VY, tap_of(src, VY, i, j, k)) * s * u;
@@ -461,15 +476,17 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 v = v * (gxi * gyi * gz_h);
                 st(ovz, st_vz + pw, v);
                 if constexpr (MODE == kFwdSave) st(wfield(G.save[VZ], w), st_vz + pw, v);
-            } else if constexpr (born) {
+            }
+            if constexpr (born) {
                 const T bb = buoy(r0, r1);
                 const T db = -(bb * bb) * ((dr0 + dr1) * T(0.5));
                 T add = dt * db * d;
                 if (srcv) add += db * cf(VZ, tap_of(src, VZ, i, j, k)) * s;
-                st(ovz, st_vz + pw, vz0 + add);
-            } else if constexpr (MODE == kAdjA) {
+                st(bvz, st_vz + pw, bvz0 + add);
+            }
+            if constexpr (MODE == kAdjA) {
                 st(ovz, st_vz + pw, (gxi * gyi * gz_h) * vz0 - dt * d);
-            } else {
+            } else if constexpr (MODE == kAdjB) {
                 const T u = (gxi * gyi * gz_h) * vz0;
                 T g = dt * d * u;
                 if (srcv) g += cf(VZ, tap_of(src, VZ, i, j, k)) * s * u;
@@ -507,6 +524,8 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     __shared__ T s_vy[2][NV + 1];
     __shared__ T s_vz[2][NV + 1];
     __shared__ T s_mu[3][NM + 1];
+    constexpr bool bsf = MODE == kBornS;
+    __shared__ T s_dmu[3][bsf ? NM + 1 : 1];  // dmu ring of the Born stress term
 
     const int nx = G.nx, ny = G.ny, nz = G.nz;
     const int sy = (int)G.sy;
@@ -551,15 +570,14 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     auto cf = [&](int c, int t) -> T { return t >= 0 ? s_coef[(c - SXX) * 8 + (t & 7)] : T(0); };
     const unsigned st_xz = (in && i <= nx - 2) ? oc : kOOB;
     const unsigned st_yz = (in && j <= ny - 2) ? oc : kOOB;
-    // kBornS runs the forward update without damping (see the mode list)
     constexpr bool fwd = MODE == kFwd || MODE == kFwdSave || MODE == kBornS;
-    constexpr bool damp = MODE != kBornS;
     constexpr bool use_model = MODE != kAdjB;
 
     // upward for the forward passes and stress-B (see stress_sweeps_up); the z queues shift
     // the other way and the mu ring takes the new plane at the other end, with the same
     // arithmetic per sample in both directions
     constexpr bool up = stress_sweeps_up<MODE>();
+    static_assert(!bsf || up, "the Born stress mode sweeps upward");
     const int kfirst = up ? k1 - 1 : k0;
 
     const Window w = window<T>(k0, k1, nz, sz);
@@ -576,7 +594,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     T m1 = up ? T(0) : zld(mu, k0 + 1, use_model);  // own mu one plane below (downward sweep)
 
     struct Plane {
-        T cl, cm, sxx, syy, szz, sxy, sxz, syz, hx, hy, hz, a0, a1, a2, a3, a4;
+        T cl, cm, sxx, syy, szz, sxy, sxz, syz, hx, hy, hz, a0, a1, a2, a3, a4, dl, dm, b0, b1, b2, b3, b4, b5;
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const unsigned pk = wplane(w, kk, ok), o = oc + pk, om_ = oc + wplane(w, kk, ok && use_model);
@@ -599,18 +617,35 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         P.hx = ld<T>(bx, hvx.off + pk);
         P.hy = ld<T>(by, hvy.off + pk);
         P.hz = ld<T>(bz, hvz.off + pk);
+        if constexpr (bsf) {
+            P.dl = ld<T>(wfield(io.acc[0], w), om_);
+            P.dm = ld<T>(wfield(io.acc[1], w), om_);
+            P.b0 = ld<T>(wfield(io.out[0], w), o);
+            P.b1 = ld<T>(wfield(io.out[1], w), o);
+            P.b2 = ld<T>(wfield(io.out[2], w), o);
+            P.b3 = ld<T>(wfield(io.out[3], w), o);
+            P.b4 = ld<T>(wfield(io.out[4], w), o);
+            P.b5 = ld<T>(wfield(io.out[5], w), o);
+        }
     };
     auto loadmu = [&](int kk, bool ok) -> T { return ld<T>(wfield(mu, w), hm.off + wplane(w, kk, ok && use_model)); };
+    auto loaddmu = [&](int kk, bool ok) -> T { return ld<T>(wfield(io.acc[1], w), hm.off + wplane(w, kk, ok)); };
 
     Plane P;
     loadplane(kfirst, true, P);
-    T hmu;
+    T hmu, hdmu = T(0);
     if constexpr (up) {
         // mu plane k1 (below the first plane) complete; plane k1 - 1's halo one ahead
         T *M = s_mu[k1 % 3];
         M[om] = zld(mu, k1, use_model);
         M[hm.lds] = loadmu(k1, true);
         hmu = loadmu(k1 - 1, true);
+        if constexpr (bsf) {
+            T *D = s_dmu[k1 % 3];
+            D[om] = zld(io.acc[1], k1, true);
+            D[hm.lds] = loaddmu(k1, true);
+            hdmu = loaddmu(k1 - 1, true);
+        }
     } else {
         T *M = s_mu[k0 % 3];
         M[om] = P.cm;
@@ -623,6 +658,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         const int b = it & 1;
         T *Lx = s_vx[b], *Ly = s_vy[b], *Lz = s_vz[b];
         T *M0 = s_mu[k % 3], *M1 = s_mu[(k + 1) % 3];
+        T *D0 = s_dmu[bsf ? k % 3 : 0], *D1 = s_dmu[bsf ? (k + 1) % 3 : 0];
         Lx[ovx] = qvx[1];
         Ly[ovy] = qvy[1];
         Lz[ovz] = qvz[2];
@@ -632,6 +668,10 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         if constexpr (up) {  // mu plane k enters the ring (plane k + 1 is there)
             M0[om] = P.cm;
             M0[hm.lds] = hmu;
+            if constexpr (bsf) {
+                D0[om] = P.dm;
+                D0[hm.lds] = hdmu;
+            }
         } else {  // mu plane k + 1 enters the ring (plane k is there)
             M1[om] = m1;
             M1[hm.lds] = hmu;
@@ -639,6 +679,8 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         const T l = P.cl, mm = P.cm;
         const T o_xx = P.sxx, o_yy = P.syy, o_zz = P.szz, o_xy = P.sxy, o_xz = P.sxz, o_yz = P.syz;
         const T a0 = P.a0, a1 = P.a1, a2 = P.a2, a3 = P.a3, a4 = P.a4;
+        const T dl = P.dl, dm = P.dm;
+        const T b_xx = P.b0, b_yy = P.b1, b_zz = P.b2, b_xy = P.b3, b_xz = P.b4, b_yz = P.b5;
         // loads of the next plane of the sweep and the queue heads (skipped past the chunk)
         const int kn = up ? k - 1 : k + 1;
         const bool more = it + 1 < k1 - k0;
@@ -647,6 +689,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         const T nvz = zld(fvz, up ? k - 3 : k + 2, more);
         const T nm1 = up ? T(0) : zld(mu, k + 2, more && use_model);
         const T nhm = loadmu(up ? k - 1 : k + 2, more);
+        const T nhdm = bsf ? loaddmu(k - 1, more) : T(0);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         // second order next to a vacuum surface: ezz at integer k, dz vx / dz vy at k + 1/2
         const bool vzo = VAC && o2_int(sp.n, k), vxo = VAC && o2_half(sp.x, k), vyo = VAC && o2_half(sp.y, k);
@@ -667,15 +710,15 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         if (FS && k == 0) ezz = -l / (l + T(2) * mm) * (exx + eyy);
         else if (FS && k == 1) ezz = (qvz[2] - qvz[1]) * rdz;
         else ezz = dz_or_o2(vzo, qvz[2], qvz[1], qvz[3], qvz[0], rdz);
-        const T gn = damp ? gxi * gyi * gz_i : T(1);
+        const T gn = gxi * gyi * gz_i;
         const T exy = dstag(Lx[ovx + W3], Lx[ovx], Lx[ovx + 2 * W3], Lx[ovx - W3], rdy)
                     + dstag(Ly[ovy + 1], Ly[ovy], Ly[ovy + 2], Ly[ovy - 1], rdx);
         const T dzvx = dz_or_o2((FS && k == 0) || vxo, qvx[2], qvx[1], qvx[3], qvx[0], rdz);
         const T exz = dzvx + dstag(Lz[ovz + 1], Lz[ovz], Lz[ovz + 2], Lz[ovz - 1], rdx);
         const T dzvy = dz_or_o2((FS && k == 0) || vyo, qvy[2], qvy[1], qvy[3], qvy[0], rdz);
         const T eyz = dzvy + dstag(Lz[ovz + W3], Lz[ovz], Lz[ovz + 2 * W3], Lz[ovz - W3], rdy);
-        const T g_xy = damp ? gxh * gyh * gz_i : T(1), g_xz = damp ? gxh * gyi * gz_h : T(1);
-        const T g_yz = damp ? gxi * gyh * gz_h : T(1);
+        const T g_xy = gxh * gyh * gz_i, g_xz = gxh * gyi * gz_h;
+        const T g_yz = gxi * gyh * gz_h;
         const unsigned o_stxz = k <= nz - 2 ? st_xz : kOOB, o_styz = k <= nz - 2 ? st_yz : kOOB;
         if constexpr (fwd) {
             const T tr = exx + eyy + ezz;
@@ -703,6 +746,22 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             st(wfield(G.f[SXY], w), st_xy + pw, nxy * g_xy);
             st(wfield(G.f[SXZ], w), o_stxz + pw, nxz * g_xz);
             st(wfield(G.f[SYZ], w), o_styz + pw, nyz * g_yz);
+            if constexpr (bsf) {
+                // the perturbation's stress term: dlam, dmu with the same strain rates
+                // (no damping, no source)
+                const T bxx = b_xx + dt * (dl * tr + T(2) * dm * exx);
+                const T byy = b_yy + dt * (dl * tr + T(2) * dm * eyy);
+                const T bzz = b_zz + dt * (dl * tr + T(2) * dm * ezz);
+                const T dxy = ((D0[om] + D0[om + 1]) + (D0[om + WM] + D0[om + WM + 1])) / T(4);
+                const T dxz = ((D0[om] + D0[om + 1]) + (D1[om] + D1[om + 1])) / T(4);
+                const T dyz = ((D0[om] + D0[om + WM]) + (D1[om] + D1[om + WM])) / T(4);
+                st(wfield(io.out[0], w), oc + pw, bxx);
+                st(wfield(io.out[1], w), oc + pw, byy);
+                st(wfield(io.out[2], w), oc + pw, bzz);
+                st(wfield(io.out[3], w), st_xy + pw, b_xy + dt * dxy * exy);
+                st(wfield(io.out[4], w), o_stxz + pw, b_xz + dt * dxz * exz);
+                st(wfield(io.out[5], w), o_styz + pw, b_yz + dt * dyz * eyz);
+            }
         } else if constexpr (MODE == kAdjA) {
             // gradients of C and X = C T with T = G_s A_s
             const T txx = gn * o_xx, tyy = gn * o_yy, tzz = gn * o_zz;
@@ -742,6 +801,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             m1 = nm1;
         }
         hmu = nhm;
+        hdmu = nhdm;
     }
 }
 
@@ -769,6 +829,24 @@ __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, 
     int i0, j0, k0, k1;
     tile_coords(tm, tile_of(blockIdx.x, nwg, stress_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
     stress_tile_body<T, TX, TY, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1);
+}
+
+// Born stress pass (kBornS): the background's stress update and the perturbation's
+// stress term in one sweep; the workgroups past the tiles sample the background's
+// receivers.
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) stress_tile_born(Grid<T> G, Inject<T> src, int n, TileMap tm, TileIO<T> io,
+                                                           RecJob<T> rec)
+{
+    const int nwg = tm.ntx * tm.nty * tm.nzc;
+    if ((int)blockIdx.x >= nwg) {
+        const int q = ((int)blockIdx.x - nwg) * (TX * TY) + (int)threadIdx.x;
+        if (q < rec.nq) sample_receiver(rec, q, n);
+        return;
+    }
+    int i0, j0, k0, k1;
+    tile_coords(tm, tile_of(blockIdx.x, nwg, stress_sweeps_up<kBornS>()), i0, j0, k0, k1, TX, TY, G.nz);
+    stress_tile_body<T, TX, TY, false, kBornS>(G, src, n, i0, j0, k0, k1, io);
 }
 
 // Adjoint passes, one workgroup per tile (no free surface).
