@@ -131,3 +131,38 @@ def test_fwi_descent_lowers_the_misfit():
     print(f"[fwi] misfit history {hist}", flush=True)
     assert len(hist) == 4
     assert all(b < a for a, b in zip(hist, hist[1:]))
+
+
+@pytest.mark.parametrize("dtype,tol,tile_x", [(torch.float32, 1e-4, 256), (torch.float64, 1e-12, 128)])
+def test_born_bench_tile_shape(dtype, tol, tile_x):
+    """The tile configuration the benchmark times (256-wide tiles, 64-plane z chunks; FP64
+    has no 256-wide tile, it takes its widest, 128) on a grid with a ragged last chunk
+    (planes 64-69), the source and receivers next to the chunk boundary, and 400 receivers
+    (their sampling spans several extra workgroups of both stress launches)."""
+    shape = (40, 30, 70)
+    nx, ny, nz = shape
+    rng = np.random.Generator(np.random.PCG64(919))
+    vp = np.where(np.arange(nz) < nz // 2, 2500.0, 3200.0)[:, None, None] * np.ones((nz, ny, nx))
+    vp = vp * (1.0 + 0.03 * W.gaussian_field((nz, ny, nx), 30.0, 10.0, rng))
+    model = W.elastic_from_vp(vp)
+    dm = [a * rng.standard_normal(a.shape) * 0.1 for a in model]
+    rec = W.receiver_grid(np.linspace(6, nx - 7, 20), np.linspace(6, ny - 7, 20), 55.5)
+    nt = 80
+    s = dict(src_pos=(19.4, 14.7, 61.2), moment=(1e15, -3e14, 5e14, 2e14, -1e14, 4e14), force=(0.0,) * 3,
+             wavelet=W.ricker(25.0, nt, DT, at_half=True))
+    cfg = oracle.Config(shape, 10.0, DT, nt, sponge=SPONGE, alpha=ALPHA)
+    osrc = oracle.Source(s["src_pos"], moment=s["moment"], force=s["force"])
+    tr_ref, dtr_ref = oracle.born(cfg, *model, *dm, osrc, s["wavelet"], rec)
+    print(f"[born] bench tile shape {dtype}", flush=True)
+    from paper_2112_15071_amd import Simulator
+
+    sim = Simulator(*model, 10.0, DT, nt, dtype=dtype, sponge=SPONGE, sponge_alpha=ALPHA)
+    sim.set_kernel("tile", 4, 64, tile_x)
+    tr, dtr = sim.born(*dm, rec_pos=rec, **s)
+    tr, dtr = tr.double().cpu().numpy(), dtr.double().cpu().numpy()
+    for c in range(3):
+        assert rel_l2(dtr[:, c], dtr_ref[:, c]) <= tol, (c, rel_l2(dtr[:, c], dtr_ref[:, c]))
+        assert rel_l2(tr[:, c], tr_ref[:, c]) <= tol, c
+    fwd = sim.forward(rec_pos=rec, **s).double().cpu().numpy()
+    assert np.array_equal(fwd, tr)
+    sim.close()
