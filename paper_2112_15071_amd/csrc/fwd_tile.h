@@ -213,6 +213,15 @@ template <int MODE> constexpr bool stress_sweeps_up()
     return MODE == kFwd || MODE == kFwdSave || MODE == kAdjB || MODE == kBornS;
 }
 
+// Waits for every outstanding memory operation of the wave (s_waitcnt with all counters
+// zero).  Called once between a sweep's prologue loads and its plane loop: the compiler
+// places the loop header's waits for the state of both paths into the header, and when a
+// prologue load is still in flight there it puts a full vmcnt(0) at the top of every
+// iteration, which then also waits for the previous plane's stores to be acknowledged
+// before the next plane's loads can be issued.  With the prologue drained, each iteration
+// waits only for its own plane's loads and leaves the stores in flight.
+__device__ __forceinline__ void drain_loads() { __builtin_amdgcn_s_waitcnt(0); }
+
 // Tile of workgroup b of nwg (XCD-contiguous ranges), reversed for upward passes.
 __device__ __forceinline__ int tile_of(int b, int nwg, bool reverse)
 {
@@ -359,6 +368,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     };
     Plane P;
     loadplane(kfirst, true, P);
+    drain_loads();
 
     for (int it = 0; it < k1 - k0; ++it) {
         const int k = up ? k1 - 1 - it : k0 + it;
@@ -653,6 +663,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         hmu = loadmu(k0 + 1, true);
     }
 
+    drain_loads();
     for (int it = 0; it < k1 - k0; ++it) {
         const int k = up ? k1 - 1 - it : k0 + it;
         const int b = it & 1;
