@@ -434,6 +434,9 @@ def bench_gradient(wave=4, nshots=8):
     # per-shot loop through one gradient workspace
     sim = Simulator(*model, 10.0, 5e-4, 1500, sponge=20, device=dev)
     sim.autotune(steps=10)
+    # the gradient's own kernel choice (its adjoint passes can rank tile shapes unlike the forward)
+    gt = sim.autotune_gradient(shot_desc(shots[0]))
+    log(f"[bench] gradient kernel {sim.kernel()} (tried {gt['tried']})")
     gws = sim.grad_workspace(k)
     g_loop = [torch.zeros_like(model[0]) for _ in range(3)]
     sync()
@@ -455,7 +458,8 @@ def bench_gradient(wave=4, nshots=8):
     for x in sims:
         x.set_kernel(kern["variant"], kern["tile_y"], kern["zchunk"], kern["tile_x"])
     batch = BatchSimulator(sims)
-    batch.set_kernel(kern["tile_x"], kern["tile_y"])
+    bt = batch.autotune_gradient([shot_desc(s) for s in shots[:wave]])
+    log(f"[bench] batched gradient tile {bt['tile']}, z chunk {bt['zchunk']} (tried {bt['tried']})")
     gws_b = [x.grad_workspace(k) for x in sims]
     g_b = [torch.zeros_like(model[0]) for _ in range(3)]
     sync()
@@ -477,6 +481,7 @@ def bench_gradient(wave=4, nshots=8):
     n = len(shots)
     return dict(loop_shots_per_s=round(n / t_loop, 4), batched_shots_per_s=round(n / t_b, 4),
                 loop_s=round(t_loop, 2), batched_s=round(t_b, 2), speedup=round(t_loop / t_b, 3), wave=wave,
+                loop_kernel=kern, batch_tile=bt["tile"], batch_zchunk=bt["zchunk"],
                 misfit=float(J_loop), max_rel_diff_batched_vs_loop=diff,
                 bytes_per_cell_step_per_shot=GRAD_BYTES_PER_CELL_STEP)
 

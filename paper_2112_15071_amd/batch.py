@@ -60,6 +60,60 @@ class BatchSimulator:
         best["per_shape"] = {f"{k[0]}": v for k, v in seen.items()}
         return best
 
+    # (tile_x, tile_y, zchunk) configurations the batched-gradient tuner tries
+    GRADIENT_CANDIDATES = ((256, 4, 64), (256, 4, 128), (128, 8, 64), (128, 4, 64), (128, 4, 128), (64, 16, 64),
+                           (64, 8, 32))
+
+    @staticmethod
+    def _set_zchunk(sims, zc: int) -> None:
+        for sim in sims:
+            k = sim.kernel()
+            sim.set_kernel(k["variant"], k["tile_y"], zc, k["tile_x"])
+
+    def autotune_gradient(self, shots: List[Dict], steps: int = 40, ckpt_every: int = 20, candidates=None) -> dict:
+        """Pick the tile shape and z chunk of the batched gradient: times the batched
+        gradient over ``steps`` steps (checkpoints every ``ckpt_every``, zero observed data,
+        each shot's wavelet cut to ``steps``) on scratch contexts over the same models for
+        every candidate (tile_x, tile_y, zchunk), then sets the fastest tile shape here and
+        its z chunk on every simulator of the batch."""
+        import time
+
+        from .simulator import _shot_args
+
+        steps = min(int(steps), min(sim.nt for sim in self.sims))
+        ck = min(ckpt_every, steps)
+        scratch = [sim.like(steps) for sim in self.sims]
+        sb = BatchSimulator(scratch)
+        args = [_shot_args(sh, steps) for sh in shots]
+        d_obs = [torch.zeros((Simulator._rec(a.get("rec_pos"))[1], 3, steps), dtype=sim.dtype, device=sim.device)
+                 for a, sim in zip(args, scratch)]
+        gws = [sim.grad_workspace(ck) for sim in scratch]
+        g = [[torch.zeros_like(sim.lam) for sim in scratch] for _ in range(3)]  # per shot: grids may differ
+        times = {}
+        for c in candidates or self.GRADIENT_CANDIDATES:
+            tx, ty, zc = c
+            try:
+                sb.set_kernel(tx, ty)
+                BatchSimulator._set_zchunk(scratch, zc)
+            except _abi.FD3DError:
+                continue  # a shape not built for this dtype, or too deep a window
+            sb.gradient(args, d_obs, *g, ckpt_every=ck, gws=gws)
+            torch.cuda.current_stream().synchronize()
+            t0 = time.perf_counter()
+            sb.gradient(args, d_obs, *g, ckpt_every=ck, gws=gws)
+            torch.cuda.current_stream().synchronize()
+            times[c] = (time.perf_counter() - t0) * 1e3 / steps
+        sb.close()
+        for sim in scratch:
+            sim.close()
+        if not times:
+            raise RuntimeError("no batched-gradient configuration runs for this batch")
+        best = min(times, key=times.get)
+        self.set_kernel(best[0], best[1])
+        BatchSimulator._set_zchunk(self.sims, best[2])
+        return dict(tile=[best[0], best[1]], zchunk=best[2], ms_per_step=times[best],
+                    tried={f"{x}x{y},{z}": round(v, 4) for (x, y, z), v in times.items()})
+
     def forward(self, shots: List[Dict], use_graph: bool = True, keep_state: bool = False,
                 traces: List[torch.Tensor] = None) -> List[torch.Tensor]:
         if len(shots) != len(self.sims):

@@ -78,6 +78,14 @@ def upsample(coarse: torch.Tensor, shape) -> torch.Tensor:
     return out
 
 
+def _shot_args(shot: dict, steps: int) -> dict:
+    """Source and receiver arguments of a shot description, its wavelet cut to ``steps``."""
+    args = {k: shot[k] for k in ("src_pos", "moment", "force", "rec_pos") if shot.get(k) is not None}
+    if shot.get("wavelet") is not None:
+        args["wavelet"] = torch.as_tensor(shot["wavelet"])[:steps]
+    return args
+
+
 class Simulator:
     """One grid and model on one GPU; forward runs of ``nt`` steps."""
 
@@ -180,6 +188,61 @@ class Simulator:
             except OSError:
                 pass
         return dict(e, cached=False)
+
+    # kernel configurations the gradient tuner tries (variant, tile_x, tile_y, zchunk)
+    GRADIENT_CANDIDATES = (("tile", 256, 4, 64), ("tile", 256, 4, 128), ("tile", 128, 4, 64), ("tile", 128, 4, 128),
+                           ("tile", 128, 8, 64), ("tile", 64, 16, 64), ("tile", 64, 8, 32))
+
+    def like(self, nt: int) -> "Simulator":
+        """A new context over the same model arrays, spacing and options, with nt steps and
+        this context's kernel configuration."""
+        o = self.opts
+        sim = Simulator(self.lam, self.mu, self.rho, self.spacing, self.dt, nt, dtype=self.dtype,
+                        sponge=[o.sponge[f] for f in range(6)], sponge_alpha=o.sponge_alpha,
+                        free_surface=bool(o.free_surface), check_finite=bool(o.check_finite),
+                        max_receivers=o.max_receivers, device=self.device, vacuum_top=o.vacuum_top,
+                        vacuum_map=self.vacuum_map)
+        k = self.kernel()
+        sim.set_kernel(k["variant"], k["tile_y"], k["zchunk"], k["tile_x"])
+        return sim
+
+    def autotune_gradient(self, shot: dict, steps: int = 40, ckpt_every: int = 20, candidates=None) -> dict:
+        """Pick the kernel configuration for gradients of this grid: times fd3d_gradient over
+        ``steps`` steps (checkpoints every ``ckpt_every``, zero observed data, ``shot``'s
+        source and receivers with its wavelet cut to ``steps``) on a scratch context over the
+        same model for every candidate (variant, tile_x, tile_y, zchunk), and sets the fastest
+        here.  The forward tuner (``autotune``) times the forward passes only; the adjoint
+        passes move more fields per cell and can rank tile shapes differently."""
+        import time
+
+        cands = candidates or self.GRADIENT_CANDIDATES
+        steps = min(int(steps), self.nt)
+        scratch = self.like(steps)
+        gws = scratch.grad_workspace(min(ckpt_every, steps))
+        args = _shot_args(shot, steps)
+        nrec = Simulator._rec(args.get("rec_pos"))[1]
+        d_obs = torch.zeros((nrec, 3, steps), dtype=self.dtype, device=self.device)
+        g = [torch.zeros_like(self.lam) for _ in range(3)]
+        times = {}
+        for c in cands:
+            variant, tx, ty, zc = c
+            try:
+                scratch.set_kernel(variant, ty, zc, tx)
+            except _abi.FD3DError:
+                continue  # not built for this dtype or too deep a window for this grid
+            scratch.gradient(gws, d_obs, *g, **args)
+            torch.cuda.current_stream().synchronize()
+            t0 = time.perf_counter()
+            scratch.gradient(gws, d_obs, *g, **args)
+            torch.cuda.current_stream().synchronize()
+            times[c] = (time.perf_counter() - t0) * 1e3 / steps
+        scratch.close()
+        if not times:
+            raise RuntimeError("no gradient kernel candidate runs on this grid")
+        best = min(times, key=times.get)
+        self.set_kernel(best[0], best[2], best[3], best[1])
+        return dict(self.kernel(), ms_per_step=times[best],
+                    tried={f"{v},{x},{y},{z}": round(t, 4) for (v, x, y, z), t in times.items()})
 
     def info(self):
         """(vp_max, vs_min, rho_min, dt_max) read back at creation."""

@@ -178,6 +178,56 @@ def test_gradient_tile_shapes_agree(case):
             assert torch.equal(a, b)
 
 
+def test_gradient_tuners_pick_a_candidate_and_keep_the_gradient(case):
+    """The gradient tuners (per shot and batched) set one of their candidates, and every
+    shot's gradient through the tuned configuration equals, bit for bit, its gradient
+    through the default configuration."""
+    from paper_2112_15071_amd import Simulator
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    model, shots, d_obs, _ = case
+    obs = [torch.as_tensor(o, dtype=torch.float32) for o in d_obs]
+
+    def grads(sim):
+        gws = sim.grad_workspace(9)
+        out = []
+        for s, o in zip(shots, obs):
+            g = [torch.zeros(model[0].shape, device="cuda") for _ in range(3)]
+            sim.gradient(gws, o, *g, **s)
+            torch.cuda.synchronize()
+            out.append([x.cpu() for x in g])
+        return out
+
+    sim = Simulator(*model, H, DT, NT, sponge=SPONGE, sponge_alpha=ALPHA)
+    ref = grads(sim)
+    t = sim.autotune_gradient(shots[0], steps=12, ckpt_every=5)
+    print(f"[grad] tuned {t}", flush=True)
+    k = sim.kernel()
+    assert (k["variant"], k["tile_x"], k["tile_y"], k["zchunk"]) in Simulator.GRADIENT_CANDIDATES
+    assert len(t["tried"]) >= 2
+    for a, b in zip(ref, grads(sim)):
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+    sim.close()
+
+    sims = [Simulator(*model, H, DT, NT, sponge=SPONGE, sponge_alpha=ALPHA) for _ in shots]
+    batch = BatchSimulator(sims)
+    bt = batch.autotune_gradient(shots, steps=12, ckpt_every=5)
+    print(f"[grad] batched tuned {bt}", flush=True)
+    assert (*bt["tile"], bt["zchunk"]) in BatchSimulator.GRADIENT_CANDIDATES
+    assert all(x.kernel()["zchunk"] == bt["zchunk"] for x in sims)
+    gws = [x.grad_workspace(9) for x in sims]
+    g = [[torch.zeros(model[0].shape, device="cuda") for _ in shots] for _ in range(3)]
+    batch.gradient(shots, obs, *g, ckpt_every=9, gws=gws)
+    torch.cuda.synchronize()
+    for q in range(len(shots)):
+        for c in range(3):
+            assert torch.equal(g[c][q].cpu(), ref[q][c]), (q, c)
+    batch.close()
+    for x in sims:
+        x.close()
+
+
 def test_autograd_functions_agree(case):
     from paper_2112_15071_amd.fwi import Misfit, Traces
 
