@@ -10,7 +10,8 @@ Also reported (same JSON line):
   batched  -- the 24-shot uneven batch (128^3 .. 256x256x128, 1500 steps): per-shot loop
               vs one persistent launch per pass replayed from a hipGraph (Gcell-steps/s);
   gradient -- the 8-shot 256^3 FWI gradient (1500 steps, checkpoints every 50): per-shot
-              loop vs batched waves (shots/s);
+              loop vs batched waves (shots/s), each with the kernel configuration its
+              gradient tuner picks;
   roofline -- the dominant forward kernel's algorithmic bytes / its HIP-event duration;
   c2_forward -- the 512x512x256 free-surface workload (300 steps);
   stream_copy_gbs -- a plain 1 GiB device copy (read + write GB/s), the practical ceiling;
