@@ -498,8 +498,19 @@ bool window_ok(const fd3d_ctx *c, int zc)
     return (long)(zc + 8) * (long)c->n[0] * (long)c->n[1] * (long)c->tsize <= kMaxWindowBytes;
 }
 
+// Cache policy of a context's single-grid tile launches: the model arrays and the
+// gradient's stored states are streamed (non-temporal) when the grid's working set, nine
+// fields and three model arrays, exceeds the 256 MB Infinity Cache.  Below that the whole
+// working set can stay cached from step to step, and streaming would evict the model.
+constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
+inline bool stream_model(const fd3d_ctx *c)
+{
+    return 12.0 * (double)c->n[0] * (double)c->n[1] * (double)c->n[2] * (double)c->tsize > kInfinityCacheBytes;
+}
+
 // rec: receiver sampling carried by a forward stress launch (extra workgroups).
-template <typename T, int TX, int TY, bool FS>
+// NTP: cache policy of the model loads and stored states (see stream_model).
+template <typename T, int TX, int TY, bool FS, bool NTP>
 void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &tm, int pass, hipStream_t st,
                   const TileIO<T> &io = TileIO<T>{}, const RecJob<T> &rec = RecJob<T>{})
 {
@@ -510,23 +521,25 @@ void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &
     if (G.save[VX] != nullptr && pass == kPassStress) pass = kPassStressSave;
     if constexpr (!FS) {  // the vacuum surface has instantiations of its own (forward only)
         if (G.ks > 0 && pass == kPassVel) {
-            vel_tile<T, TX, TY, false, kFwd, true><<<nwg, NT, 0, st>>>(G, inj, n, tm);
+            vel_tile<T, TX, TY, false, kFwd, true, NTP><<<nwg, NT, 0, st>>>(G, inj, n, tm);
             return;
         }
         if (G.ks > 0 && pass == kPassStress) {
-            stress_tile<T, TX, TY, false, kFwd, true><<<nws, NT, 0, st>>>(G, inj, n, tm, rec);
+            stress_tile<T, TX, TY, false, kFwd, true, NTP><<<nws, NT, 0, st>>>(G, inj, n, tm, rec);
             return;
         }
     }
     switch (pass) {
-    case kPassVel: vel_tile<T, TX, TY, FS><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
-    case kPassStress: stress_tile<T, TX, TY, FS><<<nws, NT, 0, st>>>(G, inj, n, tm, rec); break;
-    case kPassVelSave: vel_tile<T, TX, TY, FS, kFwdSave><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
-    case kPassStressSave: stress_tile<T, TX, TY, FS, kFwdSave><<<nws, NT, 0, st>>>(G, inj, n, tm, rec); break;
-    case kPassStressA: stress_tile_adj<T, TX, TY, kAdjA><<<nwg, NT, 0, st>>>(G, inj, tm, io); break;
-    case kPassVelA: vel_tile_adj<T, TX, TY, kAdjA><<<nwg, NT, 0, st>>>(G, inj, n, tm, io); break;
-    case kPassVelB: vel_tile_adj<T, TX, TY, kAdjB><<<nwg, NT, 0, st>>>(G, inj, n, tm, io); break;
-    default: stress_tile_adj<T, TX, TY, kAdjB><<<nwg, NT, 0, st>>>(G, inj, tm, io); break;
+    case kPassVel: vel_tile<T, TX, TY, FS, kFwd, false, NTP><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
+    case kPassStress: stress_tile<T, TX, TY, FS, kFwd, false, NTP><<<nws, NT, 0, st>>>(G, inj, n, tm, rec); break;
+    case kPassVelSave: vel_tile<T, TX, TY, FS, kFwdSave, false, NTP><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
+    case kPassStressSave:
+        stress_tile<T, TX, TY, FS, kFwdSave, false, NTP><<<nws, NT, 0, st>>>(G, inj, n, tm, rec);
+        break;
+    case kPassStressA: stress_tile_adj<T, TX, TY, kAdjA, NTP><<<nwg, NT, 0, st>>>(G, inj, tm, io); break;
+    case kPassVelA: vel_tile_adj<T, TX, TY, kAdjA, NTP><<<nwg, NT, 0, st>>>(G, inj, n, tm, io); break;
+    case kPassVelB: vel_tile_adj<T, TX, TY, kAdjB, NTP><<<nwg, NT, 0, st>>>(G, inj, n, tm, io); break;
+    default: stress_tile_adj<T, TX, TY, kAdjB, NTP><<<nwg, NT, 0, st>>>(G, inj, tm, io); break;
     }
 }
 
@@ -546,7 +559,12 @@ void launch_pass(const fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int 
     }
     const TileMap tm = tile_map(c);
     with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
-        launch_tiles<T, decltype(tx)::value, decltype(ty)::value, FS>(G, inj, n, tm, pass, st, io, rec);
+        constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
+        // FP64 (the debug mode) keeps the plain policy and needs no second instantiation
+        if (sizeof(T) == 4 && stream_model(c))
+            launch_tiles<T, TX, TY, FS, sizeof(T) == 4>(G, inj, n, tm, pass, st, io, rec);
+        else
+            launch_tiles<T, TX, TY, FS, false>(G, inj, n, tm, pass, st, io, rec);
     });
 }
 
@@ -924,6 +942,7 @@ struct BatchGroup {
     int s0, ns, tiles, recs, wgs;
     int tx, ty, tx2, ty2;
     int vac;  // some shot of the group has a vacuum surface
+    int ntp;  // cache policy of the group's forward passes (see group_streams)
 };
 
 struct fd3d_batch {
@@ -990,6 +1009,22 @@ template <typename T, typename F> decltype(auto) with_batch_tiles(const BatchGro
 }
 
 // The batch's own tile shapes as one group covering every shot (counts not filled in).
+// Streaming (non-temporal) policy for the forward passes of a group of contexts, as
+// stream_model for one grid: FP32, the group's working sets add up to more than the
+// Infinity Cache, and no two of its shots share a model array (a shared model is re-read
+// by the other shots' tiles of the same launch).
+bool group_streams(const fd3d_ctx *const *ctx, int ns)
+{
+    if (ns < 1 || ctx[0]->tsize != 4) return false;
+    double bytes = 0.0;
+    for (int q = 0; q < ns; ++q) {
+        bytes += 12.0 * (double)ctx[q]->n[0] * (double)ctx[q]->n[1] * (double)ctx[q]->n[2] * (double)ctx[q]->tsize;
+        for (int r = 0; r < q; ++r)
+            if (ctx[q]->lam == ctx[r]->lam || ctx[q]->mu == ctx[r]->mu || ctx[q]->rho == ctx[r]->rho) return false;
+    }
+    return bytes > kInfinityCacheBytes;
+}
+
 BatchGroup whole_batch(const fd3d_batch *b)
 {
     BatchGroup g{};
@@ -999,6 +1034,7 @@ BatchGroup whole_batch(const fd3d_batch *b)
     g.ty = b->tile_y;
     g.tx2 = b->tile2_x;
     g.ty2 = b->tile2_y;
+    g.ntp = group_streams(b->ctx.data(), b->nshot);
     return g;
 }
 
@@ -1042,6 +1078,16 @@ int launch_multi(const BatchGroup &gr, const ShotFwd<T> *d, int n, int pass, hip
         }
         if (gr.vac && pass == kPassStress) {
             stress_tile_multi<T, TX, TY, TX2, TY2, false, kFwd, true><<<gs, NT, 0, st>>>(d, S, W, n, rec);
+            return FD3D_OK;
+        }
+    }
+    if constexpr (sizeof(T) == 4) {  // forward passes of a streaming group (see group_streams)
+        if (gr.ntp && pass == kPassVel) {
+            vel_tile_multi<T, TX, TY, TX2, TY2, FS, kFwd, false, true><<<g, NT, 0, st>>>(d, S, W, n);
+            return FD3D_OK;
+        }
+        if (gr.ntp && pass == kPassStress) {
+            stress_tile_multi<T, TX, TY, TX2, TY2, FS, kFwd, false, true><<<gs, NT, 0, st>>>(d, S, W, n, rec);
             return FD3D_OK;
         }
     }
@@ -1131,6 +1177,9 @@ void make_groups(fd3d_batch *b)
         int e = s + 1;
         while (e < b->nshot && bytes + shot_footprint(ctx_at(e)) <= b->group_bytes) bytes += shot_footprint(ctx_at(e++));
         g.ns = e - s;
+        std::vector<const fd3d_ctx *> members;
+        for (int q = s; q < e; ++q) members.push_back(ctx_at(q));
+        g.ntp = group_streams(members.data(), g.ns);
         const fd3d_ctx *c0 = ctx_at(s);
         bool same = c0->variant == FD3D_KERNEL_TILE;
         for (int q = s + 1; q < e && same; ++q)
@@ -1523,16 +1572,19 @@ int born_impl(fd3d_ctx *c, fd3d_ctx *dc, const fd3d_source *src, const void *dla
         for (int q = 0; q < 6; ++q) iosf.out[q] = D.f[SXX + q];
         iosf.acc[0] = (T *)dlam;
         iosf.acc[1] = (T *)dmu;
+        const bool ntp = sizeof(T) == 4 && stream_model(c);  // cache policy, as in launch_pass
         for (int n = 0; n < c->nt; ++n) {
             with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
                 constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
-                vel_tile_adj<T, TX, TY, kBornV><<<nwg, TX * TY, 0, st>>>(G, inj, n, tm, iovf);
+                if (ntp) vel_tile_adj<T, TX, TY, kBornV, sizeof(T) == 4><<<nwg, TX * TY, 0, st>>>(G, inj, n, tm, iovf);
+                else vel_tile_adj<T, TX, TY, kBornV><<<nwg, TX * TY, 0, st>>>(G, inj, n, tm, iovf);
             });
             launch_pass<T, false>(dc, D, dinj, n, kPassVel, st);
             with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
                 constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
-                stress_tile_born<T, TX, TY><<<nwg + rec_blocks(recg, TX * TY), TX * TY, 0, st>>>(G, inj, n, tm, iosf,
-                                                                                                  recg);
+                const int nb = nwg + rec_blocks(recg, TX * TY);
+                if (ntp) stress_tile_born<T, TX, TY, sizeof(T) == 4><<<nb, TX * TY, 0, st>>>(G, inj, n, tm, iosf, recg);
+                else stress_tile_born<T, TX, TY><<<nb, TX * TY, 0, st>>>(G, inj, n, tm, iosf, recg);
             });
             launch_pass<T, false>(dc, D, dinj, n, kPassStress, st, TileIO<T>{}, recd);
         }

@@ -80,6 +80,8 @@ __device__ __forceinline__ unsigned wplane(const Window &w, int kk, bool ok)
     return ok ? (unsigned)(kk - w.b0) * w.pb : kSkip;
 }
 
+constexpr int kNT = 2;  // buffer instruction cache policy: nt (non-temporal)
+
 __device__ __forceinline__ float bload(rsrc_t r, unsigned off, float)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
@@ -90,6 +92,28 @@ __device__ __forceinline__ double bload(rsrc_t r, unsigned off, double)
 }
 template <typename T> __device__ __forceinline__ T ld(rsrc_t r, unsigned off) { return bload(r, off, T(0)); }
 
+// Loads of the model arrays and stores of the gradient's recompute under a cache policy
+// chosen per launch (NTP, see stream_model on the host): with NTP they carry the
+// non-temporal bit (nt = 2 on gfx950).  The model arrays are read by one pass per step
+// each, and the recompute's (sigma^n, v^{n+1/2}) only by the adjoint, many steps later;
+// on grids whose working set exceeds the 256 MB Infinity Cache, streaming them leaves
+// more of it to the fields the next pass reads (256^3 forward 43.6-43.9 -> 44.7-45.0
+// Gcell-steps/s, stress pass 0.213 -> 0.204 ms; gradient -3.6 % per shot).  On grids that
+// fit, or when the shots of a batch share one model, the plain policy keeps the model
+// cached between uses.
+template <int AUX> __device__ __forceinline__ float bload_p(rsrc_t r, unsigned off, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+}
+template <int AUX> __device__ __forceinline__ double bload_p(rsrc_t r, unsigned off, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+}
+template <bool NTP, typename T> __device__ __forceinline__ T ldm(rsrc_t r, unsigned off)
+{
+    return bload_p<NTP ? kNT : 0>(r, off, T(0));
+}
+
 __device__ __forceinline__ void st(rsrc_t r, unsigned off, float v)
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
@@ -98,6 +122,14 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void st(rsrc_t r, unsigned off, double v)
 {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+template <bool NTP> __device__ __forceinline__ void stm(rsrc_t r, unsigned off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, NTP ? kNT : 0);
+}
+template <bool NTP> __device__ __forceinline__ void stm(rsrc_t r, unsigned off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, NTP ? kNT : 0);
 }
 
 // Uniform value through the scalar cache.
@@ -246,7 +278,7 @@ __device__ __forceinline__ void stage_coef(T *lds, const Inject<T> &src, bool on
 
 // ---------------------------------------------------------------------------------
 // (V) velocity pass, tiled.  Same arithmetic per sample as vel_cell.
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false>
 __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0, int k0,
                                               int k1, const TileIO<T> &io = TileIO<T>{})
 {
@@ -327,7 +359,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         const int kz = kfirst - 1 + m;
         qzz[m] = (FS && kz < 0) ? -zld(fzz, -kz, true) : zld(fzz, kz, true);
     }
-    T r0 = zld(rho, kfirst, use_rho), r1 = zld(rho, kfirst + 1, use_rho);
+    T r0 = ldm<NTP, T>(wfield(rho, w), oc + wplane(w, kfirst, use_rho));
+    T r1 = ldm<NTP, T>(wfield(rho, w), oc + wplane(w, kfirst + 1, use_rho));
     T dr0 = T(0), dr1 = T(0);
     if constexpr (born) {
         dr0 = zld(io.acc[0], kfirst, true);
@@ -363,7 +396,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         P.xz = ld<T>(bxz, hxz.off + pk);
         P.yy = ld<T>(byy, hyy.off + pk);
         P.yz = ld<T>(byz, hyz.off + pk);
-        P.r = ld<T>(br, hr.off + pr);
+        P.r = ldm<NTP, T>(br, hr.off + pr);
         if constexpr (born) P.dr = ld<T>(wfield(io.acc[0], w), hr.off + pr);
     };
     Plane P;
@@ -399,7 +432,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         const bool more = it + 1 < k1 - k0;
         loadplane(up ? k - 1 : k + 1, more, P);
         const T nxz = zld(fxz, up ? k - 3 : k + 2, more), nyz = zld(fyz, up ? k - 3 : k + 2, more);
-        const T nzz = zld(fzz, up ? k - 2 : k + 3, more), nr = zld(rho, up ? k - 1 : k + 2, more && use_rho);
+        const T nzz = zld(fzz, up ? k - 2 : k + 3, more), nr = ldm<NTP, T>(wfield(rho, w), oc + wplane(w, up ? k - 1 : k + 2, more && use_rho));
         const T ndr = born ? zld(io.acc[0], up ? k - 1 : k + 2, more) : T(0);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         // second order next to a vacuum surface: vx, vy at integer k, vz at k + 1/2 (only in
@@ -422,7 +455,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 if (srcv) v += bb * cf(VX, tap_of(src, VX, i, j, k)) * s;
                 v = v * (gxh * gyi * gz_i);
                 st(ovx, st_vx + pw, v);
-                if constexpr (MODE == kFwdSave) st(wfield(G.save[VX], w), st_vx + pw, v);
+                if constexpr (MODE == kFwdSave) stm<NTP>(wfield(G.save[VX], w), st_vx + pw, v);
             }
             if constexpr (born) {
                 const T bb = buoy(r0, Lr[ty * WR + tx + 1]);
@@ -453,7 +486,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 if (srcv) v += bb * cf(VY, tap_of(src, VY, i, j, k)) * s;
                 v = v * (gxi * gyh * gz_i);
                 st(ovy, st_vy + pw, v);
-                if constexpr (MODE == kFwdSave) st(wfield(G.save[VY], w), st_vy + pw, v);
+                if constexpr (MODE == kFwdSave) stm<NTP>(wfield(G.save[VY], w), st_vy + pw, v);
             }
             if constexpr (born) {
                 const T bb = buoy(r0, Lr[(ty + 1) * WR + tx]);
@@ -485,7 +518,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 if (srcv) v += bb * cf(VZ, tap_of(src, VZ, i, j, k)) * s;
                 v = v * (gxi * gyi * gz_h);
                 st(ovz, st_vz + pw, v);
-                if constexpr (MODE == kFwdSave) st(wfield(G.save[VZ], w), st_vz + pw, v);
+                if constexpr (MODE == kFwdSave) stm<NTP>(wfield(G.save[VZ], w), st_vz + pw, v);
             }
             if constexpr (born) {
                 const T bb = buoy(r0, r1);
@@ -522,7 +555,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 
 // ---------------------------------------------------------------------------------
 // (S) stress pass, tiled.  Same arithmetic per sample as stress_cell.
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false>
 __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0,
                                                  int k0, int k1, const TileIO<T> &io = TileIO<T>{})
 {
@@ -609,8 +642,8 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const unsigned pk = wplane(w, kk, ok), o = oc + pk, om_ = oc + wplane(w, kk, ok && use_model);
         const rsrc_t bx = wfield(fvx, w), by = wfield(fvy, w), bz = wfield(fvz, w);
-        P.cl = ld<T>(wfield(lam, w), om_);
-        P.cm = ld<T>(wfield(mu, w), om_);
+        P.cl = ldm<NTP, T>(wfield(lam, w), om_);
+        P.cm = ldm<NTP, T>(wfield(mu, w), om_);
         if constexpr (MODE == kAdjA) {
             P.a0 = ld<T>(wfield(io.acc[0], w), o);
             P.a1 = ld<T>(wfield(io.acc[1], w), o);
@@ -638,7 +671,9 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             P.b5 = ld<T>(wfield(io.out[5], w), o);
         }
     };
-    auto loadmu = [&](int kk, bool ok) -> T { return ld<T>(wfield(mu, w), hm.off + wplane(w, kk, ok && use_model)); };
+    auto loadmu = [&](int kk, bool ok) -> T {
+        return ldm<NTP, T>(wfield(mu, w), hm.off + wplane(w, kk, ok && use_model));
+    };
     auto loaddmu = [&](int kk, bool ok) -> T { return ld<T>(wfield(io.acc[1], w), hm.off + wplane(w, kk, ok)); };
 
     Plane P;
@@ -708,12 +743,12 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         __syncthreads();
 
         if constexpr (MODE == kFwdSave) {
-            st(wfield(G.save[SXX], w), oc + pw, o_xx);
-            st(wfield(G.save[SYY], w), oc + pw, o_yy);
-            st(wfield(G.save[SZZ], w), oc + pw, o_zz);
-            st(wfield(G.save[SXY], w), oc + pw, o_xy);
-            st(wfield(G.save[SXZ], w), oc + pw, o_xz);
-            st(wfield(G.save[SYZ], w), oc + pw, o_yz);
+            stm<NTP>(wfield(G.save[SXX], w), oc + pw, o_xx);
+            stm<NTP>(wfield(G.save[SYY], w), oc + pw, o_yy);
+            stm<NTP>(wfield(G.save[SZZ], w), oc + pw, o_zz);
+            stm<NTP>(wfield(G.save[SXY], w), oc + pw, o_xy);
+            stm<NTP>(wfield(G.save[SXZ], w), oc + pw, o_xz);
+            stm<NTP>(wfield(G.save[SYZ], w), oc + pw, o_yz);
         }
         const T exx = dstag(Lx[ovx], Lx[ovx - 1], Lx[ovx + 1], Lx[ovx - 2], rdx);
         const T eyy = dstag(Ly[ovy], Ly[ovy - W3], Ly[ovy + W3], Ly[ovy - 2 * W3], rdy);
@@ -818,17 +853,17 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
 
 // ---------------------------------------------------------------------------------
 // Single-grid launches: one workgroup per tile (MODE kFwd or kFwdSave).
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false>
 __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
 {
     int i0, j0, k0, k1;
     tile_coords(tm, tile_of(blockIdx.x, gridDim.x, vel_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
-    vel_tile_body<T, TX, TY, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1);
+    vel_tile_body<T, TX, TY, FS, MODE, VAC, NTP>(G, src, n, i0, j0, k0, k1);
 }
 
 // The stress pass only reads v^{n+1/2}, so workgroups past the grid's tiles sample the
 // receivers of the step (rec.nq work items) in the same launch.
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false>
 __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, int n, TileMap tm, RecJob<T> rec)
 {
     const int nwg = tm.ntx * tm.nty * tm.nzc;
@@ -839,13 +874,13 @@ __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, 
     }
     int i0, j0, k0, k1;
     tile_coords(tm, tile_of(blockIdx.x, nwg, stress_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
-    stress_tile_body<T, TX, TY, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1);
+    stress_tile_body<T, TX, TY, FS, MODE, VAC, NTP>(G, src, n, i0, j0, k0, k1);
 }
 
 // Born stress pass (kBornS): the background's stress update and the perturbation's
 // stress term in one sweep; the workgroups past the tiles sample the background's
 // receivers.
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, bool NTP = false>
 __global__ void __launch_bounds__(TX *TY) stress_tile_born(Grid<T> G, Inject<T> src, int n, TileMap tm, TileIO<T> io,
                                                            RecJob<T> rec)
 {
@@ -857,24 +892,24 @@ __global__ void __launch_bounds__(TX *TY) stress_tile_born(Grid<T> G, Inject<T> 
     }
     int i0, j0, k0, k1;
     tile_coords(tm, tile_of(blockIdx.x, nwg, stress_sweeps_up<kBornS>()), i0, j0, k0, k1, TX, TY, G.nz);
-    stress_tile_body<T, TX, TY, false, kBornS>(G, src, n, i0, j0, k0, k1, io);
+    stress_tile_body<T, TX, TY, false, kBornS, false, NTP>(G, src, n, i0, j0, k0, k1, io);
 }
 
 // Adjoint passes, one workgroup per tile (no free surface).
-template <typename T, int TX, int TY, int MODE>
+template <typename T, int TX, int TY, int MODE, bool NTP = false>
 __global__ void __launch_bounds__(TX *TY) vel_tile_adj(Grid<T> G, Inject<T> src, int n, TileMap tm, TileIO<T> io)
 {
     int i0, j0, k0, k1;
     tile_coords(tm, tile_of(blockIdx.x, gridDim.x, vel_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
-    vel_tile_body<T, TX, TY, false, MODE>(G, src, n, i0, j0, k0, k1, io);
+    vel_tile_body<T, TX, TY, false, MODE, false, NTP>(G, src, n, i0, j0, k0, k1, io);
 }
 
-template <typename T, int TX, int TY, int MODE>
+template <typename T, int TX, int TY, int MODE, bool NTP = false>
 __global__ void __launch_bounds__(TX *TY) stress_tile_adj(Grid<T> G, Inject<T> src, TileMap tm, TileIO<T> io)
 {
     int i0, j0, k0, k1;
     tile_coords(tm, tile_of(blockIdx.x, gridDim.x, stress_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
-    stress_tile_body<T, TX, TY, false, MODE>(G, src, 0, i0, j0, k0, k1, io);
+    stress_tile_body<T, TX, TY, false, MODE, false, NTP>(G, src, 0, i0, j0, k0, k1, io);
 }
 
 // ---------------------------------------------------------------------------------
@@ -909,7 +944,7 @@ template <typename D> constexpr int base_stride() { return (int)(sizeof(D) / siz
 // A batch may use a second tile shape with the same workgroup size (TX2 x TY2, 0: none)
 // for the shots whose descriptor sets `alt`, so that grids of different widths all get a
 // tile shape that covers them without idle columns.
-template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd, bool VAC = false>
+template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false>
 __global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
                                                           int n)
 {
@@ -930,20 +965,20 @@ __global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__res
         if constexpr (TX2 != 0) {
             if (d.alt) {
                 tile_coords(tm, w - d.base, i0, j0, k0, k1, TX2, TY2, G.nz);
-                vel_tile_body<T, TX2, TY2, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1, io);
+                vel_tile_body<T, TX2, TY2, FS, MODE, VAC, NTP>(G, src, n, i0, j0, k0, k1, io);
                 __syncthreads();
                 continue;
             }
         }
         tile_coords(tm, w - d.base, i0, j0, k0, k1, TX, TY, G.nz);
-        vel_tile_body<T, TX, TY, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1, io);
+        vel_tile_body<T, TX, TY, FS, MODE, VAC, NTP>(G, src, n, i0, j0, k0, k1, io);
         __syncthreads();
     }
 }
 
 // Workgroups past rec.wgs sample the receivers of the step (the stress pass only reads
 // the velocity).
-template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd, bool VAC = false>
+template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false>
 __global__ void __launch_bounds__(TX *TY) stress_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
                                                           int n, RecMulti<T> rec)
 {
@@ -968,13 +1003,13 @@ __global__ void __launch_bounds__(TX *TY) stress_tile_multi(const ShotFwd<T> *__
         if constexpr (TX2 != 0) {
             if (d.alt) {
                 tile_coords(tm, w - d.base, i0, j0, k0, k1, TX2, TY2, G.nz);
-                stress_tile_body<T, TX2, TY2, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1, io);
+                stress_tile_body<T, TX2, TY2, FS, MODE, VAC, NTP>(G, src, n, i0, j0, k0, k1, io);
                 __syncthreads();
                 continue;
             }
         }
         tile_coords(tm, w - d.base, i0, j0, k0, k1, TX, TY, G.nz);
-        stress_tile_body<T, TX, TY, FS, MODE, VAC>(G, src, n, i0, j0, k0, k1, io);
+        stress_tile_body<T, TX, TY, FS, MODE, VAC, NTP>(G, src, n, i0, j0, k0, k1, io);
         __syncthreads();
     }
 }
