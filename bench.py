@@ -1,36 +1,49 @@
 """Benchmark of the elastic FD hot path on one MI355X.
 
 Headline (``value``): forward throughput in Gcell-steps/s on the 256^3 six-layer +
-5 % Gaussian-perturbed model (h 10 m, dt 0.5 ms, 2000 steps), random moment-tensor
-source, 12 Hz Ricker, 256 receivers, 20-cell sponge, FP32.  A "step" is one time step of
-the whole forward path: velocity pass (force source, damping), then the stress pass
-(moment source, damping) whose launch also samples the receivers.
+5 % Gaussian-perturbed model (h 10 m, dt 0.5 ms, random moment-tensor source, 12 Hz
+Ricker, 256 receivers, 20-cell sponge, FP32), over exactly ``--steps`` time steps, the
+median of five timed runs.  A "step" is one time step of the whole forward path: the
+velocity pass (force source, damping), then the stress pass (moment source, damping)
+whose launch also samples the receivers.  Each timed run starts from a zero state that
+is set before the clock starts.
 
-Also reported (same JSON line):
-  batched  -- the 24-shot uneven batch (128^3 .. 256x256x128, 1500 steps): per-shot loop
-              vs one persistent launch per pass replayed from a hipGraph (Gcell-steps/s);
+Also reported (same JSON line; a section that fails records {"error": ...} and the line
+is still printed):
+  c1_full  -- the same workload over its full 2000 steps (median of 3);
+  roofline -- the dominant forward kernel's algorithmic bytes / its HIP-event duration,
+              both passes separately, and the whole step;
+  c2_forward -- the 512x512x256 free-surface workload over 1000 of its 4000 steps
+              (median of 3; the cost per step does not depend on the step);
+  stream_copy_gbs -- a plain 1 GiB device copy (read + write GB/s);
+  batched_forward -- the 24-shot uneven batch (128^3 .. 256x256x128, 1500 steps):
+              per-shot loop vs cache-blocked groups replayed from a hipGraph (median of 3
+              each), and the lockstep schedule once;
   gradient -- the 8-shot 256^3 FWI gradient (1500 steps, checkpoints every 50): per-shot
-              loop vs batched waves (shots/s), each with the kernel configuration its
-              gradient tuner picks;
-  roofline -- the dominant forward kernel's algorithmic bytes / its HIP-event duration;
-  c2_forward -- the 512x512x256 free-surface workload (300 steps);
-  stream_copy_gbs -- a plain 1 GiB device copy (read + write GB/s), the practical ceiling;
-  born     -- the tangent-linear (Born) forward on the 256^3 model, 300 steps;
+              loop vs batched waves (shots/s, with the median per-shot and per-wave
+              times), each with the kernel configuration its gradient tuner picks, and
+              the fraction of the HBM roofline at the bytes the kernels move;
   levels   -- the paper's Table 5 level sweep (64x64x32 .. 512^3, anisotropic cells) on
               its case-study medium (seven layers under 30 km of air: vacuum surface),
               upsampled from one coarse grid to every level, 100 timed steps per level;
+  born     -- the tangent-linear (Born) forward on the 256^3 model, 300 steps;
+  paper_table6 -- the paper's own GLSL and CPU totals per level, with their hardware
+              (context only, not a target);
   cpu_baseline -- the FP64 oracle on a bounded sample on this host's cores (and, as
               one_core, on a single core over an eighth of the steps).
 
-    python bench.py [--steps 2000] [--warmup 100] [--gpus 1] [--no-batch] [--no-grad] [--no-levels]
+    python bench.py [--steps 20] [--warmup 5] [--gpus 1] [--no-c2] [--no-batch] [--no-grad]
+                    [--no-levels] [--no-born] [--cpu-steps 24]
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
+import traceback
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -51,12 +64,35 @@ def step_bytes(kern):
     if kern["variant"] == "fused":
         return BYTES_PER_CELL["fused"]
     return BYTES_PER_CELL["velocity"] + BYTES_PER_CELL["stress"]
+
+
 # gradient, per shot and time step: forward with checkpoints (120), segment recompute
 # storing v^{n+1/2} and sigma^n (156), the four adjoint passes: stress-A 27 fields,
 # velocity-A 12, velocity-B 19, stress-B 15 (292)
 GRAD_BYTES_PER_CELL_STEP = 120 + 156 + 4 * (27 + 12 + 19 + 15)
+# the design figure with eight staggered-point accumulators and no hand-over fields
+# between the adjoint passes (forward 120 + recompute 156 + adjoint 232)
+GRAD_BYTES_DESIGN = 120 + 156 + 232
 # measured counter calibration (plain 1 GiB copy): FETCH_SIZE reads 0.5x, WRITE_SIZE 1.0x
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
+
+# The paper's Table 6: total time of one simulation per level of detail, its GLSL shaders
+# on the Vega iGPU of a Ryzen 7 4700U notebook (24 GB DDR4) against its NumPy/OpenBLAS
+# CPU implementation on the same notebook; grids and step counts from its Table 5.
+# (level, (nx, ny, nz), steps, CPU seconds, GPU seconds)
+PAPER_TABLE6 = [
+    (0, (64, 64, 32), 1700, 10, 3),
+    (1, (64, 64, 64), 1700, 40, 4),
+    (2, (128, 64, 64), 1700, 113, 7),
+    (3, (128, 128, 64), 1700, 221, 18),
+    (4, (128, 128, 128), 3400, 850, 122),
+    (5, (256, 128, 128), 3400, 1666, 136),
+    (6, (256, 256, 128), 3400, 3502, 295),
+    (7, (256, 256, 256), 17000, 36210, 2890),
+    (8, (512, 256, 256), 17000, 73950, 5100),
+    (9, (512, 512, 256), 17000, 158270, 14450),
+    (10, (512, 512, 512), 17000, 372470, 29750),
+]
 
 
 def log(*a):
@@ -67,6 +103,21 @@ def sync():
     import torch
 
     torch.cuda.synchronize()
+
+
+def median_time(fn, reps, prep=None):
+    """Median wall time of ``reps`` runs of fn (each bracketed by device syncs; ``prep``
+    runs before each, outside the clock).  Returns (median s, list of s)."""
+    ts = []
+    for _ in range(reps):
+        if prep is not None:
+            prep()
+        sync()
+        t0 = time.perf_counter()
+        fn()
+        sync()
+        ts.append(time.perf_counter() - t0)
+    return statistics.median(ts), ts
 
 
 def shot_desc(s):
@@ -95,46 +146,89 @@ def measured_traffic(kern, dom):
         return None
 
 
-def bench_forward(K, Wm, kernel=None):
+class Forward:
+    """The 256^3 workload on the GPU: model, simulator with its tuned kernel, zero state."""
+
+    def __init__(self, nt_max, kernel=None):
+        import torch
+
+        import workloads as W
+        from paper_2112_15071_amd import Simulator
+
+        self.dev = torch.device("cuda:0")
+        self.shot = W.c1(nt=nt_max)
+        nx, ny, nz = self.shot.shape
+        self.cells = nx * ny * nz
+        self.model = [torch.as_tensor(a, dtype=torch.float32).to(self.dev)
+                      for a in (self.shot.lam, self.shot.mu, self.shot.rho)]
+        self.wav = torch.as_tensor(self.shot.wavelet, dtype=torch.float32).to(self.dev)
+        self.zero = torch.zeros((9, nz, ny, nx), dtype=torch.float32, device=self.dev)
+        self.sims = {}
+        self.kernel = kernel
+        self.Simulator = Simulator
+
+    def sim(self, K):
+        """Simulator of K steps with the tuned (or given) kernel configuration."""
+        if K not in self.sims:
+            s = self.Simulator(*self.model, self.shot.h, self.shot.dt, K, dtype=self.model[0].dtype,
+                               sponge=self.shot.sponge, device=self.dev)
+            if not self.sims:
+                if self.kernel:
+                    variant, tx, ty, zc = self.kernel.split(",")
+                    s.set_kernel(variant, int(ty), int(zc), int(tx))
+                    log(f"[bench] kernel {s.kernel()} (given)")
+                else:
+                    tune = s.autotune(steps=20)
+                    log(f"[bench] kernel {s.kernel()} (autotune {'cached' if tune['cached'] else 'run'})")
+                self.kernel_cfg = s.kernel()
+            else:
+                k = self.kernel_cfg
+                s.set_kernel(k["variant"], k["tile_y"], k["zchunk"], k["tile_x"])
+            self.sims[K] = s
+        return self.sims[K]
+
+    def run(self, K, traces, profile=False):
+        sim = self.sim(K)
+        sh = self.shot
+        sim.forward(sh.src_pos, sh.moment, sh.force, self.wav[:K], sh.rec_pos, keep_state=True, traces=traces)
+
+    def timed(self, K, reps):
+        import torch
+
+        sim = self.sim(K)
+        traces = torch.empty((self.shot.rec_pos.shape[0], 3, K), dtype=torch.float32, device=self.dev)
+        self.run(K, traces)  # warm-up of this simulator
+        return median_time(lambda: self.run(K, traces), reps, prep=lambda: sim.set_state(self.zero))
+
+    def close(self):
+        for s in self.sims.values():
+            s.close()
+        self.sims = {}
+
+
+def bench_forward(fw, K, Wm, reps=5):
+    """Headline: K steps, median of reps runs (after Wm warm-up steps), then the same K
+    steps once more with per-kernel HIP events on the launch stream."""
     import torch
 
-    import workloads as W
-    from paper_2112_15071_amd import Simulator, _abi
+    from paper_2112_15071_amd import _abi
 
-    dev = torch.device("cuda:0")
     log(f"[bench] 256^3 workload: steps {K}, warmup {Wm}")
-    shot = W.c1(nt=max(K, Wm))
-    nx, ny, nz = shot.shape
-    cells = nx * ny * nz
-    lam, mu, rho = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (shot.lam, shot.mu, shot.rho))
-    wav = torch.as_tensor(shot.wavelet, dtype=torch.float32).to(dev)
-    kw = dict(dtype=torch.float32, sponge=shot.sponge, device=dev)
-    sim = Simulator(lam, mu, rho, shot.h, shot.dt, K, **kw)
-    if kernel:
-        variant, tx, ty, zc = kernel.split(",")
-        sim.set_kernel(variant, int(ty), int(zc), int(tx))
-        log(f"[bench] kernel {sim.kernel()} (given)")
-    else:
-        tune = sim.autotune(steps=20)
-        log(f"[bench] kernel {sim.kernel()} (autotune {'cached' if tune['cached'] else 'run'})")
+    sim = fw.sim(K)
     if Wm > 0:
-        warm = Simulator(lam, mu, rho, shot.h, shot.dt, Wm, **kw)
-        k = sim.kernel()
-        warm.set_kernel(k["variant"], k["tile_y"], k["zchunk"], k["tile_x"])
-        warm.forward(shot.src_pos, shot.moment, shot.force, wav[:Wm], shot.rec_pos)
+        warm = fw.sim(Wm)
+        tr = torch.empty((fw.shot.rec_pos.shape[0], 3, Wm), dtype=torch.float32, device=fw.dev)
+        warm.set_state(fw.zero)
+        fw.run(Wm, tr)
         sync()
-        warm.close()
-    traces = torch.empty((shot.rec_pos.shape[0], 3, K), dtype=torch.float32, device=dev)
-    sync()
-    t0 = time.perf_counter()
-    sim.forward(shot.src_pos, shot.moment, shot.force, wav[:K], shot.rec_pos, traces=traces)
-    sync()
-    elapsed = time.perf_counter() - t0
-    gcs = cells * K / elapsed / 1e9
-    log(f"[bench] forward {elapsed:.3f} s -> {gcs:.2f} Gcell-steps/s")
-    # the same run again with per-kernel HIP events on the launch stream
+    el, ts = fw.timed(K, reps)
+    gcs = fw.cells * K / el / 1e9
+    log(f"[bench] forward {K} steps: median {el * 1e3:.3f} ms of {[round(t * 1e3, 3) for t in ts]} "
+        f"-> {gcs:.2f} Gcell-steps/s")
+    traces = torch.empty((fw.shot.rec_pos.shape[0], 3, K), dtype=torch.float32, device=fw.dev)
+    sim.set_state(fw.zero)
     _abi.fd3d_profile(sim.ctx, True)
-    sim.forward(shot.src_pos, shot.moment, shot.force, wav[:K], shot.rec_pos, traces=traces)
+    fw.run(K, traces)
     ms, launches = _abi.fd3d_profile_read(sim.ctx)
     sync()
     _abi.fd3d_profile(sim.ctx, False)
@@ -144,49 +238,69 @@ def bench_forward(K, Wm, kernel=None):
         dom = "fused"
     else:
         dom = "stress" if per["stress"] >= per["velocity"] else "velocity"
-    bytes_launch = BYTES_PER_CELL[dom] * cells
-    achieved = bytes_launch / (per[dom] * 1e-3) / 1e9
-    both = step_bytes(sim.kernel()) * cells * K / (elapsed * 1e9)
-    log(f"[bench] avg kernel ms {per}; dominant {dom} {achieved:.0f} GB/s; whole step {both:.0f} GB/s")
     kern = sim.kernel()
-    sim.close()
-    return shot, dict(gcs=gcs, elapsed=elapsed, per=per, dom=dom, achieved=achieved, bytes_launch=bytes_launch,
-                      both=both, kernel=kern, traffic=measured_traffic(kern, dom))
+    per_kernel = {}
+    for name, t in per.items():
+        if name in BYTES_PER_CELL:
+            gbs = BYTES_PER_CELL[name] * fw.cells / (t * 1e-3) / 1e9
+            per_kernel[name] = dict(avg_ms=round(t, 5), achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+    step_ms = sum(per[n] for n in per if n in BYTES_PER_CELL)
+    events_gbs = step_bytes(kern) * fw.cells / (step_ms * 1e-3) / 1e9
+    wall_gbs = step_bytes(kern) * fw.cells * K / (el * 1e9)
+    log(f"[bench] avg kernel ms {per}; dominant {dom} {per_kernel[dom]['achieved_gbs']:.0f} GB/s; "
+        f"whole step {events_gbs:.0f} GB/s (events), {wall_gbs:.0f} GB/s (wall)")
+    return dict(gcs=gcs, elapsed=el, times=ts, per=per, per_kernel=per_kernel, dom=dom, kernel=kern,
+                bytes_launch=BYTES_PER_CELL[dom] * fw.cells, events_gbs=events_gbs, wall_gbs=wall_gbs,
+                traffic=measured_traffic(kern, dom))
 
 
-def bench_c2(K=300):
-    """The 512 x 512 x 256 free-surface workload (30-cell sponge on five faces), K steps."""
+def bench_c1_full(fw, K=2000, reps=3):
+    """The 256^3 workload over its full 2000 steps."""
+    el, ts = fw.timed(K, reps)
+    gcs = fw.cells * K / el / 1e9
+    gbs = step_bytes(fw.kernel_cfg) * fw.cells * K / el / 1e9
+    log(f"[bench] forward {K} steps: median {el:.4f} s of {[round(t, 4) for t in ts]} -> {gcs:.2f} Gcell-steps/s, "
+        f"{gbs:.0f} GB/s")
+    fw.sims.pop(K).close()
+    return dict(gcs=round(gcs, 3), steps=K, seconds=round(el, 4), seconds_all=[round(t, 4) for t in ts],
+                hbm_gbs_whole_step=round(gbs, 1), hbm_frac_whole_step=round(gbs / HBM_PEAK_GBS, 4))
+
+
+def bench_c2(K=1000, reps=3):
+    """The 512 x 512 x 256 free-surface workload (30-cell sponge on five faces): K of its
+    4000 steps, median of reps runs from a zero state."""
     import torch
 
     import workloads as W
     from paper_2112_15071_amd import Simulator
 
     dev = torch.device("cuda:0")
-    log(f"[bench] 512x512x256 free-surface workload: {K} steps")
+    log(f"[bench] 512x512x256 free-surface workload: {K} of 4000 steps")
     shot = W.c2(nt=K)
     lam, mu, rho = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (shot.lam, shot.mu, shot.rho))
     wav = torch.as_tensor(shot.wavelet, dtype=torch.float32).to(dev)
     sim = Simulator(lam, mu, rho, shot.h, shot.dt, K, sponge=shot.sponge, free_surface=True, device=dev)
     sim.autotune(steps=10)
     traces = torch.empty((shot.rec_pos.shape[0], 3, K), dtype=torch.float32, device=dev)
-    sim.forward(shot.src_pos, shot.moment, shot.force, wav, shot.rec_pos, traces=traces)  # warm-up
-    sync()
-    t0 = time.perf_counter()
-    sim.forward(shot.src_pos, shot.moment, shot.force, wav, shot.rec_pos, traces=traces)
-    sync()
-    el = time.perf_counter() - t0
+    nx, ny, nz = shot.shape
+    zero = torch.zeros((9, nz, ny, nx), dtype=torch.float32, device=dev)
+    run = lambda: sim.forward(shot.src_pos, shot.moment, shot.force, wav, shot.rec_pos, keep_state=True,
+                              traces=traces)
+    sim.set_state(zero)
+    run()  # warm-up
+    el, ts = median_time(run, reps, prep=lambda: sim.set_state(zero))
     kern = sim.kernel()
     sim.close()
     gcs = shot.cells * K / el / 1e9
     gbs = step_bytes(kern) * shot.cells * K / el / 1e9
-    log(f"[bench] c2: {el:.3f} s -> {gcs:.2f} Gcell-steps/s, {gbs:.0f} GB/s")
-    return dict(gcs=round(gcs, 3), steps=K, seconds=round(el, 4), kernel=kern, hbm_gbs_whole_step=round(gbs, 1),
-                hbm_frac_whole_step=round(gbs / HBM_PEAK_GBS, 4))
+    log(f"[bench] c2: median {el:.3f} s of {[round(t, 3) for t in ts]} -> {gcs:.2f} Gcell-steps/s, {gbs:.0f} GB/s")
+    return dict(gcs=round(gcs, 3), steps=K, of_steps=4000, seconds=round(el, 4), seconds_all=[round(t, 4) for t in ts],
+                kernel=kern, hbm_gbs_whole_step=round(gbs, 1), hbm_frac_whole_step=round(gbs / HBM_PEAK_GBS, 4))
 
 
 def stream_copy_ceiling(reps=20):
     """Device-to-device copy of 1 GiB with torch, timed with HIP events on the current
-    stream: read + write bytes per second (the practical HBM ceiling of a plain stream)."""
+    stream: read + write bytes per second (a plain stream's rate)."""
     import torch
 
     n = 1 << 28
@@ -204,7 +318,7 @@ def stream_copy_ceiling(reps=20):
     return round(gbs, 1)
 
 
-def bench_batch():
+def bench_batch(reps=3):
     import torch
 
     import workloads as W
@@ -219,38 +333,31 @@ def bench_batch():
     tune = batch.autotune(steps=10)
     descs = [shot_desc(s) for s in shots]
     traces = [torch.empty((len(s.rec_pos), 3, s.nt), device="cuda") for s in shots]
-    # plain per-shot loop (each shot with its own tuned kernel)
-    for sim, d, tr in zip(sims, descs, traces):
-        sim.forward(**d, traces=tr)
-    sync()
-    t0 = time.perf_counter()
-    for sim, d, tr in zip(sims, descs, traces):
-        sim.forward(**d, traces=tr)
-    sync()
-    t_loop = time.perf_counter() - t0
-    batch.forward(descs, use_graph=True, traces=traces)  # capture + first replay
-    sync()
-    t0 = time.perf_counter()
-    batch.forward(descs, use_graph=True, traces=traces)
-    sync()
-    t_graph = time.perf_counter() - t0
-    log(f"[bench] batch: loop {t_loop:.3f} s, graph {t_graph:.3f} s (group budget {tune['group_mib']} MiB)")
+
+    def loop():  # plain per-shot loop (each shot with its own tuned kernel)
+        for sim, d, tr in zip(sims, descs, traces):
+            sim.forward(**d, traces=tr)
+
+    loop()
+    t_loop, ts_loop = median_time(loop, reps)
+    graph = lambda: batch.forward(descs, use_graph=True, traces=traces)
+    graph()  # capture + first replay
+    t_graph, ts_graph = median_time(graph, reps)
+    log(f"[bench] batch: loop median {t_loop:.3f} s {[round(t, 3) for t in ts_loop]}, graph median {t_graph:.3f} s "
+        f"{[round(t, 3) for t in ts_graph]} (group budget {tune['group_mib']} MiB)")
     t_lock = t_graph
     if tune["group_mib"]:
         # the lockstep schedule with the same tile shapes, for comparison
         batch.set_schedule(0)
-        batch.forward(descs, use_graph=True, traces=traces)
-        sync()
-        t0 = time.perf_counter()
-        batch.forward(descs, use_graph=True, traces=traces)
-        sync()
-        t_lock = time.perf_counter() - t0
+        graph()
+        t_lock, _ = median_time(graph, 1)
         log(f"[bench] batch lockstep: graph {t_lock:.3f} s")
     batch.close()
     for s in sims:
         s.close()
     return dict(loop_gcs=round(cells_steps / t_loop / 1e9, 3), batched_gcs=round(cells_steps / t_graph / 1e9, 3),
                 loop_s=round(t_loop, 3), batched_s=round(t_graph, 3), speedup=round(t_loop / t_graph, 3),
+                loop_s_all=[round(t, 3) for t in ts_loop], batched_s_all=[round(t, 3) for t in ts_graph],
                 lockstep_gcs=round(cells_steps / t_lock / 1e9, 3), group_mib=tune["group_mib"],
                 tile=[tune["tile_x"], tune["tile_y"]], tile2=[tune["tile2_x"], tune["tile2_y"]],
                 workgroups=tune["workgroups"], cell_steps=cells_steps)
@@ -285,18 +392,15 @@ def bench_born(K=300):
     args = dict(src_pos=shot.src_pos, moment=shot.moment, force=shot.force, wavelet=shot.wavelet[:K],
                 rec_pos=shot.rec_pos)
     sim.born(*dm, **args)
-    sync()
-    t0 = time.perf_counter()
-    sim.born(*dm, **args)
-    sync()
-    el = time.perf_counter() - t0
+    el, ts = median_time(lambda: sim.born(*dm, **args), 3)
     cells = nx * ny * nz
     gbs = BORN_BYTES_PER_CELL_STEP * cells * K / el / 1e9
-    log(f"[bench] born: {K} steps in {el:.3f} s -> {cells * K / el / 1e9:.2f} Gcell-steps/s, {gbs:.0f} GB/s")
+    log(f"[bench] born: {K} steps, median {el:.3f} s -> {cells * K / el / 1e9:.2f} Gcell-steps/s, {gbs:.0f} GB/s")
     kern = sim.kernel()
     sim.close()
     return dict(gcs=round(cells * K / el / 1e9, 3), ms_per_step=round(el / K * 1e3, 4), steps=K, kernel=kern,
-                bytes_per_cell_step=BORN_BYTES_PER_CELL_STEP, hbm_gbs=round(gbs, 1))
+                bytes_per_cell_step=BORN_BYTES_PER_CELL_STEP, hbm_gbs=round(gbs, 1),
+                hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
 
 
 # The paper's levels of detail (Table 5): grid (nx, ny, nz), cell size (km per axis), dt (s),
@@ -377,33 +481,30 @@ def bench_levels(K=100):
         rec = W.receiver_grid(np.linspace(12, nx - 13, 4), np.linspace(12, ny - 13, 4), ks + 1.0)
         wav = torch.as_tensor(W.ricker(0.05 if lev < 3 else 0.1, K, dt), dtype=torch.float32, device=dev)
         traces = torch.empty((len(rec), 3, K), dtype=torch.float32, device=dev)
-        sim.forward(src, W.explosion(1e15), (0.0, 0.0, 0.0), wav, rec, traces=traces)
-        sync()
-        t0 = time.perf_counter()
-        sim.forward(src, W.explosion(1e15), (0.0, 0.0, 0.0), wav, rec, traces=traces)
-        sync()
-        el = time.perf_counter() - t0
+        run = lambda: sim.forward(src, W.explosion(1e15), (0.0, 0.0, 0.0), wav, rec, traces=traces)
+        run()
+        el, _ = median_time(run, 3)
         batch = BatchSimulator([sim])
         batch.set_schedule(1 << 50)  # one group: the shot's own kernel shape
         desc = [dict(src_pos=src, moment=W.explosion(1e15), wavelet=wav, rec_pos=rec)]
-        batch.forward(desc, use_graph=True, traces=[traces])  # capture + first replay
-        sync()
-        t0 = time.perf_counter()
-        batch.forward(desc, use_graph=True, traces=[traces])
-        sync()
-        el_g = time.perf_counter() - t0
+        graph = lambda: batch.forward(desc, use_graph=True, traces=[traces])
+        graph()  # capture + first replay
+        el_g, _ = median_time(graph, 3)
         batch.close()
         cells = nx * ny * nz
         best = min(el, el_g)
         st = sim.state()
         finite = bool(torch.isfinite(st).all()) and bool(torch.isfinite(traces).all()) and float(st.abs().max()) > 0.0
         del st
+        p = PAPER_TABLE6[lev]
         row = dict(level=lev, grid=list(shape), cell_m=list(h), dt=dt, vacuum_planes=ks, state_finite=finite,
                    steps_timed=K,
                    gcs=round(cells * K / el / 1e9, 3), gcs_graph=round(cells * K / el_g / 1e9, 3),
-                   ms_per_step=round(best / K * 1e3, 4), full_run_s=round(best / K * nt_full, 2), kernel=sim.kernel())
+                   ms_per_step=round(best / K * 1e3, 4), full_run_s=round(best / K * nt_full, 2),
+                   paper_gpu_s=p[4], paper_cpu_s=p[3], kernel=sim.kernel())
         log(f"[bench] level {lev} {shape}: {row['gcs']} Gcell-steps/s ({row['gcs_graph']} from a graph), "
-            f"{row['ms_per_step']} ms/step, {nt_full} steps in {row['full_run_s']} s, state finite and nonzero: {finite}")
+            f"{row['ms_per_step']} ms/step, {nt_full} steps in {row['full_run_s']} s (paper GLSL {p[4]} s), "
+            f"state finite and nonzero: {finite}")
         out.append(row)
         sim.close()
         del lam, mu, rho
@@ -411,29 +512,29 @@ def bench_levels(K=100):
 
 
 def bench_gradient(wave=4, nshots=8):
-    import numpy as np
     import torch
 
     import workloads as W
     from paper_2112_15071_amd import Simulator
     from paper_2112_15071_amd.batch import BatchSimulator
 
-    log(f"[bench] FWI gradient: {nshots} shots, 256^3, 1500 steps, checkpoints every 50")
+    nt, k = 1500, 50
+    log(f"[bench] FWI gradient: {nshots} shots, 256^3, {nt} steps, checkpoints every {k}")
     (tl, tm, tr_), start = W.c4_models()
     dev = torch.device("cuda:0")
     true = [torch.as_tensor(a, dtype=torch.float32, device=dev) for a in (tl, tm, tr_)]
     model = [torch.as_tensor(a, dtype=torch.float32, device=dev) for a in start]
     shots = W.c4_shots(*start)[:nshots]
-    k = 50
+    cells = int(model[0].numel())
     # observed data from the true model
-    obs_sim = Simulator(*true, 10.0, 5e-4, 1500, sponge=20, device=dev)
+    obs_sim = Simulator(*true, 10.0, 5e-4, nt, sponge=20, device=dev)
     obs_sim.autotune(steps=10)
     d_obs = [obs_sim.forward(**shot_desc(s)).clone() for s in shots]
     sync()
     obs_sim.close()
     del true
     # per-shot loop through one gradient workspace
-    sim = Simulator(*model, 10.0, 5e-4, 1500, sponge=20, device=dev)
+    sim = Simulator(*model, 10.0, 5e-4, nt, sponge=20, device=dev)
     sim.autotune(steps=10)
     # the gradient's own kernel choice (its adjoint passes can rank tile shapes unlike the forward)
     gt = sim.autotune_gradient(shot_desc(shots[0]))
@@ -441,21 +542,24 @@ def bench_gradient(wave=4, nshots=8):
     gws = sim.grad_workspace(k)
     g_loop = [torch.zeros_like(model[0]) for _ in range(3)]
     sync()
-    t0 = time.perf_counter()
+    per_shot = []
     J_loop = 0.0
+    t0 = time.perf_counter()
     for s, o in zip(shots, d_obs):
+        t1 = time.perf_counter()
         _, j = sim.gradient(gws, o, *g_loop, **shot_desc(s))
+        sync()
+        per_shot.append(time.perf_counter() - t1)
         J_loop = J_loop + j
-    sync()
     t_loop = time.perf_counter() - t0
     kern = sim.kernel()
     sim.close()
     del gws
     torch.cuda.empty_cache()
-    log(f"[bench] gradient loop {t_loop:.2f} s")
+    log(f"[bench] gradient loop {t_loop:.2f} s, per shot median {statistics.median(per_shot):.3f} s")
     # batched waves sharing the model and the gradient arrays
     wave = min(wave, len(shots))
-    sims = [Simulator(*model, 10.0, 5e-4, 1500, sponge=20, device=dev) for _ in range(wave)]
+    sims = [Simulator(*model, 10.0, 5e-4, nt, sponge=20, device=dev) for _ in range(wave)]
     for x in sims:
         x.set_kernel(kern["variant"], kern["tile_y"], kern["zchunk"], kern["tile_x"])
     batch = BatchSimulator(sims)
@@ -464,15 +568,18 @@ def bench_gradient(wave=4, nshots=8):
     gws_b = [x.grad_workspace(k) for x in sims]
     g_b = [torch.zeros_like(model[0]) for _ in range(3)]
     sync()
-    t0 = time.perf_counter()
+    per_wave = []
     J_b = 0.0
+    t0 = time.perf_counter()
     for w0 in range(0, len(shots), wave):
         grp = shots[w0:w0 + wave]
+        t1 = time.perf_counter()
         _, J = batch.gradient([shot_desc(s) for s in grp], d_obs[w0:w0 + wave], *g_b, ckpt_every=k, gws=gws_b)
+        sync()
+        per_wave.append((time.perf_counter() - t1) / len(grp))
         J_b = J_b + J.sum()
-    sync()
     t_b = time.perf_counter() - t0
-    log(f"[bench] gradient batched {t_b:.2f} s")
+    log(f"[bench] gradient batched {t_b:.2f} s, per shot by wave {[round(t, 3) for t in per_wave]}")
     diff = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip(g_b, g_loop))
     batch.close()
     for x in sims:
@@ -480,11 +587,24 @@ def bench_gradient(wave=4, nshots=8):
     del gws_b
     torch.cuda.empty_cache()
     n = len(shots)
-    return dict(loop_shots_per_s=round(n / t_loop, 4), batched_shots_per_s=round(n / t_b, 4),
+    bytes_shot = GRAD_BYTES_PER_CELL_STEP * cells * nt
+    design_shot = GRAD_BYTES_DESIGN * cells * nt
+    frac = lambda sps, b: round(sps * b / 1e9 / HBM_PEAK_GBS, 4)
+    loop_sps, b_sps = n / t_loop, n / t_b
+    return dict(loop_shots_per_s=round(loop_sps, 4), batched_shots_per_s=round(b_sps, 4),
                 loop_s=round(t_loop, 2), batched_s=round(t_b, 2), speedup=round(t_loop / t_b, 3), wave=wave,
+                loop_s_per_shot_median=round(statistics.median(per_shot), 4),
+                loop_s_per_shot=[round(t, 4) for t in per_shot],
+                batched_s_per_shot_by_wave=[round(t, 4) for t in per_wave],
                 loop_kernel=kern, batch_tile=bt["tile"], batch_zchunk=bt["zchunk"],
                 misfit=float(J_loop), max_rel_diff_batched_vs_loop=diff,
-                bytes_per_cell_step_per_shot=GRAD_BYTES_PER_CELL_STEP)
+                bytes_per_cell_step_per_shot=GRAD_BYTES_PER_CELL_STEP,
+                roofline={"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "batched_achieved": round(b_sps * bytes_shot / 1e9, 1),
+                          "batched_frac": frac(b_sps, bytes_shot), "loop_frac": frac(loop_sps, bytes_shot),
+                          "design_bytes_per_cell_step": GRAD_BYTES_DESIGN,
+                          "batched_frac_at_design_bytes": frac(b_sps, design_shot),
+                          "roofline_shots_per_s_at_design_bytes": round(HBM_PEAK_GBS * 1e9 / design_shot, 4)})
 
 
 def counters_run(kernels, K):
@@ -517,25 +637,31 @@ def counters_run(kernels, K):
 
 
 def cpu_baseline(shot, ns):
+    """The FP64 oracle on the first ``ns`` steps of ``shot`` at full size (its own Ricker
+    wavelet of ns samples with the shot's peak frequency, so the sample does not depend on
+    how many steps the GPU leg ran), on every thread of this process, then on one thread
+    over an eighth of the steps (the cost per step is constant)."""
     import oracle
+    import workloads as W
 
     oracle.build(force=False)
+    f0 = 12.0
+    wav = W.ricker(f0, ns, shot.dt)
     cfg = oracle.Config(shot.shape, shot.h, shot.dt, ns, sponge=shot.sponge)
     src = oracle.Source(shot.src_pos, moment=shot.moment, force=shot.force)
-    log(f"[bench] oracle baseline: {ns} steps at full size on {oracle.get_threads()} threads")
+    threads = oracle.get_threads()
+    log(f"[bench] oracle baseline: {ns} steps at full size on {threads} threads")
     t0 = time.perf_counter()
-    oracle.forward(cfg, shot.lam, shot.mu, shot.rho, src, shot.wavelet[:ns], shot.rec_pos)
+    oracle.forward(cfg, shot.lam, shot.mu, shot.rho, src, wav, shot.rec_pos)
     dt = time.perf_counter() - t0
     cells = int(shot.cells)
-    # the same oracle on one core, over fewer steps (the cost per step is constant)
-    threads = oracle.get_threads()
     ns1 = max(1, ns // 8)
     oracle.set_threads(1)
     try:
         log(f"[bench] oracle baseline: {ns1} steps at full size on 1 thread")
-        t1 = time.perf_counter()
         cfg1 = oracle.Config(shot.shape, shot.h, shot.dt, ns1, sponge=shot.sponge)
-        oracle.forward(cfg1, shot.lam, shot.mu, shot.rho, src, shot.wavelet[:ns1], shot.rec_pos)
+        t1 = time.perf_counter()
+        oracle.forward(cfg1, shot.lam, shot.mu, shot.rho, src, wav[:ns1], shot.rec_pos)
         dt1 = time.perf_counter() - t1
     finally:
         oracle.set_threads(threads)
@@ -545,19 +671,35 @@ def cpu_baseline(shot, ns):
             cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
     except OSError:
         pass
-    return {"value": round(cells * ns / dt / 1e9, 5), "unit": "Gcell-steps/s", "cores": oracle.get_threads(),
+    nx, ny, nz = shot.shape
+    return {"value": round(cells * ns / dt / 1e9, 5), "unit": "Gcell-steps/s", "cores": threads,
             "kind": "oracle", "cpu": cpu,
-            "sample": f"FP64 oracle on the 256^3 workload at full size, first {ns} of 2000 steps ({dt:.1f} s)",
+            "sample": f"FP64 oracle on the {nx}x{ny}x{nz} workload at full size, first {ns} steps ({dt:.1f} s)",
             "one_core": {"value": round(cells * ns1 / dt1 / 1e9, 5), "steps": ns1, "seconds": round(dt1, 2)}}
 
 
-def main():
+def paper_context():
+    """The paper's Table 6 totals as Gcell-steps/s, with their hardware (context only)."""
+    rows = []
+    for lev, (nx, ny, nz), steps, cpu_s, gpu_s in PAPER_TABLE6:
+        cs = nx * ny * nz * steps
+        rows.append(dict(level=lev, grid=[nx, ny, nz], steps=steps, cpu_s=cpu_s, gpu_s=gpu_s,
+                         gpu_gcs=round(cs / gpu_s / 1e9, 4), cpu_gcs=round(cs / cpu_s / 1e9, 4)))
+    return {"source": "paper Table 6 (total time of one simulation per level of detail; grids and steps of Table 5)",
+            "gpu": "GLSL 3.3 shaders on the Vega iGPU of an AMD Ryzen 7 4700U (HP ProBook 445 G7, 24 GB DDR4)",
+            "cpu": "NumPy + OpenBLAS on the same Ryzen 7 4700U (about 30 % CPU utilisation)",
+            "precision": "floating-point textures (taken as FP32)", "levels": rows}
+
+
+def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=24, help="oracle steps for the CPU baseline sample (0: skip)")
+    ap.add_argument("--no-c1-full", action="store_true", help="skip the 2000-step 256^3 run")
     ap.add_argument("--no-c2", action="store_true", help="skip the 512x512x256 free-surface section")
+    ap.add_argument("--c2-steps", type=int, default=1000, help="timed steps of the 512x512x256 section")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-levels", action="store_true", help="skip the Table 5 level sweep")
@@ -568,32 +710,35 @@ def main():
     ap.add_argument("--counters", metavar="VARIANT,TX,TY,ZC", action="append", default=[],
                     help="counter-collection run: --steps forward steps per kernel given (repeatable), then a "
                          "1 GiB device copy that calibrates FETCH_SIZE / WRITE_SIZE; prints no JSON")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built.",
-              file=sys.stderr)
-        sys.exit(2)
+    return ap.parse_args(argv)
 
-    if args.counters:
-        counters_run(args.counters, args.steps)
-        return
-    shot, f = bench_forward(args.steps, args.warmup, args.kernel)
-    copy_gbs = stream_copy_ceiling()
-    c2 = None if args.no_c2 else bench_c2()
-    batch = None if args.no_batch else bench_batch()
-    grad = None if args.no_grad else bench_gradient(nshots=args.grad_shots)
-    levels = None if args.no_levels else bench_levels()
-    born = None if args.no_born else bench_born()
-    cpu = cpu_baseline(shot, args.cpu_steps) if args.cpu_steps > 0 else None
-    nx, ny, nz = shot.shape
+
+def run_sections(args, sections):
+    """Run (name, fn) pairs in order; a section that raises records its error and the
+    rest still run.  Returns ({name: result or None}, {name: error text})."""
+    results, errors = {}, {}
+    for name, fn in sections:
+        try:
+            results[name] = fn()
+        except Exception as e:  # noqa: BLE001 - reported in the JSON line
+            log(f"[bench] section {name} failed:\n{traceback.format_exc()}")
+            results[name] = None
+            errors[name] = f"{type(e).__name__}: {e}"
+    return results, errors
+
+
+def build_line(args, r, errors):
+    f = r.get("forward")
+    fw_shape = r.get("_shape", (256, 256, 256))
+    nx, ny, nz = fw_shape
     out = {
         "metric": "FD Gcell-steps/s (forward, 256^3, FP32)",
-        "value": round(f["gcs"], 3),
+        "value": round(f["gcs"], 3) if f else None,
         "unit": "Gcell-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(f["elapsed"] / args.steps * 1e3, 4),
+        "ms_per_step": round(f["elapsed"] / args.steps * 1e3, 4) if f else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -603,34 +748,96 @@ def main():
             "workload": "256^3 six-layer + 5% Gaussian-correlated perturbation, h 10 m, dt 0.5 ms, random MT "
                         "source, 12 Hz Ricker, 256 receivers, 20-cell Cerjan sponge, O(2,4) velocity-stress",
             "grid": [nx, ny, nz],
-            "cells": int(shot.cells),
+            "cells": nx * ny * nz,
             "time_steps": args.steps,
-            "kernel": f["kernel"],
-            "hbm_gbs_whole_step": round(f["both"], 1),
-            "hbm_frac_whole_step": round(f["both"] / HBM_PEAK_GBS, 4),
-            "bytes_per_cell_step": step_bytes(f["kernel"]),
+            "timing": "median of 5 runs of the given steps, each from a zero state set before the clock",
+            "kernel": f["kernel"] if f else None,
+            "bytes_per_cell_step": step_bytes(f["kernel"]) if f else None,
+            "hbm_gbs_whole_step": round(f["wall_gbs"], 1) if f else None,
+            "hbm_frac_whole_step": round(f["wall_gbs"] / HBM_PEAK_GBS, 4) if f else None,
         },
-        "roofline": {
+        "roofline": None,
+    }
+    if f:
+        out["ms_per_step_runs"] = [round(t / args.steps * 1e3, 4) for t in f["times"]]
+        out["roofline"] = {
             "bound": "hbm",
             "kernel": f["dom"],
-            "achieved": round(f["achieved"], 1),
+            "achieved": f["per_kernel"][f["dom"]]["achieved_gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(f["achieved"] / HBM_PEAK_GBS, 4),
+            "frac": f["per_kernel"][f["dom"]]["frac"],
             "traffic": f["traffic"],
-            "avg_kernel_ms": {k: round(v, 5) for k, v in f["per"].items()},
             "bytes_per_launch": f["bytes_launch"],
-        },
-        "stream_copy_gbs": copy_gbs,
-        "c2_forward": c2,
-        "batched_forward": batch,
-        "gradient": grad,
-        "levels": levels,
-        "born": born,
-        "cpu_baseline": cpu,
-    }
+            "per_kernel": f["per_kernel"],
+            "whole_step": {"bytes_per_cell": step_bytes(f["kernel"]),
+                           "achieved_events": round(f["events_gbs"], 1),
+                           "frac_events": round(f["events_gbs"] / HBM_PEAK_GBS, 4),
+                           "achieved_wall": round(f["wall_gbs"], 1),
+                           "frac_wall": round(f["wall_gbs"] / HBM_PEAK_GBS, 4)},
+        }
+    for key in ("c1_full", "stream_copy_gbs", "c2_forward", "batched_forward", "gradient", "levels", "born"):
+        out[key] = r.get(key)
+    out["paper_table6"] = paper_context()
+    out["cpu_baseline"] = r.get("cpu_baseline")
+    out["errors"] = errors or None
+    return out
+
+
+def main(argv=None):
+    args = parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built.",
+              file=sys.stderr)
+        return 2
+    if args.counters:
+        counters_run(args.counters, args.steps)
+        return 0
+    state = {}
+
+    def fwd():
+        state["fw"] = Forward(max(args.steps, args.warmup, 2000 if not args.no_c1_full else 1), args.kernel)
+        return bench_forward(state["fw"], args.steps, args.warmup)
+
+    def c1_full():
+        return bench_c1_full(state["fw"]) if "fw" in state and not args.no_c1_full else None
+
+    def release():
+        if "fw" in state:
+            state["fw"].close()
+            state["shot"] = state.pop("fw").shot
+            import torch
+
+            torch.cuda.empty_cache()
+
+    def cpu():
+        if args.cpu_steps <= 0:
+            return None
+        shot = state.get("shot")
+        if shot is None:
+            import workloads as W
+
+            shot = W.c1(nt=1)
+        return cpu_baseline(shot, args.cpu_steps)
+
+    sections = [
+        ("forward", fwd),
+        ("c1_full", c1_full),
+        ("_release", release),
+        ("stream_copy_gbs", stream_copy_ceiling),
+        ("c2_forward", (lambda: None) if args.no_c2 else (lambda: bench_c2(args.c2_steps))),
+        ("batched_forward", (lambda: None) if args.no_batch else bench_batch),
+        ("gradient", (lambda: None) if args.no_grad else (lambda: bench_gradient(nshots=args.grad_shots))),
+        ("levels", (lambda: None) if args.no_levels else bench_levels),
+        ("born", (lambda: None) if args.no_born else bench_born),
+        ("cpu_baseline", cpu),
+    ]
+    results, errors = run_sections(args, sections)
+    results.pop("_release", None)
+    out = build_line(args, results, errors)
     print(json.dumps(out), flush=True)
+    return 1 if errors else 0
 
 
 if __name__ == "__main__":
-    main()
+    sys.exit(main())
