@@ -32,10 +32,16 @@ def gpu_run(shot, dtype, nt=None, kernel=None, **kw):
     return out
 
 
-def compare(gpu, ref, tol, what=""):
-    """rel-L2 per trace component (over receivers and samples) and per field."""
+def compare(gpu, ref, tol, what="", nonzero=True):
+    """rel-L2 per trace component (over receivers and samples) and per field.  With
+    ``nonzero`` every reference trace component must have recorded something, so that a
+    comparison of all-zero traces (where rel-L2 degenerates to the norm of the other
+    side) cannot pass."""
     tr, st = gpu
     rtr, rst = ref
+    if nonzero and rtr.size:
+        for c in range(3):
+            assert np.linalg.norm(rtr[:, c]) > 0.0, f"{what}: reference trace component {'xyz'[c]} is all zero"
     worst = {}
     for c in range(3):
         worst[f"trace_{'xyz'[c]}"] = rel_l2(tr[:, c], rtr[:, c])

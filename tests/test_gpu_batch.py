@@ -189,14 +189,28 @@ def test_graph_replays_with_new_sources():
         s.close()
 
 
+def early_c3(nt):
+    """The 24-shot uneven batch at full size with wavelets that peak within a truncated
+    run and four extra receivers 4-6 cells from each source, so traces are non-zero."""
+    import dataclasses
+
+    out = []
+    for s in W.c3(nt=nt):
+        near = np.asarray(s.src_pos) + np.array([[4.3, 0.2, -1.5], [-5.1, 1.4, 0.5], [0.7, 4.6, 2.25],
+                                                 [-1.2, -5.3, -2.75]])
+        out.append(dataclasses.replace(s, wavelet=W.ricker(10.0, nt, s.dt, t0=0.004),
+                                       rec_pos=np.concatenate([s.rec_pos, near])))
+    return out
+
+
 def test_full_size_uneven_batch_truncated():
-    """The 24-shot uneven batch at full size (128^3 .. 256x256x128), 12 steps, in the
-    launch configuration of the benchmark: every shot equals its single-shot run."""
+    """The 24-shot uneven batch at full size (128^3 .. 256x256x128), 12 steps, lockstep
+    with the batch's default tile shape: every shot equals its single-shot run."""
     from paper_2112_15071_amd import Simulator
     from paper_2112_15071_amd.batch import BatchSimulator
 
     nt = 12
-    shots = W.c3(nt=nt)
+    shots = early_c3(nt)
     print(f"[batch] 24 uneven shots x {nt}", flush=True)
     sims = [Simulator(s.lam, s.mu, s.rho, s.h, s.dt, nt, sponge=s.sponge) for s in shots]
     batch = BatchSimulator(sims)
@@ -207,9 +221,55 @@ def test_full_size_uneven_batch_truncated():
         one = Simulator(s.lam, s.mu, s.rho, s.h, s.dt, nt, sponge=s.sponge)
         one.set_kernel("tile", tile[1], one.kernel()["zchunk"], tile[0])
         tr = one.forward(**desc(s))
+        assert float(tr.abs().max()) > 0, k
         assert torch.equal(tr, trs[k]), k
         assert torch.equal(one.state(), sims[k].state()), k
         one.close()
+    batch.close()
+    for s in sims:
+        s.close()
+
+
+def test_full_size_uneven_batch_bench_schedule():
+    """The 24-shot batch at full size in the benchmark's configuration: the batch tuner
+    (per-shape kernels, batched tile shapes, cache-blocked group budgets) decides the
+    launches, then a 192 MiB group budget (the benchmark's pick on MI355X) is run as well;
+    16 steps replayed twice from the graph.  Every shot equals its single-shot run with its
+    own tuned kernel bit for bit, and one shot of each size matches the oracle."""
+    from paper_2112_15071_amd import Simulator
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    nt = 16
+    shots = early_c3(nt)
+    sims = [Simulator(s.lam, s.mu, s.rho, s.h, s.dt, nt, sponge=s.sponge) for s in shots]
+    batch = BatchSimulator(sims)
+    tune = batch.autotune(steps=3, cache=False)
+    print(f"[batch] bench schedule: tuned group budget {tune['group_mib']} MiB, tiles "
+          f"{tune['tile_x']}x{tune['tile_y']} + {tune['tile2_x']}x{tune['tile2_y']}", flush=True)
+    ref = []
+    for k, s in enumerate(shots):
+        one = Simulator(s.lam, s.mu, s.rho, s.h, s.dt, nt, sponge=s.sponge)
+        kern = sims[k].kernel()
+        one.set_kernel(kern["variant"], kern["tile_y"], kern["zchunk"], kern["tile_x"])
+        ref.append((one.forward(**desc(s)).clone(), one.state()))
+        one.close()
+    for budget in (None, 192 << 20):
+        if budget is not None:
+            batch.set_schedule(budget)
+        for rep in range(2):
+            trs = batch.forward([desc(s) for s in shots], use_graph=True)
+            torch.cuda.synchronize()
+            for k in range(len(shots)):
+                assert torch.equal(trs[k], ref[k][0]), (budget, rep, k)
+                assert torch.equal(sims[k].state(), ref[k][1]), (budget, rep, k)
+    seen = set()
+    for k, s in enumerate(shots):
+        if s.shape in seen:
+            continue
+        seen.add(s.shape)
+        print(f"[batch] bench schedule: shot {k} {s.shape} against the oracle", flush=True)
+        compare((ref[k][0].double().cpu().numpy(), ref[k][1].double().cpu().numpy()), oracle_run(s), 1e-4,
+                f"batched shot {k} {s.shape}")
     batch.close()
     for s in sims:
         s.close()
