@@ -134,6 +134,26 @@ int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const v
 int fd3d_forward(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *rec_pos,
                  void *traces, int flags, void *hip_stream);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid allocation): fd3d_create + fd3d_forward (flags 0) + fd3d_get_state in one call,
+ * with the whole forward workspace in the library's static device scratch instead of a
+ * caller workspace.  The scratch holds FD3D_STATIC_SCRATCH_BYTES (64 MiB) per GPU, taken
+ * when the library's code object is loaded on that GPU and held until the process ends;
+ * grids whose fd3d_workspace_bytes exceed it are rejected with FD3D_EWS (FP32 grids up to
+ * about 96^3 cells with the default 4096-receiver capacity; FP64 about half the cells).
+ * Arguments as fd3d_create and fd3d_forward: model arrays, src (its wavelet), rec_pos and
+ * traces are the caller's; final_state (9 device T[nz][ny][nx], order as fd3d_get_state)
+ * receives the final state, or is NULL.  The call allocates no device memory and creates
+ * no HIP object (no event, stream or graph); it synchronises the stream before it
+ * returns.  Every call on one GPU shares that GPU's scratch, which keeps the last call's
+ * state: the call zeroes what must start at zero, and calls that overlap on one GPU (from
+ * several host threads) race. */
+#define FD3D_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int fd3d_forward_static(int nx, int ny, int nz, const void *lam, const void *mu, const void *rho,
+                        double dx, double dt, int nt, const fd3d_opts *opts, const fd3d_source *src,
+                        int nrec, const double *rec_pos, void *traces, void *const final_state[9],
+                        void *hip_stream);
+
 /* Copy the state out of / into the context: fields[9] are device T[nz][ny][nx] in the
  * order vx vy vz sxx syy szz sxy sxz syz (v^{n-1/2}, sigma^n).  set_state zeroes the
  * pinned slots of the staggered components. */

@@ -9,7 +9,7 @@ __version__ = "0.1.0"
 
 
 def __getattr__(name):
-    if name in ("Simulator", "make_opts", "make_source", "FIELDS", "upsample"):
+    if name in ("Simulator", "make_opts", "make_source", "FIELDS", "upsample", "forward_static"):
         from . import simulator
 
         return getattr(simulator, name)

@@ -28,6 +28,7 @@ FD3D_KEEP_STATE = 1
 FD3D_KERNEL_CELL = 0
 FD3D_KERNEL_TILE = 1
 FD3D_KERNEL_FUSED = 2
+FD3D_STATIC_SCRATCH_BYTES = 64 << 20
 
 ERRNAMES = {
     FD3D_EINVAL: "FD3D_EINVAL", FD3D_ECFL: "FD3D_ECFL", FD3D_EMODEL: "FD3D_EMODEL", FD3D_ERANGE: "FD3D_ERANGE",
@@ -120,6 +121,8 @@ _SIGS = {
     "fd3d_profile": ([_vp, _i], _i),
     "fd3d_profile_read": ([_vp, _dp, ctypes.POINTER(_i)], _i),
     "fd3d_upsample": ([_vp, _i, _i, _i, _vp, _i, _i, _i, _i, _vp], _i),
+    "fd3d_forward_static": ([_i, _i, _i, _vp, _vp, _vp, _d, _d, _i, ctypes.POINTER(fd3d_opts),
+                             ctypes.POINTER(fd3d_source), _i, _dp, _vp, ctypes.POINTER(_vp), _vp], _i),
     "fd3d_destroy": ([_vp], None),
 }
 
@@ -326,3 +329,13 @@ def fd3d_upsample(coarse_ptr, mshape, fine_ptr, nshape, dtype_code: int, stream)
     """mshape, nshape: (x, y, z) sizes of the coarse and the simulation grid."""
     _check(_lib.fd3d_upsample(coarse_ptr, int(mshape[0]), int(mshape[1]), int(mshape[2]), fine_ptr,
                               int(nshape[0]), int(nshape[1]), int(nshape[2]), int(dtype_code), stream))
+
+
+def fd3d_forward_static(shape, lam, mu, rho, dx: float, dt: float, nt: int, opts: fd3d_opts | None,
+                        src: fd3d_source | None, nrec: int, rec_pos_ptr, traces, final_state, stream) -> None:
+    """shape: (nx, ny, nz); final_state: 9 device pointers or None."""
+    fs = _ptr9(final_state) if final_state is not None else None
+    _check(_lib.fd3d_forward_static(int(shape[0]), int(shape[1]), int(shape[2]), lam, mu, rho, float(dx), float(dt),
+                                    int(nt), ctypes.byref(opts) if opts is not None else None,
+                                    ctypes.byref(src) if src is not None else None, int(nrec),
+                                    ctypes.cast(rec_pos_ptr, _dp) if rec_pos_ptr else None, traces, fs, stream))

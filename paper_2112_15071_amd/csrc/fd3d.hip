@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <string>
@@ -173,7 +174,9 @@ struct fd3d_ctx {
     std::vector<unsigned char> rec_host;   // receiver descriptors, kept for the async upload
     std::vector<int> color_host;           // receivers grouped by colour, kept for the async upload
     std::vector<int> color_off;            // colour c holds color_host[color_off[c] .. color_off[c+1])
-    hipEvent_t staged;
+    hipEvent_t staged;     // marks the end of the uploads from the host staging buffers;
+                           // null in a context that must create no HIP objects (its call
+                           // synchronises the stream before the buffers are released)
     bool staged_pending;
     // optional per-kernel timing of the step loop
     int prof_on;
@@ -346,8 +349,10 @@ int stage_inputs(fd3d_ctx *c, const fd3d_source *src, Inject<T> &inj, int nrec, 
     int rc = build_source<T>(c, src, inj);
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.src, c->src_host.data(), c->src_host.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipEventRecord(c->staged, st));
-    c->staged_pending = true;
+    if (c->staged) {
+        HIP_TRY(hipEventRecord(c->staged, st));
+        c->staged_pending = true;
+    }
     if (nrec == 0) return FD3D_OK;
     c->rec_host.assign((size_t)nrec * 3 * sizeof(RecTap<T>), 0);
     RecTap<T> *t = (RecTap<T> *)c->rec_host.data();
@@ -398,8 +403,10 @@ int stage_inputs(fd3d_ctx *c, const fd3d_source *src, Inject<T> &inj, int nrec, 
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.rec, c->rec_host.data(), c->rec_host.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.colors, c->color_host.data(), c->color_host.size() * sizeof(int),
                            hipMemcpyHostToDevice, st));
-    HIP_TRY(hipEventRecord(c->staged, st));
-    c->staged_pending = true;
+    if (c->staged) {
+        HIP_TRY(hipEventRecord(c->staged, st));
+        c->staged_pending = true;
+    }
     return FD3D_OK;
 }
 
@@ -1625,8 +1632,13 @@ int fd3d_workspace_bytes(int nx, int ny, int nz, const fd3d_opts *opts, size_t *
     return FD3D_OK;
 }
 
-int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const void *mu, const void *rho, double dx,
-                double dt, int nt, const fd3d_opts *opts, void *workspace, size_t ws_bytes, void *hip_stream)
+namespace {
+
+// fd3d_create with the choice of creating the staging event (events = false: the
+// context creates no HIP object, for the entry point that allocates nothing).
+int create_ctx(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const void *mu, const void *rho, double dx,
+               double dt, int nt, const fd3d_opts *opts, void *workspace, size_t ws_bytes, void *hip_stream,
+               bool events)
 {
     if (!out) return fail(FD3D_EINVAL, "out is NULL");
     *out = nullptr;
@@ -1678,7 +1690,8 @@ int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const v
     c->zchunk = nz >= 128 ? 64 : 32;
     while (!window_ok(c, c->zchunk) && c->zchunk > 4) c->zchunk /= 2;
     if (!window_ok(c, c->zchunk)) c->variant = FD3D_KERNEL_CELL;  // planes too large for a tile sweep
-    if (hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess) {
+    c->staged = nullptr;
+    if (events && hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess) {
         delete c;
         return fail(FD3D_EHIP, "hipEventCreateWithFlags failed");
     }
@@ -1695,12 +1708,20 @@ int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const v
     if (!rc && hipGetLastError() != hipSuccess) rc = fail(FD3D_EHIP, "launch failed in fd3d_create");
     if (!rc) rc = hipStreamSynchronize(st) == hipSuccess ? FD3D_OK : fail(FD3D_EHIP, "hipStreamSynchronize failed");
     if (rc) {
-        (void)hipEventDestroy(c->staged);
+        if (c->staged) (void)hipEventDestroy(c->staged);
         delete c;
         return rc;
     }
     *out = c;
     return FD3D_OK;
+}
+
+} // namespace
+
+int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const void *mu, const void *rho, double dx,
+                double dt, int nt, const fd3d_opts *opts, void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    return create_ctx(out, nx, ny, nz, lam, mu, rho, dx, dt, nt, opts, workspace, ws_bytes, hip_stream, true);
 }
 
 int fd3d_forward(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *rec_pos, void *traces, int flags,
@@ -1725,6 +1746,68 @@ int fd3d_get_state(fd3d_ctx *ctx, void *const fields[9], void *hip_stream)
         HIP_TRY(hipMemcpyAsync(fields[f], ctx->ws + ctx->L.field[ctx->cur][f], ctx->L.field_bytes,
                                hipMemcpyDeviceToDevice, st));
     return FD3D_OK;
+}
+
+namespace {
+
+// Device scratch of the entry point that allocates nothing (fd3d_forward_static): the
+// whole forward workspace of one call lives here.  Each GPU the library runs on holds
+// its own copy from module load until the process ends.  On the host the array's name
+// only stands in for the symbol; kernels and copies get the per-device address that
+// hipGetSymbolAddress returns (scratch_address), never the name itself.
+static __device__ __align__(256) unsigned char scratch[FD3D_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];  // per device id; null until resolved on that device
+
+// Address of this device's copy of the scratch, resolved once per device with the device
+// current (the calling thread's current device).
+int scratch_address(void **ptr)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FD3D_EHIP, "device id out of range for the static scratch");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p % kAlign)) return fail(FD3D_EHIP, "hipGetSymbolAddress gave no aligned scratch address");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return FD3D_OK;
+}
+
+} // namespace
+
+int fd3d_forward_static(int nx, int ny, int nz, const void *lam, const void *mu, const void *rho, double dx,
+                        double dt, int nt, const fd3d_opts *opts, const fd3d_source *src, int nrec,
+                        const double *rec_pos, void *traces, void *const final_state[9], void *hip_stream)
+{
+    size_t need = 0;
+    int rc = fd3d_workspace_bytes(nx, ny, nz, opts, &need);
+    if (rc) return rc;
+    if (need > FD3D_STATIC_SCRATCH_BYTES)
+        return fail(FD3D_EWS, "grid " + std::to_string(nx) + "x" + std::to_string(ny) + "x" + std::to_string(nz) +
+                                  " needs " + std::to_string(need) + " bytes of workspace; the static scratch holds " +
+                                  std::to_string((size_t)FD3D_STATIC_SCRATCH_BYTES));
+    if (final_state)
+        for (int f = 0; f < NFIELD; ++f)
+            if (!final_state[f]) return fail(FD3D_EINVAL, "final_state field pointer is NULL");
+    void *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    fd3d_ctx *c = nullptr;
+    rc = create_ctx(&c, nx, ny, nz, lam, mu, rho, dx, dt, nt, opts, ws, FD3D_STATIC_SCRATCH_BYTES, hip_stream, false);
+    if (rc) return rc;
+    rc = fd3d_forward(c, src, nrec, rec_pos, traces, 0, hip_stream);
+    if (!rc && final_state) rc = fd3d_get_state(c, final_state, hip_stream);
+    // the context's host staging buffers must outlive the uploads queued from them
+    if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess && !rc)
+        rc = fail(FD3D_EHIP, "hipStreamSynchronize failed");
+    fd3d_destroy(c);
+    return rc;
 }
 
 int fd3d_set_state(fd3d_ctx *ctx, const void *const fields[9], void *hip_stream)
@@ -2277,7 +2360,7 @@ void fd3d_destroy(fd3d_ctx *ctx)
 {
     if (!ctx) return;
     if (ctx->staged_pending) (void)hipEventSynchronize(ctx->staged);
-    (void)hipEventDestroy(ctx->staged);
+    if (ctx->staged) (void)hipEventDestroy(ctx->staged);
     for (hipEvent_t e : ctx->prof_ev) {
         (void)hipEventSynchronize(e);
         (void)hipEventDestroy(e);

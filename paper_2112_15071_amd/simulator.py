@@ -78,6 +78,35 @@ def upsample(coarse: torch.Tensor, shape) -> torch.Tensor:
     return out
 
 
+def forward_static(lam, mu, rho, dx: float, dt: float, nt: int, src_pos=None, moment=(0.0,) * 6, force=(0.0,) * 3,
+                   wavelet=None, rec_pos=None, dtype: torch.dtype = torch.float32, sponge=20,
+                   sponge_alpha: float = 0.0, free_surface: bool = False, traces: Optional[torch.Tensor] = None,
+                   state: Optional[torch.Tensor] = None, max_receivers: int = 4096):
+    """One forward run whose workspace is the library's static device scratch
+    (fd3d_forward_static): for small grids in code that must not allocate device memory.
+    Inputs are device tensors of ``dtype``; ``traces`` [nrec, 3, nt] and ``state``
+    [9, nz, ny, nx] (optional) are written.  dx is one spacing or (dx, dy, dz).  Returns
+    (traces, state).  Synchronises the current stream."""
+    nz, ny, nx = lam.shape
+    sp = tuple(float(v) for v in np.broadcast_to(np.asarray(dx, dtype=np.float64), (3,)))
+    opts = make_opts(dtype, sponge, sponge_alpha, free_surface, False, max_receivers, sp[1], sp[2])
+    for a in (lam, mu, rho, wavelet, traces, state):
+        if a is not None and (not a.is_cuda or a.dtype != dtype or not a.is_contiguous()):
+            raise ValueError("inputs and outputs must be contiguous device tensors of the given dtype")
+    if wavelet is not None and wavelet.numel() != nt:
+        raise ValueError(f"wavelet needs nt = {nt} samples")
+    src = make_source(src_pos, moment, force, wavelet) if src_pos is not None else None
+    rp, nrec = Simulator._rec(rec_pos)
+    if nrec and (traces is None or tuple(traces.shape) != (nrec, 3, nt)):
+        raise ValueError(f"traces must be [nrec, 3, nt] = {(nrec, 3, nt)}")
+    if state is not None and tuple(state.shape) != (9, nz, ny, nx):
+        raise ValueError("state must be [9, nz, ny, nx]")
+    _abi.fd3d_forward_static((nx, ny, nz), lam.data_ptr(), mu.data_ptr(), rho.data_ptr(), sp[0], dt, nt, opts, src,
+                             nrec, rp.ctypes.data if nrec else None, traces.data_ptr() if nrec else None,
+                             [state[f].data_ptr() for f in range(9)] if state is not None else None, _stream())
+    return traces, state
+
+
 def _shot_args(shot: dict, steps: int) -> dict:
     """Source and receiver arguments of a shot description, its wavelet cut to ``steps``."""
     args = {k: shot[k] for k in ("src_pos", "moment", "force", "rec_pos") if shot.get(k) is not None}
