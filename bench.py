@@ -27,13 +27,16 @@ is still printed):
               its case-study medium (seven layers under 30 km of air: vacuum surface),
               upsampled from one coarse grid to every level, 100 timed steps per level;
   born     -- the tangent-linear (Born) forward on the 256^3 model, 300 steps;
+  coarse_medium -- a medium given on a 64^3 node grid over the 256^3 box: upsampled once
+              to the nodes (set-up reading) vs sampled inside the step kernels at every
+              value's own position (in-kernel reading), 300 steps each;
   paper_table6 -- the paper's own GLSL and CPU totals per level, with their hardware
               (context only, not a target);
   cpu_baseline -- the FP64 oracle on a bounded sample on this host's cores (and, as
               one_core, on a single core over an eighth of the steps).
 
     python bench.py [--steps 20] [--warmup 5] [--gpus 1] [--no-c2] [--no-batch] [--no-grad]
-                    [--no-levels] [--no-born] [--cpu-steps 24]
+                    [--no-levels] [--no-born] [--no-coarse] [--cpu-steps 24]
 """
 from __future__ import annotations
 
@@ -361,6 +364,51 @@ def bench_batch(reps=3):
                 lockstep_gcs=round(cells_steps / t_lock / 1e9, 3), group_mib=tune["group_mib"],
                 tile=[tune["tile_x"], tune["tile_y"]], tile2=[tune["tile2_x"], tune["tile2_y"]],
                 workgroups=tune["workgroups"], cell_steps=cells_steps)
+
+
+def bench_coarse_medium(K=300, reps=3, coarse=(64, 64, 64), shape=(256, 256, 256)):
+    """The two readings of a coarse medium (Sec. 2.2.1) on the 256^3 grid: the six-layer +
+    perturbed generator on a 64^3 node grid over the same box (40.5 m node spacing), with
+    the 256^3 workload's source, receivers, spacing and dt.  A: sampled once at the
+    simulation nodes (fd3d_upsample, outside the clock), then the step kernels take node
+    means (120 B per cell-step); B: the step kernels read the coarse arrays themselves,
+    trilinear samples at every value's own position (108 B per cell-step: no model arrays
+    streamed, the coarse ones stay cached).  K steps from a zero state, median of reps."""
+    import torch
+
+    import workloads as W
+    from paper_2112_15071_amd import Simulator, upsample
+
+    dev = torch.device("cuda:0")
+    nx, ny, nz = shape
+    mx, my, mz = coarse
+    shot = W.c1(nt=K)
+    hc = 10.0 * (nx - 1) / (mx - 1)
+    model_c = [torch.as_tensor(a, dtype=torch.float32, device=dev) for a in W.layered_perturbed(coarse, hc, 1001)]
+    model_n = [upsample(a, shape) for a in model_c]
+    wav = torch.as_tensor(shot.wavelet[:K], dtype=torch.float32, device=dev)
+    zero = torch.zeros((9, nz, ny, nx), dtype=torch.float32, device=dev)
+    traces = torch.empty((len(shot.rec_pos), 3, K), dtype=torch.float32, device=dev)
+    out = {}
+    for name, model, grid in (("setup_upsample", model_n, None), ("in_kernel", model_c, shape)):
+        sim = Simulator(*model, shot.h, shot.dt, K, sponge=shot.sponge, device=dev, grid=grid)
+        sim.autotune(steps=10)
+        run = lambda: sim.forward(shot.src_pos, shot.moment, shot.force, wav, shot.rec_pos, keep_state=True,
+                                  traces=traces)
+        sim.set_state(zero)
+        run()
+        el, ts = median_time(run, reps, prep=lambda: sim.set_state(zero))
+        gcs = nx * ny * nz * K / el / 1e9
+        b = 120 if grid is None else 108
+        out[name] = dict(gcs=round(gcs, 3), ms_per_step=round(el / K * 1e3, 4), kernel=sim.kernel(),
+                         bytes_per_cell_step=b, hbm_gbs=round(b * nx * ny * nz * K / el / 1e9, 1))
+        log(f"[bench] coarse medium {name}: {gcs:.2f} Gcell-steps/s ({el / K * 1e3:.4f} ms/step), {sim.kernel()}")
+        sim.close()
+    out["speedup_in_kernel"] = round(out["in_kernel"]["gcs"] / out["setup_upsample"]["gcs"], 4)
+    out["coarse_nodes"] = list(coarse)
+    out["grid"] = list(shape)
+    out["steps"] = K
+    return out
 
 
 # Born (tangent-linear) forward, per cell and step, with the tile kernels: the background's
@@ -704,6 +752,7 @@ def parse_args(argv=None):
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-levels", action="store_true", help="skip the Table 5 level sweep")
     ap.add_argument("--no-born", action="store_true", help="skip the Born (tangent-linear) section")
+    ap.add_argument("--no-coarse", action="store_true", help="skip the coarse-medium A/B section")
     ap.add_argument("--kernel", metavar="VARIANT,TX,TY,ZC", default=None,
                     help="forward kernel configuration (default: autotuned, cached per grid)")
     ap.add_argument("--grad-shots", type=int, default=8, help="shots of the gradient section (profiling runs: fewer)")
@@ -776,7 +825,8 @@ def build_line(args, r, errors):
                            "achieved_wall": round(f["wall_gbs"], 1),
                            "frac_wall": round(f["wall_gbs"] / HBM_PEAK_GBS, 4)},
         }
-    for key in ("c1_full", "stream_copy_gbs", "c2_forward", "batched_forward", "gradient", "levels", "born"):
+    for key in ("c1_full", "stream_copy_gbs", "c2_forward", "batched_forward", "gradient", "levels", "born",
+                "coarse_medium"):
         out[key] = r.get(key)
     out["paper_table6"] = paper_context()
     out["cpu_baseline"] = r.get("cpu_baseline")
@@ -830,6 +880,7 @@ def main(argv=None):
         ("gradient", (lambda: None) if args.no_grad else (lambda: bench_gradient(nshots=args.grad_shots))),
         ("levels", (lambda: None) if args.no_levels else bench_levels),
         ("born", (lambda: None) if args.no_born else bench_born),
+        ("coarse_medium", (lambda: None) if args.no_coarse else bench_coarse_medium),
         ("cpu_baseline", cpu),
     ]
     results, errors = run_sections(args, sections)

@@ -95,6 +95,19 @@ typedef struct fd3d_opts {
                           * must stay alive and unchanged while the context is used).  A
                           * sample between columns (half position in x or y) takes the
                           * deepest plane beside it.  NULL: vacuum_top everywhere. */
+    int coarse[3];       /* all >= 2: coarse medium (Sec. 2.2.1: medium textures smaller than
+                          * the simulation grid, every read a trilinear sample).  lam, mu, rho
+                          * given to fd3d_create are then node arrays of (mx, my, mz) =
+                          * coarse[0..2] nodes spanning the same box as the simulation grid
+                          * (simulation coordinate x sits at coarse coordinate
+                          * x (m - 1) / (n - 1)), and the step kernels read every medium value
+                          * as the trilinear sample at its own position: rho at the three
+                          * velocity samples, lambda and mu at the nodes, mu at the three shear
+                          * samples (instead of means of node values).  Forward only (no
+                          * gradient, Born or batch), tile kernels only, not with vacuum_top.
+                          * fd3d_upsample followed by node arrays is the other reading of a
+                          * coarse medium: it differs where a mean straddles a coarse node.
+                          * All 0: lam, mu, rho are node arrays of the simulation grid. */
 } fd3d_opts;
 
 typedef struct fd3d_source {
@@ -313,12 +326,13 @@ typedef struct fd3d_kernel {
 int fd3d_set_kernel(fd3d_ctx *ctx, const fd3d_kernel *k);
 int fd3d_get_kernel(const fd3d_ctx *ctx, fd3d_kernel *k);
 
-/* Autotuner: times the cell kernel and every supported tile shape with z chunks of 4, 8,
- * 16, 32, 64 and 128 planes and fused shape with 8 ... 128 (the chunks that fit the grid)
- * for `steps` steps on this context (a warm-up and a timed run each, no source, on the
- * caller's stream; waits for each timing), keeps the fastest for later calls and writes
- * it to *best (and its ms per step to *best_ms) when non-NULL.  The forward state is
- * zeroed afterwards. */
+/* Autotuner: times the cell kernel and every supported tile and fused shape with z chunks
+ * of 4, 8, 16, 32, 64 and 128 planes and of ceil(nz / m) planes for m = 1 .. 8 (the whole
+ * depth and its even splits; fused from 8 planes; the chunks that fit the grid) for
+ * `steps` steps on this context (a warm-up and two timed runs each, the faster counting;
+ * no source; on the caller's stream; waits for each timing), keeps the fastest for later
+ * calls and writes it to *best (and its ms per step to *best_ms) when non-NULL.  The
+ * forward state is zeroed afterwards. */
 int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, void *hip_stream);
 
 /* Per-kernel timing of the step loop.  With enable = 1, later forward calls record a

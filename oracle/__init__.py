@@ -53,6 +53,7 @@ class _Cfg(ctypes.Structure):
         ("vacuum_map", ctypes.POINTER(ctypes.c_int)),
         ("sponge", ctypes.c_int * 6),
         ("alpha", ctypes.c_double),
+        ("coarse", ctypes.c_int * 3),
     ]
 
 
@@ -87,6 +88,8 @@ def _load():
         ]
         lib.oracle_born.restype = ctypes.c_int
         lib.oracle_profiles.argtypes = [ctypes.POINTER(_Cfg), dp]
+        lib.oracle_medium.argtypes = [ctypes.POINTER(_Cfg), dp, dp, dp, dp]
+        lib.oracle_medium.restype = ctypes.c_int
         lib.oracle_deriv1d.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp]
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_get_threads.restype = ctypes.c_int
@@ -109,6 +112,9 @@ class Config:
     periodic: Sequence[bool] = (False, False, False)
     vacuum_top: int = 0  # > 0: vacuum formulation, first solid node plane
     vacuum_map: Optional[np.ndarray] = None  # [ny, nx] first solid plane per column (topography)
+    # (mx, my, mz): the medium arrays are a coarse node grid over the same box, sampled
+    # trilinearly at every value's own position (Sec. 2.2.1); None: node arrays
+    coarse: Optional[Sequence[int]] = None
 
     def _c(self) -> _Cfg:
         c = _Cfg()
@@ -135,7 +141,18 @@ class Config:
         for f in range(6):
             c.sponge[f] = int(sp[f])
         c.alpha = float(self.alpha)
+        if self.coarse is not None:
+            for a in range(3):
+                c.coarse[a] = int(self.coarse[a])
         return c
+
+    @property
+    def medium_zyx(self):
+        """Shape of the medium arrays: the coarse grid's, or the simulation grid's."""
+        if self.coarse is None:
+            return self.zyx
+        mx, my, mz = (int(v) for v in self.coarse)
+        return (mz, my, mx)
 
     @property
     def zyx(self):
@@ -190,7 +207,7 @@ def forward(cfg: Config, lam, mu, rho, src: Optional[Source] = None, wavelet=Non
     """
     lib = _load()
     zyx = cfg.zyx
-    lam, mu, rho = (_f64(a, zyx) for a in (lam, mu, rho))
+    lam, mu, rho = (_f64(a, cfg.medium_zyx) for a in (lam, mu, rho))
     wav = None if wavelet is None else _f64(wavelet, (cfg.nt,))
     rp = np.zeros((0, 3)) if rec_pos is None else _f64(rec_pos)
     rp = rp.reshape(-1, 3)
@@ -280,6 +297,22 @@ def misfit(traces, d_obs) -> float:
     """J = 1/2 sum (d - d_obs)^2 (no dt weighting)."""
     r = np.asarray(traces) - np.asarray(d_obs)
     return 0.5 * float(np.sum(r * r))
+
+
+MEDIUM = ("rho_vx", "rho_vy", "rho_vz", "lam", "mu", "mu_xy", "mu_xz", "mu_yz")
+
+
+def medium(cfg: Config, lam, mu, rho) -> np.ndarray:
+    """The medium values the scheme uses (Sec. 2.2.1), [8, nz, ny, nx] in the order of
+    MEDIUM: rho at the three velocity samples, lambda and mu at the nodes, mu at the three
+    shear samples (zero at pinned samples); node means of node arrays, or trilinear samples
+    of a coarse grid when ``cfg.coarse`` is set."""
+    lib = _load()
+    lam, mu, rho = (_f64(a, cfg.medium_zyx) for a in (lam, mu, rho))
+    out = np.zeros((8,) + cfg.zyx)
+    if lib.oracle_medium(ctypes.byref(cfg._c()), _ptr(lam), _ptr(mu), _ptr(rho), _ptr(out)):
+        raise ValueError("oracle_medium failed")
+    return out
 
 
 def upsample(coarse, shape) -> np.ndarray:

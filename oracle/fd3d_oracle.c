@@ -74,6 +74,10 @@ typedef struct {
                               (topography); NULL: vacuum_top everywhere */
     int sponge[6];     /* damping width in cells: x-, x+, y-, y+, z- (top), z+ */
     double alpha;      /* Cerjan coefficient; <= 0 selects 0.3 / width per face */
+    int coarse[3];     /* all > 0: the medium arrays hold a coarse node grid (mx, my, mz)
+                          spanning the same box, and every medium value is a trilinear
+                          sample of it at the value's own position (see coarse_at); all
+                          0: the medium arrays are given at the simulation nodes */
 } oracle_cfg;
 
 typedef struct {
@@ -216,9 +220,46 @@ static double dminus_v(const oracle_cfg *c, const double *f, int comp, int axis,
     return (C1 * (g0 - gm1) + C2 * (gp1 - gm2)) / c->h[axis];
 }
 
+/* Coarse medium (Sec. 2.2.1: the medium textures may be smaller than the simulation grid,
+ * every read being a trilinear sample).  Reading: both grids span the same box corner node
+ * to corner node, so simulation coordinate x (grid units, integer or half-integer) sits at
+ * coarse coordinate X = x (m - 1) / (n - 1) per axis (an axis of m = 1 is constant); the
+ * value is the trilinear interpolation of the eight coarse nodes around X -- the texture
+ * read at the sample's own position, with no further averaging. */
+static double coarse_at(const oracle_cfg *c, const double *m, double x, double y, double z)
+{
+    const double q[3] = {x, y, z};
+    long lo[3], hi[3];
+    double f[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        const int cm = c->coarse[ax], n = c->n[ax];
+        double X = (cm > 1) ? q[ax] * (double)(cm - 1) / (double)(n - 1) : 0.0;
+        if (X < 0.0) X = 0.0;
+        if (X > cm - 1) X = cm - 1;
+        long b = (long)floor(X);
+        if (b > cm - 2) b = cm - 2;
+        if (b < 0) b = 0;
+        lo[ax] = b;
+        hi[ax] = cm > 1 ? b + 1 : b;
+        f[ax] = cm > 1 ? X - (double)b : 0.0;
+    }
+    double v = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+                const long i = dx ? hi[0] : lo[0], j = dy ? hi[1] : lo[1], k = dz ? hi[2] : lo[2];
+                v += w * m[i + (long)c->coarse[0] * (j + (long)c->coarse[1] * k)];
+            }
+    return v;
+}
+
+static int is_coarse(const oracle_cfg *c) { return c->coarse[0] > 0; }
+
 /* Model value at a node (wrapping on periodic axes). */
 static double node(const oracle_cfg *c, const double *m, long i, long j, long k)
 {
+    if (is_coarse(c)) return coarse_at(c, m, (double)i, (double)j, (double)k);
     long a = 0, b = 0, d = 0;
     map_axis(c, 0, 0, i, &a);
     map_axis(c, 1, 0, j, &b);
@@ -230,6 +271,7 @@ static double node(const oracle_cfg *c, const double *m, long i, long j, long k)
 static double rho_eff(const ctx_t *x, int comp, long i, long j, long k)
 {
     long e0 = comp == VX, e1 = comp == VY, e2 = comp == VZ;
+    if (is_coarse(x->c)) return coarse_at(x->c, x->rho, i + 0.5 * e0, j + 0.5 * e1, k + 0.5 * e2);
     return (node(x->c, x->rho, i, j, k) + node(x->c, x->rho, i + e0, j + e1, k + e2)) / 2.0;
 }
 
@@ -237,6 +279,7 @@ static double rho_eff(const ctx_t *x, int comp, long i, long j, long k)
 static double mu_eff(const ctx_t *x, int comp, long i, long j, long k)
 {
     long a0 = STAG[comp][0], a1 = STAG[comp][1], a2 = STAG[comp][2];
+    if (is_coarse(x->c)) return coarse_at(x->c, x->mu, i + 0.5 * a0, j + 0.5 * a1, k + 0.5 * a2);
     /* the two staggered axes of this component */
     long u[3] = {0, 0, 0}, w[3] = {0, 0, 0};
     int first = 1;
@@ -477,6 +520,10 @@ static int check_cfg(const oracle_cfg *c)
     if (c->free_surface && c->periodic[2]) return -1;
     if (c->vacuum_top < 0 || c->vacuum_top >= c->n[2] || (c->vacuum_top > 0 && (c->free_surface || c->periodic[2])))
         return -1;
+    if (c->coarse[0] || c->coarse[1] || c->coarse[2]) {
+        for (int a = 0; a < 3; ++a)
+            if (c->coarse[a] < 1 || c->periodic[a]) return -1;
+    }
     if (c->vacuum_map) {
         if (c->vacuum_top <= 0) return -1;
         for (long q = 0; q < (long)c->n[0] * c->n[1]; ++q)
@@ -533,7 +580,7 @@ int oracle_born(const oracle_cfg *cfg, const double *lam, const double *mu, cons
                 const double *dlam, const double *dmu, const double *drho, const oracle_src *src,
                 const double *wavelet, int nrec, const double *rec_pos, double *traces, double *dtraces)
 {
-    if (check_cfg(cfg) || cfg->free_surface || cfg->vacuum_top) return -1;
+    if (check_cfg(cfg) || cfg->free_surface || cfg->vacuum_top || is_coarse(cfg)) return -1;
     const oracle_cfg *c = cfg;
     ctx_t x = {cfg, lam, mu, rho, {{0}}};
     ctx_t dx = {cfg, dlam, dmu, drho, {{0}}};  /* perturbation arrays, for the same means */
@@ -628,7 +675,7 @@ int oracle_gradient(const oracle_cfg *cfg, const double *lam, const double *mu, 
                     const double *residual, const double *state0, double *g_lam, double *g_mu,
                     double *g_rho, double *adj_state)
 {
-    if (check_cfg(cfg) || cfg->free_surface || cfg->vacuum_top) return -1;
+    if (check_cfg(cfg) || cfg->free_surface || cfg->vacuum_top || is_coarse(cfg)) return -1;
     const oracle_cfg *c = cfg;
     ctx_t x = {cfg, lam, mu, rho, {{0}}};
     build_profiles(&x);
@@ -807,6 +854,29 @@ int oracle_gradient(const oracle_cfg *cfg, const double *lam, const double *mu, 
 }
 
 /* Damping profiles as built above, exported for the pins: out[ax][half][n]. */
+/* The medium values the scheme uses (Sec. 2.2.1), eight arrays [nz][ny][nx] into out:
+ * rho at the vx, vy, vz samples, lambda and mu at the nodes, mu at the sxy, sxz, syz
+ * samples; zero at inactive (pinned) samples.  Node means of node arrays, or trilinear
+ * samples of a coarse grid (cfg->coarse). */
+int oracle_medium(const oracle_cfg *cfg, const double *lam, const double *mu, const double *rho, double *out)
+{
+    if (check_cfg(cfg)) return -1;
+    ctx_t x = {cfg, lam, mu, rho, {{0}}};
+    long N = nodes(cfg);
+    for (long k = 0; k < cfg->n[2]; ++k)
+        for (long j = 0; j < cfg->n[1]; ++j)
+            for (long i = 0; i < cfg->n[0]; ++i) {
+                long p = lin(cfg, i, j, k);
+                for (int comp = VX; comp <= VZ; ++comp)
+                    out[(comp - VX) * N + p] = active(cfg, comp, i, j, k) ? rho_eff(&x, comp, i, j, k) : 0.0;
+                out[3 * N + p] = node(cfg, lam, i, j, k);
+                out[4 * N + p] = node(cfg, mu, i, j, k);
+                for (int comp = SXY; comp <= SYZ; ++comp)
+                    out[(5 + comp - SXY) * N + p] = active(cfg, comp, i, j, k) ? mu_eff(&x, comp, i, j, k) : 0.0;
+            }
+    return 0;
+}
+
 int oracle_profiles(const oracle_cfg *cfg, double *out)
 {
     ctx_t x = {cfg, NULL, NULL, NULL, {{0}}};

@@ -54,6 +54,7 @@ class fd3d_opts(ctypes.Structure):
         ("dz", ctypes.c_double),
         ("vacuum_top", ctypes.c_int),
         ("vacuum_map", ctypes.c_void_p),
+        ("coarse", ctypes.c_int * 3),
     ]
 
 

@@ -47,7 +47,47 @@ template <typename T> struct Grid {
                            // the velocity pass stores v^{n+1/2}, the stress pass sigma^n
     int ks;                // vacuum surface: first solid node plane (0: no vacuum)
     const int *ksmap;      // optional first solid plane per node column [ny][nx] (topography)
+    int cm[3];             // coarse medium: lam, mu, rho hold (mx, my, mz) nodes (cm[0] = 0: node arrays)
+    T cs[3];               // (m - 1) / (n - 1) per axis: coarse coordinate per grid unit
 };
+
+// Coarse medium (Sec. 2.2.1: the medium textures may be smaller than the simulation grid,
+// every read a trilinear sample).  The coarse node grid spans the same box as the
+// simulation grid, so coordinate x (grid units, integer or half-integer) sits at coarse
+// coordinate X = x (m - 1) / (n - 1); a medium value is the trilinear interpolation of the
+// eight coarse nodes around the value's own position.  Per axis: the lower coarse node and
+// the weight of the upper one (m >= 2; positions past the last node extrapolate from the
+// last cell, which only pinned samples reach).
+template <typename T> struct CoarseAxis {
+    int lo;
+    T f;
+};
+
+template <typename T> __device__ __forceinline__ CoarseAxis<T> coarse_axis(T x, T scale, int m)
+{
+    const T X = x * scale;
+    const int b = (int)X;  // X >= 0
+    const int lo = b < m - 2 ? b : m - 2;
+    return {lo, X - (T)lo};
+}
+
+// Bilinear sample of coarse plane kc at the column (ax, ay) of a coarse array with mx
+// nodes per row and mxy per plane.
+template <typename T>
+__device__ __forceinline__ T coarse_bil(const T *a, int mx, int mxy, const CoarseAxis<T> &ax,
+                                        const CoarseAxis<T> &ay, int kc)
+{
+    const T *p = a + (long)kc * mxy + (long)ay.lo * mx + ax.lo;
+    const T lo = (T(1) - ax.f) * p[0] + ax.f * p[1];
+    const T hi = (T(1) - ax.f) * p[mx] + ax.f * p[mx + 1];
+    return (T(1) - ay.f) * lo + ay.f * hi;
+}
+
+template <typename T> __device__ __forceinline__ T lerp_w(T a, T b, T f) { return (T(1) - f) * a + f * b; }
+
+// Reciprocal of a sampled density (FP32: the hardware reciprocal, as buoy).
+__device__ __forceinline__ float rcp_rho(float r) { return __builtin_amdgcn_rcpf(r); }
+__device__ __forceinline__ double rcp_rho(double r) { return 1.0 / r; }
 
 // First solid planes seen by the samples of column (i, j): at the node, and between
 // columns i, i+1 (x half positions) and rows j, j+1 (y half positions), where a sample

@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -111,6 +112,11 @@ int check_opts(const fd3d_opts *o)
     if (o->vacuum_top > 0 && o->free_surface)
         return fail(FD3D_EINVAL, "opts.vacuum_top and opts.free_surface exclude each other");
     if (o->vacuum_map && o->vacuum_top <= 0) return fail(FD3D_EINVAL, "opts.vacuum_map needs opts.vacuum_top > 0");
+    if (o->coarse[0] || o->coarse[1] || o->coarse[2]) {
+        for (int a = 0; a < 3; ++a)
+            if (o->coarse[a] < 2) return fail(FD3D_EINVAL, "opts.coarse needs >= 2 nodes per axis (or all 0)");
+        if (o->vacuum_top > 0) return fail(FD3D_EINVAL, "opts.coarse with opts.vacuum_top is not supported");
+    }
     return FD3D_OK;
 }
 
@@ -124,6 +130,9 @@ fd3d_opts default_opts()
 }
 
 int max_rec_of(const fd3d_opts &o) { return o.max_receivers > 0 ? o.max_receivers : kDefaultMaxRec; }
+
+// The medium arrays are a coarse grid read by trilinear samples (opts.coarse).
+bool coarse_on(const fd3d_opts &o) { return o.coarse[0] > 0; }
 
 // Cerjan factor of one face at distance d (cells) from it.
 double face_factor(double d, int width, double alpha)
@@ -174,6 +183,9 @@ struct fd3d_ctx {
     std::vector<unsigned char> rec_host;   // receiver descriptors, kept for the async upload
     std::vector<int> color_host;           // receivers grouped by colour, kept for the async upload
     std::vector<int> color_off;            // colour c holds color_host[color_off[c] .. color_off[c+1])
+    std::vector<unsigned char> src_dev;    // source coefficients now in the workspace
+    std::vector<double> rec_dev;           // receiver positions whose descriptors are in the workspace
+    bool rec_dev_valid;                    // rec_dev describes the workspace's descriptors
     hipEvent_t staged;     // marks the end of the uploads from the host staging buffers;
                            // null in a context that must create no HIP objects (its call
                            // synchronises the stream before the buffers are released)
@@ -211,6 +223,10 @@ template <typename T> Grid<T> make_grid(const fd3d_ctx *c)
     G.rdz = (T)(1.0 / c->dz);
     G.ks = c->opts.vacuum_top;
     G.ksmap = (const int *)c->opts.vacuum_map;
+    for (int a = 0; a < 3; ++a) {
+        G.cm[a] = coarse_on(c->opts) ? c->opts.coarse[a] : 0;
+        G.cs[a] = G.cm[a] ? (T)((double)(G.cm[a] - 1) / (double)(c->n[a] - 1)) : T(0);
+    }
     G.lam = (const T *)c->lam;
     G.mu = (const T *)c->mu;
     G.rho = (const T *)c->rho;
@@ -248,7 +264,11 @@ template <typename T> int upload_profiles(fd3d_ctx *c, hipStream_t st)
 
 template <typename T> int model_check(fd3d_ctx *c, hipStream_t st)
 {
-    const long N = (long)c->n[0] * c->n[1] * c->n[2];
+    // statistics over the medium's own nodes; with a coarse medium every sample is a convex
+    // combination of coarse nodes, so their extremes bound the sampled ones (vp, vs by the
+    // mediant inequality)
+    const fd3d_opts &o = c->opts;
+    const long N = coarse_on(o) ? (long)o.coarse[0] * o.coarse[1] * o.coarse[2] : (long)c->n[0] * c->n[1] * c->n[2];
     double *part = (double *)(c->ws + c->L.part);
     double *out = (double *)(c->ws + c->L.stats);
     model_stats<T><<<kReduceBlocks, kReduceThreads, 0, st>>>((const T *)c->lam, (const T *)c->mu,
@@ -348,12 +368,20 @@ int stage_inputs(fd3d_ctx *c, const fd3d_source *src, Inject<T> &inj, int nrec, 
     }
     int rc = build_source<T>(c, src, inj);
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(c->ws + c->L.src, c->src_host.data(), c->src_host.size(), hipMemcpyHostToDevice, st));
-    if (c->staged) {
-        HIP_TRY(hipEventRecord(c->staged, st));
-        c->staged_pending = true;
+    // inputs equal to the ones already in the workspace (a repeated shot) are not staged again
+    if (c->src_host != c->src_dev) {
+        HIP_TRY(hipMemcpyAsync(c->ws + c->L.src, c->src_host.data(), c->src_host.size(), hipMemcpyHostToDevice, st));
+        c->src_dev = c->src_host;
+        if (c->staged) {
+            HIP_TRY(hipEventRecord(c->staged, st));
+            c->staged_pending = true;
+        }
     }
     if (nrec == 0) return FD3D_OK;
+    if (c->rec_dev_valid && c->rec_dev.size() == (size_t)nrec * 3 &&
+        std::memcmp(c->rec_dev.data(), rec_pos, (size_t)nrec * 3 * sizeof(double)) == 0)
+        return FD3D_OK;
+    c->rec_dev_valid = false;
     c->rec_host.assign((size_t)nrec * 3 * sizeof(RecTap<T>), 0);
     RecTap<T> *t = (RecTap<T> *)c->rec_host.data();
     int base[3];
@@ -403,6 +431,8 @@ int stage_inputs(fd3d_ctx *c, const fd3d_source *src, Inject<T> &inj, int nrec, 
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.rec, c->rec_host.data(), c->rec_host.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.colors, c->color_host.data(), c->color_host.size() * sizeof(int),
                            hipMemcpyHostToDevice, st));
+    c->rec_dev.assign(rec_pos, rec_pos + (size_t)nrec * 3);
+    c->rec_dev_valid = true;
     if (c->staged) {
         HIP_TRY(hipEventRecord(c->staged, st));
         c->staged_pending = true;
@@ -512,6 +542,7 @@ bool window_ok(const fd3d_ctx *c, int zc)
 constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
 inline bool stream_model(const fd3d_ctx *c)
 {
+    if (coarse_on(c->opts)) return false;  // the coarse medium is small and stays cached
     return 12.0 * (double)c->n[0] * (double)c->n[1] * (double)c->n[2] * (double)c->tsize > kInfinityCacheBytes;
 }
 
@@ -526,6 +557,11 @@ void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &
     const int nws = nwg + rec_blocks(rec, NT);
     if (G.save[VX] != nullptr && pass == kPassVel) pass = kPassVelSave;
     if (G.save[VX] != nullptr && pass == kPassStress) pass = kPassStressSave;
+    if (G.cm[0] > 0) {  // coarse medium: instantiations of their own (forward passes only)
+        if (pass == kPassVel) vel_tile<T, TX, TY, FS, kFwd, false, false, true><<<nwg, NT, 0, st>>>(G, inj, n, tm);
+        else stress_tile<T, TX, TY, FS, kFwd, false, false, true><<<nws, NT, 0, st>>>(G, inj, n, tm, rec);
+        return;
+    }
     if constexpr (!FS) {  // the vacuum surface has instantiations of its own (forward only)
         if (G.ks > 0 && pass == kPassVel) {
             vel_tile<T, TX, TY, false, kFwd, true, NTP><<<nwg, NT, 0, st>>>(G, inj, n, tm);
@@ -607,7 +643,7 @@ void step(fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int nrec, 
 // Fused tile shapes: FP32 64x4 and 64x8, FP64 64x4.
 bool fused_supported(const fd3d_ctx *c, int tx, int ty)
 {
-    return c->opts.vacuum_top == 0 && tx == 64 && (ty == 4 || (ty == 8 && c->tsize == 4));
+    return c->opts.vacuum_top == 0 && !coarse_on(c->opts) && tx == 64 && (ty == 4 || (ty == 8 && c->tsize == 4));
 }
 
 // Arguments of one fused step from the current state copy into the other one.
@@ -1281,8 +1317,11 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
         const int rc = batch_sequence<T>(b, flags, b->cap);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(b->cap, &g);
-        if (rc) return rc;
-        if (e != hipSuccess) return fail(FD3D_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        if (rc || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);  // a partial capture is not kept
+            if (rc) return rc;
+            return fail(FD3D_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        }
         b->graph = g;
         HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
         b->graph_valid = true;
@@ -1296,6 +1335,7 @@ int check_gws(const fd3d_ctx *ctx, void *gws, size_t gws_bytes, int k)
 {
     if (ctx->opts.free_surface || ctx->opts.vacuum_top)
         return fail(FD3D_EINVAL, "the gradient supports damped boundaries only (no free surface)");
+    if (coarse_on(ctx->opts)) return fail(FD3D_EINVAL, "the gradient needs the medium at the simulation nodes");
     if (ctx->nt < 1) return fail(FD3D_EINVAL, "gradient needs nt >= 1");
     if (k < 1 || k > ctx->nt) return fail(FD3D_EINVAL, "ckpt_every must be in [1, nt]");
     if (!gws || ((uintptr_t)gws % kAlign)) return fail(FD3D_EINVAL, "gradient workspace must be 256-byte aligned");
@@ -1675,6 +1715,7 @@ int create_ctx(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const vo
     c->ws_bytes = ws_bytes;
     c->L = make_layout(nx, ny, nz, c->tsize, c->opts.max_receivers);
     c->staged_pending = false;
+    c->rec_dev_valid = false;
     c->prof_on = 0;
     c->prof_used = 0;
     c->grad_ws = nullptr;
@@ -1690,6 +1731,10 @@ int create_ctx(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const vo
     c->zchunk = nz >= 128 ? 64 : 32;
     while (!window_ok(c, c->zchunk) && c->zchunk > 4) c->zchunk /= 2;
     if (!window_ok(c, c->zchunk)) c->variant = FD3D_KERNEL_CELL;  // planes too large for a tile sweep
+    if (coarse_on(c->opts) && c->variant != FD3D_KERNEL_TILE) {
+        delete c;
+        return fail(FD3D_EINVAL, "planes too large for the tile kernels, which a coarse medium needs");
+    }
     c->staged = nullptr;
     if (events && hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess) {
         delete c;
@@ -1916,6 +1961,8 @@ int fd3d_born(fd3d_ctx *ctx, fd3d_ctx *dctx, const fd3d_source *src, const void 
     if (ctx->opts.sponge_alpha != dctx->opts.sponge_alpha) return fail(FD3D_EINVAL, "contexts differ in damping");
     if (ctx->opts.free_surface || dctx->opts.free_surface || ctx->opts.vacuum_top || dctx->opts.vacuum_top)
         return fail(FD3D_EINVAL, "the Born forward supports damped boundaries only (no free surface)");
+    if (coarse_on(ctx->opts) || coarse_on(dctx->opts))
+        return fail(FD3D_EINVAL, "the Born forward needs the medium at the simulation nodes");
     if (ctx->variant == FD3D_KERNEL_FUSED || dctx->variant == FD3D_KERNEL_FUSED)
         return fail(FD3D_EINVAL, "the Born forward runs the tile or cell kernels (set one with fd3d_set_kernel)");
     hipStream_t st = (hipStream_t)hip_stream;
@@ -1971,6 +2018,8 @@ int fd3d_set_kernel(fd3d_ctx *ctx, const fd3d_kernel *k)
         return fail(FD3D_EINVAL, "unsupported fused tile shape " + std::to_string(k->tile_x) + "x" +
                                      std::to_string(k->tile_y));
     if (k->zchunk < 4) return fail(FD3D_EINVAL, "zchunk must be >= 4");
+    if (coarse_on(ctx->opts) && k->variant != FD3D_KERNEL_TILE)
+        return fail(FD3D_EINVAL, "a coarse medium runs on the tile kernels only");
     if (k->variant != FD3D_KERNEL_CELL && !window_ok(ctx, k->zchunk))
         return fail(FD3D_EINVAL, "zchunk too large: (zchunk + 8) planes must fit in 1 GiB");
     ctx->variant = k->variant;
@@ -2014,6 +2063,8 @@ int fd3d_batch_create(fd3d_batch **out, int nshot, fd3d_ctx *const *ctxs, void *
         if (ctxs[s]->nt != ctxs[0]->nt) return fail(FD3D_EINVAL, "all shots must share nt");
         if (ctxs[s]->opts.free_surface != ctxs[0]->opts.free_surface)
             return fail(FD3D_EINVAL, "all shots must share the free-surface option");
+        if (coarse_on(ctxs[s]->opts))
+            return fail(FD3D_EINVAL, "context " + std::to_string(s) + ": a batch needs media at the simulation nodes");
         if (!window_ok(ctxs[s], ctxs[s]->zchunk))
             return fail(FD3D_EINVAL, "context " + std::to_string(s) + ": zchunk too large for a tile sweep");
         for (int q = 0; q < s; ++q)
@@ -2253,7 +2304,15 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
     static const int shapes[][3] = {{FD3D_KERNEL_CELL, 64, 4},   {FD3D_KERNEL_TILE, 64, 4},   {FD3D_KERNEL_TILE, 64, 8},
                                     {FD3D_KERNEL_TILE, 64, 16},  {FD3D_KERNEL_TILE, 128, 4},  {FD3D_KERNEL_TILE, 128, 8},
                                     {FD3D_KERNEL_TILE, 256, 4},  {FD3D_KERNEL_FUSED, 64, 4},  {FD3D_KERNEL_FUSED, 64, 8}};
-    static const int chunks[] = {4, 8, 16, 32, 64, 128};
+    // z chunks: powers of two, and the depths that cut the grid into m equal sweeps
+    // (m = 1 .. 8), so that the workgroup count can match whole rounds of the CUs (on a
+    // 512 x 512 x 256 grid, 256 x 4 tiles sweeping all 256 planes are one workgroup per CU)
+    std::vector<int> chunks = {4, 8, 16, 32, 64, 128};
+    for (int m = 1; m <= 8; ++m) {
+        const int zc = (ctx->n[2] + m - 1) / m;
+        if (zc >= 4 && std::find(chunks.begin(), chunks.end(), zc) == chunks.end()) chunks.push_back(zc);
+    }
+    std::sort(chunks.begin(), chunks.end());
     const int nt_save = ctx->nt;
     const fd3d_kernel keep = {ctx->variant, ctx->tile_x, ctx->tile_y, ctx->zchunk};
     fd3d_kernel win = keep;
@@ -2265,6 +2324,7 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
     int rc = FD3D_OK;
     for (const auto &sh : shapes) {
         if (sh[0] == FD3D_KERNEL_TILE && !tile_supported(ctx->tsize, sh[1], sh[2])) continue;
+        if (coarse_on(ctx->opts) && sh[0] != FD3D_KERNEL_TILE) continue;
         if (sh[0] == FD3D_KERNEL_FUSED && !fused_supported(ctx, sh[1], sh[2])) continue;
         if (sh[1] > 64 && ctx->n[0] < sh[1] / 2) continue;  // mostly idle lanes
         for (int zc : chunks) {
@@ -2276,19 +2336,24 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
             ctx->tile_x = sh[1];
             ctx->tile_y = sh[2];
             ctx->zchunk = zc;
-            // one warm-up run, one timed run, both from the current (clobbered) state
-            for (int rep = 0; rep < 2 && !rc; ++rep) {
-                if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(FD3D_EHIP, "hipEventRecord");
+            // one warm-up run and two timed runs (the faster counts), all from the current
+            // (clobbered) state
+            float ms = 3.0e38f;
+            for (int rep = 0; rep < 3 && !rc; ++rep) {
+                if (rep >= 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(FD3D_EHIP, "hipEventRecord");
                 if (!rc) rc = ctx->tsize == 8 ? forward_impl<double>(ctx, nullptr, 0, nullptr, nullptr, FD3D_KEEP_STATE, st)
                                              : forward_impl<float>(ctx, nullptr, 0, nullptr, nullptr, FD3D_KEEP_STATE, st);
+                if (!rc && rep >= 1) {
+                    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                        rc = fail(FD3D_EHIP, "timing events failed");
+                        break;
+                    }
+                    float t = 0.0f;
+                    (void)hipEventElapsedTime(&t, e0, e1);
+                    ms = std::min(ms, t);
+                }
             }
             if (rc) break;
-            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                rc = fail(FD3D_EHIP, "timing events failed");
-                break;
-            }
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
             if (ms < win_ms) {
                 win_ms = ms;
                 win = fd3d_kernel{sh[0], sh[1], sh[2], zc};

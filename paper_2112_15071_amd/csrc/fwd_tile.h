@@ -278,10 +278,14 @@ __device__ __forceinline__ void stage_coef(T *lds, const Inject<T> &src, bool on
 
 // ---------------------------------------------------------------------------------
 // (V) velocity pass, tiled.  Same arithmetic per sample as vel_cell.
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false>
+// CM (forward only): the medium is a coarse node grid read by trilinear samples at the
+// velocity samples' own positions (CoarseAxis); the node density plane and queue are not
+// read.
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false, bool CM = false>
 __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0, int k0,
                                               int k1, const TileIO<T> &io = TileIO<T>{})
 {
+    static_assert(!CM || MODE == kFwd, "the coarse medium is read by the forward passes only");
     constexpr int NT = TX * TY;
     // LDS plane shapes: sxx x(-1,+2); sxy x(-2,+1) y(-2,+1); sxz x(-2,+1); syy y(-1,+2);
     // syz y(-2,+1); rho x(+1) y(+1) with the corner.  The last element is a dummy slot.
@@ -336,7 +340,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     stage_coef<T, VX, 3>(s_coef, src, srcv, tid);
     auto cf = [&](int c, int t) -> T { return t >= 0 ? s_coef[(c - VX) * 8 + (t & 7)] : T(0); };
     constexpr bool fwd = MODE == kFwd || MODE == kFwdSave || MODE == kBornV;
-    constexpr bool use_rho = MODE != kAdjA;
+    constexpr bool use_rho = MODE != kAdjA && !CM;
     constexpr bool up = vel_sweeps_up<MODE>();
     static_assert(!(up && FS), "upward velocity sweeps have no free-surface images");
     const int kfirst = up ? k1 - 1 : k0;
@@ -359,8 +363,25 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         const int kz = kfirst - 1 + m;
         qzz[m] = (FS && kz < 0) ? -zld(fzz, -kz, true) : zld(fzz, kz, true);
     }
-    T r0 = ldm<NTP, T>(wfield(rho, w), oc + wplane(w, kfirst, use_rho));
-    T r1 = ldm<NTP, T>(wfield(rho, w), oc + wplane(w, kfirst + 1, use_rho));
+    T r0 = T(0), r1 = T(0);
+    if constexpr (!CM) {
+        r0 = ldm<NTP, T>(wfield(rho, w), oc + wplane(w, kfirst, use_rho));
+        r1 = ldm<NTP, T>(wfield(rho, w), oc + wplane(w, kfirst + 1, use_rho));
+    }
+    // coarse medium: per-column coarse coordinates of the vx (i + 1/2, j), vy (i, j + 1/2)
+    // and vz (i, j) columns, and the bilinear density samples of the coarse planes that
+    // the current plane's z positions (k for vx, vy; k + 1/2 for vz) lie between,
+    // recomputed only when those coarse planes change (a uniform branch)
+    const int cmx = CM ? G.cm[0] : 0, cmxy = CM ? G.cm[0] * G.cm[1] : 0;
+    CoarseAxis<T> cxn{}, cxh{}, cyn{}, cyh{};
+    if constexpr (CM) {
+        cxn = coarse_axis<T>(T(i), G.cs[0], G.cm[0]);
+        cxh = coarse_axis<T>(T(i) + T(0.5), G.cs[0], G.cm[0]);
+        cyn = coarse_axis<T>(T(j), G.cs[1], G.cm[1]);
+        cyh = coarse_axis<T>(T(j) + T(0.5), G.cs[1], G.cm[1]);
+    }
+    int ck_int = -1, ck_half = -1;
+    T cbx0 = T(0), cbx1 = T(0), cby0 = T(0), cby1 = T(0), cbz0 = T(0), cbz1 = T(0);
     T dr0 = T(0), dr1 = T(0);
     if constexpr (born) {
         dr0 = zld(io.acc[0], kfirst, true);
@@ -396,7 +417,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         P.xz = ld<T>(bxz, hxz.off + pk);
         P.yy = ld<T>(byy, hyy.off + pk);
         P.yz = ld<T>(byz, hyz.off + pk);
-        P.r = ldm<NTP, T>(br, hr.off + pr);
+        if constexpr (!CM) P.r = ldm<NTP, T>(br, hr.off + pr);
+        else P.r = T(0);
         if constexpr (born) P.dr = ld<T>(wfield(io.acc[0], w), hr.off + pr);
     };
     Plane P;
@@ -428,11 +450,35 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
         const T ga0 = P.g0, ga1 = P.g1, ga2 = P.g2;
         const T bvx0 = P.dvx, bvy0 = P.dvy, bvz0 = P.dvz;  // the perturbation's velocity (kBornV)
+        // buoyancy at the three velocity samples: node means (Sec. 2.2.1), or the coarse
+        // medium sampled at each sample's own position (its loads issued before the next
+        // plane's, so that waiting for them leaves the prefetch in flight)
+        T bvx_c = T(0), bvy_c = T(0), bvz_c = T(0);
+        if constexpr (CM) {
+            const CoarseAxis<T> zi = coarse_axis<T>(T(k), G.cs[2], G.cm[2]);
+            const CoarseAxis<T> zh = coarse_axis<T>(T(k) + T(0.5), G.cs[2], G.cm[2]);
+            if (zi.lo != ck_int) {
+                cbx0 = coarse_bil(rho, cmx, cmxy, cxh, cyn, zi.lo);
+                cbx1 = coarse_bil(rho, cmx, cmxy, cxh, cyn, zi.lo + 1);
+                cby0 = coarse_bil(rho, cmx, cmxy, cxn, cyh, zi.lo);
+                cby1 = coarse_bil(rho, cmx, cmxy, cxn, cyh, zi.lo + 1);
+                ck_int = zi.lo;
+            }
+            if (zh.lo != ck_half) {
+                cbz0 = coarse_bil(rho, cmx, cmxy, cxn, cyn, zh.lo);
+                cbz1 = coarse_bil(rho, cmx, cmxy, cxn, cyn, zh.lo + 1);
+                ck_half = zh.lo;
+            }
+            bvx_c = rcp_rho(lerp_w(cbx0, cbx1, zi.f));
+            bvy_c = rcp_rho(lerp_w(cby0, cby1, zi.f));
+            bvz_c = rcp_rho(lerp_w(cbz0, cbz1, zh.f));
+        }
         // loads of the next plane of the sweep and the queue heads (skipped past the chunk)
         const bool more = it + 1 < k1 - k0;
         loadplane(up ? k - 1 : k + 1, more, P);
         const T nxz = zld(fxz, up ? k - 3 : k + 2, more), nyz = zld(fyz, up ? k - 3 : k + 2, more);
-        const T nzz = zld(fzz, up ? k - 2 : k + 3, more), nr = ldm<NTP, T>(wfield(rho, w), oc + wplane(w, up ? k - 1 : k + 2, more && use_rho));
+        const T nzz = zld(fzz, up ? k - 2 : k + 3, more);
+        const T nr = CM ? T(0) : ldm<NTP, T>(wfield(rho, w), oc + wplane(w, up ? k - 1 : k + 2, more && use_rho));
         const T ndr = born ? zld(io.acc[0], up ? k - 1 : k + 2, more) : T(0);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         // second order next to a vacuum surface: vx, vy at integer k, vz at k + 1/2 (only in
@@ -450,7 +496,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                       + dstag(Lxy[ox], Lxy[ox - W3], Lxy[ox + W3], Lxy[ox - 2 * W3], rdy)
                       + dz_or_o2(vxo, qxz[2], qxz[1], qxz[3], qxz[0], rdz);
             if constexpr (fwd) {
-                const T bb = buoy(r0, Lr[ty * WR + tx + 1]);
+                const T bb = CM ? bvx_c : buoy(r0, Lr[ty * WR + tx + 1]);
                 T v = vx0 + dt * bb * d;
                 if (srcv) v += bb * cf(VX, tap_of(src, VX, i, j, k)) * s;
                 v = v * (gxh * gyi * gz_i);
@@ -481,7 +527,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                       + dstag(Lyy[oy + TX], Lyy[oy], Lyy[oy + 2 * TX], Lyy[oy - TX], rdy)
                       + dz_or_o2(vyo, qyz[2], qyz[1], qyz[3], qyz[0], rdz);
             if constexpr (fwd) {
-                const T bb = buoy(r0, Lr[(ty + 1) * WR + tx]);
+                const T bb = CM ? bvy_c : buoy(r0, Lr[(ty + 1) * WR + tx]);
                 T v = vy0 + dt * bb * d;
                 if (srcv) v += bb * cf(VY, tap_of(src, VY, i, j, k)) * s;
                 v = v * (gxi * gyh * gz_i);
@@ -513,7 +559,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                       + dz_or_o2(vzo, qzz[2], qzz[1], qzz[3], qzz[0], rdz);
             const unsigned st_vz = k <= nz - 2 ? oc : kOOB;
             if constexpr (fwd) {
-                const T bb = buoy(r0, r1);
+                const T bb = CM ? bvz_c : buoy(r0, r1);
                 T v = vz0 + dt * bb * d;
                 if (srcv) v += bb * cf(VZ, tap_of(src, VZ, i, j, k)) * s;
                 v = v * (gxi * gyi * gz_h);
@@ -555,10 +601,14 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 
 // ---------------------------------------------------------------------------------
 // (S) stress pass, tiled.  Same arithmetic per sample as stress_cell.
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false>
+// CM (forward only): lambda, mu at the node and mu at the shear samples are trilinear
+// samples of a coarse medium at each sample's own position (CoarseAxis); the node
+// arrays, their halo and the mu ring are not read.
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false, bool CM = false>
 __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0,
                                                  int k0, int k1, const TileIO<T> &io = TileIO<T>{})
 {
+    static_assert(!CM || MODE == kFwd, "the coarse medium is read by the forward passes only");
     constexpr int NT = TX * TY;
     // vx x(-2,+1) y(-1,+2); vy x(-1,+2) y(-2,+1); vz x(-1,+2) y(-1,+2); mu x(+1) y(+1) corner
     constexpr int W3 = TX + 3, H3 = TY + 3, WM = TX + 1, HM = TY + 1;
@@ -614,7 +664,22 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     const unsigned st_xz = (in && i <= nx - 2) ? oc : kOOB;
     const unsigned st_yz = (in && j <= ny - 2) ? oc : kOOB;
     constexpr bool fwd = MODE == kFwd || MODE == kFwdSave || MODE == kBornS;
-    constexpr bool use_model = MODE != kAdjB;
+    constexpr bool use_model = MODE != kAdjB && !CM;
+    // coarse medium: per-column coarse coordinates of the node (i, j), xy (i + 1/2, j + 1/2),
+    // xz (i + 1/2, j) and yz (i, j + 1/2) columns; bilinear samples of the coarse planes
+    // around z = k (lambda, mu at the node, mu at xy) and z = k + 1/2 (mu at xz, yz),
+    // recomputed only when those planes change (a uniform branch)
+    const int cmx = CM ? G.cm[0] : 0, cmxy = CM ? G.cm[0] * G.cm[1] : 0;
+    CoarseAxis<T> cxn{}, cxh{}, cyn{}, cyh{};
+    if constexpr (CM) {
+        cxn = coarse_axis<T>(T(i), G.cs[0], G.cm[0]);
+        cxh = coarse_axis<T>(T(i) + T(0.5), G.cs[0], G.cm[0]);
+        cyn = coarse_axis<T>(T(j), G.cs[1], G.cm[1]);
+        cyh = coarse_axis<T>(T(j) + T(0.5), G.cs[1], G.cm[1]);
+    }
+    int ck_int = -1, ck_half = -1;
+    T cl0 = T(0), cl1 = T(0), cm0 = T(0), cm1 = T(0), cxy0 = T(0), cxy1 = T(0);
+    T cxz0 = T(0), cxz1 = T(0), cyz0 = T(0), cyz1 = T(0);
 
     // upward for the forward passes and stress-B (see stress_sweeps_up); the z queues shift
     // the other way and the mu ring takes the new plane at the other end, with the same
@@ -634,7 +699,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         qvy[m] = zld(fvy, kfirst - 1 + m, true);
         qvz[m] = zld(fvz, kfirst - 2 + m, true);
     }
-    T m1 = up ? T(0) : zld(mu, k0 + 1, use_model);  // own mu one plane below (downward sweep)
+    T m1 = (up || CM) ? T(0) : zld(mu, k0 + 1, use_model);  // own mu one plane below (downward sweep)
 
     struct Plane {
         T cl, cm, sxx, syy, szz, sxy, sxz, syz, hx, hy, hz, a0, a1, a2, a3, a4, dl, dm, b0, b1, b2, b3, b4, b5;
@@ -642,8 +707,12 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const unsigned pk = wplane(w, kk, ok), o = oc + pk, om_ = oc + wplane(w, kk, ok && use_model);
         const rsrc_t bx = wfield(fvx, w), by = wfield(fvy, w), bz = wfield(fvz, w);
-        P.cl = ldm<NTP, T>(wfield(lam, w), om_);
-        P.cm = ldm<NTP, T>(wfield(mu, w), om_);
+        if constexpr (!CM) {
+            P.cl = ldm<NTP, T>(wfield(lam, w), om_);
+            P.cm = ldm<NTP, T>(wfield(mu, w), om_);
+        } else {
+            P.cl = P.cm = T(0);
+        }
         if constexpr (MODE == kAdjA) {
             P.a0 = ld<T>(wfield(io.acc[0], w), o);
             P.a1 = ld<T>(wfield(io.acc[1], w), o);
@@ -678,8 +747,10 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
 
     Plane P;
     loadplane(kfirst, true, P);
-    T hmu, hdmu = T(0);
-    if constexpr (up) {
+    T hmu = T(0), hdmu = T(0);
+    if constexpr (CM) {
+        // no mu ring
+    } else if constexpr (up) {
         // mu plane k1 (below the first plane) complete; plane k1 - 1's halo one ahead
         T *M = s_mu[k1 % 3];
         M[om] = zld(mu, k1, use_model);
@@ -711,7 +782,9 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         Lx[hvx.lds] = P.hx;
         Ly[hvy.lds] = P.hy;
         Lz[hvz.lds] = P.hz;
-        if constexpr (up) {  // mu plane k enters the ring (plane k + 1 is there)
+        if constexpr (CM) {
+            // the coarse samples replace the ring
+        } else if constexpr (up) {  // mu plane k enters the ring (plane k + 1 is there)
             M0[om] = P.cm;
             M0[hm.lds] = hmu;
             if constexpr (bsf) {
@@ -722,7 +795,34 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             M1[om] = m1;
             M1[hm.lds] = hmu;
         }
-        const T l = P.cl, mm = P.cm;
+        T l = P.cl, mm = P.cm;
+        // coarse medium samples of this plane (loads issued before the next plane's)
+        T cmu_xy = T(0), cmu_xz = T(0), cmu_yz = T(0);
+        if constexpr (CM) {
+            const CoarseAxis<T> zi = coarse_axis<T>(T(k), G.cs[2], G.cm[2]);
+            const CoarseAxis<T> zh = coarse_axis<T>(T(k) + T(0.5), G.cs[2], G.cm[2]);
+            if (zi.lo != ck_int) {
+                cl0 = coarse_bil(lam, cmx, cmxy, cxn, cyn, zi.lo);
+                cl1 = coarse_bil(lam, cmx, cmxy, cxn, cyn, zi.lo + 1);
+                cm0 = coarse_bil(mu, cmx, cmxy, cxn, cyn, zi.lo);
+                cm1 = coarse_bil(mu, cmx, cmxy, cxn, cyn, zi.lo + 1);
+                cxy0 = coarse_bil(mu, cmx, cmxy, cxh, cyh, zi.lo);
+                cxy1 = coarse_bil(mu, cmx, cmxy, cxh, cyh, zi.lo + 1);
+                ck_int = zi.lo;
+            }
+            if (zh.lo != ck_half) {
+                cxz0 = coarse_bil(mu, cmx, cmxy, cxh, cyn, zh.lo);
+                cxz1 = coarse_bil(mu, cmx, cmxy, cxh, cyn, zh.lo + 1);
+                cyz0 = coarse_bil(mu, cmx, cmxy, cxn, cyh, zh.lo);
+                cyz1 = coarse_bil(mu, cmx, cmxy, cxn, cyh, zh.lo + 1);
+                ck_half = zh.lo;
+            }
+            l = lerp_w(cl0, cl1, zi.f);
+            mm = lerp_w(cm0, cm1, zi.f);
+            cmu_xy = lerp_w(cxy0, cxy1, zi.f);
+            cmu_xz = lerp_w(cxz0, cxz1, zh.f);
+            cmu_yz = lerp_w(cyz0, cyz1, zh.f);
+        }
         const T o_xx = P.sxx, o_yy = P.syy, o_zz = P.szz, o_xy = P.sxy, o_xz = P.sxz, o_yz = P.syz;
         const T a0 = P.a0, a1 = P.a1, a2 = P.a2, a3 = P.a3, a4 = P.a4;
         const T dl = P.dl, dm = P.dm;
@@ -733,8 +833,8 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         loadplane(kn, more, P);
         const T nvx = zld(fvx, up ? k - 2 : k + 3, more), nvy = zld(fvy, up ? k - 2 : k + 3, more);
         const T nvz = zld(fvz, up ? k - 3 : k + 2, more);
-        const T nm1 = up ? T(0) : zld(mu, k + 2, more && use_model);
-        const T nhm = loadmu(up ? k - 1 : k + 2, more);
+        const T nm1 = (up || CM) ? T(0) : zld(mu, k + 2, more && use_model);
+        const T nhm = CM ? T(0) : loadmu(up ? k - 1 : k + 2, more);
         const T nhdm = bsf ? loaddmu(k - 1, more) : T(0);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         // second order next to a vacuum surface: ezz at integer k, dz vx / dz vy at k + 1/2
@@ -771,9 +871,9 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             T nxx = o_xx + dt * (l * tr + T(2) * mm * exx);
             T nyy = o_yy + dt * (l * tr + T(2) * mm * eyy);
             T nzz = o_zz + dt * (l * tr + T(2) * mm * ezz);
-            const T mxy = ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
-            const T mxz = ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
-            const T myz = ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);
+            const T mxy = CM ? cmu_xy : ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
+            const T mxz = CM ? cmu_xz : ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
+            const T myz = CM ? cmu_yz : ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);
             T nxy = o_xy + dt * mxy * exy;
             T nxz = o_xz + dt * mxz * exz;
             T nyz = o_yz + dt * myz * eyz;
@@ -821,9 +921,9 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             st(wfield(io.acc[2], w), st_xy + pw, a2 + dt * exy * txy);
             st(wfield(io.acc[3], w), o_stxz + pw, a3 + dt * exz * txz);
             st(wfield(io.acc[4], w), o_styz + pw, a4 + dt * eyz * tyz);
-            const T mxy = ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
-            const T mxz = ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
-            const T myz = ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);
+            const T mxy = CM ? cmu_xy : ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
+            const T mxz = CM ? cmu_xz : ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
+            const T myz = CM ? cmu_yz : ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);
             st(wfield(io.out[3], w), st_xy + pw, mxy * txy);
             st(wfield(io.out[4], w), o_stxz + pw, mxz * txz);
             st(wfield(io.out[5], w), o_styz + pw, myz * tyz);
@@ -853,17 +953,17 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
 
 // ---------------------------------------------------------------------------------
 // Single-grid launches: one workgroup per tile (MODE kFwd or kFwdSave).
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false, bool CM = false>
 __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
 {
     int i0, j0, k0, k1;
     tile_coords(tm, tile_of(blockIdx.x, gridDim.x, vel_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
-    vel_tile_body<T, TX, TY, FS, MODE, VAC, NTP>(G, src, n, i0, j0, k0, k1);
+    vel_tile_body<T, TX, TY, FS, MODE, VAC, NTP, CM>(G, src, n, i0, j0, k0, k1);
 }
 
 // The stress pass only reads v^{n+1/2}, so workgroups past the grid's tiles sample the
 // receivers of the step (rec.nq work items) in the same launch.
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false, bool CM = false>
 __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, int n, TileMap tm, RecJob<T> rec)
 {
     const int nwg = tm.ntx * tm.nty * tm.nzc;
@@ -874,7 +974,7 @@ __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, 
     }
     int i0, j0, k0, k1;
     tile_coords(tm, tile_of(blockIdx.x, nwg, stress_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
-    stress_tile_body<T, TX, TY, FS, MODE, VAC, NTP>(G, src, n, i0, j0, k0, k1);
+    stress_tile_body<T, TX, TY, FS, MODE, VAC, NTP, CM>(G, src, n, i0, j0, k0, k1);
 }
 
 // Born stress pass (kBornS): the background's stress update and the perturbation's

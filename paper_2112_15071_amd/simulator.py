@@ -35,7 +35,7 @@ def _stream() -> int:
 
 def make_opts(dtype: torch.dtype, sponge=0, sponge_alpha: float = 0.0, free_surface: bool = False,
               check_finite: bool = False, max_receivers: int = 4096, dy: float = 0.0,
-              dz: float = 0.0, vacuum_top: int = 0, vacuum_map: int = 0) -> _abi.fd3d_opts:
+              dz: float = 0.0, vacuum_top: int = 0, vacuum_map: int = 0, coarse=None) -> _abi.fd3d_opts:
     o = _abi.fd3d_opts()
     o.dtype = _dtype_code(dtype)
     sp = [int(sponge)] * 6 if np.isscalar(sponge) else [int(v) for v in sponge]
@@ -50,6 +50,9 @@ def make_opts(dtype: torch.dtype, sponge=0, sponge_alpha: float = 0.0, free_surf
     o.dy, o.dz = float(dy), float(dz)
     o.vacuum_top = int(vacuum_top)
     o.vacuum_map = int(vacuum_map) or None
+    if coarse is not None:
+        for a in range(3):
+            o.coarse[a] = int(coarse[a])
     return o
 
 
@@ -120,7 +123,11 @@ class Simulator:
 
     def __init__(self, lam, mu, rho, dx: float, dt: float, nt: int, dtype: torch.dtype = torch.float32,
                  sponge=20, sponge_alpha: float = 0.0, free_surface: bool = False, check_finite: bool = False,
-                 max_receivers: int = 4096, device="cuda", vacuum_top: int = 0, vacuum_map=None):
+                 max_receivers: int = 4096, device="cuda", vacuum_top: int = 0, vacuum_map=None, grid=None):
+        """``grid`` = (nx, ny, nz) of the simulation when it differs from the medium arrays'
+        shape: lam, mu, rho are then a coarse medium over the same box, read by trilinear
+        samples at every value's own position inside the step kernels (fd3d_opts.coarse;
+        forward only, tile kernels)."""
         self.device = torch.device(device)
         self.dtype = dtype
         self.lam, self.mu, self.rho = (torch.as_tensor(a).to(device=self.device, dtype=dtype).contiguous()
@@ -128,6 +135,10 @@ class Simulator:
         if self.lam.dim() != 3 or self.mu.shape != self.lam.shape or self.rho.shape != self.lam.shape:
             raise ValueError("lam, mu, rho must share one [nz, ny, nx] shape")
         nz, ny, nx = self.lam.shape
+        self.coarse = None
+        if grid is not None and tuple(int(v) for v in grid) != (nx, ny, nz):
+            self.coarse = (nx, ny, nz)
+            nx, ny, nz = (int(v) for v in grid)
         self.shape = (nx, ny, nz)
         # one spacing, or (dx, dy, dz) for cells of different size per axis
         self.spacing = tuple(float(v) for v in (np.broadcast_to(np.asarray(dx, dtype=np.float64), (3,))))
@@ -141,7 +152,7 @@ class Simulator:
             vacuum_top = vacuum_top or int(self.vacuum_map.max())
         self.opts = make_opts(dtype, sponge, sponge_alpha, free_surface, check_finite, max_receivers,
                               self.spacing[1], self.spacing[2], vacuum_top,
-                              self.vacuum_map.data_ptr() if self.vacuum_map is not None else 0)
+                              self.vacuum_map.data_ptr() if self.vacuum_map is not None else 0, self.coarse)
         nbytes = _abi.fd3d_workspace_bytes(nx, ny, nz, self.opts)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._ctx = _abi.fd3d_create(nx, ny, nz, self.lam.data_ptr(), self.mu.data_ptr(), self.rho.data_ptr(),
@@ -191,7 +202,8 @@ class Simulator:
         nx, ny, nz = self.shape
         props = torch.cuda.get_device_properties(self.device)
         dev = f"{props.multi_processor_count}cu-{props.total_memory >> 30}gib"
-        key = f"{nx}x{ny}x{nz}/{str(self.dtype)}/fs{int(self.opts.free_surface)}/{dev}"
+        cm = "" if self.coarse is None else "/cm{}x{}x{}".format(*self.coarse)
+        key = f"{nx}x{ny}x{nz}/{str(self.dtype)}/fs{int(self.opts.free_surface)}{cm}/{dev}"
         path = os.environ.get("FD3D_AUTOTUNE_CACHE", os.path.expanduser("~/.cache/fd3d/autotune.json"))
         table = {}
         if cache and os.path.exists(path):
@@ -230,7 +242,7 @@ class Simulator:
                         sponge=[o.sponge[f] for f in range(6)], sponge_alpha=o.sponge_alpha,
                         free_surface=bool(o.free_surface), check_finite=bool(o.check_finite),
                         max_receivers=o.max_receivers, device=self.device, vacuum_top=o.vacuum_top,
-                        vacuum_map=self.vacuum_map)
+                        vacuum_map=self.vacuum_map, grid=self.shape)
         k = self.kernel()
         sim.set_kernel(k["variant"], k["tile_y"], k["zchunk"], k["tile_x"])
         return sim

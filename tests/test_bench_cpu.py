@@ -45,7 +45,7 @@ def test_line_printed_when_sections_fail(monkeypatch, capsys):
     monkeypatch.setattr(bench, "Forward", boom)
     monkeypatch.setattr(bench, "stream_copy_ceiling", boom)
     rc = bench.main(["--steps", "20", "--warmup", "5", "--no-c2", "--no-batch", "--no-grad", "--no-levels",
-                     "--no-born", "--cpu-steps", "0"])
+                     "--no-born", "--no-coarse", "--cpu-steps", "0"])
     assert rc == 1
     lines = [l for l in capsys.readouterr().out.splitlines() if l.startswith("{")]
     assert len(lines) == 1
