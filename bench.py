@@ -655,8 +655,9 @@ def bench_gradient(wave=4, nshots=8):
                           "roofline_shots_per_s_at_design_bytes": round(HBM_PEAK_GBS * 1e9 / design_shot, 4)})
 
 
-def counters_run(kernels, K):
-    """Forward steps on the 256^3 workload with each kernel configuration in turn, then
+def counters_run(kernels, K, grad=False):
+    """Forward steps on the 256^3 workload with each kernel configuration in turn (with
+    ``grad``, then a K-step checkpointed gradient with the first configuration), then
     three copies of 1 GiB with torch (a plain copy kernel of known size, which calibrates
     the HBM byte counters).  Meant to run under rocprofv3 --pmc."""
     import torch
@@ -674,6 +675,20 @@ def counters_run(kernels, K):
         sim.set_kernel(variant, int(ty), int(zc), int(tx))
         log(f"[counters] {spec}: {K} steps")
         sim.forward(shot.src_pos, shot.moment, shot.force, wav[:K], shot.rec_pos)
+        sync()
+        sim.close()
+    if grad:
+        # one checkpointed gradient of the first configuration: its recompute (forward
+        # passes that store v and sigma) and the four adjoint passes
+        variant, tx, ty, zc = kernels[0].split(",")
+        sim = Simulator(lam, mu, rho, shot.h, shot.dt, K, dtype=torch.float32, sponge=shot.sponge, device=dev)
+        sim.set_kernel(variant, int(ty), int(zc), int(tx))
+        k = max(1, K // 2)
+        gws = sim.grad_workspace(k)
+        g = [torch.zeros_like(lam) for _ in range(3)]
+        d_obs = torch.zeros((shot.rec_pos.shape[0], 3, K), dtype=torch.float32, device=dev)
+        log(f"[counters] gradient {kernels[0]}: {K} steps, checkpoints every {k}")
+        sim.gradient(gws, d_obs, *g, **shot_desc(shot))
         sync()
         sim.close()
     a = torch.ones(1 << 28, device=dev)
@@ -759,6 +774,8 @@ def parse_args(argv=None):
     ap.add_argument("--counters", metavar="VARIANT,TX,TY,ZC", action="append", default=[],
                     help="counter-collection run: --steps forward steps per kernel given (repeatable), then a "
                          "1 GiB device copy that calibrates FETCH_SIZE / WRITE_SIZE; prints no JSON")
+    ap.add_argument("--counters-grad", action="store_true",
+                    help="with --counters: also a --steps-step checkpointed gradient with the first configuration")
     return ap.parse_args(argv)
 
 
@@ -841,7 +858,7 @@ def main(argv=None):
               file=sys.stderr)
         return 2
     if args.counters:
-        counters_run(args.counters, args.steps)
+        counters_run(args.counters, args.steps, args.counters_grad)
         return 0
     state = {}
 
