@@ -65,6 +65,17 @@ extern "C" {
 #define FD3D_KERNEL_FUSED 2 /* velocity and stress of a step in one z sweep over a double-buffered
                                state; tiles 64x4 and 64x8 (FP32), 64x4 (FP64) */
 
+/* field storage in the workspace (fd3d_opts.layout); every layout gives the same results */
+#define FD3D_LAYOUT_AUTO 0     /* interleaved rows when a tile sweep over the whole depth fits one
+                                  buffer window (9 nx ny nz samples in 1 GiB), separate arrays
+                                  otherwise */
+#define FD3D_LAYOUT_SEPARATE 1 /* one array per field; the model arrays are read in place */
+#define FD3D_LAYOUT_ROWS 2     /* interleaved rows: [nz][ny][9][nx], field q in row q, so that a
+                                  tile's rows of the nine fields lie side by side; the model is
+                                  copied once, at create, into a block of the same shape.  Needs
+                                  min(12, nz) planes of 9 nx ny samples within 1 GiB and
+                                  9 nx ny nz < 2^31 (else FD3D_EINVAL) */
+
 /* fd3d_forward flags */
 #define FD3D_KEEP_STATE 1 /* start from the current state instead of zeros */
 
@@ -108,6 +119,7 @@ typedef struct fd3d_opts {
                           * fd3d_upsample followed by node arrays is the other reading of a
                           * coarse medium: it differs where a mean straddles a coarse node.
                           * All 0: lam, mu, rho are node arrays of the simulation grid. */
+    int layout;          /* FD3D_LAYOUT_AUTO (0), FD3D_LAYOUT_SEPARATE or FD3D_LAYOUT_ROWS */
 } fd3d_opts;
 
 typedef struct fd3d_source {
@@ -177,6 +189,9 @@ int fd3d_set_state(fd3d_ctx *ctx, const void *const fields[9], void *hip_stream)
  * (0 if none), out[2] = rho_min, out[3] = largest stable dt (m/s, m/s, kg/m^3, s). */
 int fd3d_model_info(const fd3d_ctx *ctx, double out[4]);
 
+/* Field storage the context chose: FD3D_LAYOUT_SEPARATE or FD3D_LAYOUT_ROWS (never AUTO). */
+int fd3d_get_layout(const fd3d_ctx *ctx, int *layout);
+
 /* ---- FWI gradient: discrete adjoint with snapshot checkpointing -------------------
  *
  * J = 1/2 sum_{r,c,n} (d - d_obs)^2 over the traces of one shot; residual = dJ/dd.
@@ -187,7 +202,9 @@ int fd3d_model_info(const fd3d_ctx *ctx, double out[4]);
  * recomputes its segment while storing v^{n+1/2} and sigma^n per step, then runs the
  * adjoint steps of the segment backwards.  Damped boundaries only (FD3D_EINVAL with the
  * free surface).  The gradient workspace gws is caller-owned device memory, 256-byte
- * aligned: 17 + 9 (ceil(nt / ckpt_every) + ckpt_every) field slots plus a residual buffer.
+ * aligned: groups of nine fields in the context's field layout (adjoint state, gradient
+ * accumulators, intermediate fields, one per checkpoint -- ceil(nt / ckpt_every) -- and
+ * one per step of a segment -- ckpt_every) plus a residual buffer.
  */
 
 /* Bytes of gradient workspace for checkpoints every ckpt_every steps (1 <= k <= nt). */

@@ -29,6 +29,9 @@ FD3D_KERNEL_CELL = 0
 FD3D_KERNEL_TILE = 1
 FD3D_KERNEL_FUSED = 2
 FD3D_STATIC_SCRATCH_BYTES = 64 << 20
+FD3D_LAYOUT_AUTO = 0
+FD3D_LAYOUT_SEPARATE = 1
+FD3D_LAYOUT_ROWS = 2
 
 ERRNAMES = {
     FD3D_EINVAL: "FD3D_EINVAL", FD3D_ECFL: "FD3D_ECFL", FD3D_EMODEL: "FD3D_EMODEL", FD3D_ERANGE: "FD3D_ERANGE",
@@ -55,6 +58,7 @@ class fd3d_opts(ctypes.Structure):
         ("vacuum_top", ctypes.c_int),
         ("vacuum_map", ctypes.c_void_p),
         ("coarse", ctypes.c_int * 3),
+        ("layout", ctypes.c_int),
     ]
 
 
@@ -96,6 +100,7 @@ _SIGS = {
     "fd3d_get_state": ([_vp, ctypes.POINTER(_vp), _vp], _i),
     "fd3d_set_state": ([_vp, ctypes.POINTER(_vp), _vp], _i),
     "fd3d_model_info": ([_vp, _dp], _i),
+    "fd3d_get_layout": ([_vp, ctypes.POINTER(_i)], _i),
     "fd3d_grad_workspace_bytes": ([_vp, _i, ctypes.POINTER(_sz)], _i),
     "fd3d_forward_ckpt": ([_vp, ctypes.POINTER(fd3d_source), _i, _dp, _vp, _i, _vp, _sz, _i, _vp], _i),
     "fd3d_adjoint": ([_vp, ctypes.POINTER(fd3d_source), _i, _dp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i),
@@ -186,6 +191,12 @@ def fd3d_model_info(ctx):
     out = (ctypes.c_double * 4)()
     _check(_lib.fd3d_model_info(ctx, out))
     return list(out)
+
+
+def fd3d_get_layout(ctx) -> int:
+    out = ctypes.c_int(0)
+    _check(_lib.fd3d_get_layout(ctx, ctypes.byref(out)))
+    return out.value
 
 
 def _src(src):

@@ -260,7 +260,8 @@ __global__ void __launch_bounds__(256) grad_finalize(Grid<T> G, AdjGrid<T> A, T 
     const int k = blockIdx.z;
     if (i >= G.nx || j >= G.ny) return;
     const long p = i + G.sy * j + G.sz * k;
-    g_lam[p] += A.gl[p];
+    const long po = i + (long)G.nx * (j + (long)G.ny * k);  // the node arrays' own index
+    g_lam[po] += A.gl[p];
     T sh = T(0);
     for (int di = -1; di <= 0; ++di)
         for (int dj = -1; dj <= 0; ++dj) sh += rdc(A.gs[0], SXY, i + di, j + dj, k, G);
@@ -268,7 +269,7 @@ __global__ void __launch_bounds__(256) grad_finalize(Grid<T> G, AdjGrid<T> A, T 
         for (int dk = -1; dk <= 0; ++dk) sh += rdc(A.gs[1], SXZ, i + di, j, k + dk, G);
     for (int dj = -1; dj <= 0; ++dj)
         for (int dk = -1; dk <= 0; ++dk) sh += rdc(A.gs[2], SYZ, i, j + dj, k + dk, G);
-    g_mu[p] += A.gm[p] + sh / T(4);
+    g_mu[po] += A.gm[p] + sh / T(4);
     T gr = T(0);
     for (int c = 0; c < 3; ++c) {
         const long e = c == 0 ? 1 : (c == 1 ? G.sy : G.sz);
@@ -282,10 +283,11 @@ __global__ void __launch_bounds__(256) grad_finalize(Grid<T> G, AdjGrid<T> A, T 
             }
         }
     }
-    g_rho[p] += gr;
+    g_rho[po] += gr;
 }
 
-// Adjoint of the initial velocity: the pending damping factor of A_v applied into out.
+// Adjoint of the initial velocity: the pending damping factor of A_v applied into out (a
+// node array, x fastest and unpadded).
 template <typename T>
 __global__ void __launch_bounds__(256) scale_velocity(Grid<T> G, const T *__restrict__ a, int c, T *__restrict__ out)
 {
@@ -293,8 +295,7 @@ __global__ void __launch_bounds__(256) scale_velocity(Grid<T> G, const T *__rest
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int k = blockIdx.z;
     if (i >= G.nx || j >= G.ny) return;
-    const long p = i + G.sy * j + G.sz * k;
-    out[p] = damp(G, c, i, j, k) * a[p];
+    out[i + (long)G.nx * (j + (long)G.ny * k)] = damp(G, c, i, j, k) * a[i + G.sy * j + G.sz * k];
 }
 
 // ---------------------------------------------------------------------------------

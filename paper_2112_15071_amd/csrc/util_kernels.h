@@ -17,10 +17,12 @@ __global__ void __launch_bounds__(256) fill_zero(T *__restrict__ p, long n)
         p[q] = T(0);
 }
 
-// dst = src for active samples of component c, 0 for its pinned slots.
+// dst = src for the active samples of a component with half offsets (sx, sy, sz), 0 at its
+// pinned slots (all offsets 0: a plain copy).  Each side has its own row and plane strides
+// (a node array: nx, nx ny; a field of the interleaved-rows layout: 9 nx, 9 nx ny).
 template <typename T>
-__global__ void __launch_bounds__(256) copy_masked(T *__restrict__ dst, const T *__restrict__ src, int nx, int ny,
-                                                   int nz, int sx, int sy, int sz)
+__global__ void __launch_bounds__(256) copy_masked(T *__restrict__ dst, long dsy, long dsz, const T *__restrict__ src,
+                                                   long ssy, long ssz, int nx, int ny, int nz, int sx, int sy, int sz)
 {
     const long n = (long)nx * ny * nz;
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
@@ -28,7 +30,7 @@ __global__ void __launch_bounds__(256) copy_masked(T *__restrict__ dst, const T 
         const int j = (int)((q / nx) % ny);
         const int k = (int)(q / ((long)nx * ny));
         const bool ok = i <= nx - 1 - sx && j <= ny - 1 - sy && k <= nz - 1 - sz;
-        dst[q] = ok ? src[q] : T(0);
+        dst[i + dsy * j + dsz * k] = ok ? src[i + ssy * j + ssz * k] : T(0);
     }
 }
 
@@ -121,8 +123,13 @@ __global__ void __launch_bounds__(256) finite_check(Grid<T> G, int *__restrict__
 {
     const long n = (long)G.nx * G.ny * G.nz;
     bool bad = false;
-    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x)
-        for (int c = 0; c < NFIELD; ++c) bad |= !isfinite(G.f[c][q]);
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(q % G.nx);
+        const int j = (int)((q / G.nx) % G.ny);
+        const int k = (int)(q / ((long)G.nx * G.ny));
+        const long p = i + G.sy * j + G.sz * k;
+        for (int c = 0; c < NFIELD; ++c) bad |= !isfinite(G.f[c][p]);
+    }
     if (bad) flag[0] = 1;
 }
 

@@ -35,7 +35,8 @@ def _stream() -> int:
 
 def make_opts(dtype: torch.dtype, sponge=0, sponge_alpha: float = 0.0, free_surface: bool = False,
               check_finite: bool = False, max_receivers: int = 4096, dy: float = 0.0,
-              dz: float = 0.0, vacuum_top: int = 0, vacuum_map: int = 0, coarse=None) -> _abi.fd3d_opts:
+              dz: float = 0.0, vacuum_top: int = 0, vacuum_map: int = 0, coarse=None,
+              layout: str = "auto") -> _abi.fd3d_opts:
     o = _abi.fd3d_opts()
     o.dtype = _dtype_code(dtype)
     sp = [int(sponge)] * 6 if np.isscalar(sponge) else [int(v) for v in sponge]
@@ -53,7 +54,15 @@ def make_opts(dtype: torch.dtype, sponge=0, sponge_alpha: float = 0.0, free_surf
     if coarse is not None:
         for a in range(3):
             o.coarse[a] = int(coarse[a])
+    if layout not in LAYOUTS:
+        raise ValueError(f"layout must be one of {sorted(LAYOUTS)}")
+    o.layout = LAYOUTS[layout]
     return o
+
+
+# field storage in the workspace (fd3d_opts.layout): "rows" interleaves the nine fields' rows
+# ([nz][ny][9][nx]), "separate" keeps one array per field, "auto" lets the library choose
+LAYOUTS = {"auto": _abi.FD3D_LAYOUT_AUTO, "separate": _abi.FD3D_LAYOUT_SEPARATE, "rows": _abi.FD3D_LAYOUT_ROWS}
 
 
 def make_source(pos, moment=(0.0,) * 6, force=(0.0,) * 3, wavelet: Optional[torch.Tensor] = None) -> _abi.fd3d_source:
@@ -123,11 +132,13 @@ class Simulator:
 
     def __init__(self, lam, mu, rho, dx: float, dt: float, nt: int, dtype: torch.dtype = torch.float32,
                  sponge=20, sponge_alpha: float = 0.0, free_surface: bool = False, check_finite: bool = False,
-                 max_receivers: int = 4096, device="cuda", vacuum_top: int = 0, vacuum_map=None, grid=None):
+                 max_receivers: int = 4096, device="cuda", vacuum_top: int = 0, vacuum_map=None, grid=None,
+                 layout: str = "auto"):
         """``grid`` = (nx, ny, nz) of the simulation when it differs from the medium arrays'
         shape: lam, mu, rho are then a coarse medium over the same box, read by trilinear
         samples at every value's own position inside the step kernels (fd3d_opts.coarse;
-        forward only, tile kernels)."""
+        forward only, tile kernels).  ``layout``: the fields' storage ("auto", "separate",
+        "rows"; fd3d_opts.layout), which changes speed, never results."""
         self.device = torch.device(device)
         self.dtype = dtype
         self.lam, self.mu, self.rho = (torch.as_tensor(a).to(device=self.device, dtype=dtype).contiguous()
@@ -152,7 +163,8 @@ class Simulator:
             vacuum_top = vacuum_top or int(self.vacuum_map.max())
         self.opts = make_opts(dtype, sponge, sponge_alpha, free_surface, check_finite, max_receivers,
                               self.spacing[1], self.spacing[2], vacuum_top,
-                              self.vacuum_map.data_ptr() if self.vacuum_map is not None else 0, self.coarse)
+                              self.vacuum_map.data_ptr() if self.vacuum_map is not None else 0, self.coarse,
+                              layout)
         nbytes = _abi.fd3d_workspace_bytes(nx, ny, nz, self.opts)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._ctx = _abi.fd3d_create(nx, ny, nz, self.lam.data_ptr(), self.mu.data_ptr(), self.rho.data_ptr(),
@@ -190,6 +202,10 @@ class Simulator:
         k.tile_x, k.tile_y, k.zchunk = int(tile_x), int(tile_y), int(zchunk)
         _abi.fd3d_set_kernel(self._ctx, k)
 
+    def layout(self) -> str:
+        """The field storage the library chose: "separate" or "rows"."""
+        return {v: n for n, v in LAYOUTS.items()}[_abi.fd3d_get_layout(self._ctx)]
+
     def kernel(self) -> dict:
         k = _abi.fd3d_get_kernel(self._ctx)
         name = {v: n for n, v in self._VARIANTS.items()}[k.variant]
@@ -203,7 +219,7 @@ class Simulator:
         props = torch.cuda.get_device_properties(self.device)
         dev = f"{props.multi_processor_count}cu-{props.total_memory >> 30}gib"
         cm = "" if self.coarse is None else "/cm{}x{}x{}".format(*self.coarse)
-        key = f"{nx}x{ny}x{nz}/{str(self.dtype)}/fs{int(self.opts.free_surface)}{cm}/{dev}"
+        key = f"{nx}x{ny}x{nz}/{str(self.dtype)}/fs{int(self.opts.free_surface)}{cm}/{self.layout()}/{dev}"
         path = os.environ.get("FD3D_AUTOTUNE_CACHE", os.path.expanduser("~/.cache/fd3d/autotune.json"))
         table = {}
         if cache and os.path.exists(path):
@@ -242,7 +258,7 @@ class Simulator:
                         sponge=[o.sponge[f] for f in range(6)], sponge_alpha=o.sponge_alpha,
                         free_surface=bool(o.free_surface), check_finite=bool(o.check_finite),
                         max_receivers=o.max_receivers, device=self.device, vacuum_top=o.vacuum_top,
-                        vacuum_map=self.vacuum_map, grid=self.shape)
+                        vacuum_map=self.vacuum_map, grid=self.shape, layout=self.layout())
         k = self.kernel()
         sim.set_kernel(k["variant"], k["tile_y"], k["zchunk"], k["tile_x"])
         return sim
@@ -314,7 +330,7 @@ class Simulator:
             sp = [o.sponge[f] for f in range(6)]
             self._born_sim = Simulator(self.lam, self.mu, self.rho, self.spacing, self.dt, self.nt, dtype=self.dtype,
                                        sponge=sp, sponge_alpha=o.sponge_alpha, free_surface=bool(o.free_surface),
-                                       max_receivers=o.max_receivers, device=self.device)
+                                       max_receivers=o.max_receivers, device=self.device, layout=self.layout())
         d = self._born_sim
         k = self.kernel()
         d.set_kernel(k["variant"], k["tile_y"], k["zchunk"], k["tile_x"])

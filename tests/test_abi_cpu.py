@@ -77,3 +77,34 @@ def test_host_only_calls():
     with pytest.raises(_abi.FD3DError) as e:
         _abi.fd3d_upsample(4096, (4, 4, 4), 4096 + 128, (8, 8, 8), _abi.FD3D_F32, None)
     assert "overlap" in _abi.fd3d_last_error()
+
+
+def test_layout_option():
+    from paper_2112_15071_amd import _abi
+
+    o = _abi.fd3d_opts()
+    o.dtype = _abi.FD3D_F32
+    size = {}
+    for lay in (_abi.FD3D_LAYOUT_AUTO, _abi.FD3D_LAYOUT_SEPARATE, _abi.FD3D_LAYOUT_ROWS):
+        o.layout = lay
+        size[lay] = _abi.fd3d_workspace_bytes(64, 64, 64, o)
+    # interleaved rows keep the model's copy beside the two state blocks
+    assert size[_abi.FD3D_LAYOUT_ROWS] >= size[_abi.FD3D_LAYOUT_SEPARATE] + 8 * 64 ** 3 * 4
+    # small planes: a whole-depth sweep fits one window, so automatic means rows
+    assert size[_abi.FD3D_LAYOUT_AUTO] == size[_abi.FD3D_LAYOUT_ROWS]
+    # 512 x 512 planes: 264 planes of 9 rows exceed 1 GiB, so automatic means separate arrays
+    big = {}
+    for lay in (_abi.FD3D_LAYOUT_AUTO, _abi.FD3D_LAYOUT_SEPARATE):
+        o.layout = lay
+        big[lay] = _abi.fd3d_workspace_bytes(512, 512, 256, o)
+    assert big[_abi.FD3D_LAYOUT_AUTO] == big[_abi.FD3D_LAYOUT_SEPARATE]
+    # forced rows need 12 planes of 9 nx ny samples within 1 GiB
+    o.layout = _abi.FD3D_LAYOUT_ROWS
+    assert _abi.fd3d_workspace_bytes(1024, 1024, 64, o) > 0
+    with pytest.raises(_abi.FD3DError) as e:
+        _abi.fd3d_workspace_bytes(4096, 4096, 16, o)
+    assert e.value.code == _abi.FD3D_EINVAL and "rows" in _abi.fd3d_last_error()
+    o.layout = 3
+    with pytest.raises(_abi.FD3DError) as e:
+        _abi.fd3d_workspace_bytes(64, 64, 64, o)
+    assert "layout" in _abi.fd3d_last_error()

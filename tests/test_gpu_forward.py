@@ -332,27 +332,29 @@ def test_anisotropic_cells(dtype, free_surface):
 
 
 def test_largest_tile_window_equals_cell():
-    """4096 x 4096 x 12 FP32: 64 MiB planes, so an 8-plane sweep's buffer window is exactly
-    the 1 GiB limit of the 32-bit buffer offsets (out-of-grid samples at 2^31, skipped
-    planes at 2^30).  The tile kernel there agrees bit for bit with the cell kernel, and a
-    16-plane sweep is refused."""
+    """4096 x 4096 x 24 FP32: 64 MiB planes, so the window of an 8-plane sweep through the
+    middle chunk (planes 8-15, window 4-19) is exactly the 1 GiB limit of the 32-bit buffer
+    offsets (out-of-grid samples at 2^31, skipped planes at 2^30).  The tile kernel there
+    agrees bit for bit with the cell kernel, and a 16-plane sweep (a 24-plane window) is
+    refused."""
     from paper_2112_15071_amd import Simulator, _abi
 
     nx = ny = 4096
-    nz = 12
+    nz = 24
     dev = torch.device("cuda")
     lam = torch.full((nz, ny, nx), 2500.0 * (3000.0 ** 2 - 2 * 1732.0 ** 2), device=dev)
     mu = torch.full((nz, ny, nx), 2500.0 * 1732.0 ** 2, device=dev)
     rho = torch.full((nz, ny, nx), 2500.0, device=dev)
     nt = 3
     wav = W.ricker(30.0, nt, 1e-3, t0=0.0)
-    rec = np.array([[2048.5, 2047.25, 6.5], [100.0, 4000.0, 2.0], [4090.5, 3.5, 9.0]])
+    rec = np.array([[2048.5, 2047.25, 12.5], [100.0, 4000.0, 2.0], [4090.5, 3.5, 20.0], [2050.0, 2046.0, 7.5]])
     outs = []
     for kern in (("tile", 4, 8, 256), ("cell", 8, 32)):
         sim = Simulator(lam, mu, rho, 10.0, 1e-3, nt, sponge=(3,) * 6, device=dev)
         sim.set_kernel(*kern)
         print(f"[largest window] {kern}", flush=True)
-        tr = sim.forward((2048.3, 2047.6, 6.2), W.explosion(1e15), (1e9, 0.0, -1e9), wav, rec)
+        assert sim.layout() == "separate"
+        tr = sim.forward((2048.3, 2047.6, 12.2), W.explosion(1e15), (1e9, 0.0, -1e9), wav, rec)
         outs.append((tr.clone(), sim.state()))
         if kern[0] == "tile":
             with pytest.raises(_abi.FD3DError):
