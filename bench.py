@@ -143,7 +143,7 @@ def measured_traffic(kern, dom):
                 h.update(f.read())
         if h.hexdigest() != table["sources_sha256"]:
             return None
-        key = f"{kern['variant']},{kern['tile_x']},{kern['tile_y']},{kern['zchunk']}"
+        key = f"{kern['variant']},{kern['tile_x']},{kern['tile_y']},{kern['zchunk']},{kern['layout']}"
         return table["kernels"][key][dom]["hbm_bytes"]
     except (OSError, KeyError, ValueError):
         return None
@@ -152,7 +152,7 @@ def measured_traffic(kern, dom):
 class Forward:
     """The 256^3 workload on the GPU: model, simulator with its tuned kernel, zero state."""
 
-    def __init__(self, nt_max, kernel=None):
+    def __init__(self, nt_max, kernel=None, layout="auto"):
         import torch
 
         import workloads as W
@@ -168,13 +168,14 @@ class Forward:
         self.zero = torch.zeros((9, nz, ny, nx), dtype=torch.float32, device=self.dev)
         self.sims = {}
         self.kernel = kernel
+        self.layout = layout
         self.Simulator = Simulator
 
     def sim(self, K):
         """Simulator of K steps with the tuned (or given) kernel configuration."""
         if K not in self.sims:
             s = self.Simulator(*self.model, self.shot.h, self.shot.dt, K, dtype=self.model[0].dtype,
-                               sponge=self.shot.sponge, device=self.dev)
+                               sponge=self.shot.sponge, device=self.dev, layout=self.layout)
             if not self.sims:
                 if self.kernel:
                     variant, tx, ty, zc = self.kernel.split(",")
@@ -241,7 +242,7 @@ def bench_forward(fw, K, Wm, reps=5):
         dom = "fused"
     else:
         dom = "stress" if per["stress"] >= per["velocity"] else "velocity"
-    kern = sim.kernel()
+    kern = dict(sim.kernel(), layout=sim.layout())
     per_kernel = {}
     for name, t in per.items():
         if name in BYTES_PER_CELL:
@@ -407,6 +408,41 @@ def bench_coarse_medium(K=300, reps=3, coarse=(64, 64, 64), shape=(256, 256, 256
     out["speedup_in_kernel"] = round(out["in_kernel"]["gcs"] / out["setup_upsample"]["gcs"], 4)
     out["coarse_nodes"] = list(coarse)
     out["grid"] = list(shape)
+    out["steps"] = K
+    return out
+
+
+def bench_layout_ab(K=300, reps=3):
+    """The 256^3 workload with each field storage (fd3d_opts.layout): separate arrays and
+    interleaved rows, each with its own tuned kernel; K steps from a zero state, median of
+    reps.  The results are bitwise equal (tested); only the time differs."""
+    import torch
+
+    import workloads as W
+    from paper_2112_15071_amd import Simulator
+
+    dev = torch.device("cuda:0")
+    shot = W.c1(nt=K)
+    nx, ny, nz = shot.shape
+    model = [torch.as_tensor(a, dtype=torch.float32, device=dev) for a in (shot.lam, shot.mu, shot.rho)]
+    wav = torch.as_tensor(shot.wavelet[:K], dtype=torch.float32, device=dev)
+    zero = torch.zeros((9, nz, ny, nx), dtype=torch.float32, device=dev)
+    traces = torch.empty((len(shot.rec_pos), 3, K), dtype=torch.float32, device=dev)
+    out = {}
+    for lay in ("separate", "rows"):
+        sim = Simulator(*model, shot.h, shot.dt, K, sponge=shot.sponge, device=dev, layout=lay)
+        sim.autotune(steps=20)
+        run = lambda: sim.forward(shot.src_pos, shot.moment, shot.force, wav, shot.rec_pos, keep_state=True,
+                                  traces=traces)
+        sim.set_state(zero)
+        run()
+        el, ts = median_time(run, reps, prep=lambda: sim.set_state(zero))
+        gcs = nx * ny * nz * K / el / 1e9
+        out[lay] = dict(gcs=round(gcs, 3), ms_per_step=round(el / K * 1e3, 4), kernel=sim.kernel(),
+                        hbm_gbs=round(120 * nx * ny * nz * K / el / 1e9, 1))
+        log(f"[bench] layout {lay}: {gcs:.2f} Gcell-steps/s ({el / K * 1e3:.4f} ms/step), {sim.kernel()}")
+        sim.close()
+    out["speedup_rows"] = round(out["rows"]["gcs"] / out["separate"]["gcs"], 4)
     out["steps"] = K
     return out
 
@@ -669,20 +705,23 @@ def counters_run(kernels, K, grad=False):
     shot = W.c1(nt=K)
     lam, mu, rho = (torch.as_tensor(a, dtype=torch.float32).to(dev) for a in (shot.lam, shot.mu, shot.rho))
     wav = torch.as_tensor(shot.wavelet, dtype=torch.float32).to(dev)
-    for spec in kernels:
-        variant, tx, ty, zc = spec.split(",")
-        sim = Simulator(lam, mu, rho, shot.h, shot.dt, K, dtype=torch.float32, sponge=shot.sponge, device=dev)
+    def make(spec):
+        variant, tx, ty, zc, *lay = spec.split(",")
+        sim = Simulator(lam, mu, rho, shot.h, shot.dt, K, dtype=torch.float32, sponge=shot.sponge, device=dev,
+                        layout=lay[0] if lay else "auto")
         sim.set_kernel(variant, int(ty), int(zc), int(tx))
-        log(f"[counters] {spec}: {K} steps")
+        return sim
+
+    for spec in kernels:
+        sim = make(spec)
+        log(f"[counters] {spec} ({sim.layout()}): {K} steps")
         sim.forward(shot.src_pos, shot.moment, shot.force, wav[:K], shot.rec_pos)
         sync()
         sim.close()
     if grad:
         # one checkpointed gradient of the first configuration: its recompute (forward
         # passes that store v and sigma) and the four adjoint passes
-        variant, tx, ty, zc = kernels[0].split(",")
-        sim = Simulator(lam, mu, rho, shot.h, shot.dt, K, dtype=torch.float32, sponge=shot.sponge, device=dev)
-        sim.set_kernel(variant, int(ty), int(zc), int(tx))
+        sim = make(kernels[0])
         k = max(1, K // 2)
         gws = sim.grad_workspace(k)
         g = [torch.zeros_like(lam) for _ in range(3)]
@@ -771,7 +810,10 @@ def parse_args(argv=None):
     ap.add_argument("--kernel", metavar="VARIANT,TX,TY,ZC", default=None,
                     help="forward kernel configuration (default: autotuned, cached per grid)")
     ap.add_argument("--grad-shots", type=int, default=8, help="shots of the gradient section (profiling runs: fewer)")
-    ap.add_argument("--counters", metavar="VARIANT,TX,TY,ZC", action="append", default=[],
+    ap.add_argument("--layout", choices=("auto", "separate", "rows"), default="auto",
+                    help="field storage of the 256^3 forward sections (default: the library's choice)")
+    ap.add_argument("--no-layout-ab", action="store_true", help="skip the separate-vs-rows A/B section")
+    ap.add_argument("--counters", metavar="VARIANT,TX,TY,ZC[,LAYOUT]", action="append", default=[],
                     help="counter-collection run: --steps forward steps per kernel given (repeatable), then a "
                          "1 GiB device copy that calibrates FETCH_SIZE / WRITE_SIZE; prints no JSON")
     ap.add_argument("--counters-grad", action="store_true",
@@ -843,7 +885,7 @@ def build_line(args, r, errors):
                            "frac_wall": round(f["wall_gbs"] / HBM_PEAK_GBS, 4)},
         }
     for key in ("c1_full", "stream_copy_gbs", "c2_forward", "batched_forward", "gradient", "levels", "born",
-                "coarse_medium"):
+                "coarse_medium", "layout_ab"):
         out[key] = r.get(key)
     out["paper_table6"] = paper_context()
     out["cpu_baseline"] = r.get("cpu_baseline")
@@ -863,7 +905,8 @@ def main(argv=None):
     state = {}
 
     def fwd():
-        state["fw"] = Forward(max(args.steps, args.warmup, 2000 if not args.no_c1_full else 1), args.kernel)
+        state["fw"] = Forward(max(args.steps, args.warmup, 2000 if not args.no_c1_full else 1), args.kernel,
+                              args.layout)
         return bench_forward(state["fw"], args.steps, args.warmup)
 
     def c1_full():
@@ -898,6 +941,7 @@ def main(argv=None):
         ("levels", (lambda: None) if args.no_levels else bench_levels),
         ("born", (lambda: None) if args.no_born else bench_born),
         ("coarse_medium", (lambda: None) if args.no_coarse else bench_coarse_medium),
+        ("layout_ab", (lambda: None) if args.no_layout_ab else bench_layout_ab),
         ("cpu_baseline", cpu),
     ]
     results, errors = run_sections(args, sections)

@@ -45,7 +45,7 @@ def test_line_printed_when_sections_fail(monkeypatch, capsys):
     monkeypatch.setattr(bench, "Forward", boom)
     monkeypatch.setattr(bench, "stream_copy_ceiling", boom)
     rc = bench.main(["--steps", "20", "--warmup", "5", "--no-c2", "--no-batch", "--no-grad", "--no-levels",
-                     "--no-born", "--no-coarse", "--cpu-steps", "0"])
+                     "--no-born", "--no-coarse", "--no-layout-ab", "--cpu-steps", "0"])
     assert rc == 1
     lines = [l for l in capsys.readouterr().out.splitlines() if l.startswith("{")]
     assert len(lines) == 1
@@ -79,3 +79,14 @@ def test_paper_table6_rates():
     # level 7: 256^3 x 17000 steps in 48 min 10 s on the paper's iGPU
     assert lev7["gpu_s"] == 48 * 60 + 10
     assert lev7["gpu_gcs"] == pytest.approx(256 ** 3 * 17000 / 2890 / 1e9, rel=1e-3)
+
+
+def test_traffic_table_is_keyed_by_layout():
+    # the committed counter table holds HBM bytes per configuration and field layout; a
+    # configuration it does not hold reports no traffic
+    k = {"variant": "tile", "tile_x": 256, "tile_y": 4, "zchunk": 64}
+    got = {lay: bench.measured_traffic(dict(k, layout=lay), "stress") for lay in ("separate", "rows", "nope")}
+    assert got["nope"] is None
+    for lay in ("separate", "rows"):
+        assert got[lay] is None or 1.0 <= got[lay] / (68 * 256 ** 3) <= 1.2, (lay, got[lay])
+    assert got["separate"] is not None or got["rows"] is not None
