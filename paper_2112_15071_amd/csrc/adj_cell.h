@@ -344,4 +344,35 @@ template <typename T> __global__ void __launch_bounds__(256) copy_multi(const Co
         c.dst[q] = c.src[q];
 }
 
+// Residual r = d - d_obs of one shot's traces and per-block partial sums of r^2 / 2
+// (deterministic two-stage reduction: misfit_final adds the partials in order).
+template <typename T>
+__global__ void __launch_bounds__(256) residual_misfit(const T *__restrict__ d, const T *__restrict__ obs,
+                                                       T *__restrict__ r, long n, double *__restrict__ part)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
+        const T v = d[q] - obs[q];
+        r[q] = v;
+        acc += (double)v * (double)v;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) misfit_final(const double *__restrict__ part, int nb, T *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b];
+    out[0] = (T)(0.5 * s);
+}
+
 } // namespace fd3d

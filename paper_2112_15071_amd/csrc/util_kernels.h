@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(kReduceThreads) model_stats(const T *__restric
     if (t < kStats) part[blockIdx.x * kStats + t] = sh[t][0];
 }
 
-__global__ void __launch_bounds__(kReduceThreads) stats_final(const double *__restrict__ part, int nblocks,
+static __global__ void __launch_bounds__(kReduceThreads) stats_final(const double *__restrict__ part, int nblocks,
                                                               double *__restrict__ out)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;

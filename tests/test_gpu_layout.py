@@ -234,3 +234,46 @@ def test_batch_with_mixed_layouts_equals_single_shots():
     batch.close()
     for s in bs:
         s.close()
+
+
+def test_batch_shots_over_one_model_share_its_copy():
+    """Shots created over the same model tensors (interleaved rows: each context holds a
+    copy) read the first shot's copy inside a batch; a shot over other tensors keeps its
+    own.  Forward and gradient of every shot equal its single-shot run."""
+    from paper_2112_15071_amd import Simulator
+    from paper_2112_15071_amd.batch import BatchSimulator
+
+    nt, shape = 24, (44, 40, 34)
+    print(f"[layout] batch over one shared model {shape} x {nt}", flush=True)
+    shared = [torch.as_tensor(a, dtype=torch.float32, device="cuda") for a in model(shape, seed=50)]
+    other = [torch.as_tensor(a, dtype=torch.float32, device="cuda") for a in model(shape, seed=51)]
+    mods = [shared, shared, other, shared]
+    shots = [shot(shape, nt, seed=60 + k) for k in range(4)]
+    ref = []
+    for m, sh in zip(mods, shots):
+        s = Simulator(*m, H, DT, nt, sponge=5)
+        assert s.layout() == "rows"
+        tr = s.forward(**sh).clone()
+        gws = s.grad_workspace(8)
+        g = [torch.zeros(shape[::-1], dtype=torch.float32, device="cuda") for _ in range(3)]
+        _, j = s.gradient(gws, torch.zeros_like(tr), *g, **sh)
+        torch.cuda.synchronize()
+        ref.append((tr, j.clone(), g))
+        s.close()
+    bs = [Simulator(*m, H, DT, nt, sponge=5) for m in mods]
+    batch = BatchSimulator(bs)
+    trs = batch.forward(shots, use_graph=True)
+    torch.cuda.synchronize()
+    for k in range(4):
+        assert torch.equal(trs[k], ref[k][0]), k
+    g_b = [[torch.zeros(shape[::-1], dtype=torch.float32, device="cuda") for _ in range(3)] for _ in mods]
+    _, misfit = batch.gradient(shots, [torch.zeros_like(t) for t in trs], [g[0] for g in g_b],
+                               [g[1] for g in g_b], [g[2] for g in g_b], ckpt_every=8)
+    torch.cuda.synchronize()
+    for k in range(4):
+        assert torch.equal(misfit[k:k + 1], ref[k][1]), k
+        for p in range(3):
+            assert torch.equal(g_b[k][p], ref[k][2][p]), (k, p)
+    batch.close()
+    for s in bs:
+        s.close()
