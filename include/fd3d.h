@@ -164,8 +164,9 @@ int fd3d_forward(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *
  * with the whole forward workspace in the library's static device scratch instead of a
  * caller workspace.  The scratch holds FD3D_STATIC_SCRATCH_BYTES (64 MiB) per GPU, taken
  * when the library's code object is loaded on that GPU and held until the process ends;
- * grids whose fd3d_workspace_bytes exceed it are rejected with FD3D_EWS (FP32 grids up to
- * about 96^3 cells with the default 4096-receiver capacity; FP64 about half the cells).
+ * grids whose fd3d_workspace_bytes exceed it are rejected with FD3D_EWS (with the default
+ * options -- 4096 receivers, the automatic field layout, which is interleaved rows with a
+ * model copy for grids this small -- FP32 grids up to 84^3 cells, FP64 up to 67^3).
  * Arguments as fd3d_create and fd3d_forward: model arrays, src (its wavelet), rec_pos and
  * traces are the caller's; final_state (9 device T[nz][ny][nx], order as fd3d_get_state)
  * receives the final state, or is NULL.  The call allocates no device memory and creates
