@@ -160,6 +160,15 @@ def test_c1_full_size_truncated(c1_ref, dtype, kern):
     compare(got, ref, TOL[dtype], f"c1 truncated {kern}")
 
 
+def test_c1_full_size_truncated_separate_arrays(c1_ref):
+    """The same 256^3 case with the fields in separate arrays (the library picks
+    interleaved rows on this grid in FP32; FP64 above already runs separate arrays)."""
+    shot, ref = c1_ref
+    print(f"[c1] gpu 256^3 x {C1_NT} float32 tile 256x4 z64, separate arrays", flush=True)
+    got = gpu_run(shot, torch.float32, kernel=("tile", 4, 64, 256), layout="separate")
+    compare(got, ref, TOL[torch.float32], "c1 truncated, separate arrays")
+
+
 C2_NT = 8
 
 
@@ -181,6 +190,15 @@ def test_c2_full_size_truncated(c2_ref, dtype, kern):
     print(f"[c2] gpu 512x512x256 x {C2_NT} {dtype} {kern}", flush=True)
     got = gpu_run(shot, dtype, kernel=kern)
     compare(got, ref, TOL[dtype], f"c2 truncated {kern}")
+
+
+def test_c2_full_size_truncated_interleaved_rows(c2_ref):
+    """The 512x512x256 case with the fields in interleaved rows (the library picks
+    separate arrays there; a 64-plane sweep keeps the window within 1 GiB)."""
+    shot, ref = c2_ref
+    print(f"[c2] gpu 512x512x256 x {C2_NT} float32 tile 256x4 z64, interleaved rows", flush=True)
+    got = gpu_run(shot, torch.float32, kernel=("tile", 4, 64, 256), layout="rows")
+    compare(got, ref, TOL[torch.float32], "c2 truncated, interleaved rows")
 
 
 @pytest.fixture(scope="module")
