@@ -147,6 +147,9 @@ int fd3d_workspace_bytes(int nx, int ny, int nz, const fd3d_opts *opts, size_t *
  * (6/7) / (vp_max sqrt(1/dx^2 + 1/dy^2 + 1/dz^2)), i.e. 6/(7 sqrt 3) dx / vp_max for cubic
  * cells (FD3D_ECFL; Eq.(5) prints the rounded 0.495), builds the damping profiles on the host in double
  * and uploads them.  workspace: device, >= fd3d_workspace_bytes, 256-byte aligned.
+ * With interleaved rows (fd3d_opts.layout) the model is copied into the workspace here
+ * and the passes read that copy; the caller's arrays must still stay alive and unchanged
+ * (batches and the Born forward recognise a shared model by their addresses).
  * Synchronises the stream once (model statistics). */
 int fd3d_create(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const void *mu,
                 const void *rho, double dx, double dt, int nt, const fd3d_opts *opts,
