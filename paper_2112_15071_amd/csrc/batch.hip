@@ -1,28 +1,24 @@
-// Batches of shots (uneven grids, own models, sources and receivers) stepped together:
-// persistent launches per pass over many shots, the lockstep and cache-blocked
-// schedules, their capture as one hipGraph, the batch tuner and the batched gradient.
+// Batches: many contexts (uneven grids, own models, sources and receivers) stepped
+// together, one persistent launch per pass for all shots, optionally captured once as a
+// hipGraph holding the whole nt-step sequence; the batch tuner and the batched gradient.
+//
+// Schedules.  Lockstep: every launch covers every shot, and the shots advance one step
+// at a time together.  Cache-blocked groups: the shots, taken from the smallest working
+// set (nine fields and three model arrays) to the largest, are cut into runs whose
+// working sets add up to at most a given number of bytes; one group runs all its nt
+// steps (one launch per pass over the group's shots) before the next group starts.
+// Sized to the last-level (Infinity) cache, a group's fields stay resident from one step
+// to the next.  Shots are independent, so both schedules give every shot the same result
+// bit for bit.
 #include "host.h"
 
 #include <new>
 
 using namespace fd3d;
 
-// ---------------------------------------------------------------------------------
-// Batches: many contexts (uneven grids, own models, sources and receivers) stepped
-// together, one persistent launch per pass for all shots, optionally captured once as
-// a hipGraph holding the whole nt-step sequence.
-//
-// Schedules.  Lockstep: every launch covers every shot, and the shots advance one step
-// at a time together.  Cache-blocked groups: the shots, taken from the smallest working
-// set (nine fields and three model arrays) to the largest, are cut into runs whose
-// working sets add up to at most a given number of bytes; one group runs all its nt
-// steps (one launch per pass over the group's shots) before the next group starts.  Sized to the last-level (Infinity)
-// cache, a group's fields stay resident from one step to the next.  Shots are
-// independent, so both schedules give every shot the same result bit for bit.
-
-// Shots at positions [s0, s0 + ns) of the batch's schedule order, stepped by one launch per pass: their work items and
-// receiver components (counted from the group's first), the persistent grid size and
-// the tile shapes of the launch (tx2 = 0: one shape).
+// Shots at positions [s0, s0 + ns) of the batch's schedule order, stepped by one launch
+// per pass: their work items and receiver components (counted from the group's first),
+// the persistent grid size and the tile shapes of the launch (tx2 = 0: one shape).
 struct BatchGroup {
     int s0, ns, tiles, recs, wgs;
     int tx, ty, tx2, ty2;

@@ -91,6 +91,8 @@ inline bool coarse_on(const fd3d_opts &o) { return o.coarse[0] > 0; }
 
 } // namespace fd3d
 
+// A context (fd3d_create): one grid, its model and options, its workspace layout, the
+// host staging of sources and receivers, the kernel choice and the gradient state.
 struct fd3d_ctx {
     int n[3];
     int nt;
