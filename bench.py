@@ -70,12 +70,13 @@ def step_bytes(kern):
 
 
 # gradient, per shot and time step: forward with checkpoints (120), segment recompute
-# storing v^{n+1/2} and sigma^n (156), the four adjoint passes: stress-A 27 fields,
-# velocity-A 12, velocity-B 19, stress-B 15 (292)
-GRAD_BYTES_PER_CELL_STEP = 120 + 156 + 4 * (27 + 12 + 19 + 15)
+# storing v^{n+1/2} (132), the adjoint passes: stress-A 27 fields, velocity-A 12, the
+# pointwise buoyancy pass 19 (A_v, v^{n+1/2}, v^{n-1/2}, rho, g_b read and written, Y
+# written), stress-B 15 (292)
+GRAD_BYTES_PER_CELL_STEP = 120 + 132 + 4 * (27 + 12 + 19 + 15)
 # the design figure with eight staggered-point accumulators and no hand-over fields
-# between the adjoint passes (forward 120 + recompute 156 + adjoint 232)
-GRAD_BYTES_DESIGN = 120 + 156 + 232
+# between the adjoint passes (forward 120 + recompute 132 + adjoint 232)
+GRAD_BYTES_DESIGN = 120 + 132 + 232
 # measured counter calibration (plain 1 GiB copy): FETCH_SIZE reads 0.5x, WRITE_SIZE 1.0x
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 

@@ -7,10 +7,16 @@
 //   start of step n:  adjoint(sigma^{n+1}) = A_s,  adjoint(v^{n+1/2}) so far = G_v A_v
 //   adj_stress:  T = G_s A_s;  A_v <- G_v A_v - dt D_S(C T);  gradients of C from E v^{n+1/2}
 //   residual:    A_v += W^T r^n
-//   adj_vel:     U = G_v A_v;  A_s <- G_s A_s - dt E(b U);  gradient of b from D_S sigma^n
+//   adj_vel:     U = G_v A_v;  A_s <- G_s A_s - dt E(b U);  gradient of b
 // leaving adjoint(sigma^n) = A_s and adjoint(v^{n-1/2}) = G_v A_v.  D_S is the
 // divergence stencil of the velocity pass and E the strain-rate stencil of the stress
 // pass; under the zero-halo rules D_S = -E^T, so these are the transposed passes.
+//
+// The gradient of b needs, at each velocity sample, the step's increment over b,
+// dt D_S sigma^n + c s (c the force source's coefficient), which the velocity pass
+// multiplied by b, added to v^{n-1/2} and damped: v^{n+1/2} = G_v (v^{n-1/2} + b (...)).
+// It is recovered pointwise from the two stored velocities, (v^{n+1/2} / G_v - v^{n-1/2})
+// rho_eff, so the segment recompute stores v^{n+1/2} only (not sigma^n).
 #pragma once
 
 #include "common.h"
@@ -25,7 +31,7 @@ template <typename T> struct AdjGrid {
     T *gs[3];          // mu_xy, mu_xz, mu_yz at the shear-stress points
     T *gb[3];          // buoyancy at vx, vy, vz points
     const T *vst[3];   // stored v^{n+1/2}
-    const T *sst[6];   // stored sigma^n
+    const T *vprev[3]; // stored v^{n-1/2}
 };
 
 template <typename T>
@@ -131,21 +137,47 @@ __device__ __forceinline__ T yval(const Grid<T> &G, const AdjGrid<T> &A, int c, 
     return (damp(G, c, i, j, k) * A.a[c][p]) * buoy(G.rho[p], G.rho[p + e]);
 }
 
-// Stored sigma^n for the divergence stencil (zero outside the active range).
+// Contribution of step n to the gradient of b at velocity sample c of node (i,j,k):
+// U (v^{n+1/2} / G_v - v^{n-1/2}) rho_eff, the step's increment dt D_S sigma^n + c s
+// recovered from the stored velocities (see the top of this file).
 template <typename T>
-__device__ __forceinline__ T sv(const Grid<T> &G, const AdjGrid<T> &A, int c, int i, int j, int k)
+__device__ __forceinline__ T gb_term(const Grid<T> &G, const AdjGrid<T> &A, int c, int i, int j, int k, long p)
 {
-    return rdc(A.sst[c - SXX], c, i, j, k, G);
+    const long e = c == VX ? 1 : (c == VY ? G.sy : G.sz);
+    const T g = damp(G, c, i, j, k);
+    const T u = g * A.a[c][p];
+    const T inc = A.vst[c - VX][p] / g - A.vprev[c - VX][p];
+    return u * (inc * ((G.rho[p] + G.rho[p + e]) * T(0.5)));
+}
+
+// The pointwise part of the tiled adjoint velocity step at the samples of node (i,j,k):
+// the gradient of b, and Y = b U for the stress-type pass that follows (y[c]).
+template <typename T>
+__global__ void __launch_bounds__(256) adj_gb_point(Grid<T> G, AdjGrid<T> A, T *__restrict__ y0, T *__restrict__ y1,
+                                                   T *__restrict__ y2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= G.nx || j >= G.ny) return;
+    const long p = i + G.sy * j + G.sz * k;
+    T *y[3] = {y0, y1, y2};
+    const bool act[3] = {i <= G.nx - 2, j <= G.ny - 2, k <= G.nz - 2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (!act[c]) continue;
+        const long e = c == 0 ? 1 : (c == 1 ? G.sy : G.sz);
+        A.gb[c][p] += gb_term(G, A, VX + c, i, j, k, p);
+        y[c][p] = (damp(G, VX + c, i, j, k) * A.a[VX + c][p]) * buoy(G.rho[p], G.rho[p + e]);
+    }
 }
 
 // (a12) adjoint of the velocity pass, at the samples of node (i,j,k).
 template <typename T>
-__device__ __forceinline__ void adj_vel_body(const Grid<T> &G, const AdjGrid<T> &A, const Inject<T> &src, int n, int i,
-                                             int j, int k)
+__device__ __forceinline__ void adj_vel_body(const Grid<T> &G, const AdjGrid<T> &A, int i, int j, int k)
 {
     const long p = i + G.sy * j + G.sz * k;
     const T rdx = G.rdx, rdy = G.rdy, rdz = G.rdz, dt = G.dt;
-    const T s = src.on ? src.wavelet[n] : T(0);
 
     // A_s <- G_s A_s - dt E(b U)
     {
@@ -173,37 +205,10 @@ __device__ __forceinline__ void adj_vel_body(const Grid<T> &G, const AdjGrid<T> 
         A.a[SYZ][p] = damp(G, SYZ, i, j, k) * A.a[SYZ][p] - dt * e;
     }
 
-    // gradient of b: dt (D_S sigma^n + w F s / dx^3) U at the velocity samples
-    if (i <= G.nx - 2) {
-        const T d = dstag(sv(G, A, SXX, i + 1, j, k), sv(G, A, SXX, i, j, k), sv(G, A, SXX, i + 2, j, k), sv(G, A, SXX, i - 1, j, k), rdx)
-                  + dstag(sv(G, A, SXY, i, j, k), sv(G, A, SXY, i, j - 1, k), sv(G, A, SXY, i, j + 1, k), sv(G, A, SXY, i, j - 2, k), rdy)
-                  + dstag(sv(G, A, SXZ, i, j, k), sv(G, A, SXZ, i, j, k - 1), sv(G, A, SXZ, i, j, k + 1), sv(G, A, SXZ, i, j, k - 2), rdz);
-        const T u = damp(G, VX, i, j, k) * A.a[VX][p];
-        T g = dt * d * u;
-        const int t = tap_of(src, VX, i, j, k);
-        if (t >= 0) g += src.coef[VX * 8 + t] * s * u;
-        A.gb[0][p] += g;
-    }
-    if (j <= G.ny - 2) {
-        const T d = dstag(sv(G, A, SXY, i, j, k), sv(G, A, SXY, i - 1, j, k), sv(G, A, SXY, i + 1, j, k), sv(G, A, SXY, i - 2, j, k), rdx)
-                  + dstag(sv(G, A, SYY, i, j + 1, k), sv(G, A, SYY, i, j, k), sv(G, A, SYY, i, j + 2, k), sv(G, A, SYY, i, j - 1, k), rdy)
-                  + dstag(sv(G, A, SYZ, i, j, k), sv(G, A, SYZ, i, j, k - 1), sv(G, A, SYZ, i, j, k + 1), sv(G, A, SYZ, i, j, k - 2), rdz);
-        const T u = damp(G, VY, i, j, k) * A.a[VY][p];
-        T g = dt * d * u;
-        const int t = tap_of(src, VY, i, j, k);
-        if (t >= 0) g += src.coef[VY * 8 + t] * s * u;
-        A.gb[1][p] += g;
-    }
-    if (k <= G.nz - 2) {
-        const T d = dstag(sv(G, A, SXZ, i, j, k), sv(G, A, SXZ, i - 1, j, k), sv(G, A, SXZ, i + 1, j, k), sv(G, A, SXZ, i - 2, j, k), rdx)
-                  + dstag(sv(G, A, SYZ, i, j, k), sv(G, A, SYZ, i, j - 1, k), sv(G, A, SYZ, i, j + 1, k), sv(G, A, SYZ, i, j - 2, k), rdy)
-                  + dstag(sv(G, A, SZZ, i, j, k + 1), sv(G, A, SZZ, i, j, k), sv(G, A, SZZ, i, j, k + 2), sv(G, A, SZZ, i, j, k - 1), rdz);
-        const T u = damp(G, VZ, i, j, k) * A.a[VZ][p];
-        T g = dt * d * u;
-        const int t = tap_of(src, VZ, i, j, k);
-        if (t >= 0) g += src.coef[VZ * 8 + t] * s * u;
-        A.gb[2][p] += g;
-    }
+    // gradient of b at the velocity samples: U times the step's increment over b
+    if (i <= G.nx - 2) A.gb[0][p] += gb_term(G, A, VX, i, j, k, p);
+    if (j <= G.ny - 2) A.gb[1][p] += gb_term(G, A, VY, i, j, k, p);
+    if (k <= G.nz - 2) A.gb[2][p] += gb_term(G, A, VZ, i, j, k, p);
 }
 
 // Single-grid launches of the two adjoint passes (64 x 4 threads per block, one z plane).
@@ -215,12 +220,12 @@ template <typename T> __global__ void __launch_bounds__(256) adj_stress_cell(Gri
     adj_stress_body(G, A, i, j, (int)blockIdx.z);
 }
 
-template <typename T> __global__ void __launch_bounds__(256) adj_vel_cell(Grid<T> G, AdjGrid<T> A, Inject<T> src, int n)
+template <typename T> __global__ void __launch_bounds__(256) adj_vel_cell(Grid<T> G, AdjGrid<T> A)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= G.nx || j >= G.ny) return;
-    adj_vel_body(G, A, src, n, i, j, (int)blockIdx.z);
+    adj_vel_body(G, A, i, j, (int)blockIdx.z);
 }
 
 // (a11) adjoint of the sampling for the receivers of one colour (no two of them share a

@@ -203,12 +203,8 @@ int launch_multi(const BatchGroup &gr, const ShotFwd<T> *d, int n, int pass, hip
     case kPassVel: vel_tile_multi<T, TX, TY, TX2, TY2, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
     case kPassStress: stress_tile_multi<T, TX, TY, TX2, TY2, FS><<<gs, NT, 0, st>>>(d, S, W, n, rec); break;
     case kPassVelSave: vel_tile_multi<T, TX, TY, TX2, TY2, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n); break;
-    case kPassStressSave:
-        stress_tile_multi<T, TX, TY, TX2, TY2, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n, none);
-        break;
     case kPassStressA: stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n, none); break;
     case kPassVelA: vel_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
-    case kPassVelB: vel_tile_multi<T, TX, TY, TX2, TY2, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n); break;
     default: stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n, none); break;
     }
     return FD3D_OK;
@@ -400,11 +396,11 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
 // ---- batched gradient ----------------------------------------------------------
 // Batch workspace of fd3d_batch_gradient: descriptor arrays (nshot entries each) of the
 // forward pass, of the segment recompute per segment slot m (store pointers of slot m),
-// of the adjoint passes (stress-A and velocity-B per slot m, which read the fields
-// stored in slot m; velocity-A and stress-B once), of the residual injection, and per
-// checkpoint the save and restore copy lists.
+// of the adjoint passes (stress-A per slot m, which reads the velocity stored in slot m;
+// velocity-A and stress-B once), of the residual injection, and per checkpoint the save
+// and restore copy lists.
 struct BatchGradLayout {
-    size_t fwd0, fwd_slot, sa_slot, vb_slot, va, sb, inj, save_copy, rest_copy, total;
+    size_t fwd0, fwd_slot, sa_slot, va, sb, inj, save_copy, rest_copy, total;
     size_t fwd_bytes, inj_bytes, copy_bytes;
     int k, nseg;
 };
@@ -423,8 +419,6 @@ template <typename T> BatchGradLayout make_batch_grad_layout(const fd3d_batch *b
     L.fwd_slot = off;
     off += (size_t)k * L.fwd_bytes;
     L.sa_slot = off;
-    off += (size_t)k * L.fwd_bytes;
-    L.vb_slot = off;
     off += (size_t)k * L.fwd_bytes;
     L.va = off;
     off += L.fwd_bytes;
@@ -510,34 +504,30 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     unsigned char *h = b->grad_host.data();
     const size_t fbytes = S * sizeof(ShotFwd<T>);
     std::memcpy(h + BL.fwd0, fw.data(), fbytes);
-    // descriptors of one adjoint pass: the shot's tile map and sources, the pass's grid and outputs
-    auto adj_desc = [&](int s, const AdjTiles<T> &P, int p, bool with_src) {
+    // descriptors of one adjoint pass: the shot's tile map, the pass's grid and outputs, no source
+    auto adj_desc = [&](int s, const AdjTiles<T> &P, int p) {
         ShotFwd<T> d = fw[s];
         d.G = P.g[p];
         d.io = P.io[p];
-        if (!with_src) {
-            std::memset(&d.src, 0, sizeof d.src);
-            for (int f = 0; f < NFIELD; ++f) d.src.i0[f] = d.src.j0[f] = d.src.k0[f] = -(1 << 28);
-        }
+        std::memset(&d.src, 0, sizeof d.src);
+        for (int f = 0; f < NFIELD; ++f) d.src.i0[f] = d.src.j0[f] = d.src.k0[f] = -(1 << 28);
         return d;
     };
     std::vector<ShotFwd<T>> va(S), sb(S);
     for (int m = 0; m < k; ++m) {
-        std::vector<ShotFwd<T>> f2 = fw, sa(S), vb(S);
+        std::vector<ShotFwd<T>> f2 = fw, sa(S);
         for (int s = 0; s < S; ++s) {
-            char *slot = (char *)gws[s] + GL[s].seg + (size_t)m * GL[s].group;
-            for (int f = 0; f < NFIELD; ++f) f2[s].G.save[f] = (T *)(slot + f * GL[s].fstep);
+            char *slot = seg_slot((char *)gws[s], GL[s], m);
+            for (int q = 0; q < 3; ++q) f2[s].G.save[VX + q] = (T *)(slot + q * GL[s].fstep);
             const AdjTiles<T> P = adj_tiles<T>(fw[s].G, (char *)gws[s], GL[s], slot);
-            sa[s] = adj_desc(s, P, 0, false);
-            vb[s] = adj_desc(s, P, 2, true);
+            sa[s] = adj_desc(s, P, 0);
             if (m == 0) {
-                va[s] = adj_desc(s, P, 1, false);
-                sb[s] = adj_desc(s, P, 3, false);
+                va[s] = adj_desc(s, P, 1);
+                sb[s] = adj_desc(s, P, 2);
             }
         }
         std::memcpy(h + BL.fwd_slot + m * BL.fwd_bytes, f2.data(), fbytes);
         std::memcpy(h + BL.sa_slot + m * BL.fwd_bytes, sa.data(), fbytes);
-        std::memcpy(h + BL.vb_slot + m * BL.fwd_bytes, vb.data(), fbytes);
     }
     std::memcpy(h + BL.va, va.data(), fbytes);
     std::memcpy(h + BL.sb, sb.data(), fbytes);
@@ -605,7 +595,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         for (int n = n0; n < n1; ++n) {
             const ShotFwd<T> *d = desc(BL.fwd_slot + (n - n0) * BL.fwd_bytes);
             pass(d, n, kPassVelSave);
-            pass(d, n, kPassStressSave);
+            pass(d, n, kPassStress);
         }
         for (int n = n1 - 1; n >= n0; --n) {
             pass(desc(BL.sa_slot + (n - n0) * BL.fwd_bytes), n, kPassStressA);
@@ -613,7 +603,11 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
             for (int q = 0; q < ncol; ++q)
                 if (cbase[q] > 0)
                     inject_residual_multi<T><<<(cbase[q] + 255) / 256, 256, 0, st>>>(idesc, S, q, cbase[q], b->nt, n);
-            pass(desc(BL.vb_slot + (n - n0) * BL.fwd_bytes), n, kPassVelB);
+            for (int s = 0; s < S; ++s) {  // b gradient and Y, shot by shot (pointwise)
+                char *w = (char *)gws[s];
+                set_stored_velocity(ag[s], GL[s], seg_slot(w, GL[s], n - n0), prev_velocity(w, GL[s], sg, n - n0));
+                launch_gb_point<T>(fw[s].G, ag[s], w, GL[s], st);
+            }
             pass(desc(BL.sb), n, kPassStressB);
         }
     }

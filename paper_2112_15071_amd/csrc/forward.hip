@@ -19,7 +19,6 @@ void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &
     constexpr int NT = TX * TY;
     const int nws = nwg + rec_blocks(rec, NT);
     if (G.save[VX] != nullptr && pass == kPassVel) pass = kPassVelSave;
-    if (G.save[VX] != nullptr && pass == kPassStress) pass = kPassStressSave;
     if (G.cm[0] > 0) {  // coarse medium: instantiations of their own (forward passes only)
         if (pass == kPassVel) vel_tile<T, TX, TY, FS, kFwd, false, false, true><<<nwg, NT, 0, st>>>(G, inj, n, tm);
         else stress_tile<T, TX, TY, FS, kFwd, false, false, true><<<nws, NT, 0, st>>>(G, inj, n, tm, rec);
@@ -37,9 +36,8 @@ void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &
     }
     switch (pass) {
     case kPassVel: vel_tile<T, TX, TY, FS, kFwd, false, NTP><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
-    case kPassStress: stress_tile<T, TX, TY, FS, kFwd, false, NTP><<<nws, NT, 0, st>>>(G, inj, n, tm, rec); break;
     case kPassVelSave: vel_tile<T, TX, TY, FS, kFwdSave, false, NTP><<<nwg, NT, 0, st>>>(G, inj, n, tm); break;
-    default: stress_tile<T, TX, TY, FS, kFwdSave, false, NTP><<<nws, NT, 0, st>>>(G, inj, n, tm, rec); break;
+    default: stress_tile<T, TX, TY, FS, kFwd, false, NTP><<<nws, NT, 0, st>>>(G, inj, n, tm, rec); break;
     }
 }
 

@@ -216,34 +216,30 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
     k1 = min(k0 + tm.zc, nz);
 }
 
-// What a tile body computes.  kFwd: the forward pass; kFwdSave: the forward pass that
-// also stores v^{n+1/2} and sigma^n through the grid's save pointers (the gradient's
-// segment recompute).  For the velocity-type body,
-// kAdjA: A_v <- G_v A_v - dt D_S(X) (X = C G_s A_s, precomputed) and kAdjB:
-// g_b += dt D_S(sigma^n) U + force term, Y = U / rho_eff (U = G_v A_v).  For the
-// stress-type body, kAdjA: gradients of C from E(v^{n+1/2}) and T = G_s A_s, X = C T;
-// kAdjB: A_s <- G_s A_s - dt E(Y).  The adjoint modes read and write the arrays named
-// by the grid (f[] pointing at the adjoint, stored or scratch fields) and by TileIO.
-// Modes of the tile bodies: forward, adjoint A/B passes, forward that also stores the
-// state for the adjoint, and the Born (tangent-linear) forward, whose source terms use
-// the derivatives the background's own passes compute: kBornV is the background's
-// forward velocity update plus dt db (D_S sigma) + db c s added to the perturbation's
-// velocity in io.out[0..2] (db = -b^2 drho_eff, drho in io.acc[0]); kBornS is the
-// background's forward stress update plus dt (dC E v) added to the perturbation's stress
-// in io.out[0..5] (dlam, dmu in io.acc[0], io.acc[1]; no damping, no source).
+// What a tile body computes.  kFwd: the forward pass; kFwdSave (velocity-type body): the
+// forward velocity pass that also stores v^{n+1/2} through the grid's save pointers (the
+// gradient's segment recompute).  For the velocity-type body, kAdjA:
+// A_v <- G_v A_v - dt D_S(X) (X = C G_s A_s, precomputed).  For the stress-type body,
+// kAdjA: gradients of C from E(v^{n+1/2}) and T = G_s A_s, X = C T; kAdjB:
+// A_s <- G_s A_s - dt E(Y) (Y = G_v A_v / rho_eff, formed pointwise with the buoyancy
+// gradient by adj_gb_point).  The adjoint modes read and write the arrays named by the
+// grid (f[] pointing at the adjoint, stored or scratch fields) and by TileIO.  The Born
+// (tangent-linear) modes use the derivatives the background's own passes compute: kBornV
+// is the background's forward velocity update plus dt db (D_S sigma) + db c s added to
+// the perturbation's velocity in io.out[0..2] (db = -b^2 drho_eff, drho in io.acc[0]);
+// kBornS is the background's forward stress update plus dt (dC E v) added to the
+// perturbation's stress in io.out[0..5] (dlam, dmu in io.acc[0], io.acc[1]; no damping,
+// no source).
 enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3, kBornV = 4, kBornS = 5 };
 
 // Sweep direction of each pass (true: upward, decreasing k), chosen so that every pass
 // starts where the pass before it ended and finds those planes still in the last-level
-// cache: forward velocity down, stress up; adjoint stress-A down, velocity-A up,
-// velocity-B down, stress-B up.  A pass that sweeps up also takes its tiles in reverse
-// order, so that when the tiles run in several rounds its first round covers the last
-// round of the pass before.
+// cache: forward velocity down, stress up; adjoint stress-A down, velocity-A up, then the
+// pointwise buoyancy pass in memory order (down), stress-B up.  A pass that sweeps up also
+// takes its tiles in reverse order, so that when the tiles run in several rounds its first
+// round covers the last round of the pass before.
 template <int MODE> constexpr bool vel_sweeps_up() { return MODE == kAdjA; }
-template <int MODE> constexpr bool stress_sweeps_up()
-{
-    return MODE == kFwd || MODE == kFwdSave || MODE == kAdjB || MODE == kBornS;
-}
+template <int MODE> constexpr bool stress_sweeps_up() { return MODE == kFwd || MODE == kAdjB || MODE == kBornS; }
 
 // Waits for every outstanding memory operation of the wave (s_waitcnt with all counters
 // zero).  Called once between a sweep's prologue loads and its plane loop: the compiler
@@ -262,8 +258,9 @@ __device__ __forceinline__ int tile_of(int b, int nwg, bool reverse)
 }
 
 template <typename T> struct TileIO {
-    T *out[6];  // X (6) or Y (3) scratch
-    T *acc[5];  // gradient accumulators: (gl, gm, g_mu_xy, g_mu_xz, g_mu_yz) or (g_bx, g_by, g_bz)
+    T *out[6];  // X (stress-A), or the Born perturbation's velocity (3) or stress (6)
+    T *acc[5];  // stress-A's gradient accumulators (gl, gm, g_mu_xy, g_mu_xz, g_mu_yz), or the
+                // Born model perturbation (drho; dlam, dmu)
 };
 
 // Source coefficients of NC consecutive components starting at C0, staged in LDS when a
@@ -286,6 +283,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                                               int k1, const TileIO<T> &io = TileIO<T>{})
 {
     static_assert(!CM || MODE == kFwd, "the coarse medium is read by the forward passes only");
+    static_assert(MODE == kFwd || MODE == kFwdSave || MODE == kAdjA || MODE == kBornV, "velocity-type modes");
     constexpr int NT = TX * TY;
     // LDS plane shapes: sxx x(-1,+2); sxy x(-2,+1) y(-2,+1); sxz x(-2,+1); syy y(-1,+2);
     // syz y(-2,+1); rho x(+1) y(+1) with the corner.  The last element is a dummy slot.
@@ -390,17 +388,12 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 
     // plane registers, loaded one plane ahead
     struct Plane {
-        T cxx, cyy, cxy, vx, vy, vz, xx, xy, xz, yy, yz, r, g0, g1, g2, dr, dvx, dvy, dvz;
+        T cxx, cyy, cxy, vx, vy, vz, xx, xy, xz, yy, yz, r, dr, dvx, dvy, dvz;
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const unsigned pk = wplane(w, kk, ok), pr = wplane(w, kk, ok && use_rho), o = oc + pk;
         const rsrc_t bxx = wfield(fxx, w), byy = wfield(fyy, w), bxy = wfield(fxy, w);
         const rsrc_t bxz = wfield(fxz, w), byz = wfield(fyz, w), br = wfield(rho, w);
-        if constexpr (MODE == kAdjB) {
-            P.g0 = ld<T>(wfield(io.acc[0], w), o);
-            P.g1 = ld<T>(wfield(io.acc[1], w), o);
-            P.g2 = ld<T>(wfield(io.acc[2], w), o);
-        }
         if constexpr (born) {
             P.dvx = ld<T>(wfield(io.out[0], w), o);
             P.dvy = ld<T>(wfield(io.out[1], w), o);
@@ -448,7 +441,6 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             Ldr[hr.lds] = P.dr;
         }
         const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
-        const T ga0 = P.g0, ga1 = P.g1, ga2 = P.g2;
         const T bvx0 = P.dvx, bvy0 = P.dvy, bvz0 = P.dvz;  // the perturbation's velocity (kBornV)
         // buoyancy at the three velocity samples: node means (Sec. 2.2.1), or the coarse
         // medium sampled at each sample's own position (its loads issued before the next
@@ -510,15 +502,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 if (srcv) add += db * cf(VX, tap_of(src, VX, i, j, k)) * s;
                 st(bvx, st_vx + pw, bvx0 + add);
             }
-            if constexpr (MODE == kAdjA) {
-                st(ovx, st_vx + pw, (gxh * gyi * gz_i) * vx0 - dt * d);
-            } else if constexpr (MODE == kAdjB) {
-                const T u = (gxh * gyi * gz_i) * vx0;
-                T g = dt * d * u;
-                if (srcv) g += cf(VX, tap_of(src, VX, i, j, k)) * s * u;
-                st(wfield(io.acc[0], w), st_vx + pw, ga0 + g);
-                st(wfield(io.out[0], w), st_vx + pw, u * buoy(r0, Lr[ty * WR + tx + 1]));
-            }
+            if constexpr (MODE == kAdjA) st(ovx, st_vx + pw, (gxh * gyi * gz_i) * vx0 - dt * d);
         }
         {
             const int ox = (ty + 2) * W3 + tx + 2;
@@ -541,15 +525,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 if (srcv) add += db * cf(VY, tap_of(src, VY, i, j, k)) * s;
                 st(bvy, st_vy + pw, bvy0 + add);
             }
-            if constexpr (MODE == kAdjA) {
-                st(ovy, st_vy + pw, (gxi * gyh * gz_i) * vy0 - dt * d);
-            } else if constexpr (MODE == kAdjB) {
-                const T u = (gxi * gyh * gz_i) * vy0;
-                T g = dt * d * u;
-                if (srcv) g += cf(VY, tap_of(src, VY, i, j, k)) * s * u;
-                st(wfield(io.acc[1], w), st_vy + pw, ga1 + g);
-                st(wfield(io.out[1], w), st_vy + pw, u * buoy(r0, Lr[(ty + 1) * WR + tx]));
-            }
+            if constexpr (MODE == kAdjA) st(ovy, st_vy + pw, (gxi * gyh * gz_i) * vy0 - dt * d);
         }
         {
             const int o = own_c3 + tx + 2;
@@ -573,15 +549,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 if (srcv) add += db * cf(VZ, tap_of(src, VZ, i, j, k)) * s;
                 st(bvz, st_vz + pw, bvz0 + add);
             }
-            if constexpr (MODE == kAdjA) {
-                st(ovz, st_vz + pw, (gxi * gyi * gz_h) * vz0 - dt * d);
-            } else if constexpr (MODE == kAdjB) {
-                const T u = (gxi * gyi * gz_h) * vz0;
-                T g = dt * d * u;
-                if (srcv) g += cf(VZ, tap_of(src, VZ, i, j, k)) * s * u;
-                st(wfield(io.acc[2], w), st_vz + pw, ga2 + g);
-                st(wfield(io.out[2], w), st_vz + pw, u * buoy(r0, r1));
-            }
+            if constexpr (MODE == kAdjA) st(ovz, st_vz + pw, (gxi * gyi * gz_h) * vz0 - dt * d);
         }
         if constexpr (up) {
             qxz[3] = qxz[2]; qxz[2] = qxz[1]; qxz[1] = qxz[0]; qxz[0] = nxz;
@@ -608,6 +576,7 @@ template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false
 __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0,
                                                  int k0, int k1, const TileIO<T> &io = TileIO<T>{})
 {
+    static_assert(MODE == kFwd || MODE == kAdjA || MODE == kAdjB || MODE == kBornS, "stress-type modes");
     static_assert(!CM || MODE == kFwd, "the coarse medium is read by the forward passes only");
     constexpr int NT = TX * TY;
     // vx x(-2,+1) y(-1,+2); vy x(-1,+2) y(-2,+1); vz x(-1,+2) y(-1,+2); mu x(+1) y(+1) corner
@@ -663,7 +632,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     auto cf = [&](int c, int t) -> T { return t >= 0 ? s_coef[(c - SXX) * 8 + (t & 7)] : T(0); };
     const unsigned st_xz = (in && i <= nx - 2) ? oc : kOOB;
     const unsigned st_yz = (in && j <= ny - 2) ? oc : kOOB;
-    constexpr bool fwd = MODE == kFwd || MODE == kFwdSave || MODE == kBornS;
+    constexpr bool fwd = MODE == kFwd || MODE == kBornS;
     constexpr bool use_model = MODE != kAdjB && !CM;
     // coarse medium: per-column coarse coordinates of the node (i, j), xy (i + 1/2, j + 1/2),
     // xz (i + 1/2, j) and yz (i, j + 1/2) columns; bilinear samples of the coarse planes
@@ -842,14 +811,6 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         const unsigned pw = wplane(w, k, true);
         __syncthreads();
 
-        if constexpr (MODE == kFwdSave) {
-            stm<NTP>(wfield(G.save[SXX], w), oc + pw, o_xx);
-            stm<NTP>(wfield(G.save[SYY], w), oc + pw, o_yy);
-            stm<NTP>(wfield(G.save[SZZ], w), oc + pw, o_zz);
-            stm<NTP>(wfield(G.save[SXY], w), oc + pw, o_xy);
-            stm<NTP>(wfield(G.save[SXZ], w), oc + pw, o_xz);
-            stm<NTP>(wfield(G.save[SYZ], w), oc + pw, o_yz);
-        }
         const T exx = dstag(Lx[ovx], Lx[ovx - 1], Lx[ovx + 1], Lx[ovx - 2], rdx);
         const T eyy = dstag(Ly[ovy], Ly[ovy - W3], Ly[ovy + W3], Ly[ovy - 2 * W3], rdy);
         T ezz;
@@ -952,7 +913,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
 }
 
 // ---------------------------------------------------------------------------------
-// Single-grid launches: one workgroup per tile (MODE kFwd or kFwdSave).
+// Single-grid launches: one workgroup per tile.
 template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false, bool CM = false>
 __global__ void __launch_bounds__(TX *TY) vel_tile(Grid<T> G, Inject<T> src, int n, TileMap tm)
 {

@@ -7,8 +7,8 @@ using namespace fd3d;
 
 namespace {
 
-// One adjoint pass of a tiled step (stress-A, velocity-A, velocity-B, stress-B) on the
-// context's tile shape and cache policy; inj: the source (read by velocity-B).
+// One adjoint pass of a tiled step (stress-A, velocity-A, stress-B) on the context's tile
+// shape and cache policy.
 template <typename T>
 void launch_adj_pass(const fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int pass, hipStream_t st,
                      const TileIO<T> &io)
@@ -28,10 +28,6 @@ void launch_adj_pass(const fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, 
             if (ntp) vel_tile_adj<T, TX, TY, kAdjA, F32><<<nwg, NT, 0, st>>>(G, inj, n, tm, io);
             else vel_tile_adj<T, TX, TY, kAdjA, false><<<nwg, NT, 0, st>>>(G, inj, n, tm, io);
             break;
-        case kPassVelB:
-            if (ntp) vel_tile_adj<T, TX, TY, kAdjB, F32><<<nwg, NT, 0, st>>>(G, inj, n, tm, io);
-            else vel_tile_adj<T, TX, TY, kAdjB, false><<<nwg, NT, 0, st>>>(G, inj, n, tm, io);
-            break;
         default:
             if (ntp) stress_tile_adj<T, TX, TY, kAdjB, F32><<<nwg, NT, 0, st>>>(G, inj, tm, io);
             else stress_tile_adj<T, TX, TY, kAdjB, false><<<nwg, NT, 0, st>>>(G, inj, tm, io);
@@ -41,8 +37,8 @@ void launch_adj_pass(const fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, 
 }
 
 // Reverse sweep over the checkpointed segments: recompute each segment (storing
-// v^{n+1/2} and sigma^n per step), then run the adjoint steps backwards; finally map
-// the staggered-point gradients to the node arrays (accumulated into g_*).
+// v^{n+1/2} per step), then run the adjoint steps backwards; finally map the
+// staggered-point gradients to the node arrays (accumulated into g_*).
 template <typename T>
 int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *rec_pos, const T *residual, T *g_lam,
                  T *g_mu, T *g_rho, char *gws, const GradLayout &GL, hipStream_t st)
@@ -76,27 +72,26 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
             HIP_TRY(hipMemcpyAsync(state_chunk<T>(c, G, q), ck + q * GL.chunk, c->L.field_bytes,
                                    hipMemcpyDeviceToDevice, st));
         for (int n = n0; n < n1; ++n) {
-            char *slot = gws + GL.seg + (size_t)(n - n0) * GL.group;
+            char *slot = seg_slot(gws, GL, n - n0);
             Grid<T> Gs = G;
-            for (int f = 0; f < NFIELD; ++f) Gs.save[f] = (T *)(slot + f * GL.fstep);
+            for (int q = 0; q < 3; ++q) Gs.save[VX + q] = (T *)(slot + q * GL.fstep);
             if (c->opts.free_surface) step<T, true>(c, Gs, inj, n, 0, taps, nullptr, st, tm);
             else step<T, false>(c, Gs, inj, n, 0, taps, nullptr, st, tm);
         }
         for (int n = n1 - 1; n >= n0; --n) {
-            const char *slot = gws + GL.seg + (size_t)(n - n0) * GL.group;
+            const char *slot = seg_slot(gws, GL, n - n0);
+            set_stored_velocity(A, GL, slot, prev_velocity(gws, GL, sgi, n - n0));
             if (tiled) {
                 const AdjTiles<T> P = adj_tiles<T>(G, gws, GL, slot);
                 launch_adj_pass<T>(c, P.g[0], none, n, kPassStressA, st, P.io[0]);
                 launch_adj_pass<T>(c, P.g[1], none, n, kPassVelA, st, P.io[1]);
                 inject(n);
-                launch_adj_pass<T>(c, P.g[2], inj, n, kPassVelB, st, P.io[2]);
-                launch_adj_pass<T>(c, P.g[3], none, n, kPassStressB, st, P.io[3]);
+                launch_gb_point<T>(G, A, gws, GL, st);
+                launch_adj_pass<T>(c, P.g[2], none, n, kPassStressB, st, P.io[2]);
             } else {
-                for (int q = 0; q < 3; ++q) A.vst[q] = (const T *)(slot + q * GL.fstep);
-                for (int q = 0; q < 6; ++q) A.sst[q] = (const T *)(slot + (3 + q) * GL.fstep);
                 adj_stress_cell<T><<<grd, blk, 0, st>>>(G, A);
                 inject(n);
-                adj_vel_cell<T><<<grd, blk, 0, st>>>(G, A, inj, n);
+                adj_vel_cell<T><<<grd, blk, 0, st>>>(G, A);
             }
         }
     }
@@ -128,12 +123,31 @@ GradLayout make_grad_layout(const fd3d_ctx *c, int k)
     g.ckpt = off;
     off += (size_t)g.nseg * g.group;
     g.seg = off;
-    off += (size_t)k * g.group;
+    off += (size_t)((k + 2) / 3) * g.group;
     g.res = off;
     off += round_up((size_t)c->opts.max_receivers * 3 * (size_t)(c->nt > 0 ? c->nt : 1) * c->tsize, kAlign);
     g.misfit = off;
     off += kAlign;
     g.total = off;
+    return g;
+}
+
+// Smallest damping factor of a velocity sample: the product of the three axes' smallest
+// profile values (either half-cell position).
+static double min_velocity_damping(const fd3d_ctx *c)
+{
+    double g = 1.0;
+    size_t off = 0;
+    for (int a = 0; a < 3; ++a) {
+        double m = 1.0;
+        for (size_t i = 0; i < 2 * (size_t)c->n[a]; ++i) {
+            const double v = c->tsize == 4 ? (double)((const float *)c->prof_host.data())[off + i]
+                                           : ((const double *)c->prof_host.data())[off + i];
+            m = std::min(m, v);
+        }
+        g *= m;
+        off += 2 * (size_t)c->n[a];
+    }
     return g;
 }
 
@@ -144,6 +158,9 @@ int check_gws(const fd3d_ctx *ctx, void *gws, size_t gws_bytes, int k)
     if (coarse_on(ctx->opts)) return fail(FD3D_EINVAL, "the gradient needs the medium at the simulation nodes");
     if (ctx->nt < 1) return fail(FD3D_EINVAL, "gradient needs nt >= 1");
     if (k < 1 || k > ctx->nt) return fail(FD3D_EINVAL, "ckpt_every must be in [1, nt]");
+    // the b gradient divides the stored v^{n+1/2} by its damping factor
+    if (min_velocity_damping(ctx) < 1e-6)
+        return fail(FD3D_EINVAL, "the gradient needs damping factors of at least 1e-6 (sponge_alpha too strong)");
     if (!gws || ((uintptr_t)gws % kAlign)) return fail(FD3D_EINVAL, "gradient workspace must be 256-byte aligned");
     const size_t need = make_grad_layout(ctx, k).total;
     if (gws_bytes < need) return fail(FD3D_EWS, "gradient workspace too small: need " + std::to_string(need) + " bytes");

@@ -273,11 +273,10 @@ template <typename T, typename F> decltype(auto) with_tile(int tx, int ty, F &&f
 
 // Passes of a step.  Forward: velocity, stress.  Adjoint step (reverse order of the
 // forward step): stress-A (C gradients, X = C G_s A_s), velocity-A (A_v update),
-// velocity-B (b gradient, Y = G_v A_v / rho_eff), stress-B (A_s update).
-// The forward passes also come in a variant that stores v^{n+1/2} and sigma^n through the
-// grid's save pointers (the gradient's segment recompute).
-enum Pass { kPassVel = 0, kPassStress = 1, kPassStressA, kPassVelA, kPassVelB, kPassStressB, kPassVelSave,
-            kPassStressSave };
+// stress-B (A_s update from Y = G_v A_v / rho_eff, which the pointwise adj_gb_point forms
+// with the b gradient).  The velocity pass also comes in a variant that stores v^{n+1/2}
+// through the grid's save pointers (the gradient's segment recompute).
+enum Pass { kPassVel = 0, kPassStress = 1, kPassStressA, kPassVelA, kPassStressB, kPassVelSave };
 
 // Tile and fused sweeps address a window of at most zchunk + 8 planes (and at most the
 // grid's nz) through one buffer descriptor per field, of at most 1 GiB.
@@ -330,10 +329,10 @@ void step(fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int nrec, 
 bool fused_supported(const fd3d_ctx *c, int tx, int ty);
 
 // Gradient workspace (byte offsets): adjoint state, staggered-point gradient
-// accumulators, the tiled adjoint's intermediate fields, checkpoints every k steps, one
-// k-step segment of stored fields, and the residual buffer of fd3d_gradient.  Every group
-// of fields has the layout of the context's state (one block of interleaved rows, or
-// padded arrays): field q of a group at q * fstep.
+// accumulators, the tiled adjoint's intermediate fields, checkpoints every k steps, the
+// stored velocities of one k-step segment, and the residual buffer of fd3d_gradient.
+// Every group of fields has the layout of the context's state (one block of interleaved
+// rows, or padded arrays): field q of a group at q * fstep.
 struct GradLayout {
     size_t fstep;   // bytes from one field of a group to the next
     size_t group;   // bytes of a group of nine fields
@@ -342,7 +341,7 @@ struct GradLayout {
     size_t acc;     // 8 fields: gl, gm, g_mu_xy, g_mu_xz, g_mu_yz, g_bx, g_by, g_bz
     size_t scr;     // 9 fields: X = C G_s A_s (6, stress layout), Y = G_v A_v / rho_eff (3)
     size_t ckpt;    // nseg groups: state at the start of steps 0, k, 2k, ...
-    size_t seg;     // k groups: v^{n+1/2} (3) then sigma^n (6) per step of a segment
+    size_t seg;     // ceil(k/3) groups: v^{n+1/2} of three steps of a segment per group
     size_t res;     // residual [max_rec][3][nt]
     size_t misfit;  // one T
     size_t total;
@@ -351,6 +350,19 @@ struct GradLayout {
 
 // Gradient workspace layout for checkpoints every k steps.
 GradLayout make_grad_layout(const fd3d_ctx *c, int k);
+
+// Stored v^{n+1/2} of step m of a segment (m < k): fields 3 (m mod 3) .. +2 of group m / 3.
+inline char *seg_slot(char *gws, const GradLayout &GL, int m)
+{
+    return gws + GL.seg + (size_t)(m / 3) * GL.group + (size_t)(3 * (m % 3)) * GL.fstep;
+}
+
+// v^{n-1/2} of segment step m: the previous step's stored v^{n+1/2}, or for m = 0 the
+// velocity fields of the segment's checkpoint.
+inline char *prev_velocity(char *gws, const GradLayout &GL, int seg_index, int m)
+{
+    return m > 0 ? seg_slot(gws, GL, m - 1) : gws + GL.ckpt + (size_t)seg_index * GL.group;
+}
 
 // The q-th field-sized chunk of the current state (q < 9): field q of separate arrays, or
 // the q-th ninth of the block of interleaved rows.  Checkpoints copy a state chunk by
@@ -377,23 +389,31 @@ template <typename T> AdjGrid<T> make_adj(char *gws, const GradLayout &GL)
         A.gs[q] = acc[2 + q];
         A.gb[q] = acc[5 + q];
     }
-    for (int q = 0; q < 3; ++q) A.vst[q] = nullptr;
-    for (int q = 0; q < 6; ++q) A.sst[q] = nullptr;
+    for (int q = 0; q < 3; ++q) A.vst[q] = A.vprev[q] = nullptr;
     return A;
 }
 
-// Fields of the four tiled adjoint passes of one step whose stored v^{n+1/2}, sigma^n
-// sit in segment slot `slot`: grids (f[] re-pointed) and tile outputs.
+// The stored velocities of one adjoint step: v^{n+1/2} at `slot`, v^{n-1/2} at `prev`.
+template <typename T> void set_stored_velocity(AdjGrid<T> &A, const GradLayout &GL, const char *slot, const char *prev)
+{
+    for (int q = 0; q < 3; ++q) {
+        A.vst[q] = (const T *)(slot + q * GL.fstep);
+        A.vprev[q] = (const T *)(prev + q * GL.fstep);
+    }
+}
+
+// Fields of the three tiled adjoint passes of one step whose stored v^{n+1/2} sits in
+// segment slot `slot`: grids (f[] re-pointed) and tile outputs.
 template <typename T> struct AdjTiles {
-    Grid<T> g[4];     // stress-A, velocity-A, velocity-B, stress-B
-    TileIO<T> io[4];
+    Grid<T> g[3];     // stress-A, velocity-A, stress-B
+    TileIO<T> io[3];
 };
 
 template <typename T> AdjTiles<T> adj_tiles(const Grid<T> &G, char *gws, const GradLayout &GL, const char *slot)
 {
     auto fld = [&](size_t base, int q) { return (T *)(gws + base + q * GL.fstep); };
     AdjTiles<T> P;
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < 3; ++p) {
         P.g[p] = G;
         for (int f = 0; f < NFIELD; ++f) P.g[p].save[f] = nullptr;
         std::memset(&P.io[p], 0, sizeof P.io[p]);
@@ -401,16 +421,12 @@ template <typename T> AdjTiles<T> adj_tiles(const Grid<T> &G, char *gws, const G
     for (int q = 0; q < 3; ++q) {
         P.g[0].f[VX + q] = (T *)(slot + q * GL.fstep);  // stored v^{n+1/2}
         P.g[1].f[VX + q] = fld(GL.adj, VX + q);           // A_v
-        P.g[2].f[VX + q] = fld(GL.adj, VX + q);
-        P.g[3].f[VX + q] = fld(GL.scr, 6 + q);            // Y
-        P.io[2].acc[q] = fld(GL.acc, 5 + q);              // g_b
-        P.io[2].out[q] = fld(GL.scr, 6 + q);
+        P.g[2].f[VX + q] = fld(GL.scr, 6 + q);            // Y
     }
     for (int q = 0; q < 6; ++q) {
-        P.g[0].f[SXX + q] = fld(GL.adj, SXX + q);           // A_s
-        P.g[1].f[SXX + q] = fld(GL.scr, q);                 // X
-        P.g[2].f[SXX + q] = (T *)(slot + (3 + q) * GL.fstep);  // stored sigma^n
-        P.g[3].f[SXX + q] = fld(GL.adj, SXX + q);
+        P.g[0].f[SXX + q] = fld(GL.adj, SXX + q);  // A_s
+        P.g[1].f[SXX + q] = fld(GL.scr, q);        // X
+        P.g[2].f[SXX + q] = fld(GL.adj, SXX + q);
         P.io[0].out[q] = fld(GL.scr, q);
     }
     for (int q = 0; q < 5; ++q) P.io[0].acc[q] = fld(GL.acc, q);  // gl, gm, g_mu_xy, g_mu_xz, g_mu_yz
@@ -422,7 +438,16 @@ template <typename T> AdjTiles<T> adj_tiles(const Grid<T> &G, char *gws, const G
 template <typename T> void zero_grad_fields(char *gws, const GradLayout &GL, hipStream_t st)
 {
     fill_zero<T><<<2048, 256, 0, st>>>((T *)(gws + GL.adj), (long)((GL.ckpt - GL.adj) / sizeof(T)));
-    fill_zero<T><<<2048, 256, 0, st>>>((T *)(gws + GL.seg), (long)((size_t)GL.k * GL.group / sizeof(T)));
+    fill_zero<T><<<2048, 256, 0, st>>>((T *)(gws + GL.seg), (long)((GL.res - GL.seg) / sizeof(T)));
+}
+
+// The pointwise part of the adjoint velocity step (b gradient, Y) over a grid.
+template <typename T> void launch_gb_point(const Grid<T> &G, const AdjGrid<T> &A, char *gws, const GradLayout &GL,
+                                           hipStream_t st)
+{
+    auto fld = [&](int q) { return (T *)(gws + GL.scr + q * GL.fstep); };
+    const dim3 blk(64, 4), grd((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
+    adj_gb_point<T><<<grd, blk, 0, st>>>(G, A, fld(6), fld(7), fld(8));
 }
 
 // Validates a caller's gradient workspace for checkpoints every k steps.
