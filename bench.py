@@ -70,10 +70,9 @@ def step_bytes(kern):
 
 
 # gradient, per shot and time step: forward with checkpoints (120), segment recompute
-# storing v^{n+1/2} (132), the adjoint passes: stress-A 27 fields, velocity-A 12, the
-# pointwise buoyancy pass 19 (A_v, v^{n+1/2}, v^{n-1/2}, rho, g_b read and written, Y
-# written), stress-B 15 (292)
-GRAD_BYTES_PER_CELL_STEP = 120 + 132 + 4 * (27 + 12 + 19 + 15)
+# storing v^{n+1/2} (132), the adjoint passes: stress-A 27 fields, velocity-A 25 (X, Y,
+# v^{n+1/2}, v^{n-1/2}, rho and g_b read, Y and g_b written), stress-B 15 (268)
+GRAD_BYTES_PER_CELL_STEP = 120 + 132 + 4 * (27 + 25 + 15)
 # the design figure with eight staggered-point accumulators and no hand-over fields
 # between the adjoint passes (forward 120 + recompute 132 + adjoint 232)
 GRAD_BYTES_DESIGN = 120 + 132 + 232

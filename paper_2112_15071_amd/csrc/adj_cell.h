@@ -12,11 +12,16 @@
 // divergence stencil of the velocity pass and E the strain-rate stencil of the stress
 // pass; under the zero-halo rules D_S = -E^T, so these are the transposed passes.
 //
-// The gradient of b needs, at each velocity sample, the step's increment over b,
+// The gradient of b needs, at each velocity sample, U times the step's increment over b,
 // dt D_S sigma^n + c s (c the force source's coefficient), which the velocity pass
 // multiplied by b, added to v^{n-1/2} and damped: v^{n+1/2} = G_v (v^{n-1/2} + b (...)).
-// It is recovered pointwise from the two stored velocities, (v^{n+1/2} / G_v - v^{n-1/2})
-// rho_eff, so the segment recompute stores v^{n+1/2} only (not sigma^n).
+// With U = G_v A_v that product is A_v (v^{n+1/2} - G_v v^{n-1/2}) rho_eff, formed from
+// the two stored velocities, so the segment recompute stores v^{n+1/2} only (not sigma^n).
+//
+// The tiled adjoint (velocity-type and stress-type tile bodies) keeps, in place of A_v,
+// Y = b G_v A_v, the field its adjoint stress pass reads: its velocity pass forms A_v from
+// the Y of the step after (G_v A_v = Y rho_eff), the gradient of b and the new Y in one
+// sweep, and its residual injection adds the injected share to Y and g_b at the taps.
 #pragma once
 
 #include "common.h"
@@ -138,38 +143,14 @@ __device__ __forceinline__ T yval(const Grid<T> &G, const AdjGrid<T> &A, int c, 
 }
 
 // Contribution of step n to the gradient of b at velocity sample c of node (i,j,k):
-// U (v^{n+1/2} / G_v - v^{n-1/2}) rho_eff, the step's increment dt D_S sigma^n + c s
-// recovered from the stored velocities (see the top of this file).
+// A_v (v^{n+1/2} - G_v v^{n-1/2}) rho_eff (see the top of this file).
 template <typename T>
 __device__ __forceinline__ T gb_term(const Grid<T> &G, const AdjGrid<T> &A, int c, int i, int j, int k, long p)
 {
     const long e = c == VX ? 1 : (c == VY ? G.sy : G.sz);
     const T g = damp(G, c, i, j, k);
-    const T u = g * A.a[c][p];
-    const T inc = A.vst[c - VX][p] / g - A.vprev[c - VX][p];
-    return u * (inc * ((G.rho[p] + G.rho[p + e]) * T(0.5)));
-}
-
-// The pointwise part of the tiled adjoint velocity step at the samples of node (i,j,k):
-// the gradient of b, and Y = b U for the stress-type pass that follows (y[c]).
-template <typename T>
-__global__ void __launch_bounds__(256) adj_gb_point(Grid<T> G, AdjGrid<T> A, T *__restrict__ y0, T *__restrict__ y1,
-                                                   T *__restrict__ y2)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= G.nx || j >= G.ny) return;
-    const long p = i + G.sy * j + G.sz * k;
-    T *y[3] = {y0, y1, y2};
-    const bool act[3] = {i <= G.nx - 2, j <= G.ny - 2, k <= G.nz - 2};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        if (!act[c]) continue;
-        const long e = c == 0 ? 1 : (c == 1 ? G.sy : G.sz);
-        A.gb[c][p] += gb_term(G, A, VX + c, i, j, k, p);
-        y[c][p] = (damp(G, VX + c, i, j, k) * A.a[VX + c][p]) * buoy(G.rho[p], G.rho[p + e]);
-    }
+    const T inc = A.vst[c - VX][p] - g * A.vprev[c - VX][p];
+    return A.a[c][p] * (inc * ((G.rho[p] + G.rho[p + e]) * T(0.5)));
 }
 
 // (a12) adjoint of the velocity pass, at the samples of node (i,j,k).
@@ -253,6 +234,50 @@ __global__ void __launch_bounds__(256) inject_residual(T *__restrict__ ax, T *__
     inject_one(ax, ay, az, taps, list[q / 3], q % 3, res, nt, n);
 }
 
+// (a11) for the tiled adjoint, whose velocity pass has already formed Y and the gradient
+// of b from A_v: the injected d = w r at a tap adds G_v d b to Y and
+// d (v^{n+1/2} - G_v v^{n-1/2}) rho_eff to g_b there, its share of both.  Field pointers
+// and strides of one grid (a tap's storage index gives its node).
+template <typename T> struct TapAdjoint {
+    T *y[3], *gb[3];
+    const T *vst[3], *vprev[3];  // stored v^{n+1/2}, v^{n-1/2}
+    const T *rho;
+    const T *g[3][2];  // damping profiles (as Grid::g)
+    long sy, sz;
+};
+
+template <typename T>
+__device__ __forceinline__ void inject_one_tiled(const TapAdjoint<T> &A, const RecTap<T> *__restrict__ taps, int r,
+                                                 int c, const T *__restrict__ res, int nt, int n)
+{
+    const RecTap<T> &t = taps[r * 3 + c];
+    const T v = res[((long)r * 3 + c) * nt + n];
+    const long e = c == 0 ? 1 : (c == 1 ? A.sy : A.sz);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const long q = t.idx[m];
+        if (q < 0) continue;
+        const T d = t.w[m] * v;
+        const int k = (int)(q / A.sz);
+        const long rem = q - (long)k * A.sz;
+        const int j = (int)(rem / A.sy), i = (int)(rem - (long)j * A.sy);
+        const T g = A.g[0][c == 0][i] * A.g[1][c == 1][j] * A.g[2][c == 2][k];
+        const T ra = A.rho[q], rb = A.rho[q + e];
+        A.y[c][q] += (g * d) * buoy(ra, rb);
+        A.gb[c][q] += d * ((A.vst[c][q] - g * A.vprev[c][q]) * ((ra + rb) * T(0.5)));
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) inject_residual_tiled(TapAdjoint<T> A, const RecTap<T> *__restrict__ taps,
+                                                             const int *__restrict__ list, int count,
+                                                             const T *__restrict__ res, int nt, int n)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 3 * count) return;
+    inject_one_tiled(A, taps, list[q / 3], q % 3, res, nt, n);
+}
+
 // (a13) chain rule from the staggered-point gradients to the node arrays (gathers, no
 // atomics): g_lam += gl; g_mu += gm + 1/4 sum of the shear gradients whose mean uses the
 // node; g_rho += sum over the adjacent velocity samples of -b^2/2 g_b.
@@ -291,8 +316,9 @@ __global__ void __launch_bounds__(256) grad_finalize(Grid<T> G, AdjGrid<T> A, T 
     g_rho[po] += gr;
 }
 
-// Adjoint of the initial velocity: the pending damping factor of A_v applied into out (a
-// node array, x fastest and unpadded).
+// Adjoint of the initial velocity, G_v A_v, into out (a node array, x fastest and
+// unpadded): from A_v (the one-thread-per-cell adjoint), or from Y (the tiled adjoint),
+// below.
 template <typename T>
 __global__ void __launch_bounds__(256) scale_velocity(Grid<T> G, const T *__restrict__ a, int c, T *__restrict__ out)
 {
@@ -303,6 +329,23 @@ __global__ void __launch_bounds__(256) scale_velocity(Grid<T> G, const T *__rest
     out[i + (long)G.nx * (j + (long)G.ny * k)] = damp(G, c, i, j, k) * a[i + G.sy * j + G.sz * k];
 }
 
+// G_v A_v = Y rho_eff at the active samples of component c (zero elsewhere).
+template <typename T>
+__global__ void __launch_bounds__(256) velocity_from_y(Grid<T> G, const T *__restrict__ y, int c, T *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= G.nx || j >= G.ny) return;
+    const bool act = c == VX ? i <= G.nx - 2 : (c == VY ? j <= G.ny - 2 : k <= G.nz - 2);
+    T v = T(0);
+    if (act) {
+        const long p = i + G.sy * j + G.sz * k, e = c == VX ? 1 : (c == VY ? G.sy : G.sz);
+        v = y[p] * ((G.rho[p] + G.rho[p + e]) * T(0.5));
+    }
+    out[i + (long)G.nx * (j + (long)G.ny * k)] = v;
+}
+
 // ---------------------------------------------------------------------------------
 // Residual injection for many shots per launch.  Colour c's receivers of every shot form
 // one flat work list (shot-major, three components per receiver); shots never share
@@ -310,7 +353,7 @@ __global__ void __launch_bounds__(256) scale_velocity(Grid<T> G, const T *__rest
 constexpr int kMaxBatchColors = 4;
 
 template <typename T> struct ShotInject {
-    T *a[3];  // A_v
+    TapAdjoint<T> t;  // the shot's Y, g_b, stored velocities of the step's segment slot, model
     const RecTap<T> *taps;
     const int *colors;
     const T *res;
@@ -332,7 +375,7 @@ __global__ void __launch_bounds__(256) inject_residual_multi(const ShotInject<T>
     const ShotInject<T> &sh = d[s];
     const int l = q - sh.rbase[color];
     const int r = sh.colors[sh.coff[color] + l / 3];
-    inject_one(sh.a[0], sh.a[1], sh.a[2], sh.taps, r, l % 3, sh.res, nt, n);
+    inject_one_tiled(sh.t, sh.taps, r, l % 3, sh.res, nt, n);
 }
 
 // Copies of many equally long arrays (checkpoint save / restore of every shot).

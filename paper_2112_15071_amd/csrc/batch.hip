@@ -396,12 +396,12 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
 // ---- batched gradient ----------------------------------------------------------
 // Batch workspace of fd3d_batch_gradient: descriptor arrays (nshot entries each) of the
 // forward pass, of the segment recompute per segment slot m (store pointers of slot m),
-// of the adjoint passes (stress-A per slot m, which reads the velocity stored in slot m;
-// velocity-A and stress-B once), of the residual injection, and per checkpoint the save
-// and restore copy lists.
+// of the adjoint passes (stress-A and velocity-A per slot m, which read the velocities
+// stored for segment step m; stress-B once), of the residual injection per slot m, and per
+// checkpoint the save and restore copy lists (the restore also fills the prev group).
 struct BatchGradLayout {
-    size_t fwd0, fwd_slot, sa_slot, va, sb, inj, save_copy, rest_copy, total;
-    size_t fwd_bytes, inj_bytes, copy_bytes;
+    size_t fwd0, fwd_slot, sa_slot, va_slot, sb, inj_slot, save_copy, rest_copy, total;
+    size_t fwd_bytes, inj_bytes, copy_bytes, rest_bytes;
     int k, nseg;
 };
 
@@ -413,6 +413,7 @@ template <typename T> BatchGradLayout make_batch_grad_layout(const fd3d_batch *b
     L.fwd_bytes = round_up((size_t)b->nshot * sizeof(ShotFwd<T>), kAlign);
     L.inj_bytes = round_up((size_t)b->nshot * sizeof(ShotInject<T>), kAlign);
     L.copy_bytes = round_up((size_t)b->nshot * 9 * sizeof(CopyDesc<T>), kAlign);
+    L.rest_bytes = round_up((size_t)b->nshot * 10 * sizeof(CopyDesc<T>), kAlign);
     size_t off = 0;
     L.fwd0 = off;
     off += L.fwd_bytes;
@@ -420,16 +421,16 @@ template <typename T> BatchGradLayout make_batch_grad_layout(const fd3d_batch *b
     off += (size_t)k * L.fwd_bytes;
     L.sa_slot = off;
     off += (size_t)k * L.fwd_bytes;
-    L.va = off;
-    off += L.fwd_bytes;
+    L.va_slot = off;
+    off += (size_t)k * L.fwd_bytes;
     L.sb = off;
     off += L.fwd_bytes;
-    L.inj = off;
-    off += L.inj_bytes;
+    L.inj_slot = off;
+    off += (size_t)k * L.inj_bytes;
     L.save_copy = off;
     off += (size_t)L.nseg * L.copy_bytes;
     L.rest_copy = off;
-    off += (size_t)L.nseg * L.copy_bytes;
+    off += (size_t)L.nseg * L.rest_bytes;
     L.total = off;
     return L;
 }
@@ -484,8 +485,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         rr[s].base = recs;
         recs += 3 * nr;
         ag[s] = make_adj<T>((char *)gws[s], GL[s]);
-        ShotInject<T> &a = ij[s];
-        for (int q = 0; q < 3; ++q) a.a[q] = ag[s].a[VX + q];
+        ShotInject<T> &a = ij[s];  // .t per segment slot below
         a.taps = rr[s].taps;
         a.colors = (const int *)(c->ws + c->L.colors);
         a.res = (const T *)((char *)gws[s] + GL[s].res);
@@ -513,38 +513,41 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         for (int f = 0; f < NFIELD; ++f) d.src.i0[f] = d.src.j0[f] = d.src.k0[f] = -(1 << 28);
         return d;
     };
-    std::vector<ShotFwd<T>> va(S), sb(S);
+    std::vector<ShotFwd<T>> sb(S);
     for (int m = 0; m < k; ++m) {
-        std::vector<ShotFwd<T>> f2 = fw, sa(S);
+        std::vector<ShotFwd<T>> f2 = fw, sa(S), va(S);
+        std::vector<ShotInject<T>> ijm = ij;
         for (int s = 0; s < S; ++s) {
-            char *slot = seg_slot((char *)gws[s], GL[s], m);
+            char *w = (char *)gws[s];
+            char *slot = seg_slot(w, GL[s], m);
             for (int q = 0; q < 3; ++q) f2[s].G.save[VX + q] = (T *)(slot + q * GL[s].fstep);
-            const AdjTiles<T> P = adj_tiles<T>(fw[s].G, (char *)gws[s], GL[s], slot);
+            const AdjTiles<T> P = adj_tiles<T>(fw[s].G, w, GL[s], m);
             sa[s] = adj_desc(s, P, 0);
-            if (m == 0) {
-                va[s] = adj_desc(s, P, 1);
-                sb[s] = adj_desc(s, P, 2);
-            }
+            va[s] = adj_desc(s, P, 1);
+            if (m == 0) sb[s] = adj_desc(s, P, 2);
+            ijm[s].t = tap_adjoint<T>(fw[s].G, w, GL[s], m);
         }
         std::memcpy(h + BL.fwd_slot + m * BL.fwd_bytes, f2.data(), fbytes);
         std::memcpy(h + BL.sa_slot + m * BL.fwd_bytes, sa.data(), fbytes);
+        std::memcpy(h + BL.va_slot + m * BL.fwd_bytes, va.data(), fbytes);
+        std::memcpy(h + BL.inj_slot + m * BL.inj_bytes, ijm.data(), S * sizeof(ShotInject<T>));
     }
-    std::memcpy(h + BL.va, va.data(), fbytes);
     std::memcpy(h + BL.sb, sb.data(), fbytes);
-    std::memcpy(h + BL.inj, ij.data(), S * sizeof(ShotInject<T>));
     for (int cidx = 0; cidx < BL.nseg; ++cidx) {
-        std::vector<CopyDesc<T>> sv(S * 9), rs(S * 9);
+        std::vector<CopyDesc<T>> sv(S * 9), rs(S * 10);
         for (int s = 0; s < S; ++s) {
             char *ck = (char *)gws[s] + GL[s].ckpt + (size_t)cidx * GL[s].group;
             const long n = (long)(b->ctx[s]->L.field_bytes / sizeof(T));
             for (int q = 0; q < NFIELD; ++q) {
                 T *live = (T *)state_chunk<T>(b->ctx[s], fw[s].G, q), *kept = (T *)(ck + q * GL[s].chunk);
                 sv[s * 9 + q] = CopyDesc<T>{live, kept, n};
-                rs[s * 9 + q] = CopyDesc<T>{kept, live, n};
+                rs[s * 10 + q] = CopyDesc<T>{kept, live, n};
             }
+            rs[s * 10 + 9] = CopyDesc<T>{(const T *)ck, (T *)((char *)gws[s] + GL[s].prev),
+                                         (long)(prev_copy_bytes(b->ctx[s], GL[s]) / sizeof(T))};
         }
         std::memcpy(h + BL.save_copy + cidx * BL.copy_bytes, sv.data(), sv.size() * sizeof(CopyDesc<T>));
-        std::memcpy(h + BL.rest_copy + cidx * BL.copy_bytes, rs.data(), rs.size() * sizeof(CopyDesc<T>));
+        std::memcpy(h + BL.rest_copy + cidx * BL.rest_bytes, rs.data(), rs.size() * sizeof(CopyDesc<T>));
     }
     b->rec_host.assign((const unsigned char *)rr.data(), (const unsigned char *)(rr.data() + S));
     HIP_TRY(hipMemcpyAsync(bws, h, BL.total, hipMemcpyHostToDevice, st));
@@ -564,8 +567,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     // forward with checkpoints
     auto desc = [&](size_t off) { return (const ShotFwd<T> *)(bws + off); };
     const ShotRec<T> *rdesc = (const ShotRec<T> *)(b->ws + b->off_rec);
-    const ShotInject<T> *idesc = (const ShotInject<T> *)(bws + BL.inj);
-    const dim3 cgrid(256, 9 * S);
+    const dim3 cgrid(256, 9 * S), rgrid(256, 10 * S);
     if (!(flags & FD3D_KEEP_STATE))
         for (fd3d_ctx *c : b->ctx) zero_fields<T>(c, st);
     auto pass = [&](const ShotFwd<T> *d, int n, int p, const ShotRec<T> *r = nullptr) {
@@ -591,23 +593,20 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     // reverse sweep over the segments
     for (int sg = BL.nseg - 1; sg >= 0; --sg) {
         const int n0 = sg * k, n1 = std::min(n0 + k, b->nt);
-        copy_multi<T><<<cgrid, 256, 0, st>>>((const CopyDesc<T> *)(bws + BL.rest_copy + sg * BL.copy_bytes));
+        copy_multi<T><<<rgrid, 256, 0, st>>>((const CopyDesc<T> *)(bws + BL.rest_copy + sg * BL.rest_bytes));
         for (int n = n0; n < n1; ++n) {
             const ShotFwd<T> *d = desc(BL.fwd_slot + (n - n0) * BL.fwd_bytes);
             pass(d, n, kPassVelSave);
             pass(d, n, kPassStress);
         }
         for (int n = n1 - 1; n >= n0; --n) {
-            pass(desc(BL.sa_slot + (n - n0) * BL.fwd_bytes), n, kPassStressA);
-            pass(desc(BL.va), n, kPassVelA);
+            const int m = n - n0;
+            pass(desc(BL.sa_slot + m * BL.fwd_bytes), n, kPassStressA);
+            pass(desc(BL.va_slot + m * BL.fwd_bytes), n, kPassVelA);
+            const ShotInject<T> *idesc = (const ShotInject<T> *)(bws + BL.inj_slot + m * BL.inj_bytes);
             for (int q = 0; q < ncol; ++q)
                 if (cbase[q] > 0)
                     inject_residual_multi<T><<<(cbase[q] + 255) / 256, 256, 0, st>>>(idesc, S, q, cbase[q], b->nt, n);
-            for (int s = 0; s < S; ++s) {  // b gradient and Y, shot by shot (pointwise)
-                char *w = (char *)gws[s];
-                set_stored_velocity(ag[s], GL[s], seg_slot(w, GL[s], n - n0), prev_velocity(w, GL[s], sg, n - n0));
-                launch_gb_point<T>(fw[s].G, ag[s], w, GL[s], st);
-            }
             pass(desc(BL.sb), n, kPassStressB);
         }
     }
@@ -619,6 +618,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         c->grad_ws = (const char *)gws[s];
         c->grad_k = k;
         c->grad_ready = 1;
+        c->grad_y = 1;
     }
     HIP_TRY(hipGetLastError());
     return FD3D_OK;

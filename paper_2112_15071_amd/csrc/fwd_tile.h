@@ -218,12 +218,14 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
 
 // What a tile body computes.  kFwd: the forward pass; kFwdSave (velocity-type body): the
 // forward velocity pass that also stores v^{n+1/2} through the grid's save pointers (the
-// gradient's segment recompute).  For the velocity-type body, kAdjA:
-// A_v <- G_v A_v - dt D_S(X) (X = C G_s A_s, precomputed).  For the stress-type body,
-// kAdjA: gradients of C from E(v^{n+1/2}) and T = G_s A_s, X = C T; kAdjB:
-// A_s <- G_s A_s - dt E(Y) (Y = G_v A_v / rho_eff, formed pointwise with the buoyancy
-// gradient by adj_gb_point).  The adjoint modes read and write the arrays named by the
-// grid (f[] pointing at the adjoint, stored or scratch fields) and by TileIO.  The Born
+// gradient's segment recompute).  For the velocity-type body, kAdjA: the adjoint velocity
+// update A_v = U' - dt D_S(X) (X = C G_s A_s, precomputed; U' = Y' rho_eff, the damped
+// adjoint velocity of the step after, held as Y'), then at the own sample the buoyancy
+// gradient g_b += A_v (v^{n+1/2} - G_v v^{n-1/2}) rho_eff and Y = b G_v A_v, written over
+// Y' (A_v itself is not stored).  For the stress-type body, kAdjA: gradients of C from
+// E(v^{n+1/2}) and T = G_s A_s, X = C T; kAdjB: A_s <- G_s A_s - dt E(Y).  The adjoint
+// modes read and write the arrays named by the grid (f[] pointing at the adjoint, stored
+// or scratch fields) and by TileIO.  The Born
 // (tangent-linear) modes use the derivatives the background's own passes compute: kBornV
 // is the background's forward velocity update plus dt db (D_S sigma) + db c s added to
 // the perturbation's velocity in io.out[0..2] (db = -b^2 drho_eff, drho in io.acc[0]);
@@ -232,12 +234,15 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
 // no source).
 enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3, kBornV = 4, kBornS = 5 };
 
-// Sweep direction of each pass (true: upward, decreasing k), chosen so that every pass
-// starts where the pass before it ended and finds those planes still in the last-level
-// cache: forward velocity down, stress up; adjoint stress-A down, velocity-A up, then the
-// pointwise buoyancy pass in memory order (down), stress-B up.  A pass that sweeps up also
-// takes its tiles in reverse order, so that when the tiles run in several rounds its first
-// round covers the last round of the pass before.
+// Sweep direction of each pass (true: upward, decreasing k), chosen so that a pass starts
+// where the pass before it ended and finds those planes still in the last-level cache:
+// forward velocity down, stress up; adjoint stress-A down, velocity-A up, stress-B up.
+// With three adjoint passes per step one hand-over starts cold: stress-B starts at the
+// bottom, away from where velocity-A ended, and ends at the top where the next step's
+// stress-A begins (stress-B writes the six adjoint stresses that stress-A reads next;
+// velocity-A hands stress-B only Y).  A pass that sweeps up also takes its tiles in
+// reverse order, so that when the tiles run in several rounds its first round covers the
+// last round of the pass before.
 template <int MODE> constexpr bool vel_sweeps_up() { return MODE == kAdjA; }
 template <int MODE> constexpr bool stress_sweeps_up() { return MODE == kFwd || MODE == kAdjB || MODE == kBornS; }
 
@@ -259,8 +264,10 @@ __device__ __forceinline__ int tile_of(int b, int nwg, bool reverse)
 
 template <typename T> struct TileIO {
     T *out[6];  // X (stress-A), or the Born perturbation's velocity (3) or stress (6)
-    T *acc[5];  // stress-A's gradient accumulators (gl, gm, g_mu_xy, g_mu_xz, g_mu_yz), or the
-                // Born model perturbation (drho; dlam, dmu)
+    T *acc[5];  // gradient accumulators: stress-A's (gl, gm, g_mu_xy, g_mu_xz, g_mu_yz),
+                // velocity-A's (g_bx, g_by, g_bz); or the Born model perturbation (drho;
+                // dlam, dmu)
+    const T *vst[3], *vprev[3];  // velocity-A: stored v^{n+1/2}, v^{n-1/2}
 };
 
 // Source coefficients of NC consecutive components starting at C0, staged in LDS when a
@@ -338,7 +345,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     stage_coef<T, VX, 3>(s_coef, src, srcv, tid);
     auto cf = [&](int c, int t) -> T { return t >= 0 ? s_coef[(c - VX) * 8 + (t & 7)] : T(0); };
     constexpr bool fwd = MODE == kFwd || MODE == kFwdSave || MODE == kBornV;
-    constexpr bool use_rho = MODE != kAdjA && !CM;
+    constexpr bool adj = MODE == kAdjA;
+    constexpr bool use_rho = !CM;
     constexpr bool up = vel_sweeps_up<MODE>();
     static_assert(!(up && FS), "upward velocity sweeps have no free-surface images");
     const int kfirst = up ? k1 - 1 : k0;
@@ -389,6 +397,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     // plane registers, loaded one plane ahead
     struct Plane {
         T cxx, cyy, cxy, vx, vy, vz, xx, xy, xz, yy, yz, r, dr, dvx, dvy, dvz;
+        T s[3], p[3], gb[3];  // velocity-A: stored v^{n+1/2}, v^{n-1/2}, buoyancy gradients
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const unsigned pk = wplane(w, kk, ok), pr = wplane(w, kk, ok && use_rho), o = oc + pk;
@@ -398,6 +407,14 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             P.dvx = ld<T>(wfield(io.out[0], w), o);
             P.dvy = ld<T>(wfield(io.out[1], w), o);
             P.dvz = ld<T>(wfield(io.out[2], w), o);
+        }
+        if constexpr (adj) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                P.s[c] = ldm<NTP, T>(wfield(io.vst[c], w), o);
+                P.p[c] = ldm<NTP, T>(wfield(io.vprev[c], w), o);
+                P.gb[c] = ld<T>(wfield(io.acc[c], w), o);
+            }
         }
         P.cxx = ld<T>(bxx, o);
         P.cyy = ld<T>(byy, o);
@@ -442,6 +459,13 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         }
         const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
         const T bvx0 = P.dvx, bvy0 = P.dvy, bvz0 = P.dvz;  // the perturbation's velocity (kBornV)
+        T st0[3], pv0[3], gb0[3];  // velocity-A's own-sample inputs of this plane
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            st0[c] = P.s[c];
+            pv0[c] = P.p[c];
+            gb0[c] = P.gb[c];
+        }
         // buoyancy at the three velocity samples: node means (Sec. 2.2.1), or the coarse
         // medium sampled at each sample's own position (its loads issued before the next
         // plane's, so that waiting for them leaves the prefetch in flight)
@@ -481,6 +505,14 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         const unsigned pw = wplane(w, k, true);
         const rsrc_t ovx = wfield(G.f[VX], w), ovy = wfield(G.f[VY], w), ovz = wfield(G.f[VZ], w);
         const rsrc_t bvx = wfield(io.out[0], w), bvy = wfield(io.out[1], w), bvz = wfield(io.out[2], w);
+        // velocity-A at component c's sample: y0 = Y' there, ra, rb the two densities of its
+        // mean, g its damping factor, d the divergence of X; stores Y and g_b (at so)
+        auto adj_v = [&](int c, rsrc_t oy, unsigned so, T y0, T ra, T rb, T g, T d) {
+            const T re = (ra + rb) * T(0.5);
+            const T a = y0 * re - dt * d;
+            st(oy, so, (g * a) * buoy(ra, rb));
+            st(wfield(io.acc[c], w), so, gb0[c] + a * ((st0[c] - g * pv0[c]) * re));
+        };
         {
             const int o = own_c3 + tx + 1;
             const int ox = (ty + 2) * W3 + tx + 2;
@@ -502,7 +534,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 if (srcv) add += db * cf(VX, tap_of(src, VX, i, j, k)) * s;
                 st(bvx, st_vx + pw, bvx0 + add);
             }
-            if constexpr (MODE == kAdjA) st(ovx, st_vx + pw, (gxh * gyi * gz_i) * vx0 - dt * d);
+            if constexpr (adj) adj_v(0, ovx, st_vx + pw, vx0, r0, Lr[ty * WR + tx + 1], gxh * gyi * gz_i, d);
         }
         {
             const int ox = (ty + 2) * W3 + tx + 2;
@@ -525,7 +557,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 if (srcv) add += db * cf(VY, tap_of(src, VY, i, j, k)) * s;
                 st(bvy, st_vy + pw, bvy0 + add);
             }
-            if constexpr (MODE == kAdjA) st(ovy, st_vy + pw, (gxi * gyh * gz_i) * vy0 - dt * d);
+            if constexpr (adj) adj_v(1, ovy, st_vy + pw, vy0, r0, Lr[(ty + 1) * WR + tx], gxi * gyh * gz_i, d);
         }
         {
             const int o = own_c3 + tx + 2;
@@ -549,7 +581,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 if (srcv) add += db * cf(VZ, tap_of(src, VZ, i, j, k)) * s;
                 st(bvz, st_vz + pw, bvz0 + add);
             }
-            if constexpr (MODE == kAdjA) st(ovz, st_vz + pw, (gxi * gyi * gz_h) * vz0 - dt * d);
+            if constexpr (adj) adj_v(2, ovz, st_vz + pw, vz0, r0, r1, gxi * gyi * gz_h, d);
         }
         if constexpr (up) {
             qxz[3] = qxz[2]; qxz[2] = qxz[1]; qxz[1] = qxz[0]; qxz[0] = nxz;

@@ -8,7 +8,7 @@ using namespace fd3d;
 namespace {
 
 // One adjoint pass of a tiled step (stress-A, velocity-A, stress-B) on the context's tile
-// shape and cache policy.
+// shape and cache policy (the streaming policy also covers velocity-A's stored velocities).
 template <typename T>
 void launch_adj_pass(const fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int pass, hipStream_t st,
                      const TileIO<T> &io)
@@ -57,20 +57,28 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
     Inject<T> none;
     std::memset(&none, 0, sizeof none);
     for (int f = 0; f < NFIELD; ++f) none.i0[f] = none.j0[f] = none.k0[f] = -(1 << 28);
-    auto inject = [&](int n) {
+    // residual injection per tap-disjoint colour: into A_v (cell adjoint), or into Y and g_b
+    // (tiled adjoint, segment step m)
+    auto inject = [&](int n, int m) {
+        const TapAdjoint<T> ta = tiled ? tap_adjoint<T>(G, gws, GL, m) : TapAdjoint<T>{};
         for (size_t col = 0; col + 1 < c->color_off.size(); ++col) {
             const int cnt = c->color_off[col + 1] - c->color_off[col];
-            inject_residual<T><<<(3 * cnt + 255) / 256, 256, 0, st>>>(A.a[VX], A.a[VY], A.a[VZ], taps,
-                                                                     colors + c->color_off[col], cnt, residual,
-                                                                     c->nt, n);
+            const int *list = colors + c->color_off[col];
+            if (tiled)
+                inject_residual_tiled<T><<<(3 * cnt + 255) / 256, 256, 0, st>>>(ta, taps, list, cnt, residual, c->nt, n);
+            else
+                inject_residual<T><<<(3 * cnt + 255) / 256, 256, 0, st>>>(A.a[VX], A.a[VY], A.a[VZ], taps, list, cnt,
+                                                                         residual, c->nt, n);
         }
     };
+    c->grad_y = tiled;
     for (int sgi = GL.nseg - 1; sgi >= 0; --sgi) {
         const int n0 = sgi * GL.k, n1 = std::min(n0 + GL.k, c->nt);
         const char *ck = gws + GL.ckpt + (size_t)sgi * GL.group;
         for (int q = 0; q < NFIELD; ++q)
             HIP_TRY(hipMemcpyAsync(state_chunk<T>(c, G, q), ck + q * GL.chunk, c->L.field_bytes,
                                    hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(gws + GL.prev, ck, prev_copy_bytes(c, GL), hipMemcpyDeviceToDevice, st));
         for (int n = n0; n < n1; ++n) {
             char *slot = seg_slot(gws, GL, n - n0);
             Grid<T> Gs = G;
@@ -79,18 +87,17 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
             else step<T, false>(c, Gs, inj, n, 0, taps, nullptr, st, tm);
         }
         for (int n = n1 - 1; n >= n0; --n) {
-            const char *slot = seg_slot(gws, GL, n - n0);
-            set_stored_velocity(A, GL, slot, prev_velocity(gws, GL, sgi, n - n0));
+            const int m = n - n0;
             if (tiled) {
-                const AdjTiles<T> P = adj_tiles<T>(G, gws, GL, slot);
+                const AdjTiles<T> P = adj_tiles<T>(G, gws, GL, m);
                 launch_adj_pass<T>(c, P.g[0], none, n, kPassStressA, st, P.io[0]);
                 launch_adj_pass<T>(c, P.g[1], none, n, kPassVelA, st, P.io[1]);
-                inject(n);
-                launch_gb_point<T>(G, A, gws, GL, st);
+                inject(n, m);
                 launch_adj_pass<T>(c, P.g[2], none, n, kPassStressB, st, P.io[2]);
             } else {
+                set_stored_velocity(A, gws, GL, m);
                 adj_stress_cell<T><<<grd, blk, 0, st>>>(G, A);
-                inject(n);
+                inject(n, m);
                 adj_vel_cell<T><<<grd, blk, 0, st>>>(G, A);
             }
         }
@@ -124,30 +131,13 @@ GradLayout make_grad_layout(const fd3d_ctx *c, int k)
     off += (size_t)g.nseg * g.group;
     g.seg = off;
     off += (size_t)((k + 2) / 3) * g.group;
+    g.prev = off;
+    off += g.group;
     g.res = off;
     off += round_up((size_t)c->opts.max_receivers * 3 * (size_t)(c->nt > 0 ? c->nt : 1) * c->tsize, kAlign);
     g.misfit = off;
     off += kAlign;
     g.total = off;
-    return g;
-}
-
-// Smallest damping factor of a velocity sample: the product of the three axes' smallest
-// profile values (either half-cell position).
-static double min_velocity_damping(const fd3d_ctx *c)
-{
-    double g = 1.0;
-    size_t off = 0;
-    for (int a = 0; a < 3; ++a) {
-        double m = 1.0;
-        for (size_t i = 0; i < 2 * (size_t)c->n[a]; ++i) {
-            const double v = c->tsize == 4 ? (double)((const float *)c->prof_host.data())[off + i]
-                                           : ((const double *)c->prof_host.data())[off + i];
-            m = std::min(m, v);
-        }
-        g *= m;
-        off += 2 * (size_t)c->n[a];
-    }
     return g;
 }
 
@@ -158,9 +148,6 @@ int check_gws(const fd3d_ctx *ctx, void *gws, size_t gws_bytes, int k)
     if (coarse_on(ctx->opts)) return fail(FD3D_EINVAL, "the gradient needs the medium at the simulation nodes");
     if (ctx->nt < 1) return fail(FD3D_EINVAL, "gradient needs nt >= 1");
     if (k < 1 || k > ctx->nt) return fail(FD3D_EINVAL, "ckpt_every must be in [1, nt]");
-    // the b gradient divides the stored v^{n+1/2} by its damping factor
-    if (min_velocity_damping(ctx) < 1e-6)
-        return fail(FD3D_EINVAL, "the gradient needs damping factors of at least 1e-6 (sponge_alpha too strong)");
     if (!gws || ((uintptr_t)gws % kAlign)) return fail(FD3D_EINVAL, "gradient workspace must be 256-byte aligned");
     const size_t need = make_grad_layout(ctx, k).total;
     if (gws_bytes < need) return fail(FD3D_EWS, "gradient workspace too small: need " + std::to_string(need) + " bytes");
@@ -264,7 +251,13 @@ int fd3d_get_adjoint_state(fd3d_ctx *ctx, const void *gws, void *const fields[9]
     const dim3 blk(64, 4, 1), grd((ctx->n[0] + 63) / 64, (ctx->n[1] + 3) / 4, ctx->n[2]);
     for (int f = 0; f < NFIELD; ++f) {
         const char *a = (const char *)gws + GL.adj + f * GL.fstep;
-        if (f <= VZ) {
+        if (f <= VZ && ctx->grad_y) {  // tiled adjoint: from Y (intermediate fields 6-8)
+            const char *y = (const char *)gws + GL.scr + (6 + f) * GL.fstep;
+            if (ctx->tsize == 8)
+                velocity_from_y<double><<<grd, blk, 0, st>>>(make_grid<double>(ctx), (const double *)y, f, (double *)fields[f]);
+            else
+                velocity_from_y<float><<<grd, blk, 0, st>>>(make_grid<float>(ctx), (const float *)y, f, (float *)fields[f]);
+        } else if (f <= VZ) {
             if (ctx->tsize == 8)
                 scale_velocity<double><<<grd, blk, 0, st>>>(make_grid<double>(ctx), (const double *)a, f, (double *)fields[f]);
             else

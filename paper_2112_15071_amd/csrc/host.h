@@ -131,6 +131,7 @@ struct fd3d_ctx {
     const char *grad_ws;
     int grad_k;
     int grad_ready;
+    int grad_y;  // the last adjoint was the tiled one: the adjoint velocity is held as Y
 };
 
 namespace fd3d {
@@ -272,10 +273,10 @@ template <typename T, typename F> decltype(auto) with_tile(int tx, int ty, F &&f
 }
 
 // Passes of a step.  Forward: velocity, stress.  Adjoint step (reverse order of the
-// forward step): stress-A (C gradients, X = C G_s A_s), velocity-A (A_v update),
-// stress-B (A_s update from Y = G_v A_v / rho_eff, which the pointwise adj_gb_point forms
-// with the b gradient).  The velocity pass also comes in a variant that stores v^{n+1/2}
-// through the grid's save pointers (the gradient's segment recompute).
+// forward step): stress-A (C gradients, X = C G_s A_s), velocity-A (A_v update, b
+// gradient, Y = G_v A_v / rho_eff), stress-B (A_s update from Y).  The velocity pass also
+// comes in a variant that stores v^{n+1/2} through the grid's save pointers (the
+// gradient's segment recompute).
 enum Pass { kPassVel = 0, kPassStress = 1, kPassStressA, kPassVelA, kPassStressB, kPassVelSave };
 
 // Tile and fused sweeps address a window of at most zchunk + 8 planes (and at most the
@@ -342,6 +343,7 @@ struct GradLayout {
     size_t scr;     // 9 fields: X = C G_s A_s (6, stress layout), Y = G_v A_v / rho_eff (3)
     size_t ckpt;    // nseg groups: state at the start of steps 0, k, 2k, ...
     size_t seg;     // ceil(k/3) groups: v^{n+1/2} of three steps of a segment per group
+    size_t prev;    // one group: a copy of the segment's checkpoint (its v^{n-1/2} for the first step)
     size_t res;     // residual [max_rec][3][nt]
     size_t misfit;  // one T
     size_t total;
@@ -357,11 +359,18 @@ inline char *seg_slot(char *gws, const GradLayout &GL, int m)
     return gws + GL.seg + (size_t)(m / 3) * GL.group + (size_t)(3 * (m % 3)) * GL.fstep;
 }
 
-// v^{n-1/2} of segment step m: the previous step's stored v^{n+1/2}, or for m = 0 the
-// velocity fields of the segment's checkpoint.
-inline char *prev_velocity(char *gws, const GradLayout &GL, int seg_index, int m)
+// Bytes of a checkpoint group copied to the segment's prev group: the velocity fields (the
+// first three separate arrays), or the whole block of interleaved rows.
+inline size_t prev_copy_bytes(const fd3d_ctx *c, const GradLayout &GL)
 {
-    return m > 0 ? seg_slot(gws, GL, m - 1) : gws + GL.ckpt + (size_t)seg_index * GL.group;
+    return c->L.rows ? GL.group : 3 * GL.fstep;
+}
+
+// v^{n-1/2} of segment step m: the previous step's stored v^{n+1/2}, or for m = 0 the
+// velocity fields of the copy of the segment's checkpoint.
+inline char *prev_velocity(char *gws, const GradLayout &GL, int m)
+{
+    return m > 0 ? seg_slot(gws, GL, m - 1) : gws + GL.prev;
 }
 
 // The q-th field-sized chunk of the current state (q < 9): field q of separate arrays, or
@@ -393,25 +402,28 @@ template <typename T> AdjGrid<T> make_adj(char *gws, const GradLayout &GL)
     return A;
 }
 
-// The stored velocities of one adjoint step: v^{n+1/2} at `slot`, v^{n-1/2} at `prev`.
-template <typename T> void set_stored_velocity(AdjGrid<T> &A, const GradLayout &GL, const char *slot, const char *prev)
+// The stored velocities of segment step m for the one-thread-per-cell adjoint.
+template <typename T> void set_stored_velocity(AdjGrid<T> &A, char *gws, const GradLayout &GL, int m)
 {
+    const char *slot = seg_slot(gws, GL, m), *prev = prev_velocity(gws, GL, m);
     for (int q = 0; q < 3; ++q) {
         A.vst[q] = (const T *)(slot + q * GL.fstep);
         A.vprev[q] = (const T *)(prev + q * GL.fstep);
     }
 }
 
-// Fields of the three tiled adjoint passes of one step whose stored v^{n+1/2} sits in
-// segment slot `slot`: grids (f[] re-pointed) and tile outputs.
+// Fields of the three tiled adjoint passes of segment step m: grids (f[] re-pointed) and
+// tile outputs.  The tiled adjoint holds Y = G_v A_v / rho_eff (intermediate fields 6-8)
+// in place of A_v.
 template <typename T> struct AdjTiles {
     Grid<T> g[3];     // stress-A, velocity-A, stress-B
     TileIO<T> io[3];
 };
 
-template <typename T> AdjTiles<T> adj_tiles(const Grid<T> &G, char *gws, const GradLayout &GL, const char *slot)
+template <typename T> AdjTiles<T> adj_tiles(const Grid<T> &G, char *gws, const GradLayout &GL, int m)
 {
     auto fld = [&](size_t base, int q) { return (T *)(gws + base + q * GL.fstep); };
+    const char *slot = seg_slot(gws, GL, m), *prev = prev_velocity(gws, GL, m);
     AdjTiles<T> P;
     for (int p = 0; p < 3; ++p) {
         P.g[p] = G;
@@ -420,8 +432,11 @@ template <typename T> AdjTiles<T> adj_tiles(const Grid<T> &G, char *gws, const G
     }
     for (int q = 0; q < 3; ++q) {
         P.g[0].f[VX + q] = (T *)(slot + q * GL.fstep);  // stored v^{n+1/2}
-        P.g[1].f[VX + q] = fld(GL.adj, VX + q);           // A_v
-        P.g[2].f[VX + q] = fld(GL.scr, 6 + q);            // Y
+        P.g[1].f[VX + q] = fld(GL.scr, 6 + q);            // Y
+        P.g[2].f[VX + q] = fld(GL.scr, 6 + q);
+        P.io[1].acc[q] = fld(GL.acc, 5 + q);              // g_b
+        P.io[1].vst[q] = (const T *)(slot + q * GL.fstep);
+        P.io[1].vprev[q] = (const T *)(prev + q * GL.fstep);
     }
     for (int q = 0; q < 6; ++q) {
         P.g[0].f[SXX + q] = fld(GL.adj, SXX + q);  // A_s
@@ -433,21 +448,31 @@ template <typename T> AdjTiles<T> adj_tiles(const Grid<T> &G, char *gws, const G
     return P;
 }
 
+// What the tiled adjoint's residual injection of segment step m updates.
+template <typename T> TapAdjoint<T> tap_adjoint(const Grid<T> &G, char *gws, const GradLayout &GL, int m)
+{
+    const AdjTiles<T> P = adj_tiles<T>(G, gws, GL, m);
+    TapAdjoint<T> A;
+    for (int q = 0; q < 3; ++q) {
+        A.y[q] = P.g[1].f[VX + q];
+        A.gb[q] = P.io[1].acc[q];
+        A.vst[q] = P.io[1].vst[q];
+        A.vprev[q] = P.io[1].vprev[q];
+    }
+    A.rho = G.rho;
+    for (int a = 0; a < 3; ++a)
+        for (int h = 0; h < 2; ++h) A.g[a][h] = G.g[a][h];
+    A.sy = G.sy;
+    A.sz = G.sz;
+    return A;
+}
+
 // Zero the adjoint state, accumulators and intermediate fields, and the segment slots
 // (whose samples at the pinned staggered positions are never stored and must read 0).
 template <typename T> void zero_grad_fields(char *gws, const GradLayout &GL, hipStream_t st)
 {
     fill_zero<T><<<2048, 256, 0, st>>>((T *)(gws + GL.adj), (long)((GL.ckpt - GL.adj) / sizeof(T)));
     fill_zero<T><<<2048, 256, 0, st>>>((T *)(gws + GL.seg), (long)((GL.res - GL.seg) / sizeof(T)));
-}
-
-// The pointwise part of the adjoint velocity step (b gradient, Y) over a grid.
-template <typename T> void launch_gb_point(const Grid<T> &G, const AdjGrid<T> &A, char *gws, const GradLayout &GL,
-                                           hipStream_t st)
-{
-    auto fld = [&](int q) { return (T *)(gws + GL.scr + q * GL.fstep); };
-    const dim3 blk(64, 4), grd((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
-    adj_gb_point<T><<<grd, blk, 0, st>>>(G, A, fld(6), fld(7), fld(8));
 }
 
 // Validates a caller's gradient workspace for checkpoints every k steps.
