@@ -70,9 +70,9 @@ def step_bytes(kern):
 
 
 # gradient, per shot and time step: forward with checkpoints (120), segment recompute
-# storing v^{n+1/2} (132), the adjoint passes: stress-A 27 fields, velocity-A 25 (X, Y,
-# v^{n+1/2}, v^{n-1/2}, rho and g_b read, Y and g_b written), stress-B 15 (268)
-GRAD_BYTES_PER_CELL_STEP = 120 + 132 + 4 * (27 + 25 + 15)
+# storing v^{n+1/2} (132), the adjoint passes: stress-A 27 fields, velocity-A 22 (X, Y,
+# v^{n+1/2}, rho and g_b read, Y and g_b written), stress-B 15 (256)
+GRAD_BYTES_PER_CELL_STEP = 120 + 132 + 4 * (27 + 22 + 15)
 # the design figure with eight staggered-point accumulators and no hand-over fields
 # between the adjoint passes (forward 120 + recompute 132 + adjoint 232)
 GRAD_BYTES_DESIGN = 120 + 132 + 232
@@ -810,6 +810,7 @@ def parse_args(argv=None):
     ap.add_argument("--kernel", metavar="VARIANT,TX,TY,ZC", default=None,
                     help="forward kernel configuration (default: autotuned, cached per grid)")
     ap.add_argument("--grad-shots", type=int, default=8, help="shots of the gradient section (profiling runs: fewer)")
+    ap.add_argument("--grad-wave", type=int, default=4, help="shots per batched gradient wave")
     ap.add_argument("--layout", choices=("auto", "separate", "rows"), default="auto",
                     help="field storage of the 256^3 forward sections (default: the library's choice)")
     ap.add_argument("--no-layout-ab", action="store_true", help="skip the separate-vs-rows A/B section")
@@ -937,7 +938,7 @@ def main(argv=None):
         ("stream_copy_gbs", stream_copy_ceiling),
         ("c2_forward", (lambda: None) if args.no_c2 else (lambda: bench_c2(args.c2_steps))),
         ("batched_forward", (lambda: None) if args.no_batch else bench_batch),
-        ("gradient", (lambda: None) if args.no_grad else (lambda: bench_gradient(nshots=args.grad_shots))),
+        ("gradient", (lambda: None) if args.no_grad else (lambda: bench_gradient(wave=args.grad_wave, nshots=args.grad_shots))),
         ("levels", (lambda: None) if args.no_levels else bench_levels),
         ("born", (lambda: None) if args.no_born else bench_born),
         ("coarse_medium", (lambda: None) if args.no_coarse else bench_coarse_medium),

@@ -20,8 +20,14 @@
 //
 // The tiled adjoint (velocity-type and stress-type tile bodies) keeps, in place of A_v,
 // Y = b G_v A_v, the field its adjoint stress pass reads: its velocity pass forms A_v from
-// the Y of the step after (G_v A_v = Y rho_eff), the gradient of b and the new Y in one
-// sweep, and its residual injection adds the injected share to Y and g_b at the taps.
+// the Y of the step after (G_v A_v = Y rho_eff), its share of the gradient of b and the
+// new Y in one sweep, and its residual injection adds the injected share to Y and g_b at
+// the taps.  Its gradient of b is the same sum taken by parts over the steps: with
+// A_v^n = G_v A_v^{n+1} + r^n - dt D_S X^n (r^n the injected residual),
+//   sum_n A_v^n (v^{n+1/2} - G_v v^{n-1/2}) rho_eff
+//     = sum_n v^{n+1/2} rho_eff (r^n - dt D_S X^n) - v^{-1/2} rho_eff G_v A_v^0,
+// which needs v^{n+1/2} alone; the last term (the initial velocity, zero unless the
+// forward started from a given state) is added once at the end of the sweep.
 #pragma once
 
 #include "common.h"
@@ -234,38 +240,37 @@ __global__ void __launch_bounds__(256) inject_residual(T *__restrict__ ax, T *__
     inject_one(ax, ay, az, taps, list[q / 3], q % 3, res, nt, n);
 }
 
-// (a11) for the tiled adjoint, whose velocity pass has already formed Y and the gradient
-// of b from A_v: the injected d = w r at a tap adds G_v d b to Y and
-// d (v^{n+1/2} - G_v v^{n-1/2}) rho_eff to g_b there, its share of both.  Field pointers
-// and strides of one grid (a tap's storage index gives its node).
+// (a11) for the tiled adjoint, whose velocity pass has already formed Y and its share of
+// the gradient of b: the injected d = w r at a tap adds G_v d b to Y and
+// d v^{n+1/2} rho_eff to g_b there.  Field pointers and strides of one grid (a tap's
+// storage index gives its node).
 template <typename T> struct TapAdjoint {
     T *y[3], *gb[3];
-    const T *vst[3], *vprev[3];  // stored v^{n+1/2}, v^{n-1/2}
+    const T *vst[3];  // stored v^{n+1/2}
     const T *rho;
     const T *g[3][2];  // damping profiles (as Grid::g)
     long sy, sz;
 };
 
+// Tap m of component c of receiver r (one thread per tap: the eight taps of a receiver
+// component are distinct samples).  Storage indices are below 2^31, so the node is found
+// with 32-bit divisions.
 template <typename T>
-__device__ __forceinline__ void inject_one_tiled(const TapAdjoint<T> &A, const RecTap<T> *__restrict__ taps, int r,
-                                                 int c, const T *__restrict__ res, int nt, int n)
+__device__ __forceinline__ void inject_tap_tiled(const TapAdjoint<T> &A, const RecTap<T> *__restrict__ taps, int r,
+                                                 int c, int m, const T *__restrict__ res, int nt, int n)
 {
     const RecTap<T> &t = taps[r * 3 + c];
-    const T v = res[((long)r * 3 + c) * nt + n];
+    const int q = t.idx[m];
+    if (q < 0) return;
+    const T d = t.w[m] * res[((long)r * 3 + c) * nt + n];
+    const unsigned sy = (unsigned)A.sy, sz = (unsigned)A.sz;
+    const unsigned k = (unsigned)q / sz, rem = (unsigned)q - k * sz;
+    const unsigned j = rem / sy, i = rem - j * sy;
+    const T g = A.g[0][c == 0][i] * A.g[1][c == 1][j] * A.g[2][c == 2][k];
     const long e = c == 0 ? 1 : (c == 1 ? A.sy : A.sz);
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const long q = t.idx[m];
-        if (q < 0) continue;
-        const T d = t.w[m] * v;
-        const int k = (int)(q / A.sz);
-        const long rem = q - (long)k * A.sz;
-        const int j = (int)(rem / A.sy), i = (int)(rem - (long)j * A.sy);
-        const T g = A.g[0][c == 0][i] * A.g[1][c == 1][j] * A.g[2][c == 2][k];
-        const T ra = A.rho[q], rb = A.rho[q + e];
-        A.y[c][q] += (g * d) * buoy(ra, rb);
-        A.gb[c][q] += d * ((A.vst[c][q] - g * A.vprev[c][q]) * ((ra + rb) * T(0.5)));
-    }
+    const T ra = A.rho[q], rb = A.rho[q + e];
+    A.y[c][q] += (g * d) * buoy(ra, rb);
+    A.gb[c][q] += (A.vst[c][q] * ((ra + rb) * T(0.5))) * d;
 }
 
 template <typename T>
@@ -274,8 +279,9 @@ __global__ void __launch_bounds__(256) inject_residual_tiled(TapAdjoint<T> A, co
                                                              const T *__restrict__ res, int nt, int n)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= 3 * count) return;
-    inject_one_tiled(A, taps, list[q / 3], q % 3, res, nt, n);
+    if (q >= 24 * count) return;
+    const int rc = q >> 3;
+    inject_tap_tiled(A, taps, list[rc / 3], rc % 3, q & 7, res, nt, n);
 }
 
 // (a13) chain rule from the staggered-point gradients to the node arrays (gathers, no
@@ -329,6 +335,31 @@ __global__ void __launch_bounds__(256) scale_velocity(Grid<T> G, const T *__rest
     out[i + (long)G.nx * (j + (long)G.ny * k)] = damp(G, c, i, j, k) * a[i + G.sy * j + G.sz * k];
 }
 
+// The last term of the tiled adjoint's gradient of b: g_b -= v^{-1/2} rho_eff (Y rho_eff),
+// with v^{-1/2} the initial velocity (v0) and Y that of the first step.
+template <typename T>
+__global__ void __launch_bounds__(256) gb_initial_velocity(Grid<T> G, const T *__restrict__ v0x,
+                                                           const T *__restrict__ v0y, const T *__restrict__ v0z,
+                                                           const T *__restrict__ yx, const T *__restrict__ yy,
+                                                           const T *__restrict__ yz, T *gbx, T *gby, T *gbz)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= G.nx || j >= G.ny) return;
+    const long p = i + G.sy * j + G.sz * k;
+    const T *v0[3] = {v0x, v0y, v0z}, *y[3] = {yx, yy, yz};
+    T *gb[3] = {gbx, gby, gbz};
+    const bool act[3] = {i <= G.nx - 2, j <= G.ny - 2, k <= G.nz - 2};
+    const long e[3] = {1, G.sy, G.sz};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (!act[c]) continue;
+        const T re = (G.rho[p] + G.rho[p + e[c]]) * T(0.5);
+        gb[c][p] -= (v0[c][p] * re) * (y[c][p] * re);
+    }
+}
+
 // G_v A_v = Y rho_eff at the active samples of component c (zero elsewhere).
 template <typename T>
 __global__ void __launch_bounds__(256) velocity_from_y(Grid<T> G, const T *__restrict__ y, int c, T *__restrict__ out)
@@ -361,6 +392,7 @@ template <typename T> struct ShotInject {
     int rbase[kMaxBatchColors];     // first work item of this shot in colour c's flat list
 };
 
+// total: work items of the colour (three per receiver); one thread per tap of an item.
 template <typename T>
 __global__ void __launch_bounds__(256) inject_residual_multi(const ShotInject<T> *__restrict__ d, int nshot, int color,
                                                              int total, int nt, int n)
@@ -368,14 +400,15 @@ __global__ void __launch_bounds__(256) inject_residual_multi(const ShotInject<T>
     __shared__ int s_base[kMaxShots];
     for (int t = threadIdx.x; t < nshot; t += blockDim.x) s_base[t] = d[t].rbase[color];
     __syncthreads();
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= total) return;
+    const int qt = blockIdx.x * blockDim.x + threadIdx.x;
+    if (qt >= 8 * total) return;
+    const int q = qt >> 3;
     int s = 0;
     while (s + 1 < nshot && s_base[s + 1] <= q) ++s;
     const ShotInject<T> &sh = d[s];
     const int l = q - sh.rbase[color];
     const int r = sh.colors[sh.coff[color] + l / 3];
-    inject_one_tiled(sh.t, sh.taps, r, l % 3, sh.res, nt, n);
+    inject_tap_tiled(sh.t, sh.taps, r, l % 3, qt & 7, sh.res, nt, n);
 }
 
 // Copies of many equally long arrays (checkpoint save / restore of every shot).

@@ -396,12 +396,12 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
 // ---- batched gradient ----------------------------------------------------------
 // Batch workspace of fd3d_batch_gradient: descriptor arrays (nshot entries each) of the
 // forward pass, of the segment recompute per segment slot m (store pointers of slot m),
-// of the adjoint passes (stress-A and velocity-A per slot m, which read the velocities
+// of the adjoint passes (stress-A and velocity-A per slot m, which read the velocity
 // stored for segment step m; stress-B once), of the residual injection per slot m, and per
-// checkpoint the save and restore copy lists (the restore also fills the prev group).
+// checkpoint the save and restore copy lists.
 struct BatchGradLayout {
     size_t fwd0, fwd_slot, sa_slot, va_slot, sb, inj_slot, save_copy, rest_copy, total;
-    size_t fwd_bytes, inj_bytes, copy_bytes, rest_bytes;
+    size_t fwd_bytes, inj_bytes, copy_bytes;
     int k, nseg;
 };
 
@@ -413,7 +413,6 @@ template <typename T> BatchGradLayout make_batch_grad_layout(const fd3d_batch *b
     L.fwd_bytes = round_up((size_t)b->nshot * sizeof(ShotFwd<T>), kAlign);
     L.inj_bytes = round_up((size_t)b->nshot * sizeof(ShotInject<T>), kAlign);
     L.copy_bytes = round_up((size_t)b->nshot * 9 * sizeof(CopyDesc<T>), kAlign);
-    L.rest_bytes = round_up((size_t)b->nshot * 10 * sizeof(CopyDesc<T>), kAlign);
     size_t off = 0;
     L.fwd0 = off;
     off += L.fwd_bytes;
@@ -430,7 +429,7 @@ template <typename T> BatchGradLayout make_batch_grad_layout(const fd3d_batch *b
     L.save_copy = off;
     off += (size_t)L.nseg * L.copy_bytes;
     L.rest_copy = off;
-    off += (size_t)L.nseg * L.rest_bytes;
+    off += (size_t)L.nseg * L.copy_bytes;
     L.total = off;
     return L;
 }
@@ -534,20 +533,18 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     }
     std::memcpy(h + BL.sb, sb.data(), fbytes);
     for (int cidx = 0; cidx < BL.nseg; ++cidx) {
-        std::vector<CopyDesc<T>> sv(S * 9), rs(S * 10);
+        std::vector<CopyDesc<T>> sv(S * 9), rs(S * 9);
         for (int s = 0; s < S; ++s) {
             char *ck = (char *)gws[s] + GL[s].ckpt + (size_t)cidx * GL[s].group;
             const long n = (long)(b->ctx[s]->L.field_bytes / sizeof(T));
             for (int q = 0; q < NFIELD; ++q) {
                 T *live = (T *)state_chunk<T>(b->ctx[s], fw[s].G, q), *kept = (T *)(ck + q * GL[s].chunk);
                 sv[s * 9 + q] = CopyDesc<T>{live, kept, n};
-                rs[s * 10 + q] = CopyDesc<T>{kept, live, n};
+                rs[s * 9 + q] = CopyDesc<T>{kept, live, n};
             }
-            rs[s * 10 + 9] = CopyDesc<T>{(const T *)ck, (T *)((char *)gws[s] + GL[s].prev),
-                                         (long)(prev_copy_bytes(b->ctx[s], GL[s]) / sizeof(T))};
         }
         std::memcpy(h + BL.save_copy + cidx * BL.copy_bytes, sv.data(), sv.size() * sizeof(CopyDesc<T>));
-        std::memcpy(h + BL.rest_copy + cidx * BL.rest_bytes, rs.data(), rs.size() * sizeof(CopyDesc<T>));
+        std::memcpy(h + BL.rest_copy + cidx * BL.copy_bytes, rs.data(), rs.size() * sizeof(CopyDesc<T>));
     }
     b->rec_host.assign((const unsigned char *)rr.data(), (const unsigned char *)(rr.data() + S));
     HIP_TRY(hipMemcpyAsync(bws, h, BL.total, hipMemcpyHostToDevice, st));
@@ -567,7 +564,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     // forward with checkpoints
     auto desc = [&](size_t off) { return (const ShotFwd<T> *)(bws + off); };
     const ShotRec<T> *rdesc = (const ShotRec<T> *)(b->ws + b->off_rec);
-    const dim3 cgrid(256, 9 * S), rgrid(256, 10 * S);
+    const dim3 cgrid(256, 9 * S);
     if (!(flags & FD3D_KEEP_STATE))
         for (fd3d_ctx *c : b->ctx) zero_fields<T>(c, st);
     auto pass = [&](const ShotFwd<T> *d, int n, int p, const ShotRec<T> *r = nullptr) {
@@ -593,7 +590,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     // reverse sweep over the segments
     for (int sg = BL.nseg - 1; sg >= 0; --sg) {
         const int n0 = sg * k, n1 = std::min(n0 + k, b->nt);
-        copy_multi<T><<<rgrid, 256, 0, st>>>((const CopyDesc<T> *)(bws + BL.rest_copy + sg * BL.rest_bytes));
+        copy_multi<T><<<cgrid, 256, 0, st>>>((const CopyDesc<T> *)(bws + BL.rest_copy + sg * BL.copy_bytes));
         for (int n = n0; n < n1; ++n) {
             const ShotFwd<T> *d = desc(BL.fwd_slot + (n - n0) * BL.fwd_bytes);
             pass(d, n, kPassVelSave);
@@ -606,7 +603,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
             const ShotInject<T> *idesc = (const ShotInject<T> *)(bws + BL.inj_slot + m * BL.inj_bytes);
             for (int q = 0; q < ncol; ++q)
                 if (cbase[q] > 0)
-                    inject_residual_multi<T><<<(cbase[q] + 255) / 256, 256, 0, st>>>(idesc, S, q, cbase[q], b->nt, n);
+                    inject_residual_multi<T><<<(8 * cbase[q] + 255) / 256, 256, 0, st>>>(idesc, S, q, cbase[q], b->nt, n);
             pass(desc(BL.sb), n, kPassStressB);
         }
     }
@@ -614,6 +611,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     for (int s = 0; s < S; ++s) {
         fd3d_ctx *c = b->ctx[s];
         const dim3 blk(64, 4, 1), grd((c->n[0] + 63) / 64, (c->n[1] + 3) / 4, c->n[2]);
+        launch_gb_initial<T>(fw[s].G, ag[s], (char *)gws[s], GL[s], st);
         grad_finalize<T><<<grd, blk, 0, st>>>(fw[s].G, ag[s], (T *)g_lam[s], (T *)g_mu[s], (T *)g_rho[s]);
         c->grad_ws = (const char *)gws[s];
         c->grad_k = k;

@@ -221,8 +221,8 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
 // gradient's segment recompute).  For the velocity-type body, kAdjA: the adjoint velocity
 // update A_v = U' - dt D_S(X) (X = C G_s A_s, precomputed; U' = Y' rho_eff, the damped
 // adjoint velocity of the step after, held as Y'), then at the own sample the buoyancy
-// gradient g_b += A_v (v^{n+1/2} - G_v v^{n-1/2}) rho_eff and Y = b G_v A_v, written over
-// Y' (A_v itself is not stored).  For the stress-type body, kAdjA: gradients of C from
+// gradient's share g_b -= v^{n+1/2} rho_eff dt D_S(X) and Y = b G_v A_v, written over Y'
+// (A_v itself is not stored).  For the stress-type body, kAdjA: gradients of C from
 // E(v^{n+1/2}) and T = G_s A_s, X = C T; kAdjB: A_s <- G_s A_s - dt E(Y).  The adjoint
 // modes read and write the arrays named by the grid (f[] pointing at the adjoint, stored
 // or scratch fields) and by TileIO.  The Born
@@ -267,7 +267,7 @@ template <typename T> struct TileIO {
     T *acc[5];  // gradient accumulators: stress-A's (gl, gm, g_mu_xy, g_mu_xz, g_mu_yz),
                 // velocity-A's (g_bx, g_by, g_bz); or the Born model perturbation (drho;
                 // dlam, dmu)
-    const T *vst[3], *vprev[3];  // velocity-A: stored v^{n+1/2}, v^{n-1/2}
+    const T *vst[3];  // velocity-A: stored v^{n+1/2}
 };
 
 // Source coefficients of NC consecutive components starting at C0, staged in LDS when a
@@ -397,7 +397,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     // plane registers, loaded one plane ahead
     struct Plane {
         T cxx, cyy, cxy, vx, vy, vz, xx, xy, xz, yy, yz, r, dr, dvx, dvy, dvz;
-        T s[3], p[3], gb[3];  // velocity-A: stored v^{n+1/2}, v^{n-1/2}, buoyancy gradients
+        T s[3], gb[3];  // velocity-A: stored v^{n+1/2}, buoyancy gradients
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const unsigned pk = wplane(w, kk, ok), pr = wplane(w, kk, ok && use_rho), o = oc + pk;
@@ -412,7 +412,6 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 P.s[c] = ldm<NTP, T>(wfield(io.vst[c], w), o);
-                P.p[c] = ldm<NTP, T>(wfield(io.vprev[c], w), o);
                 P.gb[c] = ld<T>(wfield(io.acc[c], w), o);
             }
         }
@@ -459,11 +458,10 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         }
         const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
         const T bvx0 = P.dvx, bvy0 = P.dvy, bvz0 = P.dvz;  // the perturbation's velocity (kBornV)
-        T st0[3], pv0[3], gb0[3];  // velocity-A's own-sample inputs of this plane
+        T st0[3], gb0[3];  // velocity-A's own-sample inputs of this plane
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             st0[c] = P.s[c];
-            pv0[c] = P.p[c];
             gb0[c] = P.gb[c];
         }
         // buoyancy at the three velocity samples: node means (Sec. 2.2.1), or the coarse
@@ -509,9 +507,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         // mean, g its damping factor, d the divergence of X; stores Y and g_b (at so)
         auto adj_v = [&](int c, rsrc_t oy, unsigned so, T y0, T ra, T rb, T g, T d) {
             const T re = (ra + rb) * T(0.5);
-            const T a = y0 * re - dt * d;
-            st(oy, so, (g * a) * buoy(ra, rb));
-            st(wfield(io.acc[c], w), so, gb0[c] + a * ((st0[c] - g * pv0[c]) * re));
+            const T dd = dt * d;
+            st(oy, so, (g * (y0 * re - dd)) * buoy(ra, rb));
+            st(wfield(io.acc[c], w), so, gb0[c] - (st0[c] * re) * dd);
         };
         {
             const int o = own_c3 + tx + 1;

@@ -65,7 +65,7 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
             const int cnt = c->color_off[col + 1] - c->color_off[col];
             const int *list = colors + c->color_off[col];
             if (tiled)
-                inject_residual_tiled<T><<<(3 * cnt + 255) / 256, 256, 0, st>>>(ta, taps, list, cnt, residual, c->nt, n);
+                inject_residual_tiled<T><<<(24 * cnt + 255) / 256, 256, 0, st>>>(ta, taps, list, cnt, residual, c->nt, n);
             else
                 inject_residual<T><<<(3 * cnt + 255) / 256, 256, 0, st>>>(A.a[VX], A.a[VY], A.a[VZ], taps, list, cnt,
                                                                          residual, c->nt, n);
@@ -78,7 +78,8 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
         for (int q = 0; q < NFIELD; ++q)
             HIP_TRY(hipMemcpyAsync(state_chunk<T>(c, G, q), ck + q * GL.chunk, c->L.field_bytes,
                                    hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(gws + GL.prev, ck, prev_copy_bytes(c, GL), hipMemcpyDeviceToDevice, st));
+        if (!tiled)  // the cell adjoint's v^{n-1/2} of the segment's first step
+            HIP_TRY(hipMemcpyAsync(gws + GL.prev, ck, prev_copy_bytes(c, GL), hipMemcpyDeviceToDevice, st));
         for (int n = n0; n < n1; ++n) {
             char *slot = seg_slot(gws, GL, n - n0);
             Grid<T> Gs = G;
@@ -102,6 +103,7 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
             }
         }
     }
+    if (tiled) launch_gb_initial<T>(G, A, gws, GL, st);
     grad_finalize<T><<<grd, blk, 0, st>>>(G, A, g_lam, g_mu, g_rho);
     HIP_TRY(hipGetLastError());
     return FD3D_OK;

@@ -402,7 +402,8 @@ template <typename T> AdjGrid<T> make_adj(char *gws, const GradLayout &GL)
     return A;
 }
 
-// The stored velocities of segment step m for the one-thread-per-cell adjoint.
+// The stored velocities of segment step m for the one-thread-per-cell adjoint (the tiled
+// adjoint reads v^{n+1/2} only).
 template <typename T> void set_stored_velocity(AdjGrid<T> &A, char *gws, const GradLayout &GL, int m)
 {
     const char *slot = seg_slot(gws, GL, m), *prev = prev_velocity(gws, GL, m);
@@ -423,7 +424,7 @@ template <typename T> struct AdjTiles {
 template <typename T> AdjTiles<T> adj_tiles(const Grid<T> &G, char *gws, const GradLayout &GL, int m)
 {
     auto fld = [&](size_t base, int q) { return (T *)(gws + base + q * GL.fstep); };
-    const char *slot = seg_slot(gws, GL, m), *prev = prev_velocity(gws, GL, m);
+    const char *slot = seg_slot(gws, GL, m);
     AdjTiles<T> P;
     for (int p = 0; p < 3; ++p) {
         P.g[p] = G;
@@ -436,7 +437,6 @@ template <typename T> AdjTiles<T> adj_tiles(const Grid<T> &G, char *gws, const G
         P.g[2].f[VX + q] = fld(GL.scr, 6 + q);
         P.io[1].acc[q] = fld(GL.acc, 5 + q);              // g_b
         P.io[1].vst[q] = (const T *)(slot + q * GL.fstep);
-        P.io[1].vprev[q] = (const T *)(prev + q * GL.fstep);
     }
     for (int q = 0; q < 6; ++q) {
         P.g[0].f[SXX + q] = fld(GL.adj, SXX + q);  // A_s
@@ -457,7 +457,6 @@ template <typename T> TapAdjoint<T> tap_adjoint(const Grid<T> &G, char *gws, con
         A.y[q] = P.g[1].f[VX + q];
         A.gb[q] = P.io[1].acc[q];
         A.vst[q] = P.io[1].vst[q];
-        A.vprev[q] = P.io[1].vprev[q];
     }
     A.rho = G.rho;
     for (int a = 0; a < 3; ++a)
@@ -465,6 +464,17 @@ template <typename T> TapAdjoint<T> tap_adjoint(const Grid<T> &G, char *gws, con
     A.sy = G.sy;
     A.sz = G.sz;
     return A;
+}
+
+// The tiled adjoint's last term of the gradient of b, from the initial velocity (the
+// velocity fields of checkpoint 0) and the first step's Y.
+template <typename T> void launch_gb_initial(const Grid<T> &G, const AdjGrid<T> &A, char *gws, const GradLayout &GL,
+                                             hipStream_t st)
+{
+    auto v0 = [&](int q) { return (const T *)(gws + GL.ckpt + q * GL.fstep); };
+    auto y = [&](int q) { return (const T *)(gws + GL.scr + (6 + q) * GL.fstep); };
+    const dim3 blk(64, 4, 1), grd((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
+    gb_initial_velocity<T><<<grd, blk, 0, st>>>(G, v0(0), v0(1), v0(2), y(0), y(1), y(2), A.gb[0], A.gb[1], A.gb[2]);
 }
 
 // Zero the adjoint state, accumulators and intermediate fields, and the segment slots
