@@ -70,12 +70,13 @@ def step_bytes(kern):
 
 
 # gradient, per shot and time step: forward with checkpoints (120), segment recompute
-# storing v^{n+1/2} (132), the adjoint passes: stress-A 27 fields, velocity-A 22 (X, Y,
-# v^{n+1/2}, rho and g_b read, Y and g_b written), stress-B 15 (256)
-GRAD_BYTES_PER_CELL_STEP = 120 + 132 + 4 * (27 + 22 + 15)
+# (120: its velocity pass writes v^{n+1/2} into the segment slot instead of over the
+# state), the adjoint passes: stress-A 27 fields, velocity-A 22 (X, Y, v^{n+1/2}, rho and
+# g_b read, Y and g_b written), stress-B 15 (256)
+GRAD_BYTES_PER_CELL_STEP = 120 + 120 + 4 * (27 + 22 + 15)
 # the design figure with eight staggered-point accumulators and no hand-over fields
-# between the adjoint passes (forward 120 + recompute 132 + adjoint 232)
-GRAD_BYTES_DESIGN = 120 + 132 + 232
+# between the adjoint passes (forward 120 + recompute 120 + adjoint 232)
+GRAD_BYTES_DESIGN = 120 + 120 + 232
 # measured counter calibration (plain 1 GiB copy): FETCH_SIZE reads 0.5x, WRITE_SIZE 1.0x
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
@@ -595,7 +596,7 @@ def bench_levels(K=100):
     return out
 
 
-def bench_gradient(wave=4, nshots=8):
+def bench_gradient(wave=None, nshots=8):
     import torch
 
     import workloads as W
@@ -637,11 +638,16 @@ def bench_gradient(wave=4, nshots=8):
         J_loop = J_loop + j
     t_loop = time.perf_counter() - t0
     kern = sim.kernel()
+    per_shot_bytes = gws.numel() + sim.workspace.numel()
     sim.close()
     del gws
     torch.cuda.empty_cache()
     log(f"[bench] gradient loop {t_loop:.2f} s, per shot median {statistics.median(per_shot):.3f} s")
-    # batched waves sharing the model and the gradient arrays
+    # batched waves sharing the model and the gradient arrays: as many shots per wave as
+    # fit in 95 % of the free device memory (a shot: its gradient and forward workspaces)
+    if wave is None:
+        wave = max(1, int(0.95 * torch.cuda.mem_get_info()[0]) // per_shot_bytes)
+        log(f"[bench] batched gradient wave: {wave} shots ({per_shot_bytes / 2**30:.1f} GiB each)")
     wave = min(wave, len(shots))
     sims = [Simulator(*model, 10.0, 5e-4, nt, sponge=20, device=dev) for _ in range(wave)]
     for x in sims:
@@ -810,7 +816,8 @@ def parse_args(argv=None):
     ap.add_argument("--kernel", metavar="VARIANT,TX,TY,ZC", default=None,
                     help="forward kernel configuration (default: autotuned, cached per grid)")
     ap.add_argument("--grad-shots", type=int, default=8, help="shots of the gradient section (profiling runs: fewer)")
-    ap.add_argument("--grad-wave", type=int, default=4, help="shots per batched gradient wave")
+    ap.add_argument("--grad-wave", type=int, default=None,
+                    help="shots per batched gradient wave (default: as many as fit in device memory)")
     ap.add_argument("--layout", choices=("auto", "separate", "rows"), default="auto",
                     help="field storage of the 256^3 forward sections (default: the library's choice)")
     ap.add_argument("--no-layout-ab", action="store_true", help="skip the separate-vs-rows A/B section")

@@ -395,12 +395,13 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
 
 // ---- batched gradient ----------------------------------------------------------
 // Batch workspace of fd3d_batch_gradient: descriptor arrays (nshot entries each) of the
-// forward pass, of the segment recompute per segment slot m (store pointers of slot m),
+// forward pass, of the segment recompute per segment slot m (velocity: v^{n-1/2} from
+// slot m-1, or the live state for m = 0, v^{n+1/2} into slot m; stress: v^{n+1/2} of slot m),
 // of the adjoint passes (stress-A and velocity-A per slot m, which read the velocity
 // stored for segment step m; stress-B once), of the residual injection per slot m, and per
 // checkpoint the save and restore copy lists.
 struct BatchGradLayout {
-    size_t fwd0, fwd_slot, sa_slot, va_slot, sb, inj_slot, save_copy, rest_copy, total;
+    size_t fwd0, fwd_slot, fst_slot, sa_slot, va_slot, sb, inj_slot, save_copy, rest_copy, total;
     size_t fwd_bytes, inj_bytes, copy_bytes;
     int k, nseg;
 };
@@ -417,6 +418,8 @@ template <typename T> BatchGradLayout make_batch_grad_layout(const fd3d_batch *b
     L.fwd0 = off;
     off += L.fwd_bytes;
     L.fwd_slot = off;
+    off += (size_t)k * L.fwd_bytes;
+    L.fst_slot = off;
     off += (size_t)k * L.fwd_bytes;
     L.sa_slot = off;
     off += (size_t)k * L.fwd_bytes;
@@ -514,12 +517,15 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     };
     std::vector<ShotFwd<T>> sb(S);
     for (int m = 0; m < k; ++m) {
-        std::vector<ShotFwd<T>> f2 = fw, sa(S), va(S);
+        std::vector<ShotFwd<T>> f2 = fw, f3 = fw, sa(S), va(S);
         std::vector<ShotInject<T>> ijm = ij;
         for (int s = 0; s < S; ++s) {
             char *w = (char *)gws[s];
             char *slot = seg_slot(w, GL[s], m);
-            for (int q = 0; q < 3; ++q) f2[s].G.save[VX + q] = (T *)(slot + q * GL[s].fstep);
+            for (int q = 0; q < 3; ++q) {
+                f2[s].G.save[VX + q] = f3[s].G.f[VX + q] = (T *)(slot + q * GL[s].fstep);
+                if (m > 0) f2[s].G.f[VX + q] = (T *)(seg_slot(w, GL[s], m - 1) + q * GL[s].fstep);
+            }
             const AdjTiles<T> P = adj_tiles<T>(fw[s].G, w, GL[s], m);
             sa[s] = adj_desc(s, P, 0);
             va[s] = adj_desc(s, P, 1);
@@ -527,6 +533,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
             ijm[s].t = tap_adjoint<T>(fw[s].G, w, GL[s], m);
         }
         std::memcpy(h + BL.fwd_slot + m * BL.fwd_bytes, f2.data(), fbytes);
+        std::memcpy(h + BL.fst_slot + m * BL.fwd_bytes, f3.data(), fbytes);
         std::memcpy(h + BL.sa_slot + m * BL.fwd_bytes, sa.data(), fbytes);
         std::memcpy(h + BL.va_slot + m * BL.fwd_bytes, va.data(), fbytes);
         std::memcpy(h + BL.inj_slot + m * BL.inj_bytes, ijm.data(), S * sizeof(ShotInject<T>));
@@ -592,9 +599,8 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         const int n0 = sg * k, n1 = std::min(n0 + k, b->nt);
         copy_multi<T><<<cgrid, 256, 0, st>>>((const CopyDesc<T> *)(bws + BL.rest_copy + sg * BL.copy_bytes));
         for (int n = n0; n < n1; ++n) {
-            const ShotFwd<T> *d = desc(BL.fwd_slot + (n - n0) * BL.fwd_bytes);
-            pass(d, n, kPassVelSave);
-            pass(d, n, kPassStress);
+            pass(desc(BL.fwd_slot + (n - n0) * BL.fwd_bytes), n, kPassVelSave);
+            pass(desc(BL.fst_slot + (n - n0) * BL.fwd_bytes), n, kPassStress);
         }
         for (int n = n1 - 1; n >= n0; --n) {
             const int m = n - n0;

@@ -43,8 +43,8 @@ template <typename T> struct Grid {
     const T *lam, *mu, *rho;
     T *f[NFIELD];
     const T *g[3][2];      // damping profile per axis at integer [0] / half [1] positions
-    T *save[NFIELD];       // optional copies written by the passes (gradient recompute):
-                           // the velocity pass stores v^{n+1/2}, the stress pass sigma^n
+    T *save[NFIELD];       // gradient recompute: where the velocity pass writes v^{n+1/2}
+                           // (save[VX..VZ]; the others unused)
     int ks;                // vacuum surface: first solid node plane (0: no vacuum)
     const int *ksmap;      // optional first solid plane per node column [ny][nx] (topography)
     int cm[3];             // coarse medium: lam, mu, rho hold (mx, my, mz) nodes (cm[0] = 0: node arrays)

@@ -106,10 +106,6 @@ __global__ void __launch_bounds__(256) stress_cell(Grid<T> G, Inject<T> src, int
     else ezz = dz_or_o2(o2_int(sp.n, k), rd<VZ>(G, i, j, k), rd<VZ>(G, i, j, k - 1), rd<VZ>(G, i, j, k + 1), rd<VZ>(G, i, j, k - 2), rdz);
     const T tr = exx + eyy + ezz;
     const T gn = G.g[0][0][i] * G.g[1][0][j] * G.g[2][0][k];
-    if (G.save[SXX]) {
-#pragma unroll
-        for (int c = SXX; c <= SYZ; ++c) G.save[c][p] = G.f[c][p];
-    }
     {
         T sxx = G.f[SXX][p] + dt * (l * tr + T(2) * m * exx);
         T syy = G.f[SYY][p] + dt * (l * tr + T(2) * m * eyy);

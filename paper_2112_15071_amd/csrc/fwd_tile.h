@@ -217,8 +217,9 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
 }
 
 // What a tile body computes.  kFwd: the forward pass; kFwdSave (velocity-type body): the
-// forward velocity pass that also stores v^{n+1/2} through the grid's save pointers (the
-// gradient's segment recompute).  For the velocity-type body, kAdjA: the adjoint velocity
+// forward velocity pass that writes v^{n+1/2} through the grid's save pointers instead of
+// over v^{n-1/2} (the gradient's segment recompute, whose steps read v^{n-1/2} from the
+// previous step's slot).  For the velocity-type body, kAdjA: the adjoint velocity
 // update A_v = U' - dt D_S(X) (X = C G_s A_s, precomputed; U' = Y' rho_eff, the damped
 // adjoint velocity of the step after, held as Y'), then at the own sample the buoyancy
 // gradient's share g_b -= v^{n+1/2} rho_eff dt D_S(X) and Y = b G_v A_v, written over Y'
@@ -522,8 +523,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 T v = vx0 + dt * bb * d;
                 if (srcv) v += bb * cf(VX, tap_of(src, VX, i, j, k)) * s;
                 v = v * (gxh * gyi * gz_i);
-                st(ovx, st_vx + pw, v);
-                if constexpr (MODE == kFwdSave) stm<NTP>(wfield(G.save[VX], w), st_vx + pw, v);
+                st(MODE == kFwdSave ? wfield(G.save[VX], w) : ovx, st_vx + pw, v);
             }
             if constexpr (born) {
                 const T bb = buoy(r0, Lr[ty * WR + tx + 1]);
@@ -545,8 +545,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 T v = vy0 + dt * bb * d;
                 if (srcv) v += bb * cf(VY, tap_of(src, VY, i, j, k)) * s;
                 v = v * (gxi * gyh * gz_i);
-                st(ovy, st_vy + pw, v);
-                if constexpr (MODE == kFwdSave) stm<NTP>(wfield(G.save[VY], w), st_vy + pw, v);
+                st(MODE == kFwdSave ? wfield(G.save[VY], w) : ovy, st_vy + pw, v);
             }
             if constexpr (born) {
                 const T bb = buoy(r0, Lr[(ty + 1) * WR + tx]);
@@ -569,8 +568,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 T v = vz0 + dt * bb * d;
                 if (srcv) v += bb * cf(VZ, tap_of(src, VZ, i, j, k)) * s;
                 v = v * (gxi * gyi * gz_h);
-                st(ovz, st_vz + pw, v);
-                if constexpr (MODE == kFwdSave) stm<NTP>(wfield(G.save[VZ], w), st_vz + pw, v);
+                st(MODE == kFwdSave ? wfield(G.save[VZ], w) : ovz, st_vz + pw, v);
             }
             if constexpr (born) {
                 const T bb = buoy(r0, r1);

@@ -81,11 +81,25 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
         if (!tiled)  // the cell adjoint's v^{n-1/2} of the segment's first step
             HIP_TRY(hipMemcpyAsync(gws + GL.prev, ck, prev_copy_bytes(c, GL), hipMemcpyDeviceToDevice, st));
         for (int n = n0; n < n1; ++n) {
-            char *slot = seg_slot(gws, GL, n - n0);
-            Grid<T> Gs = G;
-            for (int q = 0; q < 3; ++q) Gs.save[VX + q] = (T *)(slot + q * GL.fstep);
-            if (c->opts.free_surface) step<T, true>(c, Gs, inj, n, 0, taps, nullptr, st, tm);
-            else step<T, false>(c, Gs, inj, n, 0, taps, nullptr, st, tm);
+            const int m = n - n0;
+            char *slot = seg_slot(gws, GL, m);
+            if (tiled) {  // velocities out of place: slot m-1 (the live state for m = 0) -> slot m
+                Grid<T> Gv = G, Gs = G;
+                for (int q = 0; q < 3; ++q) {
+                    Gv.save[VX + q] = Gs.f[VX + q] = (T *)(slot + q * GL.fstep);
+                    if (m > 0) Gv.f[VX + q] = (T *)(seg_slot(gws, GL, m - 1) + q * GL.fstep);
+                }
+                tm.begin(0);
+                launch_pass<T, false>(c, Gv, inj, n, kPassVel, st);
+                tm.end();
+                tm.begin(2);
+                launch_pass<T, false>(c, Gs, inj, n, kPassStress, st);
+                tm.end();
+            } else {  // in place, also storing v^{n+1/2} in slot m
+                Grid<T> Gs = G;
+                for (int q = 0; q < 3; ++q) Gs.save[VX + q] = (T *)(slot + q * GL.fstep);
+                step<T, false>(c, Gs, inj, n, 0, taps, nullptr, st, tm);
+            }
         }
         for (int n = n1 - 1; n >= n0; --n) {
             const int m = n - n0;

@@ -275,8 +275,9 @@ template <typename T, typename F> decltype(auto) with_tile(int tx, int ty, F &&f
 // Passes of a step.  Forward: velocity, stress.  Adjoint step (reverse order of the
 // forward step): stress-A (C gradients, X = C G_s A_s), velocity-A (A_v update, b
 // gradient, Y = G_v A_v / rho_eff), stress-B (A_s update from Y).  The velocity pass also
-// comes in a variant that stores v^{n+1/2} through the grid's save pointers (the
-// gradient's segment recompute).
+// comes in a variant for the gradient's segment recompute: the tile kernels write
+// v^{n+1/2} through the grid's save pointers instead of over v^{n-1/2}, the cell kernel
+// writes it to both.
 enum Pass { kPassVel = 0, kPassStress = 1, kPassStressA, kPassVelA, kPassStressB, kPassVelSave };
 
 // Tile and fused sweeps address a window of at most zchunk + 8 planes (and at most the
