@@ -725,8 +725,9 @@ def counters_run(kernels, K, grad=False):
         sync()
         sim.close()
     if grad:
-        # one checkpointed gradient of the first configuration: its recompute (forward
-        # passes that store v and sigma) and the four adjoint passes
+        # one checkpointed gradient of the first configuration: its recompute (the velocity
+        # pass writing v^{n+1/2} into the segment slots, the stress pass) and the adjoint
+        # passes
         sim = make(kernels[0])
         k = max(1, K // 2)
         gws = sim.grad_workspace(k)
