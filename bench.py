@@ -71,9 +71,11 @@ def step_bytes(kern):
 
 # gradient, per shot and time step: forward with checkpoints (120), segment recompute
 # (120: its velocity pass writes v^{n+1/2} into the segment slot instead of over the
-# state), the adjoint passes: stress-A 27 fields, velocity-A 22 (X, Y, v^{n+1/2}, rho and
-# g_b read, Y and g_b written), stress-B 15 (256)
-GRAD_BYTES_PER_CELL_STEP = 120 + 120 + 4 * (27 + 22 + 15)
+# state), the adjoint passes: stress-M 36 fields (the adjoint stress update of the step
+# after and stress-A of this step: A_s, Y, stored v, lambda, mu and 5 accumulators read;
+# A_s, X and the accumulators written), velocity-A 22 (X, Y, v^{n+1/2}, rho and g_b read,
+# Y and g_b written): 232
+GRAD_BYTES_PER_CELL_STEP = 120 + 120 + 4 * (36 + 22)
 # the design figure with eight staggered-point accumulators and no hand-over fields
 # between the adjoint passes (forward 120 + recompute 120 + adjoint 232)
 GRAD_BYTES_DESIGN = 120 + 120 + 232

@@ -204,6 +204,10 @@ int launch_multi(const BatchGroup &gr, const ShotFwd<T> *d, int n, int pass, hip
     case kPassStress: stress_tile_multi<T, TX, TY, TX2, TY2, FS><<<gs, NT, 0, st>>>(d, S, W, n, rec); break;
     case kPassVelSave: vel_tile_multi<T, TX, TY, TX2, TY2, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n); break;
     case kPassStressA: stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n, none); break;
+    case kPassStressM:  // one tile shape only: two shapes' LDS planes of this pass exceed a CU's LDS
+        if constexpr (TX2 == 0) stress_tile_multi<T, TX, TY, 0, 0, false, kAdjM><<<g, NT, 0, st>>>(d, S, W, n, none);
+        else return fail(FD3D_EINVAL, "stress-M batches take one tile shape");
+        break;
     case kPassVelA: vel_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
     default: stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n, none); break;
     }
@@ -397,9 +401,9 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
 // Batch workspace of fd3d_batch_gradient: descriptor arrays (nshot entries each) of the
 // forward pass, of the segment recompute per segment slot m (velocity: v^{n-1/2} from
 // slot m-1, or the live state for m = 0, v^{n+1/2} into slot m; stress: v^{n+1/2} of slot m),
-// of the adjoint passes (stress-A and velocity-A per slot m, which read the velocity
-// stored for segment step m; stress-B once), of the residual injection per slot m, and per
-// checkpoint the save and restore copy lists.
+// of the adjoint passes (stress-M and velocity-A per slot m, which read the velocity
+// stored for segment step m; the closing stress-B), of the residual injection per slot m,
+// and per checkpoint the save and restore copy lists.
 struct BatchGradLayout {
     size_t fwd0, fwd_slot, fst_slot, sa_slot, va_slot, sb, inj_slot, save_copy, rest_copy, total;
     size_t fwd_bytes, inj_bytes, copy_bytes;
@@ -568,6 +572,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
     all.tiles = tiles;
     all.recs = recs;
 
+    const bool merged = all.tx2 == 0;  // stress-M (one tile shape)
     // forward with checkpoints
     auto desc = [&](size_t off) { return (const ShotFwd<T> *)(bws + off); };
     const ShotRec<T> *rdesc = (const ShotRec<T> *)(b->ws + b->off_rec);
@@ -604,15 +609,22 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         }
         for (int n = n1 - 1; n >= n0; --n) {
             const int m = n - n0;
-            pass(desc(BL.sa_slot + m * BL.fwd_bytes), n, kPassStressA);
+            // stress-B of step n + 1 and stress-A of step n in one pass (with two tile shapes,
+            // whose LDS planes of that pass do not fit one CU, as two passes)
+            if (merged) {
+                pass(desc(BL.sa_slot + m * BL.fwd_bytes), n, kPassStressM);
+            } else {
+                if (n + 1 < b->nt) pass(desc(BL.sb), n + 1, kPassStressB);
+                pass(desc(BL.sa_slot + m * BL.fwd_bytes), n, kPassStressA);
+            }
             pass(desc(BL.va_slot + m * BL.fwd_bytes), n, kPassVelA);
             const ShotInject<T> *idesc = (const ShotInject<T> *)(bws + BL.inj_slot + m * BL.inj_bytes);
             for (int q = 0; q < ncol; ++q)
                 if (cbase[q] > 0)
                     inject_residual_multi<T><<<(8 * cbase[q] + 255) / 256, 256, 0, st>>>(idesc, S, q, cbase[q], b->nt, n);
-            pass(desc(BL.sb), n, kPassStressB);
         }
     }
+    pass(desc(BL.sb), 0, kPassStressB);  // stress-B of step 0
     // chain rule per shot, in shot order (shots may share the output arrays)
     for (int s = 0; s < S; ++s) {
         fd3d_ctx *c = b->ctx[s];

@@ -224,26 +224,25 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
 // adjoint velocity of the step after, held as Y'), then at the own sample the buoyancy
 // gradient's share g_b -= v^{n+1/2} rho_eff dt D_S(X) and Y = b G_v A_v, written over Y'
 // (A_v itself is not stored).  For the stress-type body, kAdjA: gradients of C from
-// E(v^{n+1/2}) and T = G_s A_s, X = C T; kAdjB: A_s <- G_s A_s - dt E(Y).  The adjoint
-// modes read and write the arrays named by the grid (f[] pointing at the adjoint, stored
-// or scratch fields) and by TileIO.  The Born
+// E(v^{n+1/2}) and T = G_s A_s, X = C T; kAdjB: A_s <- G_s A_s - dt E(Y); kAdjM: kAdjB of
+// the step after (Y of that step in io.y) then kAdjA of this step, in one sweep (the
+// updated A_s is stored and feeds T directly).  The adjoint modes read and write the
+// arrays named by the grid (f[] pointing at the adjoint, stored or scratch fields) and by
+// TileIO.  The Born
 // (tangent-linear) modes use the derivatives the background's own passes compute: kBornV
 // is the background's forward velocity update plus dt db (D_S sigma) + db c s added to
 // the perturbation's velocity in io.out[0..2] (db = -b^2 drho_eff, drho in io.acc[0]);
 // kBornS is the background's forward stress update plus dt (dC E v) added to the
 // perturbation's stress in io.out[0..5] (dlam, dmu in io.acc[0], io.acc[1]; no damping,
 // no source).
-enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3, kBornV = 4, kBornS = 5 };
+enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3, kBornV = 4, kBornS = 5, kAdjM = 6 };
 
 // Sweep direction of each pass (true: upward, decreasing k), chosen so that a pass starts
 // where the pass before it ended and finds those planes still in the last-level cache:
-// forward velocity down, stress up; adjoint stress-A down, velocity-A up, stress-B up.
-// With three adjoint passes per step one hand-over starts cold: stress-B starts at the
-// bottom, away from where velocity-A ended, and ends at the top where the next step's
-// stress-A begins (stress-B writes the six adjoint stresses that stress-A reads next;
-// velocity-A hands stress-B only Y).  A pass that sweeps up also takes its tiles in
-// reverse order, so that when the tiles run in several rounds its first round covers the
-// last round of the pass before.
+// forward velocity down, stress up; adjoint stress-M (and stress-A) down, velocity-A up;
+// the adjoint's closing stress-B up, after the last velocity-A.  A pass that sweeps up
+// also takes its tiles in reverse order, so that when the tiles run in several rounds its
+// first round covers the last round of the pass before.
 template <int MODE> constexpr bool vel_sweeps_up() { return MODE == kAdjA; }
 template <int MODE> constexpr bool stress_sweeps_up() { return MODE == kFwd || MODE == kAdjB || MODE == kBornS; }
 
@@ -269,6 +268,7 @@ template <typename T> struct TileIO {
                 // velocity-A's (g_bx, g_by, g_bz); or the Born model perturbation (drho;
                 // dlam, dmu)
     const T *vst[3];  // velocity-A: stored v^{n+1/2}
+    const T *y[3];    // stress-M: Y of the step after
 };
 
 // Source coefficients of NC consecutive components starting at C0, staged in LDS when a
@@ -604,7 +604,10 @@ template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false
 __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0,
                                                  int k0, int k1, const TileIO<T> &io = TileIO<T>{})
 {
-    static_assert(MODE == kFwd || MODE == kAdjA || MODE == kAdjB || MODE == kBornS, "stress-type modes");
+    static_assert(MODE == kFwd || MODE == kAdjA || MODE == kAdjB || MODE == kAdjM || MODE == kBornS,
+                  "stress-type modes");
+    constexpr bool adjm = MODE == kAdjM;
+    static_assert(!adjm || (!FS && !VAC && !CM), "stress-M: damped boundaries, node medium");
     static_assert(!CM || MODE == kFwd, "the coarse medium is read by the forward passes only");
     constexpr int NT = TX * TY;
     // vx x(-2,+1) y(-1,+2); vy x(-1,+2) y(-2,+1); vz x(-1,+2) y(-1,+2); mu x(+1) y(+1) corner
@@ -613,6 +616,9 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     __shared__ T s_vx[2][NV + 1];
     __shared__ T s_vy[2][NV + 1];
     __shared__ T s_vz[2][NV + 1];
+    __shared__ T s_yx[2][adjm ? NV + 1 : 1];  // stress-M: Y, with the halos of v
+    __shared__ T s_yy[2][adjm ? NV + 1 : 1];
+    __shared__ T s_yz[2][adjm ? NV + 1 : 1];
     __shared__ T s_mu[3][NM + 1];
     constexpr bool bsf = MODE == kBornS;
     __shared__ T s_dmu[3][bsf ? NM + 1 : 1];  // dmu ring of the Born stress term
@@ -683,6 +689,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     // arithmetic per sample in both directions
     constexpr bool up = stress_sweeps_up<MODE>();
     static_assert(!bsf || up, "the Born stress mode sweeps upward");
+    static_assert(!adjm || !up, "stress-M sweeps downward");
     const int kfirst = up ? k1 - 1 : k0;
 
     const Window w = window<T>(k0, k1, nz, sz);
@@ -690,16 +697,23 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
 
     // z queues: vx, vy at k-1..k+2; vz at k-2..k+1 (zero above k = 0: never used with FS)
     T qvx[4], qvy[4], qvz[4];
+    T qyx[4] = {}, qyy[4] = {}, qyz[4] = {};  // stress-M: the same queues of Y
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         qvx[m] = zld(fvx, kfirst - 1 + m, true);
         qvy[m] = zld(fvy, kfirst - 1 + m, true);
         qvz[m] = zld(fvz, kfirst - 2 + m, true);
+        if constexpr (adjm) {
+            qyx[m] = zld(io.y[0], kfirst - 1 + m, true);
+            qyy[m] = zld(io.y[1], kfirst - 1 + m, true);
+            qyz[m] = zld(io.y[2], kfirst - 2 + m, true);
+        }
     }
     T m1 = (up || CM) ? T(0) : zld(mu, k0 + 1, use_model);  // own mu one plane below (downward sweep)
 
     struct Plane {
         T cl, cm, sxx, syy, szz, sxy, sxz, syz, hx, hy, hz, a0, a1, a2, a3, a4, dl, dm, b0, b1, b2, b3, b4, b5;
+        T yhx, yhy, yhz;  // stress-M: halo samples of Y
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const unsigned pk = wplane(w, kk, ok), o = oc + pk, om_ = oc + wplane(w, kk, ok && use_model);
@@ -710,7 +724,12 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         } else {
             P.cl = P.cm = T(0);
         }
-        if constexpr (MODE == kAdjA) {
+        if constexpr (adjm) {
+            P.yhx = ld<T>(wfield(io.y[0], w), hvx.off + pk);
+            P.yhy = ld<T>(wfield(io.y[1], w), hvy.off + pk);
+            P.yhz = ld<T>(wfield(io.y[2], w), hvz.off + pk);
+        }
+        if constexpr (MODE == kAdjA || adjm) {
             P.a0 = ld<T>(wfield(io.acc[0], w), o);
             P.a1 = ld<T>(wfield(io.acc[1], w), o);
             P.a2 = ld<T>(wfield(io.acc[2], w), o);
@@ -779,6 +798,15 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         Lx[hvx.lds] = P.hx;
         Ly[hvy.lds] = P.hy;
         Lz[hvz.lds] = P.hz;
+        T *Yx = s_yx[adjm ? b : 0], *Yy = s_yy[adjm ? b : 0], *Yz = s_yz[adjm ? b : 0];
+        if constexpr (adjm) {
+            Yx[ovx] = qyx[1];
+            Yy[ovy] = qyy[1];
+            Yz[ovz] = qyz[2];
+            Yx[hvx.lds] = P.yhx;
+            Yy[hvy.lds] = P.yhy;
+            Yz[hvz.lds] = P.yhz;
+        }
         if constexpr (CM) {
             // the coarse samples replace the ring
         } else if constexpr (up) {  // mu plane k enters the ring (plane k + 1 is there)
@@ -830,6 +858,12 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         loadplane(kn, more, P);
         const T nvx = zld(fvx, up ? k - 2 : k + 3, more), nvy = zld(fvy, up ? k - 2 : k + 3, more);
         const T nvz = zld(fvz, up ? k - 3 : k + 2, more);
+        T nyx = T(0), nyy = T(0), nyz = T(0);
+        if constexpr (adjm) {
+            nyx = zld(io.y[0], k + 3, more);
+            nyy = zld(io.y[1], k + 3, more);
+            nyz = zld(io.y[2], k + 2, more);
+        }
         const T nm1 = (up || CM) ? T(0) : zld(mu, k + 2, more && use_model);
         const T nhm = CM ? T(0) : loadmu(up ? k - 1 : k + 2, more);
         const T nhdm = bsf ? loaddmu(k - 1, more) : T(0);
@@ -897,16 +931,42 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
                 st(wfield(io.out[4], w), o_stxz + pw, b_xz + dt * dxz * exz);
                 st(wfield(io.out[5], w), o_styz + pw, b_yz + dt * dyz * eyz);
             }
-        } else if constexpr (MODE == kAdjA) {
+        } else if constexpr (MODE == kAdjA || adjm) {
+            // stress-M: first the adjoint stress update of the step after, A_s <- G_s A_s -
+            // dt E(Y), stored, and taken as this step's A_s below
+            T s_xx = o_xx, s_yy = o_yy, s_zz = o_zz, s_xy = o_xy, s_xz = o_xz, s_yz = o_yz;
+            if constexpr (adjm) {
+                const T yxx = dstag(Yx[ovx], Yx[ovx - 1], Yx[ovx + 1], Yx[ovx - 2], rdx);
+                const T yyy = dstag(Yy[ovy], Yy[ovy - W3], Yy[ovy + W3], Yy[ovy - 2 * W3], rdy);
+                const T yzz = dz_or_o2(false, qyz[2], qyz[1], qyz[3], qyz[0], rdz);
+                const T yxy = dstag(Yx[ovx + W3], Yx[ovx], Yx[ovx + 2 * W3], Yx[ovx - W3], rdy)
+                            + dstag(Yy[ovy + 1], Yy[ovy], Yy[ovy + 2], Yy[ovy - 1], rdx);
+                const T yxz = dz_or_o2(false, qyx[2], qyx[1], qyx[3], qyx[0], rdz)
+                            + dstag(Yz[ovz + 1], Yz[ovz], Yz[ovz + 2], Yz[ovz - 1], rdx);
+                const T yyz = dz_or_o2(false, qyy[2], qyy[1], qyy[3], qyy[0], rdz)
+                            + dstag(Yz[ovz + W3], Yz[ovz], Yz[ovz + 2 * W3], Yz[ovz - W3], rdy);
+                s_xx = gn * o_xx - dt * yxx;
+                s_yy = gn * o_yy - dt * yyy;
+                s_zz = gn * o_zz - dt * yzz;
+                s_xy = g_xy * o_xy - dt * yxy;
+                s_xz = g_xz * o_xz - dt * yxz;
+                s_yz = g_yz * o_yz - dt * yyz;
+                st(wfield(G.f[SXX], w), oc + pw, s_xx);
+                st(wfield(G.f[SYY], w), oc + pw, s_yy);
+                st(wfield(G.f[SZZ], w), oc + pw, s_zz);
+                st(wfield(G.f[SXY], w), st_xy + pw, s_xy);
+                st(wfield(G.f[SXZ], w), o_stxz + pw, s_xz);
+                st(wfield(G.f[SYZ], w), o_styz + pw, s_yz);
+            }
             // gradients of C and X = C T with T = G_s A_s
-            const T txx = gn * o_xx, tyy = gn * o_yy, tzz = gn * o_zz;
+            const T txx = gn * s_xx, tyy = gn * s_yy, tzz = gn * s_zz;
             const T trT = (txx + tyy) + tzz;
             st(wfield(io.acc[0], w), oc + pw, a0 + dt * ((exx + eyy) + ezz) * trT);
             st(wfield(io.acc[1], w), oc + pw, a1 + dt * T(2) * ((exx * txx + eyy * tyy) + ezz * tzz));
             st(wfield(io.out[0], w), oc + pw, l * trT + T(2) * mm * txx);
             st(wfield(io.out[1], w), oc + pw, l * trT + T(2) * mm * tyy);
             st(wfield(io.out[2], w), oc + pw, l * trT + T(2) * mm * tzz);
-            const T txy = g_xy * o_xy, txz = g_xz * o_xz, tyz = g_yz * o_yz;
+            const T txy = g_xy * s_xy, txz = g_xz * s_xz, tyz = g_yz * s_yz;
             st(wfield(io.acc[2], w), st_xy + pw, a2 + dt * exy * txy);
             st(wfield(io.acc[3], w), o_stxz + pw, a3 + dt * exz * txz);
             st(wfield(io.acc[4], w), o_styz + pw, a4 + dt * eyz * tyz);
@@ -933,6 +993,11 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             qvx[0] = qvx[1]; qvx[1] = qvx[2]; qvx[2] = qvx[3]; qvx[3] = nvx;
             qvy[0] = qvy[1]; qvy[1] = qvy[2]; qvy[2] = qvy[3]; qvy[3] = nvy;
             qvz[0] = qvz[1]; qvz[1] = qvz[2]; qvz[2] = qvz[3]; qvz[3] = nvz;
+            if constexpr (adjm) {
+                qyx[0] = qyx[1]; qyx[1] = qyx[2]; qyx[2] = qyx[3]; qyx[3] = nyx;
+                qyy[0] = qyy[1]; qyy[1] = qyy[2]; qyy[2] = qyy[3]; qyy[3] = nyy;
+                qyz[0] = qyz[1]; qyz[1] = qyz[2]; qyz[2] = qyz[3]; qyz[3] = nyz;
+            }
             m1 = nm1;
         }
         hmu = nhm;

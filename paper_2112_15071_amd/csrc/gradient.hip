@@ -7,7 +7,7 @@ using namespace fd3d;
 
 namespace {
 
-// One adjoint pass of a tiled step (stress-A, velocity-A, stress-B) on the context's tile
+// One adjoint pass of a tiled step (stress-A, stress-M, velocity-A, stress-B) on the context's tile
 // shape and cache policy (the streaming policy also covers velocity-A's stored velocities).
 template <typename T>
 void launch_adj_pass(const fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int pass, hipStream_t st,
@@ -23,6 +23,10 @@ void launch_adj_pass(const fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, 
         case kPassStressA:
             if (ntp) stress_tile_adj<T, TX, TY, kAdjA, F32><<<nwg, NT, 0, st>>>(G, inj, tm, io);
             else stress_tile_adj<T, TX, TY, kAdjA, false><<<nwg, NT, 0, st>>>(G, inj, tm, io);
+            break;
+        case kPassStressM:
+            if (ntp) stress_tile_adj<T, TX, TY, kAdjM, F32><<<nwg, NT, 0, st>>>(G, inj, tm, io);
+            else stress_tile_adj<T, TX, TY, kAdjM, false><<<nwg, NT, 0, st>>>(G, inj, tm, io);
             break;
         case kPassVelA:
             if (ntp) vel_tile_adj<T, TX, TY, kAdjA, F32><<<nwg, NT, 0, st>>>(G, inj, n, tm, io);
@@ -103,12 +107,11 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
         }
         for (int n = n1 - 1; n >= n0; --n) {
             const int m = n - n0;
-            if (tiled) {
+            if (tiled) {  // stress-B of step n + 1 and stress-A of step n in one pass
                 const AdjTiles<T> P = adj_tiles<T>(G, gws, GL, m);
-                launch_adj_pass<T>(c, P.g[0], none, n, kPassStressA, st, P.io[0]);
+                launch_adj_pass<T>(c, P.g[0], none, n, kPassStressM, st, P.io[0]);
                 launch_adj_pass<T>(c, P.g[1], none, n, kPassVelA, st, P.io[1]);
                 inject(n, m);
-                launch_adj_pass<T>(c, P.g[2], none, n, kPassStressB, st, P.io[2]);
             } else {
                 set_stored_velocity(A, gws, GL, m);
                 adj_stress_cell<T><<<grd, blk, 0, st>>>(G, A);
@@ -117,7 +120,11 @@ int adjoint_impl(fd3d_ctx *c, const fd3d_source *src, int nrec, const double *re
             }
         }
     }
-    if (tiled) launch_gb_initial<T>(G, A, gws, GL, st);
+    if (tiled) {  // stress-B of step 0, then the initial velocity's term of the b gradient
+        const AdjTiles<T> P = adj_tiles<T>(G, gws, GL, 0);
+        launch_adj_pass<T>(c, P.g[2], none, 0, kPassStressB, st, P.io[2]);
+        launch_gb_initial<T>(G, A, gws, GL, st);
+    }
     grad_finalize<T><<<grd, blk, 0, st>>>(G, A, g_lam, g_mu, g_rho);
     HIP_TRY(hipGetLastError());
     return FD3D_OK;

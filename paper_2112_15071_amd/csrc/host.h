@@ -274,11 +274,13 @@ template <typename T, typename F> decltype(auto) with_tile(int tx, int ty, F &&f
 
 // Passes of a step.  Forward: velocity, stress.  Adjoint step (reverse order of the
 // forward step): stress-A (C gradients, X = C G_s A_s), velocity-A (A_v update, b
-// gradient, Y = G_v A_v / rho_eff), stress-B (A_s update from Y).  The velocity pass also
+// gradient, Y = G_v A_v / rho_eff), stress-B (A_s update from Y); the tiled adjoint runs
+// stress-B of step n+1 and stress-A of step n as one pass, stress-M, and a last stress-B
+// after step 0.  The velocity pass also
 // comes in a variant for the gradient's segment recompute: the tile kernels write
 // v^{n+1/2} through the grid's save pointers instead of over v^{n-1/2}, the cell kernel
 // writes it to both.
-enum Pass { kPassVel = 0, kPassStress = 1, kPassStressA, kPassVelA, kPassStressB, kPassVelSave };
+enum Pass { kPassVel = 0, kPassStress = 1, kPassStressA, kPassVelA, kPassStressB, kPassVelSave, kPassStressM };
 
 // Tile and fused sweeps address a window of at most zchunk + 8 planes (and at most the
 // grid's nz) through one buffer descriptor per field, of at most 1 GiB.
@@ -418,7 +420,7 @@ template <typename T> void set_stored_velocity(AdjGrid<T> &A, char *gws, const G
 // tile outputs.  The tiled adjoint holds Y = G_v A_v / rho_eff (intermediate fields 6-8)
 // in place of A_v.
 template <typename T> struct AdjTiles {
-    Grid<T> g[3];     // stress-A, velocity-A, stress-B
+    Grid<T> g[3];     // stress-A (or stress-M), velocity-A, stress-B
     TileIO<T> io[3];
 };
 
@@ -438,6 +440,7 @@ template <typename T> AdjTiles<T> adj_tiles(const Grid<T> &G, char *gws, const G
         P.g[2].f[VX + q] = fld(GL.scr, 6 + q);
         P.io[1].acc[q] = fld(GL.acc, 5 + q);              // g_b
         P.io[1].vst[q] = (const T *)(slot + q * GL.fstep);
+        P.io[0].y[q] = fld(GL.scr, 6 + q);                // Y of the step after (stress-M)
     }
     for (int q = 0; q < 6; ++q) {
         P.g[0].f[SXX + q] = fld(GL.adj, SXX + q);  // A_s
