@@ -79,6 +79,9 @@ GRAD_BYTES_PER_CELL_STEP = 120 + 120 + 4 * (36 + 22)
 # the design figure with eight staggered-point accumulators and no hand-over fields
 # between the adjoint passes (forward 120 + recompute 120 + adjoint 232)
 GRAD_BYTES_DESIGN = 120 + 120 + 232
+# the same adjoint with a recompute that also stores sigma^n (156: the form whose buoyancy
+# gradient reads D_S sigma^n), the usual figure for a checkpointed elastic adjoint
+GRAD_BYTES_SIGMA_STORED = 120 + 156 + 232
 # measured counter calibration (plain 1 GiB copy): FETCH_SIZE reads 0.5x, WRITE_SIZE 1.0x
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
@@ -696,7 +699,9 @@ def bench_gradient(wave=None, nshots=8):
                           "batched_frac": frac(b_sps, bytes_shot), "loop_frac": frac(loop_sps, bytes_shot),
                           "design_bytes_per_cell_step": GRAD_BYTES_DESIGN,
                           "batched_frac_at_design_bytes": frac(b_sps, design_shot),
-                          "roofline_shots_per_s_at_design_bytes": round(HBM_PEAK_GBS * 1e9 / design_shot, 4)})
+                          "roofline_shots_per_s_at_design_bytes": round(HBM_PEAK_GBS * 1e9 / design_shot, 4),
+                          "sigma_stored_bytes_per_cell_step": GRAD_BYTES_SIGMA_STORED,
+                          "batched_frac_at_sigma_stored_bytes": frac(b_sps, GRAD_BYTES_SIGMA_STORED * cells * nt)})
 
 
 def counters_run(kernels, K, grad=False):
