@@ -145,6 +145,42 @@ def test_dot_product(dtype, tol):
     sim.close()
 
 
+@pytest.mark.parametrize("kernel", [("tile", 4, 8, 64), ("cell", 4, 8, 64)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 2e-4), (torch.float64, 1e-10)])
+def test_gradient_from_a_given_initial_state(kernel, dtype, tol):
+    """The forward starts from a random state (the cell adjoint's buoyancy term takes
+    v^{-1/2} in its first step, the tiled adjoint's sum by parts a term of its own in it);
+    a random residual; the model gradient against the oracle's store-all adjoint started
+    from the same state."""
+    from paper_2112_15071_amd import Simulator
+
+    shape, nt = (18, 16, 14), 40
+    rng = np.random.default_rng(41)
+    lam, mu, rho = W.elastic_from_vp(3000.0 * (1 + 0.2 * rng.random((14, 16, 18))))
+    rho = rho * (1 + 0.1 * rng.random(rho.shape))
+    x0 = random_state(shape, rng)
+    rec = np.array([[4.2, 5.5, 6.1], [12.7, 9.3, 3.3], [8.0, 8.0, 8.0], [8.3, 8.6, 8.1]])
+    pos, mom = (9.3, 7.6, 6.4), W.explosion(1e14)
+    wav = W.ricker(30.0, nt, DT)
+    sponge = (4, 5, 3, 4, 5, 3)
+    r = rng.standard_normal((rec.shape[0], 3, nt))
+    cfg = oracle.Config(shape, H, DT, nt, sponge=sponge)
+    ref = oracle.gradient(cfg, lam, mu, rho, oracle.Source(pos, moment=mom), wav, rec, r, state0=x0)[:3]
+    sim = Simulator(lam, mu, rho, H, DT, nt, dtype=dtype, sponge=sponge)
+    sim.set_kernel(*kernel)
+    sim.set_state(torch.as_tensor(x0, dtype=dtype))
+    gws = sim.grad_workspace(9)
+    src = dict(src_pos=pos, moment=mom, wavelet=wav, rec_pos=rec)
+    sim.forward_ckpt(gws, keep_state=True, **src)
+    g = [torch.zeros((14, 16, 18), dtype=dtype, device="cuda") for _ in range(3)]
+    sim.adjoint(gws, torch.as_tensor(r, dtype=dtype), *g, **src)
+    torch.cuda.synchronize()
+    sim.close()
+    for p in range(3):
+        err = rel_l2(g[p].double().cpu().numpy(), ref[p])
+        assert err <= tol, (p, err)
+
+
 def test_fused_forward_gives_the_same_gradient(case):
     """The fused kernel (double-buffered state) in the checkpointed forward, with the tile
     kernels of the same tile shape in the recompute and the adjoint: bitwise the gradient
