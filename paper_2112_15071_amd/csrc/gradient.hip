@@ -7,8 +7,9 @@ using namespace fd3d;
 
 namespace {
 
-// One adjoint pass of a tiled step (stress-A, stress-M, velocity-A, stress-B) on the context's tile
-// shape and cache policy (the streaming policy also covers velocity-A's stored velocities).
+// One adjoint pass of a tiled step (stress-A, stress-M, velocity-A, stress-B) on the
+// context's tile shape and cache policy (the streaming policy also covers the stored
+// velocities).
 template <typename T>
 void launch_adj_pass(const fd3d_ctx *c, const Grid<T> &G, const Inject<T> &inj, int n, int pass, hipStream_t st,
                      const TileIO<T> &io)

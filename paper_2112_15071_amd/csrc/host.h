@@ -276,10 +276,9 @@ template <typename T, typename F> decltype(auto) with_tile(int tx, int ty, F &&f
 // forward step): stress-A (C gradients, X = C G_s A_s), velocity-A (A_v update, b
 // gradient, Y = G_v A_v / rho_eff), stress-B (A_s update from Y); the tiled adjoint runs
 // stress-B of step n+1 and stress-A of step n as one pass, stress-M, and a last stress-B
-// after step 0.  The velocity pass also
-// comes in a variant for the gradient's segment recompute: the tile kernels write
-// v^{n+1/2} through the grid's save pointers instead of over v^{n-1/2}, the cell kernel
-// writes it to both.
+// after step 0.  The velocity pass also comes in a variant for the gradient's segment
+// recompute: the tile kernels write v^{n+1/2} through the grid's save pointers instead of
+// over v^{n-1/2}, the cell kernel writes it to both.
 enum Pass { kPassVel = 0, kPassStress = 1, kPassStressA, kPassVelA, kPassStressB, kPassVelSave, kPassStressM };
 
 // Tile and fused sweeps address a window of at most zchunk + 8 planes (and at most the
@@ -334,7 +333,9 @@ bool fused_supported(const fd3d_ctx *c, int tx, int ty);
 
 // Gradient workspace (byte offsets): adjoint state, staggered-point gradient
 // accumulators, the tiled adjoint's intermediate fields, checkpoints every k steps, the
-// stored velocities of one k-step segment, and the residual buffer of fd3d_gradient.
+// stored velocities of one k-step segment, a copy of the segment's checkpoint (the cell
+// adjoint's v^{n-1/2} of the segment's first step), and the residual buffer of
+// fd3d_gradient.
 // Every group of fields has the layout of the context's state (one block of interleaved
 // rows, or padded arrays): field q of a group at q * fstep.
 struct GradLayout {
@@ -346,7 +347,7 @@ struct GradLayout {
     size_t scr;     // 9 fields: X = C G_s A_s (6, stress layout), Y = G_v A_v / rho_eff (3)
     size_t ckpt;    // nseg groups: state at the start of steps 0, k, 2k, ...
     size_t seg;     // ceil(k/3) groups: v^{n+1/2} of three steps of a segment per group
-    size_t prev;    // one group: a copy of the segment's checkpoint (its v^{n-1/2} for the first step)
+    size_t prev;    // one group: a copy of the segment's checkpoint (cell adjoint)
     size_t res;     // residual [max_rec][3][nt]
     size_t misfit;  // one T
     size_t total;
