@@ -60,15 +60,17 @@ class BatchSimulator:
         best["per_shape"] = {f"{k[0]}": v for k, v in seen.items()}
         return best
 
-    # (tile_x, tile_y, zchunk) configurations the batched-gradient tuner tries
-    GRADIENT_CANDIDATES = ((256, 4, 64), (256, 4, 128), (128, 8, 64), (128, 4, 64), (128, 4, 128), (64, 16, 64),
-                           (64, 8, 32))
+    # (tile_x, tile_y, zchunk) configurations the batched-gradient tuner tries; zchunk 0:
+    # each shot's whole depth (with several shots per launch, whole-depth sweeps can fill
+    # the chip where one shot's cannot)
+    GRADIENT_CANDIDATES = ((256, 4, 64), (256, 4, 128), (256, 4, 0), (128, 8, 64), (128, 4, 64), (128, 4, 128),
+                           (64, 16, 64), (64, 8, 32))
 
     @staticmethod
     def _set_zchunk(sims, zc: int) -> None:
         for sim in sims:
             k = sim.kernel()
-            sim.set_kernel(k["variant"], k["tile_y"], zc, k["tile_x"])
+            sim.set_kernel(k["variant"], k["tile_y"], zc if zc > 0 else sim.shape[2], k["tile_x"])
 
     def autotune_gradient(self, shots: List[Dict], steps: int = 40, ckpt_every: int = 20, candidates=None) -> dict:
         """Pick the tile shape and z chunk of the batched gradient: times the batched
@@ -111,8 +113,8 @@ class BatchSimulator:
         best = min(times, key=times.get)
         self.set_kernel(best[0], best[1])
         BatchSimulator._set_zchunk(self.sims, best[2])
-        return dict(tile=[best[0], best[1]], zchunk=best[2], ms_per_step=times[best],
-                    tried={f"{x}x{y},{z}": round(v, 4) for (x, y, z), v in times.items()})
+        return dict(tile=[best[0], best[1]], zchunk=self.sims[0].kernel()["zchunk"], ms_per_step=times[best],
+                    tried={f"{x}x{y},{z if z else 'nz'}": round(v, 4) for (x, y, z), v in times.items()})
 
     def forward(self, shots: List[Dict], use_graph: bool = True, keep_state: bool = False,
                 traces: List[torch.Tensor] = None) -> List[torch.Tensor]:
