@@ -247,8 +247,8 @@ class Simulator:
         return dict(e, cached=False)
 
     # kernel configurations the gradient tuner tries (variant, tile_x, tile_y, zchunk)
-    GRADIENT_CANDIDATES = (("tile", 256, 4, 64), ("tile", 256, 4, 128), ("tile", 128, 4, 64), ("tile", 128, 4, 128),
-                           ("tile", 128, 8, 64), ("tile", 64, 16, 64), ("tile", 64, 8, 32))
+    GRADIENT_CANDIDATES = (("tile", 256, 4, 64), ("tile", 256, 4, 128), ("tile", 256, 4, 0), ("tile", 128, 4, 64),
+                           ("tile", 128, 4, 128), ("tile", 128, 8, 64), ("tile", 64, 16, 64), ("tile", 64, 8, 32))
 
     def like(self, nt: int) -> "Simulator":
         """A new context over the same model arrays, spacing and options, with nt steps and
@@ -267,8 +267,8 @@ class Simulator:
         """Pick the kernel configuration for gradients of this grid: times fd3d_gradient over
         ``steps`` steps (checkpoints every ``ckpt_every``, zero observed data, ``shot``'s
         source and receivers with its wavelet cut to ``steps``) on a scratch context over the
-        same model for every candidate (variant, tile_x, tile_y, zchunk), and sets the fastest
-        here.  The forward tuner (``autotune``) times the forward passes only; the adjoint
+        same model for every candidate (variant, tile_x, tile_y, zchunk; zchunk 0: the whole
+        depth), and sets the fastest here.  The forward tuner (``autotune``) times the forward passes only; the adjoint
         passes move more fields per cell and can rank tile shapes differently."""
         import time
 
@@ -284,7 +284,7 @@ class Simulator:
         for c in cands:
             variant, tx, ty, zc = c
             try:
-                scratch.set_kernel(variant, ty, zc, tx)
+                scratch.set_kernel(variant, ty, zc if zc > 0 else self.shape[2], tx)
             except _abi.FD3DError:
                 continue  # not built for this dtype or too deep a window for this grid
             scratch.gradient(gws, d_obs, *g, **args)
@@ -297,9 +297,9 @@ class Simulator:
         if not times:
             raise RuntimeError("no gradient kernel candidate runs on this grid")
         best = min(times, key=times.get)
-        self.set_kernel(best[0], best[2], best[3], best[1])
+        self.set_kernel(best[0], best[2], best[3] if best[3] > 0 else self.shape[2], best[1])
         return dict(self.kernel(), ms_per_step=times[best],
-                    tried={f"{v},{x},{y},{z}": round(t, 4) for (v, x, y, z), t in times.items()})
+                    tried={f"{v},{x},{y},{z if z else 'nz'}": round(t, 4) for (v, x, y, z), t in times.items()})
 
     def info(self):
         """(vp_max, vs_min, rho_min, dt_max) read back at creation."""
