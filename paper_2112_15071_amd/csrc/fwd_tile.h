@@ -199,6 +199,14 @@ __device__ __forceinline__ Slot cslot(bool mine, int i0, int j0, int nx, int ny,
     return s;
 }
 
+// Whether any lane of the wave holds a halo slot of a field (wave-uniform): waves without
+// one skip that field's halo load and LDS store (the halo threads are the first and the
+// last ones of the workgroup, so most waves hold none of the x-halo slots).
+__device__ __forceinline__ bool wave_holds(const Slot &s, int dummy)
+{
+    return __builtin_amdgcn_ballot_w64(s.lds != dummy) != 0;
+}
+
 // The halo slot of a field that this thread actually holds, when the x-halo threads (the
 // last ones), the y-halo threads (the first ones) and the corner thread are disjoint,
 // which holds for every supported tile shape (3 TX + 3 TY < TX TY).
@@ -328,6 +336,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                                   yslot<T, TX, TY, 0, 1, 0, WR>(tid, i0, j0, nx, ny, sy, NR), NR),
                            cslot<T, TX, TY>(tid == NT / 2, i0, j0, nx, ny, sy, NR), NR);
     const int own_c3 = ty * W3;  // row base in the x-halo planes without y halo
+    const bool wxx = wave_holds(hxx, NXX), wxy = wave_holds(hxy, NXY), wxz = wave_holds(hxz, NXZ);
+    const bool wyy = wave_holds(hyy, NYY), wyz = wave_holds(hyz, NYZ), wr = wave_holds(hr, NR);
 
     const T *fxx = G.f[SXX], *fyy = G.f[SYY], *fzz = G.f[SZZ];
     const T *fxy = G.f[SXY], *fxz = G.f[SXZ], *fyz = G.f[SYZ];
@@ -422,16 +432,19 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         P.vx = ld<T>(wfield(G.f[VX], w), o);
         P.vy = ld<T>(wfield(G.f[VY], w), o);
         P.vz = ld<T>(wfield(G.f[VZ], w), o);
-        P.xx = ld<T>(bxx, hxx.off + pk);
-        P.xy = ld<T>(bxy, hxy.off + pk);
-        P.xz = ld<T>(bxz, hxz.off + pk);
-        P.yy = ld<T>(byy, hyy.off + pk);
-        P.yz = ld<T>(byz, hyz.off + pk);
-        if constexpr (!CM) P.r = ldm<NTP, T>(br, hr.off + pr);
-        else P.r = T(0);
-        if constexpr (born) P.dr = ld<T>(wfield(io.acc[0], w), hr.off + pr);
+        if (wxx) P.xx = ld<T>(bxx, hxx.off + pk);
+        if (wxy) P.xy = ld<T>(bxy, hxy.off + pk);
+        if (wxz) P.xz = ld<T>(bxz, hxz.off + pk);
+        if (wyy) P.yy = ld<T>(byy, hyy.off + pk);
+        if (wyz) P.yz = ld<T>(byz, hyz.off + pk);
+        if constexpr (!CM) {
+            if (wr) P.r = ldm<NTP, T>(br, hr.off + pr);
+        }
+        if constexpr (born) {
+            if (wr) P.dr = ld<T>(wfield(io.acc[0], w), hr.off + pr);
+        }
     };
-    Plane P;
+    Plane P{};
     loadplane(kfirst, true, P);
     drain_loads();
 
@@ -446,16 +459,16 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         Lyy[(ty + 1) * TX + tx] = P.cyy;
         Lyz[(ty + 2) * TX + tx] = qyz[2];
         Lr[ty * WR + tx] = r0;
-        Lxx[hxx.lds] = P.xx;
-        Lxy[hxy.lds] = P.xy;
-        Lxz[hxz.lds] = P.xz;
-        Lyy[hyy.lds] = P.yy;
-        Lyz[hyz.lds] = P.yz;
-        Lr[hr.lds] = P.r;
+        if (wxx) Lxx[hxx.lds] = P.xx;
+        if (wxy) Lxy[hxy.lds] = P.xy;
+        if (wxz) Lxz[hxz.lds] = P.xz;
+        if (wyy) Lyy[hyy.lds] = P.yy;
+        if (wyz) Lyz[hyz.lds] = P.yz;
+        if (wr) Lr[hr.lds] = P.r;
         T *Ldr = s_dr[b];
         if constexpr (born) {
             Ldr[ty * WR + tx] = dr0;
-            Ldr[hr.lds] = P.dr;
+            if (wr) Ldr[hr.lds] = P.dr;
         }
         const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
         const T bvx0 = P.dvx, bvy0 = P.dvy, bvz0 = P.dvz;  // the perturbation's velocity (kBornV)
@@ -648,6 +661,8 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     const int ovy = (ty + 2) * W3 + tx + 1;
     const int ovz = (ty + 1) * W3 + tx + 1;
     const int om = ty * WM + tx;
+    const bool wvx = wave_holds(hvx, NV), wvy = wave_holds(hvy, NV), wvz = wave_holds(hvz, NV);
+    const bool wm = wave_holds(hm, NM);
 
     const T *fvx = G.f[VX], *fvy = G.f[VY], *fvz = G.f[VZ];
     const T *mu = G.mu, *lam = G.lam;
@@ -725,9 +740,9 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             P.cl = P.cm = T(0);
         }
         if constexpr (adjm) {
-            P.yhx = ld<T>(wfield(io.y[0], w), hvx.off + pk);
-            P.yhy = ld<T>(wfield(io.y[1], w), hvy.off + pk);
-            P.yhz = ld<T>(wfield(io.y[2], w), hvz.off + pk);
+            if (wvx) P.yhx = ld<T>(wfield(io.y[0], w), hvx.off + pk);
+            if (wvy) P.yhy = ld<T>(wfield(io.y[1], w), hvy.off + pk);
+            if (wvz) P.yhz = ld<T>(wfield(io.y[2], w), hvz.off + pk);
         }
         if constexpr (MODE == kAdjA || adjm) {
             P.a0 = ld<T>(wfield(io.acc[0], w), o);
@@ -742,9 +757,9 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         P.sxy = ld<T>(wfield(G.f[SXY], w), o);
         P.sxz = ld<T>(wfield(G.f[SXZ], w), o);
         P.syz = ld<T>(wfield(G.f[SYZ], w), o);
-        P.hx = ld<T>(bx, hvx.off + pk);
-        P.hy = ld<T>(by, hvy.off + pk);
-        P.hz = ld<T>(bz, hvz.off + pk);
+        if (wvx) P.hx = ld<T>(bx, hvx.off + pk);
+        if (wvy) P.hy = ld<T>(by, hvy.off + pk);
+        if (wvz) P.hz = ld<T>(bz, hvz.off + pk);
         if constexpr (bsf) {
             P.dl = ld<T>(wfield(io.acc[0], w), om_);
             P.dm = ld<T>(wfield(io.acc[1], w), om_);
@@ -761,7 +776,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     };
     auto loaddmu = [&](int kk, bool ok) -> T { return ld<T>(wfield(io.acc[1], w), hm.off + wplane(w, kk, ok)); };
 
-    Plane P;
+    Plane P{};
     loadplane(kfirst, true, P);
     T hmu = T(0), hdmu = T(0);
     if constexpr (CM) {
@@ -770,19 +785,25 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         // mu plane k1 (below the first plane) complete; plane k1 - 1's halo one ahead
         T *M = s_mu[k1 % 3];
         M[om] = zld(mu, k1, use_model);
-        M[hm.lds] = loadmu(k1, true);
-        hmu = loadmu(k1 - 1, true);
+        if (wm) {
+            M[hm.lds] = loadmu(k1, true);
+            hmu = loadmu(k1 - 1, true);
+        }
         if constexpr (bsf) {
             T *D = s_dmu[k1 % 3];
             D[om] = zld(io.acc[1], k1, true);
-            D[hm.lds] = loaddmu(k1, true);
-            hdmu = loaddmu(k1 - 1, true);
+            if (wm) {
+                D[hm.lds] = loaddmu(k1, true);
+                hdmu = loaddmu(k1 - 1, true);
+            }
         }
     } else {
         T *M = s_mu[k0 % 3];
         M[om] = P.cm;
-        M[hm.lds] = loadmu(k0, true);
-        hmu = loadmu(k0 + 1, true);
+        if (wm) {
+            M[hm.lds] = loadmu(k0, true);
+            hmu = loadmu(k0 + 1, true);
+        }
     }
 
     drain_loads();
@@ -795,30 +816,30 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         Lx[ovx] = qvx[1];
         Ly[ovy] = qvy[1];
         Lz[ovz] = qvz[2];
-        Lx[hvx.lds] = P.hx;
-        Ly[hvy.lds] = P.hy;
-        Lz[hvz.lds] = P.hz;
+        if (wvx) Lx[hvx.lds] = P.hx;
+        if (wvy) Ly[hvy.lds] = P.hy;
+        if (wvz) Lz[hvz.lds] = P.hz;
         T *Yx = s_yx[adjm ? b : 0], *Yy = s_yy[adjm ? b : 0], *Yz = s_yz[adjm ? b : 0];
         if constexpr (adjm) {
             Yx[ovx] = qyx[1];
             Yy[ovy] = qyy[1];
             Yz[ovz] = qyz[2];
-            Yx[hvx.lds] = P.yhx;
-            Yy[hvy.lds] = P.yhy;
-            Yz[hvz.lds] = P.yhz;
+            if (wvx) Yx[hvx.lds] = P.yhx;
+            if (wvy) Yy[hvy.lds] = P.yhy;
+            if (wvz) Yz[hvz.lds] = P.yhz;
         }
         if constexpr (CM) {
             // the coarse samples replace the ring
         } else if constexpr (up) {  // mu plane k enters the ring (plane k + 1 is there)
             M0[om] = P.cm;
-            M0[hm.lds] = hmu;
+            if (wm) M0[hm.lds] = hmu;
             if constexpr (bsf) {
                 D0[om] = P.dm;
-                D0[hm.lds] = hdmu;
+                if (wm) D0[hm.lds] = hdmu;
             }
         } else {  // mu plane k + 1 enters the ring (plane k is there)
             M1[om] = m1;
-            M1[hm.lds] = hmu;
+            if (wm) M1[hm.lds] = hmu;
         }
         T l = P.cl, mm = P.cm;
         // coarse medium samples of this plane (loads issued before the next plane's)
@@ -865,8 +886,9 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             nyz = zld(io.y[2], k + 2, more);
         }
         const T nm1 = (up || CM) ? T(0) : zld(mu, k + 2, more && use_model);
-        const T nhm = CM ? T(0) : loadmu(up ? k - 1 : k + 2, more);
-        const T nhdm = bsf ? loaddmu(k - 1, more) : T(0);
+        T nhm = T(0), nhdm = T(0);
+        if (!CM && wm) nhm = loadmu(up ? k - 1 : k + 2, more);
+        if (bsf && wm) nhdm = loaddmu(k - 1, more);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         // second order next to a vacuum surface: ezz at integer k, dz vx / dz vy at k + 1/2
         const bool vzo = VAC && o2_int(sp.n, k), vxo = VAC && o2_half(sp.x, k), vyo = VAC && o2_half(sp.y, k);
