@@ -10,7 +10,7 @@ using namespace fd3d;
 namespace {
 
 // rec: receiver sampling carried by a forward stress launch (extra workgroups).
-// NTP: cache policy of the model loads and stored states (see stream_model).
+// NTP: cache policy of the model loads and the gradient's stored data (see stream_model).
 template <typename T, int TX, int TY, bool FS, bool NTP>
 void launch_tiles(const Grid<T> &G, const Inject<T> &inj, int n, const TileMap &tm, int pass, hipStream_t st,
                   const RecJob<T> &rec)

@@ -92,15 +92,16 @@ __device__ __forceinline__ double bload(rsrc_t r, unsigned off, double)
 }
 template <typename T> __device__ __forceinline__ T ld(rsrc_t r, unsigned off) { return bload(r, off, T(0)); }
 
-// Loads of the model arrays and stores of the gradient's recompute under a cache policy
-// chosen per launch (NTP, see stream_model on the host): with NTP they carry the
-// non-temporal bit (nt = 2 on gfx950).  The model arrays are read by one pass per step
-// each, and the recompute's (sigma^n, v^{n+1/2}) only by the adjoint, many steps later;
-// on grids whose working set exceeds the 256 MB Infinity Cache, streaming them leaves
-// more of it to the fields the next pass reads (256^3 forward 43.6-43.9 -> 44.7-45.0
-// Gcell-steps/s, stress pass 0.213 -> 0.204 ms; gradient -3.6 % per shot).  On grids that
-// fit, or when the shots of a batch share one model, the plain policy keeps the model
-// cached between uses.
+// Loads of the model arrays, and the gradient's stored velocities and accumulators, under
+// a cache policy chosen per launch (NTP, see stream_model on the host): with NTP they
+// carry the non-temporal bit (nt = 2 on gfx950).  The model arrays are read by one pass
+// per step each, the recompute's v^{n+1/2} only by the adjoint, many steps later, and an
+// accumulator by one pass per step; on grids whose working set exceeds the 256 MB
+// Infinity Cache, streaming them leaves more of it to the fields the next pass reads
+// (256^3 forward 43.6-43.9 -> 44.7-45.0 Gcell-steps/s, stress pass 0.213 -> 0.204 ms;
+// gradient -3.6 % per shot; the stored velocities' and accumulators' stores and loads a
+// further -3.2 %).  On grids that fit, or when the shots of a batch share one model, the
+// plain policy keeps the model cached between uses.
 template <int AUX> __device__ __forceinline__ float bload_p(rsrc_t r, unsigned off, float)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
@@ -423,7 +424,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 P.s[c] = ldm<NTP, T>(wfield(io.vst[c], w), o);
-                P.gb[c] = ld<T>(wfield(io.acc[c], w), o);
+                P.gb[c] = ldm<NTP, T>(wfield(io.acc[c], w), o);
             }
         }
         P.cxx = ld<T>(bxx, o);
@@ -523,7 +524,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const T re = (ra + rb) * T(0.5);
             const T dd = dt * d;
             st(oy, so, (g * (y0 * re - dd)) * buoy(ra, rb));
-            st(wfield(io.acc[c], w), so, gb0[c] - (st0[c] * re) * dd);
+            stm<NTP>(wfield(io.acc[c], w), so, gb0[c] - (st0[c] * re) * dd);
         };
         {
             const int o = own_c3 + tx + 1;
@@ -536,7 +537,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 T v = vx0 + dt * bb * d;
                 if (srcv) v += bb * cf(VX, tap_of(src, VX, i, j, k)) * s;
                 v = v * (gxh * gyi * gz_i);
-                st(MODE == kFwdSave ? wfield(G.save[VX], w) : ovx, st_vx + pw, v);
+                if constexpr (MODE == kFwdSave) stm<NTP>(wfield(G.save[VX], w), st_vx + pw, v);
+                else st(ovx, st_vx + pw, v);
             }
             if constexpr (born) {
                 const T bb = buoy(r0, Lr[ty * WR + tx + 1]);
@@ -558,7 +560,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 T v = vy0 + dt * bb * d;
                 if (srcv) v += bb * cf(VY, tap_of(src, VY, i, j, k)) * s;
                 v = v * (gxi * gyh * gz_i);
-                st(MODE == kFwdSave ? wfield(G.save[VY], w) : ovy, st_vy + pw, v);
+                if constexpr (MODE == kFwdSave) stm<NTP>(wfield(G.save[VY], w), st_vy + pw, v);
+                else st(ovy, st_vy + pw, v);
             }
             if constexpr (born) {
                 const T bb = buoy(r0, Lr[(ty + 1) * WR + tx]);
@@ -581,7 +584,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 T v = vz0 + dt * bb * d;
                 if (srcv) v += bb * cf(VZ, tap_of(src, VZ, i, j, k)) * s;
                 v = v * (gxi * gyi * gz_h);
-                st(MODE == kFwdSave ? wfield(G.save[VZ], w) : ovz, st_vz + pw, v);
+                if constexpr (MODE == kFwdSave) stm<NTP>(wfield(G.save[VZ], w), st_vz + pw, v);
+                else st(ovz, st_vz + pw, v);
             }
             if constexpr (born) {
                 const T bb = buoy(r0, r1);
@@ -745,11 +749,11 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             if (wvz) P.yhz = ld<T>(wfield(io.y[2], w), hvz.off + pk);
         }
         if constexpr (MODE == kAdjA || adjm) {
-            P.a0 = ld<T>(wfield(io.acc[0], w), o);
-            P.a1 = ld<T>(wfield(io.acc[1], w), o);
-            P.a2 = ld<T>(wfield(io.acc[2], w), o);
-            P.a3 = ld<T>(wfield(io.acc[3], w), o);
-            P.a4 = ld<T>(wfield(io.acc[4], w), o);
+            P.a0 = ldm<NTP, T>(wfield(io.acc[0], w), o);
+            P.a1 = ldm<NTP, T>(wfield(io.acc[1], w), o);
+            P.a2 = ldm<NTP, T>(wfield(io.acc[2], w), o);
+            P.a3 = ldm<NTP, T>(wfield(io.acc[3], w), o);
+            P.a4 = ldm<NTP, T>(wfield(io.acc[4], w), o);
         }
         P.sxx = ld<T>(wfield(G.f[SXX], w), o);
         P.syy = ld<T>(wfield(G.f[SYY], w), o);
@@ -983,15 +987,15 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             // gradients of C and X = C T with T = G_s A_s
             const T txx = gn * s_xx, tyy = gn * s_yy, tzz = gn * s_zz;
             const T trT = (txx + tyy) + tzz;
-            st(wfield(io.acc[0], w), oc + pw, a0 + dt * ((exx + eyy) + ezz) * trT);
-            st(wfield(io.acc[1], w), oc + pw, a1 + dt * T(2) * ((exx * txx + eyy * tyy) + ezz * tzz));
+            stm<NTP>(wfield(io.acc[0], w), oc + pw, a0 + dt * ((exx + eyy) + ezz) * trT);
+            stm<NTP>(wfield(io.acc[1], w), oc + pw, a1 + dt * T(2) * ((exx * txx + eyy * tyy) + ezz * tzz));
             st(wfield(io.out[0], w), oc + pw, l * trT + T(2) * mm * txx);
             st(wfield(io.out[1], w), oc + pw, l * trT + T(2) * mm * tyy);
             st(wfield(io.out[2], w), oc + pw, l * trT + T(2) * mm * tzz);
             const T txy = g_xy * s_xy, txz = g_xz * s_xz, tyz = g_yz * s_yz;
-            st(wfield(io.acc[2], w), st_xy + pw, a2 + dt * exy * txy);
-            st(wfield(io.acc[3], w), o_stxz + pw, a3 + dt * exz * txz);
-            st(wfield(io.acc[4], w), o_styz + pw, a4 + dt * eyz * tyz);
+            stm<NTP>(wfield(io.acc[2], w), st_xy + pw, a2 + dt * exy * txy);
+            stm<NTP>(wfield(io.acc[3], w), o_stxz + pw, a3 + dt * exz * txz);
+            stm<NTP>(wfield(io.acc[4], w), o_styz + pw, a4 + dt * eyz * tyz);
             const T mxy = CM ? cmu_xy : ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
             const T mxz = CM ? cmu_xz : ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
             const T myz = CM ? cmu_yz : ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);

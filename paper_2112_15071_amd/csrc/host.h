@@ -290,9 +290,10 @@ inline bool window_ok(const fd3d_ctx *c, int zc)
 }
 
 // Cache policy of a context's single-grid tile launches: the model arrays and the
-// gradient's stored states are streamed (non-temporal) when the grid's working set, nine
-// fields and three model arrays, exceeds the 256 MB Infinity Cache.  Below that the whole
-// working set can stay cached from step to step, and streaming would evict the model.
+// gradient's stored velocities and accumulators are streamed (non-temporal) when the
+// grid's working set, nine fields and three model arrays, exceeds the 256 MB Infinity
+// Cache.  Below that the whole working set can stay cached from step to step, and
+// streaming would evict the model.
 constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
 inline bool stream_model(const fd3d_ctx *c)
 {
