@@ -199,16 +199,21 @@ int launch_multi(const BatchGroup &gr, const ShotFwd<T> *d, int n, int pass, hip
             return FD3D_OK;
         }
     }
+    // the gradient's passes stream its per-shot data (stored velocities, accumulators) and
+    // keep the model, which the shots share, under the plain policy
+    constexpr int NTD = sizeof(T) == 4 ? 2 : 0;
     switch (pass) {
     case kPassVel: vel_tile_multi<T, TX, TY, TX2, TY2, FS><<<g, NT, 0, st>>>(d, S, W, n); break;
     case kPassStress: stress_tile_multi<T, TX, TY, TX2, TY2, FS><<<gs, NT, 0, st>>>(d, S, W, n, rec); break;
-    case kPassVelSave: vel_tile_multi<T, TX, TY, TX2, TY2, FS, kFwdSave><<<g, NT, 0, st>>>(d, S, W, n); break;
-    case kPassStressA: stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n, none); break;
+    case kPassVelSave: vel_tile_multi<T, TX, TY, TX2, TY2, FS, kFwdSave, false, NTD><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassStressA:
+        stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA, false, NTD><<<g, NT, 0, st>>>(d, S, W, n, none);
+        break;
     case kPassStressM:  // one tile shape only: two shapes' LDS planes of this pass exceed a CU's LDS
-        if constexpr (TX2 == 0) stress_tile_multi<T, TX, TY, 0, 0, false, kAdjM><<<g, NT, 0, st>>>(d, S, W, n, none);
+        if constexpr (TX2 == 0) stress_tile_multi<T, TX, TY, 0, 0, false, kAdjM, false, NTD><<<g, NT, 0, st>>>(d, S, W, n, none);
         else return fail(FD3D_EINVAL, "stress-M batches take one tile shape");
         break;
-    case kPassVelA: vel_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA><<<g, NT, 0, st>>>(d, S, W, n); break;
+    case kPassVelA: vel_tile_multi<T, TX, TY, TX2, TY2, false, kAdjA, false, NTD><<<g, NT, 0, st>>>(d, S, W, n); break;
     default: stress_tile_multi<T, TX, TY, TX2, TY2, false, kAdjB><<<g, NT, 0, st>>>(d, S, W, n, none); break;
     }
     return FD3D_OK;

@@ -93,15 +93,17 @@ __device__ __forceinline__ double bload(rsrc_t r, unsigned off, double)
 template <typename T> __device__ __forceinline__ T ld(rsrc_t r, unsigned off) { return bload(r, off, T(0)); }
 
 // Loads of the model arrays, and the gradient's stored velocities and accumulators, under
-// a cache policy chosen per launch (NTP, see stream_model on the host): with NTP they
-// carry the non-temporal bit (nt = 2 on gfx950).  The model arrays are read by one pass
-// per step each, the recompute's v^{n+1/2} only by the adjoint, many steps later, and an
-// accumulator by one pass per step; on grids whose working set exceeds the 256 MB
-// Infinity Cache, streaming them leaves more of it to the fields the next pass reads
-// (256^3 forward 43.6-43.9 -> 44.7-45.0 Gcell-steps/s, stress pass 0.213 -> 0.204 ms;
-// gradient -3.6 % per shot; the stored velocities' and accumulators' stores and loads a
-// further -3.2 %).  On grids that fit, or when the shots of a batch share one model, the
-// plain policy keeps the model cached between uses.
+// a cache policy chosen per launch (the NTP template argument of the tile bodies: 0 plain,
+// 1 streaming all of them, 2 streaming the gradient's data but not the model; see
+// stream_model on the host): streamed accesses carry the non-temporal bit (nt = 2 on
+// gfx950).  The model arrays are read by one pass per step each, the recompute's
+// v^{n+1/2} only by the adjoint, many steps later, and an accumulator by one pass per
+// step; on grids whose working set exceeds the 256 MB Infinity Cache, streaming them
+// leaves more of it to the fields the next pass reads (256^3 forward 43.6-43.9 ->
+// 44.7-45.0 Gcell-steps/s, stress pass 0.213 -> 0.204 ms; gradient -3.6 % per shot; the
+// stored velocities' and accumulators' stores and loads a further -3.2 %).  On grids that
+// fit the plain policy keeps the model cached between uses; batched gradient launches,
+// whose shots share one model, stream the gradient's data only (-2.9 % per shot).
 template <int AUX> __device__ __forceinline__ float bload_p(rsrc_t r, unsigned off, float)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
@@ -295,7 +297,7 @@ __device__ __forceinline__ void stage_coef(T *lds, const Inject<T> &src, bool on
 // CM (forward only): the medium is a coarse node grid read by trilinear samples at the
 // velocity samples' own positions (CoarseAxis); the node density plane and queue are not
 // read.
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false, bool CM = false>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, int NTP = 0, bool CM = false>
 __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0, int k0,
                                               int k1, const TileIO<T> &io = TileIO<T>{})
 {
@@ -383,8 +385,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     }
     T r0 = T(0), r1 = T(0);
     if constexpr (!CM) {
-        r0 = ldm<NTP, T>(wfield(rho, w), oc + wplane(w, kfirst, use_rho));
-        r1 = ldm<NTP, T>(wfield(rho, w), oc + wplane(w, kfirst + 1, use_rho));
+        r0 = ldm<NTP == 1, T>(wfield(rho, w), oc + wplane(w, kfirst, use_rho));
+        r1 = ldm<NTP == 1, T>(wfield(rho, w), oc + wplane(w, kfirst + 1, use_rho));
     }
     // coarse medium: per-column coarse coordinates of the vx (i + 1/2, j), vy (i, j + 1/2)
     // and vz (i, j) columns, and the bilinear density samples of the coarse planes that
@@ -423,8 +425,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         if constexpr (adj) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                P.s[c] = ldm<NTP, T>(wfield(io.vst[c], w), o);
-                P.gb[c] = ldm<NTP, T>(wfield(io.acc[c], w), o);
+                P.s[c] = ldm<NTP != 0, T>(wfield(io.vst[c], w), o);
+                P.gb[c] = ldm<NTP != 0, T>(wfield(io.acc[c], w), o);
             }
         }
         P.cxx = ld<T>(bxx, o);
@@ -439,7 +441,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         if (wyy) P.yy = ld<T>(byy, hyy.off + pk);
         if (wyz) P.yz = ld<T>(byz, hyz.off + pk);
         if constexpr (!CM) {
-            if (wr) P.r = ldm<NTP, T>(br, hr.off + pr);
+            if (wr) P.r = ldm<NTP == 1, T>(br, hr.off + pr);
         }
         if constexpr (born) {
             if (wr) P.dr = ld<T>(wfield(io.acc[0], w), hr.off + pr);
@@ -507,7 +509,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         loadplane(up ? k - 1 : k + 1, more, P);
         const T nxz = zld(fxz, up ? k - 3 : k + 2, more), nyz = zld(fyz, up ? k - 3 : k + 2, more);
         const T nzz = zld(fzz, up ? k - 2 : k + 3, more);
-        const T nr = CM ? T(0) : ldm<NTP, T>(wfield(rho, w), oc + wplane(w, up ? k - 1 : k + 2, more && use_rho));
+        const T nr = CM ? T(0) : ldm<NTP == 1, T>(wfield(rho, w), oc + wplane(w, up ? k - 1 : k + 2, more && use_rho));
         const T ndr = born ? zld(io.acc[0], up ? k - 1 : k + 2, more) : T(0);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         // second order next to a vacuum surface: vx, vy at integer k, vz at k + 1/2 (only in
@@ -524,7 +526,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             const T re = (ra + rb) * T(0.5);
             const T dd = dt * d;
             st(oy, so, (g * (y0 * re - dd)) * buoy(ra, rb));
-            stm<NTP>(wfield(io.acc[c], w), so, gb0[c] - (st0[c] * re) * dd);
+            stm<NTP != 0>(wfield(io.acc[c], w), so, gb0[c] - (st0[c] * re) * dd);
         };
         {
             const int o = own_c3 + tx + 1;
@@ -537,7 +539,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 T v = vx0 + dt * bb * d;
                 if (srcv) v += bb * cf(VX, tap_of(src, VX, i, j, k)) * s;
                 v = v * (gxh * gyi * gz_i);
-                if constexpr (MODE == kFwdSave) stm<NTP>(wfield(G.save[VX], w), st_vx + pw, v);
+                if constexpr (MODE == kFwdSave) stm<NTP != 0>(wfield(G.save[VX], w), st_vx + pw, v);
                 else st(ovx, st_vx + pw, v);
             }
             if constexpr (born) {
@@ -560,7 +562,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 T v = vy0 + dt * bb * d;
                 if (srcv) v += bb * cf(VY, tap_of(src, VY, i, j, k)) * s;
                 v = v * (gxi * gyh * gz_i);
-                if constexpr (MODE == kFwdSave) stm<NTP>(wfield(G.save[VY], w), st_vy + pw, v);
+                if constexpr (MODE == kFwdSave) stm<NTP != 0>(wfield(G.save[VY], w), st_vy + pw, v);
                 else st(ovy, st_vy + pw, v);
             }
             if constexpr (born) {
@@ -584,7 +586,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 T v = vz0 + dt * bb * d;
                 if (srcv) v += bb * cf(VZ, tap_of(src, VZ, i, j, k)) * s;
                 v = v * (gxi * gyi * gz_h);
-                if constexpr (MODE == kFwdSave) stm<NTP>(wfield(G.save[VZ], w), st_vz + pw, v);
+                if constexpr (MODE == kFwdSave) stm<NTP != 0>(wfield(G.save[VZ], w), st_vz + pw, v);
                 else st(ovz, st_vz + pw, v);
             }
             if constexpr (born) {
@@ -617,7 +619,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 // CM (forward only): lambda, mu at the node and mu at the shear samples are trilinear
 // samples of a coarse medium at each sample's own position (CoarseAxis); the node
 // arrays, their halo and the mu ring are not read.
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false, bool CM = false>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, int NTP = 0, bool CM = false>
 __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0,
                                                  int k0, int k1, const TileIO<T> &io = TileIO<T>{})
 {
@@ -738,8 +740,8 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         const unsigned pk = wplane(w, kk, ok), o = oc + pk, om_ = oc + wplane(w, kk, ok && use_model);
         const rsrc_t bx = wfield(fvx, w), by = wfield(fvy, w), bz = wfield(fvz, w);
         if constexpr (!CM) {
-            P.cl = ldm<NTP, T>(wfield(lam, w), om_);
-            P.cm = ldm<NTP, T>(wfield(mu, w), om_);
+            P.cl = ldm<NTP == 1, T>(wfield(lam, w), om_);
+            P.cm = ldm<NTP == 1, T>(wfield(mu, w), om_);
         } else {
             P.cl = P.cm = T(0);
         }
@@ -749,11 +751,11 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             if (wvz) P.yhz = ld<T>(wfield(io.y[2], w), hvz.off + pk);
         }
         if constexpr (MODE == kAdjA || adjm) {
-            P.a0 = ldm<NTP, T>(wfield(io.acc[0], w), o);
-            P.a1 = ldm<NTP, T>(wfield(io.acc[1], w), o);
-            P.a2 = ldm<NTP, T>(wfield(io.acc[2], w), o);
-            P.a3 = ldm<NTP, T>(wfield(io.acc[3], w), o);
-            P.a4 = ldm<NTP, T>(wfield(io.acc[4], w), o);
+            P.a0 = ldm<NTP != 0, T>(wfield(io.acc[0], w), o);
+            P.a1 = ldm<NTP != 0, T>(wfield(io.acc[1], w), o);
+            P.a2 = ldm<NTP != 0, T>(wfield(io.acc[2], w), o);
+            P.a3 = ldm<NTP != 0, T>(wfield(io.acc[3], w), o);
+            P.a4 = ldm<NTP != 0, T>(wfield(io.acc[4], w), o);
         }
         P.sxx = ld<T>(wfield(G.f[SXX], w), o);
         P.syy = ld<T>(wfield(G.f[SYY], w), o);
@@ -776,7 +778,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         }
     };
     auto loadmu = [&](int kk, bool ok) -> T {
-        return ldm<NTP, T>(wfield(mu, w), hm.off + wplane(w, kk, ok && use_model));
+        return ldm<NTP == 1, T>(wfield(mu, w), hm.off + wplane(w, kk, ok && use_model));
     };
     auto loaddmu = [&](int kk, bool ok) -> T { return ld<T>(wfield(io.acc[1], w), hm.off + wplane(w, kk, ok)); };
 
@@ -987,15 +989,15 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             // gradients of C and X = C T with T = G_s A_s
             const T txx = gn * s_xx, tyy = gn * s_yy, tzz = gn * s_zz;
             const T trT = (txx + tyy) + tzz;
-            stm<NTP>(wfield(io.acc[0], w), oc + pw, a0 + dt * ((exx + eyy) + ezz) * trT);
-            stm<NTP>(wfield(io.acc[1], w), oc + pw, a1 + dt * T(2) * ((exx * txx + eyy * tyy) + ezz * tzz));
+            stm<NTP != 0>(wfield(io.acc[0], w), oc + pw, a0 + dt * ((exx + eyy) + ezz) * trT);
+            stm<NTP != 0>(wfield(io.acc[1], w), oc + pw, a1 + dt * T(2) * ((exx * txx + eyy * tyy) + ezz * tzz));
             st(wfield(io.out[0], w), oc + pw, l * trT + T(2) * mm * txx);
             st(wfield(io.out[1], w), oc + pw, l * trT + T(2) * mm * tyy);
             st(wfield(io.out[2], w), oc + pw, l * trT + T(2) * mm * tzz);
             const T txy = g_xy * s_xy, txz = g_xz * s_xz, tyz = g_yz * s_yz;
-            stm<NTP>(wfield(io.acc[2], w), st_xy + pw, a2 + dt * exy * txy);
-            stm<NTP>(wfield(io.acc[3], w), o_stxz + pw, a3 + dt * exz * txz);
-            stm<NTP>(wfield(io.acc[4], w), o_styz + pw, a4 + dt * eyz * tyz);
+            stm<NTP != 0>(wfield(io.acc[2], w), st_xy + pw, a2 + dt * exy * txy);
+            stm<NTP != 0>(wfield(io.acc[3], w), o_stxz + pw, a3 + dt * exz * txz);
+            stm<NTP != 0>(wfield(io.acc[4], w), o_styz + pw, a4 + dt * eyz * tyz);
             const T mxy = CM ? cmu_xy : ((M0[om] + M0[om + 1]) + (M0[om + WM] + M0[om + WM + 1])) / T(4);
             const T mxz = CM ? cmu_xz : ((M0[om] + M0[om + 1]) + (M1[om] + M1[om + 1])) / T(4);
             const T myz = CM ? cmu_yz : ((M0[om] + M0[om + WM]) + (M1[om] + M1[om + WM])) / T(4);
@@ -1124,7 +1126,7 @@ template <typename D> constexpr int base_stride() { return (int)(sizeof(D) / siz
 // A batch may use a second tile shape with the same workgroup size (TX2 x TY2, 0: none)
 // for the shots whose descriptor sets `alt`, so that grids of different widths all get a
 // tile shape that covers them without idle columns.
-template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false>
+template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd, bool VAC = false, int NTP = 0>
 __global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
                                                           int n)
 {
@@ -1158,7 +1160,7 @@ __global__ void __launch_bounds__(TX *TY) vel_tile_multi(const ShotFwd<T> *__res
 
 // Workgroups past rec.wgs sample the receivers of the step (the stress pass only reads
 // the velocity).
-template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd, bool VAC = false, bool NTP = false>
+template <typename T, int TX, int TY, int TX2, int TY2, bool FS, int MODE = kFwd, bool VAC = false, int NTP = 0>
 __global__ void __launch_bounds__(TX *TY) stress_tile_multi(const ShotFwd<T> *__restrict__ shots, int nshot, int total,
                                                           int n, RecMulti<T> rec)
 {
