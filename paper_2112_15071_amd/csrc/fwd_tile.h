@@ -339,8 +339,10 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                                   yslot<T, TX, TY, 0, 1, 0, WR>(tid, i0, j0, nx, ny, sy, NR), NR),
                            cslot<T, TX, TY>(tid == NT / 2, i0, j0, nx, ny, sy, NR), NR);
     const int own_c3 = ty * W3;  // row base in the x-halo planes without y halo
-    const bool wxx = wave_holds(hxx, NXX), wxy = wave_holds(hxy, NXY), wxz = wave_holds(hxz, NXZ);
-    const bool wyy = wave_holds(hyy, NYY), wyz = wave_holds(hyz, NYZ), wr = wave_holds(hr, NR);
+    // (the coarse-medium instantiations issue every halo access: their own branches make
+    // the skip cost more than it saves)
+    const bool wxx = CM || wave_holds(hxx, NXX), wxy = CM || wave_holds(hxy, NXY), wxz = CM || wave_holds(hxz, NXZ);
+    const bool wyy = CM || wave_holds(hyy, NYY), wyz = CM || wave_holds(hyz, NYZ), wr = CM || wave_holds(hr, NR);
 
     const T *fxx = G.f[SXX], *fyy = G.f[SYY], *fzz = G.f[SZZ];
     const T *fxy = G.f[SXY], *fxz = G.f[SXZ], *fyz = G.f[SYZ];
@@ -667,8 +669,8 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     const int ovy = (ty + 2) * W3 + tx + 1;
     const int ovz = (ty + 1) * W3 + tx + 1;
     const int om = ty * WM + tx;
-    const bool wvx = wave_holds(hvx, NV), wvy = wave_holds(hvy, NV), wvz = wave_holds(hvz, NV);
-    const bool wm = wave_holds(hm, NM);
+    const bool wvx = CM || wave_holds(hvx, NV), wvy = CM || wave_holds(hvy, NV), wvz = CM || wave_holds(hvz, NV);
+    const bool wm = CM || wave_holds(hm, NM);
 
     const T *fvx = G.f[VX], *fvy = G.f[VY], *fvz = G.f[VZ];
     const T *mu = G.mu, *lam = G.lam;
