@@ -204,13 +204,16 @@ int fd3d_get_layout(const fd3d_ctx *ctx, int *layout);
  * given to fd3d_create (chain rule through the Sec. 2.2.1 means).  The forward state is
  * checkpointed every ckpt_every steps; the reverse sweep restores a checkpoint,
  * recomputes its segment while storing v^{n+1/2} per step, then runs the adjoint steps
- * of the segment backwards (the buoyancy gradient takes each step's increment from the
- * stored v^{n+1/2} and v^{n-1/2}).  Damped boundaries only (FD3D_EINVAL with the free
- * surface).  The gradient workspace gws is caller-owned device memory, 256-byte aligned:
- * groups of nine fields in the context's field layout (adjoint state, gradient
- * accumulators, intermediate fields, one per checkpoint -- ceil(nt / ckpt_every) --, the
- * velocities of a segment, three steps per group -- ceil(ckpt_every / 3) --, and a copy of
- * the segment's checkpoint) plus a residual buffer.
+ * of the segment backwards.  The buoyancy gradient of the one-thread-per-cell kernels
+ * takes each step's increment from the stored v^{n+1/2} and v^{n-1/2}; the tile kernels
+ * sum the same terms by parts over the steps, from v^{n+1/2} alone, plus one term of the
+ * initial velocity after step 0 (equal up to rounding).  Damped boundaries only
+ * (FD3D_EINVAL with the free surface).  The gradient workspace gws is caller-owned
+ * device memory, 256-byte aligned: groups of nine fields in the context's field layout
+ * (adjoint state, gradient accumulators, intermediate fields, one per checkpoint --
+ * ceil(nt / ckpt_every) --, the velocities of a segment, three steps per group --
+ * ceil(ckpt_every / 3) --, and a copy of the segment's checkpoint, which only the
+ * one-thread-per-cell kernels read) plus a residual buffer.
  */
 
 /* Bytes of gradient workspace for checkpoints every ckpt_every steps (1 <= k <= nt). */
