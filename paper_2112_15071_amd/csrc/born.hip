@@ -60,7 +60,9 @@ int born_impl(fd3d_ctx *c, fd3d_ctx *dc, const fd3d_source *src, const void *dla
     if (tiled) {
         // each source term in the background's pass that computes its derivatives (the Born
         // modes of the tile bodies), then the perturbation's own pass; the stress launches
-        // sample the receivers
+        // sample the receivers.  The four passes alternate their sweep direction (background
+        // velocity up, perturbation velocity down, background stress up, perturbation stress
+        // down), so that each starts on the planes the one before it left in the cache.
         TileIO<T> iovf, iosf;
         std::memset(&iovf, 0, sizeof iovf);
         std::memset(&iosf, 0, sizeof iosf);
@@ -70,6 +72,10 @@ int born_impl(fd3d_ctx *c, fd3d_ctx *dc, const fd3d_source *src, const void *dla
         iosf.acc[0] = (T *)dlam;
         iosf.acc[1] = (T *)dmu;
         const bool ntp = sizeof(T) == 4 && stream_model(c);  // cache policy, as in launch_pass
+        const bool dtiled = dc->variant == FD3D_KERNEL_TILE;
+        const TileMap dtm = tile_map(dc);
+        const int dnwg = dtm.ntx * dtm.nty * dtm.nzc;
+        const bool dntp = sizeof(T) == 4 && stream_model(dc);
         for (int n = 0; n < c->nt; ++n) {
             with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
                 constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
@@ -83,7 +89,16 @@ int born_impl(fd3d_ctx *c, fd3d_ctx *dc, const fd3d_source *src, const void *dla
                 if (ntp) stress_tile_born<T, TX, TY, sizeof(T) == 4><<<nb, TX * TY, 0, st>>>(G, inj, n, tm, iosf, recg);
                 else stress_tile_born<T, TX, TY><<<nb, TX * TY, 0, st>>>(G, inj, n, tm, iosf, recg);
             });
-            launch_pass<T, false>(dc, D, dinj, n, kPassStress, st, TileIO<T>{}, recd);
+            if (!dtiled) {
+                launch_pass<T, false>(dc, D, dinj, n, kPassStress, st, TileIO<T>{}, recd);
+                continue;
+            }
+            with_tile<T>(dc->tile_x, dc->tile_y, [&](auto tx, auto ty) {
+                constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
+                const int nb = dnwg + rec_blocks(recd, TX * TY);
+                if (dntp) stress_tile_down<T, TX, TY, sizeof(T) == 4><<<nb, TX * TY, 0, st>>>(D, dinj, n, dtm, recd);
+                else stress_tile_down<T, TX, TY><<<nb, TX * TY, 0, st>>>(D, dinj, n, dtm, recd);
+            });
         }
         HIP_TRY(hipGetLastError());
         return FD3D_OK;

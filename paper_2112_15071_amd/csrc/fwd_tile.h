@@ -251,10 +251,12 @@ enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3, kBornV = 4, kBornS = 5, kAd
 // Sweep direction of each pass (true: upward, decreasing k), chosen so that a pass starts
 // where the pass before it ended and finds those planes still in the last-level cache:
 // forward velocity down, stress up; adjoint stress-M (and stress-A) down, velocity-A up;
-// the adjoint's closing stress-B up, after the last velocity-A.  A pass that sweeps up
-// also takes its tiles in reverse order, so that when the tiles run in several rounds its
-// first round covers the last round of the pass before.
-template <int MODE> constexpr bool vel_sweeps_up() { return MODE == kAdjA; }
+// the adjoint's closing stress-B up, after the last velocity-A; in the Born step the
+// background's velocity (kBornV) up, the perturbation's velocity down, the background's
+// stress (kBornS) up and the perturbation's stress down (stress_tile_down).  A pass that
+// sweeps up also takes its tiles in reverse order, so that when the tiles run in several
+// rounds its first round covers the last round of the pass before.
+template <int MODE> constexpr bool vel_sweeps_up() { return MODE == kAdjA || MODE == kBornV; }
 template <int MODE> constexpr bool stress_sweeps_up() { return MODE == kFwd || MODE == kAdjB || MODE == kBornS; }
 
 // Waits for every outstanding memory operation of the wave (s_waitcnt with all counters
@@ -621,7 +623,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 // CM (forward only): lambda, mu at the node and mu at the shear samples are trilinear
 // samples of a coarse medium at each sample's own position (CoarseAxis); the node
 // arrays, their halo and the mu ring are not read.
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, int NTP = 0, bool CM = false>
+// REV: the forward pass swept downward (damped boundaries, node medium).
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, int NTP = 0, bool CM = false,
+          bool REV = false>
 __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0,
                                                  int k0, int k1, const TileIO<T> &io = TileIO<T>{})
 {
@@ -710,7 +714,8 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     // upward for the forward passes and stress-B (see stress_sweeps_up); the z queues shift
     // the other way and the mu ring takes the new plane at the other end, with the same
     // arithmetic per sample in both directions
-    constexpr bool up = stress_sweeps_up<MODE>();
+    static_assert(!REV || (MODE == kFwd && !FS && !VAC && !CM), "downward forward stress: damped, node medium");
+    constexpr bool up = stress_sweeps_up<MODE>() != REV;
     static_assert(!bsf || up, "the Born stress mode sweeps upward");
     static_assert(!adjm || !up, "stress-M sweeps downward");
     const int kfirst = up ? k1 - 1 : k0;
@@ -1059,6 +1064,23 @@ __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, 
     int i0, j0, k0, k1;
     tile_coords(tm, tile_of(blockIdx.x, nwg, stress_sweeps_up<MODE>()), i0, j0, k0, k1, TX, TY, G.nz);
     stress_tile_body<T, TX, TY, FS, MODE, VAC, NTP, CM>(G, src, n, i0, j0, k0, k1);
+}
+
+// The forward stress pass swept downward, for the perturbation's stress pass of the Born
+// step (after the background's upward one); otherwise as stress_tile (no free surface, no
+// vacuum surface, node medium).
+template <typename T, int TX, int TY, bool NTP = false>
+__global__ void __launch_bounds__(TX *TY) stress_tile_down(Grid<T> G, Inject<T> src, int n, TileMap tm, RecJob<T> rec)
+{
+    const int nwg = tm.ntx * tm.nty * tm.nzc;
+    if ((int)blockIdx.x >= nwg) {
+        const int q = ((int)blockIdx.x - nwg) * (TX * TY) + (int)threadIdx.x;
+        if (q < rec.nq) sample_receiver(rec, q, n);
+        return;
+    }
+    int i0, j0, k0, k1;
+    tile_coords(tm, tile_of(blockIdx.x, nwg, false), i0, j0, k0, k1, TX, TY, G.nz);
+    stress_tile_body<T, TX, TY, false, kFwd, false, NTP, false, true>(G, src, n, i0, j0, k0, k1);
 }
 
 // Born stress pass (kBornS): the background's stress update and the perturbation's
