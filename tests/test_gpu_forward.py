@@ -180,12 +180,13 @@ def c2_ref():
     return shot, oracle_run(shot)
 
 
-@pytest.mark.parametrize("dtype,kern", [(torch.float32, ("tile", 4, 128, 256)), (torch.float64, None),
-                                        (torch.float32, ("fused", 8, 64))])
+@pytest.mark.parametrize("dtype,kern", [(torch.float32, ("tile", 4, 256, 256)), (torch.float32, ("tile", 4, 128, 256)),
+                                        (torch.float64, None), (torch.float32, ("fused", 8, 64))])
 def test_c2_full_size_truncated(c2_ref, dtype, kern):
     """512x512x256 with the free surface and the 30-cell sponge, 8 steps, the workload's
     1024 surface receivers plus 52 around the deep source: the benchmark's kernel (256 x 4
-    tiles, 128-plane sweeps), FP64, and the fused variant."""
+    tiles, whole-depth 256-plane sweeps over separate arrays), 128-plane sweeps, FP64, and
+    the fused variant."""
     shot, ref = c2_ref
     print(f"[c2] gpu 512x512x256 x {C2_NT} {dtype} {kern}", flush=True)
     got = gpu_run(shot, dtype, kernel=kern)

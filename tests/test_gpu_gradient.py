@@ -341,11 +341,12 @@ def test_anisotropic_gradient_matches_oracle(dtype, tol):
 
 def test_full_size_gradient_truncated():
     """The 256^3 FWI gradient workload (smoothed starting model, explosions at z = 24,
-    16 x 16 receivers at z = 22, 20-cell sponge) in the benchmark's launch configuration
-    (256 x 4 tiles, 64-plane sweeps), truncated to 12 steps with checkpoints every 5 (two
-    whole segments and a partial one).  The Ricker is centred at 3 ms so that the source
-    acts inside the window.  Shot 0 against the oracle's store-all adjoint over the whole
-    grid; two shots batched equal to the per-shot loop bitwise."""
+    16 x 16 receivers at z = 22, 20-cell sponge) in the benchmark's launch configurations
+    (per-shot loop: 256 x 4 tiles, 64-plane sweeps; batched: 256 x 4 tiles, whole-depth
+    sweeps), truncated to 12 steps with checkpoints every 5 (two whole segments and a
+    partial one).  The Ricker is centred at 3 ms so that the source acts inside the window.
+    Shot 0 against the oracle's store-all adjoint over the whole grid; two shots batched,
+    with whole-depth and with 64-plane sweeps, equal to the per-shot loop bitwise."""
     from paper_2112_15071_amd import Simulator
     from paper_2112_15071_amd.batch import BatchSimulator
 
@@ -380,18 +381,20 @@ def test_full_size_gradient_truncated():
         err = rel_l2(g_loop[0][p].double().cpu().numpy(), g_ref[p])
         assert err <= 2e-4, (p, err)
 
-    print("[grad-full] gpu batched, 2 shots", flush=True)
-    sims = [Simulator(*model, h, dt, nt, dtype=torch.float32, sponge=shots[0].sponge) for _ in shots]
-    for x in sims:
-        x.set_kernel("tile", 4, 64, 256)
-    batch = BatchSimulator(sims)
-    batch.set_kernel(256, 4)
-    g_b = [[torch.zeros_like(model[0]) for _ in range(3)] for _ in shots]
-    batch.gradient(descs, obs, *[[g[p] for g in g_b] for p in range(3)], ckpt_every=k)
-    torch.cuda.synchronize()
-    batch.close()
-    for x in sims:
-        x.close()
-    for s in range(len(shots)):
-        for p in range(3):
-            assert torch.equal(g_b[s][p], g_loop[s][p]), (s, p)
+    for zc in (model[0].shape[0], 64):
+        print(f"[grad-full] gpu batched, 2 shots, tile 256x4, {zc} planes", flush=True)
+        sims = [Simulator(*model, h, dt, nt, dtype=torch.float32, sponge=shots[0].sponge) for _ in shots]
+        for x in sims:
+            x.set_kernel("tile", 4, zc, 256)
+        batch = BatchSimulator(sims)
+        batch.set_kernel(256, 4)
+        g_b = [[torch.zeros_like(model[0]) for _ in range(3)] for _ in shots]
+        batch.gradient(descs, obs, *[[g[p] for g in g_b] for p in range(3)], ckpt_every=k)
+        torch.cuda.synchronize()
+        batch.close()
+        for x in sims:
+            x.close()
+        for s in range(len(shots)):
+            for p in range(3):
+                assert torch.equal(g_b[s][p], g_loop[s][p]), (zc, s, p)
+        del g_b
