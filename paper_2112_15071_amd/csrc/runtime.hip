@@ -493,6 +493,8 @@ int create_ctx(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const vo
     if (!rc && hipGetLastError() != hipSuccess) rc = fail(FD3D_EHIP, "launch failed in fd3d_create");
     if (!rc) rc = hipStreamSynchronize(st) == hipSuccess ? FD3D_OK : fail(FD3D_EHIP, "hipStreamSynchronize failed");
     if (rc) {
+        // uploads queued from the context's host buffers before the failure finish first
+        (void)hipStreamSynchronize(st);
         if (c->staged) (void)hipEventDestroy(c->staged);
         delete c;
         return rc;
