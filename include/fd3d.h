@@ -256,7 +256,9 @@ int fd3d_born(fd3d_ctx *ctx, fd3d_ctx *dctx, const fd3d_source *src, const void 
               void *dtraces, void *hip_stream);
 
 /* After fd3d_adjoint: the adjoint of the initial state (v^{-1/2}, sigma^0) into fields[9]
- * (device T[nz][ny][nx], order as fd3d_get_state) -- the dot-product test quantity. */
+ * (device T[nz][ny][nx], order as fd3d_get_state) -- the dot-product test quantity.
+ * FD3D_ESTATE unless an adjoint (fd3d_adjoint, fd3d_gradient or a batched gradient) has
+ * run on gws since its checkpointed forward. */
 int fd3d_get_adjoint_state(fd3d_ctx *ctx, const void *gws, void *const fields[9],
                            void *hip_stream);
 

@@ -639,6 +639,7 @@ int batch_gradient_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec,
         c->grad_ws = (const char *)gws[s];
         c->grad_k = k;
         c->grad_ready = 1;
+        c->adj_done = 1;
         c->grad_y = 1;
     }
     HIP_TRY(hipGetLastError());

@@ -202,6 +202,7 @@ int fd3d_forward_ckpt(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const dou
     const GradLayout GL = make_grad_layout(ctx, ckpt_every);
     hipStream_t st = (hipStream_t)hip_stream;
     ctx->grad_ready = 0;
+    ctx->adj_done = 0;
     rc = ctx->tsize == 8 ? forward_impl<double>(ctx, src, nrec, rec_pos, traces, flags, st, (char *)gws, &GL)
                          : forward_impl<float>(ctx, src, nrec, rec_pos, traces, flags, st, (char *)gws, &GL);
     if (rc) return rc;
@@ -225,10 +226,13 @@ int fd3d_adjoint(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double *
     const GradLayout GL = make_grad_layout(ctx, ctx->grad_k);
     hipStream_t st = (hipStream_t)hip_stream;
     if (ctx->tsize == 8)
-        return adjoint_impl<double>(ctx, src, nrec, rec_pos, (const double *)residual, (double *)g_lam,
-                                    (double *)g_mu, (double *)g_rho, (char *)gws, GL, st);
-    return adjoint_impl<float>(ctx, src, nrec, rec_pos, (const float *)residual, (float *)g_lam, (float *)g_mu,
-                               (float *)g_rho, (char *)gws, GL, st);
+        rc = adjoint_impl<double>(ctx, src, nrec, rec_pos, (const double *)residual, (double *)g_lam,
+                                  (double *)g_mu, (double *)g_rho, (char *)gws, GL, st);
+    else
+        rc = adjoint_impl<float>(ctx, src, nrec, rec_pos, (const float *)residual, (float *)g_lam, (float *)g_mu,
+                                 (float *)g_rho, (char *)gws, GL, st);
+    ctx->adj_done = rc == FD3D_OK;
+    return rc;
 }
 
 extern "C++" {
@@ -267,7 +271,8 @@ int fd3d_gradient(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double 
 int fd3d_get_adjoint_state(fd3d_ctx *ctx, const void *gws, void *const fields[9], void *hip_stream)
 {
     if (!ctx || !gws || !fields) return fail(FD3D_EINVAL, "ctx/gws/fields is NULL");
-    if (!ctx->grad_ready || gws != ctx->grad_ws) return fail(FD3D_ESTATE, "no adjoint state in this workspace");
+    if (!ctx->grad_ready || !ctx->adj_done || gws != ctx->grad_ws)
+        return fail(FD3D_ESTATE, "no adjoint state in this workspace (fd3d_adjoint has not run on it)");
     for (int f = 0; f < NFIELD; ++f)
         if (!fields[f]) return fail(FD3D_EINVAL, "field pointer is NULL");
     const GradLayout GL = make_grad_layout(ctx, ctx->grad_k);

@@ -131,7 +131,8 @@ struct fd3d_ctx {
     const char *grad_ws;
     int grad_k;
     int grad_ready;
-    int grad_y;  // the last adjoint was the tiled one: the adjoint velocity is held as Y
+    int adj_done;  // an adjoint has run on grad_ws since its checkpointed forward
+    int grad_y;    // the last adjoint was the tiled one: the adjoint velocity is held as Y
 };
 
 namespace fd3d {

@@ -458,6 +458,7 @@ int create_ctx(fd3d_ctx **out, int nx, int ny, int nz, const void *lam, const vo
     c->grad_ws = nullptr;
     c->grad_k = 0;
     c->grad_ready = 0;
+    c->adj_done = 0;
     c->grad_y = 0;
     // default tile shape by row length (measured on MI355X at 256^3: 256x4 tiles with
     // 64-plane sweeps keep one 1024-thread workgroup per CU and 1 KiB row segments)

@@ -312,6 +312,17 @@ def test_adjoint_needs_checkpoints_and_damped_top():
     with pytest.raises(FD3DError) as e:
         sim.adjoint(gws, torch.zeros((1, 3, 10)), *g, rec_pos=[[8.0, 8.0, 8.0]])
     assert e.value.code == FD3D_ESTATE
+    # the adjoint state exists only once an adjoint has run on the checkpoints
+    sim.forward_ckpt(gws, rec_pos=[[8.0, 8.0, 8.0]])
+    with pytest.raises(FD3DError) as e:
+        sim.adjoint_state(gws)
+    assert e.value.code == FD3D_ESTATE
+    sim.adjoint(gws, torch.zeros((1, 3, 10), device="cuda"), *g, rec_pos=[[8.0, 8.0, 8.0]])
+    assert sim.adjoint_state(gws).shape[0] == 9
+    sim.forward_ckpt(gws, rec_pos=[[8.0, 8.0, 8.0]])  # new checkpoints: no adjoint state again
+    with pytest.raises(FD3DError) as e:
+        sim.adjoint_state(gws)
+    assert e.value.code == FD3D_ESTATE
     sim.close()
     fs = Simulator(lam, mu, rho, H, DT, 10, free_surface=True)
     with pytest.raises(FD3DError) as e:
