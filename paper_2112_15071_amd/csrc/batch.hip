@@ -393,8 +393,12 @@ int batch_forward_impl(fd3d_batch *b, const fd3d_source *srcs, const int *nrec, 
             if (rc) return rc;
             return fail(FD3D_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
         }
+        const hipError_t ie = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(FD3D_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        }
         b->graph = g;
-        HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
         b->graph_valid = true;
         b->graph_key = (long)key;
     }
