@@ -767,8 +767,11 @@ int fd3d_batch_autotune(fd3d_batch *b, int steps, int best[6], double *best_ms, 
     int win_mib = 0;
     double win_ms = 1e300;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
         return fail(FD3D_EHIP, "hipEventCreate failed");
+    }
     b->nt = steps;
     b->group_bytes = 0;
     int rc = FD3D_OK;

@@ -290,8 +290,11 @@ int fd3d_autotune(fd3d_ctx *ctx, int steps, fd3d_kernel *best, double *best_ms, 
     fd3d_kernel win = keep;
     double win_ms = 1e300;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
         return fail(FD3D_EHIP, "hipEventCreate failed");
+    }
     ctx->nt = steps;
     int rc = FD3D_OK;
     for (const auto &sh : shapes) {
