@@ -453,12 +453,12 @@ def bench_layout_ab(K=300, reps=3):
     return out
 
 
-# Born (tangent-linear) forward, per cell and step, with the tile kernels: the background's
-# and the perturbation's forward passes (120 each), plus what the source terms add to the
-# background's passes: the velocity pass reads drho and the perturbation's velocity and
-# writes it (7 values), the stress pass reads dlam, dmu and the perturbation's stress and
-# writes it (14 values)
-BORN_BYTES_PER_CELL_STEP = 120 + 120 + 4 * (1 + 2 * 3) + 4 * (2 + 2 * 6)
+# Born (tangent-linear) forward, per cell and step, with the tile kernels: one velocity
+# sweep and one stress sweep step the background (the forward's 120) and the perturbation
+# together; the velocity sweep adds drho, the perturbation's stress read and its velocity
+# read and written (13 values), the stress sweep dlam, dmu, the perturbation's velocity
+# read and its stress read and written (17 values)
+BORN_BYTES_PER_CELL_STEP = 120 + 4 * (1 + 6 + 2 * 3) + 4 * (2 + 3 + 2 * 6)
 
 
 def bench_born(K=300):

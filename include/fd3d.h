@@ -246,11 +246,13 @@ int fd3d_gradient(fd3d_ctx *ctx, const fd3d_source *src, int nrec, const double 
  * velocity and stress passes as the background, fed before each pass by the
  * perturbation's first-order effect on the background -- dt db (D_S sigma + force term)
  * with db = -b^2 drho_eff, then dt dC E(v) with dC built from dlam, dmu (means as for C).
+ * With the tile kernels one velocity sweep and one stress sweep step both states.
  * ctx runs the background (src, traces: device T[nrec][3][nt] or NULL); dctx is a second
- * context over the same model arrays, grid, dtype, nt, dt, spacing and damping, whose
- * state holds the perturbation (dtraces: device T[nrec][3][nt]).  Both states start at
- * zero and are overwritten.  Damped boundaries only; tile or cell kernels (not fused).
- * FD3D_EINVAL when the contexts do not match. */
+ * context over the same model arrays, grid, dtype, nt, dt, spacing, damping, field layout
+ * and kernel configuration (fd3d_set_kernel), whose state holds the perturbation
+ * (dtraces: device T[nrec][3][nt]).  Both states start at zero and are overwritten.
+ * Damped boundaries only; tile or cell kernels (not fused).  FD3D_EINVAL when the
+ * contexts do not match. */
 int fd3d_born(fd3d_ctx *ctx, fd3d_ctx *dctx, const fd3d_source *src, const void *dlam,
               const void *dmu, const void *drho, int nrec, const double *rec_pos, void *traces,
               void *dtraces, void *hip_stream);

@@ -58,46 +58,34 @@ int born_impl(fd3d_ctx *c, fd3d_ctx *dc, const fd3d_source *src, const void *dla
     const RecJob<T> recd = rec_job<T>(D.f[VX], D.f[VY], D.f[VZ], dtaps, nrec, c->nt, (T *)dtraces);
     const RecJob<T> recg = rec_job<T>(G.f[VX], G.f[VY], G.f[VZ], taps, traces ? nrec : 0, c->nt, (T *)traces);
     if (tiled) {
-        // each source term in the background's pass that computes its derivatives (the Born
-        // modes of the tile bodies), then the perturbation's own pass; the stress launches
-        // sample the receivers.  The four passes alternate their sweep direction (background
-        // velocity up, perturbation velocity down, background stress up, perturbation stress
-        // down), so that each starts on the planes the one before it left in the cache.
-        TileIO<T> iovf, iosf;
-        std::memset(&iovf, 0, sizeof iovf);
-        std::memset(&iosf, 0, sizeof iosf);
-        for (int q = 0; q < 3; ++q) iovf.out[q] = D.f[VX + q];
-        iovf.acc[0] = (T *)drho;
-        for (int q = 0; q < 6; ++q) iosf.out[q] = D.f[SXX + q];
-        iosf.acc[0] = (T *)dlam;
-        iosf.acc[1] = (T *)dmu;
+        // the background and the perturbation in one velocity sweep and one stress sweep
+        // (the Born modes of the tile bodies); the stress sweep samples both receiver sets
+        TileIO<T> iov, ios;
+        std::memset(&iov, 0, sizeof iov);
+        std::memset(&ios, 0, sizeof ios);
+        for (int q = 0; q < 3; ++q) {
+            iov.out[q] = D.f[VX + q];
+            ios.pin[q] = D.f[VX + q];
+        }
+        for (int q = 0; q < 6; ++q) {
+            iov.pin[q] = D.f[SXX + q];
+            ios.out[q] = D.f[SXX + q];
+        }
+        iov.acc[0] = (T *)drho;
+        ios.acc[0] = (T *)dlam;
+        ios.acc[1] = (T *)dmu;
         const bool ntp = sizeof(T) == 4 && stream_model(c);  // cache policy, as in launch_pass
-        const bool dtiled = dc->variant == FD3D_KERNEL_TILE;
-        const TileMap dtm = tile_map(dc);
-        const int dnwg = dtm.ntx * dtm.nty * dtm.nzc;
-        const bool dntp = sizeof(T) == 4 && stream_model(dc);
         for (int n = 0; n < c->nt; ++n) {
             with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
-                constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
-                if (ntp) vel_tile_adj<T, TX, TY, kBornV, sizeof(T) == 4><<<nwg, TX * TY, 0, st>>>(G, inj, n, tm, iovf);
-                else vel_tile_adj<T, TX, TY, kBornV><<<nwg, TX * TY, 0, st>>>(G, inj, n, tm, iovf);
-            });
-            launch_pass<T, false>(dc, D, dinj, n, kPassVel, st);
-            with_tile<T>(c->tile_x, c->tile_y, [&](auto tx, auto ty) {
-                constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
-                const int nb = nwg + rec_blocks(recg, TX * TY);
-                if (ntp) stress_tile_born<T, TX, TY, sizeof(T) == 4><<<nb, TX * TY, 0, st>>>(G, inj, n, tm, iosf, recg);
-                else stress_tile_born<T, TX, TY><<<nb, TX * TY, 0, st>>>(G, inj, n, tm, iosf, recg);
-            });
-            if (!dtiled) {
-                launch_pass<T, false>(dc, D, dinj, n, kPassStress, st, TileIO<T>{}, recd);
-                continue;
-            }
-            with_tile<T>(dc->tile_x, dc->tile_y, [&](auto tx, auto ty) {
-                constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
-                const int nb = dnwg + rec_blocks(recd, TX * TY);
-                if (dntp) stress_tile_down<T, TX, TY, sizeof(T) == 4><<<nb, TX * TY, 0, st>>>(D, dinj, n, dtm, recd);
-                else stress_tile_down<T, TX, TY><<<nb, TX * TY, 0, st>>>(D, dinj, n, dtm, recd);
+                constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value, NT = TX * TY;
+                const int nb = nwg + (recg.nq + recd.nq + NT - 1) / NT;
+                if (ntp) {
+                    vel_tile_adj<T, TX, TY, kBornV, sizeof(T) == 4><<<nwg, NT, 0, st>>>(G, inj, n, tm, iov);
+                    stress_tile_born<T, TX, TY, sizeof(T) == 4><<<nb, NT, 0, st>>>(G, inj, n, tm, ios, recg, recd);
+                } else {
+                    vel_tile_adj<T, TX, TY, kBornV><<<nwg, NT, 0, st>>>(G, inj, n, tm, iov);
+                    stress_tile_born<T, TX, TY><<<nb, NT, 0, st>>>(G, inj, n, tm, ios, recg, recd);
+                }
             });
         }
         HIP_TRY(hipGetLastError());
@@ -146,6 +134,10 @@ int fd3d_born(fd3d_ctx *ctx, fd3d_ctx *dctx, const fd3d_source *src, const void 
         return fail(FD3D_EINVAL, "the Born forward needs the medium at the simulation nodes");
     if (ctx->variant == FD3D_KERNEL_FUSED || dctx->variant == FD3D_KERNEL_FUSED)
         return fail(FD3D_EINVAL, "the Born forward runs the tile or cell kernels (set one with fd3d_set_kernel)");
+    if (ctx->variant != dctx->variant ||
+        (ctx->variant == FD3D_KERNEL_TILE && (ctx->tile_x != dctx->tile_x || ctx->tile_y != dctx->tile_y ||
+                                              ctx->zchunk != dctx->zchunk)))
+        return fail(FD3D_EINVAL, "the Born forward steps both contexts with one kernel configuration");
     hipStream_t st = (hipStream_t)hip_stream;
     return ctx->tsize == 8 ? born_impl<double>(ctx, dctx, src, dlam, dmu, drho, nrec, rec_pos, traces, dtraces, st)
                            : born_impl<float>(ctx, dctx, src, dlam, dmu, drho, nrec, rec_pos, traces, dtraces, st);

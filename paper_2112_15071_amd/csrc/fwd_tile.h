@@ -240,23 +240,25 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
 // updated A_s is stored and feeds T directly).  The adjoint modes read and write the
 // arrays named by the grid (f[] pointing at the adjoint, stored or scratch fields) and by
 // TileIO.  The Born
-// (tangent-linear) modes use the derivatives the background's own passes compute: kBornV
-// is the background's forward velocity update plus dt db (D_S sigma) + db c s added to
-// the perturbation's velocity in io.out[0..2] (db = -b^2 drho_eff, drho in io.acc[0]);
-// kBornS is the background's forward stress update plus dt (dC E v) added to the
-// perturbation's stress in io.out[0..5] (dlam, dmu in io.acc[0], io.acc[1]; no damping,
-// no source).
+// (tangent-linear) modes step the background and the perturbation in one sweep: kBornV is
+// the background's forward velocity update, then the perturbation's, whose velocity
+// (io.out[0..2]) first takes the source term dt db (D_S sigma) + db c s formed from the
+// background's derivatives (db = -b^2 drho_eff, drho in io.acc[0]) and then its own
+// forward update from its stress (io.pin[0..5], staged like the background's); kBornS is
+// the background's forward stress update, then the perturbation's stress (io.out[0..5])
+// takes dt (dC E v) (dlam, dmu in io.acc[0], io.acc[1]; no damping, no source) and then
+// its own forward update from its velocity (io.pin[0..2]).  Each perturbation sample sees
+// the operations of a separate source pass followed by a forward pass, in that order.
 enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3, kBornV = 4, kBornS = 5, kAdjM = 6 };
 
 // Sweep direction of each pass (true: upward, decreasing k), chosen so that a pass starts
 // where the pass before it ended and finds those planes still in the last-level cache:
 // forward velocity down, stress up; adjoint stress-M (and stress-A) down, velocity-A up;
-// the adjoint's closing stress-B up, after the last velocity-A; in the Born step the
-// background's velocity (kBornV) up, the perturbation's velocity down, the background's
-// stress (kBornS) up and the perturbation's stress down (stress_tile_down).  A pass that
-// sweeps up also takes its tiles in reverse order, so that when the tiles run in several
-// rounds its first round covers the last round of the pass before.
-template <int MODE> constexpr bool vel_sweeps_up() { return MODE == kAdjA || MODE == kBornV; }
+// the adjoint's closing stress-B up, after the last velocity-A; Born velocity down, Born
+// stress up.  A pass that sweeps up also takes its tiles in reverse order, so that when
+// the tiles run in several rounds its first round covers the last round of the pass
+// before.
+template <int MODE> constexpr bool vel_sweeps_up() { return MODE == kAdjA; }
 template <int MODE> constexpr bool stress_sweeps_up() { return MODE == kFwd || MODE == kAdjB || MODE == kBornS; }
 
 // Waits for every outstanding memory operation of the wave (s_waitcnt with all counters
@@ -282,6 +284,8 @@ template <typename T> struct TileIO {
                 // dlam, dmu)
     const T *vst[3];  // velocity-A: stored v^{n+1/2}
     const T *y[3];    // stress-M: Y of the step after
+    const T *pin[6];  // Born: the perturbation's stress (velocity sweep) or velocity (stress
+                      // sweep), read with halos
 };
 
 // Source coefficients of NC consecutive components starting at C0, staged in LDS when a
@@ -317,7 +321,15 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     __shared__ T s_yz[2][NYZ + 1];
     __shared__ T s_r[2][NR + 1];
     constexpr bool born = MODE == kBornV;
+    static_assert(!born || (!FS && !VAC && !CM), "Born: damped boundaries, node medium");
     __shared__ T s_dr[2][born ? NR + 1 : 1];  // drho plane of the Born source term
+    // Born: the perturbation's stress planes, with the shapes and halo slots of the
+    // background's
+    __shared__ T s_pxx[2][born ? NXX + 1 : 1];
+    __shared__ T s_pxy[2][born ? NXY + 1 : 1];
+    __shared__ T s_pxz[2][born ? NXZ + 1 : 1];
+    __shared__ T s_pyy[2][born ? NYY + 1 : 1];
+    __shared__ T s_pyz[2][born ? NYZ + 1 : 1];
 
     const int nx = G.nx, ny = G.ny, nz = G.nz;
     const int sy = (int)G.sy;
@@ -349,6 +361,8 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     const T *fxx = G.f[SXX], *fyy = G.f[SYY], *fzz = G.f[SZZ];
     const T *fxy = G.f[SXY], *fxz = G.f[SXZ], *fyz = G.f[SYZ];
     const T *rho = G.rho;
+    const T *pxx = io.pin[0], *pyy = io.pin[1], *pzz = io.pin[2];  // Born: the perturbation's stress
+    const T *pxy = io.pin[3], *pxz = io.pin[4], *pyz = io.pin[5];
     const T rdx = G.rdx, rdy = G.rdy, rdz = G.rdz, dt = G.dt;
     const T s = src.on ? sload(src.wavelet, n) : T(0);
     const T gxh = in ? G.g[0][1][i] : T(0), gxi = in ? G.g[0][0][i] : T(0);
@@ -387,6 +401,15 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         const int kz = kfirst - 1 + m;
         qzz[m] = (FS && kz < 0) ? -zld(fzz, -kz, true) : zld(fzz, kz, true);
     }
+    T pqxz[4] = {}, pqyz[4] = {}, pqzz[4] = {};  // Born: the perturbation's queues
+    if constexpr (born) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            pqxz[m] = zld(pxz, kfirst - 2 + m, true);
+            pqyz[m] = zld(pyz, kfirst - 2 + m, true);
+            pqzz[m] = zld(pzz, kfirst - 1 + m, true);
+        }
+    }
     T r0 = T(0), r1 = T(0);
     if constexpr (!CM) {
         r0 = ldm<NTP == 1, T>(wfield(rho, w), oc + wplane(w, kfirst, use_rho));
@@ -416,6 +439,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
     struct Plane {
         T cxx, cyy, cxy, vx, vy, vz, xx, xy, xz, yy, yz, r, dr, dvx, dvy, dvz;
         T s[3], gb[3];  // velocity-A: stored v^{n+1/2}, buoyancy gradients
+        T qcxx, qcyy, qcxy, qxx, qxy, qxz, qyy, qyz;  // Born: the perturbation's own and halo stress
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const unsigned pk = wplane(w, kk, ok), pr = wplane(w, kk, ok && use_rho), o = oc + pk;
@@ -425,6 +449,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             P.dvx = ld<T>(wfield(io.out[0], w), o);
             P.dvy = ld<T>(wfield(io.out[1], w), o);
             P.dvz = ld<T>(wfield(io.out[2], w), o);
+            P.qcxx = ld<T>(wfield(pxx, w), o);
+            P.qcyy = ld<T>(wfield(pyy, w), o);
+            P.qcxy = ld<T>(wfield(pxy, w), o);
         }
         if constexpr (adj) {
 #pragma unroll
@@ -449,6 +476,11 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         }
         if constexpr (born) {
             if (wr) P.dr = ld<T>(wfield(io.acc[0], w), hr.off + pr);
+            if (wxx) P.qxx = ld<T>(wfield(pxx, w), hxx.off + pk);
+            if (wxy) P.qxy = ld<T>(wfield(pxy, w), hxy.off + pk);
+            if (wxz) P.qxz = ld<T>(wfield(pxz, w), hxz.off + pk);
+            if (wyy) P.qyy = ld<T>(wfield(pyy, w), hyy.off + pk);
+            if (wyz) P.qyz = ld<T>(wfield(pyz, w), hyz.off + pk);
         }
     };
     Plane P{};
@@ -473,9 +505,20 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         if (wyz) Lyz[hyz.lds] = P.yz;
         if (wr) Lr[hr.lds] = P.r;
         T *Ldr = s_dr[b];
+        T *Qxx = s_pxx[b], *Qxy = s_pxy[b], *Qxz = s_pxz[b], *Qyy = s_pyy[b], *Qyz = s_pyz[b];
         if constexpr (born) {
             Ldr[ty * WR + tx] = dr0;
             if (wr) Ldr[hr.lds] = P.dr;
+            Qxx[own_c3 + tx + 1] = P.qcxx;
+            Qxy[(ty + 2) * W3 + tx + 2] = P.qcxy;
+            Qxz[own_c3 + tx + 2] = pqxz[2];
+            Qyy[(ty + 1) * TX + tx] = P.qcyy;
+            Qyz[(ty + 2) * TX + tx] = pqyz[2];
+            if (wxx) Qxx[hxx.lds] = P.qxx;
+            if (wxy) Qxy[hxy.lds] = P.qxy;
+            if (wxz) Qxz[hxz.lds] = P.qxz;
+            if (wyy) Qyy[hyy.lds] = P.qyy;
+            if (wyz) Qyz[hyz.lds] = P.qyz;
         }
         const T vx0 = P.vx, vy0 = P.vy, vz0 = P.vz;
         const T bvx0 = P.dvx, bvy0 = P.dvy, bvz0 = P.dvz;  // the perturbation's velocity (kBornV)
@@ -515,6 +558,9 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
         const T nzz = zld(fzz, up ? k - 2 : k + 3, more);
         const T nr = CM ? T(0) : ldm<NTP == 1, T>(wfield(rho, w), oc + wplane(w, up ? k - 1 : k + 2, more && use_rho));
         const T ndr = born ? zld(io.acc[0], up ? k - 1 : k + 2, more) : T(0);
+        const T npxz = born ? zld(pxz, up ? k - 3 : k + 2, more) : T(0);
+        const T npyz = born ? zld(pyz, up ? k - 3 : k + 2, more) : T(0);
+        const T npzz = born ? zld(pzz, up ? k - 2 : k + 3, more) : T(0);
         const T gz_i = sload(G.g[2][0], k), gz_h = sload(G.g[2][1], k);
         // second order next to a vacuum surface: vx, vy at integer k, vz at k + 1/2 (only in
         // the instantiations for grids with a vacuum surface)
@@ -546,12 +592,17 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 if constexpr (MODE == kFwdSave) stm<NTP != 0>(wfield(G.save[VX], w), st_vx + pw, v);
                 else st(ovx, st_vx + pw, v);
             }
-            if constexpr (born) {
+            if constexpr (born) {  // the source term, then the perturbation's own update
                 const T bb = buoy(r0, Lr[ty * WR + tx + 1]);
                 const T db = -(bb * bb) * ((dr0 + Ldr[ty * WR + tx + 1]) * T(0.5));
                 T add = dt * db * d;
                 if (srcv) add += db * cf(VX, tap_of(src, VX, i, j, k)) * s;
-                st(bvx, st_vx + pw, bvx0 + add);
+                const T pv = bvx0 + add;
+                const T pd = dstag(Qxx[o + 1], Qxx[o], Qxx[o + 2], Qxx[o - 1], rdx)
+                           + dstag(Qxy[ox], Qxy[ox - W3], Qxy[ox + W3], Qxy[ox - 2 * W3], rdy)
+                           + dz_or_o2(false, pqxz[2], pqxz[1], pqxz[3], pqxz[0], rdz);
+                const T v = pv + dt * bb * pd;
+                st(bvx, st_vx + pw, v * (gxh * gyi * gz_i));
             }
             if constexpr (adj) adj_v(0, ovx, st_vx + pw, vx0, r0, Lr[ty * WR + tx + 1], gxh * gyi * gz_i, d);
         }
@@ -574,7 +625,12 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 const T db = -(bb * bb) * ((dr0 + Ldr[(ty + 1) * WR + tx]) * T(0.5));
                 T add = dt * db * d;
                 if (srcv) add += db * cf(VY, tap_of(src, VY, i, j, k)) * s;
-                st(bvy, st_vy + pw, bvy0 + add);
+                const T pv = bvy0 + add;
+                const T pd = dstag(Qxy[ox], Qxy[ox - 1], Qxy[ox + 1], Qxy[ox - 2], rdx)
+                           + dstag(Qyy[oy + TX], Qyy[oy], Qyy[oy + 2 * TX], Qyy[oy - TX], rdy)
+                           + dz_or_o2(false, pqyz[2], pqyz[1], pqyz[3], pqyz[0], rdz);
+                const T v = pv + dt * bb * pd;
+                st(bvy, st_vy + pw, v * (gxi * gyh * gz_i));
             }
             if constexpr (adj) adj_v(1, ovy, st_vy + pw, vy0, r0, Lr[(ty + 1) * WR + tx], gxi * gyh * gz_i, d);
         }
@@ -598,7 +654,12 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
                 const T db = -(bb * bb) * ((dr0 + dr1) * T(0.5));
                 T add = dt * db * d;
                 if (srcv) add += db * cf(VZ, tap_of(src, VZ, i, j, k)) * s;
-                st(bvz, st_vz + pw, bvz0 + add);
+                const T pv = bvz0 + add;
+                const T pd = dstag(Qxz[o], Qxz[o - 1], Qxz[o + 1], Qxz[o - 2], rdx)
+                           + dstag(Qyz[oy], Qyz[oy - TX], Qyz[oy + TX], Qyz[oy - 2 * TX], rdy)
+                           + dz_or_o2(false, pqzz[2], pqzz[1], pqzz[3], pqzz[0], rdz);
+                const T v = pv + dt * bb * pd;
+                st(bvz, st_vz + pw, v * (gxi * gyi * gz_h));
             }
             if constexpr (adj) adj_v(2, ovz, st_vz + pw, vz0, r0, r1, gxi * gyi * gz_h, d);
         }
@@ -608,12 +669,18 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
             qzz[3] = qzz[2]; qzz[2] = qzz[1]; qzz[1] = qzz[0]; qzz[0] = nzz;
             r1 = r0; r0 = nr;
             dr1 = dr0; dr0 = ndr;
+            pqxz[3] = pqxz[2]; pqxz[2] = pqxz[1]; pqxz[1] = pqxz[0]; pqxz[0] = npxz;
+            pqyz[3] = pqyz[2]; pqyz[2] = pqyz[1]; pqyz[1] = pqyz[0]; pqyz[0] = npyz;
+            pqzz[3] = pqzz[2]; pqzz[2] = pqzz[1]; pqzz[1] = pqzz[0]; pqzz[0] = npzz;
         } else {
             qxz[0] = qxz[1]; qxz[1] = qxz[2]; qxz[2] = qxz[3]; qxz[3] = nxz;
             qyz[0] = qyz[1]; qyz[1] = qyz[2]; qyz[2] = qyz[3]; qyz[3] = nyz;
             qzz[0] = qzz[1]; qzz[1] = qzz[2]; qzz[2] = qzz[3]; qzz[3] = nzz;
             r0 = r1; r1 = nr;
             dr0 = dr1; dr1 = ndr;
+            pqxz[0] = pqxz[1]; pqxz[1] = pqxz[2]; pqxz[2] = pqxz[3]; pqxz[3] = npxz;
+            pqyz[0] = pqyz[1]; pqyz[1] = pqyz[2]; pqyz[2] = pqyz[3]; pqyz[3] = npyz;
+            pqzz[0] = pqzz[1]; pqzz[1] = pqzz[2]; pqzz[2] = pqzz[3]; pqzz[3] = npzz;
         }
     }
 }
@@ -623,9 +690,7 @@ __device__ __forceinline__ void vel_tile_body(const Grid<T> &G, const Inject<T> 
 // CM (forward only): lambda, mu at the node and mu at the shear samples are trilinear
 // samples of a coarse medium at each sample's own position (CoarseAxis); the node
 // arrays, their halo and the mu ring are not read.
-// REV: the forward pass swept downward (damped boundaries, node medium).
-template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, int NTP = 0, bool CM = false,
-          bool REV = false>
+template <typename T, int TX, int TY, bool FS, int MODE = kFwd, bool VAC = false, int NTP = 0, bool CM = false>
 __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<T> &src, int n, int i0, int j0,
                                                  int k0, int k1, const TileIO<T> &io = TileIO<T>{})
 {
@@ -646,7 +711,11 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     __shared__ T s_yz[2][adjm ? NV + 1 : 1];
     __shared__ T s_mu[3][NM + 1];
     constexpr bool bsf = MODE == kBornS;
+    static_assert(!bsf || (!FS && !VAC && !CM), "Born: damped boundaries, node medium");
     __shared__ T s_dmu[3][bsf ? NM + 1 : 1];  // dmu ring of the Born stress term
+    __shared__ T s_pvx[2][bsf ? NV + 1 : 1];  // Born: the perturbation's velocity planes
+    __shared__ T s_pvy[2][bsf ? NV + 1 : 1];
+    __shared__ T s_pvz[2][bsf ? NV + 1 : 1];
 
     const int nx = G.nx, ny = G.ny, nz = G.nz;
     const int sy = (int)G.sy;
@@ -678,6 +747,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
 
     const T *fvx = G.f[VX], *fvy = G.f[VY], *fvz = G.f[VZ];
     const T *mu = G.mu, *lam = G.lam;
+    const T *pvx = io.pin[0], *pvy = io.pin[1], *pvz = io.pin[2];  // Born: the perturbation's velocity
     const T rdx = G.rdx, rdy = G.rdy, rdz = G.rdz, dt = G.dt;
     const T s = src.on ? sload(src.wavelet, n) : T(0);
     const T gxh = in ? G.g[0][1][i] : T(0), gxi = in ? G.g[0][0][i] : T(0);
@@ -714,8 +784,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     // upward for the forward passes and stress-B (see stress_sweeps_up); the z queues shift
     // the other way and the mu ring takes the new plane at the other end, with the same
     // arithmetic per sample in both directions
-    static_assert(!REV || (MODE == kFwd && !FS && !VAC && !CM), "downward forward stress: damped, node medium");
-    constexpr bool up = stress_sweeps_up<MODE>() != REV;
+    constexpr bool up = stress_sweeps_up<MODE>();
     static_assert(!bsf || up, "the Born stress mode sweeps upward");
     static_assert(!adjm || !up, "stress-M sweeps downward");
     const int kfirst = up ? k1 - 1 : k0;
@@ -726,11 +795,17 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     // z queues: vx, vy at k-1..k+2; vz at k-2..k+1 (zero above k = 0: never used with FS)
     T qvx[4], qvy[4], qvz[4];
     T qyx[4] = {}, qyy[4] = {}, qyz[4] = {};  // stress-M: the same queues of Y
+    T pqvx[4] = {}, pqvy[4] = {}, pqvz[4] = {};  // Born: the same queues of the perturbation
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         qvx[m] = zld(fvx, kfirst - 1 + m, true);
         qvy[m] = zld(fvy, kfirst - 1 + m, true);
         qvz[m] = zld(fvz, kfirst - 2 + m, true);
+        if constexpr (bsf) {
+            pqvx[m] = zld(pvx, kfirst - 1 + m, true);
+            pqvy[m] = zld(pvy, kfirst - 1 + m, true);
+            pqvz[m] = zld(pvz, kfirst - 2 + m, true);
+        }
         if constexpr (adjm) {
             qyx[m] = zld(io.y[0], kfirst - 1 + m, true);
             qyy[m] = zld(io.y[1], kfirst - 1 + m, true);
@@ -742,6 +817,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
     struct Plane {
         T cl, cm, sxx, syy, szz, sxy, sxz, syz, hx, hy, hz, a0, a1, a2, a3, a4, dl, dm, b0, b1, b2, b3, b4, b5;
         T yhx, yhy, yhz;  // stress-M: halo samples of Y
+        T phx, phy, phz;  // Born: halo samples of the perturbation's velocity
     };
     auto loadplane = [&](int kk, bool ok, Plane &P) {
         const unsigned pk = wplane(w, kk, ok), o = oc + pk, om_ = oc + wplane(w, kk, ok && use_model);
@@ -774,6 +850,9 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         if (wvy) P.hy = ld<T>(by, hvy.off + pk);
         if (wvz) P.hz = ld<T>(bz, hvz.off + pk);
         if constexpr (bsf) {
+            if (wvx) P.phx = ld<T>(wfield(pvx, w), hvx.off + pk);
+            if (wvy) P.phy = ld<T>(wfield(pvy, w), hvy.off + pk);
+            if (wvz) P.phz = ld<T>(wfield(pvz, w), hvz.off + pk);
             P.dl = ld<T>(wfield(io.acc[0], w), om_);
             P.dm = ld<T>(wfield(io.acc[1], w), om_);
             P.b0 = ld<T>(wfield(io.out[0], w), o);
@@ -841,6 +920,15 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             if (wvy) Yy[hvy.lds] = P.yhy;
             if (wvz) Yz[hvz.lds] = P.yhz;
         }
+        T *Qx = s_pvx[bsf ? b : 0], *Qy = s_pvy[bsf ? b : 0], *Qz = s_pvz[bsf ? b : 0];
+        if constexpr (bsf) {
+            Qx[ovx] = pqvx[1];
+            Qy[ovy] = pqvy[1];
+            Qz[ovz] = pqvz[2];
+            if (wvx) Qx[hvx.lds] = P.phx;
+            if (wvy) Qy[hvy.lds] = P.phy;
+            if (wvz) Qz[hvz.lds] = P.phz;
+        }
         if constexpr (CM) {
             // the coarse samples replace the ring
         } else if constexpr (up) {  // mu plane k enters the ring (plane k + 1 is there)
@@ -892,6 +980,12 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         loadplane(kn, more, P);
         const T nvx = zld(fvx, up ? k - 2 : k + 3, more), nvy = zld(fvy, up ? k - 2 : k + 3, more);
         const T nvz = zld(fvz, up ? k - 3 : k + 2, more);
+        T npvx = T(0), npvy = T(0), npvz = T(0);
+        if constexpr (bsf) {
+            npvx = zld(pvx, up ? k - 2 : k + 3, more);
+            npvy = zld(pvy, up ? k - 2 : k + 3, more);
+            npvz = zld(pvz, up ? k - 3 : k + 2, more);
+        }
         T nyx = T(0), nyy = T(0), nyz = T(0);
         if constexpr (adjm) {
             nyx = zld(io.y[0], k + 3, more);
@@ -952,19 +1046,37 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             st(wfield(G.f[SYZ], w), o_styz + pw, nyz * g_yz);
             if constexpr (bsf) {
                 // the perturbation's stress term: dlam, dmu with the same strain rates
-                // (no damping, no source)
+                // (no damping, no source) ...
                 const T bxx = b_xx + dt * (dl * tr + T(2) * dm * exx);
                 const T byy = b_yy + dt * (dl * tr + T(2) * dm * eyy);
                 const T bzz = b_zz + dt * (dl * tr + T(2) * dm * ezz);
                 const T dxy = ((D0[om] + D0[om + 1]) + (D0[om + WM] + D0[om + WM + 1])) / T(4);
                 const T dxz = ((D0[om] + D0[om + 1]) + (D1[om] + D1[om + 1])) / T(4);
                 const T dyz = ((D0[om] + D0[om + WM]) + (D1[om] + D1[om + WM])) / T(4);
-                st(wfield(io.out[0], w), oc + pw, bxx);
-                st(wfield(io.out[1], w), oc + pw, byy);
-                st(wfield(io.out[2], w), oc + pw, bzz);
-                st(wfield(io.out[3], w), st_xy + pw, b_xy + dt * dxy * exy);
-                st(wfield(io.out[4], w), o_stxz + pw, b_xz + dt * dxz * exz);
-                st(wfield(io.out[5], w), o_styz + pw, b_yz + dt * dyz * eyz);
+                const T bxy = b_xy + dt * dxy * exy, bxz = b_xz + dt * dxz * exz, byz = b_yz + dt * dyz * eyz;
+                // ... then its own forward update from its velocity's strain rates
+                const T pexx = dstag(Qx[ovx], Qx[ovx - 1], Qx[ovx + 1], Qx[ovx - 2], rdx);
+                const T peyy = dstag(Qy[ovy], Qy[ovy - W3], Qy[ovy + W3], Qy[ovy - 2 * W3], rdy);
+                const T pezz = dz_or_o2(false, pqvz[2], pqvz[1], pqvz[3], pqvz[0], rdz);
+                const T pexy = dstag(Qx[ovx + W3], Qx[ovx], Qx[ovx + 2 * W3], Qx[ovx - W3], rdy)
+                             + dstag(Qy[ovy + 1], Qy[ovy], Qy[ovy + 2], Qy[ovy - 1], rdx);
+                const T pdzvx = dz_or_o2(false, pqvx[2], pqvx[1], pqvx[3], pqvx[0], rdz);
+                const T pexz = pdzvx + dstag(Qz[ovz + 1], Qz[ovz], Qz[ovz + 2], Qz[ovz - 1], rdx);
+                const T pdzvy = dz_or_o2(false, pqvy[2], pqvy[1], pqvy[3], pqvy[0], rdz);
+                const T peyz = pdzvy + dstag(Qz[ovz + W3], Qz[ovz], Qz[ovz + 2 * W3], Qz[ovz - W3], rdy);
+                const T ptr = pexx + peyy + pezz;
+                const T pxx_ = bxx + dt * (l * ptr + T(2) * mm * pexx);
+                const T pyy_ = byy + dt * (l * ptr + T(2) * mm * peyy);
+                const T pzz_ = bzz + dt * (l * ptr + T(2) * mm * pezz);
+                const T pxy_ = bxy + dt * mxy * pexy;
+                const T pxz_ = bxz + dt * mxz * pexz;
+                const T pyz_ = byz + dt * myz * peyz;
+                st(wfield(io.out[0], w), oc + pw, pxx_ * gn);
+                st(wfield(io.out[1], w), oc + pw, pyy_ * gn);
+                st(wfield(io.out[2], w), oc + pw, pzz_ * gn);
+                st(wfield(io.out[3], w), st_xy + pw, pxy_ * g_xy);
+                st(wfield(io.out[4], w), o_stxz + pw, pxz_ * g_xz);
+                st(wfield(io.out[5], w), o_styz + pw, pyz_ * g_yz);
             }
         } else if constexpr (MODE == kAdjA || adjm) {
             // stress-M: first the adjoint stress update of the step after, A_s <- G_s A_s -
@@ -1024,6 +1136,9 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             qvx[3] = qvx[2]; qvx[2] = qvx[1]; qvx[1] = qvx[0]; qvx[0] = nvx;
             qvy[3] = qvy[2]; qvy[2] = qvy[1]; qvy[1] = qvy[0]; qvy[0] = nvy;
             qvz[3] = qvz[2]; qvz[2] = qvz[1]; qvz[1] = qvz[0]; qvz[0] = nvz;
+            pqvx[3] = pqvx[2]; pqvx[2] = pqvx[1]; pqvx[1] = pqvx[0]; pqvx[0] = npvx;
+            pqvy[3] = pqvy[2]; pqvy[2] = pqvy[1]; pqvy[1] = pqvy[0]; pqvy[0] = npvy;
+            pqvz[3] = pqvz[2]; pqvz[2] = pqvz[1]; pqvz[1] = pqvz[0]; pqvz[0] = npvz;
         } else {
             qvx[0] = qvx[1]; qvx[1] = qvx[2]; qvx[2] = qvx[3]; qvx[3] = nvx;
             qvy[0] = qvy[1]; qvy[1] = qvy[2]; qvy[2] = qvy[3]; qvy[3] = nvy;
@@ -1066,34 +1181,18 @@ __global__ void __launch_bounds__(TX *TY) stress_tile(Grid<T> G, Inject<T> src, 
     stress_tile_body<T, TX, TY, FS, MODE, VAC, NTP, CM>(G, src, n, i0, j0, k0, k1);
 }
 
-// The forward stress pass swept downward, for the perturbation's stress pass of the Born
-// step (after the background's upward one); otherwise as stress_tile (no free surface, no
-// vacuum surface, node medium).
-template <typename T, int TX, int TY, bool NTP = false>
-__global__ void __launch_bounds__(TX *TY) stress_tile_down(Grid<T> G, Inject<T> src, int n, TileMap tm, RecJob<T> rec)
-{
-    const int nwg = tm.ntx * tm.nty * tm.nzc;
-    if ((int)blockIdx.x >= nwg) {
-        const int q = ((int)blockIdx.x - nwg) * (TX * TY) + (int)threadIdx.x;
-        if (q < rec.nq) sample_receiver(rec, q, n);
-        return;
-    }
-    int i0, j0, k0, k1;
-    tile_coords(tm, tile_of(blockIdx.x, nwg, false), i0, j0, k0, k1, TX, TY, G.nz);
-    stress_tile_body<T, TX, TY, false, kFwd, false, NTP, false, true>(G, src, n, i0, j0, k0, k1);
-}
-
-// Born stress pass (kBornS): the background's stress update and the perturbation's
-// stress term in one sweep; the workgroups past the tiles sample the background's
-// receivers.
+// Born stress pass (kBornS): the background's and the perturbation's stress updates in
+// one sweep; the workgroups past the tiles sample the background's receivers (rec), then
+// the perturbation's (prec).
 template <typename T, int TX, int TY, bool NTP = false>
 __global__ void __launch_bounds__(TX *TY) stress_tile_born(Grid<T> G, Inject<T> src, int n, TileMap tm, TileIO<T> io,
-                                                           RecJob<T> rec)
+                                                           RecJob<T> rec, RecJob<T> prec)
 {
     const int nwg = tm.ntx * tm.nty * tm.nzc;
     if ((int)blockIdx.x >= nwg) {
         const int q = ((int)blockIdx.x - nwg) * (TX * TY) + (int)threadIdx.x;
         if (q < rec.nq) sample_receiver(rec, q, n);
+        else if (q - rec.nq < prec.nq) sample_receiver(prec, q - rec.nq, n);
         return;
     }
     int i0, j0, k0, k1;

@@ -103,8 +103,18 @@ def test_born_rejects_mismatched_contexts():
         _abi.fd3d_born(a.ctx, b.ctx, None, *(x.data_ptr() for x in dmt), 0, None, None, None, 0)
     with pytest.raises(_abi.FD3DError):
         _abi.fd3d_born(a.ctx, a.ctx, None, *(x.data_ptr() for x in dmt), 0, None, None, None, 0)
-    a.close()
-    b.close()
+    # both states are stepped by the same sweeps: one kernel configuration for both
+    from paper_2112_15071_amd import Simulator
+
+    c = sim_for(model, torch.float32, kernel=("tile", 4, 8, 64))
+    d = Simulator(c.lam, c.mu, c.rho, 10.0, DT, NT, dtype=torch.float32, sponge=SPONGE, sponge_alpha=ALPHA,
+                  layout=c.layout())
+    d.set_kernel("tile", 4, 16, 64)
+    with pytest.raises(_abi.FD3DError) as e:
+        _abi.fd3d_born(c.ctx, d.ctx, None, *(x.data_ptr() for x in dmt), 0, None, None, None, 0)
+    assert e.value.code == _abi.FD3D_EINVAL and "kernel configuration" in str(e.value), str(e.value)
+    for x in (a, b, c, d):
+        x.close()
 
 
 def test_fwi_descent_lowers_the_misfit():
