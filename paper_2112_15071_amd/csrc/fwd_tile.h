@@ -239,16 +239,16 @@ __device__ __forceinline__ void tile_coords(const TileMap &tm, int t, int &i0, i
 // the step after (Y of that step in io.y) then kAdjA of this step, in one sweep (the
 // updated A_s is stored and feeds T directly).  The adjoint modes read and write the
 // arrays named by the grid (f[] pointing at the adjoint, stored or scratch fields) and by
-// TileIO.  The Born
-// (tangent-linear) modes step the background and the perturbation in one sweep: kBornV is
-// the background's forward velocity update, then the perturbation's, whose velocity
-// (io.out[0..2]) first takes the source term dt db (D_S sigma) + db c s formed from the
-// background's derivatives (db = -b^2 drho_eff, drho in io.acc[0]) and then its own
-// forward update from its stress (io.pin[0..5], staged like the background's); kBornS is
-// the background's forward stress update, then the perturbation's stress (io.out[0..5])
-// takes dt (dC E v) (dlam, dmu in io.acc[0], io.acc[1]; no damping, no source) and then
-// its own forward update from its velocity (io.pin[0..2]).  Each perturbation sample sees
-// the operations of a separate source pass followed by a forward pass, in that order.
+// TileIO.  The Born (tangent-linear) modes step the background and the perturbation in
+// one sweep: kBornV is the background's forward velocity update, then the perturbation's,
+// whose velocity (io.out[0..2]) first takes the source term dt db (D_S sigma) + db c s
+// formed from the background's derivatives (db = -b^2 drho_eff, drho in io.acc[0]) and
+// then its own forward update from its stress (io.pin[0..5], staged like the
+// background's); kBornS is the background's forward stress update, then the perturbation's
+// stress (io.out[0..5]) takes dt (dC E v) (dlam, dmu in io.acc[0], io.acc[1]; no damping,
+// no source) and then its own forward update from its velocity (io.pin[0..2]).  Each
+// perturbation sample sees the operations of a separate source pass followed by a forward
+// pass, in that order.
 enum { kFwd = 0, kAdjA = 1, kAdjB = 2, kFwdSave = 3, kBornV = 4, kBornS = 5, kAdjM = 6 };
 
 // Sweep direction of each pass (true: upward, decreasing k), chosen so that a pass starts
