@@ -812,7 +812,9 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             qyz[m] = zld(io.y[2], kfirst - 2 + m, true);
         }
     }
-    T m1 = (up || CM) ? T(0) : zld(mu, k0 + 1, use_model);  // own mu one plane below (downward sweep)
+    // downward sweeps: the own mu of each plane is loaded once, one plane ahead, into the
+    // ring, which also supplies the node's mu (the upward ring takes it from the plane loads)
+    T m1 = (up || CM) ? T(0) : ldm<NTP == 1, T>(wfield(mu, w), oc + wplane(w, k0 + 1, use_model));
 
     struct Plane {
         T cl, cm, sxx, syy, szz, sxy, sxz, syz, hx, hy, hz, a0, a1, a2, a3, a4, dl, dm, b0, b1, b2, b3, b4, b5;
@@ -824,7 +826,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         const rsrc_t bx = wfield(fvx, w), by = wfield(fvy, w), bz = wfield(fvz, w);
         if constexpr (!CM) {
             P.cl = ldm<NTP == 1, T>(wfield(lam, w), om_);
-            P.cm = ldm<NTP == 1, T>(wfield(mu, w), om_);
+            P.cm = up ? ldm<NTP == 1, T>(wfield(mu, w), om_) : T(0);
         } else {
             P.cl = P.cm = T(0);
         }
@@ -891,7 +893,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
         }
     } else {
         T *M = s_mu[k0 % 3];
-        M[om] = P.cm;
+        M[om] = ldm<NTP == 1, T>(wfield(mu, w), oc + wplane(w, k0, use_model));
         if (wm) {
             M[hm.lds] = loadmu(k0, true);
             hmu = loadmu(k0 + 1, true);
@@ -942,7 +944,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             M1[om] = m1;
             if (wm) M1[hm.lds] = hmu;
         }
-        T l = P.cl, mm = P.cm;
+        T l = P.cl, mm = (up || CM) ? P.cm : M0[om];
         // coarse medium samples of this plane (loads issued before the next plane's)
         T cmu_xy = T(0), cmu_xz = T(0), cmu_yz = T(0);
         if constexpr (CM) {
@@ -992,7 +994,7 @@ __device__ __forceinline__ void stress_tile_body(const Grid<T> &G, const Inject<
             nyy = zld(io.y[1], k + 3, more);
             nyz = zld(io.y[2], k + 2, more);
         }
-        const T nm1 = (up || CM) ? T(0) : zld(mu, k + 2, more && use_model);
+        const T nm1 = (up || CM) ? T(0) : ldm<NTP == 1, T>(wfield(mu, w), oc + wplane(w, k + 2, more && use_model));
         T nhm = T(0), nhdm = T(0);
         if (!CM && wm) nhm = loadmu(up ? k - 1 : k + 2, more);
         if (bsf && wm) nhdm = loaddmu(k - 1, more);
