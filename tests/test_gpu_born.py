@@ -117,6 +117,22 @@ def test_born_rejects_mismatched_contexts():
         x.close()
 
 
+@pytest.mark.parametrize("kernel", [("tile", 4, 8, 64), ("cell", 8, 32)])
+def test_born_without_receivers_leaves_the_same_states(kernel):
+    """No receivers (no receiver workgroups in the stress sweeps): the background's and the
+    perturbation's final states equal those of a run that records, bit for bit."""
+    model, dm, rec, _ = setup()
+    s = shot_of("moment")
+    sim = sim_for(model, torch.float32, kernel=kernel)
+    sim.born(*dm, rec_pos=rec, **s)
+    bg, pt = sim.state(), sim._born_sim.state()
+    assert float(pt.abs().max()) > 0.0
+    tr, dtr = sim.born(*dm, rec_pos=None, **s)
+    assert tr.shape[0] == 0 and dtr.shape[0] == 0
+    assert torch.equal(sim.state(), bg) and torch.equal(sim._born_sim.state(), pt)
+    sim.close()
+
+
 def test_fwi_descent_lowers_the_misfit():
     """Three steepest-descent iterations from a smoothed model towards the model that
     made the data: the misfit falls at every iteration."""
